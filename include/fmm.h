@@ -1,0 +1,145 @@
+/*
+ * fmm.h -- C ABI of the MI355X (gfx950) unigrid fast-multipole Poisson solver
+ * with isolated (vacuum) boundary conditions.
+ *
+ * Method: Lee & Teyssier, "A Scalable Fast Multipole Method Poisson Solver for
+ * the RAMSES code: I. Unigrid Algorithm".  One upward pass (P2M on the leaf
+ * cells, eq. (multipole); M2M through the FMM grids, eq. (M2M), Sec. 2.1) and
+ * one downward pass (M2L over the fixed oct-shared interaction lists of
+ * Sec. 2.2, eq. (M2L); L2L, eq. (L2L); and at the finest FMM level L2P, M2P
+ * at the unigrid cell centres and the near-field direct sum, eq. (direct),
+ * Sec. 2.3 and Sec. 4).  Cartesian expansions to order p; the FMM grids sit
+ * delta_l = 1 level above the unigrid (App. A).
+ *
+ * Conventions shared by every entry point
+ *  - Grid: unit box [0,1]^3, n cells per axis, cell (i,j,k) centred at
+ *    ((i+1/2)/n, (j+1/2)/n, (k+1/2)/n).  Arrays are C order, k fastest:
+ *    rho[i][j][k], phi[i][j][k], g[3][i][j][k] (component-major).
+ *  - Units: G = 1; the mass of a cell is rho * (1/n)^3.  phi is the
+ *    potential sum_w m_w g(x - x_w) with the softened Green's function of
+ *    eq. (direct) (g = -1/dx for the cell itself); g = -grad(phi) is the
+ *    acceleration.
+ *  - Precision: an FMM_FP64 plan takes and returns double; FMM_FP32 and
+ *    FMM_BF16 plans take and return float (see fmm_precision).
+ *  - Memory: rho, phi, g, dphi, dg and drho are caller-owned DEVICE pointers
+ *    (hipMalloc / torch tensors on the plan's device), contiguous, not
+ *    aliasing each other.  The plan owns its own workspace.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream).  Calls only enqueue work; they return before it finishes.  A
+ *    nonzero status reports an argument or launch error; errors inside
+ *    kernels are not detected.
+ *  - Concurrency: a plan's workspace is reused by every call; calls on one
+ *    plan that overlap in time (two streams, two threads) race.  Use one plan
+ *    per stream.
+ *  - Errors: every call returns fmm_status (or NULL for constructors) and
+ *    records a message readable with fmm_last_error() in the same thread.
+ */
+#ifndef FMM_H
+#define FMM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmm_plan fmm_plan;
+
+typedef enum {
+  FMM_OK = 0,
+  FMM_ERR_INVALID_ARG = -1,   /* bad size, order, pointer or option */
+  FMM_ERR_UNSUPPORTED = -2,   /* well-formed but not provided (periodic BC, delta_l != 1) */
+  FMM_ERR_OUT_OF_MEMORY = -3, /* device allocation failed */
+  FMM_ERR_DEVICE = -4,        /* HIP runtime error (no device, launch failure) */
+  FMM_ERR_NONFINITE = -5      /* rho holds NaN/Inf (only with check_finite) */
+} fmm_status;
+
+/*
+ * Compute policy.  FMM_FP64: every step in double.  FMM_FP32 / FMM_BF16:
+ * the dominant contractions (M2L on fine levels, M2P) run on the matrix cores
+ * with FP32 / BF16 operands and FP32 accumulation, while the derivative
+ * tables are computed in FP64 on the device and the coarse levels
+ * (k <= coarse_fp64_levels) keep FP64 multipoles and locals; I/O is float.
+ */
+typedef enum { FMM_FP64 = 0, FMM_FP32 = 1, FMM_BF16 = 2 } fmm_precision;
+
+typedef struct {
+  int struct_size;          /* sizeof(fmm_options), for forward compatibility */
+  int precision;            /* fmm_precision, default FMM_FP64 */
+  int nmax;                 /* multipole order, -1 = p (default); 0 <= nmax <= p */
+  int coarse_fp64_levels;   /* mixed plans: levels k <= this stay FP64; default 4 */
+  int delta_l;              /* level offset unigrid -> finest FMM grid; only 1 */
+  int check_finite;         /* nonzero: fmm_solve scans rho for NaN/Inf first */
+} fmm_options;
+
+/* Fill *opt with the defaults above.  Returns FMM_OK or FMM_ERR_INVALID_ARG. */
+int fmm_options_default(fmm_options* opt);
+
+/*
+ * Create a plan for an n^3 unigrid solved to expansion order p.
+ *   n: power of two, 8 <= n <= 1024 (the finest FMM grid, n/2 cells per axis,
+ *      must hold at least one interaction list, Sec. 2.2).
+ *   p: 1 <= p <= 8.
+ *   isolated: must be 1; the paper's solver handles only isolated boundary
+ *      conditions (Sec. 2), so 0 gives FMM_ERR_UNSUPPORTED.
+ * Allocates the multipole/local pyramids on the current HIP device and
+ * computes the FP64 Green's-function derivative tables there (the fixed
+ * interaction geometry of Sec. 2.2).  Synchronous.  Returns NULL on error.
+ */
+fmm_plan* fmm_plan_create(int n, int p, int isolated);
+fmm_plan* fmm_plan_create_ex(int n, int p, int isolated, const fmm_options* opt);
+
+/* Release a plan and its device memory (synchronises the device).  NULL-safe. */
+void fmm_plan_destroy(fmm_plan* plan);
+
+/*
+ * phi (and g, if not NULL) of the density rho.  Enqueued on `stream`.
+ * rho: n^3 values; phi: n^3; g: 3 n^3 or NULL.
+ */
+int fmm_solve(fmm_plan* plan, const void* rho, void* phi, void* g, void* stream);
+
+/*
+ * Vector-Jacobian product of fmm_solve: drho = d(<phi, dphi> + <g, dg>)/drho.
+ * The solve is linear in rho, so no forward state is needed; the kernels run
+ * the transposes of the forward passes in reverse order (P2P^T, L2P^T and
+ * M2P^T, then L2L^T and M2L^T from the finest level up, M2M^T down, P2M^T).
+ * dphi: n^3 (required); dg: 3 n^3 or NULL (treated as zero); drho: n^3.
+ */
+int fmm_solve_backward(fmm_plan* plan, const void* dphi, const void* dg, void* drho, void* stream);
+
+/* Device bytes owned by the plan (tables and pyramids); 0 for NULL. */
+size_t fmm_plan_workspace_bytes(const fmm_plan* plan);
+
+/* Plan accessors: n, p, nmax, precision, finest FMM level F = log2(n) - 1. */
+int fmm_plan_info(const fmm_plan* plan, int* n, int* p, int* nmax, int* precision, int* finest_level);
+
+/* Last error message of the calling thread ("" if none).  Never NULL. */
+const char* fmm_last_error(void);
+
+/* Status code of the calling thread's last call (FMM_OK after a success);
+ * the way to learn why a constructor returned NULL. */
+int fmm_last_status(void);
+
+/*
+ * Inspection of the plan's intermediate state after fmm_solve has completed
+ * on the device (the caller synchronises the stream first).  Copies to HOST
+ * memory `out`, as double, the scaled expansions the kernels keep:
+ *   which = 0: multipoles of level `level` (2 <= level <= F),
+ *              Mhat[a] = (-1)^|a| M[a] / (a! h^|a| dx^3), M[a] = sum m (x - c)^a
+ *   which = 1: locals of level `level` (3 <= level <= F),
+ *              Lhat[b] = h^(|b|+1) L[b] / dx^3, L[b] = d^b phi at the centre
+ * with h = 2^-level the cell size and dx = 1/n.  Layout out[cell][term] with
+ * cells of the level in C order and terms in the order of
+ * fmm_multi_index().  `count` is the number of doubles `out` holds.
+ */
+int fmm_debug_expansions(fmm_plan* plan, int which, int level, double* out, size_t count);
+
+/* Multi-index order of the expansions: out[3*t + d] = exponent of axis d of
+ * term t, for the nterms = (P+1)(P+2)(P+3)/6 terms of order <= P.  `out` holds
+ * 3 * nterms ints.  Returns nterms, or FMM_ERR_INVALID_ARG. */
+int fmm_multi_index(int P, int* out, size_t count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMM_H */

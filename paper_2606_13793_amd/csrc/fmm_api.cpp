@@ -1,0 +1,324 @@
+// C ABI of the unigrid FMM library: argument validation, plan construction
+// and the solve entry points.  Validation happens before any HIP call, so
+// invalid arguments are reported identically with or without a device.
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fmm.h"
+#include "fmm_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+thread_local int g_status = FMM_OK;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  g_status = code;
+  return code;
+}
+
+int ok() {
+  g_err.clear();
+  g_status = FMM_OK;
+  return FMM_OK;
+}
+
+int ilog2_exact(int n) {
+  if (n <= 0 || (n & (n - 1)) != 0) return -1;
+  int L = 0;
+  while ((1 << L) < n) ++L;
+  return L;
+}
+
+int validate(int n, int p, int isolated, const fmm_options* o) {
+  if (isolated == 0)
+    return fail(FMM_ERR_UNSUPPORTED, "only isolated (vacuum) boundary conditions are provided (isolated=0 given)");
+  if (isolated != 1) return fail(FMM_ERR_INVALID_ARG, "isolated must be 1 (got %d)", isolated);
+  const int L = ilog2_exact(n);
+  if (L < 3 || L > 10) return fail(FMM_ERR_INVALID_ARG, "n must be a power of two in [8, 1024] (got %d)", n);
+  if (p < 1 || p > fmm::PMAX) return fail(FMM_ERR_INVALID_ARG, "p must be in [1, %d] (got %d)", fmm::PMAX, p);
+  if (o) {
+    if (o->struct_size < (int)sizeof(fmm_options))
+      return fail(FMM_ERR_INVALID_ARG, "fmm_options.struct_size %d < %d", o->struct_size, (int)sizeof(fmm_options));
+    if (o->precision < FMM_FP64 || o->precision > FMM_BF16)
+      return fail(FMM_ERR_INVALID_ARG, "unknown precision %d", o->precision);
+    if (o->nmax != -1 && (o->nmax < 0 || o->nmax > p))
+      return fail(FMM_ERR_INVALID_ARG, "nmax must be -1 or in [0, p] (got %d)", o->nmax);
+    if (o->delta_l != 1) return fail(FMM_ERR_UNSUPPORTED, "only delta_l = 1 is provided (got %d)", o->delta_l);
+    if (o->coarse_fp64_levels < 0) return fail(FMM_ERR_INVALID_ARG, "coarse_fp64_levels must be >= 0");
+    if (o->precision != FMM_FP64) return fail(FMM_ERR_UNSUPPORTED, "precision %d is not built yet", o->precision);
+    if (o->nmax != -1 && o->nmax != p) return fail(FMM_ERR_UNSUPPORTED, "nmax != p is not built yet");
+  }
+  return FMM_OK;
+}
+
+// device bytes a plan will allocate
+size_t plan_bytes(int n, int p) {
+  const int F = ilog2_exact(n) - 1;
+  const int NM = fmm::nterms(p), NC = (NM + 3) / 4, NCL = NC, ND = fmm::nterms(p + 1);
+  size_t b = (size_t)343 * 8 * ND * sizeof(double) + 8 * fmm::NLIST * sizeof(int) + 256;
+  for (int k = 2; k <= F; ++k) {
+    const size_t nkp = (size_t)(1 << k) + 6;
+    b += (size_t)NC * nkp * nkp * nkp * 4 * sizeof(double);
+    if (k >= 3) b += (size_t)NCL * ((size_t)1 << (3 * k)) * 4 * sizeof(double);
+  }
+  return b;
+}
+
+void release(fmm_plan* pl) {
+  if (!pl) return;
+  for (auto& lv : pl->lev) {
+    if (lv.M) (void)hipFree(lv.M);
+    if (lv.L) (void)hipFree(lv.L);
+  }
+  if (pl->dtab) (void)hipFree(pl->dtab);
+  if (pl->dtab32) (void)hipFree(pl->dtab32);
+  if (pl->dlists) (void)hipFree(pl->dlists);
+  if (pl->flag) (void)hipFree(pl->flag);
+  delete pl;
+}
+
+int dev_alloc(fmm_plan* pl, void** ptr, size_t bytes) {
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    (void)hipGetLastError();
+    return fail(FMM_ERR_OUT_OF_MEMORY, "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+  }
+  pl->bytes += bytes;
+  return FMM_OK;
+}
+
+// per parity r, the 189 offsets d = P - J of the interaction list (Sec. 2.2):
+// parent(J) adjacent to parent(P) and J not adjacent to P gives, per axis,
+// d in [r - 3, r + 2], excluding |d| <= 1 on all three axes.
+std::vector<int> build_dlists() {
+  std::vector<int> out;
+  for (int r = 0; r < 8; ++r) {
+    const int rr[3] = {(r >> 2) & 1, (r >> 1) & 1, r & 1};
+    for (int dd = 0; dd < 343; ++dd) {
+      const int d[3] = {dd / 49 - 3, (dd / 7) % 7 - 3, dd % 7 - 3};
+      bool in = true, near = true;
+      for (int a = 0; a < 3; ++a) {
+        if (d[a] < rr[a] - 3 || d[a] > rr[a] + 2) in = false;
+        if (d[a] < -1 || d[a] > 1) near = false;
+      }
+      if (in && !near) out.push_back(dd);
+    }
+  }
+  return out;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fmm_options_default(fmm_options* opt) {
+  if (!opt) return fail(FMM_ERR_INVALID_ARG, "opt is NULL");
+  std::memset(opt, 0, sizeof(*opt));
+  opt->struct_size = (int)sizeof(fmm_options);
+  opt->precision = FMM_FP64;
+  opt->nmax = -1;
+  opt->coarse_fp64_levels = 4;
+  opt->delta_l = 1;
+  opt->check_finite = 0;
+  return ok();
+}
+
+fmm_plan* fmm_plan_create(int n, int p, int isolated) { return fmm_plan_create_ex(n, p, isolated, nullptr); }
+
+fmm_plan* fmm_plan_create_ex(int n, int p, int isolated, const fmm_options* opt) {
+  if (validate(n, p, isolated, opt) != FMM_OK) return nullptr;
+  fmm_options o;
+  fmm_options_default(&o);
+  if (opt) o = *opt;
+  const size_t need = plan_bytes(n, p);
+  if (const char* cap = std::getenv("FMM_TEST_MAX_WORKSPACE")) {
+    const unsigned long long lim = std::strtoull(cap, nullptr, 10);
+    if (need > lim) {
+      fail(FMM_ERR_OUT_OF_MEMORY, "plan needs %zu device bytes, over the FMM_TEST_MAX_WORKSPACE cap %llu", need, lim);
+      return nullptr;
+    }
+  }
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    fail(FMM_ERR_DEVICE, "no HIP device: %s", hipGetErrorString(e));
+    return nullptr;
+  }
+  if ((e = fmm::upload_constants()) != hipSuccess) {
+    fail(FMM_ERR_DEVICE, "constant upload failed: %s", hipGetErrorString(e));
+    return nullptr;
+  }
+  fmm_plan* pl = new (std::nothrow) fmm_plan();
+  if (!pl) {
+    fail(FMM_ERR_OUT_OF_MEMORY, "host allocation failed");
+    return nullptr;
+  }
+  pl->n = n;
+  pl->p = p;
+  pl->nmax = (o.nmax < 0) ? p : o.nmax;
+  pl->L = ilog2_exact(n);
+  pl->F = pl->L - 1;
+  pl->precision = o.precision;
+  pl->coarse_fp64_levels = o.coarse_fp64_levels;
+  pl->check_finite = o.check_finite;
+  pl->device = dev;
+  pl->dx = 1.0 / n;
+  pl->NM = fmm::nterms(pl->nmax);
+  pl->NC = (pl->NM + 3) / 4;
+  pl->NL = fmm::nterms(p);
+  pl->NCL = (pl->NL + 3) / 4;
+  pl->ND = fmm::nterms(p + 1);
+
+  auto bail = [&](void) -> fmm_plan* {
+    release(pl);
+    return nullptr;
+  };
+  if (dev_alloc(pl, (void**)&pl->dtab, (size_t)343 * 8 * pl->ND * sizeof(double))) return bail();
+  if (dev_alloc(pl, (void**)&pl->dlists, 8 * fmm::NLIST * sizeof(int))) return bail();
+  if (dev_alloc(pl, (void**)&pl->flag, 256)) return bail();
+  for (int k = 2; k <= pl->F; ++k) {
+    fmm::Level& lv = pl->lev[k];
+    lv.k = k;
+    lv.nk = 1 << k;
+    lv.nkp = lv.nk + 6;
+    lv.ncell = 1LL << (3 * k);
+    lv.ncellp = (long long)lv.nkp * lv.nkp * lv.nkp;
+    const size_t mb = (size_t)pl->NC * lv.ncellp * 4 * sizeof(double);
+    if (dev_alloc(pl, &lv.M, mb)) return bail();
+    if (hipMemset(lv.M, 0, mb) != hipSuccess) {
+      fail(FMM_ERR_DEVICE, "hipMemset failed");
+      return bail();
+    }
+    if (k >= 3) {
+      const size_t lb = (size_t)pl->NCL * lv.ncell * 4 * sizeof(double);
+      if (dev_alloc(pl, &lv.L, lb)) return bail();
+      if (hipMemset(lv.L, 0, lb) != hipSuccess) {
+        fail(FMM_ERR_DEVICE, "hipMemset failed");
+        return bail();
+      }
+    }
+  }
+  const std::vector<int> dl = build_dlists();
+  if (dl.size() != 8 * (size_t)fmm::NLIST) {
+    fail(FMM_ERR_DEVICE, "interaction-list table has %zu entries", dl.size());
+    return bail();
+  }
+  if ((e = hipMemcpy(pl->dlists, dl.data(), dl.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) {
+    fail(FMM_ERR_DEVICE, "upload failed: %s", hipGetErrorString(e));
+    return bail();
+  }
+  if ((e = fmm::launch_dtab(pl, nullptr)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
+    fail(FMM_ERR_DEVICE, "derivative-table precompute failed: %s", hipGetErrorString(e));
+    return bail();
+  }
+  ok();
+  return pl;
+}
+
+void fmm_plan_destroy(fmm_plan* plan) {
+  if (!plan) return;
+  (void)hipDeviceSynchronize();
+  release(plan);
+}
+
+size_t fmm_plan_workspace_bytes(const fmm_plan* plan) { return plan ? plan->bytes : 0; }
+
+int fmm_plan_info(const fmm_plan* plan, int* n, int* p, int* nmax, int* precision, int* finest_level) {
+  if (!plan) return fail(FMM_ERR_INVALID_ARG, "plan is NULL");
+  if (n) *n = plan->n;
+  if (p) *p = plan->p;
+  if (nmax) *nmax = plan->nmax;
+  if (precision) *precision = plan->precision;
+  if (finest_level) *finest_level = plan->F;
+  return ok();
+}
+
+const char* fmm_last_error(void) { return g_err.c_str(); }
+
+int fmm_last_status(void) { return g_status; }
+
+int fmm_solve(fmm_plan* plan, const void* rho, void* phi, void* g, void* stream) {
+  if (!plan) return fail(FMM_ERR_INVALID_ARG, "plan is NULL");
+  if (!rho || !phi) return fail(FMM_ERR_INVALID_ARG, "rho and phi must be device pointers (got NULL)");
+  if (rho == phi || (g && (g == rho || g == phi))) return fail(FMM_ERR_INVALID_ARG, "rho, phi and g must not alias");
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e;
+  if (plan->check_finite) {
+    int bad = 0;
+    if ((e = fmm::launch_check_finite(plan, rho, &bad, s)) != hipSuccess)
+      return fail(FMM_ERR_DEVICE, "finite check failed: %s", hipGetErrorString(e));
+    if (bad) return fail(FMM_ERR_NONFINITE, "rho holds NaN or Inf");
+  }
+  if ((e = fmm::launch_solve(plan, rho, phi, g, s)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FMM_ERR_DEVICE, "solve launch failed: %s", hipGetErrorString(e));
+  }
+  return ok();
+}
+
+int fmm_solve_backward(fmm_plan* plan, const void* dphi, const void* dg, void* drho, void* stream) {
+  if (!plan) return fail(FMM_ERR_INVALID_ARG, "plan is NULL");
+  if (!dphi || !drho) return fail(FMM_ERR_INVALID_ARG, "dphi and drho must be device pointers (got NULL)");
+  if (drho == dphi || (dg && (dg == drho || dg == dphi))) return fail(FMM_ERR_INVALID_ARG, "buffers must not alias");
+  hipError_t e = fmm::launch_backward(plan, dphi, dg, drho, (hipStream_t)stream);
+  if (e == hipErrorNotSupported) return fail(FMM_ERR_UNSUPPORTED, "backward pass is not built for this plan");
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FMM_ERR_DEVICE, "backward launch failed: %s", hipGetErrorString(e));
+  }
+  return ok();
+}
+
+int fmm_multi_index(int P, int* out, size_t count) {
+  if (P < 0 || P > fmm::PDMAX) return fail(FMM_ERR_INVALID_ARG, "P must be in [0, %d]", fmm::PDMAX);
+  const int nt = fmm::nterms(P);
+  if (!out || count < (size_t)(3 * nt)) return fail(FMM_ERR_INVALID_ARG, "out must hold %d ints", 3 * nt);
+  for (int a = 0; a <= P; ++a)
+    for (int b = 0; a + b <= P; ++b)
+      for (int c = 0; a + b + c <= P; ++c) {
+        const int t = fmm::mi_index(a, b, c);
+        out[3 * t] = a;
+        out[3 * t + 1] = b;
+        out[3 * t + 2] = c;
+      }
+  ok();
+  return nt;
+}
+
+int fmm_debug_expansions(fmm_plan* plan, int which, int level, double* out, size_t count) {
+  if (!plan) return fail(FMM_ERR_INVALID_ARG, "plan is NULL");
+  if (which != 0 && which != 1) return fail(FMM_ERR_INVALID_ARG, "which must be 0 or 1");
+  const int lo = which == 0 ? 2 : 3;
+  if (level < lo || level > plan->F) return fail(FMM_ERR_INVALID_ARG, "level %d outside [%d, %d]", level, lo, plan->F);
+  const fmm::Level& lv = plan->lev[level];
+  const int nt = which == 0 ? plan->NM : plan->NL;
+  const int nch = (nt + 3) / 4;
+  if (!out || count < (size_t)lv.ncell * nt) return fail(FMM_ERR_INVALID_ARG, "out must hold %lld doubles", lv.ncell * nt);
+  const long long cells = which == 0 ? lv.ncellp : lv.ncell;
+  std::vector<double> host((size_t)nch * cells * 4);
+  hipError_t e = hipMemcpy(host.data(), which == 0 ? lv.M : lv.L, host.size() * sizeof(double), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(FMM_ERR_DEVICE, "copy failed: %s", hipGetErrorString(e));
+  const int nk = lv.nk;
+  for (long long cidx = 0; cidx < lv.ncell; ++cidx) {
+    const int c2 = (int)(cidx % nk), c1 = (int)((cidx / nk) % nk), c0 = (int)(cidx / ((long long)nk * nk));
+    const long long src = which == 0 ? ((long long)(c0 + 3) * lv.nkp + (c1 + 3)) * lv.nkp + (c2 + 3) : cidx;
+    for (int t = 0; t < nt; ++t) out[cidx * nt + t] = host[((size_t)(t >> 2) * cells + src) * 4 + (t & 3)];
+  }
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Internal declarations of the MI355X unigrid FMM library.
+//
+// Scaled representation (all operators become level-independent matrices):
+//   multipole of a level-s cell   Mhat[a] = (-1)^|a| M[a] / (a! h_s^|a| dx^3)
+//   local of a level-k cell       Lhat[b] = h_k^(|b|+1) L[b] / dx^3
+// with M[a] = sum m (x - c)^a, L[b] = d^b phi at the cell centre, h = cell
+// size, dx = 1/n and m = rho dx^3.  Green's function derivatives are taken at
+// the unit displacement Rhat = R / h_source, for which eq. (M2L) reads
+//   Lhat_k[b] = 2^-(|b|+1) sum_a D[a+b](Rhat) Mhat_{k-1}[a]
+// and M2P at the unigrid centres reads
+//   phi += dx^2/2 sum_a D[a](Rhat) Mhat_F[a],  g_d += -dx/4 sum_a D[a+e_d](Rhat) Mhat_F[a].
+//
+// Multi-index order (graded): degree n = 0, 1, ...; inside a degree the x
+// exponent ascends, then the y exponent ascends.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace fmm {
+
+constexpr int PMAX = 8;                   // highest expansion order
+constexpr int PDMAX = PMAX + 1;           // highest derivative order (M2P gradient)
+constexpr int NTMAX = (PDMAX + 1) * (PDMAX + 2) * (PDMAX + 3) / 6;  // 220
+
+constexpr __host__ __device__ int nterms(int P) { return P < 0 ? 0 : (P + 1) * (P + 2) * (P + 3) / 6; }
+constexpr __host__ __device__ int ndeg(int m) { return (m + 1) * (m + 2) / 2; }  // terms of degree m
+
+// index of (a, b, c) in the graded order
+constexpr __host__ __device__ int mi_index(int a, int b, int c) {
+  const int n = a + b + c;
+  return nterms(n - 1) + a * (n + 1) - a * (a - 1) / 2 + b;
+}
+
+// ---------------------------------------------------------------------------
+// M2L column layout: columns (child q, local term b) sorted by the degree m of
+// b; inside a degree block the child is the slow index.  Each 16-column MFMA
+// tile only needs the multipole terms with |a| <= p - (smallest m in tile),
+// which keeps ~86% of the issued MACs useful at p = 6.
+// ---------------------------------------------------------------------------
+constexpr __host__ __device__ int m2l_ncol(int P) { return 8 * nterms(P); }
+constexpr __host__ __device__ int m2l_ntiles(int P) { return (m2l_ncol(P) + 15) / 16; }
+constexpr __host__ __device__ int m2l_col_degree(int col) {
+  int m = 0;
+  while (col >= 8 * nterms(m)) ++m;
+  return m;
+}
+constexpr __host__ __device__ int m2l_tile_chunks(int P, int t) {
+  return (nterms(P - m2l_col_degree(16 * t)) + 3) / 4;
+}
+// tiles are grouped per launch under a register budget
+constexpr int M2L_MAX_TILES = 12;
+constexpr int M2L_MAX_BOFS = 72;
+constexpr int m2l_group_end(int P, int t0) {
+  int nt = 0, nb = 0, t = t0;
+  while (t < m2l_ntiles(P)) {
+    const int c = m2l_tile_chunks(P, t);
+    if (nt > 0 && (nt + 1 > M2L_MAX_TILES || nb + c > M2L_MAX_BOFS)) break;
+    ++nt;
+    nb += c;
+    ++t;
+  }
+  return t;
+}
+constexpr int m2l_group_start(int P, int g) {
+  int t = 0;
+  for (int i = 0; i < g; ++i) t = m2l_group_end(P, t);
+  return t;
+}
+constexpr int m2l_ngroups(int P) {
+  int g = 0, t = 0;
+  while (t < m2l_ntiles(P)) { t = m2l_group_end(P, t); ++g; }
+  return g;
+}
+
+// number of interaction-list offsets per parity class (6^3 - 3^3)
+constexpr int NLIST = 189;
+
+// ---------------------------------------------------------------------------
+// device state of one plan
+// ---------------------------------------------------------------------------
+struct Level {
+  int k = 0;          // level: 2^k cells per axis
+  int nk = 0;         // cells per axis
+  int nkp = 0;        // padded cells per axis (multipole grids: nk + 6)
+  long long ncell = 0;   // nk^3
+  long long ncellp = 0;  // nkp^3
+  void* M = nullptr;  // multipoles, chunked [NC][ncellp][4], zero halo of 3 cells
+  void* L = nullptr;  // locals, chunked [NCL][ncell][4] (k >= 3)
+  int m_fp64 = 1;     // 1: multipoles stored in double, 0: float
+  int l_fp64 = 1;
+};
+
+}  // namespace fmm
+
+struct fmm_plan {
+  int n = 0, p = 0, nmax = 0, L = 0, F = 0;
+  int precision = 0;
+  int coarse_fp64_levels = 4;
+  int check_finite = 0;
+  int device = 0;
+  double dx = 0.0;
+  int NM = 0, NC = 0, NL = 0, NCL = 0, ND = 0;
+  fmm::Level lev[16];
+  double* dtab = nullptr;   // [343][8][ND] D[g](Rhat) in FP64
+  float* dtab32 = nullptr;  // FP32 copy for mixed plans
+  int* dlists = nullptr;    // [8][189] offset index (0..342) per parity
+  int* flag = nullptr;      // device scratch flag (finite check)
+  size_t bytes = 0;
+};
+
+namespace fmm {
+// kernels.hip
+hipError_t upload_constants();
+hipError_t launch_dtab(fmm_plan* pl, hipStream_t s);
+hipError_t launch_solve(fmm_plan* pl, const void* rho, void* phi, void* g, hipStream_t s);
+hipError_t launch_backward(fmm_plan* pl, const void* dphi, const void* dg, void* drho, hipStream_t s);
+hipError_t launch_check_finite(fmm_plan* pl, const void* rho, int* host_flag, hipStream_t s);
+}  // namespace fmm

@@ -1,0 +1,701 @@
+// HIP kernels of the unigrid FMM solve for MI355X (gfx950).
+//
+// Pass order of one solve (Sec. 2 of the paper):
+//   k_p2m            rho -> Mhat_F                       eq. (multipole)
+//   k_m2m            Mhat_k -> Mhat_{k-1}, k = F..3      eq. (M2M)
+//   k_m2l_f64        Mhat_{k-1} -> Lhat_k,  k = 3..F     eq. (M2L), oct-shared lists (Sec. 2.2)
+//   k_l2l            Lhat_{k-1} -> Lhat_k (+=), k=4..F   eq. (L2L)
+//   k_near           rho, Lhat_F -> phi, g               eq. (direct) + L2P
+//   k_m2p_f64        Mhat_F -> phi, g (+=)               M2P at the unigrid centres (Sec. 4)
+//
+// Layouts: multipoles and locals are "chunked", [ceil(terms/4)][cells][4], so
+// that a matrix-core operand fragment (4 consecutive terms of one cell) is one
+// 32-byte load and cells of a z line are contiguous.  Multipole grids carry a
+// zero halo of 3 cells per side: the clipped interaction lists of the isolated
+// boundary then need no bounds checks.
+#include "fmm_internal.h"
+
+#include <cmath>
+#include <vector>
+
+namespace fmm {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// multi-index table for orders <= PDMAX: packed exponents a | b<<8 | c<<16,
+// and 1/a!
+__constant__ int c_mi_exp[NTMAX];
+__constant__ double c_mi_invfact[NTMAX];
+// near-field stencil in grid units, offset delta = u - w in [-3,3]^3:
+//   c_p2p_phi = -1/max(|delta|, 1),  c_p2p_g = -delta/|delta|^3 (0 at delta = 0)
+__constant__ double c_p2p_phi[343];
+__constant__ double c_p2p_g[3 * 343];
+
+__device__ __forceinline__ int mi_a(int e) { return e & 255; }
+__device__ __forceinline__ int mi_b(int e) { return (e >> 8) & 255; }
+__device__ __forceinline__ int mi_c(int e) { return (e >> 16) & 255; }
+
+hipError_t upload_constants() {
+  static bool done = false;
+  if (done) return hipSuccess;
+  int ex[NTMAX];
+  double inv[NTMAX];
+  for (int a = 0; a <= PDMAX; ++a)
+    for (int b = 0; a + b <= PDMAX; ++b)
+      for (int c = 0; a + b + c <= PDMAX; ++c) {
+        const int t = mi_index(a, b, c);
+        ex[t] = a | (b << 8) | (c << 16);
+        double f = 1.0;
+        for (int i = 2; i <= a; ++i) f *= i;
+        for (int i = 2; i <= b; ++i) f *= i;
+        for (int i = 2; i <= c; ++i) f *= i;
+        inv[t] = 1.0 / f;
+      }
+  double pp[343], pg[3 * 343];
+  for (int t = 0; t < 343; ++t) {
+    const int d0 = t / 49 - 3, d1 = (t / 7) % 7 - 3, d2 = t % 7 - 3;
+    const double r2 = double(d0 * d0 + d1 * d1 + d2 * d2);
+    if (r2 == 0.0) {
+      pp[t] = -1.0;
+      pg[t] = pg[343 + t] = pg[686 + t] = 0.0;
+    } else {
+      const double r = std::sqrt(r2);
+      pp[t] = -1.0 / r;
+      const double i3 = 1.0 / (r2 * r);
+      pg[t] = -d0 * i3;
+      pg[343 + t] = -d1 * i3;
+      pg[686 + t] = -d2 * i3;
+    }
+  }
+  hipError_t e;
+  if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_mi_exp), ex, sizeof(ex))) != hipSuccess) return e;
+  if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_mi_invfact), inv, sizeof(inv))) != hipSuccess) return e;
+  if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_p2p_phi), pp, sizeof(pp))) != hipSuccess) return e;
+  if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_p2p_g), pg, sizeof(pg))) != hipSuccess) return e;
+  done = true;
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Green's function derivatives at the 343 x 8 unit displacements
+//   Rhat = d + (2q - 1)/4,  d in [-3,3]^3, q in {0,1}^3
+// (target child q of a cell P, source J = P - d one level up, in units of the
+// source cell size).  f = 1/r obeys, for |g| = n >= 1,
+//   n r^2 d^g f = -(2n-1) sum_i g_i R_i d^(g-e_i) f - (n-1) sum_i g_i (g_i-1) d^(g-2e_i) f
+// (f is harmonic and homogeneous of degree -1); D = -d^g f is stored.
+// FP64, once per plan.
+// ---------------------------------------------------------------------------
+__global__ void k_dtab(double* __restrict__ out, int PD, int ND) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 343 * 8) return;
+  const int dd = t >> 3, q = t & 7;
+  const double R0 = double(dd / 49 - 3) + (((q >> 2) & 1) ? 0.25 : -0.25);
+  const double R1 = double((dd / 7) % 7 - 3) + (((q >> 1) & 1) ? 0.25 : -0.25);
+  const double R2 = double(dd % 7 - 3) + ((q & 1) ? 0.25 : -0.25);
+  const double r2 = R0 * R0 + R1 * R1 + R2 * R2;
+  double f[NTMAX];
+  f[0] = 1.0 / sqrt(r2);
+  for (int n = 1; n <= PD; ++n)
+    for (int a = 0; a <= n; ++a)
+      for (int b = 0; a + b <= n; ++b) {
+        const int c = n - a - b;
+        double s1 = 0.0, s2 = 0.0;
+        if (a > 0) {
+          s1 += a * R0 * f[mi_index(a - 1, b, c)];
+          if (a > 1) s2 += a * (a - 1) * f[mi_index(a - 2, b, c)];
+        }
+        if (b > 0) {
+          s1 += b * R1 * f[mi_index(a, b - 1, c)];
+          if (b > 1) s2 += b * (b - 1) * f[mi_index(a, b - 2, c)];
+        }
+        if (c > 0) {
+          s1 += c * R2 * f[mi_index(a, b, c - 1)];
+          if (c > 1) s2 += c * (c - 1) * f[mi_index(a, b, c - 2)];
+        }
+        f[mi_index(a, b, c)] = -((2 * n - 1) * s1 + (n - 1) * s2) / (n * r2);
+      }
+  for (int i = 0; i < ND; ++i) out[(size_t)t * ND + i] = -f[i];
+}
+
+__global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out, long long count) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < count) out[i] = (float)in[i];
+}
+
+// ---------------------------------------------------------------------------
+// P2M: Mhat_F[a] = sum_q rho_{2T+q} (s_q/4)^a / a!,  s_q,i = 1 - 2 q_i.
+// (-1)^(q.a) depends on a only through a mod 2, so the 8 signed sums of the
+// children are formed once (a Walsh transform) and each term is one product.
+// ---------------------------------------------------------------------------
+template <typename TI>
+__global__ void k_p2m(const TI* __restrict__ rho, double* __restrict__ M, int n, int NM, int NC) {
+  const int nF = n >> 1, nFp = nF + 6;
+  const long long nT = (long long)nF * nF * nF;
+  const long long T = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (T >= nT) return;
+  const int t2 = (int)(T % nF), t1 = (int)((T / nF) % nF), t0 = (int)(T / ((long long)nF * nF));
+  double v[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const long long u = ((long long)(2 * t0 + ((q >> 2) & 1)) * n + (2 * t1 + ((q >> 1) & 1))) * n + (2 * t2 + (q & 1));
+    v[q] = (double)rho[u];
+  }
+  double S[8];
+#pragma unroll
+  for (int pat = 0; pat < 8; ++pat) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s += (__popc(q & pat) & 1) ? -v[q] : v[q];
+    S[pat] = s;
+  }
+  const long long ncellp = (long long)nFp * nFp * nFp;
+  const long long cp = ((long long)(t0 + 3) * nFp + (t1 + 3)) * nFp + (t2 + 3);
+  for (int c = 0; c < NC; ++c) {
+    d4 o;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int al = 4 * c + e;
+      double val = 0.0;
+      if (al < NM) {
+        const int ex = c_mi_exp[al];
+        const int a = mi_a(ex), b = mi_b(ex), cc = mi_c(ex);
+        const int pat = ((a & 1) << 2) | ((b & 1) << 1) | (cc & 1);
+        val = ldexp(c_mi_invfact[al], -2 * (a + b + cc)) * S[pat];
+      }
+      o[e] = val;
+    }
+    *reinterpret_cast<d4*>(M + (c * ncellp + cp) * 4) = o;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// M2M: Mhat_{k-1}[a] = sum_q sum_{b<=a} 2^-|b| 4^-|g| / g! (-1)^(q.g) Mhat_k[2P+q][b],
+// g = a - b.  Block = 4 parents; the Walsh sums of the 8 children per term
+// are staged in LDS, then each thread forms terms.
+// ---------------------------------------------------------------------------
+template <int NMX>
+__global__ __launch_bounds__(256) void k_m2m(const double* __restrict__ Mc, double* __restrict__ Mp, int nk, int NM, int NC) {
+  __shared__ double W[4][NMX][8];
+  const int np = nk >> 1, nkp = nk + 6, npp = np + 6;
+  const long long ncp_c = (long long)nkp * nkp * nkp, ncp_p = (long long)npp * npp * npp;
+  const long long nP = (long long)np * np * np;
+  const long long P0 = (long long)blockIdx.x * 4;
+  // phase 1: Walsh sums
+  for (int w = threadIdx.x; w < 4 * NM; w += blockDim.x) {
+    const int pl = w / NM, b = w % NM;
+    const long long P = P0 + pl;
+    double v[8];
+    if (P < nP) {
+      const int p2 = (int)(P % np), p1 = (int)((P / np) % np), p0 = (int)(P / ((long long)np * np));
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const long long cc = ((long long)(2 * p0 + ((q >> 2) & 1) + 3) * nkp + (2 * p1 + ((q >> 1) & 1) + 3)) * nkp +
+                             (2 * p2 + (q & 1) + 3);
+        v[q] = Mc[((b >> 2) * ncp_c + cc) * 4 + (b & 3)];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = 0.0;
+    }
+#pragma unroll
+    for (int pat = 0; pat < 8; ++pat) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += (__popc(q & pat) & 1) ? -v[q] : v[q];
+      W[pl][b][pat] = s;
+    }
+  }
+  __syncthreads();
+  // phase 2: terms
+  for (int w = threadIdx.x; w < 4 * NC * 4; w += blockDim.x) {
+    const int pl = w / (NC * 4), al = w % (NC * 4);
+    const long long P = P0 + pl;
+    if (P >= nP) continue;
+    double acc = 0.0;
+    if (al < NM) {
+      const int ex = c_mi_exp[al];
+      const int a = mi_a(ex), b = mi_b(ex), c = mi_c(ex);
+      for (int x = 0; x <= a; ++x)
+        for (int y = 0; y <= b; ++y)
+          for (int z = 0; z <= c; ++z) {
+            const int gx = a - x, gy = b - y, gz = c - z;
+            const int be = mi_index(x, y, z), ge = mi_index(gx, gy, gz);
+            const int pat = ((gx & 1) << 2) | ((gy & 1) << 1) | (gz & 1);
+            acc += ldexp(c_mi_invfact[ge], -(x + y + z) - 2 * (gx + gy + gz)) * W[pl][be][pat];
+          }
+    }
+    const int p2 = (int)(P % np), p1 = (int)((P / np) % np), p0 = (int)(P / ((long long)np * np));
+    const long long cp = ((long long)(p0 + 3) * npp + (p1 + 3)) * npp + (p2 + 3);
+    Mp[((al >> 2) * ncp_p + cp) * 4 + (al & 3)] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// L2L: Lhat_k[T][b] += sum_{|b|+|g|<=p} 2^-(|b|+1) 4^-|g| / g! (2q-1)^g Lhat_{k-1}[P][b+g]
+// Block = 4 parents (32 children); parent locals staged in LDS.
+// ---------------------------------------------------------------------------
+template <int NLX>
+__global__ __launch_bounds__(256) void k_l2l(const double* __restrict__ Lp, double* __restrict__ Lc, int nk, int p, int NL) {
+  __shared__ double S[4][NLX];
+  const int np = nk >> 1;
+  const long long ncp = (long long)np * np * np, ncc = (long long)nk * nk * nk;
+  const long long P0 = (long long)blockIdx.x * 4;
+  for (int w = threadIdx.x; w < 4 * NL; w += blockDim.x) {
+    const int pl = w / NL, b = w % NL;
+    const long long P = P0 + pl;
+    S[pl][b] = (P < ncp) ? Lp[((b >> 2) * ncp + P) * 4 + (b & 3)] : 0.0;
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < 32 * NL; w += blockDim.x) {
+    const int ch = w / NL, b = w % NL;
+    const int pl = ch >> 3, q = ch & 7;
+    const long long P = P0 + pl;
+    if (P >= ncp) continue;
+    const int ex = c_mi_exp[b];
+    const int a0 = mi_a(ex), b0 = mi_b(ex), c0 = mi_c(ex);
+    const int m = a0 + b0 + c0;
+    const int q0 = (q >> 2) & 1, q1 = (q >> 1) & 1, q2 = q & 1;
+    double acc = 0.0;
+    for (int gx = 0; gx <= p - m; ++gx)
+      for (int gy = 0; gx + gy <= p - m; ++gy)
+        for (int gz = 0; gx + gy + gz <= p - m; ++gz) {
+          const int ng = gx + gy + gz;
+          const int sgn = ((1 - q0) * gx + (1 - q1) * gy + (1 - q2) * gz) & 1;
+          const double c = ldexp(c_mi_invfact[mi_index(gx, gy, gz)], -2 * ng);
+          const double v = S[pl][mi_index(a0 + gx, b0 + gy, c0 + gz)];
+          acc += sgn ? -c * v : c * v;
+        }
+    acc = ldexp(acc, -(m + 1));
+    const int p2 = (int)(P % np), p1 = (int)((P / np) % np), p0 = (int)(P / ((long long)np * np));
+    const long long T = ((long long)(2 * p0 + q0) * nk + (2 * p1 + q1)) * nk + (2 * p2 + q2);
+    Lc[((b >> 2) * ncc + T) * 4 + (b & 3)] += acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Near field and L2P at every unigrid cell u = 2T + q:
+//   phi = -dx^2 sum_w rho_w / max(|u-w|,1)  +  dx^2/2 sum_b Lhat_F[b] c_b(q)
+//   g   = -dx   sum_w rho_w (u-w)/|u-w|^3  +  dx s_d sum_b b_d Lhat_F[b] c_b(q)
+// with c_b(q) = (2q-1)^b 4^-|b| / b!, s_d = 1 - 2 q_d, and w over the 6^3
+// unigrid cells whose FMM cell is adjacent to T (clipped at the box).
+// ---------------------------------------------------------------------------
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_near(const TI* __restrict__ rho, const double* __restrict__ Lf,
+                                              TO* __restrict__ phi, TO* __restrict__ g, int n, int NL, double dx) {
+  const long long N = (long long)n * n * n;
+  const long long u = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (u >= N) return;
+  const int l = (int)(u % n), j = (int)((u / n) % n), i = (int)(u / ((long long)n * n));
+  const int qi = i & 1, qj = j & 1, ql = l & 1;
+  double ph = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  for (int a = -3 + qi; a <= 2 + qi; ++a) {      // delta = u - w
+    const int wi = i - a;
+    if (wi < 0 || wi >= n) continue;
+    for (int b = -3 + qj; b <= 2 + qj; ++b) {
+      const int wj = j - b;
+      if (wj < 0 || wj >= n) continue;
+      const long long rowb = ((long long)wi * n + wj) * n;
+      for (int c = -3 + ql; c <= 2 + ql; ++c) {
+        const int wl = l - c;
+        if (wl < 0 || wl >= n) continue;
+        const double r = (double)rho[rowb + wl];
+        const int t = (a + 3) * 49 + (b + 3) * 7 + (c + 3);
+        ph += r * c_p2p_phi[t];
+        g0 += r * c_p2p_g[t];
+        g1 += r * c_p2p_g[343 + t];
+        g2 += r * c_p2p_g[686 + t];
+      }
+    }
+  }
+  ph *= dx * dx;
+  g0 *= dx; g1 *= dx; g2 *= dx;
+  if (Lf) {
+    const int nF = n >> 1;
+    const long long nT = (long long)nF * nF * nF;
+    const long long T = ((long long)(i >> 1) * nF + (j >> 1)) * nF + (l >> 1);
+    double sp = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int b = 0; b < NL; ++b) {
+      const int ex = c_mi_exp[b];
+      const int x = mi_a(ex), y = mi_b(ex), z = mi_c(ex);
+      const int sgn = ((1 - qi) * x + (1 - qj) * y + (1 - ql) * z) & 1;
+      double c = ldexp(c_mi_invfact[b], -2 * (x + y + z)) * Lf[((b >> 2) * nT + T) * 4 + (b & 3)];
+      c = sgn ? -c : c;
+      sp += c;
+      s0 += x * c;
+      s1 += y * c;
+      s2 += z * c;
+    }
+    ph += 0.5 * dx * dx * sp;
+    g0 += dx * (1 - 2 * qi) * s0;
+    g1 += dx * (1 - 2 * qj) * s1;
+    g2 += dx * (1 - 2 * ql) * s2;
+  }
+  phi[u] = (TO)ph;
+  if (g) {
+    g[u] = (TO)g0;
+    g[N + u] = (TO)g1;
+    g[2 * N + u] = (TO)g2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-core M2L / M2P (FP64, v_mfma_f64_16x16x4f64).
+//
+// Both are sums over the 189 list offsets d of a parity class: with the
+// source grid s, a "row" is a cell P of grid s with parity r, and
+//   out[P][col] = sum_d sum_a B_d[a][col] Mhat_s[P - d][a]
+// where B_d[a][(q, x)] = D[a + x](Rhat_{d,q}) and x is a local term (M2L) or
+// one of {0, e_x, e_y, e_z} (M2P).  A wave owns 16 rows; lanes hold
+//   A[i][k] = Mhat[row i - d][4c + k]   (lane i + 16k)
+//   B[k][j] = D[4c + k + x_j](Rhat_{d, q_j}) from the d's table in LDS (lane j + 16k)
+//   D[i][j] at lane j + 16 (i mod 4), element i / 4.
+// The d loop stages the next offset's 8 x ND derivative table in LDS while
+// the current one is consumed (one barrier per offset).
+// ---------------------------------------------------------------------------
+struct RowCtx {
+  long long cell;  // padded linear index in the source grid
+  int c0, c1, c2;  // cell coordinates (unpadded)
+  bool valid;
+};
+
+__device__ __forceinline__ RowCtx row_of(long long gl, long long nlat, int nG, int r, int nsp) {
+  RowCtx rc;
+  rc.valid = gl < nlat;
+  const long long g = rc.valid ? gl : 0;
+  const int G2 = (int)(g % nG), G1 = (int)((g / nG) % nG), G0 = (int)(g / ((long long)nG * nG));
+  rc.c0 = 2 * G0 + ((r >> 2) & 1);
+  rc.c1 = 2 * G1 + ((r >> 1) & 1);
+  rc.c2 = 2 * G2 + (r & 1);
+  rc.cell = ((long long)(rc.c0 + 3) * nsp + (rc.c1 + 3)) * nsp + (rc.c2 + 3);
+  return rc;
+}
+
+template <int ND>
+__device__ __forceinline__ void stage_load(const double* __restrict__ src, double (&buf)[(8 * ND + 255) / 256]) {
+#pragma unroll
+  for (int s = 0; s < (8 * ND + 255) / 256; ++s) {
+    const int e = threadIdx.x + 256 * s;
+    buf[s] = (e < 8 * ND) ? src[e] : 0.0;
+  }
+}
+template <int ND>
+__device__ __forceinline__ void stage_store(double* dst, const double (&buf)[(8 * ND + 255) / 256]) {
+#pragma unroll
+  for (int s = 0; s < (8 * ND + 255) / 256; ++s) {
+    const int e = threadIdx.x + 256 * s;
+    if (e < 8 * ND) dst[e] = buf[s];
+  }
+}
+
+// M2P: columns (q, o), o in {phi, gx, gy, gz}; 32 columns = 2 tiles.
+template <int P, typename TO>
+__global__ __launch_bounds__(256, 2) void k_m2p_f64(const double* __restrict__ Mh, const double* __restrict__ Dtab,
+                                                   const int* __restrict__ dlists, TO* __restrict__ phi,
+                                                   TO* __restrict__ g, int nF, double sphi, double sg) {
+  constexpr int NM = nterms(P), NC = (NM + 3) / 4, ND = nterms(P + 1);
+  constexpr int NS = (8 * ND + 255) / 256;
+  constexpr int ZERO = 8 * ND;  // index of a zero slot
+  __shared__ double sD[2][8 * ND + 1];
+  const int r = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, kq = lane >> 4;
+  const int nG = nF >> 1, nFp = nF + 6;
+  const long long nlat = (long long)nG * nG * nG;
+  const long long ncellp = (long long)nFp * nFp * nFp;
+  const long long tile0 = ((long long)blockIdx.x * 4 + wave) * 16;
+  const RowCtx rc = row_of(tile0 + i, nlat, nG, r, nFp);
+
+  int bofs[2][NC];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int col = 16 * t + i;
+    const int q = col >> 2, o = col & 3;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int al = 4 * c + kq;
+      int off = ZERO;
+      if (al < NM) {
+        const int ex = c_mi_exp[al];
+        const int a = mi_a(ex) + (o == 1), b = mi_b(ex) + (o == 2), cc = mi_c(ex) + (o == 3);
+        off = q * ND + mi_index(a, b, cc);
+      }
+      bofs[t][c] = off;
+    }
+  }
+  if (threadIdx.x == 0) { sD[0][ZERO] = 0.0; sD[1][ZERO] = 0.0; }
+  const int* dl = dlists + r * NLIST;
+  double pre[NS];
+  stage_load<ND>(Dtab + (size_t)dl[0] * 8 * ND, pre);
+  stage_store<ND>(sD[0], pre);
+  __syncthreads();
+
+  d4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+  const double* mbase = Mh + kq;
+  for (int it = 0; it < NLIST; ++it) {
+    const int dd = dl[it];
+    const int d0 = dd / 49 - 3, d1 = (dd / 7) % 7 - 3, d2 = dd % 7 - 3;
+    const long long src = rc.cell - ((long long)d0 * nFp + d1) * nFp - d2;
+    double a[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) a[c] = mbase[(c * ncellp + src) * 4];
+    if (it + 1 < NLIST) stage_load<ND>(Dtab + (size_t)dl[it + 1] * 8 * ND, pre);
+    const double* sd = sD[it & 1];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c], sd[bofs[0][c]], acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c], sd[bofs[1][c]], acc[1], 0, 0, 0);
+    }
+    if (it + 1 < NLIST) stage_store<ND>(sD[(it + 1) & 1], pre);
+    __syncthreads();
+  }
+  // epilogue: element v of tile t is row 4v + kq, column 16t + i
+  const int n = 2 * nF;
+  const long long N = (long long)n * n * n;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const RowCtx ro = row_of(tile0 + 4 * v + kq, nlat, nG, r, nFp);
+    if (!ro.valid) continue;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int col = 16 * t + i;
+      const int q = col >> 2, o = col & 3;
+      const long long u = ((long long)(2 * ro.c0 + ((q >> 2) & 1)) * n + (2 * ro.c1 + ((q >> 1) & 1))) * n +
+                          (2 * ro.c2 + (q & 1));
+      const double val = acc[t][v];
+      if (o == 0) {
+        phi[u] = (TO)((double)phi[u] + sphi * val);
+      } else if (g) {
+        TO* gp = g + (o - 1) * N + u;
+        *gp = (TO)((double)*gp + sg * val);
+      }
+    }
+  }
+}
+
+// chunk count of each tile of an M2L launch, as a compile-time table
+template <int P, int T0, int NT>
+struct TileChunks {
+  int v[NT];
+  constexpr TileChunks() : v() {
+    for (int t = 0; t < NT; ++t) v[t] = m2l_tile_chunks(P, T0 + t);
+  }
+};
+
+// M2L: columns (q, b) sorted by |b|, tiles [T0, T1) of them.
+template <int P, int T0, int T1>
+__global__ __launch_bounds__(256, 2) void k_m2l_f64(const double* __restrict__ Mh, const double* __restrict__ Dtab,
+                                                   const int* __restrict__ dlists, double* __restrict__ Lh, int ns) {
+  constexpr int NM = nterms(P), NL = nterms(P), ND = nterms(P + 1);
+  constexpr int NT = T1 - T0;
+  constexpr int CM = m2l_tile_chunks(P, T0);  // the group's first tile needs the most terms
+  constexpr int NS = (8 * ND + 255) / 256;
+  constexpr int ZERO = 8 * ND;
+  constexpr int NCOL = 8 * NL;
+  constexpr TileChunks<P, T0, NT> kch{};
+  __shared__ double sD[2][8 * ND + 1];
+  const int r = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, kq = lane >> 4;
+  const int nG = ns >> 1, nsp = ns + 6;
+  const long long nlat = (long long)nG * nG * nG;
+  const long long ncellp = (long long)nsp * nsp * nsp;
+  const long long tile0 = ((long long)blockIdx.x * 4 + wave) * 16;
+  const RowCtx rc = row_of(tile0 + i, nlat, nG, r, nsp);
+
+  int bofs[NT][CM];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = 16 * (T0 + t) + i;
+    int q = 0, bx = 0, by = 0, bz = 0, m = P + 1;
+    if (col < NCOL) {
+      m = m2l_col_degree(col);
+      const int cin = col - 8 * nterms(m - 1);
+      q = cin / ndeg(m);
+      const int bex = c_mi_exp[nterms(m - 1) + cin % ndeg(m)];
+      bx = mi_a(bex); by = mi_b(bex); bz = mi_c(bex);
+    }
+#pragma unroll
+    for (int c = 0; c < CM; ++c) {
+      const int al = 4 * c + kq;
+      int off = ZERO;
+      if (al < NM) {
+        const int ex = c_mi_exp[al];
+        const int a = mi_a(ex), b = mi_b(ex), cc = mi_c(ex);
+        if (a + b + cc + m <= P) off = q * ND + mi_index(a + bx, b + by, cc + bz);
+      }
+      bofs[t][c] = off;
+    }
+  }
+  if (threadIdx.x == 0) { sD[0][ZERO] = 0.0; sD[1][ZERO] = 0.0; }
+  const int* dl = dlists + r * NLIST;
+  double pre[NS];
+  stage_load<ND>(Dtab + (size_t)dl[0] * 8 * ND, pre);
+  stage_store<ND>(sD[0], pre);
+  __syncthreads();
+
+  d4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = d4{0, 0, 0, 0};
+  const double* mbase = Mh + kq;
+  for (int it = 0; it < NLIST; ++it) {
+    const int dd = dl[it];
+    const int d0 = dd / 49 - 3, d1 = (dd / 7) % 7 - 3, d2 = dd % 7 - 3;
+    const long long src = rc.cell - ((long long)d0 * nsp + d1) * nsp - d2;
+    double a[CM];
+#pragma unroll
+    for (int c = 0; c < CM; ++c) a[c] = mbase[(c * ncellp + src) * 4];
+    if (it + 1 < NLIST) stage_load<ND>(Dtab + (size_t)dl[it + 1] * 8 * ND, pre);
+    const double* sd = sD[it & 1];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+      for (int c = 0; c < CM; ++c)
+        if (c < kch.v[t]) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c], sd[bofs[t][c]], acc[t], 0, 0, 0);
+    }
+    if (it + 1 < NLIST) stage_store<ND>(sD[(it + 1) & 1], pre);
+    __syncthreads();
+  }
+  // epilogue: Lhat_k[2P + q][b] = 2^-(|b|+1) acc
+  const int nk = 2 * ns;
+  const long long nck = (long long)nk * nk * nk;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const RowCtx ro = row_of(tile0 + 4 * v + kq, nlat, nG, r, nsp);
+    if (!ro.valid) continue;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int col = 16 * (T0 + t) + i;
+      if (col >= NCOL) continue;
+      const int m = m2l_col_degree(col);
+      const int cin = col - 8 * nterms(m - 1);
+      const int q = cin / ndeg(m);
+      const int bt = nterms(m - 1) + cin % ndeg(m);
+      const long long T = ((long long)(2 * ro.c0 + ((q >> 2) & 1)) * nk + (2 * ro.c1 + ((q >> 1) & 1))) * nk +
+                          (2 * ro.c2 + (q & 1));
+      Lh[((bt >> 2) * nck + T) * 4 + (bt & 3)] = ldexp(acc[t][v], -(m + 1));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launch helpers
+// ---------------------------------------------------------------------------
+static inline unsigned blocks_for(long long work, int per) { return (unsigned)((work + per - 1) / per); }
+
+hipError_t launch_dtab(fmm_plan* pl, hipStream_t s) {
+  hipLaunchKernelGGL(k_dtab, dim3(blocks_for(343 * 8, 64)), dim3(64), 0, s, pl->dtab, pl->p + 1, pl->ND);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (pl->dtab32) {
+    const long long cnt = 343LL * 8 * pl->ND;
+    hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(cnt, 256)), dim3(256), 0, s, pl->dtab, pl->dtab32, cnt);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+template <int P, int G>
+static hipError_t launch_m2l_groups(fmm_plan* pl, int k, hipStream_t s) {
+  if constexpr (G >= m2l_ngroups(P)) {
+    return hipSuccess;
+  } else {
+    constexpr int T0 = m2l_group_start(P, G), T1 = m2l_group_end(P, T0);
+    const int ns = 1 << (k - 1);
+    const long long nlat = (long long)(ns / 2) * (ns / 2) * (ns / 2);
+    dim3 grid(blocks_for(nlat, 64), 8);
+    hipLaunchKernelGGL((k_m2l_f64<P, T0, T1>), grid, dim3(256), 0, s, (const double*)pl->lev[k - 1].M, pl->dtab,
+                       pl->dlists, (double*)pl->lev[k].L, ns);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_m2l_groups<P, G + 1>(pl, k, s);
+  }
+}
+
+template <int P, typename TI, typename TO>
+static hipError_t solve_fp64(fmm_plan* pl, const TI* rho, TO* phi, TO* g, hipStream_t s) {
+  constexpr int NM = nterms(P), NC = (NM + 3) / 4, NL = nterms(P);
+  const int n = pl->n, F = pl->F;
+  hipError_t e;
+  {
+    const long long nT = (long long)(n / 2) * (n / 2) * (n / 2);
+    hipLaunchKernelGGL((k_p2m<TI>), dim3(blocks_for(nT, 256)), dim3(256), 0, s, rho, (double*)pl->lev[F].M, n, NM, NC);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  for (int k = F; k >= 3; --k) {
+    const long long nP = 1LL << (3 * (k - 1));
+    hipLaunchKernelGGL((k_m2m<nterms(PMAX)>), dim3(blocks_for(nP, 4)), dim3(256), 0, s, (const double*)pl->lev[k].M,
+                       (double*)pl->lev[k - 1].M, 1 << k, NM, NC);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  for (int k = 3; k <= F; ++k) {
+    if ((e = launch_m2l_groups<P, 0>(pl, k, s)) != hipSuccess) return e;
+    if (k >= 4) {
+      const long long nP = 1LL << (3 * (k - 1));
+      hipLaunchKernelGGL((k_l2l<nterms(PMAX)>), dim3(blocks_for(nP, 4)), dim3(256), 0, s, (const double*)pl->lev[k - 1].L,
+                         (double*)pl->lev[k].L, 1 << k, P, NL);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  {
+    const long long N = (long long)n * n * n;
+    const double* Lf = (F >= 3) ? (const double*)pl->lev[F].L : nullptr;
+    hipLaunchKernelGGL((k_near<TI, TO>), dim3(blocks_for(N, 256)), dim3(256), 0, s, rho, Lf, phi, g, n, NL, pl->dx);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  {
+    const int nF = n / 2;
+    const long long nlat = (long long)(nF / 2) * (nF / 2) * (nF / 2);
+    dim3 grid(blocks_for(nlat, 64), 8);
+    const double dx = pl->dx;
+    hipLaunchKernelGGL((k_m2p_f64<P, TO>), grid, dim3(256), 0, s, (const double*)pl->lev[F].M, pl->dtab, pl->dlists,
+                       phi, g, nF, 0.5 * dx * dx, -0.25 * dx);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename TI, typename TO>
+static hipError_t dispatch_p(fmm_plan* pl, const TI* rho, TO* phi, TO* g, hipStream_t s) {
+  switch (pl->p) {
+    case 1: return solve_fp64<1>(pl, rho, phi, g, s);
+    case 2: return solve_fp64<2>(pl, rho, phi, g, s);
+    case 3: return solve_fp64<3>(pl, rho, phi, g, s);
+    case 4: return solve_fp64<4>(pl, rho, phi, g, s);
+    case 5: return solve_fp64<5>(pl, rho, phi, g, s);
+    case 6: return solve_fp64<6>(pl, rho, phi, g, s);
+    case 7: return solve_fp64<7>(pl, rho, phi, g, s);
+    case 8: return solve_fp64<8>(pl, rho, phi, g, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_solve(fmm_plan* pl, const void* rho, void* phi, void* g, hipStream_t s) {
+  if (pl->precision == 0)
+    return dispatch_p<double, double>(pl, (const double*)rho, (double*)phi, (double*)g, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_backward(fmm_plan*, const void*, const void*, void*, hipStream_t) {
+  return hipErrorNotSupported;
+}
+
+template <typename T>
+__global__ void k_check_finite(const T* __restrict__ x, long long count, int* flag) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < count && !isfinite((double)x[i])) atomicOr(flag, 1);
+}
+
+hipError_t launch_check_finite(fmm_plan* pl, const void* rho, int* host_flag, hipStream_t s) {
+  const long long N = (long long)pl->n * pl->n * pl->n;
+  hipError_t e = hipMemsetAsync(pl->flag, 0, sizeof(int), s);
+  if (e != hipSuccess) return e;
+  if (pl->precision == 0)
+    hipLaunchKernelGGL((k_check_finite<double>), dim3(blocks_for(N, 256)), dim3(256), 0, s, (const double*)rho, N, pl->flag);
+  else
+    hipLaunchKernelGGL((k_check_finite<float>), dim3(blocks_for(N, 256)), dim3(256), 0, s, (const float*)rho, N, pl->flag);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(host_flag, pl->flag, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
+}  // namespace fmm

@@ -1,0 +1,241 @@
+"""Python binding of the C ABI in ``include/fmm.h`` (ctypes).
+
+Only argument marshalling lives here: every step of a solve runs in the HIP
+kernels of ``_lib/libfmm.so``.  PyTorch supplies device memory and the
+current HIP stream.  There is no CPU fallback: without the built library or
+without a GPU the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libfmm.so")
+
+FMM_OK = 0
+FMM_ERR_INVALID_ARG = -1
+FMM_ERR_UNSUPPORTED = -2
+FMM_ERR_OUT_OF_MEMORY = -3
+FMM_ERR_DEVICE = -4
+FMM_ERR_NONFINITE = -5
+
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+
+# every symbol the header declares
+EXPORTS = (
+    "fmm_options_default", "fmm_plan_create", "fmm_plan_create_ex", "fmm_plan_destroy",
+    "fmm_solve", "fmm_solve_backward", "fmm_plan_workspace_bytes", "fmm_plan_info",
+    "fmm_last_error", "fmm_last_status", "fmm_debug_expansions", "fmm_multi_index",
+)
+
+
+class FmmOptions(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("nmax", ctypes.c_int),
+        ("coarse_fp64_levels", ctypes.c_int),
+        ("delta_l", ctypes.c_int),
+        ("check_finite", ctypes.c_int),
+    ]
+
+
+class FmmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load ``libfmm.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_13793_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+        L.fmm_options_default.argtypes = [ctypes.POINTER(FmmOptions)]
+        L.fmm_plan_create.argtypes = [i, i, i]
+        L.fmm_plan_create.restype = vp
+        L.fmm_plan_create_ex.argtypes = [i, i, i, ctypes.POINTER(FmmOptions)]
+        L.fmm_plan_create_ex.restype = vp
+        L.fmm_plan_destroy.argtypes = [vp]
+        L.fmm_plan_destroy.restype = None
+        L.fmm_solve.argtypes = [vp, vp, vp, vp, vp]
+        L.fmm_solve_backward.argtypes = [vp, vp, vp, vp, vp]
+        L.fmm_plan_workspace_bytes.argtypes = [vp]
+        L.fmm_plan_workspace_bytes.restype = sz
+        L.fmm_plan_info.argtypes = [vp] + [ctypes.POINTER(i)] * 5
+        L.fmm_last_error.argtypes = []
+        L.fmm_last_error.restype = ctypes.c_char_p
+        L.fmm_last_status.argtypes = []
+        L.fmm_last_status.restype = ctypes.c_int
+        L.fmm_debug_expansions.argtypes = [vp, i, i, ctypes.POINTER(ctypes.c_double), sz]
+        L.fmm_multi_index.argtypes = [i, ctypes.POINTER(i), sz]
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().fmm_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != FMM_OK:
+        raise FmmError(rc, last_error())
+
+
+def multi_index(P: int) -> np.ndarray:
+    """Order of the expansion terms the kernels use, (nterms, 3) int array."""
+    nt = (P + 1) * (P + 2) * (P + 3) // 6
+    out = np.zeros(3 * nt, dtype=np.int32)
+    rc = lib().fmm_multi_index(P, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), out.size)
+    if rc < 0:
+        _check(rc)
+    return out.reshape(nt, 3)
+
+
+def _stream_ptr(stream=None) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+class Plan:
+    """An ``fmm_plan``: tables and pyramids for one grid size and order.
+
+    ``precision``: "fp64" (double I/O) or "fp32"/"bf16" (float I/O).
+    """
+
+    def __init__(self, n: int, p: int, precision: str = "fp64", nmax: int | None = None,
+                 isolated: int = 1, check_finite: bool = False, coarse_fp64_levels: int = 4,
+                 delta_l: int = 1):
+        L = lib()
+        opt = FmmOptions()
+        L.fmm_options_default(ctypes.byref(opt))
+        opt.precision = PRECISIONS[precision]
+        opt.nmax = -1 if nmax is None else int(nmax)
+        opt.check_finite = int(bool(check_finite))
+        opt.coarse_fp64_levels = int(coarse_fp64_levels)
+        opt.delta_l = int(delta_l)
+        ptr = L.fmm_plan_create_ex(int(n), int(p), int(isolated), ctypes.byref(opt))
+        if not ptr:
+            raise FmmError(L.fmm_last_status(), last_error())
+        self._ptr = ptr
+        self.n, self.p, self.precision = int(n), int(p), precision
+        self.nmax = self.p if nmax is None else int(nmax)
+        self.finest_level = int(np.log2(n)) - 1
+
+    @property
+    def ptr(self) -> int:
+        if not self._ptr:
+            raise RuntimeError("plan is closed")
+        return self._ptr
+
+    @property
+    def io_dtype(self):
+        import torch
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    def workspace_bytes(self) -> int:
+        return int(lib().fmm_plan_workspace_bytes(self.ptr))
+
+    def close(self):
+        if getattr(self, "_ptr", None):
+            lib().fmm_plan_destroy(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check_tensor(self, t, shape, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+        if t.dtype != self.io_dtype:
+            raise TypeError(f"{name} must be {self.io_dtype} for a {self.precision} plan (got {t.dtype})")
+        if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape {tuple(shape)} (got {tuple(t.shape)})")
+
+    def solve_into(self, rho, phi, g=None, stream=None):
+        n = self.n
+        self._check_tensor(rho, (n, n, n), "rho")
+        self._check_tensor(phi, (n, n, n), "phi")
+        if g is not None:
+            self._check_tensor(g, (3, n, n, n), "g")
+        _check(lib().fmm_solve(self.ptr, rho.data_ptr(), phi.data_ptr(),
+                               None if g is None else g.data_ptr(), _stream_ptr(stream)))
+
+    def solve(self, rho, want_g: bool = True, stream=None):
+        """(phi, g) of rho on the current stream (g is None if not wanted)."""
+        import torch
+        n = self.n
+        phi = torch.empty((n, n, n), dtype=self.io_dtype, device=rho.device)
+        g = torch.empty((3, n, n, n), dtype=self.io_dtype, device=rho.device) if want_g else None
+        self.solve_into(rho, phi, g, stream)
+        return phi, g
+
+    def backward(self, dphi, dg=None, stream=None):
+        """drho = d(<phi, dphi> + <g, dg>)/drho."""
+        import torch
+        n = self.n
+        self._check_tensor(dphi, (n, n, n), "dphi")
+        if dg is not None:
+            self._check_tensor(dg, (3, n, n, n), "dg")
+        drho = torch.empty((n, n, n), dtype=self.io_dtype, device=dphi.device)
+        _check(lib().fmm_solve_backward(self.ptr, dphi.data_ptr(), None if dg is None else dg.data_ptr(),
+                                        drho.data_ptr(), _stream_ptr(stream)))
+        return drho
+
+    def expansions(self, which: str, level: int) -> np.ndarray:
+        """Scaled multipoles ('M') or locals ('L') of `level` after a solve,
+        (8^level, nterms) float64 in the order of ``multi_index``."""
+        import torch
+        torch.cuda.synchronize()
+        nt = (self.nmax + 1) * (self.nmax + 2) * (self.nmax + 3) // 6 if which == "M" else \
+            (self.p + 1) * (self.p + 2) * (self.p + 3) // 6
+        out = np.zeros((8 ** level, nt))
+        _check(lib().fmm_debug_expansions(self.ptr, 0 if which == "M" else 1, level,
+                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size))
+        return out
+
+
+def _autograd_fn():
+    import torch
+
+    class _FmmSolve(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, rho, plan):
+            ctx.plan = plan
+            phi, g = plan.solve(rho.contiguous())
+            return phi, g
+
+        @staticmethod
+        def backward(ctx, dphi, dg):
+            plan = ctx.plan
+            if dphi is None:
+                dphi = torch.zeros((plan.n,) * 3, dtype=plan.io_dtype, device=dg.device)
+            drho = plan.backward(dphi.contiguous(), None if dg is None else dg.contiguous())
+            return drho, None
+
+    return _FmmSolve
+
+
+_FN = None
+
+
+def solve(plan: Plan, rho):
+    """Differentiable (phi, g) = FMM(rho); backward runs the adjoint kernels."""
+    global _FN
+    if _FN is None:
+        _FN = _autograd_fn()
+    return _FN.apply(rho, plan)

@@ -1,0 +1,154 @@
+"""The C-ABI library: it loads, exports every symbol include/fmm.h declares,
+and rejects invalid arguments before touching a device.  No compute calls."""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fmm.h")
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_2606_13793_amd import fmm
+    if not os.path.exists(fmm.LIB_PATH):
+        from paper_2606_13793_amd import build
+        build.build()
+    return fmm
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fmm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_lists_the_boundary():
+    names = header_functions()
+    for required in ("fmm_plan_create", "fmm_solve", "fmm_solve_backward", "fmm_plan_destroy", "fmm_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(F):
+    L = F.lib()
+    names = header_functions()
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(F.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", F.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (fmm_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_library_is_built_for_gfx950(F):
+    out = subprocess.run(["/opt/rocm/bin/roc-obj-ls", F.LIB_PATH], capture_output=True, text=True)
+    if out.returncode != 0:
+        pytest.skip("roc-obj-ls unavailable")
+    assert "gfx950" in out.stdout
+
+
+def _create(F, n, p, isolated=1, **opt):
+    L = F.lib()
+    o = F.FmmOptions()
+    L.fmm_options_default(ctypes.byref(o))
+    for k, v in opt.items():
+        setattr(o, k, v)
+    ptr = L.fmm_plan_create_ex(n, p, isolated, ctypes.byref(o))
+    return ptr, L.fmm_last_status(), F.last_error()
+
+
+@pytest.mark.parametrize("n,p,iso,code,text", [
+    (12, 4, 1, -1, "power of two"),
+    (4, 4, 1, -1, "power of two"),
+    (2048, 4, 1, -1, "power of two"),
+    (16, 0, 1, -1, "p must be"),
+    (16, 9, 1, -1, "p must be"),
+    (16, 4, 0, -2, "isolated"),
+    (16, 4, 2, -1, "isolated"),
+])
+def test_invalid_sizes_rejected_without_device(F, n, p, iso, code, text):
+    ptr, status, msg = _create(F, n, p, iso)
+    assert not ptr
+    assert status == code
+    assert text in msg
+
+
+@pytest.mark.parametrize("opt,code", [
+    ({"delta_l": 2}, -2),
+    ({"nmax": 7}, -1),
+    ({"nmax": -3}, -1),
+    ({"precision": 5}, -1),
+    ({"struct_size": 4}, -1),
+    ({"coarse_fp64_levels": -1}, -1),
+])
+def test_invalid_options_rejected(F, opt, code):
+    ptr, status, msg = _create(F, 16, 4, **opt)
+    assert not ptr and status == code and msg
+
+
+def test_workspace_cap_reports_out_of_memory():
+    code = (
+        "import ctypes, os\n"
+        "from paper_2606_13793_amd import fmm\n"
+        "L = fmm.lib()\n"
+        "p = L.fmm_plan_create(256, 6, 1)\n"
+        "print(bool(p), L.fmm_last_status(), fmm.last_error())\n"
+    )
+    env = dict(os.environ, FMM_TEST_MAX_WORKSPACE="1000000")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=ROOT)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.startswith("False -3"), out.stdout
+    assert "FMM_TEST_MAX_WORKSPACE" in out.stdout
+
+
+def test_null_arguments(F):
+    L = F.lib()
+    assert L.fmm_solve(None, None, None, None, None) == -1
+    assert "plan is NULL" in F.last_error()
+    assert L.fmm_solve_backward(None, None, None, None, None) == -1
+    assert L.fmm_plan_workspace_bytes(None) == 0
+    L.fmm_plan_destroy(None)  # NULL-safe
+    assert L.fmm_options_default(None) == -1
+    assert L.fmm_last_error() is not None
+
+
+def test_options_default(F):
+    o = F.FmmOptions()
+    assert F.lib().fmm_options_default(ctypes.byref(o)) == 0
+    assert o.struct_size == ctypes.sizeof(F.FmmOptions)
+    assert (o.precision, o.nmax, o.coarse_fp64_levels, o.delta_l, o.check_finite) == (0, -1, 4, 1, 0)
+
+
+def test_multi_index_order(F):
+    """Graded order: all terms of degree n, x exponent ascending, then y."""
+    for P in range(0, 10):
+        mi = F.multi_index(P)
+        assert len(mi) == (P + 1) * (P + 2) * (P + 3) // 6
+        assert len({tuple(r) for r in mi}) == len(mi)
+        deg = mi.sum(1)
+        assert (mi >= 0).all() and (deg <= P).all() and (deg[1:] >= deg[:-1]).all()
+        for n in range(P + 1):
+            block = [tuple(r) for r in mi[deg == n]]
+            assert block == sorted(block, key=lambda e: (e[0], e[1]))
+    assert F.lib().fmm_multi_index(10, None, 0) == -1
+
+
+def test_no_device_is_reported(F):
+    """Valid arguments with no GPU visible: a device error, not a crash."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    ptr, status, msg = _create(F, 16, 4)
+    assert not ptr and status == -4 and "device" in msg.lower()
+
+
+def test_binding_refuses_cpu_tensors(F):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    with pytest.raises(F.FmmError):
+        F.Plan(16, 4)
