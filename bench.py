@@ -1,0 +1,195 @@
+#!/usr/bin/env python
+"""Benchmark of the unigrid FMM solve on one MI355X.
+
+Workload (default): 256^3 unigrid, isolated BC, p = 6, FP64; density = sum
+of 256 seeded Plummer spheres (seed 256).  A step is one full solve (upward
+pass, M2L/L2L over all levels, near field + L2P, M2P) producing phi and g,
+with the density already resident in HBM.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+  value         grid cells per second (n^3 x steps / timed seconds)
+  roofline      the dominant kernel (M2P) against the FP64 matrix-core peak,
+                from HIP events recorded on the solve's stream
+  cpu_baseline  the FP64 CPU oracle on this host, on a bounded sample (full
+                upward pass + downward pass for a slab of cells), scaled to
+                cells per second of a full solve
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid cells/s per FMM solve at 256^3 p=6 (FP64 vs mixed); M2L MFMA util"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--p", type=int, default=6)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--spheres", type=int, default=256)
+    ap.add_argument("--seed", type=int, default=256)
+    ap.add_argument("--cpu-planes", type=int, default=16,
+                    help="unigrid planes of the oracle's downward-pass sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(every box has one MI355X; see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import fmm_inputs as fi
+    from paper_2606_13793_amd import costs, fmm
+
+    if not os.path.exists(fmm.LIB_PATH):
+        log("libfmm.so missing, building")
+        from paper_2606_13793_amd import build
+        build.build()
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a HIP device")
+
+    n, p, prec = args.n, args.p, args.precision
+    dev = "cuda"
+    log(f"workload n={n} p={p} precision={prec} spheres={args.spheres} seed={args.seed}")
+    params = fi.multi_plummer_params(args.spheres, args.seed)
+    rho64 = fi.plummer_density(n, params, device=dev)
+    torch.cuda.synchronize()
+    plan = fmm.Plan(n, p, prec)
+    rho = rho64 if prec == "fp64" else rho64.float()
+    phi = torch.empty((n, n, n), dtype=plan.io_dtype, device=dev)
+    g = torch.empty((3, n, n, n), dtype=plan.io_dtype, device=dev)
+    log(f"plan ready: {plan.workspace_bytes() / 2**30:.2f} GiB workspace")
+
+    for _ in range(args.warmup):
+        plan.solve_into(rho, phi, g)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.solve_into(rho, phi, g)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.profile(False)
+    prof = plan.profile_read()
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    cells_per_s = n ** 3 * args.steps / elapsed
+    log(f"timed {args.steps} solves: {ms_per_step:.3f} ms/solve, {cells_per_s:.4e} cells/s")
+
+    flops = costs.solve_flops(n, p)
+    stages = {}
+    for name, (ms, launches) in prof.items():
+        if launches or ms:
+            stages[name] = {"ms_per_step": ms / args.steps, "launches_per_step": launches / args.steps}
+            if name in flops and ms > 0:
+                stages[name]["tflops"] = flops[name] * args.steps / (ms * 1e-3) / 1e12
+    m2p_ms, m2p_launches = prof["m2p"]
+    m2p_avg_s = m2p_ms * 1e-3 / max(m2p_launches, 1)
+    m2p_tflops = flops["m2p"] / m2p_avg_s / 1e12
+    peak = PEAK_TFLOPS[prec]
+    roofline = {
+        "kernel": "M2P (k_m2p)",
+        "bound": "mfma",
+        "achieved": round(m2p_tflops, 3),
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": round(m2p_tflops / peak, 4),
+        "traffic": None,
+        "avg_launch_ms": round(m2p_avg_s * 1e3, 4),
+        "flops_per_launch": flops["m2p"],
+        "pairs_per_launch": costs.m2p_pairs(n),
+    }
+    m2l_ms, m2l_launches = prof["m2l"]
+    solve_tflops = flops["total"] / (elapsed / args.steps) / 1e12
+    extra = {
+        "m2l": {"tflops": round(flops["m2l"] / (m2l_ms * 1e-3 / args.steps) / 1e12, 3) if m2l_ms else None,
+                "frac_of_peak": round(flops["m2l"] / (m2l_ms * 1e-3 / args.steps) / 1e12 / peak, 4) if m2l_ms else None,
+                "launches_per_step": m2l_launches / args.steps},
+        "solve_tflops": round(solve_tflops, 3),
+        "solve_frac_of_peak": round(solve_tflops / peak, 4),
+        "useful_flops_per_solve": flops["total"],
+    }
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        planes = args.cpu_planes
+        i0 = n // 2 - planes // 2
+        cells = np.arange(i0 * n * n, (i0 + planes) * n * n, dtype=np.int64)
+        log(f"cpu baseline: oracle upward pass + downward on {planes} planes ({len(cells)} cells)")
+        rho_host = rho64.cpu().numpy() if prec == "fp64" else rho.double().cpu().numpy()
+        phi_o, g_o, t_up, t_down, threads = oracle.solve_timed(rho_host, p, cells)
+        t_full = t_up + t_down * (n ** 3 / len(cells))
+        cpu = {
+            "value": n ** 3 / t_full,
+            "unit": "cells/s",
+            "cores": threads,
+            "kind": "oracle",
+            "sample": (f"FP64 oracle on this host, {threads} OpenMP threads: full upward pass ({t_up:.2f} s) + "
+                       f"downward pass for {planes} central unigrid planes ({len(cells)} cells, {t_down:.2f} s); "
+                       f"full solve = upward + downward x n^3/{len(cells)} = {t_full:.1f} s"),
+        }
+        log(f"cpu baseline: {cpu['value']:.4e} cells/s ({threads} threads)")
+        idx = torch.as_tensor(cells, device=dev)
+        phi_s = phi.reshape(-1)[idx].double().cpu().numpy()
+        g_s = g.reshape(3, -1)[:, idx].double().cpu().numpy()
+        parity = {
+            "cells": int(len(cells)),
+            "phi_rel_l2": float(np.linalg.norm(phi_s - phi_o) / np.linalg.norm(phi_o)),
+            "g_rel_l2": float(np.linalg.norm(g_s - g_o) / np.linalg.norm(g_o)),
+        }
+        log(f"parity on the slab: {parity}")
+
+    out = {
+        "metric": METRIC,
+        "value": cells_per_s,
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[prec],
+        "data": "synthetic",
+        "config": {
+            "workload": f"{n}^3 unigrid FMM solve, isolated BC, p={p}, {prec}, phi+g, "
+                        f"{args.spheres}-sphere multi-Plummer density (seed {args.seed})",
+            "n": n, "p": p, "precision": prec, "spheres": args.spheres, "seed": args.seed,
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "stages": stages,
+        "kernels": extra,
+        "parity_vs_oracle": parity,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -134,6 +134,22 @@ int fmm_last_status(void);
  */
 int fmm_debug_expansions(fmm_plan* plan, int which, int level, double* out, size_t count);
 
+/*
+ * Per-stage device timing with HIP events recorded on the solve's stream.
+ * fmm_profile_enable(plan, 1) makes every following fmm_solve /
+ * fmm_solve_backward record an event pair around each stage; 0 stops it.
+ * fmm_profile_read waits for the recorded events, writes for each stage s <
+ * nstages the summed milliseconds ms[s] and the number of kernel launches
+ * launches[s] they cover (either may be NULL), and clears the record.
+ * Stages: 0 P2M, 1 M2M, 2 M2L, 3 L2L, 4 near field + L2P, 5 M2P, 6 whole
+ * call, 7 backward (whole call).  Names via fmm_profile_stage_name (NULL
+ * past the last stage).  The plan owns the events; recording adds two event
+ * records per stage to the stream.
+ */
+int fmm_profile_enable(fmm_plan* plan, int enable);
+int fmm_profile_read(fmm_plan* plan, double* ms, int* launches, int nstages);
+const char* fmm_profile_stage_name(int stage);
+
 /* Multi-index order of the expansions: out[3*t + d] = exponent of axis d of
  * term t, for the nterms = (P+1)(P+2)(P+3)/6 terms of order <= P.  `out` holds
  * 3 * nterms ints.  Returns nterms, or FMM_ERR_INVALID_ARG. */

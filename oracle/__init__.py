@@ -56,6 +56,9 @@ def lib():
                                     ctypes.c_int, ctypes.c_int, _dp]
         L.or_direct.argtypes = [ctypes.c_int, _dp, ctypes.c_longlong, _lp, _dp, _dp]
         L.or_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
+        L.or_solve_timed.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
+                                     ctypes.c_longlong, _lp, _dp, _dp, _dp]
+        L.or_threads.argtypes = []
         L.or_pair_pass.argtypes = [ctypes.c_int, ctypes.c_longlong, ctypes.c_longlong]
         L.or_list_size.argtypes = [ctypes.c_int] * 4
         L.or_pair_pass_row.argtypes = [ctypes.c_int, ctypes.c_longlong, _ip]
@@ -209,3 +212,18 @@ def pair_pass_row(n: int, u: int) -> np.ndarray:
     out = np.zeros(n ** 3, dtype=np.int32)
     lib().or_pair_pass_row(n, u, out.ctypes.data_as(_ip))
     return out
+
+
+def solve_timed(rho, p: int, targets, nmax: int | None = None):
+    """solve() at the listed targets, plus (upward s, downward s, threads)."""
+    rho = _f64(rho)
+    n = rho.shape[0]
+    nmax = p if nmax is None else nmax
+    t = np.ascontiguousarray(targets, dtype=np.int64)
+    phi = np.zeros(len(t))
+    g = np.zeros((3, len(t)))
+    times = np.zeros(2)
+    rc = lib().or_solve_timed(n, p, nmax, _d(rho), len(t), t.ctypes.data_as(_lp), _d(phi), _d(g), _d(times))
+    if rc != 0:
+        raise ValueError("bad arguments")
+    return phi, g, float(times[0]), float(times[1]), int(lib().or_threads())

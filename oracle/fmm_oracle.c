@@ -60,6 +60,17 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static double wall_seconds(void) {
+#ifdef _OPENMP
+  return omp_get_wtime();
+#else
+  return 0.0;
+#endif
+}
 
 #define OR_PMAX 9     /* highest derivative order needed: p + 1, p <= 8 */
 #define OR_NTMAX 220  /* number of multi-indices with |a| <= 9 */
@@ -515,11 +526,13 @@ int or_op_m2p(int nmax, const double *R, const double *M, double *out4) {
  *                  only the ancestors of the targets get local expansions.
  * Returns 0, or -1 on invalid arguments.
  */
-int or_solve(int n, int p, int nmax, const double *rho, i64 ntarget, const i64 *targets,
-             double *phi, double *g) {
+static int solve_impl(int n, int p, int nmax, const double *rho, i64 ntarget, const i64 *targets,
+                      double *phi, double *g, double *times) {
   ostate s;
   if (st_init(&s, n, p, nmax) != 0) return -1;
+  const double t0 = wall_seconds();
   upward(&s, rho);
+  const double t1 = wall_seconds();
   const int F = s.F, nF = 1 << F;
   unsigned char *need[32] = {0};
   if (targets) {
@@ -558,7 +571,29 @@ int or_solve(int n, int p, int nmax, const double *rho, i64 ntarget, const i64 *
   free(tab);
   for (int k = 0; k < 32; ++k) free(need[k]);
   st_free(&s);
+  if (times) { times[0] = t1 - t0; times[1] = wall_seconds() - t1; }
   return 0;
+}
+
+int or_solve(int n, int p, int nmax, const double *rho, i64 ntarget, const i64 *targets,
+             double *phi, double *g) {
+  return solve_impl(n, p, nmax, rho, ntarget, targets, phi, g, NULL);
+}
+
+/* or_solve that also reports wall seconds of the upward pass (times[0]) and
+   of the downward pass for the requested targets (times[1]). */
+int or_solve_timed(int n, int p, int nmax, const double *rho, i64 ntarget, const i64 *targets,
+                   double *phi, double *g, double *times) {
+  return solve_impl(n, p, nmax, rho, ntarget, targets, phi, g, times);
+}
+
+/* OpenMP threads the oracle runs with. */
+int or_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }
 
 /* Multipoles (level 2..F) or locals (level 3..F) of the full solve, in

@@ -78,6 +78,11 @@ size_t plan_bytes(int n, int p) {
 
 void release(fmm_plan* pl) {
   if (!pl) return;
+  for (auto& r : pl->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto ev : pl->event_pool) (void)hipEventDestroy(ev);
   for (auto& lv : pl->lev) {
     if (lv.M) (void)hipFree(lv.M);
     if (lv.L) (void)hipFree(lv.L);
@@ -120,7 +125,37 @@ std::vector<int> build_dlists() {
   return out;
 }
 
+hipEvent_t take_event(fmm_plan* pl) {
+  if (!pl->event_pool.empty()) {
+    hipEvent_t e = pl->event_pool.back();
+    pl->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+const char* const kStageNames[fmm::ST_COUNT] = {"p2m", "m2m", "m2l", "l2l", "near_l2p", "m2p", "solve", "backward"};
+
 }  // namespace
+
+namespace fmm {
+StageScope::StageScope(fmm_plan* pl, int stage, int launches, hipStream_t s) : pl_(pl), s_(s) {
+  if (!pl->profiling) return;
+  StageRec r{stage, launches, take_event(pl), take_event(pl)};
+  if (!r.a || !r.b) return;
+  if (hipEventRecord(r.a, s) != hipSuccess) return;
+  idx_ = (int)pl->recs.size();
+  pl->recs.push_back(r);
+}
+StageScope::~StageScope() {
+  if (idx_ >= 0) (void)hipEventRecord(pl_->recs[idx_].b, s_);
+}
+}  // namespace fmm
 
 extern "C" {
 
@@ -263,6 +298,7 @@ int fmm_solve(fmm_plan* plan, const void* rho, void* phi, void* g, void* stream)
       return fail(FMM_ERR_DEVICE, "finite check failed: %s", hipGetErrorString(e));
     if (bad) return fail(FMM_ERR_NONFINITE, "rho holds NaN or Inf");
   }
+  fmm::StageScope whole(plan, fmm::ST_SOLVE, 0, s);
   if ((e = fmm::launch_solve(plan, rho, phi, g, s)) != hipSuccess) {
     (void)hipGetLastError();
     return fail(FMM_ERR_DEVICE, "solve launch failed: %s", hipGetErrorString(e));
@@ -274,6 +310,7 @@ int fmm_solve_backward(fmm_plan* plan, const void* dphi, const void* dg, void* d
   if (!plan) return fail(FMM_ERR_INVALID_ARG, "plan is NULL");
   if (!dphi || !drho) return fail(FMM_ERR_INVALID_ARG, "dphi and drho must be device pointers (got NULL)");
   if (drho == dphi || (dg && (dg == drho || dg == dphi))) return fail(FMM_ERR_INVALID_ARG, "buffers must not alias");
+  fmm::StageScope whole(plan, fmm::ST_BACKWARD, 0, (hipStream_t)stream);
   hipError_t e = fmm::launch_backward(plan, dphi, dg, drho, (hipStream_t)stream);
   if (e == hipErrorNotSupported) return fail(FMM_ERR_UNSUPPORTED, "backward pass is not built for this plan");
   if (e != hipSuccess) {
@@ -281,6 +318,41 @@ int fmm_solve_backward(fmm_plan* plan, const void* dphi, const void* dg, void* d
     return fail(FMM_ERR_DEVICE, "backward launch failed: %s", hipGetErrorString(e));
   }
   return ok();
+}
+
+int fmm_profile_enable(fmm_plan* plan, int enable) {
+  if (!plan) return fail(FMM_ERR_INVALID_ARG, "plan is NULL");
+  plan->profiling = enable ? 1 : 0;
+  return ok();
+}
+
+int fmm_profile_read(fmm_plan* plan, double* ms, int* launches, int nstages) {
+  if (!plan) return fail(FMM_ERR_INVALID_ARG, "plan is NULL");
+  if (nstages < 0) return fail(FMM_ERR_INVALID_ARG, "nstages < 0");
+  for (int s = 0; s < nstages; ++s) {
+    if (ms) ms[s] = 0.0;
+    if (launches) launches[s] = 0;
+  }
+  int rc = FMM_OK;
+  for (auto& r : plan->recs) {
+    float t = 0.0f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) {
+      (void)hipGetLastError();
+      rc = FMM_ERR_DEVICE;
+    } else if (r.stage < nstages) {
+      if (ms) ms[r.stage] += t;
+      if (launches) launches[r.stage] += r.launches;
+    }
+    plan->event_pool.push_back(r.a);
+    plan->event_pool.push_back(r.b);
+  }
+  plan->recs.clear();
+  if (rc != FMM_OK) return fail(rc, "reading profile events failed");
+  return ok();
+}
+
+const char* fmm_profile_stage_name(int stage) {
+  return (stage >= 0 && stage < fmm::ST_COUNT) ? kStageNames[stage] : nullptr;
 }
 
 int fmm_multi_index(int P, int* out, size_t count) {

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 namespace fmm {
 
@@ -94,6 +95,15 @@ struct Level {
 
 }  // namespace fmm
 
+namespace fmm {
+enum Stage { ST_P2M = 0, ST_M2M, ST_M2L, ST_L2L, ST_NEAR, ST_M2P, ST_SOLVE, ST_BACKWARD, ST_COUNT };
+struct StageRec {
+  int stage;
+  int launches;
+  hipEvent_t a, b;
+};
+}  // namespace fmm
+
 struct fmm_plan {
   int n = 0, p = 0, nmax = 0, L = 0, F = 0;
   int precision = 0;
@@ -108,6 +118,10 @@ struct fmm_plan {
   int* dlists = nullptr;    // [8][189] offset index (0..342) per parity
   int* flag = nullptr;      // device scratch flag (finite check)
   size_t bytes = 0;
+  // stage profiling
+  int profiling = 0;
+  std::vector<fmm::StageRec> recs;
+  std::vector<hipEvent_t> event_pool;
 };
 
 namespace fmm {
@@ -117,4 +131,18 @@ hipError_t launch_dtab(fmm_plan* pl, hipStream_t s);
 hipError_t launch_solve(fmm_plan* pl, const void* rho, void* phi, void* g, hipStream_t s);
 hipError_t launch_backward(fmm_plan* pl, const void* dphi, const void* dg, void* drho, hipStream_t s);
 hipError_t launch_check_finite(fmm_plan* pl, const void* rho, int* host_flag, hipStream_t s);
+
+// Records an event pair around a stage when the plan is profiling.
+class StageScope {
+ public:
+  StageScope(fmm_plan* pl, int stage, int launches, hipStream_t s);
+  ~StageScope();
+  StageScope(const StageScope&) = delete;
+  StageScope& operator=(const StageScope&) = delete;
+
+ private:
+  fmm_plan* pl_;
+  hipStream_t s_;
+  int idx_ = -1;
+};
 }  // namespace fmm

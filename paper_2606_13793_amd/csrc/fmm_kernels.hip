@@ -617,19 +617,25 @@ static hipError_t solve_fp64(fmm_plan* pl, const TI* rho, TO* phi, TO* g, hipStr
   const int n = pl->n, F = pl->F;
   hipError_t e;
   {
+    StageScope sc(pl, ST_P2M, 1, s);
     const long long nT = (long long)(n / 2) * (n / 2) * (n / 2);
     hipLaunchKernelGGL((k_p2m<TI>), dim3(blocks_for(nT, 256)), dim3(256), 0, s, rho, (double*)pl->lev[F].M, n, NM, NC);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   for (int k = F; k >= 3; --k) {
+    StageScope sc(pl, ST_M2M, 1, s);
     const long long nP = 1LL << (3 * (k - 1));
     hipLaunchKernelGGL((k_m2m<nterms(PMAX)>), dim3(blocks_for(nP, 4)), dim3(256), 0, s, (const double*)pl->lev[k].M,
                        (double*)pl->lev[k - 1].M, 1 << k, NM, NC);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   for (int k = 3; k <= F; ++k) {
-    if ((e = launch_m2l_groups<P, 0>(pl, k, s)) != hipSuccess) return e;
+    {
+      StageScope sc(pl, ST_M2L, m2l_ngroups(P), s);
+      if ((e = launch_m2l_groups<P, 0>(pl, k, s)) != hipSuccess) return e;
+    }
     if (k >= 4) {
+      StageScope sc(pl, ST_L2L, 1, s);
       const long long nP = 1LL << (3 * (k - 1));
       hipLaunchKernelGGL((k_l2l<nterms(PMAX)>), dim3(blocks_for(nP, 4)), dim3(256), 0, s, (const double*)pl->lev[k - 1].L,
                          (double*)pl->lev[k].L, 1 << k, P, NL);
@@ -637,12 +643,14 @@ static hipError_t solve_fp64(fmm_plan* pl, const TI* rho, TO* phi, TO* g, hipStr
     }
   }
   {
+    StageScope sc(pl, ST_NEAR, 1, s);
     const long long N = (long long)n * n * n;
     const double* Lf = (F >= 3) ? (const double*)pl->lev[F].L : nullptr;
     hipLaunchKernelGGL((k_near<TI, TO>), dim3(blocks_for(N, 256)), dim3(256), 0, s, rho, Lf, phi, g, n, NL, pl->dx);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   {
+    StageScope sc(pl, ST_M2P, 1, s);
     const int nF = n / 2;
     const long long nlat = (long long)(nF / 2) * (nF / 2) * (nF / 2);
     dim3 grid(blocks_for(nlat, 64), 8);

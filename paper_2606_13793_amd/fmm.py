@@ -29,6 +29,7 @@ EXPORTS = (
     "fmm_options_default", "fmm_plan_create", "fmm_plan_create_ex", "fmm_plan_destroy",
     "fmm_solve", "fmm_solve_backward", "fmm_plan_workspace_bytes", "fmm_plan_info",
     "fmm_last_error", "fmm_last_status", "fmm_debug_expansions", "fmm_multi_index",
+    "fmm_profile_enable", "fmm_profile_read", "fmm_profile_stage_name",
 )
 
 
@@ -78,6 +79,10 @@ def lib():
         L.fmm_last_status.restype = ctypes.c_int
         L.fmm_debug_expansions.argtypes = [vp, i, i, ctypes.POINTER(ctypes.c_double), sz]
         L.fmm_multi_index.argtypes = [i, ctypes.POINTER(i), sz]
+        L.fmm_profile_enable.argtypes = [vp, i]
+        L.fmm_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i), i]
+        L.fmm_profile_stage_name.argtypes = [i]
+        L.fmm_profile_stage_name.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -195,6 +200,24 @@ class Plan:
         _check(lib().fmm_solve_backward(self.ptr, dphi.data_ptr(), None if dg is None else dg.data_ptr(),
                                         drho.data_ptr(), _stream_ptr(stream)))
         return drho
+
+    def profile(self, enable: bool = True):
+        """Start (or stop) per-stage HIP-event timing of later calls."""
+        _check(lib().fmm_profile_enable(self.ptr, int(bool(enable))))
+
+    def profile_read(self) -> dict:
+        """{stage: (milliseconds, kernel launches)} since the last read."""
+        L = lib()
+        names = []
+        while True:
+            nm = L.fmm_profile_stage_name(len(names))
+            if nm is None:
+                break
+            names.append(nm.decode())
+        ms = (ctypes.c_double * len(names))()
+        cnt = (ctypes.c_int * len(names))()
+        _check(L.fmm_profile_read(self.ptr, ms, cnt, len(names)))
+        return {nm: (ms[i], cnt[i]) for i, nm in enumerate(names)}
 
     def expansions(self, which: str, level: int) -> np.ndarray:
         """Scaled multipoles ('M') or locals ('L') of `level` after a solve,
