@@ -100,33 +100,34 @@ def main():
     log(f"timed {args.steps} solves: {ms_per_step:.3f} ms/solve, {cells_per_s:.4e} cells/s")
 
     flops = costs.solve_flops(n, p)
+    stage_flops = {"p2m": flops["p2m"], "m2m": flops["m2m"], "m2l": flops["m2l_l2l"], "bottom": flops["bottom"]}
     stages = {}
     for name, (ms, launches) in prof.items():
         if launches or ms:
             stages[name] = {"ms_per_step": ms / args.steps, "launches_per_step": launches / args.steps}
-            if name in flops and ms > 0:
-                stages[name]["tflops"] = flops[name] * args.steps / (ms * 1e-3) / 1e12
-    m2p_ms, m2p_launches = prof["m2p"]
-    m2p_avg_s = m2p_ms * 1e-3 / max(m2p_launches, 1)
-    m2p_tflops = flops["m2p"] / m2p_avg_s / 1e12
+            if name in stage_flops and ms > 0:
+                stages[name]["tflops"] = stage_flops[name] * args.steps / (ms * 1e-3) / 1e12
+    bot_ms, bot_launches = prof["bottom"]
+    bot_avg_s = bot_ms * 1e-3 / max(bot_launches, 1)
+    bot_tflops = stage_flops["bottom"] / bot_avg_s / 1e12
     peak = PEAK_TFLOPS[prec]
     roofline = {
-        "kernel": "M2P (k_m2p)",
+        "kernel": "bottom: M2P + L2P + near field (k_m2p)",
         "bound": "mfma",
-        "achieved": round(m2p_tflops, 3),
+        "achieved": round(bot_tflops, 3),
         "peak": peak,
         "unit": "TFLOP/s",
-        "frac": round(m2p_tflops / peak, 4),
+        "frac": round(bot_tflops / peak, 4),
         "traffic": None,
-        "avg_launch_ms": round(m2p_avg_s * 1e3, 4),
-        "flops_per_launch": flops["m2p"],
-        "pairs_per_launch": costs.m2p_pairs(n),
+        "avg_launch_ms": round(bot_avg_s * 1e3, 4),
+        "flops_per_launch": stage_flops["bottom"],
+        "m2p_pairs_per_launch": costs.m2p_pairs(n),
     }
     m2l_ms, m2l_launches = prof["m2l"]
     solve_tflops = flops["total"] / (elapsed / args.steps) / 1e12
     extra = {
-        "m2l": {"tflops": round(flops["m2l"] / (m2l_ms * 1e-3 / args.steps) / 1e12, 3) if m2l_ms else None,
-                "frac_of_peak": round(flops["m2l"] / (m2l_ms * 1e-3 / args.steps) / 1e12 / peak, 4) if m2l_ms else None,
+        "m2l": {"tflops": round(stage_flops["m2l"] / (m2l_ms * 1e-3 / args.steps) / 1e12, 3) if m2l_ms else None,
+                "frac_of_peak": round(stage_flops["m2l"] / (m2l_ms * 1e-3 / args.steps) / 1e12 / peak, 4) if m2l_ms else None,
                 "launches_per_step": m2l_launches / args.steps},
         "solve_tflops": round(solve_tflops, 3),
         "solve_frac_of_peak": round(solve_tflops / peak, 4),

@@ -141,8 +141,8 @@ int fmm_debug_expansions(fmm_plan* plan, int which, int level, double* out, size
  * fmm_profile_read waits for the recorded events, writes for each stage s <
  * nstages the summed milliseconds ms[s] and the number of kernel launches
  * launches[s] they cover (either may be NULL), and clears the record.
- * Stages: 0 P2M, 1 M2M, 2 M2L, 3 L2L, 4 near field + L2P, 5 M2P, 6 whole
- * call, 7 backward (whole call).  Names via fmm_profile_stage_name (NULL
+ * Stages: 0 P2M, 1 M2M, 2 M2L (with L2L), 3 bottom (M2P, L2P and near
+ * field), 4 whole solve, 5 whole backward.  Names via fmm_profile_stage_name (NULL
  * past the last stage).  The plan owns the events; recording adds two event
  * records per stage to the stream.
  */

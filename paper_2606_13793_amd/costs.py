@@ -67,6 +67,9 @@ def solve_flops(n: int, p: int, nmax: int | None = None) -> dict:
     out["near_l2p"] = 8 * near_pairs(n) + (8 * NL * n ** 3 if F >= 3 else 0)
     out["m2p"] = 2 * 4 * NM * 8 * list_pairs(2 ** F)
     out["total"] = sum(out.values())
+    # per fused kernel stage of the HIP solve
+    out["m2l_l2l"] = out["m2l"] + out["l2l"]
+    out["bottom"] = out["m2p"] + out["near_l2p"]
     return out
 
 

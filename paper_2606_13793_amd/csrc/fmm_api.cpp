@@ -68,6 +68,7 @@ size_t plan_bytes(int n, int p) {
   const int F = ilog2_exact(n) - 1;
   const int NM = fmm::nterms(p), NC = (NM + 3) / 4, NCL = NC, ND = fmm::nterms(p + 1);
   size_t b = (size_t)343 * 8 * ND * sizeof(double) + 8 * fmm::NLIST * sizeof(int) + 256;
+  b += ((size_t)343 * NC * 128 + (size_t)NCL * 128 + 54 * 128) * sizeof(double);
   for (int k = 2; k <= F; ++k) {
     const size_t nkp = (size_t)(1 << k) + 6;
     b += (size_t)NC * nkp * nkp * nkp * 4 * sizeof(double);
@@ -90,6 +91,9 @@ void release(fmm_plan* pl) {
   if (pl->dtab) (void)hipFree(pl->dtab);
   if (pl->dtab32) (void)hipFree(pl->dtab32);
   if (pl->dlists) (void)hipFree(pl->dlists);
+  if (pl->wm2p) (void)hipFree(pl->wm2p);
+  if (pl->wl2p) (void)hipFree(pl->wl2p);
+  if (pl->wp2p) (void)hipFree(pl->wp2p);
   if (pl->flag) (void)hipFree(pl->flag);
   delete pl;
 }
@@ -139,7 +143,7 @@ hipEvent_t take_event(fmm_plan* pl) {
   return e;
 }
 
-const char* const kStageNames[fmm::ST_COUNT] = {"p2m", "m2m", "m2l", "l2l", "near_l2p", "m2p", "solve", "backward"};
+const char* const kStageNames[fmm::ST_COUNT] = {"p2m", "m2m", "m2l", "bottom", "solve", "backward"};
 
 }  // namespace
 
@@ -224,6 +228,9 @@ fmm_plan* fmm_plan_create_ex(int n, int p, int isolated, const fmm_options* opt)
   };
   if (dev_alloc(pl, (void**)&pl->dtab, (size_t)343 * 8 * pl->ND * sizeof(double))) return bail();
   if (dev_alloc(pl, (void**)&pl->dlists, 8 * fmm::NLIST * sizeof(int))) return bail();
+  if (dev_alloc(pl, (void**)&pl->wm2p, (size_t)343 * pl->NC * 128 * sizeof(double))) return bail();
+  if (dev_alloc(pl, (void**)&pl->wl2p, (size_t)pl->NCL * 128 * sizeof(double))) return bail();
+  if (dev_alloc(pl, (void**)&pl->wp2p, (size_t)54 * 128 * sizeof(double))) return bail();
   if (dev_alloc(pl, (void**)&pl->flag, 256)) return bail();
   for (int k = 2; k <= pl->F; ++k) {
     fmm::Level& lv = pl->lev[k];

@@ -96,7 +96,7 @@ struct Level {
 }  // namespace fmm
 
 namespace fmm {
-enum Stage { ST_P2M = 0, ST_M2M, ST_M2L, ST_L2L, ST_NEAR, ST_M2P, ST_SOLVE, ST_BACKWARD, ST_COUNT };
+enum Stage { ST_P2M = 0, ST_M2M, ST_M2L, ST_BOTTOM, ST_SOLVE, ST_BACKWARD, ST_COUNT };
 struct StageRec {
   int stage;
   int launches;
@@ -116,6 +116,9 @@ struct fmm_plan {
   double* dtab = nullptr;   // [343][8][ND] D[g](Rhat) in FP64
   float* dtab32 = nullptr;  // FP32 copy for mixed plans
   int* dlists = nullptr;    // [8][189] offset index (0..342) per parity
+  double* wm2p = nullptr;   // bottom kernel B operands in fragment order
+  double* wl2p = nullptr;
+  double* wp2p = nullptr;
   int* flag = nullptr;      // device scratch flag (finite check)
   size_t bytes = 0;
   // stage profiling

@@ -3,10 +3,10 @@
 // Pass order of one solve (Sec. 2 of the paper):
 //   k_p2m            rho -> Mhat_F                       eq. (multipole)
 //   k_m2m            Mhat_k -> Mhat_{k-1}, k = F..3      eq. (M2M)
-//   k_m2l_f64        Mhat_{k-1} -> Lhat_k,  k = 3..F     eq. (M2L), oct-shared lists (Sec. 2.2)
-//   k_l2l            Lhat_{k-1} -> Lhat_k (+=), k=4..F   eq. (L2L)
-//   k_near           rho, Lhat_F -> phi, g               eq. (direct) + L2P
-//   k_m2p_f64        Mhat_F -> phi, g (+=)               M2P at the unigrid centres (Sec. 4)
+//   k_m2l_f64        Mhat_{k-1}, Lhat_{k-1} -> Lhat_k    eq. (M2L) over the oct-shared lists
+//                                                        (Sec. 2.2) + eq. (L2L) from the parent
+//   k_m2p_f64        Mhat_F, Lhat_F, rho -> phi, g       M2P at the unigrid centres (Sec. 4),
+//                                                        L2P and the near field, eq. (direct)
 //
 // Layouts: multipoles and locals are "chunked", [ceil(terms/4)][cells][4], so
 // that a matrix-core operand fragment (4 consecutive terms of one cell) is one
@@ -231,114 +231,6 @@ __global__ __launch_bounds__(256) void k_m2m(const double* __restrict__ Mc, doub
 }
 
 // ---------------------------------------------------------------------------
-// L2L: Lhat_k[T][b] += sum_{|b|+|g|<=p} 2^-(|b|+1) 4^-|g| / g! (2q-1)^g Lhat_{k-1}[P][b+g]
-// Block = 4 parents (32 children); parent locals staged in LDS.
-// ---------------------------------------------------------------------------
-template <int NLX>
-__global__ __launch_bounds__(256) void k_l2l(const double* __restrict__ Lp, double* __restrict__ Lc, int nk, int p, int NL) {
-  __shared__ double S[4][NLX];
-  const int np = nk >> 1;
-  const long long ncp = (long long)np * np * np, ncc = (long long)nk * nk * nk;
-  const long long P0 = (long long)blockIdx.x * 4;
-  for (int w = threadIdx.x; w < 4 * NL; w += blockDim.x) {
-    const int pl = w / NL, b = w % NL;
-    const long long P = P0 + pl;
-    S[pl][b] = (P < ncp) ? Lp[((b >> 2) * ncp + P) * 4 + (b & 3)] : 0.0;
-  }
-  __syncthreads();
-  for (int w = threadIdx.x; w < 32 * NL; w += blockDim.x) {
-    const int ch = w / NL, b = w % NL;
-    const int pl = ch >> 3, q = ch & 7;
-    const long long P = P0 + pl;
-    if (P >= ncp) continue;
-    const int ex = c_mi_exp[b];
-    const int a0 = mi_a(ex), b0 = mi_b(ex), c0 = mi_c(ex);
-    const int m = a0 + b0 + c0;
-    const int q0 = (q >> 2) & 1, q1 = (q >> 1) & 1, q2 = q & 1;
-    double acc = 0.0;
-    for (int gx = 0; gx <= p - m; ++gx)
-      for (int gy = 0; gx + gy <= p - m; ++gy)
-        for (int gz = 0; gx + gy + gz <= p - m; ++gz) {
-          const int ng = gx + gy + gz;
-          const int sgn = ((1 - q0) * gx + (1 - q1) * gy + (1 - q2) * gz) & 1;
-          const double c = ldexp(c_mi_invfact[mi_index(gx, gy, gz)], -2 * ng);
-          const double v = S[pl][mi_index(a0 + gx, b0 + gy, c0 + gz)];
-          acc += sgn ? -c * v : c * v;
-        }
-    acc = ldexp(acc, -(m + 1));
-    const int p2 = (int)(P % np), p1 = (int)((P / np) % np), p0 = (int)(P / ((long long)np * np));
-    const long long T = ((long long)(2 * p0 + q0) * nk + (2 * p1 + q1)) * nk + (2 * p2 + q2);
-    Lc[((b >> 2) * ncc + T) * 4 + (b & 3)] += acc;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Near field and L2P at every unigrid cell u = 2T + q:
-//   phi = -dx^2 sum_w rho_w / max(|u-w|,1)  +  dx^2/2 sum_b Lhat_F[b] c_b(q)
-//   g   = -dx   sum_w rho_w (u-w)/|u-w|^3  +  dx s_d sum_b b_d Lhat_F[b] c_b(q)
-// with c_b(q) = (2q-1)^b 4^-|b| / b!, s_d = 1 - 2 q_d, and w over the 6^3
-// unigrid cells whose FMM cell is adjacent to T (clipped at the box).
-// ---------------------------------------------------------------------------
-template <typename TI, typename TO>
-__global__ __launch_bounds__(256) void k_near(const TI* __restrict__ rho, const double* __restrict__ Lf,
-                                              TO* __restrict__ phi, TO* __restrict__ g, int n, int NL, double dx) {
-  const long long N = (long long)n * n * n;
-  const long long u = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (u >= N) return;
-  const int l = (int)(u % n), j = (int)((u / n) % n), i = (int)(u / ((long long)n * n));
-  const int qi = i & 1, qj = j & 1, ql = l & 1;
-  double ph = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
-  for (int a = -3 + qi; a <= 2 + qi; ++a) {      // delta = u - w
-    const int wi = i - a;
-    if (wi < 0 || wi >= n) continue;
-    for (int b = -3 + qj; b <= 2 + qj; ++b) {
-      const int wj = j - b;
-      if (wj < 0 || wj >= n) continue;
-      const long long rowb = ((long long)wi * n + wj) * n;
-      for (int c = -3 + ql; c <= 2 + ql; ++c) {
-        const int wl = l - c;
-        if (wl < 0 || wl >= n) continue;
-        const double r = (double)rho[rowb + wl];
-        const int t = (a + 3) * 49 + (b + 3) * 7 + (c + 3);
-        ph += r * c_p2p_phi[t];
-        g0 += r * c_p2p_g[t];
-        g1 += r * c_p2p_g[343 + t];
-        g2 += r * c_p2p_g[686 + t];
-      }
-    }
-  }
-  ph *= dx * dx;
-  g0 *= dx; g1 *= dx; g2 *= dx;
-  if (Lf) {
-    const int nF = n >> 1;
-    const long long nT = (long long)nF * nF * nF;
-    const long long T = ((long long)(i >> 1) * nF + (j >> 1)) * nF + (l >> 1);
-    double sp = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int b = 0; b < NL; ++b) {
-      const int ex = c_mi_exp[b];
-      const int x = mi_a(ex), y = mi_b(ex), z = mi_c(ex);
-      const int sgn = ((1 - qi) * x + (1 - qj) * y + (1 - ql) * z) & 1;
-      double c = ldexp(c_mi_invfact[b], -2 * (x + y + z)) * Lf[((b >> 2) * nT + T) * 4 + (b & 3)];
-      c = sgn ? -c : c;
-      sp += c;
-      s0 += x * c;
-      s1 += y * c;
-      s2 += z * c;
-    }
-    ph += 0.5 * dx * dx * sp;
-    g0 += dx * (1 - 2 * qi) * s0;
-    g1 += dx * (1 - 2 * qj) * s1;
-    g2 += dx * (1 - 2 * ql) * s2;
-  }
-  phi[u] = (TO)ph;
-  if (g) {
-    g[u] = (TO)g0;
-    g[N + u] = (TO)g1;
-    g[2 * N + u] = (TO)g2;
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Matrix-core M2L / M2P (FP64, v_mfma_f64_16x16x4f64).
 //
 // Both are sums over the 189 list offsets d of a parity class: with the
@@ -352,6 +244,49 @@ __global__ __launch_bounds__(256) void k_near(const TI* __restrict__ rho, const 
 // The d loop stages the next offset's 8 x ND derivative table in LDS while
 // the current one is consumed (one barrier per offset).
 // ---------------------------------------------------------------------------
+// L2L, eq. (L2L), in scaled form for child q of parent P:
+//   Lhat_k[b] += sum_{|b|+|g|<=p} 2^-(|b|+1) 4^-|g| / g! (2q-1)^g Lhat_{k-1}[P][b+g]
+template <int P>
+__device__ __forceinline__ double l2l_term(const double* __restrict__ Lp, long long ncp, long long Pl, int q, int bx,
+                                           int by, int bz, int m) {
+  const int q0 = (q >> 2) & 1, q1 = (q >> 1) & 1, q2 = q & 1;
+  double acc = 0.0;
+  for (int gx = 0; gx <= P - m; ++gx)
+    for (int gy = 0; gx + gy <= P - m; ++gy)
+      for (int gz = 0; gx + gy + gz <= P - m; ++gz) {
+        const int bt = mi_index(bx + gx, by + gy, bz + gz);
+        double c = ldexp(c_mi_invfact[mi_index(gx, gy, gz)], -2 * (gx + gy + gz)) *
+                   Lp[((bt >> 2) * ncp + Pl) * 4 + (bt & 3)];
+        if (((1 - q0) * gx + (1 - q1) * gy + (1 - q2) * gz) & 1) c = -c;
+        acc += c;
+      }
+  return ldexp(acc, -(m + 1));
+}
+
+// L2P coefficient of local term b for output o of child q, in the units of
+// the M2P accumulators (phi = dx^2/2 acc_phi, g_d = -dx/4 acc_gd):
+//   phi:  c_b(q) = (2q-1)^b 4^-|b| / b!
+//   g_d:  -4 (1 - 2 q_d) b_d c_b(q)
+__device__ __forceinline__ double l2p_coef(int bt, int q, int o) {
+  const int ex = c_mi_exp[bt];
+  const int x = mi_a(ex), y = mi_b(ex), z = mi_c(ex);
+  const int q0 = (q >> 2) & 1, q1 = (q >> 1) & 1, q2 = q & 1;
+  double c = ldexp(c_mi_invfact[bt], -2 * (x + y + z));
+  if (((1 - q0) * x + (1 - q1) * y + (1 - q2) * z) & 1) c = -c;
+  if (o == 1) c *= -4.0 * (1 - 2 * q0) * x;
+  if (o == 2) c *= -4.0 * (1 - 2 * q1) * y;
+  if (o == 3) c *= -4.0 * (1 - 2 * q2) * z;
+  return c;
+}
+
+// Near-field coefficient of source offset e (w = 2T + e, e in [-2,3]^3) for
+// output o of child q (u = 2T + q), delta = u - w = q - e, in accumulator
+// units: phi: -2 / max(|delta|, 1);  g_d: 4 delta_d / |delta|^3 (0 at delta = 0).
+__device__ __forceinline__ double p2p_coef(int e0, int e1, int e2, int q, int o) {
+  const int t = (((q >> 2) & 1) - e0 + 3) * 49 + (((q >> 1) & 1) - e1 + 3) * 7 + ((q & 1) - e2 + 3);
+  return o == 0 ? 2.0 * c_p2p_phi[t] : -4.0 * c_p2p_g[(o - 1) * 343 + t];
+}
+
 struct RowCtx {
   long long cell;  // padded linear index in the source grid
   int c0, c1, c2;  // cell coordinates (unpadded)
@@ -387,88 +322,179 @@ __device__ __forceinline__ void stage_store(double* dst, const double (&buf)[(8 
   }
 }
 
-// M2P: columns (q, o), o in {phi, gx, gy, gz}; 32 columns = 2 tiles.
-template <int P, typename TO>
-__global__ __launch_bounds__(256, 2) void k_m2p_f64(const double* __restrict__ Mh, const double* __restrict__ Dtab,
-                                                   const int* __restrict__ dlists, TO* __restrict__ phi,
-                                                   TO* __restrict__ g, int nF, double sphi, double sg) {
-  constexpr int NM = nterms(P), NC = (NM + 3) / 4, ND = nterms(P + 1);
-  constexpr int NS = (8 * ND + 255) / 256;
-  constexpr int ZERO = 8 * ND;  // index of a zero slot
-  __shared__ double sD[2][8 * ND + 1];
-  const int r = blockIdx.y;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// Bottom of the downward pass for the unigrid children of level-F cells:
+// columns (q, o), o in {phi, gx, gy, gz}; 32 columns = 2 tiles.  After the
+// 189 M2P offsets, two more K blocks run on the matrix cores: L2P (K = local
+// terms of the row's own cell) and the near field (K = the 216 unigrid
+// densities of the 6^3 block around the row's cell).  phi and g are written
+// once.
+//
+// Data flow: a block owns a tile of BX x BY x BZ level-F cells (all 8 parity
+// classes, one wave per class).  For each chunk of 4 multipole terms the
+// block stages the multipoles of the tile plus its 3-cell halo in LDS, z
+// de-interleaved by parity so that the 16 rows of a fragment (8 z-neighbours
+// of one parity x 2 y lines) are two contiguous 256-byte runs.  Every staged
+// value then feeds up to 189 x 8 matrix-core ops without touching L2.  The B
+// fragments (derivative tables, plan-time fragment order) come from global
+// memory and are prefetched one offset ahead.
+constexpr int BX = 8, BY = 8, BZ = 16;
+constexpr int HX = BX + 6, HY = BY + 6, HZ = BZ + 6, HZ2 = HZ / 2;
+constexpr int BOT_MT = (BX / 2) * (BY / 2) * (BZ / 2) / 16;  // row tiles per wave (8)
+constexpr int BOT_THREADS = 512;
+
+__device__ __forceinline__ int halo_index(int hx, int hy, int hz) {
+  return (((hx * HY + hy) * 2 + (hz & 1)) * HZ2 + (hz >> 1));
+}
+
+template <int P, typename TI, typename TO>
+__global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom_f64(
+    const double* __restrict__ Mh, const double* __restrict__ Lf, const TI* __restrict__ rho,
+    const double* __restrict__ Wm2p, const double* __restrict__ Wl2p, const double* __restrict__ Wp2p,
+    const int* __restrict__ dlists, TO* __restrict__ phi, TO* __restrict__ g, int nF, double sphi, double sg) {
+  constexpr int NM = nterms(P), NC = (NM + 3) / 4;
+  constexpr int NL = nterms(P), NCL = (NL + 3) / 4;
+  __shared__ d4 halo[HX * HY * HZ];
+  const int lane = threadIdx.x & 63, r = threadIdx.x >> 6;  // wave = parity class
   const int i = lane & 15, kq = lane >> 4;
-  const int nG = nF >> 1, nFp = nF + 6;
-  const long long nlat = (long long)nG * nG * nG;
+  const int r0 = (r >> 2) & 1, r1 = (r >> 1) & 1, r2 = r & 1;
+  const int nFp = nF + 6;
   const long long ncellp = (long long)nFp * nFp * nFp;
-  const long long tile0 = ((long long)blockIdx.x * 4 + wave) * 16;
-  const RowCtx rc = row_of(tile0 + i, nlat, nG, r, nFp);
+  const int tx0 = blockIdx.x * BX, ty0 = blockIdx.y * BY, tz0 = blockIdx.z * BZ;
+  // row i of tile m: lattice (gx, gy, gz) = (m >> 1, 2 (m & 1) + (i >> 3), i & 7)
+  const int gz = i & 7, gyo = i >> 3;
 
-  int bofs[2][NC];
+  d4 acc[BOT_MT][2];
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const int col = 16 * t + i;
-    const int q = col >> 2, o = col & 3;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const int al = 4 * c + kq;
-      int off = ZERO;
-      if (al < NM) {
-        const int ex = c_mi_exp[al];
-        const int a = mi_a(ex) + (o == 1), b = mi_b(ex) + (o == 2), cc = mi_c(ex) + (o == 3);
-        off = q * ND + mi_index(a, b, cc);
-      }
-      bofs[t][c] = off;
-    }
-  }
-  if (threadIdx.x == 0) { sD[0][ZERO] = 0.0; sD[1][ZERO] = 0.0; }
+  for (int m = 0; m < BOT_MT; ++m) acc[m][0] = acc[m][1] = d4{0, 0, 0, 0};
   const int* dl = dlists + r * NLIST;
-  double pre[NS];
-  stage_load<ND>(Dtab + (size_t)dl[0] * 8 * ND, pre);
-  stage_store<ND>(sD[0], pre);
-  __syncthreads();
 
-  d4 acc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-  const double* mbase = Mh + kq;
-  for (int it = 0; it < NLIST; ++it) {
-    const int dd = dl[it];
-    const int d0 = dd / 49 - 3, d1 = (dd / 7) % 7 - 3, d2 = dd % 7 - 3;
-    const long long src = rc.cell - ((long long)d0 * nFp + d1) * nFp - d2;
-    double a[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) a[c] = mbase[(c * ncellp + src) * 4];
-    if (it + 1 < NLIST) stage_load<ND>(Dtab + (size_t)dl[it + 1] * 8 * ND, pre);
-    const double* sd = sD[it & 1];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c], sd[bofs[0][c]], acc[0], 0, 0, 0);
-      acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c], sd[bofs[1][c]], acc[1], 0, 0, 0);
+  for (int c = 0; c < NC; ++c) {
+    __syncthreads();  // previous chunk fully consumed
+    for (int h = threadIdx.x; h < HX * HY * HZ; h += BOT_THREADS) {
+      const int hz = h % HZ, hy = (h / HZ) % HY, hx = h / (HZ * HY);
+      const int px = tx0 + hx, py = ty0 + hy, pz = tz0 + hz;  // padded coordinates
+      d4 v = d4{0, 0, 0, 0};
+      if (px < nFp && py < nFp && pz < nFp)
+        v = *reinterpret_cast<const d4*>(Mh + (c * ncellp + ((long long)px * nFp + py) * nFp + pz) * 4);
+      halo[halo_index(hx, hy, hz)] = v;
     }
-    if (it + 1 < NLIST) stage_store<ND>(sD[(it + 1) & 1], pre);
     __syncthreads();
+    const double* hal = reinterpret_cast<const double*>(halo);
+    const double* wc = Wm2p + (size_t)c * 128 + lane;
+    int dd = dl[0];
+    double b0 = wc[(size_t)dd * (NC * 128)], b1 = wc[(size_t)dd * (NC * 128) + 64];
+    for (int it = 0; it < NLIST; ++it) {
+      const int d0 = dd / 49 - 3, d1 = (dd / 7) % 7 - 3, d2 = dd % 7 - 3;
+      const double cb0 = b0, cb1 = b1;
+      if (it + 1 < NLIST) {  // prefetch the next offset's B fragments
+        dd = dl[it + 1];
+        b0 = wc[(size_t)dd * (NC * 128)];
+        b1 = wc[(size_t)dd * (NC * 128) + 64];
+      }
+      // source halo coordinates of row (gx, gy, gz): 3 + 2 g + r - d
+      const int zz = 3 + r2 - d2;  // in [1, 6]
+      const int zoff = (zz & 1) * HZ2 + gz + (zz >> 1);
+#pragma unroll
+      for (int m = 0; m < BOT_MT; ++m) {
+        const int hx = 3 + 2 * (m >> 1) + r0 - d0;
+        const int hy = 3 + 2 * (2 * (m & 1) + gyo) + r1 - d1;
+        const double a = hal[((hx * HY + hy) * 2 * HZ2 + zoff) * 4 + kq];
+        acc[m][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, cb0, acc[m][0], 0, 0, 0);
+        acc[m][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, cb1, acc[m][1], 0, 0, 0);
+      }
+    }
   }
-  // epilogue: element v of tile t is row 4v + kq, column 16t + i
+
   const int n = 2 * nF;
   const long long N = (long long)n * n * n;
+  const long long nT = (long long)nF * nF * nF;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const RowCtx ro = row_of(tile0 + 4 * v + kq, nlat, nG, r, nFp);
-    if (!ro.valid) continue;
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int col = 16 * t + i;
-      const int q = col >> 2, o = col & 3;
-      const long long u = ((long long)(2 * ro.c0 + ((q >> 2) & 1)) * n + (2 * ro.c1 + ((q >> 1) & 1))) * n +
-                          (2 * ro.c2 + (q & 1));
-      const double val = acc[t][v];
-      if (o == 0) {
-        phi[u] = (TO)((double)phi[u] + sphi * val);
-      } else if (g) {
-        TO* gp = g + (o - 1) * N + u;
-        *gp = (TO)((double)*gp + sg * val);
+  for (int m = 0; m < BOT_MT; ++m) {
+    // the lane's own row (A operand) and its level-F cell, clamped into the grid
+    int c0 = tx0 + 2 * (m >> 1) + r0, c1 = ty0 + 2 * (2 * (m & 1) + gyo) + r1, c2 = tz0 + 2 * gz + r2;
+    c0 = c0 < nF ? c0 : 0;
+    c1 = c1 < nF ? c1 : 0;
+    c2 = c2 < nF ? c2 : 0;
+    if (Lf) {
+      const long long Tl = ((long long)c0 * nF + c1) * nF + c2;
+#pragma unroll 4
+      for (int c = 0; c < NCL; ++c) {
+        const double a = Lf[((long long)c * nT + Tl) * 4 + kq];
+        acc[m][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Wl2p[c * 128 + lane], acc[m][0], 0, 0, 0);
+        acc[m][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Wl2p[c * 128 + 64 + lane], acc[m][1], 0, 0, 0);
       }
     }
+#pragma unroll 6
+    for (int c = 0; c < 54; ++c) {
+      const int k = 4 * c + kq;
+      const int e0 = k / 36 - 2, e1 = (k / 6) % 6 - 2, e2 = k % 6 - 2;
+      const int w0 = 2 * c0 + e0, w1 = 2 * c1 + e1, w2 = 2 * c2 + e2;
+      const bool in = w0 >= 0 && w1 >= 0 && w2 >= 0 && w0 < n && w1 < n && w2 < n;
+      const double a = in ? (double)rho[((long long)w0 * n + w1) * n + w2] : 0.0;
+      acc[m][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Wp2p[c * 128 + lane], acc[m][0], 0, 0, 0);
+      acc[m][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Wp2p[c * 128 + 64 + lane], acc[m][1], 0, 0, 0);
+    }
+    // epilogue (f64 layout): element v of tile t is row 4v + kq, column 16t + i
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * v + kq;
+      const int o0 = tx0 + 2 * (m >> 1) + r0, o1 = ty0 + 2 * (2 * (m & 1) + (row >> 3)) + r1,
+                o2 = tz0 + 2 * (row & 7) + r2;
+      if (o0 >= nF || o1 >= nF || o2 >= nF) continue;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int col = 16 * t + i;
+        const int q = col >> 2, o = col & 3;
+        const long long u = ((long long)(2 * o0 + ((q >> 2) & 1)) * n + (2 * o1 + ((q >> 1) & 1))) * n +
+                            (2 * o2 + (q & 1));
+        const double val = acc[m][t][v];
+        if (o == 0)
+          phi[u] = (TO)(sphi * val);
+        else if (g)
+          g[(o - 1) * N + u] = (TO)(sg * val);
+      }
+    }
+  }
+}
+
+// Plan-time expansion of the bottom kernel's B operands into fragment order:
+// table[chunk][tile][lane], lane = j + 16 k holds B[k][j] of column 16 tile + j.
+//   M2P:  [343 offsets][NC][2][64]  D[a + e_o](Rhat_{d,q}), a = 4 chunk + k (0 past NM)
+//   L2P:  [NCL][2][64]              l2p_coef
+//   near: [54][2][64]               p2p_coef, source e = decode(4 chunk + k)
+__global__ void k_expand_bottom(const double* __restrict__ Dtab, double* __restrict__ Wm2p,
+                                double* __restrict__ Wl2p, double* __restrict__ Wp2p, int NM, int NC, int NL,
+                                int NCL, int ND) {
+  const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long n_m2p = 343LL * NC * 128, n_l2p = (long long)NCL * 128, n_p2p = 54 * 128;
+  if (id >= n_m2p + n_l2p + n_p2p) return;
+  long long e = id;
+  const int lane = (int)(e & 63), t = (int)((e >> 6) & 1);
+  const int j = lane & 15, k = lane >> 4;
+  const int col = 16 * t + j, q = col >> 2, o = col & 3;
+  if (e < n_m2p) {
+    const int c = (int)((e >> 7) % NC), dd = (int)((e >> 7) / NC);
+    const int al = 4 * c + k;
+    double v = 0.0;
+    if (al < NM) {
+      const int ex = c_mi_exp[al];
+      v = Dtab[((size_t)dd * 8 + q) * ND + mi_index(mi_a(ex) + (o == 1), mi_b(ex) + (o == 2), mi_c(ex) + (o == 3))];
+    }
+    Wm2p[e] = v;
+    return;
+  }
+  e -= n_m2p;
+  if (e < n_l2p) {
+    const int c = (int)(e >> 7);
+    const int bt = 4 * c + k;
+    Wl2p[e] = bt < NL ? l2p_coef(bt, q, o) : 0.0;
+    return;
+  }
+  e -= n_l2p;
+  {
+    const int c = (int)(e >> 7);
+    const int kk = 4 * c + k;
+    Wp2p[e] = p2p_coef(kk / 36 - 2, (kk / 6) % 6 - 2, kk % 6 - 2, q, o);
   }
 }
 
@@ -484,7 +510,8 @@ struct TileChunks {
 // M2L: columns (q, b) sorted by |b|, tiles [T0, T1) of them.
 template <int P, int T0, int T1>
 __global__ __launch_bounds__(256, 2) void k_m2l_f64(const double* __restrict__ Mh, const double* __restrict__ Dtab,
-                                                   const int* __restrict__ dlists, double* __restrict__ Lh, int ns) {
+                                                   const int* __restrict__ dlists, const double* __restrict__ Lp,
+                                                   double* __restrict__ Lh, int ns) {
   constexpr int NM = nterms(P), NL = nterms(P), ND = nterms(P + 1);
   constexpr int NT = T1 - T0;
   constexpr int CM = m2l_tile_chunks(P, T0);  // the group's first tile needs the most terms
@@ -555,9 +582,10 @@ __global__ __launch_bounds__(256, 2) void k_m2l_f64(const double* __restrict__ M
     if (it + 1 < NLIST) stage_store<ND>(sD[(it + 1) & 1], pre);
     __syncthreads();
   }
-  // epilogue: Lhat_k[2P + q][b] = 2^-(|b|+1) acc
+  // epilogue: Lhat_k[2P + q][b] = 2^-(|b|+1) acc + L2L from Lhat_{k-1}[P]
   const int nk = 2 * ns;
   const long long nck = (long long)nk * nk * nk;
+  const long long ncs = (long long)ns * ns * ns;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const RowCtx ro = row_of(tile0 + 4 * v + kq, nlat, nG, r, nsp);
@@ -572,7 +600,13 @@ __global__ __launch_bounds__(256, 2) void k_m2l_f64(const double* __restrict__ M
       const int bt = nterms(m - 1) + cin % ndeg(m);
       const long long T = ((long long)(2 * ro.c0 + ((q >> 2) & 1)) * nk + (2 * ro.c1 + ((q >> 1) & 1))) * nk +
                           (2 * ro.c2 + (q & 1));
-      Lh[((bt >> 2) * nck + T) * 4 + (bt & 3)] = ldexp(acc[t][v], -(m + 1));
+      double val = ldexp(acc[t][v], -(m + 1));
+      if (Lp) {
+        const int bex = c_mi_exp[bt];
+        const long long Pl = ((long long)ro.c0 * ns + ro.c1) * ns + ro.c2;
+        val += l2l_term<P>(Lp, ncs, Pl, q, mi_a(bex), mi_b(bex), mi_c(bex), m);
+      }
+      Lh[((bt >> 2) * nck + T) * 4 + (bt & 3)] = val;
     }
   }
 }
@@ -586,6 +620,12 @@ hipError_t launch_dtab(fmm_plan* pl, hipStream_t s) {
   hipLaunchKernelGGL(k_dtab, dim3(blocks_for(343 * 8, 64)), dim3(64), 0, s, pl->dtab, pl->p + 1, pl->ND);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  {
+    const long long cnt = 343LL * pl->NC * 128 + (long long)pl->NCL * 128 + 54 * 128;
+    hipLaunchKernelGGL(k_expand_bottom, dim3(blocks_for(cnt, 256)), dim3(256), 0, s, pl->dtab, pl->wm2p, pl->wl2p,
+                       pl->wp2p, pl->NM, pl->NC, pl->NL, pl->NCL, pl->ND);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if (pl->dtab32) {
     const long long cnt = 343LL * 8 * pl->ND;
     hipLaunchKernelGGL(k_to_f32, dim3(blocks_for(cnt, 256)), dim3(256), 0, s, pl->dtab, pl->dtab32, cnt);
@@ -603,8 +643,9 @@ static hipError_t launch_m2l_groups(fmm_plan* pl, int k, hipStream_t s) {
     const int ns = 1 << (k - 1);
     const long long nlat = (long long)(ns / 2) * (ns / 2) * (ns / 2);
     dim3 grid(blocks_for(nlat, 64), 8);
+    const double* Lp = (k >= 4) ? (const double*)pl->lev[k - 1].L : nullptr;
     hipLaunchKernelGGL((k_m2l_f64<P, T0, T1>), grid, dim3(256), 0, s, (const double*)pl->lev[k - 1].M, pl->dtab,
-                       pl->dlists, (double*)pl->lev[k].L, ns);
+                       pl->dlists, Lp, (double*)pl->lev[k].L, ns);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_m2l_groups<P, G + 1>(pl, k, s);
@@ -613,7 +654,7 @@ static hipError_t launch_m2l_groups(fmm_plan* pl, int k, hipStream_t s) {
 
 template <int P, typename TI, typename TO>
 static hipError_t solve_fp64(fmm_plan* pl, const TI* rho, TO* phi, TO* g, hipStream_t s) {
-  constexpr int NM = nterms(P), NC = (NM + 3) / 4, NL = nterms(P);
+  constexpr int NM = nterms(P), NC = (NM + 3) / 4;
   const int n = pl->n, F = pl->F;
   hipError_t e;
   {
@@ -630,33 +671,17 @@ static hipError_t solve_fp64(fmm_plan* pl, const TI* rho, TO* phi, TO* g, hipStr
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   for (int k = 3; k <= F; ++k) {
-    {
-      StageScope sc(pl, ST_M2L, m2l_ngroups(P), s);
-      if ((e = launch_m2l_groups<P, 0>(pl, k, s)) != hipSuccess) return e;
-    }
-    if (k >= 4) {
-      StageScope sc(pl, ST_L2L, 1, s);
-      const long long nP = 1LL << (3 * (k - 1));
-      hipLaunchKernelGGL((k_l2l<nterms(PMAX)>), dim3(blocks_for(nP, 4)), dim3(256), 0, s, (const double*)pl->lev[k - 1].L,
-                         (double*)pl->lev[k].L, 1 << k, P, NL);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
+    StageScope sc(pl, ST_M2L, m2l_ngroups(P), s);
+    if ((e = launch_m2l_groups<P, 0>(pl, k, s)) != hipSuccess) return e;
   }
   {
-    StageScope sc(pl, ST_NEAR, 1, s);
-    const long long N = (long long)n * n * n;
-    const double* Lf = (F >= 3) ? (const double*)pl->lev[F].L : nullptr;
-    hipLaunchKernelGGL((k_near<TI, TO>), dim3(blocks_for(N, 256)), dim3(256), 0, s, rho, Lf, phi, g, n, NL, pl->dx);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
-  {
-    StageScope sc(pl, ST_M2P, 1, s);
+    StageScope sc(pl, ST_BOTTOM, 1, s);
     const int nF = n / 2;
-    const long long nlat = (long long)(nF / 2) * (nF / 2) * (nF / 2);
-    dim3 grid(blocks_for(nlat, 64), 8);
     const double dx = pl->dx;
-    hipLaunchKernelGGL((k_m2p_f64<P, TO>), grid, dim3(256), 0, s, (const double*)pl->lev[F].M, pl->dtab, pl->dlists,
-                       phi, g, nF, 0.5 * dx * dx, -0.25 * dx);
+    const double* Lf = (F >= 3) ? (const double*)pl->lev[F].L : nullptr;
+    dim3 bgrid(blocks_for(nF, BX), blocks_for(nF, BY), blocks_for(nF, BZ));
+    hipLaunchKernelGGL((k_bottom_f64<P, TI, TO>), bgrid, dim3(BOT_THREADS), 0, s, (const double*)pl->lev[F].M, Lf,
+                       rho, pl->wm2p, pl->wl2p, pl->wp2p, pl->dlists, phi, g, nF, 0.5 * dx * dx, -0.25 * dx);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
