@@ -100,7 +100,7 @@ def main():
     log(f"timed {args.steps} solves: {ms_per_step:.3f} ms/solve, {cells_per_s:.4e} cells/s")
 
     flops = costs.solve_flops(n, p)
-    stage_flops = {"p2m": flops["p2m"], "m2m": flops["m2m"], "m2l": flops["m2l_l2l"], "bottom": flops["bottom"]}
+    stage_flops = {"p2m": flops["p2m"], "m2m": flops["m2m"], "m2l": flops["m2l"], "bottom": flops["bottom"]}
     stages = {}
     for name, (ms, launches) in prof.items():
         if launches or ms:

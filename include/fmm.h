@@ -122,7 +122,10 @@ int fmm_last_status(void);
 
 /*
  * Inspection of the plan's intermediate state after fmm_solve has completed
- * on the device (the caller synchronises the stream first).  Copies to HOST
+ * on the device (the caller synchronises the stream first).  Synchronous;
+ * it may finish pending work on the plan's buffers (the finest level keeps
+ * only its M2L part during a solve), so call it only between solves on the
+ * null stream's device.  Copies to HOST
  * memory `out`, as double, the scaled expansions the kernels keep:
  *   which = 0: multipoles of level `level` (2 <= level <= F),
  *              Mhat[a] = (-1)^|a| M[a] / (a! h^|a| dx^3), M[a] = sum m (x - c)^a
@@ -141,8 +144,8 @@ int fmm_debug_expansions(fmm_plan* plan, int which, int level, double* out, size
  * fmm_profile_read waits for the recorded events, writes for each stage s <
  * nstages the summed milliseconds ms[s] and the number of kernel launches
  * launches[s] they cover (either may be NULL), and clears the record.
- * Stages: 0 P2M, 1 M2M, 2 M2L (with L2L), 3 bottom (M2P, L2P and near
- * field), 4 whole solve, 5 whole backward.  Names via fmm_profile_stage_name (NULL
+ * Stages: 0 P2M, 1 M2M, 2 M2L, 3 L2L, 4 bottom (M2P, L2P and near field),
+ * 5 whole solve, 6 whole backward.  Names via fmm_profile_stage_name (NULL
  * past the last stage).  The plan owns the events; recording adds two event
  * records per stage to the stream.
  */

@@ -1,6 +1,7 @@
 // C ABI of the unigrid FMM library: argument validation, plan construction
 // and the solve entry points.  Validation happens before any HIP call, so
 // invalid arguments are reported identically with or without a device.
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -68,11 +69,12 @@ size_t plan_bytes(int n, int p) {
   const int F = ilog2_exact(n) - 1;
   const int NM = fmm::nterms(p), NC = (NM + 3) / 4, NCL = NC, ND = fmm::nterms(p + 1);
   size_t b = (size_t)343 * 8 * ND * sizeof(double) + 8 * fmm::NLIST * sizeof(int) + 256;
-  b += ((size_t)343 * NC * 128 + (size_t)NCL * 128 + 54 * 128) * sizeof(double);
+  b += ((size_t)343 * NC * 128 + (size_t)NCL * 128 * 9 + 54 * 128) * sizeof(double);
+  b += (size_t)343 * fmm::m2l_nfrags(p) * 64 * sizeof(double);
   for (int k = 2; k <= F; ++k) {
     const size_t nkp = (size_t)(1 << k) + 6;
     b += (size_t)NC * nkp * nkp * nkp * 4 * sizeof(double);
-    if (k >= 3) b += (size_t)NCL * ((size_t)1 << (3 * k)) * 4 * sizeof(double);
+    if (k >= 3) b += ((size_t)1 << (3 * (k - 1))) * fmm::loc_stride(p) * sizeof(double);
   }
   return b;
 }
@@ -94,6 +96,11 @@ void release(fmm_plan* pl) {
   if (pl->wm2p) (void)hipFree(pl->wm2p);
   if (pl->wl2p) (void)hipFree(pl->wl2p);
   if (pl->wp2p) (void)hipFree(pl->wp2p);
+  if (pl->wl2p2) (void)hipFree(pl->wl2p2);
+  if (pl->wm2l) (void)hipFree(pl->wm2l);
+  if (pl->l2l_start) (void)hipFree(pl->l2l_start);
+  if (pl->l2l_idx) (void)hipFree(pl->l2l_idx);
+  if (pl->l2l_coef) (void)hipFree(pl->l2l_coef);
   if (pl->flag) (void)hipFree(pl->flag);
   delete pl;
 }
@@ -143,7 +150,7 @@ hipEvent_t take_event(fmm_plan* pl) {
   return e;
 }
 
-const char* const kStageNames[fmm::ST_COUNT] = {"p2m", "m2m", "m2l", "bottom", "solve", "backward"};
+const char* const kStageNames[fmm::ST_COUNT] = {"p2m", "m2m", "m2l", "l2l", "bottom", "solve", "backward"};
 
 }  // namespace
 
@@ -231,6 +238,46 @@ fmm_plan* fmm_plan_create_ex(int n, int p, int isolated, const fmm_options* opt)
   if (dev_alloc(pl, (void**)&pl->wm2p, (size_t)343 * pl->NC * 128 * sizeof(double))) return bail();
   if (dev_alloc(pl, (void**)&pl->wl2p, (size_t)pl->NCL * 128 * sizeof(double))) return bail();
   if (dev_alloc(pl, (void**)&pl->wp2p, (size_t)54 * 128 * sizeof(double))) return bail();
+  if (dev_alloc(pl, (void**)&pl->wl2p2, (size_t)8 * pl->NCL * 128 * sizeof(double))) return bail();
+  if (dev_alloc(pl, (void**)&pl->wm2l, (size_t)343 * fmm::m2l_nfrags(p) * 64 * sizeof(double))) return bail();
+  {
+    // L2L coefficient lists: for each local term b, the terms b + g with
+    // |b + g| <= p, coefficient 2^-(|b|+1) 4^-|g| / g!, the column of b + g
+    // (child 0) and its degree block size, and the parity pattern of g (the
+    // sign for child q is (-1)^((1-q).g))
+    std::vector<int> start(1, 0), idx;
+    std::vector<double> coef;
+    auto fact = [](int k) { double f = 1; for (int i = 2; i <= k; ++i) f *= i; return f; };
+    std::vector<int> ex(pl->NL * 3);
+    for (int a = 0; a <= p; ++a)
+      for (int b = 0; a + b <= p; ++b)
+        for (int c = 0; a + b + c <= p; ++c) {
+          const int t = fmm::mi_index(a, b, c);
+          ex[3 * t] = a; ex[3 * t + 1] = b; ex[3 * t + 2] = c;
+        }
+    for (int t = 0; t < pl->NL; ++t) {
+      const int bx = ex[3 * t], by = ex[3 * t + 1], bz = ex[3 * t + 2], m = bx + by + bz;
+      for (int gx = 0; gx <= p - m; ++gx)
+        for (int gy = 0; gx + gy <= p - m; ++gy)
+          for (int gz = 0; gx + gy + gz <= p - m; ++gz) {
+            const int ng = gx + gy + gz;
+            const int pat = ((gx & 1) << 2) | ((gy & 1) << 1) | (gz & 1);
+            const int bg = fmm::mi_index(bx + gx, by + gy, bz + gz), mg = m + ng;
+            idx.push_back((fmm::m2l_col(0, bg, mg) << 9) | (fmm::ndeg(mg) << 3) | pat);
+            coef.push_back(std::ldexp(1.0 / (fact(gx) * fact(gy) * fact(gz)), -(m + 1) - 2 * ng));
+          }
+      start.push_back((int)idx.size());
+    }
+    if (dev_alloc(pl, (void**)&pl->l2l_start, start.size() * sizeof(int))) return bail();
+    if (dev_alloc(pl, (void**)&pl->l2l_idx, idx.size() * sizeof(int))) return bail();
+    if (dev_alloc(pl, (void**)&pl->l2l_coef, coef.size() * sizeof(double))) return bail();
+    if (hipMemcpy(pl->l2l_start, start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(pl->l2l_idx, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(pl->l2l_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+      fail(FMM_ERR_DEVICE, "upload failed");
+      return bail();
+    }
+  }
   if (dev_alloc(pl, (void**)&pl->flag, 256)) return bail();
   for (int k = 2; k <= pl->F; ++k) {
     fmm::Level& lv = pl->lev[k];
@@ -246,7 +293,7 @@ fmm_plan* fmm_plan_create_ex(int n, int p, int isolated, const fmm_options* opt)
       return bail();
     }
     if (k >= 3) {
-      const size_t lb = (size_t)pl->NCL * lv.ncell * 4 * sizeof(double);
+      const size_t lb = (size_t)(lv.ncell / 8) * fmm::loc_stride(p) * sizeof(double);
       if (dev_alloc(pl, &lv.L, lb)) return bail();
       if (hipMemset(lv.L, 0, lb) != hipSuccess) {
         fail(FMM_ERR_DEVICE, "hipMemset failed");
@@ -387,15 +434,34 @@ int fmm_debug_expansions(fmm_plan* plan, int which, int level, double* out, size
   const int nt = which == 0 ? plan->NM : plan->NL;
   const int nch = (nt + 3) / 4;
   if (!out || count < (size_t)lv.ncell * nt) return fail(FMM_ERR_INVALID_ARG, "out must hold %lld doubles", lv.ncell * nt);
-  const long long cells = which == 0 ? lv.ncellp : lv.ncell;
-  std::vector<double> host((size_t)nch * cells * 4);
-  hipError_t e = hipMemcpy(host.data(), which == 0 ? lv.M : lv.L, host.size() * sizeof(double), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return fail(FMM_ERR_DEVICE, "copy failed: %s", hipGetErrorString(e));
   const int nk = lv.nk;
+  if (which == 0) {
+    std::vector<double> host((size_t)nch * lv.ncellp * 4);
+    hipError_t e = hipMemcpy(host.data(), lv.M, host.size() * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(FMM_ERR_DEVICE, "copy failed: %s", hipGetErrorString(e));
+    for (long long cidx = 0; cidx < lv.ncell; ++cidx) {
+      const int c2 = (int)(cidx % nk), c1 = (int)((cidx / nk) % nk), c0 = (int)(cidx / ((long long)nk * nk));
+      const long long src = ((long long)(c0 + 3) * lv.nkp + (c1 + 3)) * lv.nkp + (c2 + 3);
+      for (int t = 0; t < nt; ++t) out[cidx * nt + t] = host[((size_t)(t >> 2) * lv.ncellp + src) * 4 + (t & 3)];
+    }
+    return ok();
+  }
+  hipError_t fe = fmm::finish_locals(plan, level, nullptr);
+  if (fe == hipSuccess) fe = hipDeviceSynchronize();
+  if (fe != hipSuccess) return fail(FMM_ERR_DEVICE, "completing locals failed: %s", hipGetErrorString(fe));
+  const int RS = fmm::loc_stride(plan->p), ns = nk / 2;
+  std::vector<double> host((size_t)(lv.ncell / 8) * RS);
+  hipError_t e = hipMemcpy(host.data(), lv.L, host.size() * sizeof(double), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(FMM_ERR_DEVICE, "copy failed: %s", hipGetErrorString(e));
   for (long long cidx = 0; cidx < lv.ncell; ++cidx) {
     const int c2 = (int)(cidx % nk), c1 = (int)((cidx / nk) % nk), c0 = (int)(cidx / ((long long)nk * nk));
-    const long long src = which == 0 ? ((long long)(c0 + 3) * lv.nkp + (c1 + 3)) * lv.nkp + (c2 + 3) : cidx;
-    for (int t = 0; t < nt; ++t) out[cidx * nt + t] = host[((size_t)(t >> 2) * cells + src) * 4 + (t & 3)];
+    const long long P = ((long long)(c0 >> 1) * ns + (c1 >> 1)) * ns + (c2 >> 1);
+    const int q = ((c0 & 1) << 2) | ((c1 & 1) << 1) | (c2 & 1);
+    for (int t = 0; t < nt; ++t) {
+      int m = 0;
+      while (fmm::nterms(m) <= t) ++m;
+      out[cidx * nt + t] = host[(size_t)P * RS + fmm::m2l_col(q, t, m)];
+    }
   }
   return ok();
 }

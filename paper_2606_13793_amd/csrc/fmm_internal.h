@@ -42,17 +42,31 @@ constexpr __host__ __device__ int mi_index(int a, int b, int c) {
 // ---------------------------------------------------------------------------
 constexpr __host__ __device__ int m2l_ncol(int P) { return 8 * nterms(P); }
 constexpr __host__ __device__ int m2l_ntiles(int P) { return (m2l_ncol(P) + 15) / 16; }
+// row stride of the local arrays (columns padded to whole tiles)
+constexpr __host__ __device__ int loc_stride(int P) { return 16 * m2l_ntiles(P); }
 constexpr __host__ __device__ int m2l_col_degree(int col) {
   int m = 0;
   while (col >= 8 * nterms(m)) ++m;
   return m;
 }
+// column of (child q, local term index bt of degree m) in the M2L layout
+constexpr __host__ __device__ int m2l_col(int q, int bt, int m) {
+  return 8 * nterms(m - 1) + q * ndeg(m) + (bt - nterms(m - 1));
+}
 constexpr __host__ __device__ int m2l_tile_chunks(int P, int t) {
   return (nterms(P - m2l_col_degree(16 * t)) + 3) / 4;
 }
-// tiles are grouped per launch under a register budget
-constexpr int M2L_MAX_TILES = 12;
-constexpr int M2L_MAX_BOFS = 72;
+// fragments (tile, chunk) in canonical order: tile-major, chunk inside
+constexpr __host__ __device__ int m2l_frag_offset(int P, int t) {
+  int f = 0;
+  for (int u = 0; u < t; ++u) f += m2l_tile_chunks(P, u);
+  return f;
+}
+constexpr __host__ __device__ int m2l_nfrags(int P) { return m2l_frag_offset(P, m2l_ntiles(P)); }
+// tiles are grouped per launch under a register budget (accumulators of
+// M2L_MAX_TILES tiles x 4 row tiles) and a work budget (fragment chunks)
+constexpr int M2L_MAX_TILES = 5;
+constexpr int M2L_MAX_BOFS = 24;
 constexpr int m2l_group_end(int P, int t0) {
   int nt = 0, nb = 0, t = t0;
   while (t < m2l_ntiles(P)) {
@@ -88,7 +102,10 @@ struct Level {
   long long ncell = 0;   // nk^3
   long long ncellp = 0;  // nkp^3
   void* M = nullptr;  // multipoles, chunked [NC][ncellp][4], zero halo of 3 cells
-  void* L = nullptr;  // locals, chunked [NCL][ncell][4] (k >= 3)
+  // locals of level k >= 3, stored per parent cell P (level k-1) in M2L
+  // column order: L[P][m2l_col(q, b)] = Lhat of child 2P + q, term b;
+  // row stride loc_stride(p)
+  void* L = nullptr;
   int m_fp64 = 1;     // 1: multipoles stored in double, 0: float
   int l_fp64 = 1;
 };
@@ -96,7 +113,7 @@ struct Level {
 }  // namespace fmm
 
 namespace fmm {
-enum Stage { ST_P2M = 0, ST_M2M, ST_M2L, ST_BOTTOM, ST_SOLVE, ST_BACKWARD, ST_COUNT };
+enum Stage { ST_P2M = 0, ST_M2M, ST_M2L, ST_L2L, ST_BOTTOM, ST_SOLVE, ST_BACKWARD, ST_COUNT };
 struct StageRec {
   int stage;
   int launches;
@@ -119,6 +136,11 @@ struct fmm_plan {
   double* wm2p = nullptr;   // bottom kernel B operands in fragment order
   double* wl2p = nullptr;
   double* wp2p = nullptr;
+  double* wl2p2 = nullptr;  // L2P from the parent level, per parity class
+  double* wm2l = nullptr;   // M2L B operands, [343][fragments][64]
+  int* l2l_start = nullptr;     // L2L coefficient lists (CSR over local terms)
+  int* l2l_idx = nullptr;       // (index of b+g) << 3 | parity pattern of g
+  double* l2l_coef = nullptr;
   int* flag = nullptr;      // device scratch flag (finite check)
   size_t bytes = 0;
   // stage profiling
@@ -134,6 +156,9 @@ hipError_t launch_dtab(fmm_plan* pl, hipStream_t s);
 hipError_t launch_solve(fmm_plan* pl, const void* rho, void* phi, void* g, hipStream_t s);
 hipError_t launch_backward(fmm_plan* pl, const void* dphi, const void* dg, void* drho, hipStream_t s);
 hipError_t launch_check_finite(fmm_plan* pl, const void* rho, int* host_flag, hipStream_t s);
+// completes the stored locals of `level` (the finest level keeps only its M2L
+// part during a solve); used before inspecting them
+hipError_t finish_locals(fmm_plan* pl, int level, hipStream_t s);
 
 // Records an event pair around a stage when the plan is profiling.
 class StageScope {

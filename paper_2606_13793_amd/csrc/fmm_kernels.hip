@@ -348,13 +348,15 @@ __device__ __forceinline__ int halo_index(int hx, int hy, int hz) {
 
 template <int P, typename TI, typename TO>
 __global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom_f64(
-    const double* __restrict__ Mh, const double* __restrict__ Lf, const TI* __restrict__ rho,
-    const double* __restrict__ Wm2p, const double* __restrict__ Wl2p, const double* __restrict__ Wp2p,
-    const int* __restrict__ dlists, TO* __restrict__ phi, TO* __restrict__ g, int nF, double sphi, double sg) {
+    const double* __restrict__ Mh, const double* __restrict__ Lf, const double* __restrict__ Lpar,
+    const TI* __restrict__ rho, const double* __restrict__ Wm2p, const double* __restrict__ Wl2p,
+    const double* __restrict__ Wl2p2, const double* __restrict__ Wp2p, const int* __restrict__ dlists,
+    TO* __restrict__ phi, TO* __restrict__ g, int nF, double sphi, double sg) {
   constexpr int NM = nterms(P), NC = (NM + 3) / 4;
   constexpr int NL = nterms(P), NCL = (NL + 3) / 4;
   __shared__ d4 halo[HX * HY * HZ];
-  const int lane = threadIdx.x & 63, r = threadIdx.x >> 6;  // wave = parity class
+  const int lane = threadIdx.x & 63;
+  const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave = parity class (uniform)
   const int i = lane & 15, kq = lane >> 4;
   const int r0 = (r >> 2) & 1, r1 = (r >> 1) & 1, r2 = r & 1;
   const int nFp = nF + 6;
@@ -380,16 +382,23 @@ __global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom_f64(
     }
     __syncthreads();
     const double* hal = reinterpret_cast<const double*>(halo);
-    const double* wc = Wm2p + (size_t)c * 128 + lane;
-    int dd = dl[0];
-    double b0 = wc[(size_t)dd * (NC * 128)], b1 = wc[(size_t)dd * (NC * 128) + 64];
+    const double* wc = Wm2p + (size_t)c * (343 * 128) + lane;
+    // B fragments of offsets it and it + 1 in flight; blocks start at
+    // different offsets so that they do not request the same fragment at once
+    const int rot = (int)(((blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)) * 37u) % NLIST);
+    auto dl_at = [&](int j) { j += rot; return dl[j < NLIST ? j : j - NLIST]; };
+    double b0 = wc[(size_t)dl_at(0) * 128], b1 = wc[(size_t)dl_at(0) * 128 + 64];
+    double n0 = wc[(size_t)dl_at(1) * 128], n1 = wc[(size_t)dl_at(1) * 128 + 64];
     for (int it = 0; it < NLIST; ++it) {
+      const int dd = dl_at(it);
       const int d0 = dd / 49 - 3, d1 = (dd / 7) % 7 - 3, d2 = dd % 7 - 3;
       const double cb0 = b0, cb1 = b1;
-      if (it + 1 < NLIST) {  // prefetch the next offset's B fragments
-        dd = dl[it + 1];
-        b0 = wc[(size_t)dd * (NC * 128)];
-        b1 = wc[(size_t)dd * (NC * 128) + 64];
+      b0 = n0;
+      b1 = n1;
+      if (it + 2 < NLIST) {
+        const int dn = dl_at(it + 2);
+        n0 = wc[(size_t)dn * 128];
+        n1 = wc[(size_t)dn * 128 + 64];
       }
       // source halo coordinates of row (gx, gy, gz): 3 + 2 g + r - d
       const int zz = 3 + r2 - d2;  // in [1, 6]
@@ -407,7 +416,6 @@ __global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom_f64(
 
   const int n = 2 * nF;
   const long long N = (long long)n * n * n;
-  const long long nT = (long long)nF * nF * nF;
 #pragma unroll
   for (int m = 0; m < BOT_MT; ++m) {
     // the lane's own row (A operand) and its level-F cell, clamped into the grid
@@ -415,16 +423,43 @@ __global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom_f64(
     c0 = c0 < nF ? c0 : 0;
     c1 = c1 < nF ? c1 : 0;
     c2 = c2 < nF ? c2 : 0;
+    // L2P of the M2L part of the row's own local (stored with its parent P')
+    // and of the parent level's full local, evaluated at the unigrid centres
+    // (L2L followed by L2P as one exact polynomial evaluation; its B operand
+    // depends on the row's parity class r inside P')
     if (Lf) {
-      const long long Tl = ((long long)c0 * nF + c1) * nF + c2;
-#pragma unroll 4
+      constexpr int RS = loc_stride(P);
+      const int nP = nF >> 1;
+      const long long Pp = ((long long)(c0 >> 1) * nP + (c1 >> 1)) * nP + (c2 >> 1);
+      const double* own = Lf + Pp * RS;
+      const double* par = nullptr;
+      int qP = 0;
+      if (Lpar) {
+        const int nPP = nP >> 1;
+        const long long PP = ((long long)(c0 >> 2) * nPP + (c1 >> 2)) * nPP + (c2 >> 2);
+        par = Lpar + PP * RS;
+        qP = (((c0 >> 1) & 1) << 2) | (((c1 >> 1) & 1) << 1) | ((c2 >> 1) & 1);
+      }
+      const double* w2 = Wl2p2 + (size_t)r * NCL * 128 + lane;
+#pragma unroll 1
       for (int c = 0; c < NCL; ++c) {
-        const double a = Lf[((long long)c * nT + Tl) * 4 + kq];
+        const int bt = 4 * c + kq;
+        double a = 0.0, ap = 0.0;
+        if (bt < NL) {
+          const int ex = c_mi_exp[bt];
+          const int md = mi_a(ex) + mi_b(ex) + mi_c(ex);
+          a = own[m2l_col(r, bt, md)];
+          if (par) ap = par[m2l_col(qP, bt, md)];
+        }
         acc[m][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Wl2p[c * 128 + lane], acc[m][0], 0, 0, 0);
         acc[m][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Wl2p[c * 128 + 64 + lane], acc[m][1], 0, 0, 0);
+        if (par) {
+          acc[m][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap, w2[c * 128], acc[m][0], 0, 0, 0);
+          acc[m][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap, w2[c * 128 + 64], acc[m][1], 0, 0, 0);
+        }
       }
     }
-#pragma unroll 6
+#pragma unroll 1
     for (int c = 0; c < 54; ++c) {
       const int k = 4 * c + kq;
       const int e0 = k / 36 - 2, e1 = (k / 6) % 6 - 2, e2 = k % 6 - 2;
@@ -459,21 +494,22 @@ __global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom_f64(
 
 // Plan-time expansion of the bottom kernel's B operands into fragment order:
 // table[chunk][tile][lane], lane = j + 16 k holds B[k][j] of column 16 tile + j.
-//   M2P:  [343 offsets][NC][2][64]  D[a + e_o](Rhat_{d,q}), a = 4 chunk + k (0 past NM)
+//   M2P:  [NC][343 offsets][2][64]  D[a + e_o](Rhat_{d,q}), a = 4 chunk + k (0 past NM)
 //   L2P:  [NCL][2][64]              l2p_coef
 //   near: [54][2][64]               p2p_coef, source e = decode(4 chunk + k)
 __global__ void k_expand_bottom(const double* __restrict__ Dtab, double* __restrict__ Wm2p,
-                                double* __restrict__ Wl2p, double* __restrict__ Wp2p, int NM, int NC, int NL,
-                                int NCL, int ND) {
+                                double* __restrict__ Wl2p, double* __restrict__ Wp2p, double* __restrict__ Wl2p2,
+                                int NM, int NC, int NL, int NCL, int ND) {
   const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   const long long n_m2p = 343LL * NC * 128, n_l2p = (long long)NCL * 128, n_p2p = 54 * 128;
-  if (id >= n_m2p + n_l2p + n_p2p) return;
+  const long long n_l2p2 = 8LL * NCL * 128;
+  if (id >= n_m2p + n_l2p + n_p2p + n_l2p2) return;
   long long e = id;
   const int lane = (int)(e & 63), t = (int)((e >> 6) & 1);
   const int j = lane & 15, k = lane >> 4;
   const int col = 16 * t + j, q = col >> 2, o = col & 3;
   if (e < n_m2p) {
-    const int c = (int)((e >> 7) % NC), dd = (int)((e >> 7) / NC);
+    const int dd = (int)((e >> 7) % 343), c = (int)((e >> 7) / 343);
     const int al = 4 * c + k;
     double v = 0.0;
     if (al < NM) {
@@ -491,124 +527,261 @@ __global__ void k_expand_bottom(const double* __restrict__ Dtab, double* __restr
     return;
   }
   e -= n_l2p;
-  {
+  if (e < n_p2p) {
     const int c = (int)(e >> 7);
     const int kk = 4 * c + k;
     Wp2p[e] = p2p_coef(kk / 36 - 2, (kk / 6) % 6 - 2, kk % 6 - 2, q, o);
+    return;
+  }
+  e -= n_p2p;
+  {
+    // parent-level L2P: child rp of the parent, unigrid child q of that cell;
+    // w = 2 rp + q - 3/2 (units of dx) is the offset of the unigrid centre from
+    // the parent's centre.  phi: 1/2 4^-|b| w^b / b!;  g_d: 4^-|b| b_d w^(b-e_d) / b!
+    const int rp = (int)(e / (NCL * 128)), c = (int)((e >> 7) % NCL);
+    const int bt = 4 * c + k;
+    double v = 0.0;
+    if (bt < NL) {
+      const int ex = c_mi_exp[bt];
+      const int be[3] = {mi_a(ex), mi_b(ex), mi_c(ex)};
+      const double w[3] = {2.0 * ((rp >> 2) & 1) + ((q >> 2) & 1) - 1.5, 2.0 * ((rp >> 1) & 1) + ((q >> 1) & 1) - 1.5,
+                           2.0 * (rp & 1) + (q & 1) - 1.5};
+      const double base = ldexp(c_mi_invfact[bt], -2 * (be[0] + be[1] + be[2]));
+      if (o == 0) {
+        double mono = 1.0;
+        for (int ax = 0; ax < 3; ++ax)
+          for (int z = 0; z < be[ax]; ++z) mono *= w[ax];
+        v = 0.5 * base * mono;
+      } else {
+        const int dax = o - 1;
+        if (be[dax] > 0) {
+          double mono = 1.0;
+          for (int ax = 0; ax < 3; ++ax)
+            for (int z = 0; z < be[ax] - (ax == dax); ++z) mono *= w[ax];
+          v = base * be[dax] * mono;
+        }
+      }
+    }
+    Wl2p2[e] = v;
   }
 }
 
-// chunk count of each tile of an M2L launch, as a compile-time table
+// chunk count and first fragment of each tile of an M2L launch, as
+// compile-time tables (the helper functions loop and must not run on device)
 template <int P, int T0, int NT>
 struct TileChunks {
   int v[NT];
-  constexpr TileChunks() : v() {
-    for (int t = 0; t < NT; ++t) v[t] = m2l_tile_chunks(P, T0 + t);
+  int off[NT];
+  constexpr TileChunks() : v(), off() {
+    for (int t = 0; t < NT; ++t) {
+      v[t] = m2l_tile_chunks(P, T0 + t);
+      off[t] = m2l_frag_offset(P, T0 + t);
+    }
   }
 };
 
-// M2L: columns (q, b) sorted by |b|, tiles [T0, T1) of them.
-template <int P, int T0, int T1>
-__global__ __launch_bounds__(256, 2) void k_m2l_f64(const double* __restrict__ Mh, const double* __restrict__ Dtab,
-                                                   const int* __restrict__ dlists, const double* __restrict__ Lp,
-                                                   double* __restrict__ Lh, int ns) {
-  constexpr int NM = nterms(P), NL = nterms(P), ND = nterms(P + 1);
-  constexpr int NT = T1 - T0;
-  constexpr int CM = m2l_tile_chunks(P, T0);  // the group's first tile needs the most terms
-  constexpr int NS = (8 * ND + 255) / 256;
-  constexpr int ZERO = 8 * ND;
+// ---------------------------------------------------------------------------
+// M2L, eq. (M2L), over the oct-shared interaction lists (Sec. 2.2), every
+// level in one launch per column group.  Rows are cells P of a source grid
+// s = k - 1 (one wave per parity class of P); columns are (child q, local
+// term b) sorted by |b|; the result is the M2L part Lam_k of the locals of
+// the 8 children, Lam_k[2P + q][b] = 2^-(|b|+1) sum_d sum_a D[a+b](Rhat_{d,q}) Mhat_s[P-d][a].
+// A block owns an LX^3 tile of grid s plus a 3-cell halo, staged in LDS one
+// chunk of 4 multipole terms at a time (z de-interleaved by parity); B
+// fragments come from a plan-time fragment-order table, prefetched one
+// offset ahead.
+// ---------------------------------------------------------------------------
+constexpr int LX = 8;
+constexpr int LH = LX + 6, LH2 = LH / 2;
+constexpr int M2L_MT = (LX / 2) * (LX / 2) * (LX / 2) / 16;  // 4 row tiles per wave
+constexpr int M2L_THREADS = 512;
+constexpr int MAXLEV = 12;
+
+struct M2LLevels {
+  int nlev;
+  int first_block[MAXLEV + 1];
+  int tiles_per_axis[MAXLEV];
+  int ns[MAXLEV];
+  const double* M[MAXLEV];
+  double* Lam[MAXLEV];
+};
+
+__device__ __forceinline__ int lhalo_index(int hx, int hy, int hz) {
+  return ((hx * LH + hy) * 2 + (hz & 1)) * LH2 + (hz >> 1);
+}
+
+template <int P, int T0, int NT>
+__global__ __launch_bounds__(M2L_THREADS, 1) void k_m2l_f64(M2LLevels lv, const double* __restrict__ Wm2l,
+                                                           const int* __restrict__ dlists) {
+  constexpr int NL = nterms(P);
   constexpr int NCOL = 8 * NL;
   constexpr TileChunks<P, T0, NT> kch{};
-  __shared__ double sD[2][8 * ND + 1];
-  const int r = blockIdx.y;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i = lane & 15, kq = lane >> 4;
-  const int nG = ns >> 1, nsp = ns + 6;
-  const long long nlat = (long long)nG * nG * nG;
+  constexpr int CM = kch.v[0];
+  __shared__ d4 halo[LH * LH * LH];
+  int li = 0;
+  while (li + 1 < lv.nlev && (int)blockIdx.x >= lv.first_block[li + 1]) ++li;
+  const int tb = (int)blockIdx.x - lv.first_block[li];
+  const int tpa = lv.tiles_per_axis[li];
+  const int ns = lv.ns[li], nsp = ns + 6;
+  const double* __restrict__ Mh = lv.M[li];
+  double* __restrict__ Lam = lv.Lam[li];
+  const int tx0 = (tb / (tpa * tpa)) * LX, ty0 = ((tb / tpa) % tpa) * LX, tz0 = (tb % tpa) * LX;
   const long long ncellp = (long long)nsp * nsp * nsp;
-  const long long tile0 = ((long long)blockIdx.x * 4 + wave) * 16;
-  const RowCtx rc = row_of(tile0 + i, nlat, nG, r, nsp);
+  const int lane = threadIdx.x & 63;
+  const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave = parity class (uniform)
+  const int i = lane & 15, kq = lane >> 4;
+  const int r0 = (r >> 2) & 1, r1 = (r >> 1) & 1, r2 = r & 1;
+  const int gy = i >> 2, gz = i & 3;  // row i of tile m: lattice (m, gy, gz)
 
-  int bofs[NT][CM];
+  d4 acc[M2L_MT][NT];
+#pragma unroll
+  for (int m = 0; m < M2L_MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = d4{0, 0, 0, 0};
+  const int* dl = dlists + r * NLIST;
+  const double* wl = Wm2l + lane;
+
+  for (int c = 0; c < CM; ++c) {
+    __syncthreads();
+    for (int h = threadIdx.x; h < LH * LH * LH; h += M2L_THREADS) {
+      const int hz = h % LH, hy = (h / LH) % LH, hx = h / (LH * LH);
+      const int px = tx0 + hx, py = ty0 + hy, pz = tz0 + hz;
+      d4 v = d4{0, 0, 0, 0};
+      if (px < nsp && py < nsp && pz < nsp)
+        v = *reinterpret_cast<const d4*>(Mh + (c * ncellp + ((long long)px * nsp + py) * nsp + pz) * 4);
+      halo[lhalo_index(hx, hy, hz)] = v;
+    }
+    __syncthreads();
+    const double* hal = reinterpret_cast<const double*>(halo);
+    // Blocks walk the offset list from different starting points (the sum is
+    // order-independent) so that concurrent blocks do not all request the same
+    // B fragment at once.  B fragments of offsets it and it + 1 are in flight.
+    const int rot = (int)((blockIdx.x * 37u) % NLIST);
+    auto dl_at = [&](int j) { j += rot; return dl[j < NLIST ? j : j - NLIST]; };
+    double b0[NT], b1[NT];
+    {
+      const int e0 = dl_at(0), e1 = dl_at(1);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        b0[t] = (c < kch.v[t]) ? wl[((size_t)(kch.off[t] + c) * 343 + e0) * 64] : 0.0;
+        b1[t] = (c < kch.v[t]) ? wl[((size_t)(kch.off[t] + c) * 343 + e1) * 64] : 0.0;
+      }
+    }
+    for (int it = 0; it < NLIST; ++it) {
+      const int dd = dl_at(it);
+      const int d0 = dd / 49 - 3, d1 = (dd / 7) % 7 - 3, d2 = dd % 7 - 3;
+      double cb[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        cb[t] = b0[t];
+        b0[t] = b1[t];
+      }
+      if (it + 2 < NLIST) {
+        const int dn = dl_at(it + 2);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          if (c < kch.v[t]) b1[t] = wl[((size_t)(kch.off[t] + c) * 343 + dn) * 64];
+      }
+      const int zz = 3 + r2 - d2;
+      const int zoff = (zz & 1) * LH2 + gz + (zz >> 1);
+      const int hy = 3 + 2 * gy + r1 - d1;
+#pragma unroll
+      for (int m = 0; m < M2L_MT; ++m) {
+        const int hx = 3 + 2 * m + r0 - d0;
+        const double a = hal[((hx * LH + hy) * 2 * LH2 + zoff) * 4 + kq];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          if (c < kch.v[t]) acc[m][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, cb[t], acc[m][t], 0, 0, 0);
+      }
+    }
+  }
+  // epilogue (f64 layout): element v of tile t is row 4v + kq, column 16 (T0 + t) + i;
+  // locals are stored per source cell in column order, so the 16 lanes of a
+  // row write 128 contiguous bytes
+  constexpr int RS = loc_stride(P);
+  int escale[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int col = 16 * (T0 + t) + i;
-    int q = 0, bx = 0, by = 0, bz = 0, m = P + 1;
-    if (col < NCOL) {
-      m = m2l_col_degree(col);
-      const int cin = col - 8 * nterms(m - 1);
-      q = cin / ndeg(m);
-      const int bex = c_mi_exp[nterms(m - 1) + cin % ndeg(m)];
-      bx = mi_a(bex); by = mi_b(bex); bz = mi_c(bex);
-    }
-#pragma unroll
-    for (int c = 0; c < CM; ++c) {
-      const int al = 4 * c + kq;
-      int off = ZERO;
-      if (al < NM) {
-        const int ex = c_mi_exp[al];
-        const int a = mi_a(ex), b = mi_b(ex), cc = mi_c(ex);
-        if (a + b + cc + m <= P) off = q * ND + mi_index(a + bx, b + by, cc + bz);
-      }
-      bofs[t][c] = off;
-    }
+    escale[t] = -(m2l_col_degree(col < NCOL ? col : 0) + 1);
   }
-  if (threadIdx.x == 0) { sD[0][ZERO] = 0.0; sD[1][ZERO] = 0.0; }
-  const int* dl = dlists + r * NLIST;
-  double pre[NS];
-  stage_load<ND>(Dtab + (size_t)dl[0] * 8 * ND, pre);
-  stage_store<ND>(sD[0], pre);
-  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M2L_MT; ++m)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 4 * v + kq;
+      const int p0 = tx0 + 2 * m + r0, p1 = ty0 + 2 * (row >> 2) + r1, p2 = tz0 + 2 * (row & 3) + r2;
+      if (p0 >= ns || p1 >= ns || p2 >= ns) continue;
+      double* dst = Lam + (((long long)p0 * ns + p1) * ns + p2) * RS + 16 * T0 + i;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) dst[16 * t] = ldexp(acc[m][t][v], escale[t]);
+    }
+}
 
-  d4 acc[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = d4{0, 0, 0, 0};
-  const double* mbase = Mh + kq;
-  for (int it = 0; it < NLIST; ++it) {
-    const int dd = dl[it];
-    const int d0 = dd / 49 - 3, d1 = (dd / 7) % 7 - 3, d2 = dd % 7 - 3;
-    const long long src = rc.cell - ((long long)d0 * nsp + d1) * nsp - d2;
-    double a[CM];
-#pragma unroll
-    for (int c = 0; c < CM; ++c) a[c] = mbase[(c * ncellp + src) * 4];
-    if (it + 1 < NLIST) stage_load<ND>(Dtab + (size_t)dl[it + 1] * 8 * ND, pre);
-    const double* sd = sD[it & 1];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-#pragma unroll
-      for (int c = 0; c < CM; ++c)
-        if (c < kch.v[t]) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c], sd[bofs[t][c]], acc[t], 0, 0, 0);
-    }
-    if (it + 1 < NLIST) stage_store<ND>(sD[(it + 1) & 1], pre);
-    __syncthreads();
+// B fragments of the M2L in fragment order: [fragment f][343 offsets][64]
+// (the offsets of one fragment are contiguous), fragment f = (tile t, chunk
+// c); lane j + 16 k holds D[a + b](Rhat_{d,q}) of column 16 t + j = (q, b) and
+// term a = 4 c + k (0 where |a| + |b| > p).
+__global__ void k_expand_m2l(const double* __restrict__ Dtab, double* __restrict__ W, int P, int NF, int ND) {
+  const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= 343LL * NF * 64) return;
+  const int lane = (int)(id & 63);
+  const int dd = (int)((id >> 6) % 343), f = (int)((id >> 6) / 343);
+  int t = 0;
+  while (m2l_frag_offset(P, t + 1) <= f) ++t;
+  const int c = f - m2l_frag_offset(P, t);
+  const int j = lane & 15, k = lane >> 4;
+  const int col = 16 * t + j, al = 4 * c + k;
+  double v = 0.0;
+  if (col < 8 * nterms(P) && al < nterms(P)) {
+    const int md = m2l_col_degree(col);
+    const int cin = col - 8 * nterms(md - 1);
+    const int q = cin / ndeg(md);
+    const int bex = c_mi_exp[nterms(md - 1) + cin % ndeg(md)];
+    const int aex = c_mi_exp[al];
+    if (mi_a(aex) + mi_b(aex) + mi_c(aex) + md <= P)
+      v = Dtab[((size_t)dd * 8 + q) * ND +
+               mi_index(mi_a(aex) + mi_a(bex), mi_b(aex) + mi_b(bex), mi_c(aex) + mi_c(bex))];
   }
-  // epilogue: Lhat_k[2P + q][b] = 2^-(|b|+1) acc + L2L from Lhat_{k-1}[P]
-  const int nk = 2 * ns;
-  const long long nck = (long long)nk * nk * nk;
-  const long long ncs = (long long)ns * ns * ns;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const RowCtx ro = row_of(tile0 + 4 * v + kq, nlat, nG, r, nsp);
-    if (!ro.valid) continue;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int col = 16 * (T0 + t) + i;
-      if (col >= NCOL) continue;
-      const int m = m2l_col_degree(col);
-      const int cin = col - 8 * nterms(m - 1);
-      const int q = cin / ndeg(m);
-      const int bt = nterms(m - 1) + cin % ndeg(m);
-      const long long T = ((long long)(2 * ro.c0 + ((q >> 2) & 1)) * nk + (2 * ro.c1 + ((q >> 1) & 1))) * nk +
-                          (2 * ro.c2 + (q & 1));
-      double val = ldexp(acc[t][v], -(m + 1));
-      if (Lp) {
-        const int bex = c_mi_exp[bt];
-        const long long Pl = ((long long)ro.c0 * ns + ro.c1) * ns + ro.c2;
-        val += l2l_term<P>(Lp, ncs, Pl, q, mi_a(bex), mi_b(bex), mi_c(bex), m);
-      }
-      Lh[((bt >> 2) * nck + T) * 4 + (bt & 3)] = val;
-    }
+  W[id] = v;
+}
+
+// ---------------------------------------------------------------------------
+// L2L, eq. (L2L), for one level k: Lhat_k[T] += shift of Lhat_{k-1}[parent(T)]
+//   Lhat_k[b] += sum_{|b|+|g|<=p} 2^-(|b|+1) 4^-|g| / g! (2q-1)^g Lhat_{k-1}[b+g]
+// in the per-parent column layout.  Thread = (cell P of level k-1, column
+// (q, b)); lanes run along columns, so loads and stores of the child locals
+// are contiguous and, inside a degree block, every lane walks a list of the
+// same length.  Lists (CSR over b): coefficient and, packed,
+// column base of b+g (column with q = 0) << 9 | ndeg(|b+g|) << 3 | parity of g.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_l2l(const double* __restrict__ Lprev, double* __restrict__ Lk,
+                                             const int* __restrict__ cs, const int* __restrict__ cidx,
+                                             const double* __restrict__ ccoef, int ns, int NL, int RS) {
+  const long long nps = (long long)ns * ns * ns;
+  const long long id = blockIdx.x * 256LL + threadIdx.x;
+  if (id >= nps * RS) return;
+  const long long P = id / RS;
+  const int col = (int)(id % RS);
+  if (col >= 8 * NL) return;
+  const int md = m2l_col_degree(col);
+  const int cin = col - 8 * nterms(md - 1);
+  const int q = cin / ndeg(md);
+  const int bt = nterms(md - 1) + cin % ndeg(md);
+  const int p2 = (int)(P % ns), p1 = (int)((P / ns) % ns), p0 = (int)(P / ((long long)ns * ns));
+  const int nsp = ns >> 1;
+  const long long PP = ((long long)(p0 >> 1) * nsp + (p1 >> 1)) * nsp + (p2 >> 1);
+  const int qP = ((p0 & 1) << 2) | ((p1 & 1) << 1) | (p2 & 1);
+  const int nq = (~q) & 7;  // axes with q_i = 0
+  const double* src = Lprev + PP * RS;
+  double acc = 0.0;
+  for (int j = cs[bt]; j < cs[bt + 1]; ++j) {
+    const int id2 = cidx[j];
+    const int cb = id2 >> 9, nd = (id2 >> 3) & 63, pat = id2 & 7;
+    const double x = ccoef[j] * src[cb + qP * nd];
+    acc += (__popc(nq & pat) & 1) ? -x : x;
   }
+  Lk[P * RS + col] += acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -621,9 +794,16 @@ hipError_t launch_dtab(fmm_plan* pl, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   {
-    const long long cnt = 343LL * pl->NC * 128 + (long long)pl->NCL * 128 + 54 * 128;
+    const long long cnt = 343LL * pl->NC * 128 + (long long)pl->NCL * 128 + 54 * 128 + 8LL * pl->NCL * 128;
     hipLaunchKernelGGL(k_expand_bottom, dim3(blocks_for(cnt, 256)), dim3(256), 0, s, pl->dtab, pl->wm2p, pl->wl2p,
-                       pl->wp2p, pl->NM, pl->NC, pl->NL, pl->NCL, pl->ND);
+                       pl->wp2p, pl->wl2p2, pl->NM, pl->NC, pl->NL, pl->NCL, pl->ND);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  {
+    const int NF = m2l_nfrags(pl->p);
+    const long long cnt = 343LL * NF * 64;
+    hipLaunchKernelGGL(k_expand_m2l, dim3(blocks_for(cnt, 256)), dim3(256), 0, s, pl->dtab, pl->wm2l, pl->p, NF,
+                       pl->ND);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (pl->dtab32) {
@@ -635,21 +815,31 @@ hipError_t launch_dtab(fmm_plan* pl, hipStream_t s) {
 }
 
 template <int P, int G>
-static hipError_t launch_m2l_groups(fmm_plan* pl, int k, hipStream_t s) {
+static hipError_t launch_m2l_groups(fmm_plan* pl, const M2LLevels& lv, hipStream_t s) {
   if constexpr (G >= m2l_ngroups(P)) {
     return hipSuccess;
   } else {
     constexpr int T0 = m2l_group_start(P, G), T1 = m2l_group_end(P, T0);
-    const int ns = 1 << (k - 1);
-    const long long nlat = (long long)(ns / 2) * (ns / 2) * (ns / 2);
-    dim3 grid(blocks_for(nlat, 64), 8);
-    const double* Lp = (k >= 4) ? (const double*)pl->lev[k - 1].L : nullptr;
-    hipLaunchKernelGGL((k_m2l_f64<P, T0, T1>), grid, dim3(256), 0, s, (const double*)pl->lev[k - 1].M, pl->dtab,
-                       pl->dlists, Lp, (double*)pl->lev[k].L, ns);
+    hipLaunchKernelGGL((k_m2l_f64<P, T0, T1 - T0>), dim3(lv.first_block[lv.nlev]), dim3(M2L_THREADS), 0, s, lv,
+                       pl->wm2l, pl->dlists);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_m2l_groups<P, G + 1>(pl, k, s);
+    return launch_m2l_groups<P, G + 1>(pl, lv, s);
   }
+}
+
+// L2L for one level k (Lhat_k += shift of Lhat_{k-1}), in place
+static hipError_t launch_l2l(fmm_plan* pl, int k, hipStream_t s) {
+  const int ns = 1 << (k - 1), RS = loc_stride(pl->p);
+  const long long work = (long long)ns * ns * ns * RS;
+  hipLaunchKernelGGL(k_l2l, dim3(blocks_for(work, 256)), dim3(256), 0, s, (const double*)pl->lev[k - 1].L,
+                     (double*)pl->lev[k].L, pl->l2l_start, pl->l2l_idx, pl->l2l_coef, ns, pl->NL, RS);
+  return hipGetLastError();
+}
+
+hipError_t finish_locals(fmm_plan* pl, int level, hipStream_t s) {
+  if (level >= 4 && level == pl->F) return launch_l2l(pl, level, s);
+  return hipSuccess;
 }
 
 template <int P, typename TI, typename TO>
@@ -670,18 +860,40 @@ static hipError_t solve_fp64(fmm_plan* pl, const TI* rho, TO* phi, TO* g, hipStr
                        (double*)pl->lev[k - 1].M, 1 << k, NM, NC);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  for (int k = 3; k <= F; ++k) {
-    StageScope sc(pl, ST_M2L, m2l_ngroups(P), s);
-    if ((e = launch_m2l_groups<P, 0>(pl, k, s)) != hipSuccess) return e;
+  if (F >= 3) {
+    // M2L of every level k = 3..F at once (sources at s = k - 1)
+    M2LLevels lv{};
+    lv.nlev = F - 2;
+    lv.first_block[0] = 0;
+    for (int li = 0; li < lv.nlev; ++li) {
+      const int k = li + 3, ns = 1 << (k - 1);
+      lv.ns[li] = ns;
+      lv.tiles_per_axis[li] = (ns + LX - 1) / LX;
+      lv.M[li] = (const double*)pl->lev[k - 1].M;
+      lv.Lam[li] = (double*)pl->lev[k].L;
+      const int tpa = lv.tiles_per_axis[li];
+      lv.first_block[li + 1] = lv.first_block[li] + tpa * tpa * tpa;
+    }
+    {
+      StageScope sc(pl, ST_M2L, m2l_ngroups(P), s);
+      if ((e = launch_m2l_groups<P, 0>(pl, lv, s)) != hipSuccess) return e;
+    }
+    // L2L down to level F - 1; level F's far field is taken from Lhat_{F-1}
+    // directly by the bottom kernel
+    StageScope sc(pl, ST_L2L, F - 4 > 0 ? F - 4 : 0, s);
+    for (int k = 4; k <= F - 1; ++k)
+      if ((e = launch_l2l(pl, k, s)) != hipSuccess) return e;
   }
   {
     StageScope sc(pl, ST_BOTTOM, 1, s);
     const int nF = n / 2;
     const double dx = pl->dx;
     const double* Lf = (F >= 3) ? (const double*)pl->lev[F].L : nullptr;
+    const double* Lpar = (F >= 4) ? (const double*)pl->lev[F - 1].L : nullptr;
     dim3 bgrid(blocks_for(nF, BX), blocks_for(nF, BY), blocks_for(nF, BZ));
     hipLaunchKernelGGL((k_bottom_f64<P, TI, TO>), bgrid, dim3(BOT_THREADS), 0, s, (const double*)pl->lev[F].M, Lf,
-                       rho, pl->wm2p, pl->wl2p, pl->wp2p, pl->dlists, phi, g, nF, 0.5 * dx * dx, -0.25 * dx);
+                       Lpar, rho, pl->wm2p, pl->wl2p, pl->wl2p2, pl->wp2p, pl->dlists, phi, g, nF, 0.5 * dx * dx,
+                       -0.25 * dx);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
