@@ -112,7 +112,7 @@ def main():
     bot_tflops = stage_flops["bottom"] / bot_avg_s / 1e12
     peak = PEAK_TFLOPS[prec]
     roofline = {
-        "kernel": "bottom: M2P + L2P + near field (k_m2p)",
+        "kernel": "k_bottom: M2P + L2P + near field",
         "bound": "mfma",
         "achieved": round(bot_tflops, 3),
         "peak": peak,

@@ -58,7 +58,6 @@ int validate(int n, int p, int isolated, const fmm_options* o) {
       return fail(FMM_ERR_INVALID_ARG, "nmax must be -1 or in [0, p] (got %d)", o->nmax);
     if (o->delta_l != 1) return fail(FMM_ERR_UNSUPPORTED, "only delta_l = 1 is provided (got %d)", o->delta_l);
     if (o->coarse_fp64_levels < 0) return fail(FMM_ERR_INVALID_ARG, "coarse_fp64_levels must be >= 0");
-    if (o->precision != FMM_FP64) return fail(FMM_ERR_UNSUPPORTED, "precision %d is not built yet", o->precision);
     if (o->nmax != -1 && o->nmax != p) return fail(FMM_ERR_UNSUPPORTED, "nmax != p is not built yet");
   }
   return FMM_OK;
@@ -68,9 +67,10 @@ int validate(int n, int p, int isolated, const fmm_options* o) {
 size_t plan_bytes(int n, int p) {
   const int F = ilog2_exact(n) - 1;
   const int NM = fmm::nterms(p), NC = (NM + 3) / 4, NCL = NC, ND = fmm::nterms(p + 1);
-  size_t b = (size_t)343 * 8 * ND * sizeof(double) + 8 * fmm::NLIST * sizeof(int) + 256;
-  b += ((size_t)343 * NC * 128 + (size_t)NCL * 128 * 9 + 54 * 128) * sizeof(double);
-  b += (size_t)343 * fmm::m2l_nfrags(p) * 64 * sizeof(double);
+  size_t b = (size_t)343 * 8 * ND * sizeof(double) + 8 * fmm::NLIST_PAD * sizeof(int) + 256;
+  // FP64 matrix-core tables (the largest set a plan builds)
+  b += ((size_t)21 * fmm::NSLOT * 128 + (size_t)NCL * 128 * 9 + 54 * 128) * sizeof(double);
+  b += (size_t)fmm::NSLOT * fmm::m2l_nfrags(p) * 64 * sizeof(double);
   for (int k = 2; k <= F; ++k) {
     const size_t nkp = (size_t)(1 << k) + 6;
     b += (size_t)NC * nkp * nkp * nkp * 4 * sizeof(double);
@@ -93,11 +93,13 @@ void release(fmm_plan* pl) {
   if (pl->dtab) (void)hipFree(pl->dtab);
   if (pl->dtab32) (void)hipFree(pl->dtab32);
   if (pl->dlists) (void)hipFree(pl->dlists);
-  if (pl->wm2p) (void)hipFree(pl->wm2p);
-  if (pl->wl2p) (void)hipFree(pl->wl2p);
-  if (pl->wp2p) (void)hipFree(pl->wp2p);
-  if (pl->wl2p2) (void)hipFree(pl->wl2p2);
-  if (pl->wm2l) (void)hipFree(pl->wm2l);
+  for (int x = 0; x < 3; ++x) {
+    if (pl->wm2p[x]) (void)hipFree(pl->wm2p[x]);
+    if (pl->wl2p[x]) (void)hipFree(pl->wl2p[x]);
+    if (pl->wl2p2[x]) (void)hipFree(pl->wl2p2[x]);
+    if (pl->wp2p[x]) (void)hipFree(pl->wp2p[x]);
+    if (pl->wm2l[x]) (void)hipFree(pl->wm2l[x]);
+  }
   if (pl->l2l_start) (void)hipFree(pl->l2l_start);
   if (pl->l2l_idx) (void)hipFree(pl->l2l_idx);
   if (pl->l2l_coef) (void)hipFree(pl->l2l_coef);
@@ -118,11 +120,15 @@ int dev_alloc(fmm_plan* pl, void** ptr, size_t bytes) {
 
 // per parity r, the 189 offsets d = P - J of the interaction list (Sec. 2.2):
 // parent(J) adjacent to parent(P) and J not adjacent to P gives, per axis,
-// d in [r - 3, r + 2], excluding |d| <= 1 on all three axes.
+// d in [r - 3, r + 2], excluding |d| <= 1 on all three axes.  Entries are
+// packed (offset index, d + 3 per axis); entry 189 is the null offset (index
+// 343, zero weights) with d = r, which keeps halo addresses in range.
 std::vector<int> build_dlists() {
   std::vector<int> out;
+  auto pack = [](int dd, int d0, int d1, int d2) { return dd | ((d0 + 3) << 9) | ((d1 + 3) << 12) | ((d2 + 3) << 15); };
   for (int r = 0; r < 8; ++r) {
     const int rr[3] = {(r >> 2) & 1, (r >> 1) & 1, r & 1};
+    int count = 0;
     for (int dd = 0; dd < 343; ++dd) {
       const int d[3] = {dd / 49 - 3, (dd / 7) % 7 - 3, dd % 7 - 3};
       bool in = true, near = true;
@@ -130,8 +136,13 @@ std::vector<int> build_dlists() {
         if (d[a] < rr[a] - 3 || d[a] > rr[a] + 2) in = false;
         if (d[a] < -1 || d[a] > 1) near = false;
       }
-      if (in && !near) out.push_back(dd);
+      if (in && !near) {
+        out.push_back(pack(dd, d[0], d[1], d[2]));
+        ++count;
+      }
     }
+    if (count != fmm::NLIST) return {};
+    for (int pad = fmm::NLIST; pad < fmm::NLIST_PAD; ++pad) out.push_back(pack(343, rr[0], rr[1], rr[2]));
   }
   return out;
 }
@@ -234,12 +245,7 @@ fmm_plan* fmm_plan_create_ex(int n, int p, int isolated, const fmm_options* opt)
     return nullptr;
   };
   if (dev_alloc(pl, (void**)&pl->dtab, (size_t)343 * 8 * pl->ND * sizeof(double))) return bail();
-  if (dev_alloc(pl, (void**)&pl->dlists, 8 * fmm::NLIST * sizeof(int))) return bail();
-  if (dev_alloc(pl, (void**)&pl->wm2p, (size_t)343 * pl->NC * 128 * sizeof(double))) return bail();
-  if (dev_alloc(pl, (void**)&pl->wl2p, (size_t)pl->NCL * 128 * sizeof(double))) return bail();
-  if (dev_alloc(pl, (void**)&pl->wp2p, (size_t)54 * 128 * sizeof(double))) return bail();
-  if (dev_alloc(pl, (void**)&pl->wl2p2, (size_t)8 * pl->NCL * 128 * sizeof(double))) return bail();
-  if (dev_alloc(pl, (void**)&pl->wm2l, (size_t)343 * fmm::m2l_nfrags(p) * 64 * sizeof(double))) return bail();
+  if (dev_alloc(pl, (void**)&pl->dlists, 8 * fmm::NLIST_PAD * sizeof(int))) return bail();
   {
     // L2L coefficient lists: for each local term b, the terms b + g with
     // |b + g| <= p, coefficient 2^-(|b|+1) 4^-|g| / g!, the column of b + g
@@ -302,7 +308,7 @@ fmm_plan* fmm_plan_create_ex(int n, int p, int isolated, const fmm_options* opt)
     }
   }
   const std::vector<int> dl = build_dlists();
-  if (dl.size() != 8 * (size_t)fmm::NLIST) {
+  if (dl.size() != 8 * (size_t)fmm::NLIST_PAD) {
     fail(FMM_ERR_DEVICE, "interaction-list table has %zu entries", dl.size());
     return bail();
   }
@@ -311,7 +317,9 @@ fmm_plan* fmm_plan_create_ex(int n, int p, int isolated, const fmm_options* opt)
     return bail();
   }
   if ((e = fmm::launch_dtab(pl, nullptr)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
-    fail(FMM_ERR_DEVICE, "derivative-table precompute failed: %s", hipGetErrorString(e));
+    (void)hipGetLastError();
+    fail(e == hipErrorOutOfMemory ? FMM_ERR_OUT_OF_MEMORY : FMM_ERR_DEVICE, "table precompute failed: %s",
+         hipGetErrorString(e));
     return bail();
   }
   ok();

@@ -53,44 +53,53 @@ constexpr __host__ __device__ int m2l_col_degree(int col) {
 constexpr __host__ __device__ int m2l_col(int q, int bt, int m) {
   return 8 * nterms(m - 1) + q * ndeg(m) + (bt - nterms(m - 1));
 }
-constexpr __host__ __device__ int m2l_tile_chunks(int P, int t) {
-  return (nterms(P - m2l_col_degree(16 * t)) + 3) / 4;
+// number of K chunks (of KC multipole terms) tile t needs: terms |a| <= p - m
+constexpr __host__ __device__ int m2l_tile_chunks(int P, int t, int KC = 4) {
+  return (nterms(P - m2l_col_degree(16 * t)) + KC - 1) / KC;
 }
 // fragments (tile, chunk) in canonical order: tile-major, chunk inside
-constexpr __host__ __device__ int m2l_frag_offset(int P, int t) {
+constexpr __host__ __device__ int m2l_frag_offset(int P, int t, int KC = 4) {
   int f = 0;
-  for (int u = 0; u < t; ++u) f += m2l_tile_chunks(P, u);
+  for (int u = 0; u < t; ++u) f += m2l_tile_chunks(P, u, KC);
   return f;
 }
-constexpr __host__ __device__ int m2l_nfrags(int P) { return m2l_frag_offset(P, m2l_ntiles(P)); }
+constexpr __host__ __device__ int m2l_nfrags(int P, int KC = 4) { return m2l_frag_offset(P, m2l_ntiles(P), KC); }
 // tiles are grouped per launch under a register budget (accumulators of
-// M2L_MAX_TILES tiles x 4 row tiles) and a work budget (fragment chunks)
-constexpr int M2L_MAX_TILES = 5;
-constexpr int M2L_MAX_BOFS = 24;
-constexpr int m2l_group_end(int P, int t0) {
+// MAXT tiles x 4 row tiles) and a work budget (MAXB fragment chunks)
+constexpr int m2l_group_end(int P, int t0, int KC, int MAXT, int MAXB) {
   int nt = 0, nb = 0, t = t0;
   while (t < m2l_ntiles(P)) {
-    const int c = m2l_tile_chunks(P, t);
-    if (nt > 0 && (nt + 1 > M2L_MAX_TILES || nb + c > M2L_MAX_BOFS)) break;
+    const int c = m2l_tile_chunks(P, t, KC);
+    if (nt > 0 && (nt + 1 > MAXT || nb + c > MAXB)) break;
     ++nt;
     nb += c;
     ++t;
   }
   return t;
 }
-constexpr int m2l_group_start(int P, int g) {
+constexpr int m2l_group_start(int P, int g, int KC, int MAXT, int MAXB) {
   int t = 0;
-  for (int i = 0; i < g; ++i) t = m2l_group_end(P, t);
+  for (int i = 0; i < g; ++i) t = m2l_group_end(P, t, KC, MAXT, MAXB);
   return t;
 }
-constexpr int m2l_ngroups(int P) {
+constexpr int m2l_ngroups(int P, int KC, int MAXT, int MAXB) {
   int g = 0, t = 0;
-  while (t < m2l_ntiles(P)) { t = m2l_group_end(P, t); ++g; }
+  while (t < m2l_ntiles(P)) { t = m2l_group_end(P, t, KC, MAXT, MAXB); ++g; }
   return g;
 }
 
-// number of interaction-list offsets per parity class (6^3 - 3^3)
+// number of interaction-list offsets per parity class (6^3 - 3^3); the
+// device lists hold NLIST_PAD entries per class, entry NLIST being a null
+// offset (zero weights) used to pad pairs of offsets.  Entries are packed:
+// bits 0-8 offset index dd (0..342, 343 = null), then 3 bits each of
+// d0 + 3, d1 + 3, d2 + 3.
 constexpr int NLIST = 189;
+constexpr int NLIST_PAD = 192;
+constexpr int NSLOT = 344;  // B-table offset slots: 343 offsets + the null one
+__host__ __device__ inline int dl_dd(int e) { return e & 511; }
+__host__ __device__ inline int dl_d0(int e) { return ((e >> 9) & 7) - 3; }
+__host__ __device__ inline int dl_d1(int e) { return ((e >> 12) & 7) - 3; }
+__host__ __device__ inline int dl_d2(int e) { return ((e >> 15) & 7) - 3; }
 
 // ---------------------------------------------------------------------------
 // device state of one plan
@@ -132,12 +141,14 @@ struct fmm_plan {
   fmm::Level lev[16];
   double* dtab = nullptr;   // [343][8][ND] D[g](Rhat) in FP64
   float* dtab32 = nullptr;  // FP32 copy for mixed plans
-  int* dlists = nullptr;    // [8][189] offset index (0..342) per parity
-  double* wm2p = nullptr;   // bottom kernel B operands in fragment order
-  double* wl2p = nullptr;
-  double* wp2p = nullptr;
-  double* wl2p2 = nullptr;  // L2P from the parent level, per parity class
-  double* wm2l = nullptr;   // M2L B operands, [343][fragments][64]
+  int* dlists = nullptr;    // [8][NLIST_PAD] packed interaction offsets per parity
+  // matrix-core B operands in fragment order, per compute type (index
+  // 0 = FP64, 1 = FP32, 2 = BF16); only the types a plan uses are built
+  void* wm2p[3] = {nullptr, nullptr, nullptr};   // M2P
+  void* wl2p[3] = {nullptr, nullptr, nullptr};   // L2P of the own local
+  void* wl2p2[3] = {nullptr, nullptr, nullptr};  // L2P from the parent level
+  void* wp2p[3] = {nullptr, nullptr, nullptr};   // near field
+  void* wm2l[3] = {nullptr, nullptr, nullptr};   // M2L
   int* l2l_start = nullptr;     // L2L coefficient lists (CSR over local terms)
   int* l2l_idx = nullptr;       // (index of b+g) << 3 | parity pattern of g
   double* l2l_coef = nullptr;

@@ -1,0 +1,553 @@
+// Matrix-core kernels of the downward pass, generic over the compute type:
+//   double     v_mfma_f64_16x16x4f64   K = 4 per op, FP64 accumulation
+//   float      v_mfma_f32_16x16x4f32   K = 4 per op, FP32 accumulation
+//   bf16_tag   v_mfma_f32_16x16x32_bf16 K = 32 per op (two interaction
+//              offsets x 16 multipole terms), FP32 accumulation
+// Included by fmm_kernels.hip (needs its constant tables and helpers).
+//
+// Both kernels are sums over the 189 offsets d of a parity class (Sec. 2.2):
+// with the source grid s, a "row" is a cell P of grid s of parity r and
+//   out[P][col] = sum_d sum_a B_d[a][col] Mhat_s[P - d][a],
+// B_d[a][(q, x)] = D[a + x](Rhat_{d,q}).  For M2L x runs over local terms
+// (eq. (M2L)); for M2P x is one of {0, e_x, e_y, e_z} (potential and
+// acceleration at the unigrid children).  A block owns a tile of grid s plus a
+// 3-cell halo, staged in LDS one chunk of KC multipole terms at a time (z
+// de-interleaved by parity), converted from the FP64 multipoles while
+// staging; one wave per parity class.  B fragments come from plan-time
+// tables in fragment order, two offset groups in flight.
+#pragma once
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+struct bf16_tag {};
+
+template <typename CT>
+struct Mf;
+template <>
+struct Mf<double> {
+  using H = double;  // staged / tabulated element
+  using AF = double;  // operand fragment of one lane
+  using Acc = d4;
+  static constexpr int KC = 4, OPM = 1, VPL = 1, IDX = 0;
+  __device__ static Acc op(AF a, AF b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  // accumulator element v of a lane with k-group kq holds row:
+  __device__ static int row(int v, int kq) { return 4 * v + kq; }
+  __device__ __forceinline__ static AF frag(const double (&v)[1]) { return v[0]; }
+};
+template <>
+struct Mf<float> {
+  using H = float;
+  using AF = float;
+  using Acc = f4;
+  static constexpr int KC = 4, OPM = 1, VPL = 1, IDX = 1;
+  __device__ static Acc op(AF a, AF b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int v, int kq) { return 4 * kq + v; }
+  __device__ __forceinline__ static AF frag(const double (&v)[1]) { return (float)v[0]; }
+};
+template <>
+struct Mf<bf16_tag> {
+  using H = __bf16;
+  using AF = bf8;
+  using Acc = f4;
+  static constexpr int KC = 16, OPM = 2, VPL = 8, IDX = 2;
+  __device__ static Acc op(AF a, AF b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+  __device__ static int row(int v, int kq) { return 4 * kq + v; }
+  __device__ __forceinline__ static AF frag(const double (&v)[8]) {
+    AF f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) f[e] = static_cast<__bf16>(v[e]);
+    return f;
+  }
+};
+
+// Lane roles.  kq = lane / 16.  For OPM = 2 the lanes with kq < 2 take the
+// first offset of a pair and kq >= 2 the second; each lane holds VPL terms
+// starting at term-in-chunk tic.  tl is the lane's slot in a table entry of
+// EL = 64 / OPM lanes.
+template <typename CT>
+struct LaneRole {
+  int sel, tic, tl;
+  __device__ LaneRole(int lane) {
+    const int kq = lane >> 4;
+    if (Mf<CT>::OPM == 2) {
+      sel = kq >> 1;
+      tic = 8 * (kq & 1);
+      tl = (lane & 15) | ((kq & 1) << 4);
+    } else {
+      sel = 0;
+      tic = kq;
+      tl = lane;
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Bottom of the downward pass for the unigrid children of level-F cells:
+// columns (q, o), o in {phi, gx, gy, gz}; 32 columns = 2 tiles.  After the
+// 189 M2P offsets, three more K blocks: L2P of the M2L part of the row's own
+// local, L2P from the parent level's full local (L2L then L2P as one exact
+// polynomial evaluation), and the near field (the 216 unigrid densities of
+// the 6^3 block around the row's cell).  phi and g are written once.
+// ---------------------------------------------------------------------------
+constexpr int BX = 8, BY = 8, BZ = 16;
+constexpr int HX = BX + 6, HY = BY + 6, HZ = BZ + 6, HZ2 = HZ / 2;
+constexpr int BOT_MT = (BX / 2) * (BY / 2) * (BZ / 2) / 16;  // row tiles per wave (8)
+constexpr int BOT_THREADS = 512;
+
+__device__ __forceinline__ int halo_index(int hx, int hy, int hz) {
+  return (((hx * HY + hy) * 2 + (hz & 1)) * HZ2 + (hz >> 1));
+}
+
+template <int P, typename CT, typename TI, typename TO>
+__global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom(
+    const double* __restrict__ Mh, const double* __restrict__ Lf, const double* __restrict__ Lpar,
+    const TI* __restrict__ rho, const typename Mf<CT>::H* __restrict__ Wm2p,
+    const typename Mf<CT>::H* __restrict__ Wl2p, const typename Mf<CT>::H* __restrict__ Wl2p2,
+    const typename Mf<CT>::H* __restrict__ Wp2p, const int* __restrict__ dlists, TO* __restrict__ phi,
+    TO* __restrict__ g, int nF, double sphi, double sg) {
+  using M = Mf<CT>;
+  using H = typename M::H;
+  using AF = typename M::AF;
+  using Acc = typename M::Acc;
+  constexpr int KC = M::KC, OPM = M::OPM, VPL = M::VPL, EL = 64 / OPM;
+  constexpr int NM = nterms(P), NC4 = (NM + 3) / 4, NCK = (NM + KC - 1) / KC;
+  constexpr int NL = nterms(P);
+  constexpr int KT = 4 * VPL, NLT = (NL + KT - 1) / KT, NPT = (216 + KT - 1) / KT;
+  constexpr int NGRP = (NLIST + OPM - 1) / OPM;
+  __shared__ H halo[HX * HY * HZ * KC];
+  const int lane = threadIdx.x & 63;
+  const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave = parity class (uniform)
+  const int i = lane & 15, kq = lane >> 4;
+  const LaneRole<CT> lr(lane);
+  const int r0 = (r >> 2) & 1, r1 = (r >> 1) & 1, r2 = r & 1;
+  const int nFp = nF + 6;
+  const long long ncellp = (long long)nFp * nFp * nFp;
+  const int tx0 = blockIdx.x * BX, ty0 = blockIdx.y * BY, tz0 = blockIdx.z * BZ;
+  // row i of tile m: lattice (gx, gy, gz) = (m >> 1, 2 (m & 1) + (i >> 3), i & 7)
+  const int gz = i & 7, gyo = i >> 3;
+
+  Acc acc[BOT_MT][2];
+#pragma unroll
+  for (int m = 0; m < BOT_MT; ++m) acc[m][0] = acc[m][1] = Acc{0, 0, 0, 0};
+  const int* dl = dlists + r * NLIST_PAD;
+  // blocks walk the (order-independent) offset sum from different starting points
+  const int rot = (int)(((blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)) * 37u) % NLIST);
+  auto entry = [&](int pos) {
+    if (pos >= NLIST) return dl[NLIST];
+    pos += rot;
+    return dl[pos < NLIST ? pos : pos - NLIST];
+  };
+
+  for (int c = 0; c < NCK; ++c) {
+    __syncthreads();  // previous chunk fully consumed
+    for (int h = threadIdx.x; h < HX * HY * HZ; h += BOT_THREADS) {
+      const int hz = h % HZ, hy = (h / HZ) % HY, hx = h / (HZ * HY);
+      const int px = tx0 + hx, py = ty0 + hy, pz = tz0 + hz;  // padded coordinates
+      const bool in = px < nFp && py < nFp && pz < nFp;
+      H* dst = halo + halo_index(hx, hy, hz) * KC;
+#pragma unroll
+      for (int s4 = 0; s4 < KC / 4; ++s4) {
+        const int sc = c * (KC / 4) + s4;
+        d4 v = d4{0, 0, 0, 0};
+        if (in && sc < NC4) v = *reinterpret_cast<const d4*>(Mh + (sc * ncellp + ((long long)px * nFp + py) * nFp + pz) * 4);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dst[4 * s4 + e] = static_cast<H>(v[e]);
+      }
+    }
+    __syncthreads();
+    const H* wc = Wm2p + (size_t)c * NSLOT * 2 * EL * VPL + lr.tl * VPL;
+    auto bload = [&](int e, int t) {
+      return *reinterpret_cast<const AF*>(wc + ((size_t)dl_dd(e) * 2 + t) * EL * VPL);
+    };
+    int en = entry(lr.sel);
+    AF b0 = bload(en, 0), b1 = bload(en, 1);
+    en = entry(OPM + lr.sel);
+    AF n0 = bload(en, 0), n1 = bload(en, 1);
+    for (int j = 0; j < NGRP; ++j) {
+      const int e = entry(OPM * j + lr.sel);
+      const int d0 = dl_d0(e), d1 = dl_d1(e), d2 = dl_d2(e);
+      const AF cb0 = b0, cb1 = b1;
+      b0 = n0;
+      b1 = n1;
+      if (j + 2 < NGRP) {
+        const int e2 = entry(OPM * (j + 2) + lr.sel);
+        n0 = bload(e2, 0);
+        n1 = bload(e2, 1);
+      }
+      // source halo coordinates of row (gx, gy, gz): 3 + 2 g + r - d
+      const int zz = 3 + r2 - d2;  // in [1, 6]
+      const int zoff = (zz & 1) * HZ2 + gz + (zz >> 1);
+#pragma unroll
+      for (int m = 0; m < BOT_MT; ++m) {
+        const int hx = 3 + 2 * (m >> 1) + r0 - d0;
+        const int hy = 3 + 2 * (2 * (m & 1) + gyo) + r1 - d1;
+        const AF a = *reinterpret_cast<const AF*>(halo + ((hx * HY + hy) * 2 * HZ2 + zoff) * KC + lr.tic);
+        acc[m][0] = M::op(a, cb0, acc[m][0]);
+        acc[m][1] = M::op(a, cb1, acc[m][1]);
+      }
+    }
+  }
+
+  const int n = 2 * nF;
+  const long long N = (long long)n * n * n;
+  constexpr int RS = loc_stride(P);
+  // the lane's own row (A operand) of tile m and its level-F cell, clamped into the grid
+  auto cell_of = [&](int m, int& c0, int& c1, int& c2) {
+    c0 = tx0 + 2 * (m >> 1) + r0;
+    c1 = ty0 + 2 * (2 * (m & 1) + gyo) + r1;
+    c2 = tz0 + 2 * gz + r2;
+    c0 = c0 < nF ? c0 : 0;
+    c1 = c1 < nF ? c1 : 0;
+    c2 = c2 < nF ? c2 : 0;
+  };
+  // tail K blocks of row tile m: L2P of the M2L part of the own local (stored
+  // with the parent P'), L2P from the parent level's full local, near field
+  auto tail = [&](int m, Acc (&am)[2]) {
+    int c0, c1, c2;
+    cell_of(m, c0, c1, c2);
+    if (Lf) {
+      const int nP = nF >> 1, nPP = nP >> 1;
+      const double* own = Lf + (((long long)(c0 >> 1) * nP + (c1 >> 1)) * nP + (c2 >> 1)) * RS;
+      const double* par = Lpar ? Lpar + (((long long)(c0 >> 2) * nPP + (c1 >> 2)) * nPP + (c2 >> 2)) * RS : nullptr;
+      const int qP = (((c0 >> 1) & 1) << 2) | (((c1 >> 1) & 1) << 1) | ((c2 >> 1) & 1);
+      const H* w2 = Wl2p2 + (size_t)r * NLT * 2 * 64 * VPL + lane * VPL;
+#pragma unroll 1
+      for (int c = 0; c < NLT; ++c) {
+        double va[VPL], vp[VPL];
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) {
+          const int bt = KT * c + VPL * kq + v;
+          const int ex = c_mi_exp[bt < NL ? bt : 0];
+          const int deg = mi_a(ex) + mi_b(ex) + mi_c(ex);
+          va[v] = bt < NL ? own[m2l_col(r, bt, deg)] : 0.0;
+          vp[v] = (bt < NL && par) ? par[m2l_col(qP, bt, deg)] : 0.0;
+        }
+        const AF bo0 = *reinterpret_cast<const AF*>(Wl2p + ((size_t)c * 2 * 64 + lane) * VPL);
+        const AF bo1 = *reinterpret_cast<const AF*>(Wl2p + ((size_t)(c * 2 + 1) * 64 + lane) * VPL);
+        am[0] = M::op(M::frag(va), bo0, am[0]);
+        am[1] = M::op(M::frag(va), bo1, am[1]);
+        if (par) {
+          const AF bp0 = *reinterpret_cast<const AF*>(w2 + (size_t)c * 2 * 64 * VPL);
+          const AF bp1 = *reinterpret_cast<const AF*>(w2 + (size_t)(c * 2 + 1) * 64 * VPL);
+          am[0] = M::op(M::frag(vp), bp0, am[0]);
+          am[1] = M::op(M::frag(vp), bp1, am[1]);
+        }
+      }
+    }
+#pragma unroll 1
+    for (int c = 0; c < NPT; ++c) {
+      double va[VPL];
+#pragma unroll
+      for (int v = 0; v < VPL; ++v) {
+        const int k = KT * c + VPL * kq + v;
+        const int w0 = 2 * c0 + k / 36 - 2, w1 = 2 * c1 + (k / 6) % 6 - 2, w2 = 2 * c2 + k % 6 - 2;
+        va[v] = (k < 216 && w0 >= 0 && w1 >= 0 && w2 >= 0 && w0 < n && w1 < n && w2 < n)
+                    ? (double)rho[((long long)w0 * n + w1) * n + w2]
+                    : 0.0;
+      }
+      const AF bn0 = *reinterpret_cast<const AF*>(Wp2p + ((size_t)c * 2 * 64 + lane) * VPL);
+      const AF bn1 = *reinterpret_cast<const AF*>(Wp2p + ((size_t)(c * 2 + 1) * 64 + lane) * VPL);
+      am[0] = M::op(M::frag(va), bn0, am[0]);
+      am[1] = M::op(M::frag(va), bn1, am[1]);
+    }
+  };
+#pragma unroll
+  for (int m = 0; m < BOT_MT; ++m) tail(m, acc[m]);
+  // epilogue: element v of tile t is row M::row(v, kq), column 16 t + i
+#pragma unroll
+  for (int m = 0; m < BOT_MT; ++m) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = M::row(v, kq);
+      const int o0 = tx0 + 2 * (m >> 1) + r0, o1 = ty0 + 2 * (2 * (m & 1) + (row >> 3)) + r1,
+                o2 = tz0 + 2 * (row & 7) + r2;
+      if (o0 >= nF || o1 >= nF || o2 >= nF) continue;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int col = 16 * t + i;
+        const int q = col >> 2, o = col & 3;
+        const long long u = ((long long)(2 * o0 + ((q >> 2) & 1)) * n + (2 * o1 + ((q >> 1) & 1))) * n +
+                            (2 * o2 + (q & 1));
+        const double val = (double)acc[m][t][v];
+        if (o == 0)
+          phi[u] = (TO)(sphi * val);
+        else if (g)
+          g[(o - 1) * N + u] = (TO)(sg * val);
+      }
+    }
+  }
+}
+
+// Plan-time expansion of the bottom kernel's B operands into fragment order,
+// converted to the compute type (round to nearest even from FP64).
+//   M2P:   [NCK][NSLOT][2 tiles][EL][VPL]  D[a + e_o](Rhat_{d,q}), term a of the
+//          chunk for the entry lane (0 past NM and for the null slot)
+//   L2P:   [NLT][2][64][VPL]               l2p_coef
+//   L2P2:  [8][NLT][2][64][VPL]            parent-level L2P, per parity class
+//   near:  [NPT][2][64][VPL]               p2p_coef
+// A column 16 t + j is (q, o) = (col / 4, col % 4).
+template <typename CT>
+__global__ void k_expand_bottom(const double* __restrict__ Dtab, typename Mf<CT>::H* __restrict__ Wm2p,
+                                typename Mf<CT>::H* __restrict__ Wl2p, typename Mf<CT>::H* __restrict__ Wl2p2,
+                                typename Mf<CT>::H* __restrict__ Wp2p, int NM, int NL, int ND) {
+  using M = Mf<CT>;
+  using H = typename M::H;
+  constexpr int KC = M::KC, OPM = M::OPM, VPL = M::VPL, EL = 64 / OPM, KT = 4 * VPL;
+  const int NCK = (NM + KC - 1) / KC, NLT = (NL + KT - 1) / KT, NPT = (216 + KT - 1) / KT;
+  const long long n_m2p = (long long)NCK * NSLOT * 2 * EL * VPL;
+  const long long n_l2p = (long long)NLT * 2 * 64 * VPL, n_l2p2 = 8 * n_l2p, n_p2p = (long long)NPT * 2 * 64 * VPL;
+  long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= n_m2p + n_l2p + n_l2p2 + n_p2p) return;
+  if (e < n_m2p) {
+    const int v = (int)(e % VPL), el = (int)((e / VPL) % EL), t = (int)((e / ((long long)VPL * EL)) % 2);
+    const int slot = (int)((e / ((long long)VPL * EL * 2)) % NSLOT), c = (int)(e / ((long long)VPL * EL * 2 * NSLOT));
+    const int j = el & 15, col = 16 * t + j, q = col >> 2, o = col & 3;
+    const int tic = OPM == 2 ? 8 * (el >> 4) : (el >> 4);
+    const int al = c * KC + tic + v;
+    double val = 0.0;
+    if (al < NM && slot < 343) {
+      const int ex = c_mi_exp[al];
+      val = Dtab[((size_t)slot * 8 + q) * ND + mi_index(mi_a(ex) + (o == 1), mi_b(ex) + (o == 2), mi_c(ex) + (o == 3))];
+    }
+    Wm2p[e] = static_cast<H>(val);
+    return;
+  }
+  e -= n_m2p;
+  // tail tables share the layout [chunk][t][64 lanes][VPL], lane = j + 16 kq, k = KT chunk + VPL kq + v
+  H* out;
+  int rp = 0, kind;
+  if (e < n_l2p) {
+    out = Wl2p;
+    kind = 0;
+  } else if (e < n_l2p + n_l2p2) {
+    e -= n_l2p;
+    out = Wl2p2;
+    kind = 1;
+    rp = (int)(e / n_l2p);
+  } else {
+    e -= n_l2p + n_l2p2;
+    out = Wp2p;
+    kind = 2;
+  }
+  const long long el = kind == 1 ? e % n_l2p : e;
+  const int v = (int)(el % VPL), lane = (int)((el / VPL) % 64), t = (int)((el / (VPL * 64)) % 2);
+  const int c = (int)(el / (VPL * 64 * 2));
+  const int j = lane & 15, kq = lane >> 4, col = 16 * t + j, q = col >> 2, o = col & 3;
+  const int k = KT * c + VPL * kq + v;
+  double val = 0.0;
+  if (kind == 0) {
+    if (k < NL) val = l2p_coef(k, q, o);
+  } else if (kind == 1) {
+    if (k < NL) val = l2p_parent_coef(k, rp, q, o);
+  } else {
+    if (k < 216) val = p2p_coef(k / 36 - 2, (k / 6) % 6 - 2, k % 6 - 2, q, o);
+  }
+  out[e] = static_cast<H>(val);
+}
+
+// ---------------------------------------------------------------------------
+// M2L, eq. (M2L), over the oct-shared interaction lists (Sec. 2.2), every
+// level in one launch per column group.  Rows are cells P of a source grid
+// s = k - 1; columns are (child q, local term b) sorted by |b|; the result is
+// the M2L part of the locals of the 8 children,
+//   Lam_k[2P + q][b] = 2^-(|b|+1) sum_d sum_a D[a+b](Rhat_{d,q}) Mhat_s[P-d][a],
+// stored per source cell in column order.
+// ---------------------------------------------------------------------------
+constexpr int LX = 8;
+constexpr int LH = LX + 6, LH2 = LH / 2;
+constexpr int M2L_MT = (LX / 2) * (LX / 2) * (LX / 2) / 16;  // 4 row tiles per wave
+constexpr int M2L_THREADS = 512;
+constexpr int MAXLEV = 12;
+
+struct M2LLevels {
+  int nlev;
+  int first_block[MAXLEV + 1];
+  int tiles_per_axis[MAXLEV];
+  int ns[MAXLEV];
+  const double* M[MAXLEV];
+  double* Lam[MAXLEV];
+};
+
+__device__ __forceinline__ int lhalo_index(int hx, int hy, int hz) {
+  return ((hx * LH + hy) * 2 + (hz & 1)) * LH2 + (hz >> 1);
+}
+
+// column-group budgets per compute type (accumulator registers, work)
+template <typename CT>
+struct M2LBudget {
+  static constexpr int MAXT = Mf<CT>::VPL == 8 ? 4 : (sizeof(typename Mf<CT>::Acc) == 32 ? 5 : 10);
+  static constexpr int MAXB = 24;
+};
+
+// chunk count and first fragment of each tile of an M2L launch, as
+// compile-time tables (the helper functions loop and must not run on device)
+template <int P, int KC, int T0, int NT>
+struct TileChunks {
+  int v[NT];
+  int off[NT];
+  constexpr TileChunks() : v(), off() {
+    for (int t = 0; t < NT; ++t) {
+      v[t] = m2l_tile_chunks(P, T0 + t, KC);
+      off[t] = m2l_frag_offset(P, T0 + t, KC);
+    }
+  }
+};
+
+template <int P, typename CT, int T0, int NT>
+__global__ __launch_bounds__(M2L_THREADS, 1) void k_m2l(M2LLevels lv, const typename Mf<CT>::H* __restrict__ Wm2l,
+                                                       const int* __restrict__ dlists) {
+  using M = Mf<CT>;
+  using H = typename M::H;
+  using AF = typename M::AF;
+  using Acc = typename M::Acc;
+  constexpr int KC = M::KC, OPM = M::OPM, VPL = M::VPL, EL = 64 / OPM;
+  constexpr int NM = nterms(P), NC4 = (NM + 3) / 4;
+  constexpr int NL = nterms(P), NCOL = 8 * NL;
+  constexpr int NGRP = (NLIST + OPM - 1) / OPM;
+  constexpr TileChunks<P, KC, T0, NT> kch{};
+  constexpr int CM = kch.v[0];
+  __shared__ H halo[LH * LH * LH * KC];
+  int li = 0;
+  while (li + 1 < lv.nlev && (int)blockIdx.x >= lv.first_block[li + 1]) ++li;
+  const int tb = (int)blockIdx.x - lv.first_block[li];
+  const int tpa = lv.tiles_per_axis[li];
+  const int ns = lv.ns[li], nsp = ns + 6;
+  const double* __restrict__ Mh = lv.M[li];
+  double* __restrict__ Lam = lv.Lam[li];
+  const int tx0 = (tb / (tpa * tpa)) * LX, ty0 = ((tb / tpa) % tpa) * LX, tz0 = (tb % tpa) * LX;
+  const long long ncellp = (long long)nsp * nsp * nsp;
+  const int lane = threadIdx.x & 63;
+  const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave = parity class (uniform)
+  const int i = lane & 15, kq = lane >> 4;
+  const LaneRole<CT> lr(lane);
+  const int r0 = (r >> 2) & 1, r1 = (r >> 1) & 1, r2 = r & 1;
+  const int gy = i >> 2, gz = i & 3;  // row i of tile m: lattice (m, gy, gz)
+
+  Acc acc[M2L_MT][NT];
+#pragma unroll
+  for (int m = 0; m < M2L_MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = Acc{0, 0, 0, 0};
+  const int* dl = dlists + r * NLIST_PAD;
+  const int rot = (int)((blockIdx.x * 37u) % NLIST);
+  auto entry = [&](int pos) {
+    if (pos >= NLIST) return dl[NLIST];
+    pos += rot;
+    return dl[pos < NLIST ? pos : pos - NLIST];
+  };
+  const H* wl = Wm2l + lr.tl * VPL;
+  auto bload = [&](int e, int t, int c) {
+    return *reinterpret_cast<const AF*>(wl + ((size_t)(kch.off[t] + c) * NSLOT + dl_dd(e)) * EL * VPL);
+  };
+
+  for (int c = 0; c < CM; ++c) {
+    __syncthreads();
+    for (int h = threadIdx.x; h < LH * LH * LH; h += M2L_THREADS) {
+      const int hz = h % LH, hy = (h / LH) % LH, hx = h / (LH * LH);
+      const int px = tx0 + hx, py = ty0 + hy, pz = tz0 + hz;
+      const bool in = px < nsp && py < nsp && pz < nsp;
+      H* dst = halo + lhalo_index(hx, hy, hz) * KC;
+#pragma unroll
+      for (int s4 = 0; s4 < KC / 4; ++s4) {
+        const int sc = c * (KC / 4) + s4;
+        d4 v = d4{0, 0, 0, 0};
+        if (in && sc < NC4) v = *reinterpret_cast<const d4*>(Mh + (sc * ncellp + ((long long)px * nsp + py) * nsp + pz) * 4);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dst[4 * s4 + e] = static_cast<H>(v[e]);
+      }
+    }
+    __syncthreads();
+    AF b0[NT], b1[NT];
+    {
+      const int e0 = entry(lr.sel), e1 = entry(OPM + lr.sel);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        if (c < kch.v[t]) {
+          b0[t] = bload(e0, t, c);
+          b1[t] = bload(e1, t, c);
+        }
+      }
+    }
+    for (int j = 0; j < NGRP; ++j) {
+      const int e = entry(OPM * j + lr.sel);
+      const int d0 = dl_d0(e), d1 = dl_d1(e), d2 = dl_d2(e);
+      AF cb[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        cb[t] = b0[t];
+        b0[t] = b1[t];
+      }
+      if (j + 2 < NGRP) {
+        const int en = entry(OPM * (j + 2) + lr.sel);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          if (c < kch.v[t]) b1[t] = bload(en, t, c);
+      }
+      const int zz = 3 + r2 - d2;
+      const int zoff = (zz & 1) * LH2 + gz + (zz >> 1);
+      const int hy = 3 + 2 * gy + r1 - d1;
+#pragma unroll
+      for (int m = 0; m < M2L_MT; ++m) {
+        const int hx = 3 + 2 * m + r0 - d0;
+        const AF a = *reinterpret_cast<const AF*>(halo + ((hx * LH + hy) * 2 * LH2 + zoff) * KC + lr.tic);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          if (c < kch.v[t]) acc[m][t] = M::op(a, cb[t], acc[m][t]);
+      }
+    }
+  }
+  // epilogue: element v of tile t is row M::row(v, kq), column 16 (T0 + t) + i;
+  // the 16 lanes of a row write 128 contiguous bytes
+  constexpr int RS = loc_stride(P);
+  int escale[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = 16 * (T0 + t) + i;
+    escale[t] = -(m2l_col_degree(col < NCOL ? col : 0) + 1);
+  }
+#pragma unroll
+  for (int m = 0; m < M2L_MT; ++m)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = M::row(v, kq);
+      const int p0 = tx0 + 2 * m + r0, p1 = ty0 + 2 * (row >> 2) + r1, p2 = tz0 + 2 * (row & 3) + r2;
+      if (p0 >= ns || p1 >= ns || p2 >= ns) continue;
+      double* dst = Lam + (((long long)p0 * ns + p1) * ns + p2) * RS + 16 * T0 + i;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) dst[16 * t] = ldexp((double)acc[m][t][v], escale[t]);
+    }
+}
+
+// B fragments of the M2L in fragment order, converted to the compute type:
+// [fragment f][NSLOT][EL][VPL], fragment f = (tile t, chunk c); entry lane el
+// holds, for column 16 t + (el & 15) = (q, b), the terms a = KC c + tic + v of
+// D[a + b](Rhat_{d,q}) (0 where |a| + |b| > p, past the terms, or the null slot).
+template <typename CT>
+__global__ void k_expand_m2l(const double* __restrict__ Dtab, typename Mf<CT>::H* __restrict__ W, int P, int ND) {
+  using M = Mf<CT>;
+  constexpr int KC = M::KC, OPM = M::OPM, VPL = M::VPL, EL = 64 / OPM;
+  const int NF = m2l_nfrags(P, KC);
+  const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (id >= (long long)NF * NSLOT * EL * VPL) return;
+  const int v = (int)(id % VPL), el = (int)((id / VPL) % EL);
+  const int slot = (int)((id / ((long long)VPL * EL)) % NSLOT), f = (int)(id / ((long long)VPL * EL * NSLOT));
+  int t = 0;
+  while (m2l_frag_offset(P, t + 1, KC) <= f) ++t;
+  const int c = f - m2l_frag_offset(P, t, KC);
+  const int j = el & 15;
+  const int tic = OPM == 2 ? 8 * (el >> 4) : (el >> 4);
+  const int col = 16 * t + j, al = KC * c + tic + v;
+  double val = 0.0;
+  if (slot < 343 && col < 8 * nterms(P) && al < nterms(P)) {
+    const int md = m2l_col_degree(col);
+    const int cin = col - 8 * nterms(md - 1);
+    const int q = cin / ndeg(md);
+    const int bex = c_mi_exp[nterms(md - 1) + cin % ndeg(md)];
+    const int aex = c_mi_exp[al];
+    if (mi_a(aex) + mi_b(aex) + mi_c(aex) + md <= P)
+      val = Dtab[((size_t)slot * 8 + q) * ND +
+                 mi_index(mi_a(aex) + mi_a(bex), mi_b(aex) + mi_b(bex), mi_c(aex) + mi_c(bex))];
+  }
+  W[id] = static_cast<typename M::H>(val);
+}
