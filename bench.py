@@ -31,6 +31,32 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
 HBM_PEAK_GBS = 8000.0
 
 
+PROFILE = os.path.join(ROOT, "profiles", "k_bottom_256cubed_p6_fp64.md")
+KERNEL_SOURCES = ["fmm_kernels.hip", "fmm_mfma.h", "fmm_internal.h"]
+
+
+def profiled_traffic(n: int, p: int, prec: str):
+    """HBM bytes per launch of the bottom kernel from the committed rocprofv3
+    byte-counter summary, or None when it does not describe the current
+    kernel sources or this workload."""
+    import hashlib
+    if (n, p, prec) != (256, 6, "fp64") or not os.path.exists(PROFILE):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2606_13793_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    fields = {}
+    with open(PROFILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(("|", "#", " ")):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -48,6 +74,9 @@ def parse():
     ap.add_argument("--cpu-planes", type=int, default=16,
                     help="unigrid planes of the oracle's downward-pass sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="first run one plain device-to-device copy of BYTES bytes (a known-size "
+                         "reference dispatch for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -81,6 +110,15 @@ def main():
     phi = torch.empty((n, n, n), dtype=plan.io_dtype, device=dev)
     g = torch.empty((3, n, n, n), dtype=plan.io_dtype, device=dev)
     log(f"plan ready: {plan.workspace_bytes() / 2**30:.2f} GiB workspace")
+    if args.copy_calibration:
+        cnt = args.copy_calibration // 8
+        src = torch.ones(cnt, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.neg(src, out=dst)  # one elementwise kernel: reads and writes cnt doubles
+        torch.cuda.synchronize()
+        log(f"calibration copy: {cnt * 8} bytes read, {cnt * 8} bytes written")
+        del src, dst
 
     for _ in range(args.warmup):
         plan.solve_into(rho, phi, g)
@@ -118,7 +156,8 @@ def main():
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": round(bot_tflops / peak, 4),
-        "traffic": None,
+        "traffic": profiled_traffic(n, p, prec),
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "avg_launch_ms": round(bot_avg_s * 1e3, 4),
         "flops_per_launch": stage_flops["bottom"],
         "m2p_pairs_per_launch": costs.m2p_pairs(n),
