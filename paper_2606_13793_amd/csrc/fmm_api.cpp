@@ -70,7 +70,7 @@ size_t plan_bytes(int n, int p) {
   size_t b = (size_t)343 * 8 * ND * sizeof(double) + 8 * fmm::NLIST_PAD * sizeof(int) + 256;
   // FP64 matrix-core tables (the largest set a plan builds)
   b += ((size_t)21 * fmm::NSLOT * 128 + (size_t)NCL * 128 * 9 + 54 * 128) * sizeof(double);
-  b += (size_t)fmm::NSLOT * fmm::m2l_nfrags(p) * 64 * sizeof(double);
+  b += (size_t)fmm::NSLOT * fmm::conv_nfrags(fmm::CV_M2L, p, 4) * 64 * sizeof(double);
   for (int k = 2; k <= F; ++k) {
     const size_t nkp = (size_t)(1 << k) + 6;
     b += (size_t)NC * nkp * nkp * nkp * 4 * sizeof(double);
@@ -100,6 +100,15 @@ void release(fmm_plan* pl) {
     if (pl->wp2p[x]) (void)hipFree(pl->wp2p[x]);
     if (pl->wm2l[x]) (void)hipFree(pl->wm2l[x]);
   }
+  for (int x = 0; x < 3; ++x) {
+    if (pl->wt_m2l[x]) (void)hipFree(pl->wt_m2l[x]);
+    if (pl->wt_m2p[x]) (void)hipFree(pl->wt_m2p[x]);
+  }
+  if (pl->ybar) (void)hipFree(pl->ybar);
+  for (auto a : pl->abar)
+    if (a) (void)hipFree(a);
+  if (pl->adj_l2p) (void)hipFree(pl->adj_l2p);
+  if (pl->adj_l2p2) (void)hipFree(pl->adj_l2p2);
   if (pl->l2l_start) (void)hipFree(pl->l2l_start);
   if (pl->l2l_idx) (void)hipFree(pl->l2l_idx);
   if (pl->l2l_coef) (void)hipFree(pl->l2l_coef);
@@ -368,10 +377,40 @@ int fmm_solve(fmm_plan* plan, const void* rho, void* phi, void* g, void* stream)
   return ok();
 }
 
+// Adjoint workspace: the scaled adjoint outputs of the level-F cells and one
+// adjoint-local grid per level 3..F (zeroed once: their margins and padding
+// columns are never written).  The adjoint multipoles reuse the plan's
+// multipole grids.  Allocated by the first backward call of a plan.
+static int ensure_adjoint(fmm_plan* pl, hipStream_t s) {
+  if (pl->adj_ready) return FMM_OK;
+  const int nF = pl->n / 2, RS = fmm::loc_stride(pl->p);
+  const size_t yb = (size_t)8 * (nF + 6) * (nF + 6) * (nF + 6) * 4 * sizeof(double);
+  if (dev_alloc(pl, (void**)&pl->ybar, yb)) return FMM_ERR_OUT_OF_MEMORY;
+  if (hipMemset(pl->ybar, 0, yb) != hipSuccess) return fail(FMM_ERR_DEVICE, "hipMemset failed");
+  for (int k = 3; k <= pl->F; ++k) {
+    const size_t np = ((size_t)1 << (k - 1)) + 6;
+    const size_t ab = (size_t)RS * np * np * np * sizeof(double);
+    if (dev_alloc(pl, (void**)&pl->abar[k], ab)) return FMM_ERR_OUT_OF_MEMORY;
+    if (hipMemset(pl->abar[k], 0, ab) != hipSuccess) return fail(FMM_ERR_DEVICE, "hipMemset failed");
+  }
+  if (dev_alloc(pl, (void**)&pl->adj_l2p, (size_t)pl->NL * 32 * sizeof(double))) return FMM_ERR_OUT_OF_MEMORY;
+  if (dev_alloc(pl, (void**)&pl->adj_l2p2, (size_t)8 * pl->NL * 32 * sizeof(double))) return FMM_ERR_OUT_OF_MEMORY;
+  hipError_t e = fmm::launch_adjoint_tables(pl, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? FMM_ERR_OUT_OF_MEMORY : FMM_ERR_DEVICE, "adjoint tables: %s",
+                hipGetErrorString(e));
+  }
+  pl->adj_ready = 1;
+  return FMM_OK;
+}
+
 int fmm_solve_backward(fmm_plan* plan, const void* dphi, const void* dg, void* drho, void* stream) {
   if (!plan) return fail(FMM_ERR_INVALID_ARG, "plan is NULL");
   if (!dphi || !drho) return fail(FMM_ERR_INVALID_ARG, "dphi and drho must be device pointers (got NULL)");
   if (drho == dphi || (dg && (dg == drho || dg == dphi))) return fail(FMM_ERR_INVALID_ARG, "buffers must not alias");
+  if (int rc = ensure_adjoint(plan, (hipStream_t)stream)) return rc;
   fmm::StageScope whole(plan, fmm::ST_BACKWARD, 0, (hipStream_t)stream);
   hipError_t e = fmm::launch_backward(plan, dphi, dg, drho, (hipStream_t)stream);
   if (e == hipErrorNotSupported) return fail(FMM_ERR_UNSUPPORTED, "backward pass is not built for this plan");

@@ -57,34 +57,63 @@ constexpr __host__ __device__ int m2l_col(int q, int bt, int m) {
 constexpr __host__ __device__ int m2l_tile_chunks(int P, int t, int KC = 4) {
   return (nterms(P - m2l_col_degree(16 * t)) + KC - 1) / KC;
 }
-// fragments (tile, chunk) in canonical order: tile-major, chunk inside
-constexpr __host__ __device__ int m2l_frag_offset(int P, int t, int KC = 4) {
+// ---------------------------------------------------------------------------
+// The parity-class convolutions of the matrix-core kernel (k_conv):
+//   CV_M2L   forward M2L: rows = source cells P, K = multipole terms a,
+//            N = local columns (q, b)          (tiles and chunks as above)
+//   CV_M2LT  transposed M2L: rows = source cells J, K = adjoint local columns
+//            (q, b) of the targets' parents, N = multipole terms a
+//   CV_M2PT  transposed M2P: rows = level-F cells J, K = the 32 adjoint
+//            outputs (q, o) of a target cell, N = multipole terms a
+// The interaction relation is symmetric (J is in the list of P iff P is in
+// the list of J), so all three walk the same per-parity offset lists.
+// ---------------------------------------------------------------------------
+enum ConvOp { CV_M2L = 0, CV_M2LT = 1, CV_M2PT = 2 };
+// degree of multipole term index a
+constexpr __host__ __device__ int mi_degree(int a) {
+  int m = 0;
+  while (a >= nterms(m)) ++m;
+  return m;
+}
+constexpr __host__ __device__ int conv_nk(int op, int P) {
+  return op == CV_M2L ? nterms(P) : (op == CV_M2LT ? loc_stride(P) : 32);
+}
+constexpr __host__ __device__ int conv_ntiles(int op, int P) {
+  return op == CV_M2L ? m2l_ntiles(P) : (nterms(P) + 15) / 16;
+}
+constexpr __host__ __device__ int conv_tile_chunks(int op, int P, int t, int KC) {
+  return op == CV_M2L ? m2l_tile_chunks(P, t, KC)
+                      : (op == CV_M2LT ? (8 * nterms(P - mi_degree(16 * t)) + KC - 1) / KC : (32 + KC - 1) / KC);
+}
+constexpr __host__ __device__ int conv_frag_offset(int op, int P, int t, int KC) {
   int f = 0;
-  for (int u = 0; u < t; ++u) f += m2l_tile_chunks(P, u, KC);
+  for (int u = 0; u < t; ++u) f += conv_tile_chunks(op, P, u, KC);
   return f;
 }
-constexpr __host__ __device__ int m2l_nfrags(int P, int KC = 4) { return m2l_frag_offset(P, m2l_ntiles(P), KC); }
-// tiles are grouped per launch under a register budget (accumulators of
-// MAXT tiles x 4 row tiles) and a work budget (MAXB fragment chunks)
-constexpr int m2l_group_end(int P, int t0, int KC, int MAXT, int MAXB) {
+constexpr __host__ __device__ int conv_nfrags(int op, int P, int KC) {
+  return conv_frag_offset(op, P, conv_ntiles(op, P), KC);
+}
+// launch groups of tiles: at most MAXT tiles (accumulator registers) and, for
+// the forward M2L, at most MAXB fragment chunks (balanced launches)
+constexpr int conv_group_end(int op, int P, int t0, int KC, int MAXT, int MAXB) {
   int nt = 0, nb = 0, t = t0;
-  while (t < m2l_ntiles(P)) {
-    const int c = m2l_tile_chunks(P, t, KC);
-    if (nt > 0 && (nt + 1 > MAXT || nb + c > MAXB)) break;
+  while (t < conv_ntiles(op, P)) {
+    const int c = conv_tile_chunks(op, P, t, KC);
+    if (nt > 0 && (nt + 1 > MAXT || (op == CV_M2L && nb + c > MAXB))) break;
     ++nt;
     nb += c;
     ++t;
   }
   return t;
 }
-constexpr int m2l_group_start(int P, int g, int KC, int MAXT, int MAXB) {
+constexpr int conv_group_start(int op, int P, int g, int KC, int MAXT, int MAXB) {
   int t = 0;
-  for (int i = 0; i < g; ++i) t = m2l_group_end(P, t, KC, MAXT, MAXB);
+  for (int i = 0; i < g; ++i) t = conv_group_end(op, P, t, KC, MAXT, MAXB);
   return t;
 }
-constexpr int m2l_ngroups(int P, int KC, int MAXT, int MAXB) {
+constexpr int conv_ngroups(int op, int P, int KC, int MAXT, int MAXB) {
   int g = 0, t = 0;
-  while (t < m2l_ntiles(P)) { t = m2l_group_end(P, t, KC, MAXT, MAXB); ++g; }
+  while (t < conv_ntiles(op, P)) { t = conv_group_end(op, P, t, KC, MAXT, MAXB); ++g; }
   return g;
 }
 
@@ -149,6 +178,14 @@ struct fmm_plan {
   void* wl2p2[3] = {nullptr, nullptr, nullptr};  // L2P from the parent level
   void* wp2p[3] = {nullptr, nullptr, nullptr};   // near field
   void* wm2l[3] = {nullptr, nullptr, nullptr};   // M2L
+  // adjoint workspace and tables, built by the first backward call
+  int adj_ready = 0;
+  double* ybar = nullptr;       // [8][(nF+6)^3][4] scaled adjoint outputs per level-F cell
+  double* abar[16] = {};        // adjoint locals of level k: [loc_stride/4][(2^(k-1)+6)^3][4]
+  double* adj_l2p = nullptr;    // [NL][32]     L2P coefficients
+  double* adj_l2p2 = nullptr;   // [8][NL][32]  parent-level L2P coefficients
+  void* wt_m2l[3] = {nullptr, nullptr, nullptr};  // transposed M2L B fragments
+  void* wt_m2p[3] = {nullptr, nullptr, nullptr};  // transposed M2P B fragments
   int* l2l_start = nullptr;     // L2L coefficient lists (CSR over local terms)
   int* l2l_idx = nullptr;       // (index of b+g) << 3 | parity pattern of g
   double* l2l_coef = nullptr;
@@ -166,6 +203,8 @@ hipError_t upload_constants();
 hipError_t launch_dtab(fmm_plan* pl, hipStream_t s);
 hipError_t launch_solve(fmm_plan* pl, const void* rho, void* phi, void* g, hipStream_t s);
 hipError_t launch_backward(fmm_plan* pl, const void* dphi, const void* dg, void* drho, hipStream_t s);
+// builds the adjoint tables of a plan (the buffers are allocated by the caller)
+hipError_t launch_adjoint_tables(fmm_plan* pl, hipStream_t s);
 hipError_t launch_check_finite(fmm_plan* pl, const void* rho, int* host_flag, hipStream_t s);
 // completes the stored locals of `level` (the finest level keeps only its M2L
 // part during a solve); used before inspecting them

@@ -343,6 +343,266 @@ __global__ __launch_bounds__(256) void k_l2l(const double* __restrict__ Lprev, d
 }
 
 // ---------------------------------------------------------------------------
+// Adjoint (transpose) of the solve: rho_bar = A^T (phi_bar, g_bar), taking the
+// passes in reverse order, each the exact transpose of the forward kernel's
+// arithmetic in the scaled representation.  With Ybar_T[(q, o)] the scaled
+// adjoint outputs of level-F cell T (q child, o in {phi, gx, gy, gz}):
+//   Lam_bar_F = L2P^T Ybar,  Lbar_{F-1} = (parent-level L2P)^T Ybar,
+//   Lbar_{k-1} = L2L^T Lbar_k (k = F-1..4),
+//   Mbar_{k-1} = M2L^T Lbar_k (k = 3..F),  Mbar_F = M2P^T Ybar   (k_conv),
+//   Mbar_k += M2M^T Mbar_{k-1} (k = 3..F),
+//   rho_bar = P2M^T Mbar_F + near^T Ybar.
+// Adjoint locals are stored as chunked padded grids over the parent cells,
+// [loc_stride/4][(ns+6)^3][4] with columns in the M2L order, so the
+// transposed M2L stages them like multipoles.
+// ---------------------------------------------------------------------------
+
+// Ybar: [8 children][(nF+6)^3][4]: (sphi phi_bar, sg g_bar_x, sg g_bar_y, sg g_bar_z)
+template <typename TI>
+__global__ void k_adj_seed(const TI* __restrict__ dphi, const TI* __restrict__ dg, double* __restrict__ Y, int n,
+                           double sphi, double sg) {
+  const int nF = n >> 1, nFp = nF + 6;
+  const long long nT = (long long)nF * nF * nF, N = (long long)n * n * n;
+  const long long T = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (T >= nT) return;
+  const int t2 = (int)(T % nF), t1 = (int)((T / nF) % nF), t0 = (int)(T / ((long long)nF * nF));
+  const long long ncellp = (long long)nFp * nFp * nFp;
+  const long long cp = ((long long)(t0 + 3) * nFp + (t1 + 3)) * nFp + (t2 + 3);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const long long u = ((long long)(2 * t0 + ((q >> 2) & 1)) * n + (2 * t1 + ((q >> 1) & 1))) * n + (2 * t2 + (q & 1));
+    d4 v;
+    v[0] = sphi * (double)dphi[u];
+    v[1] = dg ? sg * (double)dg[u] : 0.0;
+    v[2] = dg ? sg * (double)dg[N + u] : 0.0;
+    v[3] = dg ? sg * (double)dg[2 * N + u] : 0.0;
+    *reinterpret_cast<d4*>(Y + (q * ncellp + cp) * 4) = v;
+  }
+}
+
+// plan-time coefficient tables of the transposed L2P steps:
+//   own [NL][32]:      l2p_coef(b, q, o)               at k = 4 q + o
+//   par [8][NL][32]:   l2p_parent_coef(b, rp, q, o)
+__global__ void k_adj_coef(double* __restrict__ own, double* __restrict__ par, int NL) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= 9 * NL * 32) return;
+  const int k = id % 32, b = (id / 32) % NL, z = id / (32 * NL);
+  if (z == 0)
+    own[b * 32 + k] = l2p_coef(b, k >> 2, k & 3);
+  else
+    par[((z - 1) * NL + b) * 32 + k] = l2p_parent_coef(b, z - 1, k >> 2, k & 3);
+}
+
+// L2P^T and (parent-level L2P)^T.  Block = 4 level-(F-1) cells P, whose 8
+// children's Ybar (4 x 256 values) are staged in LDS.  Outputs: the adjoint
+// local of every child T = 2P + rp in P's row (column (rp, b)) and, when the
+// parent level has locals, the adjoint full local of P in its parent's row
+// (column (qP, b)).
+__global__ __launch_bounds__(256) void k_adj_l2p(const double* __restrict__ Y, const double* __restrict__ cown,
+                                                 const double* __restrict__ cpar, double* __restrict__ Aown,
+                                                 double* __restrict__ Apar, int nF, int NL, int RS) {
+  __shared__ double y[4][256];
+  const int nP = nF >> 1, nFp = nF + 6, nPp = nP + 6, nPP = nP >> 1, nPPp = nPP + 6;
+  const long long ncF = (long long)nFp * nFp * nFp, ncP = (long long)nPp * nPp * nPp,
+                  ncPP = (long long)nPPp * nPPp * nPPp;
+  const long long nPc = (long long)nP * nP * nP;
+  const long long P0 = (long long)blockIdx.x * 4;
+  for (int w = threadIdx.x; w < 4 * 256; w += 256) {
+    const int pl = w >> 8, k = w & 255, rp = k >> 5, qo = k & 31;
+    const long long P = P0 + pl;
+    double v = 0.0;
+    if (P < nPc) {
+      const int p2 = (int)(P % nP), p1 = (int)((P / nP) % nP), p0 = (int)(P / ((long long)nP * nP));
+      const long long cT = ((long long)(2 * p0 + ((rp >> 2) & 1) + 3) * nFp + (2 * p1 + ((rp >> 1) & 1) + 3)) * nFp +
+                           (2 * p2 + (rp & 1) + 3);
+      v = Y[((qo >> 2) * ncF + cT) * 4 + (qo & 3)];
+    }
+    y[pl][k] = v;
+  }
+  __syncthreads();
+  const int per = 8 * NL + (Apar ? NL : 0);
+  for (int w = threadIdx.x; w < 4 * per; w += 256) {
+    const int pl = w / per, j = w % per;
+    const long long P = P0 + pl;
+    if (P >= nPc) continue;
+    const int p2 = (int)(P % nP), p1 = (int)((P / nP) % nP), p0 = (int)(P / ((long long)nP * nP));
+    if (j < 8 * NL) {
+      // own: column j = (rp, b) in the M2L order
+      const int md = m2l_col_degree(j);
+      const int cin = j - 8 * nterms(md - 1);
+      const int rp = cin / ndeg(md), bt = nterms(md - 1) + cin % ndeg(md);
+      const double* c = cown + bt * 32;
+      const double* yy = &y[pl][rp * 32];
+      double acc = 0.0;
+#pragma unroll 8
+      for (int k = 0; k < 32; ++k) acc += c[k] * yy[k];
+      const long long cp = ((long long)(p0 + 3) * nPp + (p1 + 3)) * nPp + (p2 + 3);
+      Aown[((j >> 2) * ncP + cp) * 4 + (j & 3)] = acc;
+    } else {
+      const int bt = j - 8 * NL;
+      double acc = 0.0;
+      for (int rp = 0; rp < 8; ++rp) {
+        const double* c = cpar + (rp * NL + bt) * 32;
+        const double* yy = &y[pl][rp * 32];
+#pragma unroll 8
+        for (int k = 0; k < 32; ++k) acc += c[k] * yy[k];
+      }
+      const int ex = c_mi_exp[bt];
+      const int col = m2l_col(((p0 & 1) << 2) | ((p1 & 1) << 1) | (p2 & 1), bt, mi_a(ex) + mi_b(ex) + mi_c(ex));
+      const long long cpp = ((long long)((p0 >> 1) + 3) * nPPp + ((p1 >> 1) + 3)) * nPPp + ((p2 >> 1) + 3);
+      Apar[((col >> 2) * ncPP + cpp) * 4 + (col & 3)] = acc;
+    }
+  }
+}
+
+// L2L^T for one level k: Lbar_{k-1}[P][b'] = sum_q sum_{b + g = b'}
+//   2^-(|b|+1) 4^-|g| / g! (2q-1)^g Lbar_k[2P+q][b].
+// Thread = (cell P of level k-1, term b'); P's row of Abar_k holds its 8
+// children, the result goes to P's parent's row of Abar_{k-1}.
+__global__ __launch_bounds__(256) void k_adj_l2l(const double* __restrict__ Ak, double* __restrict__ Akm1, int ns,
+                                                 int NL) {
+  const long long nps = (long long)ns * ns * ns;
+  const long long id = blockIdx.x * 256LL + threadIdx.x;
+  if (id >= nps * NL) return;
+  const long long P = id / NL;
+  const int bt2 = (int)(id % NL);
+  const int p2 = (int)(P % ns), p1 = (int)((P / ns) % ns), p0 = (int)(P / ((long long)ns * ns));
+  const int nsp = ns + 6, nh = ns >> 1, nhp = nh + 6;
+  const long long nck = (long long)nsp * nsp * nsp, nckm = (long long)nhp * nhp * nhp;
+  const long long cp = ((long long)(p0 + 3) * nsp + (p1 + 3)) * nsp + (p2 + 3);
+  const int ex2 = c_mi_exp[bt2];
+  const int bx = mi_a(ex2), by = mi_b(ex2), bz = mi_c(ex2);
+  double acc = 0.0;
+  for (int gx = 0; gx <= bx; ++gx)
+    for (int gy = 0; gy <= by; ++gy)
+      for (int gz = 0; gz <= bz; ++gz) {
+        const int ax = bx - gx, ay = by - gy, az = bz - gz, md = ax + ay + az, gd = gx + gy + gz;
+        const int bt = mi_index(ax, ay, az);
+        const int pat = ((gx & 1) << 2) | ((gy & 1) << 1) | (gz & 1);
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int col = m2l_col(q, bt, md);
+          const double x = Ak[((col >> 2) * nck + cp) * 4 + (col & 3)];
+          sum += (__popc((~q) & pat) & 1) ? -x : x;
+        }
+        acc += ldexp(c_mi_invfact[mi_index(gx, gy, gz)], -(md + 1) - 2 * gd) * sum;
+      }
+  const int qP = ((p0 & 1) << 2) | ((p1 & 1) << 1) | (p2 & 1);
+  const int col = m2l_col(qP, bt2, bx + by + bz);
+  const long long cpp = ((long long)((p0 >> 1) + 3) * nhp + ((p1 >> 1) + 3)) * nhp + ((p2 >> 1) + 3);
+  Akm1[((col >> 2) * nckm + cpp) * 4 + (col & 3)] = acc;
+}
+
+// M2M^T for one level k: Mbar_k[2P+q][b] += sum_{a >= b}
+//   2^-|b| 4^-|g| / g! (-1)^(q.g) Mbar_{k-1}[P][a],  g = a - b.
+// Thread = (cell P of level k-1, term b); the 8 sign patterns of g are summed
+// first and the children are formed by a Walsh transform.
+__global__ __launch_bounds__(256) void k_adj_m2m(const double* __restrict__ Mp, double* __restrict__ Mc, int np,
+                                                 int P, int NM) {
+  const long long nps = (long long)np * np * np;
+  const long long id = blockIdx.x * 256LL + threadIdx.x;
+  if (id >= nps * NM) return;
+  const long long Pc = id / NM;
+  const int bt = (int)(id % NM);
+  const int p2 = (int)(Pc % np), p1 = (int)((Pc / np) % np), p0 = (int)(Pc / ((long long)np * np));
+  const int npp = np + 6, nk = 2 * np, nkp = nk + 6;
+  const long long ncp = (long long)npp * npp * npp, nck = (long long)nkp * nkp * nkp;
+  const long long cp = ((long long)(p0 + 3) * npp + (p1 + 3)) * npp + (p2 + 3);
+  const int ex = c_mi_exp[bt];
+  const int bx = mi_a(ex), by = mi_b(ex), bz = mi_c(ex), bd = bx + by + bz;
+  double S[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) S[k] = 0.0;
+  for (int gx = 0; gx + bd <= P; ++gx)
+    for (int gy = 0; gx + gy + bd <= P; ++gy)
+      for (int gz = 0; gx + gy + gz + bd <= P; ++gz) {
+        const int a = mi_index(bx + gx, by + gy, bz + gz);
+        const double x = ldexp(c_mi_invfact[mi_index(gx, gy, gz)], -bd - 2 * (gx + gy + gz)) *
+                         Mp[((a >> 2) * ncp + cp) * 4 + (a & 3)];
+        const int pat = ((gx & 1) << 2) | ((gy & 1) << 1) | (gz & 1);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (k == pat) S[k] += x;
+      }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    double v = 0.0;
+#pragma unroll
+    for (int pat = 0; pat < 8; ++pat) v += (__popc(q & pat) & 1) ? -S[pat] : S[pat];
+    const long long cc = ((long long)(2 * p0 + ((q >> 2) & 1) + 3) * nkp + (2 * p1 + ((q >> 1) & 1) + 3)) * nkp +
+                         (2 * p2 + (q & 1) + 3);
+    Mc[((bt >> 2) * nck + cc) * 4 + (bt & 3)] += v;
+  }
+}
+
+// P2M^T + near^T: rho_bar[w] = sum_a 4^-|a| / a! (-1)^(q_w.a) Mbar_F[T_w][a]
+//   + sum_{e in [-1,1]^3} sum_{(q,o)} p2p_coef(q_w - 2e, q, o) Ybar_{T_w+e}[(q,o)].
+// Block = 8^3 unigrid cells (4^3 level-F cells); the Ybar of the 6^3 cells
+// around them and the near-field stencil are staged in LDS.
+constexpr int ADJ_BOT_THREADS = 512;
+template <typename TO>
+__global__ __launch_bounds__(ADJ_BOT_THREADS) void k_adj_bottom(const double* __restrict__ Mb,
+                                                                const double* __restrict__ Y, TO* __restrict__ drho,
+                                                                int n, int NM) {
+  __shared__ d4 ys[216 * 8];
+  __shared__ double sp[343], sg3[3 * 343];
+  const int nF = n >> 1, nFp = nF + 6;
+  const long long ncellp = (long long)nFp * nFp * nFp;
+  const int T0x = blockIdx.x * 4, T0y = blockIdx.y * 4, T0z = blockIdx.z * 4;
+  for (int h = threadIdx.x; h < 216 * 8; h += ADJ_BOT_THREADS) {
+    const int q = h & 7, c = h >> 3;
+    const int cz = c % 6, cy = (c / 6) % 6, cx = c / 36;
+    // padded coordinates of T = T0 + (cx, cy, cz) - 1, inside [2, nF + 4)
+    const long long cp = ((long long)(T0x + cx + 2) * nFp + (T0y + cy + 2)) * nFp + (T0z + cz + 2);
+    ys[h] = *reinterpret_cast<const d4*>(Y + (q * ncellp + cp) * 4);
+  }
+  for (int t = threadIdx.x; t < 343; t += ADJ_BOT_THREADS) {
+    sp[t] = c_p2p_phi[t];
+    sg3[t] = c_p2p_g[t];
+    sg3[343 + t] = c_p2p_g[343 + t];
+    sg3[686 + t] = c_p2p_g[686 + t];
+  }
+  __syncthreads();
+  const int lz = threadIdx.x & 7, ly = (threadIdx.x >> 3) & 7, lx = threadIdx.x >> 6;
+  const int qw0 = lx & 1, qw1 = ly & 1, qw2 = lz & 1;
+  const int tl0 = lx >> 1, tl1 = ly >> 1, tl2 = lz >> 1;
+  double acc = 0.0;
+  for (int e0 = -1; e0 <= 1; ++e0)
+    for (int e1 = -1; e1 <= 1; ++e1)
+      for (int e2 = -1; e2 <= 1; ++e2) {
+        const d4* yc = ys + (((tl0 + e0 + 1) * 6 + (tl1 + e1 + 1)) * 6 + (tl2 + e2 + 1)) * 8;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          // delta = u - w = 2e + q - q_w in [-3, 3]^3
+          const int t = (2 * e0 + ((q >> 2) & 1) - qw0 + 3) * 49 + (2 * e1 + ((q >> 1) & 1) - qw1 + 3) * 7 +
+                        (2 * e2 + (q & 1) - qw2 + 3);
+          const d4 v = yc[q];
+          acc += 2.0 * sp[t] * v[0] - 4.0 * (sg3[t] * v[1] + sg3[343 + t] * v[2] + sg3[686 + t] * v[3]);
+        }
+      }
+  // P2M^T from the adjoint multipoles of the cell's own level-F cell
+  const int t0 = T0x + tl0, t1 = T0y + tl1, t2 = T0z + tl2;
+  const long long cp = ((long long)(t0 + 3) * nFp + (t1 + 3)) * nFp + (t2 + 3);
+  const int qw = (qw0 << 2) | (qw1 << 1) | qw2;
+  for (int c = 0; c < (NM + 3) / 4; ++c) {
+    const d4 m = *reinterpret_cast<const d4*>(Mb + (c * ncellp + cp) * 4);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int a = 4 * c + e;
+      if (a >= NM) break;
+      const int ex = c_mi_exp[a];
+      const int ax = mi_a(ex), ay = mi_b(ex), az = mi_c(ex);
+      const int pat = ((ax & 1) << 2) | ((ay & 1) << 1) | (az & 1);
+      const double x = ldexp(c_mi_invfact[a], -2 * (ax + ay + az)) * m[e];
+      acc += (__popc(qw & pat) & 1) ? -x : x;
+    }
+  }
+  const long long w = ((long long)(2 * t0 + qw0) * n + (2 * t1 + qw1)) * n + (2 * t2 + qw2);
+  drho[w] = (TO)acc;
+}
+
+// ---------------------------------------------------------------------------
 // launch helpers
 // ---------------------------------------------------------------------------
 static inline unsigned blocks_for(long long work, int per) { return (unsigned)((work + per - 1) / per); }
@@ -350,6 +610,20 @@ static inline unsigned blocks_for(long long work, int per) { return (unsigned)((
 // ---------------------------------------------------------------------------
 // plan tables
 // ---------------------------------------------------------------------------
+// B fragments of one convolution (k_conv) in the compute type
+template <typename CT>
+static hipError_t build_conv_table(fmm_plan* pl, int op, void** out, hipStream_t s) {
+  using M = Mf<CT>;
+  constexpr int EL = 64 / M::OPM;
+  const long long cnt = (long long)conv_nfrags(op, pl->p, M::KC) * NSLOT * EL * M::VPL;
+  hipError_t e = hipMalloc(out, cnt * sizeof(typename M::H));
+  if (e != hipSuccess) return e;
+  pl->bytes += cnt * sizeof(typename M::H);
+  hipLaunchKernelGGL((k_expand_conv<CT>), dim3(blocks_for(cnt, 256)), dim3(256), 0, s, pl->dtab,
+                     (typename M::H*)*out, op, pl->p, pl->ND);
+  return hipGetLastError();
+}
+
 template <typename CT>
 static hipError_t build_tables_t(fmm_plan* pl, bool bottom, bool m2l, hipStream_t s) {
   using M = Mf<CT>;
@@ -371,12 +645,7 @@ static hipError_t build_tables_t(fmm_plan* pl, bool bottom, bool m2l, hipStream_
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (m2l && !pl->wm2l[X]) {
-    const long long cnt = (long long)m2l_nfrags(pl->p, KC) * NSLOT * EL * VPL;
-    if ((e = hipMalloc(&pl->wm2l[X], cnt * sizeof(H))) != hipSuccess) return e;
-    pl->bytes += cnt * sizeof(H);
-    hipLaunchKernelGGL((k_expand_m2l<CT>), dim3(blocks_for(cnt, 256)), dim3(256), 0, s, pl->dtab, (H*)pl->wm2l[X],
-                       pl->p, pl->ND);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = build_conv_table<CT>(pl, CV_M2L, &pl->wm2l[X], s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -401,21 +670,33 @@ hipError_t launch_dtab(fmm_plan* pl, hipStream_t s) {
   return e;
 }
 
-template <int P, typename CT, int G>
-static hipError_t launch_m2l_groups(fmm_plan* pl, const M2LLevels& lv, hipStream_t s) {
+template <int P, typename CT, int OP, int G>
+static hipError_t launch_conv_groups(const M2LLevels& lv, const void* W, const int* dlists, hipStream_t s) {
   using B = M2LBudget<CT>;
   constexpr int KC = Mf<CT>::KC;
-  if constexpr (G >= m2l_ngroups(P, KC, B::MAXT, B::MAXB)) {
+  if constexpr (G >= conv_ngroups(OP, P, KC, B::MAXT, B::MAXB)) {
     return hipSuccess;
   } else {
-    constexpr int T0 = m2l_group_start(P, G, KC, B::MAXT, B::MAXB);
-    constexpr int T1 = m2l_group_end(P, T0, KC, B::MAXT, B::MAXB);
-    hipLaunchKernelGGL((k_m2l<P, CT, T0, T1 - T0>), dim3(lv.first_block[lv.nlev]), dim3(M2L_THREADS), 0, s, lv,
-                       (const typename Mf<CT>::H*)pl->wm2l[Mf<CT>::IDX], pl->dlists);
+    constexpr int T0 = conv_group_start(OP, P, G, KC, B::MAXT, B::MAXB);
+    constexpr int T1 = conv_group_end(OP, P, T0, KC, B::MAXT, B::MAXB);
+    hipLaunchKernelGGL((k_conv<P, CT, OP, T0, T1 - T0>), dim3(lv.first_block[lv.nlev]), dim3(M2L_THREADS), 0, s, lv,
+                       (const typename Mf<CT>::H*)W, dlists);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_m2l_groups<P, CT, G + 1>(pl, lv, s);
+    return launch_conv_groups<P, CT, OP, G + 1>(lv, W, dlists, s);
   }
+}
+
+// row-grid bookkeeping of a multi-level convolution launch
+static void add_conv_level(M2LLevels& lv, int ns, const double* src, double* dst) {
+  const int li = lv.nlev++;
+  if (li == 0) lv.first_block[0] = 0;
+  lv.ns[li] = ns;
+  lv.tiles_per_axis[li] = (ns + LX - 1) / LX;
+  lv.src[li] = src;
+  lv.dst[li] = dst;
+  const int tpa = lv.tiles_per_axis[li];
+  lv.first_block[li + 1] = lv.first_block[li] + tpa * tpa * tpa;
 }
 
 // M2L of target levels k_lo..k_hi (sources at k - 1) in one launch per group
@@ -423,20 +704,11 @@ template <int P, typename CT>
 static hipError_t launch_m2l(fmm_plan* pl, int k_lo, int k_hi, hipStream_t s) {
   if (k_lo > k_hi) return hipSuccess;
   M2LLevels lv{};
-  lv.nlev = k_hi - k_lo + 1;
-  lv.first_block[0] = 0;
-  for (int li = 0; li < lv.nlev; ++li) {
-    const int k = k_lo + li, ns = 1 << (k - 1);
-    lv.ns[li] = ns;
-    lv.tiles_per_axis[li] = (ns + LX - 1) / LX;
-    lv.M[li] = (const double*)pl->lev[k - 1].M;
-    lv.Lam[li] = (double*)pl->lev[k].L;
-    const int tpa = lv.tiles_per_axis[li];
-    lv.first_block[li + 1] = lv.first_block[li] + tpa * tpa * tpa;
-  }
+  for (int k = k_lo; k <= k_hi; ++k)
+    add_conv_level(lv, 1 << (k - 1), (const double*)pl->lev[k - 1].M, (double*)pl->lev[k].L);
   using B = M2LBudget<CT>;
-  StageScope sc(pl, ST_M2L, m2l_ngroups(P, Mf<CT>::KC, B::MAXT, B::MAXB), s);
-  return launch_m2l_groups<P, CT, 0>(pl, lv, s);
+  StageScope sc(pl, ST_M2L, conv_ngroups(CV_M2L, P, Mf<CT>::KC, B::MAXT, B::MAXB), s);
+  return launch_conv_groups<P, CT, CV_M2L, 0>(lv, pl->wm2l[Mf<CT>::IDX], pl->dlists, s);
 }
 
 // L2L for one level k (Lhat_k += shift of Lhat_{k-1}), in place
@@ -527,8 +799,111 @@ hipError_t launch_solve(fmm_plan* pl, const void* rho, void* phi, void* g, hipSt
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_backward(fmm_plan*, const void*, const void*, void*, hipStream_t) {
-  return hipErrorNotSupported;
+// ---------------------------------------------------------------------------
+// adjoint solve
+// ---------------------------------------------------------------------------
+hipError_t launch_adjoint_tables(fmm_plan* pl, hipStream_t s) {
+  hipError_t e;
+  const int NL = pl->NL;
+  hipLaunchKernelGGL(k_adj_coef, dim3(blocks_for(9LL * NL * 32, 256)), dim3(256), 0, s, pl->adj_l2p, pl->adj_l2p2, NL);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int klow = m2l_low_from(pl);
+  const bool m2l64 = pl->F >= 3 && klow > 3, m2llow = pl->F >= 3 && pl->precision != 0 && klow <= pl->F;
+  if (m2l64 && (e = build_conv_table<double>(pl, CV_M2LT, &pl->wt_m2l[0], s)) != hipSuccess) return e;
+  if (m2llow) {
+    if (pl->precision == 1 && (e = build_conv_table<float>(pl, CV_M2LT, &pl->wt_m2l[1], s)) != hipSuccess) return e;
+    if (pl->precision == 2 && (e = build_conv_table<bf16_tag>(pl, CV_M2LT, &pl->wt_m2l[2], s)) != hipSuccess) return e;
+  }
+  if (!bottom_low(pl)) return build_conv_table<double>(pl, CV_M2PT, &pl->wt_m2p[0], s);
+  if (pl->precision == 1) return build_conv_table<float>(pl, CV_M2PT, &pl->wt_m2p[1], s);
+  return build_conv_table<bf16_tag>(pl, CV_M2PT, &pl->wt_m2p[2], s);
+}
+
+template <int P, typename CT, typename TI, typename TO>
+static hipError_t backward_p(fmm_plan* pl, const TI* dphi, const TI* dg, TO* drho, hipStream_t s) {
+  constexpr int NM = nterms(P), NL = nterms(P);
+  const int n = pl->n, F = pl->F, nF = n / 2;
+  const double dx = pl->dx;
+  hipError_t e;
+  const long long nT = (long long)nF * nF * nF;
+  hipLaunchKernelGGL((k_adj_seed<TI>), dim3(blocks_for(nT, 256)), dim3(256), 0, s, dphi, dg, pl->ybar, n,
+                     0.5 * dx * dx, -0.25 * dx);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (F >= 3) {
+    // transposed L2P of the own local and of the parent level's local
+    const long long nP = nT / 8;
+    hipLaunchKernelGGL(k_adj_l2p, dim3(blocks_for(nP, 4)), dim3(256), 0, s, pl->ybar, pl->adj_l2p, pl->adj_l2p2,
+                       pl->abar[F], F >= 4 ? pl->abar[F - 1] : nullptr, nF, NL, loc_stride(P));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // transposed L2L chain, fine to coarse
+    for (int k = F - 1; k >= 4; --k) {
+      const int ns = 1 << (k - 1);
+      hipLaunchKernelGGL(k_adj_l2l, dim3(blocks_for((long long)ns * ns * ns * NL, 256)), dim3(256), 0, s,
+                         pl->abar[k], pl->abar[k - 1], ns, NL);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    // transposed M2L of every target level (sources k - 1 receive)
+    const int klow = m2l_low_from(pl);
+    {
+      M2LLevels lv{};
+      for (int k = 3; k <= F && k < klow; ++k)
+        add_conv_level(lv, 1 << (k - 1), pl->abar[k], (double*)pl->lev[k - 1].M);
+      if (lv.nlev && (e = launch_conv_groups<P, double, CV_M2LT, 0>(lv, pl->wt_m2l[0], pl->dlists, s)) != hipSuccess)
+        return e;
+    }
+    if constexpr (!std::is_same<CT, double>::value) {
+      M2LLevels lv{};
+      for (int k = klow; k <= F; ++k) add_conv_level(lv, 1 << (k - 1), pl->abar[k], (double*)pl->lev[k - 1].M);
+      if (lv.nlev &&
+          (e = launch_conv_groups<P, CT, CV_M2LT, 0>(lv, pl->wt_m2l[Mf<CT>::IDX], pl->dlists, s)) != hipSuccess)
+        return e;
+    }
+  }
+  // transposed M2P at the finest level
+  {
+    M2LLevels lv{};
+    add_conv_level(lv, nF, pl->ybar, (double*)pl->lev[F].M);
+    if (bottom_low(pl))
+      e = launch_conv_groups<P, CT, CV_M2PT, 0>(lv, pl->wt_m2p[Mf<CT>::IDX], pl->dlists, s);
+    else
+      e = launch_conv_groups<P, double, CV_M2PT, 0>(lv, pl->wt_m2p[0], pl->dlists, s);
+    if (e != hipSuccess) return e;
+  }
+  // transposed M2M chain, coarse to fine
+  for (int k = 3; k <= F; ++k) {
+    const int np = 1 << (k - 1);
+    hipLaunchKernelGGL(k_adj_m2m, dim3(blocks_for((long long)np * np * np * NM, 256)), dim3(256), 0, s,
+                       (const double*)pl->lev[k - 1].M, (double*)pl->lev[k].M, np, P, NM);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  dim3 bgrid(nF / 4, nF / 4, nF / 4);
+  hipLaunchKernelGGL((k_adj_bottom<TO>), bgrid, dim3(ADJ_BOT_THREADS), 0, s, (const double*)pl->lev[F].M, pl->ybar,
+                     drho, n, NM);
+  return hipGetLastError();
+}
+
+template <typename CT, typename TI, typename TO>
+static hipError_t dispatch_bwd(fmm_plan* pl, const TI* dphi, const TI* dg, TO* drho, hipStream_t s) {
+  switch (pl->p) {
+    case 1: return backward_p<1, CT>(pl, dphi, dg, drho, s);
+    case 2: return backward_p<2, CT>(pl, dphi, dg, drho, s);
+    case 3: return backward_p<3, CT>(pl, dphi, dg, drho, s);
+    case 4: return backward_p<4, CT>(pl, dphi, dg, drho, s);
+    case 5: return backward_p<5, CT>(pl, dphi, dg, drho, s);
+    case 6: return backward_p<6, CT>(pl, dphi, dg, drho, s);
+    case 7: return backward_p<7, CT>(pl, dphi, dg, drho, s);
+    case 8: return backward_p<8, CT>(pl, dphi, dg, drho, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_backward(fmm_plan* pl, const void* dphi, const void* dg, void* drho, hipStream_t s) {
+  switch (pl->precision) {
+    case 0: return dispatch_bwd<double>(pl, (const double*)dphi, (const double*)dg, (double*)drho, s);
+    case 1: return dispatch_bwd<float>(pl, (const float*)dphi, (const float*)dg, (float*)drho, s);
+    case 2: return dispatch_bwd<bf16_tag>(pl, (const float*)dphi, (const float*)dg, (float*)drho, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename T>

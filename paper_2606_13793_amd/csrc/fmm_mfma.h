@@ -347,12 +347,23 @@ __global__ void k_expand_bottom(const double* __restrict__ Dtab, typename Mf<CT>
 }
 
 // ---------------------------------------------------------------------------
-// M2L, eq. (M2L), over the oct-shared interaction lists (Sec. 2.2), every
-// level in one launch per column group.  Rows are cells P of a source grid
-// s = k - 1; columns are (child q, local term b) sorted by |b|; the result is
-// the M2L part of the locals of the 8 children,
-//   Lam_k[2P + q][b] = 2^-(|b|+1) sum_d sum_a D[a+b](Rhat_{d,q}) Mhat_s[P-d][a],
-// stored per source cell in column order.
+// Parity-class convolution on the matrix cores, every level in one launch per
+// column group.  Rows are the cells R of a grid s (one wave per parity class
+// r of R); for each list offset d of class r the operand cell is X = R - d,
+// staged with a 3-cell halo in LDS, and
+//   out[R][col] = sum_d sum_k B_d[k][col] in[X][k].
+// CV_M2L   (eq. (M2L), Sec. 2.2): R = source parent P of grid k - 1,
+//          in = Mhat_{k-1}, col = (child q, local term b) sorted by |b|,
+//          B_d[a][(q, b)] = D[a+b](Rhat_{d,q}); the result is the M2L part of
+//          the locals of the 8 children, scaled by 2^-(|b|+1) and stored per
+//          source cell in column order.
+// CV_M2LT  transposed M2L: R = source cell J, X = a target's parent, in = the
+//          adjoint locals in that column order, col = multipole term a,
+//          B_d[(q, b)][a] = 2^-(|b|+1) D[a+b](Rhat_{-d,q}); stored as an
+//          adjoint multipole grid.
+// CV_M2PT  transposed M2P: R = level-F cell J, X = a target cell, in = the 32
+//          scaled adjoint outputs (q, o) of X, col = a,
+//          B_d[(q, o)][a] = D[a + e_o](Rhat_{-d,q}).
 // ---------------------------------------------------------------------------
 constexpr int LX = 8;
 constexpr int LH = LX + 6, LH2 = LH / 2;
@@ -364,9 +375,9 @@ struct M2LLevels {
   int nlev;
   int first_block[MAXLEV + 1];
   int tiles_per_axis[MAXLEV];
-  int ns[MAXLEV];
-  const double* M[MAXLEV];
-  double* Lam[MAXLEV];
+  int ns[MAXLEV];             // row grid cells per axis
+  const double* src[MAXLEV];  // operand grid, chunked [NK/4][(ns+6)^3][4] with a zero margin
+  double* dst[MAXLEV];        // CV_M2L: locals [ns^3][loc_stride]; else chunked padded [NC4][(ns+6)^3][4]
 };
 
 __device__ __forceinline__ int lhalo_index(int hx, int hy, int hz) {
@@ -380,32 +391,32 @@ struct M2LBudget {
   static constexpr int MAXB = 24;
 };
 
-// chunk count and first fragment of each tile of an M2L launch, as
-// compile-time tables (the helper functions loop and must not run on device)
-template <int P, int KC, int T0, int NT>
+// chunk count and first fragment of each tile of a launch, as compile-time
+// tables (the helper functions loop and must not run on device)
+template <int OP, int P, int KC, int T0, int NT>
 struct TileChunks {
   int v[NT];
   int off[NT];
   constexpr TileChunks() : v(), off() {
     for (int t = 0; t < NT; ++t) {
-      v[t] = m2l_tile_chunks(P, T0 + t, KC);
-      off[t] = m2l_frag_offset(P, T0 + t, KC);
+      v[t] = conv_tile_chunks(OP, P, T0 + t, KC);
+      off[t] = conv_frag_offset(OP, P, T0 + t, KC);
     }
   }
 };
 
-template <int P, typename CT, int T0, int NT>
-__global__ __launch_bounds__(M2L_THREADS, 1) void k_m2l(M2LLevels lv, const typename Mf<CT>::H* __restrict__ Wm2l,
-                                                       const int* __restrict__ dlists) {
+template <int P, typename CT, int OP, int T0, int NT>
+__global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(M2LLevels lv, const typename Mf<CT>::H* __restrict__ Wt,
+                                                        const int* __restrict__ dlists) {
   using M = Mf<CT>;
   using H = typename M::H;
   using AF = typename M::AF;
   using Acc = typename M::Acc;
   constexpr int KC = M::KC, OPM = M::OPM, VPL = M::VPL, EL = 64 / OPM;
-  constexpr int NM = nterms(P), NC4 = (NM + 3) / 4;
-  constexpr int NL = nterms(P), NCOL = 8 * NL;
+  constexpr int NC4 = (conv_nk(OP, P) + 3) / 4;  // 4-term chunks of the operand grid
+  constexpr int NM = nterms(P), NCOL = 8 * nterms(P);
   constexpr int NGRP = (NLIST + OPM - 1) / OPM;
-  constexpr TileChunks<P, KC, T0, NT> kch{};
+  constexpr TileChunks<OP, P, KC, T0, NT> kch{};
   constexpr int CM = kch.v[0];
   __shared__ H halo[LH * LH * LH * KC];
   int li = 0;
@@ -413,8 +424,8 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_m2l(M2LLevels lv, const type
   const int tb = (int)blockIdx.x - lv.first_block[li];
   const int tpa = lv.tiles_per_axis[li];
   const int ns = lv.ns[li], nsp = ns + 6;
-  const double* __restrict__ Mh = lv.M[li];
-  double* __restrict__ Lam = lv.Lam[li];
+  const double* __restrict__ src = lv.src[li];
+  double* __restrict__ dst = lv.dst[li];
   const int tx0 = (tb / (tpa * tpa)) * LX, ty0 = ((tb / tpa) % tpa) * LX, tz0 = (tb % tpa) * LX;
   const long long ncellp = (long long)nsp * nsp * nsp;
   const int lane = threadIdx.x & 63;
@@ -436,7 +447,7 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_m2l(M2LLevels lv, const type
     pos += rot;
     return dl[pos < NLIST ? pos : pos - NLIST];
   };
-  const H* wl = Wm2l + lr.tl * VPL;
+  const H* wl = Wt + lr.tl * VPL;
   auto bload = [&](int e, int t, int c) {
     return *reinterpret_cast<const AF*>(wl + ((size_t)(kch.off[t] + c) * NSLOT + dl_dd(e)) * EL * VPL);
   };
@@ -447,14 +458,14 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_m2l(M2LLevels lv, const type
       const int hz = h % LH, hy = (h / LH) % LH, hx = h / (LH * LH);
       const int px = tx0 + hx, py = ty0 + hy, pz = tz0 + hz;
       const bool in = px < nsp && py < nsp && pz < nsp;
-      H* dst = halo + lhalo_index(hx, hy, hz) * KC;
+      H* hd = halo + lhalo_index(hx, hy, hz) * KC;
 #pragma unroll
       for (int s4 = 0; s4 < KC / 4; ++s4) {
         const int sc = c * (KC / 4) + s4;
         d4 v = d4{0, 0, 0, 0};
-        if (in && sc < NC4) v = *reinterpret_cast<const d4*>(Mh + (sc * ncellp + ((long long)px * nsp + py) * nsp + pz) * 4);
+        if (in && sc < NC4) v = *reinterpret_cast<const d4*>(src + (sc * ncellp + ((long long)px * nsp + py) * nsp + pz) * 4);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) dst[4 * s4 + e] = static_cast<H>(v[e]);
+        for (int e = 0; e < 4; ++e) hd[4 * s4 + e] = static_cast<H>(v[e]);
       }
     }
     __syncthreads();
@@ -497,57 +508,104 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_m2l(M2LLevels lv, const type
       }
     }
   }
-  // epilogue: element v of tile t is row M::row(v, kq), column 16 (T0 + t) + i;
-  // the 16 lanes of a row write 128 contiguous bytes
-  constexpr int RS = loc_stride(P);
-  int escale[NT];
+  // epilogue: element v of tile t is row M::row(v, kq), column 16 (T0 + t) + i
+  if constexpr (OP == CV_M2L) {
+    // the 16 lanes of a row write 128 contiguous bytes
+    constexpr int RS = loc_stride(P);
+    int escale[NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int col = 16 * (T0 + t) + i;
-    escale[t] = -(m2l_col_degree(col < NCOL ? col : 0) + 1);
-  }
-#pragma unroll
-  for (int m = 0; m < M2L_MT; ++m)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int row = M::row(v, kq);
-      const int p0 = tx0 + 2 * m + r0, p1 = ty0 + 2 * (row >> 2) + r1, p2 = tz0 + 2 * (row & 3) + r2;
-      if (p0 >= ns || p1 >= ns || p2 >= ns) continue;
-      double* dst = Lam + (((long long)p0 * ns + p1) * ns + p2) * RS + 16 * T0 + i;
-#pragma unroll
-      for (int t = 0; t < NT; ++t) dst[16 * t] = ldexp((double)acc[m][t][v], escale[t]);
+    for (int t = 0; t < NT; ++t) {
+      const int col = 16 * (T0 + t) + i;
+      escale[t] = -(m2l_col_degree(col < NCOL ? col : 0) + 1);
     }
+#pragma unroll
+    for (int m = 0; m < M2L_MT; ++m)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = M::row(v, kq);
+        const int p0 = tx0 + 2 * m + r0, p1 = ty0 + 2 * (row >> 2) + r1, p2 = tz0 + 2 * (row & 3) + r2;
+        if (p0 >= ns || p1 >= ns || p2 >= ns) continue;
+        double* o = dst + (((long long)p0 * ns + p1) * ns + p2) * RS + 16 * T0 + i;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) o[16 * t] = ldexp((double)acc[m][t][v], escale[t]);
+      }
+  } else {
+#pragma unroll
+    for (int m = 0; m < M2L_MT; ++m)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = M::row(v, kq);
+        const int p0 = tx0 + 2 * m + r0, p1 = ty0 + 2 * (row >> 2) + r1, p2 = tz0 + 2 * (row & 3) + r2;
+        if (p0 >= ns || p1 >= ns || p2 >= ns) continue;
+        const long long cp = ((long long)(p0 + 3) * nsp + (p1 + 3)) * nsp + (p2 + 3);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int a = 16 * (T0 + t) + i;
+          if (a < NM) dst[((a >> 2) * ncellp + cp) * 4 + (a & 3)] = (double)acc[m][t][v];
+        }
+      }
+  }
 }
 
-// B fragments of the M2L in fragment order, converted to the compute type:
-// [fragment f][NSLOT][EL][VPL], fragment f = (tile t, chunk c); entry lane el
-// holds, for column 16 t + (el & 15) = (q, b), the terms a = KC c + tic + v of
-// D[a + b](Rhat_{d,q}) (0 where |a| + |b| > p, past the terms, or the null slot).
+// B fragments of the convolutions in fragment order, converted to the compute
+// type: [fragment f][NSLOT][EL][VPL], fragment f = (tile t, chunk c); entry
+// lane el holds, for column 16 t + (el & 15), the K indices KC c + tic + v
+// (0 where the truncation |a| + |b| <= p drops the pair, past the ends, and in
+// the null slot).
 template <typename CT>
-__global__ void k_expand_m2l(const double* __restrict__ Dtab, typename Mf<CT>::H* __restrict__ W, int P, int ND) {
+__global__ void k_expand_conv(const double* __restrict__ Dtab, typename Mf<CT>::H* __restrict__ W, int op, int P,
+                              int ND) {
   using M = Mf<CT>;
   constexpr int KC = M::KC, OPM = M::OPM, VPL = M::VPL, EL = 64 / OPM;
-  const int NF = m2l_nfrags(P, KC);
+  const int NF = conv_nfrags(op, P, KC);
   const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (id >= (long long)NF * NSLOT * EL * VPL) return;
   const int v = (int)(id % VPL), el = (int)((id / VPL) % EL);
   const int slot = (int)((id / ((long long)VPL * EL)) % NSLOT), f = (int)(id / ((long long)VPL * EL * NSLOT));
   int t = 0;
-  while (m2l_frag_offset(P, t + 1, KC) <= f) ++t;
-  const int c = f - m2l_frag_offset(P, t, KC);
+  while (conv_frag_offset(op, P, t + 1, KC) <= f) ++t;
+  const int c = f - conv_frag_offset(op, P, t, KC);
   const int j = el & 15;
   const int tic = OPM == 2 ? 8 * (el >> 4) : (el >> 4);
-  const int col = 16 * t + j, al = KC * c + tic + v;
+  const int col = 16 * t + j, kk = KC * c + tic + v;
+  const int NM = nterms(P);
   double val = 0.0;
-  if (slot < 343 && col < 8 * nterms(P) && al < nterms(P)) {
-    const int md = m2l_col_degree(col);
-    const int cin = col - 8 * nterms(md - 1);
-    const int q = cin / ndeg(md);
-    const int bex = c_mi_exp[nterms(md - 1) + cin % ndeg(md)];
-    const int aex = c_mi_exp[al];
-    if (mi_a(aex) + mi_b(aex) + mi_c(aex) + md <= P)
-      val = Dtab[((size_t)slot * 8 + q) * ND +
-                 mi_index(mi_a(aex) + mi_a(bex), mi_b(aex) + mi_b(bex), mi_c(aex) + mi_c(bex))];
+  if (slot < 343) {
+    if (op == CV_M2L) {
+      // K = multipole term a, column (q, b)
+      if (col < 8 * NM && kk < NM) {
+        const int md = m2l_col_degree(col);
+        const int cin = col - 8 * nterms(md - 1);
+        const int q = cin / ndeg(md);
+        const int bex = c_mi_exp[nterms(md - 1) + cin % ndeg(md)];
+        const int aex = c_mi_exp[kk];
+        if (mi_a(aex) + mi_b(aex) + mi_c(aex) + md <= P)
+          val = Dtab[((size_t)slot * 8 + q) * ND +
+                     mi_index(mi_a(aex) + mi_a(bex), mi_b(aex) + mi_b(bex), mi_c(aex) + mi_c(bex))];
+      }
+    } else {
+      // transposes: column = multipole term a, the derivative is taken at the
+      // negated offset (slot 342 - slot)
+      const int ns = 342 - slot;
+      if (col < NM) {
+        const int aex = c_mi_exp[col];
+        const int ax = mi_a(aex), ay = mi_b(aex), az = mi_c(aex);
+        if (op == CV_M2LT) {
+          if (kk < 8 * NM) {
+            const int md = m2l_col_degree(kk);
+            const int cin = kk - 8 * nterms(md - 1);
+            const int q = cin / ndeg(md);
+            const int bex = c_mi_exp[nterms(md - 1) + cin % ndeg(md)];
+            if (ax + ay + az + md <= P)
+              val = ldexp(Dtab[((size_t)ns * 8 + q) * ND + mi_index(ax + mi_a(bex), ay + mi_b(bex), az + mi_c(bex))],
+                          -(md + 1));
+          }
+        } else if (kk < 32) {
+          const int q = kk >> 2, o = kk & 3;
+          val = Dtab[((size_t)ns * 8 + q) * ND + mi_index(ax + (o == 1), ay + (o == 2), az + (o == 3))];
+        }
+      }
+    }
   }
   W[id] = static_cast<typename M::H>(val);
 }

@@ -1,0 +1,167 @@
+"""The HIP adjoint (fmm_solve_backward, and torch.autograd through fmm.solve)
+against the oracle's explicit transposes, the dot-product identity, central
+finite differences and the direct-sum gradient.
+
+Bars: FP64 relative L2 <= 1e-12 against the oracle's adjoint and <= 1e-13 for
+the dot-product identity; FP32 <= 1e-4 against finite differences of the FP64
+forward solve.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import fmm_inputs as fi
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    from paper_2606_13793_amd import fmm
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return fmm
+
+
+def rel(a, b):
+    a, b = np.ravel(a), np.ravel(b)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _cotangents(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n, n, n)), rng.standard_normal((3, n, n, n))
+
+
+def _gpu_backward(F, n, p, dphi, dg, precision="fp64", coarse=4):
+    import torch
+    plan = F.Plan(n, p, precision, coarse_fp64_levels=coarse)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    a = torch.as_tensor(dphi).to("cuda", dt).contiguous()
+    b = None if dg is None else torch.as_tensor(dg).to("cuda", dt).contiguous()
+    out = plan.backward(a, b)
+    torch.cuda.synchronize()
+    return out.double().cpu().numpy(), plan
+
+
+@pytest.mark.parametrize("n,p", [(8, 4), (16, 4), (16, 6), (32, 6), (64, 6)])
+def test_adjoint_matches_oracle(F, orc, n, p):
+    _say(f"case adjoint fp64 n={n} p={p}")
+    dphi, dg = _cotangents(n, 100 + n + p)
+    got, _ = _gpu_backward(F, n, p, dphi, dg)
+    ref = orc.adjoint(dphi, dg, p)
+    assert rel(got, ref) < TOL64, rel(got, ref)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 7, 8])
+def test_adjoint_every_order(F, orc, p):
+    _say(f"case adjoint fp64 order p={p} n=16")
+    dphi, dg = _cotangents(16, 200 + p)
+    got, _ = _gpu_backward(F, 16, p, dphi, dg)
+    ref = orc.adjoint(dphi, dg, p)
+    assert rel(got, ref) < TOL64, rel(got, ref)
+
+
+def test_adjoint_phi_only(F, orc):
+    _say("case adjoint fp64 dg=None n=32 p=5")
+    dphi, _ = _cotangents(32, 7)
+    got, _ = _gpu_backward(F, 32, 5, dphi, None)
+    ref = orc.adjoint(dphi, None, 5)
+    assert rel(got, ref) < TOL64, rel(got, ref)
+
+
+@pytest.mark.parametrize("n", [32, 128])
+def test_dot_product_identity(F, n):
+    """<A rho, (psi, chi)> = <rho, A^T (psi, chi)>: exact up to rounding."""
+    import torch
+    _say(f"case dot product fp64 n={n} p=6")
+    plan = F.Plan(n, 6)
+    rho = fi.plummer_density(n, fi.multi_plummer_params(16, 9 + n), device="cuda")
+    gen = torch.Generator(device="cuda").manual_seed(n)
+    psi = torch.randn((n, n, n), dtype=torch.float64, device="cuda", generator=gen)
+    chi = torch.randn((3, n, n, n), dtype=torch.float64, device="cuda", generator=gen)
+    phi, g = plan.solve(rho)
+    lhs = float((phi * psi).sum() + (g * chi).sum())
+    rhs = float((rho * plan.backward(psi, chi)).sum())
+    # the scale of the sums (Cauchy-Schwarz), against which rounding is measured
+    scale = float(phi.norm() * psi.norm() + g.norm() * chi.norm())
+    assert abs(lhs - rhs) <= 1e-13 * scale, (lhs, rhs, scale)
+
+
+@pytest.mark.parametrize("precision,bar", [("fp32", 1e-4), ("bf16", 5e-2)])
+def test_adjoint_mixed(F, orc, precision, bar):
+    """Low-precision adjoint on every level (threshold 0) against the oracle."""
+    _say(f"case adjoint {precision} n=64 p=6")
+    dphi, dg = _cotangents(64, 31)
+    dphi32, dg32 = dphi.astype(np.float32), dg.astype(np.float32)
+    got, _ = _gpu_backward(F, 64, 6, dphi32, dg32, precision, coarse=0)
+    ref = orc.adjoint(dphi32.astype(np.float64), dg32.astype(np.float64), 6)
+    e = rel(got, ref)
+    _say(f"  rel L2 {e:.3e}")
+    assert e < bar, e
+
+
+def test_autograd_matches_direct_sum_gradient(F, orc):
+    """d/drho sum (phi - phi_t)^2 through torch.autograd against the direct
+    sum's gradient 2 dx^3 G (phi - phi_t): equal up to the FMM truncation
+    error (measured here as the forward error against the direct sum)."""
+    import torch
+    n, p = 16, 6
+    _say("case autograd vs direct-sum gradient n=16 p=6")
+    rho = fi.plummer_density(n, fi.multi_plummer_params(32, 5001))
+    phi_t, _ = orc.solve(fi.plummer_density(n, fi.multi_plummer_params(32, 5002)), p)
+    plan = F.Plan(n, p)
+    x = torch.as_tensor(rho, device="cuda").requires_grad_(True)
+    phi, g = F.solve(plan, x)
+    loss = ((phi - torch.as_tensor(phi_t, device="cuda")) ** 2).sum()
+    loss.backward()
+    grad = x.grad.cpu().numpy()
+    r = phi.detach().cpu().numpy() - phi_t
+    # the exact adjoint of the oracle's solve
+    assert rel(grad, orc.adjoint(2 * r, None, p)) < TOL64
+    phi_d, _ = orc.direct(rho)
+    fwd_err = rel(phi.detach().cpu().numpy(), phi_d)
+    grad_err = rel(grad, 2 * orc.direct(r)[0])
+    _say(f"  gradient vs direct sum {grad_err:.3e} (forward truncation {fwd_err:.3e})")
+    assert grad_err < fwd_err, (grad_err, fwd_err)
+
+
+def test_fp32_adjoint_against_finite_differences(F):
+    """128^3, p = 6: the FP32 adjoint of L = sum (phi - phi_t)^2 against
+    central differences of the FP64 forward solve at 64 seeded cells.  For a
+    quadratic L the central difference is exact; it is formed cell by cell as
+    sum (phi+ - phi-)(phi+ + phi- - 2 phi_t) to avoid cancellation."""
+    import torch
+    n, p = 128, 6
+    _say("case fp32 adjoint vs FD n=128 p=6")
+    rho = fi.plummer_density(n, fi.multi_plummer_params(32, 5001), device="cuda")
+    rho_t = fi.plummer_density(n, fi.multi_plummer_params(32, 5002), device="cuda")
+    p64 = F.Plan(n, p)
+    phi_t, _ = p64.solve(rho_t)
+    phi, _ = p64.solve(rho)
+    # FP32 adjoint of the cotangent 2 (phi - phi_t)
+    p32 = F.Plan(n, p, "fp32")
+    grad = p32.backward((2 * (phi - phi_t)).float()).double()
+    cells = fi.fd_cells(n, 64, 5003)
+    eps = 1e-3 * float(rho.max())
+    fd = np.zeros(len(cells))
+    gv = grad.reshape(-1)[torch.as_tensor(cells, device="cuda")].cpu().numpy()
+    for i, c in enumerate(cells):
+        rp = rho.clone().reshape(-1)
+        rm = rho.clone().reshape(-1)
+        rp[int(c)] += eps
+        rm[int(c)] -= eps
+        fp, _ = p64.solve(rp.reshape(n, n, n), want_g=False)
+        fm, _ = p64.solve(rm.reshape(n, n, n), want_g=False)
+        fd[i] = float(((fp - fm) * (fp + fm - 2 * phi_t)).sum()) / (2 * eps)
+    e = rel(gv, fd)
+    _say(f"  rel L2 over 64 cells {e:.3e}")
+    assert e < 1e-4, e
