@@ -28,7 +28,7 @@ import numpy as np
 __all__ = [
     "PlummerSet", "multi_plummer_params", "plummer_density", "cell_centres",
     "single_plummer", "uniform_sphere_density", "batch_sizes",
-    "fd_cells",
+    "fd_cells", "batch_field_params",
 ]
 
 
@@ -39,12 +39,24 @@ class PlummerSet:
     masses: np.ndarray   # (K,)
 
 
-def multi_plummer_params(k: int, seed: int) -> PlummerSet:
-    rng = np.random.default_rng(seed)
+def _plummer_draws(rng, k: int) -> PlummerSet:
     centres = rng.uniform(0.2, 0.8, size=(k, 3))
     radii = np.exp(rng.uniform(math.log(0.005), math.log(0.05), size=k))
     masses = np.exp(rng.uniform(math.log(1e-2), math.log(1.0), size=k))
     return PlummerSet(centres, radii, masses)
+
+
+def multi_plummer_params(k: int, seed: int) -> PlummerSet:
+    """K spheres from default_rng(seed): centres, then radii, then masses."""
+    return _plummer_draws(np.random.default_rng(seed), k)
+
+
+def batch_field_params(f: int) -> PlummerSet:
+    """Field f of the uneven batch: K = integers(8, 65) drawn first from
+    default_rng(4000 + f), then the K spheres from the same generator."""
+    rng = np.random.default_rng(4000 + f)
+    k = int(rng.integers(8, 65))
+    return _plummer_draws(rng, k)
 
 
 def single_plummer(mass: float = 1.0, radius: float = 0.1,

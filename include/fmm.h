@@ -69,7 +69,8 @@ typedef struct {
   int nmax;                 /* multipole order, -1 = p (default); 0 <= nmax <= p */
   int coarse_fp64_levels;   /* mixed plans: levels k <= this stay FP64; default 4 */
   int delta_l;              /* level offset unigrid -> finest FMM grid; only 1 */
-  int check_finite;         /* nonzero: fmm_solve scans rho for NaN/Inf first */
+  int check_finite;         /* nonzero: fmm_solve scans rho for NaN/Inf first (single-field plans) */
+  int autotune;             /* batch plans: time the launch-shape candidates at creation; default 1 */
 } fmm_options;
 
 /* Fill *opt with the defaults above.  Returns FMM_OK or FMM_ERR_INVALID_ARG. */
@@ -106,6 +107,38 @@ int fmm_solve(fmm_plan* plan, const void* rho, void* phi, void* g, void* stream)
  * dphi: n^3 (required); dg: 3 n^3 or NULL (treated as zero); drho: n^3.
  */
 int fmm_solve_backward(fmm_plan* plan, const void* dphi, const void* dg, void* drho, void* stream);
+
+/*
+ * Batches: several density fields of (possibly different) sizes solved by
+ * one plan, each stage of the solve being a single launch over the tiles of
+ * every field (the unigrid solve of Sec. 2 applied per field; fields do not
+ * interact).  The derivative and B-operand tables are shared.
+ *
+ * fmm_batch_plan_create: count fields, n[i] as for fmm_plan_create, one order
+ *   p and one set of options (check_finite is not provided).  With
+ *   opt->autotune (the default) the plan times each launch-shape candidate
+ *   (bottom-kernel tile depth 16 or 8, wide or narrow M2L column groups) on
+ *   zero densities of the batch and keeps the fastest; this allocates
+ *   temporary I/O buffers for every field.  Synchronous.  NULL on error.
+ * fmm_batch_solve: rho[i], phi[i] (and g[i], if g is not NULL and g[i] is not
+ *   NULL) are device buffers of field i, laid out as for fmm_solve.  The first
+ *   call captures the launch sequence into a HIP graph on a stream of the
+ *   plan; every call launches that graph on `stream`.  The graph reads the
+ *   buffer pointers from a device table: when a call passes different
+ *   buffers than the previous one the library synchronises the device and
+ *   uploads the table first.  With profiling enabled the stages are launched
+ *   directly instead (so that their events are recorded).  fmm_solve and
+ *   fmm_solve_backward reject batch plans; fmm_batch_solve rejects single ones.
+ * fmm_batch_info: field count, the chosen bottom tile depth and M2L grouping
+ *   (0 wide, 1 narrow), and the autotuner's mean milliseconds per candidate
+ *   in the order (16, wide), (16, narrow), (8, wide), (8, narrow) for the
+ *   first ncand entries of tune_ms (zeros without autotuning).  Any pointer
+ *   may be NULL.
+ */
+fmm_plan* fmm_batch_plan_create(int count, const int* n, int p, int isolated, const fmm_options* opt);
+int fmm_batch_solve(fmm_plan* plan, const void* const* rho, void* const* phi, void* const* g, void* stream);
+int fmm_batch_info(const fmm_plan* plan, int* count, int* bottom_tile, int* m2l_grouping, double* tune_ms,
+                   int ncand);
 
 /* Device bytes owned by the plan (tables and pyramids); 0 for NULL. */
 size_t fmm_plan_workspace_bytes(const fmm_plan* plan);

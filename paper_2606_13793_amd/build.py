@@ -16,7 +16,7 @@ LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libfmm.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["fmm_api.cpp", "fmm_kernels.hip"]
+SOURCES = ["fmm_api.cpp"] + [f"fmm_p{p}.hip" for p in range(1, 9)]
 
 # Packed FP32 instructions are disabled for all device code.
 HIPFLAGS = [
@@ -49,7 +49,7 @@ def _compile(src: str) -> str:
 
 def build() -> str:
     os.makedirs(LIBDIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1, 8)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]

@@ -63,18 +63,20 @@ int validate(int n, int p, int isolated, const fmm_options* o) {
   return FMM_OK;
 }
 
-// device bytes a plan will allocate
-size_t plan_bytes(int n, int p) {
-  const int F = ilog2_exact(n) - 1;
+// device bytes a plan will allocate (tables once, grids per field)
+size_t plan_bytes(const std::vector<int>& ns, int p) {
   const int NM = fmm::nterms(p), NC = (NM + 3) / 4, NCL = NC, ND = fmm::nterms(p + 1);
   size_t b = (size_t)343 * 8 * ND * sizeof(double) + 8 * fmm::NLIST_PAD * sizeof(int) + 256;
   // FP64 matrix-core tables (the largest set a plan builds)
   b += ((size_t)21 * fmm::NSLOT * 128 + (size_t)NCL * 128 * 9 + 54 * 128) * sizeof(double);
   b += (size_t)fmm::NSLOT * fmm::conv_nfrags(fmm::CV_M2L, p, 4) * 64 * sizeof(double);
-  for (int k = 2; k <= F; ++k) {
-    const size_t nkp = (size_t)(1 << k) + 6;
-    b += (size_t)NC * nkp * nkp * nkp * 4 * sizeof(double);
-    if (k >= 3) b += ((size_t)1 << (3 * (k - 1))) * fmm::loc_stride(p) * sizeof(double);
+  for (int n : ns) {
+    const int F = ilog2_exact(n) - 1;
+    for (int k = 2; k <= F; ++k) {
+      const size_t nkp = (size_t)(1 << k) + 6;
+      b += (size_t)NC * nkp * nkp * nkp * 4 * sizeof(double);
+      if (k >= 3) b += ((size_t)1 << (3 * (k - 1))) * fmm::loc_stride(p) * sizeof(double);
+    }
   }
   return b;
 }
@@ -86,12 +88,28 @@ void release(fmm_plan* pl) {
     (void)hipEventDestroy(r.b);
   }
   for (auto ev : pl->event_pool) (void)hipEventDestroy(ev);
-  for (auto& lv : pl->lev) {
-    if (lv.M) (void)hipFree(lv.M);
-    if (lv.L) (void)hipFree(lv.L);
-  }
+  if (pl->gexec) (void)hipGraphExecDestroy(pl->gexec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+  for (auto& f : pl->fld)
+    for (auto& lv : f.lev) {
+      if (lv.M) (void)hipFree(lv.M);
+      if (lv.L) (void)hipFree(lv.L);
+    }
+  auto free_st = [](fmm::SegTable& st) {
+    if (st.dev) (void)hipFree(st.dev);
+    st = fmm::SegTable{};
+  };
+  free_st(pl->s_p2m);
+  for (auto& st : pl->s_m2m) free_st(st);
+  for (auto& st : pl->s_conv) free_st(st);
+  for (auto& st : pl->s_l2l) free_st(st);
+  for (auto& a : pl->s_bot)
+    for (auto& st : a) free_st(st);
+  for (auto& st : pl->s_m2lt) free_st(st);
+  free_st(pl->s_m2pt);
+  if (pl->io) (void)hipFree(pl->io);
   if (pl->dtab) (void)hipFree(pl->dtab);
-  if (pl->dtab32) (void)hipFree(pl->dtab32);
   if (pl->dlists) (void)hipFree(pl->dlists);
   for (int x = 0; x < 3; ++x) {
     if (pl->wm2p[x]) (void)hipFree(pl->wm2p[x]);
@@ -186,6 +204,130 @@ StageScope::StageScope(fmm_plan* pl, int stage, int launches, hipStream_t s) : p
 StageScope::~StageScope() {
   if (idx_ >= 0) (void)hipEventRecord(pl_->recs[idx_].b, s_);
 }
+
+#define FMM_BY_ORDER(P_, CALL)                 \
+  switch (P_) {                                \
+    case 1: return Impl<1>::CALL;              \
+    case 2: return Impl<2>::CALL;              \
+    case 3: return Impl<3>::CALL;              \
+    case 4: return Impl<4>::CALL;              \
+    case 5: return Impl<5>::CALL;              \
+    case 6: return Impl<6>::CALL;              \
+    case 7: return Impl<7>::CALL;              \
+    case 8: return Impl<8>::CALL;              \
+  }                                            \
+  return hipErrorInvalidValue;
+
+hipError_t upload_constants(int p) { FMM_BY_ORDER(p, upload_constants()) }
+hipError_t launch_tables(fmm_plan* pl, hipStream_t s) { FMM_BY_ORDER(pl->p, tables(pl, s)) }
+hipError_t launch_solve(fmm_plan* pl, IoArg io, hipStream_t s) { FMM_BY_ORDER(pl->p, solve(pl, io, s)) }
+hipError_t launch_backward(fmm_plan* pl, const void* dphi, const void* dg, void* drho, hipStream_t s) {
+  FMM_BY_ORDER(pl->p, backward(pl, dphi, dg, drho, s))
+}
+hipError_t launch_adjoint_tables(fmm_plan* pl, hipStream_t s) { FMM_BY_ORDER(pl->p, adjoint_tables(pl, s)) }
+hipError_t launch_check_finite(fmm_plan* pl, const void* rho, int* host_flag, hipStream_t s) {
+  FMM_BY_ORDER(pl->p, check_finite(pl, rho, host_flag, s))
+}
+hipError_t finish_locals(fmm_plan* pl, int level, hipStream_t s) { FMM_BY_ORDER(pl->p, finish_locals(pl, level, s)) }
+#undef FMM_BY_ORDER
+
+}  // namespace fmm
+
+namespace {
+
+constexpr int kConvTile = 8;  // row-grid cells per axis of a k_conv block
+constexpr int kBotTile = 8;   // level-F cells along x and y of a k_bottom block
+
+struct SegList {
+  std::vector<fmm::Seg> v;
+  long long blocks = 0;
+  void add(fmm::Seg sg, long long nb) {
+    sg.first_block = (int)blocks;
+    blocks += nb;
+    v.push_back(sg);
+  }
+};
+
+int upload_segs(fmm_plan* pl, fmm::SegTable& st, const SegList& l) {
+  st = fmm::SegTable{};
+  if (l.v.empty()) return FMM_OK;
+  if (l.blocks > 0x7fffffffLL) return fail(FMM_ERR_INVALID_ARG, "launch of %lld blocks is too large", l.blocks);
+  if (dev_alloc(pl, (void**)&st.dev, l.v.size() * sizeof(fmm::Seg))) return FMM_ERR_OUT_OF_MEMORY;
+  if (hipMemcpy(st.dev, l.v.data(), l.v.size() * sizeof(fmm::Seg), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(FMM_ERR_DEVICE, "segment upload failed");
+  st.nseg = (int)l.v.size();
+  st.blocks = (int)l.blocks;
+  return FMM_OK;
+}
+
+long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+namespace fmm {
+// Segment tables of every launch site of a solve: one launch per stage (and
+// per level for the M2M and L2L chains) covers every field of the plan.
+int build_schedule(fmm_plan* pl) {
+  const int RS = loc_stride(pl->p), klow = m2l_low_from(pl);
+  SegList p2m, m2m[16], conv[2], l2l[16], bot[2][2];
+  for (int f = 0; f < (int)pl->fld.size(); ++f) {
+    const Field& fd = pl->fld[f];
+    const int F = fd.F, nF = fd.n / 2;
+    Seg sg{};
+    sg.n = fd.n;
+    sg.field = f;
+    sg.b = (double*)fd.lev[F].M;
+    p2m.add(sg, cdiv((long long)nF * nF * nF, 256));
+    for (int k = F; k >= 3; --k) {
+      Seg m{};
+      m.n = 1 << k;
+      m.field = f;
+      m.a = (const double*)fd.lev[k].M;
+      m.b = (double*)fd.lev[k - 1].M;
+      m2m[k].add(m, cdiv(1LL << (3 * (k - 1)), 4));
+    }
+    for (int k = 3; k <= F; ++k) {
+      Seg c{};
+      c.n = 1 << (k - 1);
+      c.tpa = (int)cdiv(c.n, kConvTile);
+      c.field = f;
+      c.a = (const double*)fd.lev[k - 1].M;
+      c.b = (double*)fd.lev[k].L;
+      conv[k >= klow ? 1 : 0].add(c, (long long)c.tpa * c.tpa * c.tpa);
+    }
+    for (int k = 4; k <= F - 1; ++k) {
+      Seg l{};
+      l.n = 1 << (k - 1);
+      l.field = f;
+      l.a = (const double*)fd.lev[k - 1].L;
+      l.b = (double*)fd.lev[k].L;
+      l2l[k].add(l, cdiv((long long)l.n * l.n * l.n * RS, 256));
+    }
+    for (int z = 0; z < 2; ++z) {
+      Seg b{};
+      b.n = nF;
+      b.tpa = (int)cdiv(nF, kBotTile);
+      b.tz = (int)cdiv(nF, z == 0 ? 16 : 8);
+      b.field = f;
+      b.a = (const double*)fd.lev[F].M;
+      b.c = F >= 3 ? (const double*)fd.lev[F].L : nullptr;
+      b.d = F >= 4 ? (const double*)fd.lev[F - 1].L : nullptr;
+      bot[bottom_low(pl, F) ? 1 : 0][z].add(b, (long long)b.tpa * b.tpa * b.tz);
+    }
+  }
+  int rc;
+  if ((rc = upload_segs(pl, pl->s_p2m, p2m))) return rc;
+  for (int k = 0; k < 16; ++k) {
+    if ((rc = upload_segs(pl, pl->s_m2m[k], m2m[k]))) return rc;
+    if ((rc = upload_segs(pl, pl->s_l2l[k], l2l[k]))) return rc;
+  }
+  for (int x = 0; x < 2; ++x) {
+    if ((rc = upload_segs(pl, pl->s_conv[x], conv[x]))) return rc;
+    for (int z = 0; z < 2; ++z)
+      if ((rc = upload_segs(pl, pl->s_bot[x][z], bot[x][z]))) return rc;
+  }
+  return FMM_OK;
+}
 }  // namespace fmm
 
 extern "C" {
@@ -199,17 +341,17 @@ int fmm_options_default(fmm_options* opt) {
   opt->coarse_fp64_levels = 4;
   opt->delta_l = 1;
   opt->check_finite = 0;
+  opt->autotune = 1;
   return ok();
 }
 
-fmm_plan* fmm_plan_create(int n, int p, int isolated) { return fmm_plan_create_ex(n, p, isolated, nullptr); }
+}  // extern "C"
 
-fmm_plan* fmm_plan_create_ex(int n, int p, int isolated, const fmm_options* opt) {
-  if (validate(n, p, isolated, opt) != FMM_OK) return nullptr;
-  fmm_options o;
-  fmm_options_default(&o);
-  if (opt) o = *opt;
-  const size_t need = plan_bytes(n, p);
+namespace {
+
+// Plan for one or several fields (a batch) of the same order and precision.
+fmm_plan* create_plan(const std::vector<int>& ns, int p, const fmm_options& o, int batch) {
+  const size_t need = plan_bytes(ns, p);
   if (const char* cap = std::getenv("FMM_TEST_MAX_WORKSPACE")) {
     const unsigned long long lim = std::strtoull(cap, nullptr, 10);
     if (need > lim) {
@@ -224,7 +366,7 @@ fmm_plan* fmm_plan_create_ex(int n, int p, int isolated, const fmm_options* opt)
     fail(FMM_ERR_DEVICE, "no HIP device: %s", hipGetErrorString(e));
     return nullptr;
   }
-  if ((e = fmm::upload_constants()) != hipSuccess) {
+  if ((e = fmm::upload_constants(p)) != hipSuccess) {
     fail(FMM_ERR_DEVICE, "constant upload failed: %s", hipGetErrorString(e));
     return nullptr;
   }
@@ -233,21 +375,32 @@ fmm_plan* fmm_plan_create_ex(int n, int p, int isolated, const fmm_options* opt)
     fail(FMM_ERR_OUT_OF_MEMORY, "host allocation failed");
     return nullptr;
   }
-  pl->n = n;
   pl->p = p;
   pl->nmax = (o.nmax < 0) ? p : o.nmax;
-  pl->L = ilog2_exact(n);
-  pl->F = pl->L - 1;
   pl->precision = o.precision;
   pl->coarse_fp64_levels = o.coarse_fp64_levels;
   pl->check_finite = o.check_finite;
   pl->device = dev;
-  pl->dx = 1.0 / n;
+  pl->batch = batch;
   pl->NM = fmm::nterms(pl->nmax);
   pl->NC = (pl->NM + 3) / 4;
   pl->NL = fmm::nterms(p);
   pl->NCL = (pl->NL + 3) / 4;
   pl->ND = fmm::nterms(p + 1);
+  pl->fld.resize(ns.size());
+  for (size_t f = 0; f < ns.size(); ++f) {
+    fmm::Field& fd = pl->fld[f];
+    fd.n = ns[f];
+    fd.L = ilog2_exact(ns[f]);
+    fd.F = fd.L - 1;
+    fd.dx = 1.0 / ns[f];
+    if (fd.F > pl->maxF) pl->maxF = fd.F;
+  }
+  pl->lev = pl->fld[0].lev;
+  pl->n = pl->fld[0].n;
+  pl->L = pl->fld[0].L;
+  pl->F = pl->fld[0].F;
+  pl->dx = pl->fld[0].dx;
 
   auto bail = [&](void) -> fmm_plan* {
     release(pl);
@@ -294,25 +447,27 @@ fmm_plan* fmm_plan_create_ex(int n, int p, int isolated, const fmm_options* opt)
     }
   }
   if (dev_alloc(pl, (void**)&pl->flag, 256)) return bail();
-  for (int k = 2; k <= pl->F; ++k) {
-    fmm::Level& lv = pl->lev[k];
-    lv.k = k;
-    lv.nk = 1 << k;
-    lv.nkp = lv.nk + 6;
-    lv.ncell = 1LL << (3 * k);
-    lv.ncellp = (long long)lv.nkp * lv.nkp * lv.nkp;
-    const size_t mb = (size_t)pl->NC * lv.ncellp * 4 * sizeof(double);
-    if (dev_alloc(pl, &lv.M, mb)) return bail();
-    if (hipMemset(lv.M, 0, mb) != hipSuccess) {
-      fail(FMM_ERR_DEVICE, "hipMemset failed");
-      return bail();
-    }
-    if (k >= 3) {
-      const size_t lb = (size_t)(lv.ncell / 8) * fmm::loc_stride(p) * sizeof(double);
-      if (dev_alloc(pl, &lv.L, lb)) return bail();
-      if (hipMemset(lv.L, 0, lb) != hipSuccess) {
+  for (auto& fd : pl->fld) {
+    for (int k = 2; k <= fd.F; ++k) {
+      fmm::Level& lv = fd.lev[k];
+      lv.k = k;
+      lv.nk = 1 << k;
+      lv.nkp = lv.nk + 6;
+      lv.ncell = 1LL << (3 * k);
+      lv.ncellp = (long long)lv.nkp * lv.nkp * lv.nkp;
+      const size_t mb = (size_t)pl->NC * lv.ncellp * 4 * sizeof(double);
+      if (dev_alloc(pl, &lv.M, mb)) return bail();
+      if (hipMemset(lv.M, 0, mb) != hipSuccess) {
         fail(FMM_ERR_DEVICE, "hipMemset failed");
         return bail();
+      }
+      if (k >= 3) {
+        const size_t lb = (size_t)(lv.ncell / 8) * fmm::loc_stride(p) * sizeof(double);
+        if (dev_alloc(pl, &lv.L, lb)) return bail();
+        if (hipMemset(lv.L, 0, lb) != hipSuccess) {
+          fail(FMM_ERR_DEVICE, "hipMemset failed");
+          return bail();
+        }
       }
     }
   }
@@ -325,14 +480,211 @@ fmm_plan* fmm_plan_create_ex(int n, int p, int isolated, const fmm_options* opt)
     fail(FMM_ERR_DEVICE, "upload failed: %s", hipGetErrorString(e));
     return bail();
   }
-  if ((e = fmm::launch_dtab(pl, nullptr)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
+  if (fmm::build_schedule(pl)) return bail();
+  if ((e = fmm::launch_tables(pl, nullptr)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
     (void)hipGetLastError();
     fail(e == hipErrorOutOfMemory ? FMM_ERR_OUT_OF_MEMORY : FMM_ERR_DEVICE, "table precompute failed: %s",
          hipGetErrorString(e));
     return bail();
   }
+  if (batch) {
+    if (dev_alloc(pl, (void**)&pl->io, ns.size() * sizeof(fmm::Io))) return bail();
+    if ((e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
+      fail(FMM_ERR_DEVICE, "stream creation failed: %s", hipGetErrorString(e));
+      return bail();
+    }
+  }
   ok();
   return pl;
+}
+
+// Points the device I/O table at this call's buffers (a no-op when they are
+// the ones of the previous call).
+int set_io(fmm_plan* pl, const std::vector<fmm::Io>& io) {
+  bool same = pl->io_last.size() == io.size();
+  for (size_t i = 0; same && i < io.size(); ++i)
+    same = io[i].rho == pl->io_last[i].rho && io[i].phi == pl->io_last[i].phi && io[i].g == pl->io_last[i].g;
+  if (same) return FMM_OK;
+  hipError_t e = hipDeviceSynchronize();  // earlier calls may still read the table
+  if (e == hipSuccess) e = hipMemcpy(pl->io, io.data(), io.size() * sizeof(fmm::Io), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FMM_ERR_DEVICE, "I/O table upload failed: %s", hipGetErrorString(e));
+  }
+  pl->io_last = io;
+  return FMM_OK;
+}
+
+// Launch-shape autotuner of batch plans: every candidate (bottom tile depth,
+// M2L column grouping) solves the batch on zero densities, the fastest mean
+// of three timed solves wins.
+int autotune(fmm_plan* pl) {
+  const size_t esz = pl->precision == 0 ? sizeof(double) : sizeof(float);
+  std::vector<void*> bufs;
+  std::vector<fmm::Io> io(pl->fld.size());
+  auto cleanup = [&]() {
+    for (void* b : bufs) (void)hipFree(b);
+    pl->io_last.clear();
+  };
+  for (size_t f = 0; f < pl->fld.size(); ++f) {
+    const size_t N = (size_t)pl->fld[f].n * pl->fld[f].n * pl->fld[f].n;
+    void *r = nullptr, *ph = nullptr, *g = nullptr;
+    if (hipMalloc(&r, N * esz) != hipSuccess || hipMalloc(&ph, N * esz) != hipSuccess ||
+        hipMalloc(&g, 3 * N * esz) != hipSuccess) {
+      (void)hipGetLastError();
+      if (r) bufs.push_back(r);
+      if (ph) bufs.push_back(ph);
+      cleanup();
+      return fail(FMM_ERR_OUT_OF_MEMORY, "autotuner buffers do not fit");
+    }
+    bufs.push_back(r);
+    bufs.push_back(ph);
+    bufs.push_back(g);
+    (void)hipMemset(r, 0, N * esz);
+    io[f] = fmm::Io{r, ph, g};
+  }
+  if (int rc = set_io(pl, io)) {
+    cleanup();
+    return rc;
+  }
+  const fmm::Tuning cand[4] = {{16, 0}, {16, 1}, {8, 0}, {8, 1}};
+  hipEvent_t a = nullptr, b = nullptr;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  const fmm::IoArg arg{nullptr, nullptr, nullptr, pl->io};
+  const int prof = pl->profiling;
+  pl->profiling = 0;
+  pl->tune_ms.assign(4, 0.0);
+  double best = 1e300;
+  fmm::Tuning pick = cand[0];
+  hipError_t e = hipSuccess;
+  for (int c = 0; c < 4 && e == hipSuccess; ++c) {
+    pl->tune = cand[c];
+    e = fmm::launch_solve(pl, arg, pl->cap_stream);
+    if (e == hipSuccess) e = hipEventRecord(a, pl->cap_stream);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = fmm::launch_solve(pl, arg, pl->cap_stream);
+    if (e == hipSuccess) e = hipEventRecord(b, pl->cap_stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    pl->tune_ms[c] = ms / 3.0;
+    if (e == hipSuccess && ms / 3.0 < best) {
+      best = ms / 3.0;
+      pick = cand[c];
+    }
+  }
+  pl->profiling = prof;
+  pl->tune = pick;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  cleanup();
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FMM_ERR_DEVICE, "autotuning failed: %s", hipGetErrorString(e));
+  }
+  return FMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fmm_plan* fmm_plan_create(int n, int p, int isolated) { return fmm_plan_create_ex(n, p, isolated, nullptr); }
+
+fmm_plan* fmm_plan_create_ex(int n, int p, int isolated, const fmm_options* opt) {
+  if (validate(n, p, isolated, opt) != FMM_OK) return nullptr;
+  fmm_options o;
+  fmm_options_default(&o);
+  if (opt) o = *opt;
+  return create_plan(std::vector<int>{n}, p, o, 0);
+}
+
+fmm_plan* fmm_batch_plan_create(int count, const int* n, int p, int isolated, const fmm_options* opt) {
+  if (count < 1 || count > 4096) {
+    fail(FMM_ERR_INVALID_ARG, "count must be in [1, 4096] (got %d)", count);
+    return nullptr;
+  }
+  if (!n) {
+    fail(FMM_ERR_INVALID_ARG, "n is NULL");
+    return nullptr;
+  }
+  for (int i = 0; i < count; ++i)
+    if (validate(n[i], p, isolated, opt) != FMM_OK) return nullptr;
+  fmm_options o;
+  fmm_options_default(&o);
+  if (opt) o = *opt;
+  if (o.check_finite) {
+    fail(FMM_ERR_UNSUPPORTED, "check_finite is provided for single-field plans only");
+    return nullptr;
+  }
+  fmm_plan* pl = create_plan(std::vector<int>(n, n + count), p, o, 1);
+  if (!pl) return nullptr;
+  if (o.autotune && autotune(pl) != FMM_OK) {
+    const std::string msg = g_err;
+    const int code = g_status;
+    release(pl);
+    fail(code, "%s", msg.c_str());
+    return nullptr;
+  }
+  ok();
+  return pl;
+}
+
+int fmm_batch_solve(fmm_plan* plan, const void* const* rho, void* const* phi, void* const* g, void* stream) {
+  if (!plan) return fail(FMM_ERR_INVALID_ARG, "plan is NULL");
+  if (!plan->batch) return fail(FMM_ERR_INVALID_ARG, "not a batch plan (use fmm_solve)");
+  if (!rho || !phi) return fail(FMM_ERR_INVALID_ARG, "rho and phi must be arrays of device pointers");
+  const int cnt = (int)plan->fld.size();
+  std::vector<fmm::Io> io(cnt);
+  for (int f = 0; f < cnt; ++f) {
+    void* gf = g ? g[f] : nullptr;
+    if (!rho[f] || !phi[f]) return fail(FMM_ERR_INVALID_ARG, "field %d: rho and phi must not be NULL", f);
+    if (rho[f] == phi[f] || (gf && (gf == rho[f] || gf == phi[f])))
+      return fail(FMM_ERR_INVALID_ARG, "field %d: rho, phi and g must not alias", f);
+    io[f] = fmm::Io{rho[f], phi[f], gf};
+  }
+  if (int rc = set_io(plan, io)) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const fmm::IoArg arg{nullptr, nullptr, nullptr, plan->io};
+  hipError_t e;
+  if (plan->profiling) {
+    // direct launches, so that every stage records its events
+    fmm::StageScope whole(plan, fmm::ST_SOLVE, 0, s);
+    e = fmm::launch_solve(plan, arg, s);
+  } else {
+    if (!plan->gexec) {
+      e = hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        const hipError_t le = fmm::launch_solve(plan, arg, plan->cap_stream);
+        e = hipStreamEndCapture(plan->cap_stream, &plan->graph);
+        if (le != hipSuccess) e = le;
+      }
+      if (e == hipSuccess) e = hipGraphInstantiate(&plan->gexec, plan->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (plan->graph) (void)hipGraphDestroy(plan->graph);
+        plan->graph = nullptr;
+        plan->gexec = nullptr;
+        return fail(FMM_ERR_DEVICE, "capturing the batch graph failed: %s", hipGetErrorString(e));
+      }
+    }
+    e = hipGraphLaunch(plan->gexec, s);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FMM_ERR_DEVICE, "batch launch failed: %s", hipGetErrorString(e));
+  }
+  return ok();
+}
+
+int fmm_batch_info(const fmm_plan* plan, int* count, int* bottom_tile, int* m2l_grouping, double* tune_ms,
+                   int ncand) {
+  if (!plan) return fail(FMM_ERR_INVALID_ARG, "plan is NULL");
+  if (count) *count = (int)plan->fld.size();
+  if (bottom_tile) *bottom_tile = plan->tune.bz;
+  if (m2l_grouping) *m2l_grouping = plan->tune.grp;
+  for (int c = 0; tune_ms && c < ncand; ++c) tune_ms[c] = c < (int)plan->tune_ms.size() ? plan->tune_ms[c] : 0.0;
+  return ok();
 }
 
 void fmm_plan_destroy(fmm_plan* plan) {
@@ -359,6 +711,7 @@ int fmm_last_status(void) { return g_status; }
 
 int fmm_solve(fmm_plan* plan, const void* rho, void* phi, void* g, void* stream) {
   if (!plan) return fail(FMM_ERR_INVALID_ARG, "plan is NULL");
+  if (plan->batch) return fail(FMM_ERR_INVALID_ARG, "batch plan: use fmm_batch_solve");
   if (!rho || !phi) return fail(FMM_ERR_INVALID_ARG, "rho and phi must be device pointers (got NULL)");
   if (rho == phi || (g && (g == rho || g == phi))) return fail(FMM_ERR_INVALID_ARG, "rho, phi and g must not alias");
   hipStream_t s = (hipStream_t)stream;
@@ -370,7 +723,7 @@ int fmm_solve(fmm_plan* plan, const void* rho, void* phi, void* g, void* stream)
     if (bad) return fail(FMM_ERR_NONFINITE, "rho holds NaN or Inf");
   }
   fmm::StageScope whole(plan, fmm::ST_SOLVE, 0, s);
-  if ((e = fmm::launch_solve(plan, rho, phi, g, s)) != hipSuccess) {
+  if ((e = fmm::launch_solve(plan, fmm::IoArg{rho, phi, g, nullptr}, s)) != hipSuccess) {
     (void)hipGetLastError();
     return fail(FMM_ERR_DEVICE, "solve launch failed: %s", hipGetErrorString(e));
   }
@@ -393,6 +746,30 @@ static int ensure_adjoint(fmm_plan* pl, hipStream_t s) {
     if (dev_alloc(pl, (void**)&pl->abar[k], ab)) return FMM_ERR_OUT_OF_MEMORY;
     if (hipMemset(pl->abar[k], 0, ab) != hipSuccess) return fail(FMM_ERR_DEVICE, "hipMemset failed");
   }
+  {
+    // segment tables of the transposed convolutions: M2L^T rows are the
+    // sources of every target level, M2P^T rows the level-F cells
+    const int klow = fmm::m2l_low_from(pl);
+    SegList lt[2], pt;
+    for (int k = 3; k <= pl->F; ++k) {
+      fmm::Seg c{};
+      c.n = 1 << (k - 1);
+      c.tpa = (int)cdiv(c.n, kConvTile);
+      c.a = pl->abar[k];
+      c.b = (double*)pl->lev[k - 1].M;
+      lt[k >= klow ? 1 : 0].add(c, (long long)c.tpa * c.tpa * c.tpa);
+    }
+    fmm::Seg c{};
+    c.n = nF;
+    c.tpa = (int)cdiv(nF, kConvTile);
+    c.a = pl->ybar;
+    c.b = (double*)pl->lev[pl->F].M;
+    pt.add(c, (long long)c.tpa * c.tpa * c.tpa);
+    int rc;
+    if ((rc = upload_segs(pl, pl->s_m2lt[0], lt[0])) || (rc = upload_segs(pl, pl->s_m2lt[1], lt[1])) ||
+        (rc = upload_segs(pl, pl->s_m2pt, pt)))
+      return rc;
+  }
   if (dev_alloc(pl, (void**)&pl->adj_l2p, (size_t)pl->NL * 32 * sizeof(double))) return FMM_ERR_OUT_OF_MEMORY;
   if (dev_alloc(pl, (void**)&pl->adj_l2p2, (size_t)8 * pl->NL * 32 * sizeof(double))) return FMM_ERR_OUT_OF_MEMORY;
   hipError_t e = fmm::launch_adjoint_tables(pl, s);
@@ -408,6 +785,7 @@ static int ensure_adjoint(fmm_plan* pl, hipStream_t s) {
 
 int fmm_solve_backward(fmm_plan* plan, const void* dphi, const void* dg, void* drho, void* stream) {
   if (!plan) return fail(FMM_ERR_INVALID_ARG, "plan is NULL");
+  if (plan->batch) return fail(FMM_ERR_UNSUPPORTED, "the backward pass is provided for single-field plans");
   if (!dphi || !drho) return fail(FMM_ERR_INVALID_ARG, "dphi and drho must be device pointers (got NULL)");
   if (drho == dphi || (dg && (dg == drho || dg == dphi))) return fail(FMM_ERR_INVALID_ARG, "buffers must not alias");
   if (int rc = ensure_adjoint(plan, (hipStream_t)stream)) return rc;

@@ -1,13 +1,18 @@
-// HIP kernels of the unigrid FMM solve for MI355X (gfx950).
+// HIP kernels of the unigrid FMM solve for MI355X (gfx950), and the host code
+// that launches them.  Included once per expansion order by fmm_p<P>.hip;
+// everything but Impl<P> has internal linkage there (each translation unit
+// carries its own constant tables and kernels).
 //
 // Pass order of one solve (Sec. 2 of the paper):
 //   k_p2m            rho -> Mhat_F                       eq. (multipole)
 //   k_m2m            Mhat_k -> Mhat_{k-1}, k = F..3      eq. (M2M)
-//   k_m2l            Mhat_{k-1} -> Lam_k, k = 3..F       eq. (M2L) over the oct-shared lists
+//   k_conv (CV_M2L)  Mhat_{k-1} -> Lam_k, k = 3..F       eq. (M2L) over the oct-shared lists
 //                                                        (Sec. 2.2), all levels per launch
 //   k_l2l            Lhat_{k-1} -> Lhat_k (+=), 4..F-1   eq. (L2L)
 //   k_bottom         Mhat_F, Lhat, rho -> phi, g         M2P at the unigrid centres (Sec. 4),
 //                                                        L2P and the near field, eq. (direct)
+// Every launch spans a table of segments (grids of several levels and/or
+// fields); a block finds its segment by binary search over the first blocks.
 // The matrix-core kernels (fmm_mfma.h) are generic over FP64 / FP32 / BF16
 // operands; the upward pass and the L2L chain are FP64.
 //
@@ -16,6 +21,7 @@
 // 32-byte load and cells of a z line are contiguous.  Multipole grids carry a
 // zero halo of 3 cells per side: the clipped interaction lists of the isolated
 // boundary then need no bounds checks.
+#pragma once
 #include "fmm_internal.h"
 
 #include <cmath>
@@ -23,6 +29,7 @@
 #include <vector>
 
 namespace fmm {
+namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -39,7 +46,29 @@ __device__ __forceinline__ int mi_a(int e) { return e & 255; }
 __device__ __forceinline__ int mi_b(int e) { return (e >> 8) & 255; }
 __device__ __forceinline__ int mi_c(int e) { return (e >> 16) & 255; }
 
-hipError_t upload_constants() {
+// segment of block b: the last segment whose first block is <= b
+__device__ __forceinline__ const Seg& find_seg(const Seg* __restrict__ segs, int nseg, int b) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].first_block <= b) lo = mid; else hi = mid - 1;
+  }
+  return segs[lo];
+}
+template <typename T>
+__device__ __forceinline__ const T* io_rho(const IoArg& io, int f) {
+  return (const T*)(io.tab ? io.tab[f].rho : io.rho);
+}
+template <typename T>
+__device__ __forceinline__ T* io_phi(const IoArg& io, int f) {
+  return (T*)(io.tab ? io.tab[f].phi : io.phi);
+}
+template <typename T>
+__device__ __forceinline__ T* io_g(const IoArg& io, int f) {
+  return (T*)(io.tab ? io.tab[f].g : io.g);
+}
+
+hipError_t upload_constants_tu() {
   static bool done = false;
   if (done) return hipSuccess;
   int ex[NTMAX];
@@ -121,21 +150,21 @@ __global__ void k_dtab(double* __restrict__ out, int PD, int ND) {
   for (int i = 0; i < ND; ++i) out[(size_t)t * ND + i] = -f[i];
 }
 
-__global__ void k_to_f32(const double* __restrict__ in, float* __restrict__ out, long long count) {
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i < count) out[i] = (float)in[i];
-}
-
 // ---------------------------------------------------------------------------
 // P2M: Mhat_F[a] = sum_q rho_{2T+q} (s_q/4)^a / a!,  s_q,i = 1 - 2 q_i.
 // (-1)^(q.a) depends on a only through a mod 2, so the 8 signed sums of the
 // children are formed once (a Walsh transform) and each term is one product.
 // ---------------------------------------------------------------------------
+// Segments: n = unigrid cells per axis, field, b = Mhat_F.  256 cells T per block.
 template <typename TI>
-__global__ void k_p2m(const TI* __restrict__ rho, double* __restrict__ M, int n, int NM, int NC) {
+__global__ __launch_bounds__(256) void k_p2m(const Seg* __restrict__ segs, int nseg, IoArg io, int NM, int NC) {
+  const Seg& sg = find_seg(segs, nseg, blockIdx.x);
+  const int n = sg.n;
+  const TI* __restrict__ rho = io_rho<TI>(io, sg.field);
+  double* __restrict__ M = sg.b;
   const int nF = n >> 1, nFp = nF + 6;
   const long long nT = (long long)nF * nF * nF;
-  const long long T = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long T = (long long)(blockIdx.x - sg.first_block) * 256 + threadIdx.x;
   if (T >= nT) return;
   const int t2 = (int)(T % nF), t1 = (int)((T / nF) % nF), t0 = (int)(T / ((long long)nF * nF));
   double v[8];
@@ -177,13 +206,18 @@ __global__ void k_p2m(const TI* __restrict__ rho, double* __restrict__ M, int n,
 // g = a - b.  Block = 4 parents; the Walsh sums of the 8 children per term
 // are staged in LDS, then each thread forms terms.
 // ---------------------------------------------------------------------------
+// Segments: n = child grid cells per axis, a = Mhat_k, b = Mhat_{k-1}.
 template <int NMX>
-__global__ __launch_bounds__(256) void k_m2m(const double* __restrict__ Mc, double* __restrict__ Mp, int nk, int NM, int NC) {
+__global__ __launch_bounds__(256) void k_m2m(const Seg* __restrict__ segs, int nseg, int NM, int NC) {
   __shared__ double W[4][NMX][8];
+  const Seg& sg = find_seg(segs, nseg, blockIdx.x);
+  const double* __restrict__ Mc = sg.a;
+  double* __restrict__ Mp = sg.b;
+  const int nk = sg.n;
   const int np = nk >> 1, nkp = nk + 6, npp = np + 6;
   const long long ncp_c = (long long)nkp * nkp * nkp, ncp_p = (long long)npp * npp * npp;
   const long long nP = (long long)np * np * np;
-  const long long P0 = (long long)blockIdx.x * 4;
+  const long long P0 = (long long)(blockIdx.x - sg.first_block) * 4;
   // phase 1: Walsh sums
   for (int w = threadIdx.x; w < 4 * NM; w += blockDim.x) {
     const int pl = w / NM, b = w % NM;
@@ -296,13 +330,7 @@ __device__ __forceinline__ double l2p_parent_coef(int bt, int rp, int q, int o) 
   return base * be[dax] * mono;
 }
 
-}  // namespace fmm
-
-namespace fmm {
 #include "fmm_mfma.h"
-}  // namespace fmm
-
-namespace fmm {
 
 // ---------------------------------------------------------------------------
 // L2L, eq. (L2L), for one level k: Lhat_k[T] += shift of Lhat_{k-1}[parent(T)]
@@ -313,11 +341,16 @@ namespace fmm {
 // same length.  Lists (CSR over b): coefficient and, packed,
 // column base of b+g (column with q = 0) << 9 | ndeg(|b+g|) << 3 | parity of g.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_l2l(const double* __restrict__ Lprev, double* __restrict__ Lk,
-                                             const int* __restrict__ cs, const int* __restrict__ cidx,
-                                             const double* __restrict__ ccoef, int ns, int NL, int RS) {
+// Segments: n = cells per axis of level k - 1, a = Lhat_{k-1}, b = Lhat_k.
+__global__ __launch_bounds__(256) void k_l2l(const Seg* __restrict__ segs, int nseg, const int* __restrict__ cs,
+                                             const int* __restrict__ cidx, const double* __restrict__ ccoef, int NL,
+                                             int RS) {
+  const Seg& sg = find_seg(segs, nseg, blockIdx.x);
+  const double* __restrict__ Lprev = sg.a;
+  double* __restrict__ Lk = sg.b;
+  const int ns = sg.n;
   const long long nps = (long long)ns * ns * ns;
-  const long long id = blockIdx.x * 256LL + threadIdx.x;
+  const long long id = (long long)(blockIdx.x - sg.first_block) * 256 + threadIdx.x;
   if (id >= nps * RS) return;
   const long long P = id / RS;
   const int col = (int)(id % RS);
@@ -605,14 +638,11 @@ __global__ __launch_bounds__(ADJ_BOT_THREADS) void k_adj_bottom(const double* __
 // ---------------------------------------------------------------------------
 // launch helpers
 // ---------------------------------------------------------------------------
-static inline unsigned blocks_for(long long work, int per) { return (unsigned)((work + per - 1) / per); }
+inline unsigned blocks_for(long long work, int per) { return (unsigned)((work + per - 1) / per); }
 
-// ---------------------------------------------------------------------------
-// plan tables
-// ---------------------------------------------------------------------------
 // B fragments of one convolution (k_conv) in the compute type
 template <typename CT>
-static hipError_t build_conv_table(fmm_plan* pl, int op, void** out, hipStream_t s) {
+hipError_t build_conv_table(fmm_plan* pl, int op, void** out, hipStream_t s) {
   using M = Mf<CT>;
   constexpr int EL = 64 / M::OPM;
   const long long cnt = (long long)conv_nfrags(op, pl->p, M::KC) * NSLOT * EL * M::VPL;
@@ -625,7 +655,7 @@ static hipError_t build_conv_table(fmm_plan* pl, int op, void** out, hipStream_t
 }
 
 template <typename CT>
-static hipError_t build_tables_t(fmm_plan* pl, bool bottom, bool m2l, hipStream_t s) {
+hipError_t build_tables_t(fmm_plan* pl, bool bottom, bool m2l, hipStream_t s) {
   using M = Mf<CT>;
   using H = typename M::H;
   constexpr int KC = M::KC, OPM = M::OPM, VPL = M::VPL, EL = 64 / OPM, KT = 4 * VPL, X = M::IDX;
@@ -650,177 +680,127 @@ static hipError_t build_tables_t(fmm_plan* pl, bool bottom, bool m2l, hipStream_
   return hipSuccess;
 }
 
-// Which levels run in which compute type: FP64 plans everything in FP64;
-// mixed plans keep M2L targets k <= coarse_fp64_levels (and the bottom when
-// F <= coarse_fp64_levels) in FP64.
-static bool bottom_low(const fmm_plan* pl) { return pl->precision != 0 && pl->F > pl->coarse_fp64_levels; }
-static int m2l_low_from(const fmm_plan* pl) {
-  return pl->precision == 0 ? pl->F + 1 : (pl->coarse_fp64_levels + 1 > 3 ? pl->coarse_fp64_levels + 1 : 3);
-}
-
-hipError_t launch_dtab(fmm_plan* pl, hipStream_t s) {
+// every launch site's compute type: levels k < m2l_low_from and bottoms of
+// fields with F <= coarse_fp64_levels run in FP64
+hipError_t tables_all(fmm_plan* pl, hipStream_t s) {
   hipLaunchKernelGGL(k_dtab, dim3(blocks_for(343 * 8, 64)), dim3(64), 0, s, pl->dtab, pl->p + 1, pl->ND);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const bool need64_m2l = 3 < m2l_low_from(pl) && pl->F >= 3;
-  const bool need_low_m2l = pl->precision != 0 && m2l_low_from(pl) <= pl->F;
-  if ((e = build_tables_t<double>(pl, !bottom_low(pl), need64_m2l, s)) != hipSuccess) return e;
-  if (pl->precision == 1) e = build_tables_t<float>(pl, bottom_low(pl), need_low_m2l, s);
-  if (pl->precision == 2) e = build_tables_t<bf16_tag>(pl, bottom_low(pl), need_low_m2l, s);
+  const bool m2l64 = pl->s_conv[0].nseg > 0, m2llow = pl->s_conv[1].nseg > 0;
+  const bool bot64 = pl->s_bot[0][0].nseg > 0, botlow = pl->s_bot[1][0].nseg > 0;
+  if ((e = build_tables_t<double>(pl, bot64, m2l64, s)) != hipSuccess) return e;
+  if (pl->precision == 1) e = build_tables_t<float>(pl, botlow, m2llow, s);
+  if (pl->precision == 2) e = build_tables_t<bf16_tag>(pl, botlow, m2llow, s);
   return e;
 }
 
-template <int P, typename CT, int OP, int G>
-static hipError_t launch_conv_groups(const M2LLevels& lv, const void* W, const int* dlists, hipStream_t s) {
-  using B = M2LBudget<CT>;
+template <int P, typename CT, int OP, int V, int G>
+hipError_t launch_conv_groups(const SegTable& st, const void* W, const int* dlists, hipStream_t s) {
+  using B = M2LBudget<CT, V>;
   constexpr int KC = Mf<CT>::KC;
   if constexpr (G >= conv_ngroups(OP, P, KC, B::MAXT, B::MAXB)) {
     return hipSuccess;
   } else {
     constexpr int T0 = conv_group_start(OP, P, G, KC, B::MAXT, B::MAXB);
     constexpr int T1 = conv_group_end(OP, P, T0, KC, B::MAXT, B::MAXB);
-    hipLaunchKernelGGL((k_conv<P, CT, OP, T0, T1 - T0>), dim3(lv.first_block[lv.nlev]), dim3(M2L_THREADS), 0, s, lv,
+    hipLaunchKernelGGL((k_conv<P, CT, OP, T0, T1 - T0>), dim3(st.blocks), dim3(M2L_THREADS), 0, s, st.dev, st.nseg,
                        (const typename Mf<CT>::H*)W, dlists);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_conv_groups<P, CT, OP, G + 1>(lv, W, dlists, s);
+    return launch_conv_groups<P, CT, OP, V, G + 1>(st, W, dlists, s);
   }
 }
 
-// row-grid bookkeeping of a multi-level convolution launch
-static void add_conv_level(M2LLevels& lv, int ns, const double* src, double* dst) {
-  const int li = lv.nlev++;
-  if (li == 0) lv.first_block[0] = 0;
-  lv.ns[li] = ns;
-  lv.tiles_per_axis[li] = (ns + LX - 1) / LX;
-  lv.src[li] = src;
-  lv.dst[li] = dst;
-  const int tpa = lv.tiles_per_axis[li];
-  lv.first_block[li + 1] = lv.first_block[li] + tpa * tpa * tpa;
+template <int P, typename CT, int OP>
+hipError_t launch_conv(fmm_plan* pl, const SegTable& st, const void* W, hipStream_t s) {
+  if (!st.nseg) return hipSuccess;
+  if (OP == CV_M2L && pl->tune.grp == 1) {
+    StageScope sc(pl, ST_M2L, conv_ngroups(OP, P, Mf<CT>::KC, M2LBudget<CT, 1>::MAXT, M2LBudget<CT, 1>::MAXB), s);
+    return launch_conv_groups<P, CT, OP, 1, 0>(st, W, pl->dlists, s);
+  }
+  StageScope sc(pl, ST_M2L, conv_ngroups(OP, P, Mf<CT>::KC, M2LBudget<CT, 0>::MAXT, M2LBudget<CT, 0>::MAXB), s);
+  return launch_conv_groups<P, CT, OP, 0, 0>(st, W, pl->dlists, s);
 }
 
-// M2L of target levels k_lo..k_hi (sources at k - 1) in one launch per group
-template <int P, typename CT>
-static hipError_t launch_m2l(fmm_plan* pl, int k_lo, int k_hi, hipStream_t s) {
-  if (k_lo > k_hi) return hipSuccess;
-  M2LLevels lv{};
-  for (int k = k_lo; k <= k_hi; ++k)
-    add_conv_level(lv, 1 << (k - 1), (const double*)pl->lev[k - 1].M, (double*)pl->lev[k].L);
-  using B = M2LBudget<CT>;
-  StageScope sc(pl, ST_M2L, conv_ngroups(CV_M2L, P, Mf<CT>::KC, B::MAXT, B::MAXB), s);
-  return launch_conv_groups<P, CT, CV_M2L, 0>(lv, pl->wm2l[Mf<CT>::IDX], pl->dlists, s);
-}
-
-// L2L for one level k (Lhat_k += shift of Lhat_{k-1}), in place
-static hipError_t launch_l2l(fmm_plan* pl, int k, hipStream_t s) {
-  const int ns = 1 << (k - 1), RS = loc_stride(pl->p);
-  const long long work = (long long)ns * ns * ns * RS;
-  hipLaunchKernelGGL(k_l2l, dim3(blocks_for(work, 256)), dim3(256), 0, s, (const double*)pl->lev[k - 1].L,
-                     (double*)pl->lev[k].L, pl->l2l_start, pl->l2l_idx, pl->l2l_coef, ns, pl->NL, RS);
+hipError_t launch_l2l_site(fmm_plan* pl, const SegTable& st, hipStream_t s) {
+  if (!st.nseg) return hipSuccess;
+  hipLaunchKernelGGL(k_l2l, dim3(st.blocks), dim3(256), 0, s, st.dev, st.nseg, pl->l2l_start, pl->l2l_idx,
+                     pl->l2l_coef, pl->NL, loc_stride(pl->p));
   return hipGetLastError();
 }
 
-hipError_t finish_locals(fmm_plan* pl, int level, hipStream_t s) {
-  if (level >= 4 && level == pl->F) return launch_l2l(pl, level, s);
-  return hipSuccess;
-}
-
 template <int P, typename CT, typename TI, typename TO>
-static hipError_t launch_bottom(fmm_plan* pl, const TI* rho, TO* phi, TO* g, hipStream_t s) {
+hipError_t launch_bottom(fmm_plan* pl, int x, IoArg io, hipStream_t s) {
   using H = typename Mf<CT>::H;
   constexpr int X = Mf<CT>::IDX;
-  const int n = pl->n, F = pl->F, nF = n / 2;
-  const double dx = pl->dx;
-  const double* Lf = (F >= 3) ? (const double*)pl->lev[F].L : nullptr;
-  const double* Lpar = (F >= 4) ? (const double*)pl->lev[F - 1].L : nullptr;
-  dim3 bgrid(blocks_for(nF, BX), blocks_for(nF, BY), blocks_for(nF, BZ));
+  const int z = pl->tune.bz == 8 ? 1 : 0;
+  const SegTable& st = pl->s_bot[x][z];
+  if (!st.nseg) return hipSuccess;
   StageScope sc(pl, ST_BOTTOM, 1, s);
-  hipLaunchKernelGGL((k_bottom<P, CT, TI, TO>), bgrid, dim3(BOT_THREADS), 0, s, (const double*)pl->lev[F].M, Lf, Lpar,
-                     rho, (const H*)pl->wm2p[X], (const H*)pl->wl2p[X], (const H*)pl->wl2p2[X], (const H*)pl->wp2p[X],
-                     pl->dlists, phi, g, nF, 0.5 * dx * dx, -0.25 * dx);
+  if (z == 0)
+    hipLaunchKernelGGL((k_bottom<P, CT, TI, TO, 16>), dim3(st.blocks), dim3(BOT_THREADS), 0, s, st.dev, st.nseg, io,
+                       (const H*)pl->wm2p[X], (const H*)pl->wl2p[X], (const H*)pl->wl2p2[X], (const H*)pl->wp2p[X],
+                       pl->dlists);
+  else
+    hipLaunchKernelGGL((k_bottom<P, CT, TI, TO, 8>), dim3(st.blocks), dim3(BOT_THREADS), 0, s, st.dev, st.nseg, io,
+                       (const H*)pl->wm2p[X], (const H*)pl->wl2p[X], (const H*)pl->wl2p2[X], (const H*)pl->wp2p[X],
+                       pl->dlists);
   return hipGetLastError();
 }
 
-// One solve.  CT is the compute type of the fine levels (double for FP64 plans).
+// One solve of every field of the plan.  CT is the compute type of the fine
+// levels (double for FP64 plans).
 template <int P, typename CT, typename TI, typename TO>
-static hipError_t solve_p(fmm_plan* pl, const TI* rho, TO* phi, TO* g, hipStream_t s) {
+hipError_t solve_ct(fmm_plan* pl, IoArg io, hipStream_t s) {
   constexpr int NM = nterms(P), NC = (NM + 3) / 4;
-  const int n = pl->n, F = pl->F;
   hipError_t e;
   {
     StageScope sc(pl, ST_P2M, 1, s);
-    const long long nT = (long long)(n / 2) * (n / 2) * (n / 2);
-    hipLaunchKernelGGL((k_p2m<TI>), dim3(blocks_for(nT, 256)), dim3(256), 0, s, rho, (double*)pl->lev[F].M, n, NM, NC);
+    hipLaunchKernelGGL((k_p2m<TI>), dim3(pl->s_p2m.blocks), dim3(256), 0, s, pl->s_p2m.dev, pl->s_p2m.nseg, io, NM, NC);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  for (int k = F; k >= 3; --k) {
+  for (int k = pl->maxF; k >= 3; --k) {
+    const SegTable& st = pl->s_m2m[k];
+    if (!st.nseg) continue;
     StageScope sc(pl, ST_M2M, 1, s);
-    const long long nP = 1LL << (3 * (k - 1));
-    hipLaunchKernelGGL((k_m2m<nterms(PMAX)>), dim3(blocks_for(nP, 4)), dim3(256), 0, s, (const double*)pl->lev[k].M,
-                       (double*)pl->lev[k - 1].M, 1 << k, NM, NC);
+    hipLaunchKernelGGL((k_m2m<nterms(PMAX)>), dim3(st.blocks), dim3(256), 0, s, st.dev, st.nseg, NM, NC);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if (F >= 3) {
-    const int klow = m2l_low_from(pl);
-    if ((e = launch_m2l<P, double>(pl, 3, (klow - 1 < F ? klow - 1 : F), s)) != hipSuccess) return e;
-    if constexpr (!std::is_same<CT, double>::value)
-      if ((e = launch_m2l<P, CT>(pl, klow, F, s)) != hipSuccess) return e;
-    // L2L down to level F - 1; level F's far field is taken from Lhat_{F-1}
-    // directly by the bottom kernel
-    StageScope sc(pl, ST_L2L, F - 4 > 0 ? F - 4 : 0, s);
-    for (int k = 4; k <= F - 1; ++k)
-      if ((e = launch_l2l(pl, k, s)) != hipSuccess) return e;
+  if ((e = launch_conv<P, double, CV_M2L>(pl, pl->s_conv[0], pl->wm2l[0], s)) != hipSuccess) return e;
+  if constexpr (!std::is_same<CT, double>::value)
+    if ((e = launch_conv<P, CT, CV_M2L>(pl, pl->s_conv[1], pl->wm2l[Mf<CT>::IDX], s)) != hipSuccess) return e;
+  // L2L down to level F - 1 of each field; level F's far field is taken from
+  // Lhat_{F-1} directly by the bottom kernel
+  for (int k = 4; k <= pl->maxF - 1; ++k) {
+    StageScope sc(pl, ST_L2L, pl->s_l2l[k].nseg ? 1 : 0, s);
+    if ((e = launch_l2l_site(pl, pl->s_l2l[k], s)) != hipSuccess) return e;
   }
-  if (bottom_low(pl)) return launch_bottom<P, CT, TI, TO>(pl, rho, phi, g, s);
-  return launch_bottom<P, double, TI, TO>(pl, rho, phi, g, s);
-}
-
-template <typename CT, typename TI, typename TO>
-static hipError_t dispatch_p(fmm_plan* pl, const TI* rho, TO* phi, TO* g, hipStream_t s) {
-  switch (pl->p) {
-    case 1: return solve_p<1, CT>(pl, rho, phi, g, s);
-    case 2: return solve_p<2, CT>(pl, rho, phi, g, s);
-    case 3: return solve_p<3, CT>(pl, rho, phi, g, s);
-    case 4: return solve_p<4, CT>(pl, rho, phi, g, s);
-    case 5: return solve_p<5, CT>(pl, rho, phi, g, s);
-    case 6: return solve_p<6, CT>(pl, rho, phi, g, s);
-    case 7: return solve_p<7, CT>(pl, rho, phi, g, s);
-    case 8: return solve_p<8, CT>(pl, rho, phi, g, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_solve(fmm_plan* pl, const void* rho, void* phi, void* g, hipStream_t s) {
-  switch (pl->precision) {
-    case 0: return dispatch_p<double>(pl, (const double*)rho, (double*)phi, (double*)g, s);
-    case 1: return dispatch_p<float>(pl, (const float*)rho, (float*)phi, (float*)g, s);
-    case 2: return dispatch_p<bf16_tag>(pl, (const float*)rho, (float*)phi, (float*)g, s);
-  }
-  return hipErrorInvalidValue;
+  if ((e = launch_bottom<P, double, TI, TO>(pl, 0, io, s)) != hipSuccess) return e;
+  if constexpr (!std::is_same<CT, double>::value)
+    if ((e = launch_bottom<P, CT, TI, TO>(pl, 1, io, s)) != hipSuccess) return e;
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
-// adjoint solve
+// adjoint solve (field 0)
 // ---------------------------------------------------------------------------
-hipError_t launch_adjoint_tables(fmm_plan* pl, hipStream_t s) {
+hipError_t adjoint_tables_all(fmm_plan* pl, hipStream_t s) {
   hipError_t e;
   const int NL = pl->NL;
   hipLaunchKernelGGL(k_adj_coef, dim3(blocks_for(9LL * NL * 32, 256)), dim3(256), 0, s, pl->adj_l2p, pl->adj_l2p2, NL);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int klow = m2l_low_from(pl);
-  const bool m2l64 = pl->F >= 3 && klow > 3, m2llow = pl->F >= 3 && pl->precision != 0 && klow <= pl->F;
-  if (m2l64 && (e = build_conv_table<double>(pl, CV_M2LT, &pl->wt_m2l[0], s)) != hipSuccess) return e;
-  if (m2llow) {
+  if (pl->s_m2lt[0].nseg && (e = build_conv_table<double>(pl, CV_M2LT, &pl->wt_m2l[0], s)) != hipSuccess) return e;
+  if (pl->s_m2lt[1].nseg) {
     if (pl->precision == 1 && (e = build_conv_table<float>(pl, CV_M2LT, &pl->wt_m2l[1], s)) != hipSuccess) return e;
     if (pl->precision == 2 && (e = build_conv_table<bf16_tag>(pl, CV_M2LT, &pl->wt_m2l[2], s)) != hipSuccess) return e;
   }
-  if (!bottom_low(pl)) return build_conv_table<double>(pl, CV_M2PT, &pl->wt_m2p[0], s);
+  if (!bottom_low(pl, pl->F)) return build_conv_table<double>(pl, CV_M2PT, &pl->wt_m2p[0], s);
   if (pl->precision == 1) return build_conv_table<float>(pl, CV_M2PT, &pl->wt_m2p[1], s);
   return build_conv_table<bf16_tag>(pl, CV_M2PT, &pl->wt_m2p[2], s);
 }
 
 template <int P, typename CT, typename TI, typename TO>
-static hipError_t backward_p(fmm_plan* pl, const TI* dphi, const TI* dg, TO* drho, hipStream_t s) {
+hipError_t backward_ct(fmm_plan* pl, const TI* dphi, const TI* dg, TO* drho, hipStream_t s) {
   constexpr int NM = nterms(P), NL = nterms(P);
   const int n = pl->n, F = pl->F, nF = n / 2;
   const double dx = pl->dx;
@@ -843,32 +823,16 @@ static hipError_t backward_p(fmm_plan* pl, const TI* dphi, const TI* dg, TO* drh
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     // transposed M2L of every target level (sources k - 1 receive)
-    const int klow = m2l_low_from(pl);
-    {
-      M2LLevels lv{};
-      for (int k = 3; k <= F && k < klow; ++k)
-        add_conv_level(lv, 1 << (k - 1), pl->abar[k], (double*)pl->lev[k - 1].M);
-      if (lv.nlev && (e = launch_conv_groups<P, double, CV_M2LT, 0>(lv, pl->wt_m2l[0], pl->dlists, s)) != hipSuccess)
-        return e;
-    }
-    if constexpr (!std::is_same<CT, double>::value) {
-      M2LLevels lv{};
-      for (int k = klow; k <= F; ++k) add_conv_level(lv, 1 << (k - 1), pl->abar[k], (double*)pl->lev[k - 1].M);
-      if (lv.nlev &&
-          (e = launch_conv_groups<P, CT, CV_M2LT, 0>(lv, pl->wt_m2l[Mf<CT>::IDX], pl->dlists, s)) != hipSuccess)
-        return e;
-    }
+    if ((e = launch_conv<P, double, CV_M2LT>(pl, pl->s_m2lt[0], pl->wt_m2l[0], s)) != hipSuccess) return e;
+    if constexpr (!std::is_same<CT, double>::value)
+      if ((e = launch_conv<P, CT, CV_M2LT>(pl, pl->s_m2lt[1], pl->wt_m2l[Mf<CT>::IDX], s)) != hipSuccess) return e;
   }
   // transposed M2P at the finest level
-  {
-    M2LLevels lv{};
-    add_conv_level(lv, nF, pl->ybar, (double*)pl->lev[F].M);
-    if (bottom_low(pl))
-      e = launch_conv_groups<P, CT, CV_M2PT, 0>(lv, pl->wt_m2p[Mf<CT>::IDX], pl->dlists, s);
-    else
-      e = launch_conv_groups<P, double, CV_M2PT, 0>(lv, pl->wt_m2p[0], pl->dlists, s);
-    if (e != hipSuccess) return e;
-  }
+  if (bottom_low(pl, F))
+    e = launch_conv<P, CT, CV_M2PT>(pl, pl->s_m2pt, pl->wt_m2p[Mf<CT>::IDX], s);
+  else
+    e = launch_conv<P, double, CV_M2PT>(pl, pl->s_m2pt, pl->wt_m2p[0], s);
+  if (e != hipSuccess) return e;
   // transposed M2M chain, coarse to fine
   for (int k = 3; k <= F; ++k) {
     const int np = 1 << (k - 1);
@@ -882,37 +846,78 @@ static hipError_t backward_p(fmm_plan* pl, const TI* dphi, const TI* dg, TO* drh
   return hipGetLastError();
 }
 
-template <typename CT, typename TI, typename TO>
-static hipError_t dispatch_bwd(fmm_plan* pl, const TI* dphi, const TI* dg, TO* drho, hipStream_t s) {
-  switch (pl->p) {
-    case 1: return backward_p<1, CT>(pl, dphi, dg, drho, s);
-    case 2: return backward_p<2, CT>(pl, dphi, dg, drho, s);
-    case 3: return backward_p<3, CT>(pl, dphi, dg, drho, s);
-    case 4: return backward_p<4, CT>(pl, dphi, dg, drho, s);
-    case 5: return backward_p<5, CT>(pl, dphi, dg, drho, s);
-    case 6: return backward_p<6, CT>(pl, dphi, dg, drho, s);
-    case 7: return backward_p<7, CT>(pl, dphi, dg, drho, s);
-    case 8: return backward_p<8, CT>(pl, dphi, dg, drho, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_backward(fmm_plan* pl, const void* dphi, const void* dg, void* drho, hipStream_t s) {
-  switch (pl->precision) {
-    case 0: return dispatch_bwd<double>(pl, (const double*)dphi, (const double*)dg, (double*)drho, s);
-    case 1: return dispatch_bwd<float>(pl, (const float*)dphi, (const float*)dg, (float*)drho, s);
-    case 2: return dispatch_bwd<bf16_tag>(pl, (const float*)dphi, (const float*)dg, (float*)drho, s);
-  }
-  return hipErrorInvalidValue;
-}
-
 template <typename T>
 __global__ void k_check_finite(const T* __restrict__ x, long long count, int* flag) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (i < count && !isfinite((double)x[i])) atomicOr(flag, 1);
 }
 
-hipError_t launch_check_finite(fmm_plan* pl, const void* rho, int* host_flag, hipStream_t s) {
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// the order's entry points
+// ---------------------------------------------------------------------------
+template <int P>
+hipError_t Impl<P>::upload_constants() {
+  return upload_constants_tu();
+}
+
+template <int P>
+hipError_t Impl<P>::tables(fmm_plan* pl, hipStream_t s) {
+  return tables_all(pl, s);
+}
+
+template <int P>
+hipError_t Impl<P>::solve(fmm_plan* pl, IoArg io, hipStream_t s) {
+  switch (pl->precision) {
+    case 0: return solve_ct<P, double, double, double>(pl, io, s);
+    case 1: return solve_ct<P, float, float, float>(pl, io, s);
+    case 2: return solve_ct<P, bf16_tag, float, float>(pl, io, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int P>
+hipError_t Impl<P>::backward(fmm_plan* pl, const void* dphi, const void* dg, void* drho, hipStream_t s) {
+  switch (pl->precision) {
+    case 0: return backward_ct<P, double>(pl, (const double*)dphi, (const double*)dg, (double*)drho, s);
+    case 1: return backward_ct<P, float>(pl, (const float*)dphi, (const float*)dg, (float*)drho, s);
+    case 2: return backward_ct<P, bf16_tag>(pl, (const float*)dphi, (const float*)dg, (float*)drho, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int P>
+hipError_t Impl<P>::adjoint_tables(fmm_plan* pl, hipStream_t s) {
+  return adjoint_tables_all(pl, s);
+}
+
+// L2L into the finest level of field 0 (the solve leaves Lam_F without it)
+template <int P>
+hipError_t Impl<P>::finish_locals(fmm_plan* pl, int level, hipStream_t s) {
+  if (level < 4 || level != pl->F) return hipSuccess;
+  Seg sg{};
+  sg.first_block = 0;
+  sg.n = 1 << (level - 1);
+  sg.a = (const double*)pl->lev[level - 1].L;
+  sg.b = (double*)pl->lev[level].L;
+  Seg* dev = nullptr;
+  hipError_t e = hipMalloc(&dev, sizeof(Seg));
+  if (e != hipSuccess) return e;
+  if ((e = hipMemcpy(dev, &sg, sizeof(Seg), hipMemcpyHostToDevice)) == hipSuccess) {
+    SegTable st;
+    st.dev = dev;
+    st.nseg = 1;
+    st.blocks = (int)blocks_for((long long)sg.n * sg.n * sg.n * loc_stride(P), 256);
+    e = launch_l2l_site(pl, st, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
+  (void)hipFree(dev);
+  return e;
+}
+
+template <int P>
+hipError_t Impl<P>::check_finite(fmm_plan* pl, const void* rho, int* host_flag, hipStream_t s) {
   const long long N = (long long)pl->n * pl->n * pl->n;
   hipError_t e = hipMemsetAsync(pl->flag, 0, sizeof(int), s);
   if (e != hipSuccess) return e;

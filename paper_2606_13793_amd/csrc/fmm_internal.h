@@ -144,8 +144,56 @@ struct Level {
   // column order: L[P][m2l_col(q, b)] = Lhat of child 2P + q, term b;
   // row stride loc_stride(p)
   void* L = nullptr;
-  int m_fp64 = 1;     // 1: multipoles stored in double, 0: float
-  int l_fp64 = 1;
+};
+
+// one density field of a plan (a single-field plan has one)
+struct Field {
+  int n = 0, L = 0, F = 0;  // unigrid cells per axis, log2 n, finest FMM level L - 1
+  double dx = 0.0;
+  Level lev[16];
+};
+
+// I/O buffers of one field for one call
+struct Io {
+  const void* rho;
+  void* phi;
+  void* g;
+};
+// I/O as a kernel argument: a single field passes its buffers directly, a
+// batch points at a device table indexed by field
+struct IoArg {
+  const void* rho;
+  void* phi;
+  void* g;
+  const Io* tab;
+};
+
+// One segment of a launch that spans several grids (levels and/or fields):
+// blocks [first_block, next segment's first_block) work on this grid.  The
+// fields' meaning depends on the kernel (see each kernel).
+struct Seg {
+  int first_block;
+  int n;      // grid cells per axis
+  int tpa;    // tiles per axis (x and y)
+  int field;  // index into the I/O table
+  int tz;     // tiles along z
+  int pad_;
+  const double* a;
+  double* b;
+  const double* c;
+  const double* d;
+};
+// a segment table in device memory, plus its launch size
+struct SegTable {
+  Seg* dev = nullptr;
+  int nseg = 0;
+  int blocks = 0;
+};
+
+// launch-shape choices picked by the batch autotuner
+struct Tuning {
+  int bz = 16;   // bottom tile depth (8 or 16 level-F cells)
+  int grp = 0;   // M2L column grouping: 0 wide groups, 1 narrow groups
 };
 
 }  // namespace fmm
@@ -160,16 +208,17 @@ struct StageRec {
 }  // namespace fmm
 
 struct fmm_plan {
-  int n = 0, p = 0, nmax = 0, L = 0, F = 0;
+  int n = 0, p = 0, nmax = 0, L = 0, F = 0;  // of field 0 (the only field of a single plan)
   int precision = 0;
   int coarse_fp64_levels = 4;
   int check_finite = 0;
   int device = 0;
   double dx = 0.0;
   int NM = 0, NC = 0, NL = 0, NCL = 0, ND = 0;
-  fmm::Level lev[16];
+  std::vector<fmm::Field> fld;  // the fields; fld[0].lev are field 0's grids
+  int maxF = 0;
+  fmm::Level* lev = nullptr;    // fld[0].lev
   double* dtab = nullptr;   // [343][8][ND] D[g](Rhat) in FP64
-  float* dtab32 = nullptr;  // FP32 copy for mixed plans
   int* dlists = nullptr;    // [8][NLIST_PAD] packed interaction offsets per parity
   // matrix-core B operands in fragment order, per compute type (index
   // 0 = FP64, 1 = FP32, 2 = BF16); only the types a plan uses are built
@@ -190,6 +239,22 @@ struct fmm_plan {
   int* l2l_idx = nullptr;       // (index of b+g) << 3 | parity pattern of g
   double* l2l_coef = nullptr;
   int* flag = nullptr;      // device scratch flag (finite check)
+  // launch schedule: segment tables of every launch site, built with the plan
+  fmm::SegTable s_p2m;
+  fmm::SegTable s_m2m[16];          // M2M into level k - 1 (index k)
+  fmm::SegTable s_conv[2];          // forward M2L: [0] FP64 levels, [1] low-precision levels
+  fmm::SegTable s_l2l[16];          // L2L into level k (index k)
+  fmm::SegTable s_bot[2][2];        // bottom [FP64 | low][tile depth 16 | 8]
+  fmm::SegTable s_m2lt[2], s_m2pt;  // adjoint convolutions (field 0)
+  // batches
+  int batch = 0;                    // nonzero for fmm_batch_plan_create plans
+  fmm::Io* io = nullptr;            // device I/O table, one entry per field
+  std::vector<fmm::Io> io_last;     // what the table holds
+  fmm::Tuning tune;
+  std::vector<double> tune_ms;      // autotuner timings (ms) of each candidate
+  hipStream_t cap_stream = nullptr; // stream the batch graph is captured on
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
   size_t bytes = 0;
   // stage profiling
   int profiling = 0;
@@ -198,17 +263,45 @@ struct fmm_plan {
 };
 
 namespace fmm {
-// kernels.hip
-hipError_t upload_constants();
-hipError_t launch_dtab(fmm_plan* pl, hipStream_t s);
-hipError_t launch_solve(fmm_plan* pl, const void* rho, void* phi, void* g, hipStream_t s);
+// Everything that depends on the expansion order lives in one translation
+// unit per order (fmm_p<P>.hip) and is reached through Impl<P>.
+template <int P>
+struct Impl {
+  static hipError_t upload_constants();
+  static hipError_t tables(fmm_plan* pl, hipStream_t s);           // derivative and B tables
+  static hipError_t solve(fmm_plan* pl, IoArg io, hipStream_t s);  // every field of the plan
+  static hipError_t backward(fmm_plan* pl, const void* dphi, const void* dg, void* drho, hipStream_t s);
+  static hipError_t adjoint_tables(fmm_plan* pl, hipStream_t s);
+  static hipError_t finish_locals(fmm_plan* pl, int level, hipStream_t s);
+  static hipError_t check_finite(fmm_plan* pl, const void* rho, int* host_flag, hipStream_t s);
+};
+extern template struct Impl<1>;
+extern template struct Impl<2>;
+extern template struct Impl<3>;
+extern template struct Impl<4>;
+extern template struct Impl<5>;
+extern template struct Impl<6>;
+extern template struct Impl<7>;
+extern template struct Impl<8>;
+
+// the order's entry points, by value of p
+hipError_t upload_constants(int p);
+hipError_t launch_tables(fmm_plan* pl, hipStream_t s);
+hipError_t launch_solve(fmm_plan* pl, IoArg io, hipStream_t s);
 hipError_t launch_backward(fmm_plan* pl, const void* dphi, const void* dg, void* drho, hipStream_t s);
-// builds the adjoint tables of a plan (the buffers are allocated by the caller)
 hipError_t launch_adjoint_tables(fmm_plan* pl, hipStream_t s);
 hipError_t launch_check_finite(fmm_plan* pl, const void* rho, int* host_flag, hipStream_t s);
-// completes the stored locals of `level` (the finest level keeps only its M2L
-// part during a solve); used before inspecting them
+// completes the stored locals of `level` of field 0 (the finest level keeps
+// only its M2L part during a solve); used before inspecting them
 hipError_t finish_locals(fmm_plan* pl, int level, hipStream_t s);
+
+// segment tables of a plan's launch sites (fields, levels and tuning known)
+int build_schedule(fmm_plan* pl);
+// which levels run in which compute type (same rule for every field)
+inline bool bottom_low(const fmm_plan* pl, int F) { return pl->precision != 0 && F > pl->coarse_fp64_levels; }
+inline int m2l_low_from(const fmm_plan* pl) {
+  return pl->precision == 0 ? 64 : (pl->coarse_fp64_levels + 1 > 3 ? pl->coarse_fp64_levels + 1 : 3);
+}
 
 // Records an event pair around a stage when the plan is profiling.
 class StageScope {

@@ -90,32 +90,55 @@ struct LaneRole {
 // polynomial evaluation), and the near field (the 216 unigrid densities of
 // the 6^3 block around the row's cell).  phi and g are written once.
 // ---------------------------------------------------------------------------
-constexpr int BX = 8, BY = 8, BZ = 16;
-constexpr int HX = BX + 6, HY = BY + 6, HZ = BZ + 6, HZ2 = HZ / 2;
-constexpr int BOT_MT = (BX / 2) * (BY / 2) * (BZ / 2) / 16;  // row tiles per wave (8)
+// Tile of a block: BX x BY x BZ level-F cells (BZ = 16 or 8); per parity
+// class a 4 x 4 x BZ2 lattice of rows, BZ2 = BZ / 2, in MT = BZ2 row tiles of
+// 16: tile m holds x = m / TPX, y = YPT (m % TPX) + i / BZ2, z = i % BZ2.
+constexpr int BX = 8, BY = 8;
+constexpr int HX = BX + 6, HY = BY + 6;
 constexpr int BOT_THREADS = 512;
 
-__device__ __forceinline__ int halo_index(int hx, int hy, int hz) {
-  return (((hx * HY + hy) * 2 + (hz & 1)) * HZ2 + (hz >> 1));
-}
+template <int BZ>
+struct BotShape {
+  static constexpr int HZ = BZ + 6, HZ2 = HZ / 2, BZ2 = BZ / 2;
+  static constexpr int MT = BZ2;             // row tiles per wave
+  static constexpr int YPT = 16 / BZ2;       // y values per tile
+  static constexpr int TPX = 4 / YPT;        // tiles per x value
+  __device__ static int halo_index(int hx, int hy, int hz) {
+    return (((hx * HY + hy) * 2 + (hz & 1)) * HZ2 + (hz >> 1));
+  }
+};
 
-template <int P, typename CT, typename TI, typename TO>
+// Segments: n = nF (level-F cells per axis), tpa = tiles along x and y,
+// tz = tiles along z, field, a = Mhat_F, c = Lam_F (or null), d = the parent
+// level's locals (or null).
+template <int P, typename CT, typename TI, typename TO, int BZ>
 __global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom(
-    const double* __restrict__ Mh, const double* __restrict__ Lf, const double* __restrict__ Lpar,
-    const TI* __restrict__ rho, const typename Mf<CT>::H* __restrict__ Wm2p,
+    const Seg* __restrict__ segs, int nseg, IoArg io, const typename Mf<CT>::H* __restrict__ Wm2p,
     const typename Mf<CT>::H* __restrict__ Wl2p, const typename Mf<CT>::H* __restrict__ Wl2p2,
-    const typename Mf<CT>::H* __restrict__ Wp2p, const int* __restrict__ dlists, TO* __restrict__ phi,
-    TO* __restrict__ g, int nF, double sphi, double sg) {
+    const typename Mf<CT>::H* __restrict__ Wp2p, const int* __restrict__ dlists) {
   using M = Mf<CT>;
   using H = typename M::H;
   using AF = typename M::AF;
   using Acc = typename M::Acc;
+  using S = BotShape<BZ>;
+  constexpr int HZ = S::HZ, HZ2 = S::HZ2, BZ2 = S::BZ2, BOT_MT = S::MT, YPT = S::YPT, TPX = S::TPX;
   constexpr int KC = M::KC, OPM = M::OPM, VPL = M::VPL, EL = 64 / OPM;
   constexpr int NM = nterms(P), NC4 = (NM + 3) / 4, NCK = (NM + KC - 1) / KC;
   constexpr int NL = nterms(P);
   constexpr int KT = 4 * VPL, NLT = (NL + KT - 1) / KT, NPT = (216 + KT - 1) / KT;
   constexpr int NGRP = (NLIST + OPM - 1) / OPM;
   __shared__ H halo[HX * HY * HZ * KC];
+  const Seg& sg = find_seg(segs, nseg, blockIdx.x);
+  const int nF = sg.n;
+  const double* __restrict__ Mh = sg.a;
+  const double* __restrict__ Lf = sg.c;
+  const double* __restrict__ Lpar = sg.d;
+  const TI* __restrict__ rho = io_rho<TI>(io, sg.field);
+  TO* __restrict__ phi = io_phi<TO>(io, sg.field);
+  TO* __restrict__ g = io_g<TO>(io, sg.field);
+  const double dxf = 0.5 / nF;  // unigrid cell size
+  const double sphi = 0.5 * dxf * dxf, sgr = -0.25 * dxf;
+  const int lb = blockIdx.x - sg.first_block;
   const int lane = threadIdx.x & 63;
   const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave = parity class (uniform)
   const int i = lane & 15, kq = lane >> 4;
@@ -123,16 +146,15 @@ __global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom(
   const int r0 = (r >> 2) & 1, r1 = (r >> 1) & 1, r2 = r & 1;
   const int nFp = nF + 6;
   const long long ncellp = (long long)nFp * nFp * nFp;
-  const int tx0 = blockIdx.x * BX, ty0 = blockIdx.y * BY, tz0 = blockIdx.z * BZ;
-  // row i of tile m: lattice (gx, gy, gz) = (m >> 1, 2 (m & 1) + (i >> 3), i & 7)
-  const int gz = i & 7, gyo = i >> 3;
+  const int tx0 = (lb / (sg.tpa * sg.tz)) * BX, ty0 = ((lb / sg.tz) % sg.tpa) * BY, tz0 = (lb % sg.tz) * BZ;
+  const int gz = i % BZ2, gyo = i / BZ2;
 
   Acc acc[BOT_MT][2];
 #pragma unroll
   for (int m = 0; m < BOT_MT; ++m) acc[m][0] = acc[m][1] = Acc{0, 0, 0, 0};
   const int* dl = dlists + r * NLIST_PAD;
   // blocks walk the (order-independent) offset sum from different starting points
-  const int rot = (int)(((blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)) * 37u) % NLIST);
+  const int rot = (int)((blockIdx.x * 37u) % NLIST);
   auto entry = [&](int pos) {
     if (pos >= NLIST) return dl[NLIST];
     pos += rot;
@@ -145,7 +167,7 @@ __global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom(
       const int hz = h % HZ, hy = (h / HZ) % HY, hx = h / (HZ * HY);
       const int px = tx0 + hx, py = ty0 + hy, pz = tz0 + hz;  // padded coordinates
       const bool in = px < nFp && py < nFp && pz < nFp;
-      H* dst = halo + halo_index(hx, hy, hz) * KC;
+      H* dst = halo + S::halo_index(hx, hy, hz) * KC;
 #pragma unroll
       for (int s4 = 0; s4 < KC / 4; ++s4) {
         const int sc = c * (KC / 4) + s4;
@@ -180,8 +202,8 @@ __global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom(
       const int zoff = (zz & 1) * HZ2 + gz + (zz >> 1);
 #pragma unroll
       for (int m = 0; m < BOT_MT; ++m) {
-        const int hx = 3 + 2 * (m >> 1) + r0 - d0;
-        const int hy = 3 + 2 * (2 * (m & 1) + gyo) + r1 - d1;
+        const int hx = 3 + 2 * (m / TPX) + r0 - d0;
+        const int hy = 3 + 2 * (YPT * (m % TPX) + gyo) + r1 - d1;
         const AF a = *reinterpret_cast<const AF*>(halo + ((hx * HY + hy) * 2 * HZ2 + zoff) * KC + lr.tic);
         acc[m][0] = M::op(a, cb0, acc[m][0]);
         acc[m][1] = M::op(a, cb1, acc[m][1]);
@@ -194,8 +216,8 @@ __global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom(
   constexpr int RS = loc_stride(P);
   // the lane's own row (A operand) of tile m and its level-F cell, clamped into the grid
   auto cell_of = [&](int m, int& c0, int& c1, int& c2) {
-    c0 = tx0 + 2 * (m >> 1) + r0;
-    c1 = ty0 + 2 * (2 * (m & 1) + gyo) + r1;
+    c0 = tx0 + 2 * (m / TPX) + r0;
+    c1 = ty0 + 2 * (YPT * (m % TPX) + gyo) + r1;
     c2 = tz0 + 2 * gz + r2;
     c0 = c0 < nF ? c0 : 0;
     c1 = c1 < nF ? c1 : 0;
@@ -260,8 +282,8 @@ __global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom(
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = M::row(v, kq);
-      const int o0 = tx0 + 2 * (m >> 1) + r0, o1 = ty0 + 2 * (2 * (m & 1) + (row >> 3)) + r1,
-                o2 = tz0 + 2 * (row & 7) + r2;
+      const int o0 = tx0 + 2 * (m / TPX) + r0, o1 = ty0 + 2 * (YPT * (m % TPX) + row / BZ2) + r1,
+                o2 = tz0 + 2 * (row % BZ2) + r2;
       if (o0 >= nF || o1 >= nF || o2 >= nF) continue;
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
@@ -273,7 +295,7 @@ __global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom(
         if (o == 0)
           phi[u] = (TO)(sphi * val);
         else if (g)
-          g[(o - 1) * N + u] = (TO)(sg * val);
+          g[(o - 1) * N + u] = (TO)(sgr * val);
       }
     }
   }
@@ -371,24 +393,17 @@ constexpr int M2L_MT = (LX / 2) * (LX / 2) * (LX / 2) / 16;  // 4 row tiles per 
 constexpr int M2L_THREADS = 512;
 constexpr int MAXLEV = 12;
 
-struct M2LLevels {
-  int nlev;
-  int first_block[MAXLEV + 1];
-  int tiles_per_axis[MAXLEV];
-  int ns[MAXLEV];             // row grid cells per axis
-  const double* src[MAXLEV];  // operand grid, chunked [NK/4][(ns+6)^3][4] with a zero margin
-  double* dst[MAXLEV];        // CV_M2L: locals [ns^3][loc_stride]; else chunked padded [NC4][(ns+6)^3][4]
-};
-
 __device__ __forceinline__ int lhalo_index(int hx, int hy, int hz) {
   return ((hx * LH + hy) * 2 + (hz & 1)) * LH2 + (hz >> 1);
 }
 
-// column-group budgets per compute type (accumulator registers, work)
-template <typename CT>
+// column-group budgets per compute type (accumulator registers, work);
+// variant 1 halves the tiles per launch (more launches, fewer registers)
+template <typename CT, int V = 0>
 struct M2LBudget {
-  static constexpr int MAXT = Mf<CT>::VPL == 8 ? 4 : (sizeof(typename Mf<CT>::Acc) == 32 ? 5 : 10);
-  static constexpr int MAXB = 24;
+  static constexpr int WIDE = Mf<CT>::VPL == 8 ? 4 : (sizeof(typename Mf<CT>::Acc) == 32 ? 5 : 10);
+  static constexpr int MAXT = V == 0 ? WIDE : (WIDE + 1) / 2;
+  static constexpr int MAXB = V == 0 ? 24 : 12;
 };
 
 // chunk count and first fragment of each tile of a launch, as compile-time
@@ -405,8 +420,12 @@ struct TileChunks {
   }
 };
 
+// Segments: n = row grid cells per axis, tpa = tiles per axis, a = operand
+// grid (chunked [NK/4][(n+6)^3][4] with a zero margin), b = output (CV_M2L:
+// locals [n^3][loc_stride]; otherwise chunked padded [NC4][(n+6)^3][4]).
 template <int P, typename CT, int OP, int T0, int NT>
-__global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(M2LLevels lv, const typename Mf<CT>::H* __restrict__ Wt,
+__global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__ segs, int nseg,
+                                                        const typename Mf<CT>::H* __restrict__ Wt,
                                                         const int* __restrict__ dlists) {
   using M = Mf<CT>;
   using H = typename M::H;
@@ -419,13 +438,12 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(M2LLevels lv, const typ
   constexpr TileChunks<OP, P, KC, T0, NT> kch{};
   constexpr int CM = kch.v[0];
   __shared__ H halo[LH * LH * LH * KC];
-  int li = 0;
-  while (li + 1 < lv.nlev && (int)blockIdx.x >= lv.first_block[li + 1]) ++li;
-  const int tb = (int)blockIdx.x - lv.first_block[li];
-  const int tpa = lv.tiles_per_axis[li];
-  const int ns = lv.ns[li], nsp = ns + 6;
-  const double* __restrict__ src = lv.src[li];
-  double* __restrict__ dst = lv.dst[li];
+  const Seg& sg = find_seg(segs, nseg, blockIdx.x);
+  const int tb = (int)blockIdx.x - sg.first_block;
+  const int tpa = sg.tpa;
+  const int ns = sg.n, nsp = ns + 6;
+  const double* __restrict__ src = sg.a;
+  double* __restrict__ dst = sg.b;
   const int tx0 = (tb / (tpa * tpa)) * LX, ty0 = ((tb / tpa) % tpa) * LX, tz0 = (tb % tpa) * LX;
   const long long ncellp = (long long)nsp * nsp * nsp;
   const int lane = threadIdx.x & 63;

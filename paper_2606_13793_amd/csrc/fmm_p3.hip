@@ -1,0 +1,4 @@
+// Kernels and launch code of the FMM solve for expansion order p = 3.
+#include "fmm_impl.h"
+
+template struct fmm::Impl<3>;

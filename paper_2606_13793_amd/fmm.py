@@ -30,6 +30,7 @@ EXPORTS = (
     "fmm_solve", "fmm_solve_backward", "fmm_plan_workspace_bytes", "fmm_plan_info",
     "fmm_last_error", "fmm_last_status", "fmm_debug_expansions", "fmm_multi_index",
     "fmm_profile_enable", "fmm_profile_read", "fmm_profile_stage_name",
+    "fmm_batch_plan_create", "fmm_batch_solve", "fmm_batch_info",
 )
 
 
@@ -41,6 +42,7 @@ class FmmOptions(ctypes.Structure):
         ("coarse_fp64_levels", ctypes.c_int),
         ("delta_l", ctypes.c_int),
         ("check_finite", ctypes.c_int),
+        ("autotune", ctypes.c_int),
     ]
 
 
@@ -83,6 +85,11 @@ def lib():
         L.fmm_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i), i]
         L.fmm_profile_stage_name.argtypes = [i]
         L.fmm_profile_stage_name.restype = ctypes.c_char_p
+        L.fmm_batch_plan_create.argtypes = [i, ctypes.POINTER(i), i, i, ctypes.POINTER(FmmOptions)]
+        L.fmm_batch_plan_create.restype = vp
+        L.fmm_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+        L.fmm_batch_info.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
+                                     ctypes.POINTER(ctypes.c_double), i]
         _lib = L
     return _lib
 
@@ -230,6 +237,100 @@ class Plan:
         _check(lib().fmm_debug_expansions(self.ptr, 0 if which == "M" else 1, level,
                                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size))
         return out
+
+
+class Batch:
+    """A batch plan (``fmm_batch_plan_create``): fields of the given sizes,
+    one order and precision, each stage one launch over every field; solves
+    replay a captured HIP graph."""
+
+    def __init__(self, sizes, p: int, precision: str = "fp32", coarse_fp64_levels: int = 4,
+                 autotune: bool = True, isolated: int = 1):
+        L = lib()
+        opt = FmmOptions()
+        L.fmm_options_default(ctypes.byref(opt))
+        opt.precision = PRECISIONS[precision]
+        opt.coarse_fp64_levels = int(coarse_fp64_levels)
+        opt.autotune = int(bool(autotune))
+        self.sizes = [int(n) for n in sizes]
+        arr = (ctypes.c_int * len(self.sizes))(*self.sizes)
+        ptr = L.fmm_batch_plan_create(len(self.sizes), arr, int(p), int(isolated), ctypes.byref(opt))
+        if not ptr:
+            raise FmmError(L.fmm_last_status(), last_error())
+        self._ptr = ptr
+        self.p, self.precision = int(p), precision
+
+    @property
+    def ptr(self) -> int:
+        if not self._ptr:
+            raise RuntimeError("plan is closed")
+        return self._ptr
+
+    @property
+    def io_dtype(self):
+        import torch
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    def info(self) -> dict:
+        c, bz, grp = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        ms = (ctypes.c_double * 4)()
+        _check(lib().fmm_batch_info(self.ptr, ctypes.byref(c), ctypes.byref(bz), ctypes.byref(grp), ms, 4))
+        return {"count": c.value, "bottom_tile": bz.value, "m2l_grouping": grp.value,
+                "tune_ms": [ms[i] for i in range(4)]}
+
+    def workspace_bytes(self) -> int:
+        return int(lib().fmm_plan_workspace_bytes(self.ptr))
+
+    def profile(self, enable: bool = True):
+        _check(lib().fmm_profile_enable(self.ptr, int(bool(enable))))
+
+    def profile_read(self) -> dict:
+        return Plan.profile_read(self)
+
+    def close(self):
+        if getattr(self, "_ptr", None):
+            lib().fmm_plan_destroy(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, t, n, comps, name):
+        import torch
+        shape = (n, n, n) if comps == 1 else (comps, n, n, n)
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+        if t.dtype != self.io_dtype:
+            raise TypeError(f"{name} must be {self.io_dtype} (got {t.dtype})")
+        if tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape {shape} (got {tuple(t.shape)})")
+
+    def solve_into(self, rhos, phis, gs=None, stream=None):
+        """Solve every field: rhos[i] -> phis[i] (and gs[i] unless gs is None)."""
+        k = len(self.sizes)
+        if len(rhos) != k or len(phis) != k or (gs is not None and len(gs) != k):
+            raise ValueError(f"expected {k} fields")
+        for i, n in enumerate(self.sizes):
+            self._check(rhos[i], n, 1, f"rho[{i}]")
+            self._check(phis[i], n, 1, f"phi[{i}]")
+            if gs is not None and gs[i] is not None:
+                self._check(gs[i], n, 3, f"g[{i}]")
+        vp = ctypes.c_void_p
+        r = (vp * k)(*[t.data_ptr() for t in rhos])
+        ph = (vp * k)(*[t.data_ptr() for t in phis])
+        g = None if gs is None else (vp * k)(*[0 if t is None else t.data_ptr() for t in gs])
+        _check(lib().fmm_batch_solve(self.ptr, r, ph, g, _stream_ptr(stream)))
+
+    def solve(self, rhos, want_g: bool = True, stream=None):
+        import torch
+        dev = rhos[0].device
+        phis = [torch.empty((n, n, n), dtype=self.io_dtype, device=dev) for n in self.sizes]
+        gs = [torch.empty((3, n, n, n), dtype=self.io_dtype, device=dev) for n in self.sizes] if want_g else None
+        self.solve_into(rhos, phis, gs, stream)
+        return phis, gs
 
 
 def _autograd_fn():

@@ -152,3 +152,24 @@ def test_binding_refuses_cpu_tensors(F):
         pytest.skip("a GPU is visible")
     with pytest.raises(F.FmmError):
         F.Plan(16, 4)
+
+
+def test_batch_arguments_rejected_before_the_device(F):
+    L = F.lib()
+    o = F.FmmOptions()
+    L.fmm_options_default(ctypes.byref(o))
+    assert o.autotune == 1
+    arr = (ctypes.c_int * 3)(32, 64, 128)
+    assert not L.fmm_batch_plan_create(0, arr, 4, 1, ctypes.byref(o))
+    assert L.fmm_last_status() == -1 and "count" in F.last_error()
+    assert not L.fmm_batch_plan_create(3, None, 4, 1, ctypes.byref(o))
+    assert L.fmm_last_status() == -1
+    bad = (ctypes.c_int * 3)(32, 48, 128)
+    assert not L.fmm_batch_plan_create(3, bad, 4, 1, ctypes.byref(o))
+    assert L.fmm_last_status() == -1 and "power of two" in F.last_error()
+    assert not L.fmm_batch_plan_create(3, arr, 4, 0, ctypes.byref(o))
+    assert L.fmm_last_status() == -2
+    assert not L.fmm_batch_plan_create(3, arr, 9, 1, ctypes.byref(o))
+    assert L.fmm_last_status() == -1
+    assert L.fmm_batch_solve(None, None, None, None, None) == -1
+    assert L.fmm_batch_info(None, None, None, None, None, 0) == -1
