@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 
 
 PROFILE = os.path.join(ROOT, "profiles", "k_bottom_256cubed_p6_fp64.md")
-KERNEL_SOURCES = ["fmm_kernels.hip", "fmm_mfma.h", "fmm_internal.h"]
+KERNEL_SOURCES = ["fmm_impl.h", "fmm_mfma.h", "fmm_internal.h"]
 
 
 def profiled_traffic(n: int, p: int, prec: str):
@@ -44,7 +44,10 @@ def profiled_traffic(n: int, p: int, prec: str):
         return None
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2606_13793_amd", "csrc", f), "rb") as fh:
+        path = os.path.join(ROOT, "paper_2606_13793_amd", "csrc", f)
+        if not os.path.exists(path):
+            return None
+        with open(path, "rb") as fh:
             h.update(fh.read())
     fields = {}
     with open(PROFILE) as fh:
@@ -74,10 +77,142 @@ def parse():
     ap.add_argument("--cpu-planes", type=int, default=16,
                     help="unigrid planes of the oracle's downward-pass sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the mixed-precision, equal-accuracy, adjoint and batch sections")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device-to-device copy of BYTES bytes (a known-size "
                          "reference dispatch for hardware byte counters)")
     return ap.parse_args()
+
+
+def _event_ms(fn, steps: int, warmup: int) -> float:
+    """Mean device milliseconds of fn() over `steps` calls on the current
+    stream (HIP events), after `warmup` untimed calls."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def _rel(a, b):
+    import numpy as np
+    a, b = np.ravel(a), np.ravel(b)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def run_extras(args, rho64, fi, fmm, costs) -> dict:
+    """The other measured rows at the same workload: mixed precision (with
+    the equal-accuracy comparison against FP64 at lower order), the adjoint,
+    and the uneven 96-field batch against a loop of single solves."""
+    import numpy as np
+    import torch
+    import oracle
+    n, P = args.n, args.p
+    N = n ** 3
+    out = {}
+    # sampled cells for errors against the FP64 oracle and the direct sum
+    cells = np.sort(np.random.default_rng(7).choice(N, 64, replace=False))
+    idx = torch.as_tensor(cells, device="cuda")
+    rho_host = rho64.cpu().numpy()
+    log("extras: direct sum at 64 sampled cells")
+    phi_d, _ = oracle.direct(rho_host, targets=cells)
+
+    def sampled(plan, rho):
+        phi = torch.empty((n, n, n), dtype=plan.io_dtype, device="cuda")
+        g = torch.empty((3, n, n, n), dtype=plan.io_dtype, device="cuda")
+        plan.solve_into(rho, phi, g)
+        torch.cuda.synchronize()
+        return phi.reshape(-1)[idx].double().cpu().numpy(), g.reshape(3, -1)[:, idx].double().cpu().numpy()
+
+    # FP64 at orders 1..P: time and truncation error against the direct sum
+    fp64 = {}
+    for q in range(1, P + 1):
+        plan = fmm.Plan(n, q, "fp64")
+        phi = torch.empty((n, n, n), dtype=torch.float64, device="cuda")
+        g = torch.empty((3, n, n, n), dtype=torch.float64, device="cuda")
+        ms = _event_ms(lambda: plan.solve_into(rho64, phi, g), 5, 2)
+        ps, _ = sampled(plan, rho64)
+        fp64[q] = {"ms_per_solve": ms, "phi_err_vs_direct": _rel(ps, phi_d)}
+        del plan, phi, g
+        log(f"extras: fp64 p={q}: {ms:.2f} ms, error vs direct {fp64[q]['phi_err_vs_direct']:.3e}")
+    out["fp64_by_order"] = fp64
+    # mixed precision at order P
+    mixed = {}
+    phi_o, g_o = oracle.solve(rho64.float().double().cpu().numpy(), P, targets=cells)
+    for prec in ("fp32", "bf16"):
+        plan = fmm.Plan(n, P, prec)
+        rho = rho64.float()
+        phi = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
+        g = torch.empty((3, n, n, n), dtype=torch.float32, device="cuda")
+        ms = _event_ms(lambda: plan.solve_into(rho, phi, g), 10, 3)
+        ps, gs = sampled(plan, rho)
+        err_d = _rel(ps, phi_d)
+        # equal accuracy: the lowest FP64 order at least as accurate
+        eq = next((q for q in range(1, P + 1) if fp64[q]["phi_err_vs_direct"] <= err_d), P)
+        mixed[prec] = {
+            "ms_per_solve": ms,
+            "cells_per_s": N / (ms * 1e-3),
+            "phi_rel_l2_vs_fp64_oracle": _rel(ps, phi_o),
+            "g_rel_l2_vs_fp64_oracle": _rel(gs, g_o),
+            "phi_err_vs_direct": err_d,
+            "equal_accuracy_fp64_order": eq,
+            "equal_accuracy_fp64_cells_per_s": N / (fp64[eq]["ms_per_solve"] * 1e-3),
+            "speedup_vs_fp64_same_order": fp64[P]["ms_per_solve"] / ms,
+            "speedup_vs_fp64_equal_accuracy": fp64[eq]["ms_per_solve"] / ms,
+        }
+        log(f"extras: {prec} p={P}: {ms:.2f} ms, err vs direct {err_d:.3e}, equal-accuracy FP64 p={eq}")
+        del plan, phi, g
+    out["mixed_precision"] = mixed
+    # adjoint at the workload
+    adj = {}
+    for prec in ("fp64", "fp32"):
+        plan = fmm.Plan(n, P, prec)
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        dphi = torch.randn((n, n, n), dtype=dt, device="cuda")
+        dg = torch.randn((3, n, n, n), dtype=dt, device="cuda")
+        plan.backward(dphi, dg)  # allocates the adjoint workspace
+        ms = _event_ms(lambda: plan.backward(dphi, dg), 5, 1)
+        adj[prec] = {"ms_per_backward": ms, "cells_per_s": N / (ms * 1e-3)}
+        log(f"extras: backward {prec}: {ms:.2f} ms")
+        del plan, dphi, dg
+    out["adjoint"] = adj
+    torch.cuda.empty_cache()
+    # the uneven batch (96 fields: 55 x 32^3, 27 x 64^3, 14 x 128^3), FP32
+    sizes = fi.batch_sizes()
+    cells_b = sum(m ** 3 for m in sizes)
+    rhos = [fi.plummer_density(m, fi.batch_field_params(f), device="cuda").float() for f, m in enumerate(sizes)]
+    batched = {"fields": len(sizes), "cells": cells_b}
+    for q in (4, 6):
+        B = fmm.Batch(sizes, q, "fp32")
+        phis = [torch.empty((m, m, m), dtype=torch.float32, device="cuda") for m in sizes]
+        gs = [torch.empty((3, m, m, m), dtype=torch.float32, device="cuda") for m in sizes]
+        ms_b = _event_ms(lambda: B.solve_into(rhos, phis, gs), 5, 2)
+        info = B.info()
+        del B
+        singles = [fmm.Plan(m, q, "fp32") for m in sizes]
+        ms_l = _event_ms(lambda: [pl.solve_into(r, ph, gg) for pl, r, ph, gg in zip(singles, rhos, phis, gs)], 3, 1)
+        del singles
+        fl = sum(costs.solve_flops(m, q)["total"] for m in sizes)
+        batched[f"p{q}"] = {
+            "ms_per_batch": ms_b,
+            "cells_per_s": cells_b / (ms_b * 1e-3),
+            "useful_tflops": fl / (ms_b * 1e-3) / 1e12,
+            "loop_of_single_solves_ms": ms_l,
+            "speedup_vs_loop": ms_l / ms_b,
+            "autotuned": {"bottom_tile": info["bottom_tile"], "m2l_grouping": info["m2l_grouping"],
+                          "candidate_ms": info["tune_ms"]},
+        }
+        log(f"extras: batch p={q}: {ms_b:.2f} ms ({cells_b / (ms_b * 1e-3):.3e} cells/s), loop {ms_l:.2f} ms")
+        torch.cuda.empty_cache()
+    out["batched"] = batched
+    return out
 
 
 def main():
@@ -204,6 +339,12 @@ def main():
         }
         log(f"parity on the slab: {parity}")
 
+    extras = {}
+    if not args.no_extras and prec == "fp64":
+        del plan, phi, g
+        torch.cuda.empty_cache()
+        extras = run_extras(args, rho64, fi, fmm, costs)
+
     out = {
         "metric": METRIC,
         "value": cells_per_s,
@@ -227,6 +368,7 @@ def main():
         "stages": stages,
         "kernels": extra,
         "parity_vs_oracle": parity,
+        **extras,
     }
     print(json.dumps(out), flush=True)
 

@@ -1,6 +1,7 @@
 // C ABI of the unigrid FMM library: argument validation, plan construction
 // and the solve entry points.  Validation happens before any HIP call, so
 // invalid arguments are reported identically with or without a device.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -107,6 +108,11 @@ void release(fmm_plan* pl) {
   for (auto& a : pl->s_bot)
     for (auto& st : a) free_st(st);
   for (auto& st : pl->s_m2lt) free_st(st);
+  for (auto& st : pl->s_red) free_st(st);
+  if (pl->conv_part) (void)hipFree(pl->conv_part);
+  for (auto& row : pl->tiletab)
+    for (auto t : row)
+      if (t) (void)hipFree(t);
   free_st(pl->s_m2pt);
   if (pl->io) (void)hipFree(pl->io);
   if (pl->dtab) (void)hipFree(pl->dtab);
@@ -291,6 +297,7 @@ int build_schedule(fmm_plan* pl) {
       c.n = 1 << (k - 1);
       c.tpa = (int)cdiv(c.n, kConvTile);
       c.field = f;
+      c.split = 1;
       c.a = (const double*)fd.lev[k - 1].M;
       c.b = (double*)fd.lev[k].L;
       conv[k >= klow ? 1 : 0].add(c, (long long)c.tpa * c.tpa * c.tpa);
@@ -315,6 +322,46 @@ int build_schedule(fmm_plan* pl) {
       bot[bottom_low(pl, F) ? 1 : 0][z].add(b, (long long)b.tpa * b.tpa * b.tz);
     }
   }
+  // Launch sites with few tiles (the coarse levels of mixed-precision plans,
+  // small grids) split each tile's offset sum over several blocks; the
+  // partial sums are added in a fixed order afterwards.
+  SegList red[2];
+  {
+    long long part_doubles = 0;
+    std::vector<long long> at[2];
+    for (int x = 0; x < 2; ++x) {
+      long long T = 0;
+      for (auto& c : conv[x].v) T += (long long)c.tpa * c.tpa * c.tpa;
+      const int S = T >= 128 ? 1 : (int)std::min<long long>(16, std::max<long long>(2, 256 / std::max<long long>(T, 1)));
+      if (S == 1 || conv[x].v.empty()) continue;
+      for (auto& c : conv[x].v) {
+        at[x].push_back(part_doubles);
+        part_doubles += (long long)S * c.n * c.n * c.n * RS;
+      }
+      // rebuild the site with the split
+      SegList sp;
+      for (auto c : conv[x].v) {
+        c.split = S;
+        sp.add(c, (long long)c.tpa * c.tpa * c.tpa * S);
+      }
+      conv[x] = sp;
+    }
+    if (part_doubles) {
+      if (dev_alloc(pl, (void**)&pl->conv_part, (size_t)part_doubles * sizeof(double))) return FMM_ERR_OUT_OF_MEMORY;
+      for (int x = 0; x < 2; ++x)
+        for (size_t i = 0; i < at[x].size(); ++i) {
+          Seg& c = conv[x].v[i];
+          Seg r{};
+          r.n = c.n;
+          r.split = c.split;
+          r.field = c.field;
+          r.a = pl->conv_part + at[x][i];
+          r.b = c.b;
+          c.b = pl->conv_part + at[x][i];
+          red[x].add(r, cdiv((long long)c.n * c.n * c.n * RS, 256));
+        }
+    }
+  }
   int rc;
   if ((rc = upload_segs(pl, pl->s_p2m, p2m))) return rc;
   for (int k = 0; k < 16; ++k) {
@@ -323,6 +370,7 @@ int build_schedule(fmm_plan* pl) {
   }
   for (int x = 0; x < 2; ++x) {
     if ((rc = upload_segs(pl, pl->s_conv[x], conv[x]))) return rc;
+    if ((rc = upload_segs(pl, pl->s_red[x], red[x]))) return rc;
     for (int z = 0; z < 2; ++z)
       if ((rc = upload_segs(pl, pl->s_bot[x][z], bot[x][z]))) return rc;
   }
@@ -755,6 +803,7 @@ static int ensure_adjoint(fmm_plan* pl, hipStream_t s) {
       fmm::Seg c{};
       c.n = 1 << (k - 1);
       c.tpa = (int)cdiv(c.n, kConvTile);
+      c.split = 1;
       c.a = pl->abar[k];
       c.b = (double*)pl->lev[k - 1].M;
       lt[k >= klow ? 1 : 0].add(c, (long long)c.tpa * c.tpa * c.tpa);
@@ -762,6 +811,7 @@ static int ensure_adjoint(fmm_plan* pl, hipStream_t s) {
     fmm::Seg c{};
     c.n = nF;
     c.tpa = (int)cdiv(nF, kConvTile);
+    c.split = 1;
     c.a = pl->ybar;
     c.b = (double*)pl->lev[pl->F].M;
     pt.add(c, (long long)c.tpa * c.tpa * c.tpa);

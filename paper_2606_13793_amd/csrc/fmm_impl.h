@@ -654,6 +654,26 @@ hipError_t build_conv_table(fmm_plan* pl, int op, void** out, hipStream_t s) {
   return hipGetLastError();
 }
 
+// (K chunks, first fragment) of each column tile of a convolution kind in
+// the compute type, zero-padded by 16 entries (a group may run past the end)
+template <typename CT>
+hipError_t build_tile_table(fmm_plan* pl, int op, hipStream_t s) {
+  constexpr int X = Mf<CT>::IDX, KC = Mf<CT>::KC;
+  if (pl->tiletab[op][X]) return hipSuccess;
+  const int nt = conv_ntiles(op, pl->p);
+  std::vector<int> h(2 * (nt + 16), 0);
+  for (int t = 0; t < nt; ++t) {
+    h[2 * t] = conv_tile_chunks(op, pl->p, t, KC);
+    h[2 * t + 1] = conv_frag_offset(op, pl->p, t, KC);
+  }
+  hipError_t e = hipMalloc(&pl->tiletab[op][X], h.size() * sizeof(int));
+  if (e != hipSuccess) return e;
+  pl->bytes += h.size() * sizeof(int);
+  return hipMemcpyAsync(pl->tiletab[op][X], h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice, s) == hipSuccess
+             ? hipStreamSynchronize(s)
+             : hipGetLastError();
+}
+
 template <typename CT>
 hipError_t build_tables_t(fmm_plan* pl, bool bottom, bool m2l, hipStream_t s) {
   using M = Mf<CT>;
@@ -676,6 +696,7 @@ hipError_t build_tables_t(fmm_plan* pl, bool bottom, bool m2l, hipStream_t s) {
   }
   if (m2l && !pl->wm2l[X]) {
     if ((e = build_conv_table<CT>(pl, CV_M2L, &pl->wm2l[X], s)) != hipSuccess) return e;
+    if ((e = build_tile_table<CT>(pl, CV_M2L, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -694,32 +715,40 @@ hipError_t tables_all(fmm_plan* pl, hipStream_t s) {
   return e;
 }
 
-template <int P, typename CT, int OP, int V, int G>
-hipError_t launch_conv_groups(const SegTable& st, const void* W, const int* dlists, hipStream_t s) {
-  using B = M2LBudget<CT, V>;
-  constexpr int KC = Mf<CT>::KC;
-  if constexpr (G >= conv_ngroups(OP, P, KC, B::MAXT, B::MAXB)) {
-    return hipSuccess;
-  } else {
-    constexpr int T0 = conv_group_start(OP, P, G, KC, B::MAXT, B::MAXB);
-    constexpr int T1 = conv_group_end(OP, P, T0, KC, B::MAXT, B::MAXB);
-    hipLaunchKernelGGL((k_conv<P, CT, OP, T0, T1 - T0>), dim3(st.blocks), dim3(M2L_THREADS), 0, s, st.dev, st.nseg,
-                       (const typename Mf<CT>::H*)W, dlists);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return launch_conv_groups<P, CT, OP, V, G + 1>(st, W, dlists, s);
-  }
+// Sums the split partial M2L results of each segment into its locals.
+// Segments: n = source cells per axis, split, a = partials, b = locals.
+__global__ __launch_bounds__(256) void k_split_reduce(const Seg* __restrict__ segs, int nseg, int RS) {
+  const Seg& sg = find_seg(segs, nseg, blockIdx.x);
+  const long long cnt = (long long)sg.n * sg.n * sg.n * RS;
+  const long long x = (long long)(blockIdx.x - sg.first_block) * 256 + threadIdx.x;
+  if (x >= cnt) return;
+  double v = 0.0;
+  for (int s = 0; s < sg.split; ++s) v += sg.a[s * cnt + x];
+  sg.b[x] = v;
 }
 
+template <int P, typename CT, int OP, int NT>
+hipError_t launch_conv_nt(fmm_plan* pl, const SegTable& st, const void* W, hipStream_t s) {
+  constexpr int G = (conv_ntiles(OP, P) + NT - 1) / NT;
+  StageScope sc(pl, ST_M2L, 1, s);
+  hipLaunchKernelGGL((k_conv<P, CT, OP, NT>), dim3((unsigned)G * st.blocks), dim3(M2L_THREADS), 0, s, st.dev, st.nseg,
+                     st.blocks, (const int2*)pl->tiletab[OP][Mf<CT>::IDX], (const typename Mf<CT>::H*)W, pl->dlists);
+  return hipGetLastError();
+}
+
+// One launch per convolution site: every column group of every segment.
 template <int P, typename CT, int OP>
 hipError_t launch_conv(fmm_plan* pl, const SegTable& st, const void* W, hipStream_t s) {
   if (!st.nseg) return hipSuccess;
-  if (OP == CV_M2L && pl->tune.grp == 1) {
-    StageScope sc(pl, ST_M2L, conv_ngroups(OP, P, Mf<CT>::KC, M2LBudget<CT, 1>::MAXT, M2LBudget<CT, 1>::MAXB), s);
-    return launch_conv_groups<P, CT, OP, 1, 0>(st, W, pl->dlists, s);
-  }
-  StageScope sc(pl, ST_M2L, conv_ngroups(OP, P, Mf<CT>::KC, M2LBudget<CT, 0>::MAXT, M2LBudget<CT, 0>::MAXB), s);
-  return launch_conv_groups<P, CT, OP, 0, 0>(st, W, pl->dlists, s);
+  if constexpr (OP == CV_M2L)
+    if (pl->tune.grp == 1) return launch_conv_nt<P, CT, OP, ConvGroup<CT, 1>::NT>(pl, st, W, s);
+  return launch_conv_nt<P, CT, OP, ConvGroup<CT, 0>::NT>(pl, st, W, s);
+}
+
+hipError_t launch_split_reduce(fmm_plan* pl, const SegTable& st, hipStream_t s) {
+  if (!st.nseg) return hipSuccess;
+  hipLaunchKernelGGL(k_split_reduce, dim3(st.blocks), dim3(256), 0, s, st.dev, st.nseg, loc_stride(pl->p));
+  return hipGetLastError();
 }
 
 hipError_t launch_l2l_site(fmm_plan* pl, const SegTable& st, hipStream_t s) {
@@ -767,8 +796,11 @@ hipError_t solve_ct(fmm_plan* pl, IoArg io, hipStream_t s) {
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if ((e = launch_conv<P, double, CV_M2L>(pl, pl->s_conv[0], pl->wm2l[0], s)) != hipSuccess) return e;
-  if constexpr (!std::is_same<CT, double>::value)
+  if ((e = launch_split_reduce(pl, pl->s_red[0], s)) != hipSuccess) return e;
+  if constexpr (!std::is_same<CT, double>::value) {
     if ((e = launch_conv<P, CT, CV_M2L>(pl, pl->s_conv[1], pl->wm2l[Mf<CT>::IDX], s)) != hipSuccess) return e;
+    if ((e = launch_split_reduce(pl, pl->s_red[1], s)) != hipSuccess) return e;
+  }
   // L2L down to level F - 1 of each field; level F's far field is taken from
   // Lhat_{F-1} directly by the bottom kernel
   for (int k = 4; k <= pl->maxF - 1; ++k) {
@@ -789,13 +821,27 @@ hipError_t adjoint_tables_all(fmm_plan* pl, hipStream_t s) {
   const int NL = pl->NL;
   hipLaunchKernelGGL(k_adj_coef, dim3(blocks_for(9LL * NL * 32, 256)), dim3(256), 0, s, pl->adj_l2p, pl->adj_l2p2, NL);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (pl->s_m2lt[0].nseg && (e = build_conv_table<double>(pl, CV_M2LT, &pl->wt_m2l[0], s)) != hipSuccess) return e;
-  if (pl->s_m2lt[1].nseg) {
-    if (pl->precision == 1 && (e = build_conv_table<float>(pl, CV_M2LT, &pl->wt_m2l[1], s)) != hipSuccess) return e;
-    if (pl->precision == 2 && (e = build_conv_table<bf16_tag>(pl, CV_M2LT, &pl->wt_m2l[2], s)) != hipSuccess) return e;
+  if (pl->s_m2lt[0].nseg) {
+    if ((e = build_conv_table<double>(pl, CV_M2LT, &pl->wt_m2l[0], s)) != hipSuccess) return e;
+    if ((e = build_tile_table<double>(pl, CV_M2LT, s)) != hipSuccess) return e;
   }
-  if (!bottom_low(pl, pl->F)) return build_conv_table<double>(pl, CV_M2PT, &pl->wt_m2p[0], s);
-  if (pl->precision == 1) return build_conv_table<float>(pl, CV_M2PT, &pl->wt_m2p[1], s);
+  if (pl->s_m2lt[1].nseg) {
+    if (pl->precision == 1 && ((e = build_conv_table<float>(pl, CV_M2LT, &pl->wt_m2l[1], s)) != hipSuccess ||
+                               (e = build_tile_table<float>(pl, CV_M2LT, s)) != hipSuccess))
+      return e;
+    if (pl->precision == 2 && ((e = build_conv_table<bf16_tag>(pl, CV_M2LT, &pl->wt_m2l[2], s)) != hipSuccess ||
+                               (e = build_tile_table<bf16_tag>(pl, CV_M2LT, s)) != hipSuccess))
+      return e;
+  }
+  if (!bottom_low(pl, pl->F)) {
+    if ((e = build_tile_table<double>(pl, CV_M2PT, s)) != hipSuccess) return e;
+    return build_conv_table<double>(pl, CV_M2PT, &pl->wt_m2p[0], s);
+  }
+  if (pl->precision == 1) {
+    if ((e = build_tile_table<float>(pl, CV_M2PT, s)) != hipSuccess) return e;
+    return build_conv_table<float>(pl, CV_M2PT, &pl->wt_m2p[1], s);
+  }
+  if ((e = build_tile_table<bf16_tag>(pl, CV_M2PT, s)) != hipSuccess) return e;
   return build_conv_table<bf16_tag>(pl, CV_M2PT, &pl->wt_m2p[2], s);
 }
 

@@ -177,7 +177,7 @@ struct Seg {
   int tpa;    // tiles per axis (x and y)
   int field;  // index into the I/O table
   int tz;     // tiles along z
-  int pad_;
+  int split;  // convolutions: blocks sharing one tile, each summing a slice of the offsets
   const double* a;
   double* b;
   const double* c;
@@ -245,7 +245,12 @@ struct fmm_plan {
   fmm::SegTable s_conv[2];          // forward M2L: [0] FP64 levels, [1] low-precision levels
   fmm::SegTable s_l2l[16];          // L2L into level k (index k)
   fmm::SegTable s_bot[2][2];        // bottom [FP64 | low][tile depth 16 | 8]
+  fmm::SegTable s_red[2];           // reductions of split forward M2L partial sums
   fmm::SegTable s_m2lt[2], s_m2pt;  // adjoint convolutions (field 0)
+  double* conv_part = nullptr;      // partial sums of split forward M2L segments
+  // per convolution kind and compute type: (K chunks, first fragment) of
+  // every column tile, zero-padded past the last tile
+  int* tiletab[3][3] = {};
   // batches
   int batch = 0;                    // nonzero for fmm_batch_plan_create plans
   fmm::Io* io = nullptr;            // device I/O table, one entry per field

@@ -397,34 +397,25 @@ __device__ __forceinline__ int lhalo_index(int hx, int hy, int hz) {
   return ((hx * LH + hy) * 2 + (hz & 1)) * LH2 + (hz >> 1);
 }
 
-// column-group budgets per compute type (accumulator registers, work);
-// variant 1 halves the tiles per launch (more launches, fewer registers)
+// tiles per column group by compute type (accumulator registers); variant 1
+// halves them
 template <typename CT, int V = 0>
-struct M2LBudget {
+struct ConvGroup {
   static constexpr int WIDE = Mf<CT>::VPL == 8 ? 4 : (sizeof(typename Mf<CT>::Acc) == 32 ? 5 : 10);
-  static constexpr int MAXT = V == 0 ? WIDE : (WIDE + 1) / 2;
-  static constexpr int MAXB = V == 0 ? 24 : 12;
+  static constexpr int NT = V == 0 ? WIDE : (WIDE + 1) / 2;
 };
 
-// chunk count and first fragment of each tile of a launch, as compile-time
-// tables (the helper functions loop and must not run on device)
-template <int OP, int P, int KC, int T0, int NT>
-struct TileChunks {
-  int v[NT];
-  int off[NT];
-  constexpr TileChunks() : v(), off() {
-    for (int t = 0; t < NT; ++t) {
-      v[t] = conv_tile_chunks(OP, P, T0 + t, KC);
-      off[t] = conv_frag_offset(OP, P, T0 + t, KC);
-    }
-  }
-};
-
-// Segments: n = row grid cells per axis, tpa = tiles per axis, a = operand
+// Segments: n = row grid cells per axis, tpa = tiles per axis, split = number
+// of blocks sharing a tile (each sums a slice of the offsets), a = operand
 // grid (chunked [NK/4][(n+6)^3][4] with a zero margin), b = output (CV_M2L:
-// locals [n^3][loc_stride]; otherwise chunked padded [NC4][(n+6)^3][4]).
-template <int P, typename CT, int OP, int T0, int NT>
-__global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__ segs, int nseg,
+// locals [n^3][loc_stride], or split partial sums [split][n^3][loc_stride];
+// otherwise chunked padded [NC4][(n+6)^3][4]).
+// Grid: ngroups x T blocks, T = the tile blocks of all segments; block b works
+// on column group b / T (the heaviest groups first) of tile block b % T.
+// tiles[t] = (K chunks, first fragment) of column tile t, zero past the last.
+template <int P, typename CT, int OP, int NT>
+__global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__ segs, int nseg, int T,
+                                                        const int2* __restrict__ tiles,
                                                         const typename Mf<CT>::H* __restrict__ Wt,
                                                         const int* __restrict__ dlists) {
   using M = Mf<CT>;
@@ -433,17 +424,29 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   using Acc = typename M::Acc;
   constexpr int KC = M::KC, OPM = M::OPM, VPL = M::VPL, EL = 64 / OPM;
   constexpr int NC4 = (conv_nk(OP, P) + 3) / 4;  // 4-term chunks of the operand grid
-  constexpr int NM = nterms(P), NCOL = 8 * nterms(P);
+  constexpr int NM = nterms(P), NCOL = 8 * nterms(P), NTILES = conv_ntiles(OP, P);
   constexpr int NGRP = (NLIST + OPM - 1) / OPM;
-  constexpr TileChunks<OP, P, KC, T0, NT> kch{};
-  constexpr int CM = kch.v[0];
   __shared__ H halo[LH * LH * LH * KC];
-  const Seg& sg = find_seg(segs, nseg, blockIdx.x);
-  const int tb = (int)blockIdx.x - sg.first_block;
+  const int grp = (int)blockIdx.x / T;
+  const int T0 = grp * NT;
+  const int lbk = (int)blockIdx.x - grp * T;
+  const Seg& sg = find_seg(segs, nseg, lbk);
+  const int split = sg.split;
+  const int tbs = lbk - sg.first_block;
+  const int tb = tbs / split, part = tbs - tb * split;
   const int tpa = sg.tpa;
   const int ns = sg.n, nsp = ns + 6;
   const double* __restrict__ src = sg.a;
   double* __restrict__ dst = sg.b;
+  int vt[NT], off[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int2 e = tiles[T0 + t];
+    vt[t] = e.x;
+    off[t] = e.y;
+  }
+  const int CM = vt[0];
+  const int j0 = part * NGRP / split, j1 = (part + 1) * NGRP / split;
   const int tx0 = (tb / (tpa * tpa)) * LX, ty0 = ((tb / tpa) % tpa) * LX, tz0 = (tb % tpa) * LX;
   const long long ncellp = (long long)nsp * nsp * nsp;
   const int lane = threadIdx.x & 63;
@@ -459,7 +462,9 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[m][t] = Acc{0, 0, 0, 0};
   const int* dl = dlists + r * NLIST_PAD;
-  const int rot = (int)((blockIdx.x * 37u) % NLIST);
+  // the rotation of the offset order must be the same for every part of a
+  // split tile (the parts take consecutive slices of one ordering)
+  const int rot = (int)(((unsigned)(sg.first_block + tb * split) * 37u) % NLIST);
   auto entry = [&](int pos) {
     if (pos >= NLIST) return dl[NLIST];
     pos += rot;
@@ -467,7 +472,7 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   };
   const H* wl = Wt + lr.tl * VPL;
   auto bload = [&](int e, int t, int c) {
-    return *reinterpret_cast<const AF*>(wl + ((size_t)(kch.off[t] + c) * NSLOT + dl_dd(e)) * EL * VPL);
+    return *reinterpret_cast<const AF*>(wl + ((size_t)(off[t] + c) * NSLOT + dl_dd(e)) * EL * VPL);
   };
 
   for (int c = 0; c < CM; ++c) {
@@ -489,16 +494,16 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
     __syncthreads();
     AF b0[NT], b1[NT];
     {
-      const int e0 = entry(lr.sel), e1 = entry(OPM + lr.sel);
+      const int e0 = entry(OPM * j0 + lr.sel), e1 = entry(OPM * (j0 + 1) + lr.sel);
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        if (c < kch.v[t]) {
+        if (c < vt[t]) {
           b0[t] = bload(e0, t, c);
           b1[t] = bload(e1, t, c);
         }
       }
     }
-    for (int j = 0; j < NGRP; ++j) {
+    for (int j = j0; j < j1; ++j) {
       const int e = entry(OPM * j + lr.sel);
       const int d0 = dl_d0(e), d1 = dl_d1(e), d2 = dl_d2(e);
       AF cb[NT];
@@ -507,11 +512,11 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
         cb[t] = b0[t];
         b0[t] = b1[t];
       }
-      if (j + 2 < NGRP) {
+      if (j + 2 < j1) {
         const int en = entry(OPM * (j + 2) + lr.sel);
 #pragma unroll
         for (int t = 0; t < NT; ++t)
-          if (c < kch.v[t]) b1[t] = bload(en, t, c);
+          if (c < vt[t]) b1[t] = bload(en, t, c);
       }
       const int zz = 3 + r2 - d2;
       const int zoff = (zz & 1) * LH2 + gz + (zz >> 1);
@@ -522,7 +527,7 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
         const AF a = *reinterpret_cast<const AF*>(halo + ((hx * LH + hy) * 2 * LH2 + zoff) * KC + lr.tic);
 #pragma unroll
         for (int t = 0; t < NT; ++t)
-          if (c < kch.v[t]) acc[m][t] = M::op(a, cb[t], acc[m][t]);
+          if (c < vt[t]) acc[m][t] = M::op(a, cb[t], acc[m][t]);
       }
     }
   }
@@ -530,6 +535,7 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   if constexpr (OP == CV_M2L) {
     // the 16 lanes of a row write 128 contiguous bytes
     constexpr int RS = loc_stride(P);
+    if (split > 1) dst += (long long)part * ns * ns * ns * RS;
     int escale[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -545,7 +551,8 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
         if (p0 >= ns || p1 >= ns || p2 >= ns) continue;
         double* o = dst + (((long long)p0 * ns + p1) * ns + p2) * RS + 16 * T0 + i;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) o[16 * t] = ldexp((double)acc[m][t][v], escale[t]);
+        for (int t = 0; t < NT; ++t)
+          if (T0 + t < NTILES) o[16 * t] = ldexp((double)acc[m][t][v], escale[t]);
       }
   } else {
 #pragma unroll
