@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed-precision, equal-accuracy, adjoint and batch sections")
+    ap.add_argument("--section", default=None, choices=["mixed", "adjoint", "batch"],
+                    help="run only this extra section (for profiling) and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device-to-device copy of BYTES bytes (a known-size "
                          "reference dispatch for hardware byte counters)")
@@ -107,7 +109,7 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def run_extras(args, rho64, fi, fmm, costs) -> dict:
+def run_extras(args, rho64, fi, fmm, costs, sections=("mixed", "adjoint", "batch")) -> dict:
     """The other measured rows at the same workload: mixed precision (with
     the equal-accuracy comparison against FP64 at lower order), the adjoint,
     and the uneven 96-field batch against a loop of single solves."""
@@ -121,8 +123,10 @@ def run_extras(args, rho64, fi, fmm, costs) -> dict:
     cells = np.sort(np.random.default_rng(7).choice(N, 64, replace=False))
     idx = torch.as_tensor(cells, device="cuda")
     rho_host = rho64.cpu().numpy()
-    log("extras: direct sum at 64 sampled cells")
-    phi_d, _ = oracle.direct(rho_host, targets=cells)
+    phi_d = None
+    if "mixed" in sections:
+        log("extras: direct sum at 64 sampled cells")
+        phi_d, _ = oracle.direct(rho_host, targets=cells)
 
     def sampled(plan, rho):
         phi = torch.empty((n, n, n), dtype=plan.io_dtype, device="cuda")
@@ -133,7 +137,7 @@ def run_extras(args, rho64, fi, fmm, costs) -> dict:
 
     # FP64 at orders 1..P: time and truncation error against the direct sum
     fp64 = {}
-    for q in range(1, P + 1):
+    for q in (range(1, P + 1) if "mixed" in sections else ()):
         plan = fmm.Plan(n, q, "fp64")
         phi = torch.empty((n, n, n), dtype=torch.float64, device="cuda")
         g = torch.empty((3, n, n, n), dtype=torch.float64, device="cuda")
@@ -142,11 +146,13 @@ def run_extras(args, rho64, fi, fmm, costs) -> dict:
         fp64[q] = {"ms_per_solve": ms, "phi_err_vs_direct": _rel(ps, phi_d)}
         del plan, phi, g
         log(f"extras: fp64 p={q}: {ms:.2f} ms, error vs direct {fp64[q]['phi_err_vs_direct']:.3e}")
-    out["fp64_by_order"] = fp64
+    if fp64:
+        out["fp64_by_order"] = fp64
     # mixed precision at order P
     mixed = {}
-    phi_o, g_o = oracle.solve(rho64.float().double().cpu().numpy(), P, targets=cells)
-    for prec in ("fp32", "bf16"):
+    if "mixed" in sections:
+        phi_o, g_o = oracle.solve(rho64.float().double().cpu().numpy(), P, targets=cells)
+    for prec in (("fp32", "bf16") if "mixed" in sections else ()):
         plan = fmm.Plan(n, P, prec)
         rho = rho64.float()
         phi = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
@@ -169,10 +175,11 @@ def run_extras(args, rho64, fi, fmm, costs) -> dict:
         }
         log(f"extras: {prec} p={P}: {ms:.2f} ms, err vs direct {err_d:.3e}, equal-accuracy FP64 p={eq}")
         del plan, phi, g
-    out["mixed_precision"] = mixed
+    if mixed:
+        out["mixed_precision"] = mixed
     # adjoint at the workload
     adj = {}
-    for prec in ("fp64", "fp32"):
+    for prec in (("fp64", "fp32") if "adjoint" in sections else ()):
         plan = fmm.Plan(n, P, prec)
         dt = torch.float64 if prec == "fp64" else torch.float32
         dphi = torch.randn((n, n, n), dtype=dt, device="cuda")
@@ -182,8 +189,11 @@ def run_extras(args, rho64, fi, fmm, costs) -> dict:
         adj[prec] = {"ms_per_backward": ms, "cells_per_s": N / (ms * 1e-3)}
         log(f"extras: backward {prec}: {ms:.2f} ms")
         del plan, dphi, dg
-    out["adjoint"] = adj
+    if adj:
+        out["adjoint"] = adj
     torch.cuda.empty_cache()
+    if "batch" not in sections:
+        return out
     # the uneven batch (96 fields: 55 x 32^3, 27 x 64^3, 14 x 128^3), FP32
     sizes = fi.batch_sizes()
     cells_b = sum(m ** 3 for m in sizes)
@@ -240,6 +250,10 @@ def main():
     params = fi.multi_plummer_params(args.spheres, args.seed)
     rho64 = fi.plummer_density(n, params, device=dev)
     torch.cuda.synchronize()
+    if args.section:
+        res = run_extras(args, rho64, fi, fmm, costs, sections=(args.section,))
+        print(json.dumps({"section": args.section, "config": {"n": n, "p": p}, **res}), flush=True)
+        return
     plan = fmm.Plan(n, p, prec)
     rho = rho64 if prec == "fp64" else rho64.float()
     phi = torch.empty((n, n, n), dtype=plan.io_dtype, device=dev)
