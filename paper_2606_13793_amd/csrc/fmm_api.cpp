@@ -133,6 +133,9 @@ void release(fmm_plan* pl) {
     if (a) (void)hipFree(a);
   if (pl->adj_l2p) (void)hipFree(pl->adj_l2p);
   if (pl->adj_l2p2) (void)hipFree(pl->adj_l2p2);
+  if (pl->m2m_start) (void)hipFree(pl->m2m_start);
+  if (pl->m2m_off) (void)hipFree(pl->m2m_off);
+  if (pl->m2m_coef) (void)hipFree(pl->m2m_coef);
   if (pl->l2l_start) (void)hipFree(pl->l2l_start);
   if (pl->l2l_idx) (void)hipFree(pl->l2l_idx);
   if (pl->l2l_coef) (void)hipFree(pl->l2l_coef);
@@ -290,7 +293,8 @@ int build_schedule(fmm_plan* pl) {
       m.field = f;
       m.a = (const double*)fd.lev[k].M;
       m.b = (double*)fd.lev[k - 1].M;
-      m2m[k].add(m, cdiv(1LL << (3 * (k - 1)), 4));
+      // parents per block of k_m2m: 16 up to 56 terms, else 8
+      m2m[k].add(m, cdiv(1LL << (3 * (k - 1)), pl->NM <= 56 ? 16 : 8));
     }
     for (int k = 3; k <= F; ++k) {
       Seg c{};
@@ -490,6 +494,43 @@ fmm_plan* create_plan(const std::vector<int>& ns, int p, const fmm_options& o, i
     if (hipMemcpy(pl->l2l_start, start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(pl->l2l_idx, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(pl->l2l_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+      fail(FMM_ERR_DEVICE, "upload failed");
+      return bail();
+    }
+  }
+  {
+    // M2M coefficient lists: for each multipole term a, every b <= a with
+    // g = a - b: LDS offset 8 b + parity pattern of g, coefficient
+    // 2^-|b| 4^-|g| / g!
+    std::vector<int> start(1, 0), off;
+    std::vector<double> coef;
+    auto fact = [](int k) { double f = 1; for (int i = 2; i <= k; ++i) f *= i; return f; };
+    const int P = pl->nmax;
+    std::vector<int> ex(pl->NM * 3);
+    for (int a = 0; a <= P; ++a)
+      for (int b = 0; a + b <= P; ++b)
+        for (int c = 0; a + b + c <= P; ++c) {
+          const int t = fmm::mi_index(a, b, c);
+          ex[3 * t] = a; ex[3 * t + 1] = b; ex[3 * t + 2] = c;
+        }
+    for (int t = 0; t < pl->NM; ++t) {
+      const int ax = ex[3 * t], ay = ex[3 * t + 1], az = ex[3 * t + 2];
+      for (int x = 0; x <= ax; ++x)
+        for (int y = 0; y <= ay; ++y)
+          for (int z = 0; z <= az; ++z) {
+            const int gx = ax - x, gy = ay - y, gz = az - z;
+            const int pat = ((gx & 1) << 2) | ((gy & 1) << 1) | (gz & 1);
+            off.push_back(8 * fmm::mi_index(x, y, z) + pat);
+            coef.push_back(std::ldexp(1.0 / (fact(gx) * fact(gy) * fact(gz)), -(x + y + z) - 2 * (gx + gy + gz)));
+          }
+      start.push_back((int)off.size());
+    }
+    if (dev_alloc(pl, (void**)&pl->m2m_start, start.size() * sizeof(int))) return bail();
+    if (dev_alloc(pl, (void**)&pl->m2m_off, off.size() * sizeof(int))) return bail();
+    if (dev_alloc(pl, (void**)&pl->m2m_coef, coef.size() * sizeof(double))) return bail();
+    if (hipMemcpy(pl->m2m_start, start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(pl->m2m_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(pl->m2m_coef, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
       fail(FMM_ERR_DEVICE, "upload failed");
       return bail();
     }

@@ -203,13 +203,37 @@ __global__ __launch_bounds__(256) void k_p2m(const Seg* __restrict__ segs, int n
 
 // ---------------------------------------------------------------------------
 // M2M: Mhat_{k-1}[a] = sum_q sum_{b<=a} 2^-|b| 4^-|g| / g! (-1)^(q.g) Mhat_k[2P+q][b],
-// g = a - b.  Block = 4 parents; the Walsh sums of the 8 children per term
-// are staged in LDS, then each thread forms terms.
-// ---------------------------------------------------------------------------
+// g = a - b.  Block = 8 parents (consecutive in C order, so their children
+// are contiguous along z).  Phase 1: thread (chunk c, parent) loads the 4-term
+// chunk c of the parent's 8 children and forms, in registers, the signed sums
+// W[pat][b] = sum_q (-1)^popc(q & pat) Mhat[2P+q][b] (a Walsh transform over
+// q), staged in LDS.  Phase 2: each output term sums its b <= a.
 // Segments: n = child grid cells per axis, a = Mhat_k, b = Mhat_{k-1}.
-template <int NMX>
-__global__ __launch_bounds__(256) void k_m2m(const Seg* __restrict__ segs, int nseg, int NM, int NC) {
-  __shared__ double W[4][NMX][8];
+// ---------------------------------------------------------------------------
+template <int PO>
+struct M2MShape {
+  static constexpr int NM = nterms(PO), NC = (NM + 3) / 4;
+  static constexpr int PAR = NM <= 56 ? 16 : 8;  // parents per block (LDS budget)
+  static constexpr int THREADS = ((PAR * NC + 63) / 64) * 64;
+  // (b, g) pairs with b + g = a over all terms a: sum_n C(n + 5, 5) = C(PO + 6, 6)
+  static constexpr int NE = (PO + 1) * (PO + 2) * (PO + 3) * (PO + 4) * (PO + 5) * (PO + 6) / 720;
+};
+// Coefficient lists of the M2M terms (plan-time, in device memory): for
+// output term a, entries cstart[a] .. cstart[a+1]-1 hold the LDS offset
+// 8 b + pat(g) and the coefficient 2^-|b| 4^-|g| / g! for every b <= a,
+// g = a - b.
+template <int PO>
+__global__ __launch_bounds__(M2MShape<PO>::THREADS) void k_m2m(const Seg* __restrict__ segs, int nseg,
+                                                              const int* __restrict__ cstart,
+                                                              const int* __restrict__ coff,
+                                                              const double* __restrict__ ccoef) {
+  constexpr int NM = M2MShape<PO>::NM, NC = M2MShape<PO>::NC, M2M_THREADS = M2MShape<PO>::THREADS;
+  constexpr int NE = M2MShape<PO>::NE, M2M_PAR = M2MShape<PO>::PAR;
+  constexpr int WS = NM * 8 + 2;  // per-parent stride, padded against bank conflicts
+  __shared__ double W[M2M_PAR * WS];
+  __shared__ int sstart[NM + 1];
+  __shared__ int soff[NE];
+  __shared__ double scoef[NE];
   const Seg& sg = find_seg(segs, nseg, blockIdx.x);
   const double* __restrict__ Mc = sg.a;
   double* __restrict__ Mp = sg.b;
@@ -217,51 +241,52 @@ __global__ __launch_bounds__(256) void k_m2m(const Seg* __restrict__ segs, int n
   const int np = nk >> 1, nkp = nk + 6, npp = np + 6;
   const long long ncp_c = (long long)nkp * nkp * nkp, ncp_p = (long long)npp * npp * npp;
   const long long nP = (long long)np * np * np;
-  const long long P0 = (long long)(blockIdx.x - sg.first_block) * 4;
-  // phase 1: Walsh sums
-  for (int w = threadIdx.x; w < 4 * NM; w += blockDim.x) {
-    const int pl = w / NM, b = w % NM;
+  const long long P0 = (long long)(blockIdx.x - sg.first_block) * M2M_PAR;
+  for (int t = threadIdx.x; t <= NM; t += M2M_THREADS) sstart[t] = cstart[t];
+  for (int t = threadIdx.x; t < NE; t += M2M_THREADS) {
+    soff[t] = coff[t];
+    scoef[t] = ccoef[t];
+  }
+  // phase 1
+  {
+    const int pl = threadIdx.x % M2M_PAR, c = threadIdx.x / M2M_PAR;
     const long long P = P0 + pl;
-    double v[8];
-    if (P < nP) {
+    if (c < NC && P < nP) {
       const int p2 = (int)(P % np), p1 = (int)((P / np) % np), p0 = (int)(P / ((long long)np * np));
+      d4 v[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const long long cc = ((long long)(2 * p0 + ((q >> 2) & 1) + 3) * nkp + (2 * p1 + ((q >> 1) & 1) + 3)) * nkp +
                              (2 * p2 + (q & 1) + 3);
-        v[q] = Mc[((b >> 2) * ncp_c + cc) * 4 + (b & 3)];
+        v[q] = *reinterpret_cast<const d4*>(Mc + (c * ncp_c + cc) * 4);
       }
-    } else {
+      // in-place Walsh transform: index q becomes pattern pat
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = 0.0;
-    }
+      for (int bit = 1; bit < 8; bit <<= 1)
 #pragma unroll
-    for (int pat = 0; pat < 8; ++pat) {
-      double s = 0.0;
+        for (int q = 0; q < 8; ++q)
+          if (!(q & bit)) {
+            const d4 x = v[q], y = v[q | bit];
+            v[q] = x + y;
+            v[q | bit] = x - y;
+          }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) s += (__popc(q & pat) & 1) ? -v[q] : v[q];
-      W[pl][b][pat] = s;
+      for (int e = 0; e < 4; ++e)
+        if (4 * c + e < NM) {
+#pragma unroll
+          for (int pat = 0; pat < 8; ++pat) W[pl * WS + (4 * c + e) * 8 + pat] = v[pat][e];
+        }
     }
   }
   __syncthreads();
-  // phase 2: terms
-  for (int w = threadIdx.x; w < 4 * NC * 4; w += blockDim.x) {
-    const int pl = w / (NC * 4), al = w % (NC * 4);
+  // phase 2: thread (term a, parent), parents fastest so lanes share a list
+  for (int w = threadIdx.x; w < M2M_PAR * NM; w += M2M_THREADS) {
+    const int pl = w % M2M_PAR, al = w / M2M_PAR;
     const long long P = P0 + pl;
     if (P >= nP) continue;
+    const double* Wp = W + pl * WS;
     double acc = 0.0;
-    if (al < NM) {
-      const int ex = c_mi_exp[al];
-      const int a = mi_a(ex), b = mi_b(ex), c = mi_c(ex);
-      for (int x = 0; x <= a; ++x)
-        for (int y = 0; y <= b; ++y)
-          for (int z = 0; z <= c; ++z) {
-            const int gx = a - x, gy = b - y, gz = c - z;
-            const int be = mi_index(x, y, z), ge = mi_index(gx, gy, gz);
-            const int pat = ((gx & 1) << 2) | ((gy & 1) << 1) | (gz & 1);
-            acc += ldexp(c_mi_invfact[ge], -(x + y + z) - 2 * (gx + gy + gz)) * W[pl][be][pat];
-          }
-    }
+    for (int j = sstart[al]; j < sstart[al + 1]; ++j) acc += scoef[j] * Wp[soff[j]];
     const int p2 = (int)(P % np), p1 = (int)((P / np) % np), p0 = (int)(P / ((long long)np * np));
     const long long cp = ((long long)(p0 + 3) * npp + (p1 + 3)) * npp + (p2 + 3);
     Mp[((al >> 2) * ncp_p + cp) * 4 + (al & 3)] = acc;
@@ -792,7 +817,8 @@ hipError_t solve_ct(fmm_plan* pl, IoArg io, hipStream_t s) {
     const SegTable& st = pl->s_m2m[k];
     if (!st.nseg) continue;
     StageScope sc(pl, ST_M2M, 1, s);
-    hipLaunchKernelGGL((k_m2m<nterms(PMAX)>), dim3(st.blocks), dim3(256), 0, s, st.dev, st.nseg, NM, NC);
+    hipLaunchKernelGGL((k_m2m<P>), dim3(st.blocks), dim3(M2MShape<P>::THREADS), 0, s, st.dev, st.nseg, pl->m2m_start,
+                       pl->m2m_off, pl->m2m_coef);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if ((e = launch_conv<P, double, CV_M2L>(pl, pl->s_conv[0], pl->wm2l[0], s)) != hipSuccess) return e;

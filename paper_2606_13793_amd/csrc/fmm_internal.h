@@ -235,6 +235,9 @@ struct fmm_plan {
   double* adj_l2p2 = nullptr;   // [8][NL][32]  parent-level L2P coefficients
   void* wt_m2l[3] = {nullptr, nullptr, nullptr};  // transposed M2L B fragments
   void* wt_m2p[3] = {nullptr, nullptr, nullptr};  // transposed M2P B fragments
+  int* m2m_start = nullptr;     // M2M coefficient lists (CSR over multipole terms)
+  int* m2m_off = nullptr;       // 8 b + parity pattern of g, for b + g = a
+  double* m2m_coef = nullptr;   // 2^-|b| 4^-|g| / g!
   int* l2l_start = nullptr;     // L2L coefficient lists (CSR over local terms)
   int* l2l_idx = nullptr;       // (index of b+g) << 3 | parity pattern of g
   double* l2l_coef = nullptr;

@@ -186,9 +186,23 @@ __global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom(
     AF b0 = bload(en, 0), b1 = bload(en, 1);
     en = entry(OPM + lr.sel);
     AF n0 = bload(en, 0), n1 = bload(en, 1);
-    for (int j = 0; j < NGRP; ++j) {
-      const int e = entry(OPM * j + lr.sel);
+    // A fragments of offset group j: source halo cell of row (gx, gy, gz) is
+    // 3 + 2 g + r - d; those of the next group are read while the current
+    // group's products run
+    auto aload = [&](int e, AF (&a)[BOT_MT]) {
       const int d0 = dl_d0(e), d1 = dl_d1(e), d2 = dl_d2(e);
+      const int zz = 3 + r2 - d2;  // in [1, 6]
+      const int zoff = (zz & 1) * HZ2 + gz + (zz >> 1);
+#pragma unroll
+      for (int m = 0; m < BOT_MT; ++m) {
+        const int hx = 3 + 2 * (m / TPX) + r0 - d0;
+        const int hy = 3 + 2 * (YPT * (m % TPX) + gyo) + r1 - d1;
+        a[m] = *reinterpret_cast<const AF*>(halo + ((hx * HY + hy) * 2 * HZ2 + zoff) * KC + lr.tic);
+      }
+    };
+    AF ac[BOT_MT];
+    aload(entry(lr.sel), ac);
+    for (int j = 0; j < NGRP; ++j) {
       const AF cb0 = b0, cb1 = b1;
       b0 = n0;
       b1 = n1;
@@ -197,17 +211,15 @@ __global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom(
         n0 = bload(e2, 0);
         n1 = bload(e2, 1);
       }
-      // source halo coordinates of row (gx, gy, gz): 3 + 2 g + r - d
-      const int zz = 3 + r2 - d2;  // in [1, 6]
-      const int zoff = (zz & 1) * HZ2 + gz + (zz >> 1);
+      AF an[BOT_MT];
+      if (j + 1 < NGRP) aload(entry(OPM * (j + 1) + lr.sel), an);
 #pragma unroll
       for (int m = 0; m < BOT_MT; ++m) {
-        const int hx = 3 + 2 * (m / TPX) + r0 - d0;
-        const int hy = 3 + 2 * (YPT * (m % TPX) + gyo) + r1 - d1;
-        const AF a = *reinterpret_cast<const AF*>(halo + ((hx * HY + hy) * 2 * HZ2 + zoff) * KC + lr.tic);
-        acc[m][0] = M::op(a, cb0, acc[m][0]);
-        acc[m][1] = M::op(a, cb1, acc[m][1]);
+        acc[m][0] = M::op(ac[m], cb0, acc[m][0]);
+        acc[m][1] = M::op(ac[m], cb1, acc[m][1]);
       }
+#pragma unroll
+      for (int m = 0; m < BOT_MT; ++m) ac[m] = an[m];
     }
   }
 
@@ -503,9 +515,22 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
         }
       }
     }
-    for (int j = j0; j < j1; ++j) {
-      const int e = entry(OPM * j + lr.sel);
+    // A fragments of offset group j (source halo cell 3 + 2 g + r - d); the
+    // next group's are read while the current group's products run
+    auto aload = [&](int e, AF (&a)[M2L_MT]) {
       const int d0 = dl_d0(e), d1 = dl_d1(e), d2 = dl_d2(e);
+      const int zz = 3 + r2 - d2;
+      const int zoff = (zz & 1) * LH2 + gz + (zz >> 1);
+      const int hy = 3 + 2 * gy + r1 - d1;
+#pragma unroll
+      for (int m = 0; m < M2L_MT; ++m) {
+        const int hx = 3 + 2 * m + r0 - d0;
+        a[m] = *reinterpret_cast<const AF*>(halo + ((hx * LH + hy) * 2 * LH2 + zoff) * KC + lr.tic);
+      }
+    };
+    AF ac[M2L_MT];
+    aload(entry(OPM * j0 + lr.sel), ac);
+    for (int j = j0; j < j1; ++j) {
       AF cb[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
@@ -518,17 +543,15 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
         for (int t = 0; t < NT; ++t)
           if (c < vt[t]) b1[t] = bload(en, t, c);
       }
-      const int zz = 3 + r2 - d2;
-      const int zoff = (zz & 1) * LH2 + gz + (zz >> 1);
-      const int hy = 3 + 2 * gy + r1 - d1;
+      AF an[M2L_MT];
+      if (j + 1 < j1) aload(entry(OPM * (j + 1) + lr.sel), an);
 #pragma unroll
-      for (int m = 0; m < M2L_MT; ++m) {
-        const int hx = 3 + 2 * m + r0 - d0;
-        const AF a = *reinterpret_cast<const AF*>(halo + ((hx * LH + hy) * 2 * LH2 + zoff) * KC + lr.tic);
+      for (int m = 0; m < M2L_MT; ++m)
 #pragma unroll
         for (int t = 0; t < NT; ++t)
-          if (c < vt[t]) acc[m][t] = M::op(a, cb[t], acc[m][t]);
-      }
+          if (c < vt[t]) acc[m][t] = M::op(ac[m], cb[t], acc[m][t]);
+#pragma unroll
+      for (int m = 0; m < M2L_MT; ++m) ac[m] = an[m];
     }
   }
   // epilogue: element v of tile t is row M::row(v, kq), column 16 (T0 + t) + i
