@@ -244,7 +244,8 @@ hipError_t finish_locals(fmm_plan* pl, int level, hipStream_t s) { FMM_BY_ORDER(
 
 namespace {
 
-constexpr int kConvTile = 8;  // row-grid cells per axis of a k_conv block
+constexpr int kConvTile = 8;   // row-grid cells along x and y of a k_conv block
+constexpr int kConvTileZ = 16; // and along z
 constexpr int kBotTile = 8;   // level-F cells along x and y of a k_bottom block
 
 struct SegList {
@@ -300,11 +301,12 @@ int build_schedule(fmm_plan* pl) {
       Seg c{};
       c.n = 1 << (k - 1);
       c.tpa = (int)cdiv(c.n, kConvTile);
+      c.tz = (int)cdiv(c.n, kConvTileZ);
       c.field = f;
       c.split = 1;
       c.a = (const double*)fd.lev[k - 1].M;
       c.b = (double*)fd.lev[k].L;
-      conv[k >= klow ? 1 : 0].add(c, (long long)c.tpa * c.tpa * c.tpa);
+      conv[k >= klow ? 1 : 0].add(c, (long long)c.tpa * c.tpa * c.tz);
     }
     for (int k = 4; k <= F - 1; ++k) {
       Seg l{};
@@ -335,7 +337,7 @@ int build_schedule(fmm_plan* pl) {
     std::vector<long long> at[2];
     for (int x = 0; x < 2; ++x) {
       long long T = 0;
-      for (auto& c : conv[x].v) T += (long long)c.tpa * c.tpa * c.tpa;
+      for (auto& c : conv[x].v) T += (long long)c.tpa * c.tpa * c.tz;
       const int S = T >= 128 ? 1 : (int)std::min<long long>(16, std::max<long long>(2, 256 / std::max<long long>(T, 1)));
       if (S == 1 || conv[x].v.empty()) continue;
       for (auto& c : conv[x].v) {
@@ -346,7 +348,7 @@ int build_schedule(fmm_plan* pl) {
       SegList sp;
       for (auto c : conv[x].v) {
         c.split = S;
-        sp.add(c, (long long)c.tpa * c.tpa * c.tpa * S);
+        sp.add(c, (long long)c.tpa * c.tpa * c.tz * S);
       }
       conv[x] = sp;
     }
@@ -844,18 +846,20 @@ static int ensure_adjoint(fmm_plan* pl, hipStream_t s) {
       fmm::Seg c{};
       c.n = 1 << (k - 1);
       c.tpa = (int)cdiv(c.n, kConvTile);
+      c.tz = (int)cdiv(c.n, kConvTileZ);
       c.split = 1;
       c.a = pl->abar[k];
       c.b = (double*)pl->lev[k - 1].M;
-      lt[k >= klow ? 1 : 0].add(c, (long long)c.tpa * c.tpa * c.tpa);
+      lt[k >= klow ? 1 : 0].add(c, (long long)c.tpa * c.tpa * c.tz);
     }
     fmm::Seg c{};
     c.n = nF;
     c.tpa = (int)cdiv(nF, kConvTile);
+    c.tz = (int)cdiv(nF, kConvTileZ);
     c.split = 1;
     c.a = pl->ybar;
     c.b = (double*)pl->lev[pl->F].M;
-    pt.add(c, (long long)c.tpa * c.tpa * c.tpa);
+    pt.add(c, (long long)c.tpa * c.tpa * c.tz);
     int rc;
     if ((rc = upload_segs(pl, pl->s_m2lt[0], lt[0])) || (rc = upload_segs(pl, pl->s_m2lt[1], lt[1])) ||
         (rc = upload_segs(pl, pl->s_m2pt, pt)))

@@ -399,26 +399,22 @@ __global__ void k_expand_bottom(const double* __restrict__ Dtab, typename Mf<CT>
 //          scaled adjoint outputs (q, o) of X, col = a,
 //          B_d[(q, o)][a] = D[a + e_o](Rhat_{-d,q}).
 // ---------------------------------------------------------------------------
-constexpr int LX = 8;
-constexpr int LH = LX + 6, LH2 = LH / 2;
-constexpr int M2L_MT = (LX / 2) * (LX / 2) * (LX / 2) / 16;  // 4 row tiles per wave
+// Conv tile: CX x CX x CZ row-grid cells (the bottom kernel's shape), per
+// parity class 4 x 4 x 8 rows in CMT = 8 row tiles of 16 (BotShape<CZ>).
+constexpr int CX = 8, CZ = 16;
+constexpr int CMT = BotShape<CZ>::MT;
 constexpr int M2L_THREADS = 512;
-constexpr int MAXLEV = 12;
 
-__device__ __forceinline__ int lhalo_index(int hx, int hy, int hz) {
-  return ((hx * LH + hy) * 2 + (hz & 1)) * LH2 + (hz >> 1);
-}
-
-// tiles per column group by compute type (accumulator registers); variant 1
-// halves them
+// column tiles per group by compute type (accumulator registers: CMT row
+// tiles x NT); variant 1 halves them
 template <typename CT, int V = 0>
 struct ConvGroup {
-  static constexpr int WIDE = Mf<CT>::VPL == 8 ? 4 : (sizeof(typename Mf<CT>::Acc) == 32 ? 5 : 10);
+  static constexpr int WIDE = Mf<CT>::VPL == 8 ? 3 : (sizeof(typename Mf<CT>::Acc) == 32 ? 2 : 4);
   static constexpr int NT = V == 0 ? WIDE : (WIDE + 1) / 2;
 };
 
-// Segments: n = row grid cells per axis, tpa = tiles per axis, split = number
-// of blocks sharing a tile (each sums a slice of the offsets), a = operand
+// Segments: n = row grid cells per axis, tpa = tiles along x and y, tz =
+// tiles along z, split = number of blocks sharing a tile (each sums a slice of the offsets), a = operand
 // grid (chunked [NK/4][(n+6)^3][4] with a zero margin), b = output (CV_M2L:
 // locals [n^3][loc_stride], or split partial sums [split][n^3][loc_stride];
 // otherwise chunked padded [NC4][(n+6)^3][4]).
@@ -438,7 +434,9 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   constexpr int NC4 = (conv_nk(OP, P) + 3) / 4;  // 4-term chunks of the operand grid
   constexpr int NM = nterms(P), NCOL = 8 * nterms(P), NTILES = conv_ntiles(OP, P);
   constexpr int NGRP = (NLIST + OPM - 1) / OPM;
-  __shared__ H halo[LH * LH * LH * KC];
+  using S = BotShape<CZ>;
+  constexpr int HZ = S::HZ, HZ2 = S::HZ2, BZ2 = S::BZ2, YPT = S::YPT, TPX = S::TPX;
+  __shared__ H halo[HX * HY * HZ * KC];
   const int grp = (int)blockIdx.x / T;
   const int T0 = grp * NT;
   const int lbk = (int)blockIdx.x - grp * T;
@@ -459,18 +457,18 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   }
   const int CM = vt[0];
   const int j0 = part * NGRP / split, j1 = (part + 1) * NGRP / split;
-  const int tx0 = (tb / (tpa * tpa)) * LX, ty0 = ((tb / tpa) % tpa) * LX, tz0 = (tb % tpa) * LX;
+  const int tx0 = (tb / (tpa * sg.tz)) * CX, ty0 = ((tb / sg.tz) % tpa) * CX, tz0 = (tb % sg.tz) * CZ;
   const long long ncellp = (long long)nsp * nsp * nsp;
   const int lane = threadIdx.x & 63;
   const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave = parity class (uniform)
   const int i = lane & 15, kq = lane >> 4;
   const LaneRole<CT> lr(lane);
   const int r0 = (r >> 2) & 1, r1 = (r >> 1) & 1, r2 = r & 1;
-  const int gy = i >> 2, gz = i & 3;  // row i of tile m: lattice (m, gy, gz)
+  const int gz = i % BZ2, gyo = i / BZ2;  // row i of tile m: lattice (m / TPX, YPT (m % TPX) + gyo, gz)
 
-  Acc acc[M2L_MT][NT];
+  Acc acc[CMT][NT];
 #pragma unroll
-  for (int m = 0; m < M2L_MT; ++m)
+  for (int m = 0; m < CMT; ++m)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[m][t] = Acc{0, 0, 0, 0};
   const int* dl = dlists + r * NLIST_PAD;
@@ -489,11 +487,11 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
 
   for (int c = 0; c < CM; ++c) {
     __syncthreads();
-    for (int h = threadIdx.x; h < LH * LH * LH; h += M2L_THREADS) {
-      const int hz = h % LH, hy = (h / LH) % LH, hx = h / (LH * LH);
+    for (int h = threadIdx.x; h < HX * HY * HZ; h += M2L_THREADS) {
+      const int hz = h % HZ, hy = (h / HZ) % HY, hx = h / (HZ * HY);
       const int px = tx0 + hx, py = ty0 + hy, pz = tz0 + hz;
       const bool in = px < nsp && py < nsp && pz < nsp;
-      H* hd = halo + lhalo_index(hx, hy, hz) * KC;
+      H* hd = halo + S::halo_index(hx, hy, hz) * KC;
 #pragma unroll
       for (int s4 = 0; s4 < KC / 4; ++s4) {
         const int sc = c * (KC / 4) + s4;
@@ -517,18 +515,18 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
     }
     // A fragments of offset group j (source halo cell 3 + 2 g + r - d); the
     // next group's are read while the current group's products run
-    auto aload = [&](int e, AF (&a)[M2L_MT]) {
+    auto aload = [&](int e, AF (&a)[CMT]) {
       const int d0 = dl_d0(e), d1 = dl_d1(e), d2 = dl_d2(e);
       const int zz = 3 + r2 - d2;
-      const int zoff = (zz & 1) * LH2 + gz + (zz >> 1);
-      const int hy = 3 + 2 * gy + r1 - d1;
+      const int zoff = (zz & 1) * HZ2 + gz + (zz >> 1);
 #pragma unroll
-      for (int m = 0; m < M2L_MT; ++m) {
-        const int hx = 3 + 2 * m + r0 - d0;
-        a[m] = *reinterpret_cast<const AF*>(halo + ((hx * LH + hy) * 2 * LH2 + zoff) * KC + lr.tic);
+      for (int m = 0; m < CMT; ++m) {
+        const int hx = 3 + 2 * (m / TPX) + r0 - d0;
+        const int hy = 3 + 2 * (YPT * (m % TPX) + gyo) + r1 - d1;
+        a[m] = *reinterpret_cast<const AF*>(halo + ((hx * HY + hy) * 2 * HZ2 + zoff) * KC + lr.tic);
       }
     };
-    AF ac[M2L_MT];
+    AF ac[CMT];
     aload(entry(OPM * j0 + lr.sel), ac);
     for (int j = j0; j < j1; ++j) {
       AF cb[NT];
@@ -543,15 +541,15 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
         for (int t = 0; t < NT; ++t)
           if (c < vt[t]) b1[t] = bload(en, t, c);
       }
-      AF an[M2L_MT];
+      AF an[CMT];
       if (j + 1 < j1) aload(entry(OPM * (j + 1) + lr.sel), an);
 #pragma unroll
-      for (int m = 0; m < M2L_MT; ++m)
+      for (int m = 0; m < CMT; ++m)
 #pragma unroll
         for (int t = 0; t < NT; ++t)
           if (c < vt[t]) acc[m][t] = M::op(ac[m], cb[t], acc[m][t]);
 #pragma unroll
-      for (int m = 0; m < M2L_MT; ++m) ac[m] = an[m];
+      for (int m = 0; m < CMT; ++m) ac[m] = an[m];
     }
   }
   // epilogue: element v of tile t is row M::row(v, kq), column 16 (T0 + t) + i
@@ -566,11 +564,12 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
       escale[t] = -(m2l_col_degree(col < NCOL ? col : 0) + 1);
     }
 #pragma unroll
-    for (int m = 0; m < M2L_MT; ++m)
+    for (int m = 0; m < CMT; ++m)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = M::row(v, kq);
-        const int p0 = tx0 + 2 * m + r0, p1 = ty0 + 2 * (row >> 2) + r1, p2 = tz0 + 2 * (row & 3) + r2;
+        const int p0 = tx0 + 2 * (m / TPX) + r0, p1 = ty0 + 2 * (YPT * (m % TPX) + row / BZ2) + r1,
+                  p2 = tz0 + 2 * (row % BZ2) + r2;
         if (p0 >= ns || p1 >= ns || p2 >= ns) continue;
         double* o = dst + (((long long)p0 * ns + p1) * ns + p2) * RS + 16 * T0 + i;
 #pragma unroll
@@ -579,11 +578,12 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
       }
   } else {
 #pragma unroll
-    for (int m = 0; m < M2L_MT; ++m)
+    for (int m = 0; m < CMT; ++m)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = M::row(v, kq);
-        const int p0 = tx0 + 2 * m + r0, p1 = ty0 + 2 * (row >> 2) + r1, p2 = tz0 + 2 * (row & 3) + r2;
+        const int p0 = tx0 + 2 * (m / TPX) + r0, p1 = ty0 + 2 * (YPT * (m % TPX) + row / BZ2) + r1,
+                  p2 = tz0 + 2 * (row % BZ2) + r2;
         if (p0 >= ns || p1 >= ns || p2 >= ns) continue;
         const long long cp = ((long long)(p0 + 3) * nsp + (p1 + 3)) * nsp + (p2 + 3);
 #pragma unroll
