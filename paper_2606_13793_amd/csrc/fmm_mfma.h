@@ -103,16 +103,37 @@ struct BotShape {
   static constexpr int MT = BZ2;             // row tiles per wave
   static constexpr int YPT = 16 / BZ2;       // y values per tile
   static constexpr int TPX = 4 / YPT;        // tiles per x value
-  __device__ static int halo_index(int hx, int hy, int hz) {
-    return (((hx * HY + hy) * 2 + (hz & 1)) * HZ2 + (hz >> 1));
+};
+
+// LDS halo layout: element (hx, hy, hz, k) at hx XS + hy YS + (hz & 1) HZ2 KC +
+// (hz >> 1) KC + (k ^ swz(hy)), z de-interleaved by parity.  The 16 rows of
+// an operand fragment are 8 z cells x 2 y cells two apart; they are spread
+// over the LDS banks by an odd y stride in doubles for FP64 (8-byte reads)
+// and, for BF16 (16-byte reads, which must stay 16-byte aligned), by swapping
+// the two 16-byte halves of a cell on every other pair of y rows.
+template <typename CT, int BZ>
+struct Halo {
+  static constexpr int KC = Mf<CT>::KC, HZ2 = BotShape<BZ>::HZ2;
+  static constexpr int NAT = 2 * HZ2 * KC;  // natural y stride (elements)
+  static constexpr int YS = Mf<CT>::IDX == 0 ? (NAT | 1) : NAT;
+  static constexpr int XS = HY * YS;
+  static constexpr int SIZE = HX * XS;
+  __device__ static int cell(int hx, int hy, int hz) {
+    return hx * XS + hy * YS + ((hz & 1) * HZ2 + (hz >> 1)) * KC;
   }
+  __device__ static int swz(int hy) { return Mf<CT>::IDX == 2 ? ((hy >> 1) & 1) * 8 : 0; }
 };
 
 // Segments: n = nF (level-F cells per axis), tpa = tiles along x and y,
 // tz = tiles along z, field, a = Mhat_F, c = Lam_F (or null), d = the parent
 // level's locals (or null).
+// minimum waves per SIMD (the second launch bound): FP32 operands leave room
+// for two 512-thread blocks per CU (4 waves per SIMD, <= 128 registers)
+template <typename CT>
+constexpr int bottom_min_waves() { return Mf<CT>::IDX == 1 ? 4 : 2; }
+
 template <int P, typename CT, typename TI, typename TO, int BZ>
-__global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom(
+__global__ __launch_bounds__(BOT_THREADS, bottom_min_waves<CT>()) void k_bottom(
     const Seg* __restrict__ segs, int nseg, IoArg io, const typename Mf<CT>::H* __restrict__ Wm2p,
     const typename Mf<CT>::H* __restrict__ Wl2p, const typename Mf<CT>::H* __restrict__ Wl2p2,
     const typename Mf<CT>::H* __restrict__ Wp2p, const int* __restrict__ dlists) {
@@ -127,7 +148,10 @@ __global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom(
   constexpr int NL = nterms(P);
   constexpr int KT = 4 * VPL, NLT = (NL + KT - 1) / KT, NPT = (216 + KT - 1) / KT;
   constexpr int NGRP = (NLIST + OPM - 1) / OPM;
-  __shared__ H halo[HX * HY * HZ * KC];
+  using HL = Halo<CT, BZ>;
+  __shared__ H halo[HL::SIZE];
+  __shared__ int slist[8 * NLIST_PAD];  // the interaction lists of the 8 parity classes
+  for (int t = threadIdx.x; t < 8 * NLIST_PAD; t += BOT_THREADS) slist[t] = dlists[t];
   const Seg& sg = find_seg(segs, nseg, blockIdx.x);
   const int nF = sg.n;
   const double* __restrict__ Mh = sg.a;
@@ -152,7 +176,7 @@ __global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom(
   Acc acc[BOT_MT][2];
 #pragma unroll
   for (int m = 0; m < BOT_MT; ++m) acc[m][0] = acc[m][1] = Acc{0, 0, 0, 0};
-  const int* dl = dlists + r * NLIST_PAD;
+  const int* dl = slist + r * NLIST_PAD;  // visible after the first chunk's barrier
   // blocks walk the (order-independent) offset sum from different starting points
   const int rot = (int)((blockIdx.x * 37u) % NLIST);
   auto entry = [&](int pos) {
@@ -167,14 +191,15 @@ __global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom(
       const int hz = h % HZ, hy = (h / HZ) % HY, hx = h / (HZ * HY);
       const int px = tx0 + hx, py = ty0 + hy, pz = tz0 + hz;  // padded coordinates
       const bool in = px < nFp && py < nFp && pz < nFp;
-      H* dst = halo + S::halo_index(hx, hy, hz) * KC;
+      H* dst = halo + HL::cell(hx, hy, hz);
+      const int sw = HL::swz(hy);
 #pragma unroll
       for (int s4 = 0; s4 < KC / 4; ++s4) {
         const int sc = c * (KC / 4) + s4;
         d4 v = d4{0, 0, 0, 0};
         if (in && sc < NC4) v = *reinterpret_cast<const d4*>(Mh + (sc * ncellp + ((long long)px * nFp + py) * nFp + pz) * 4);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) dst[4 * s4 + e] = static_cast<H>(v[e]);
+        for (int e = 0; e < 4; ++e) dst[(4 * s4 + e) ^ sw] = static_cast<H>(v[e]);
       }
     }
     __syncthreads();
@@ -182,13 +207,11 @@ __global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom(
     auto bload = [&](int e, int t) {
       return *reinterpret_cast<const AF*>(wc + ((size_t)dl_dd(e) * 2 + t) * EL * VPL);
     };
-    int en = entry(lr.sel);
-    AF b0 = bload(en, 0), b1 = bload(en, 1);
-    en = entry(OPM + lr.sel);
-    AF n0 = bload(en, 0), n1 = bload(en, 1);
     // A fragments of offset group j: source halo cell of row (gx, gy, gz) is
-    // 3 + 2 g + r - d; those of the next group are read while the current
-    // group's products run
+    // 3 + 2 g + r - d.  Three register slots for the list entries, the B
+    // fragments and the A fragments of groups j, j + 1, j + 2 (the loop is
+    // unrolled by three, so no slot is copied): B is loaded two groups
+    // ahead, A one group ahead, while the current group's products run.
     auto aload = [&](int e, AF (&a)[BOT_MT]) {
       const int d0 = dl_d0(e), d1 = dl_d1(e), d2 = dl_d2(e);
       const int zz = 3 + r2 - d2;  // in [1, 6]
@@ -197,29 +220,36 @@ __global__ __launch_bounds__(BOT_THREADS, 1) void k_bottom(
       for (int m = 0; m < BOT_MT; ++m) {
         const int hx = 3 + 2 * (m / TPX) + r0 - d0;
         const int hy = 3 + 2 * (YPT * (m % TPX) + gyo) + r1 - d1;
-        a[m] = *reinterpret_cast<const AF*>(halo + ((hx * HY + hy) * 2 * HZ2 + zoff) * KC + lr.tic);
+        a[m] = *reinterpret_cast<const AF*>(halo + hx * HL::XS + hy * HL::YS + zoff * KC + (lr.tic ^ HL::swz(hy)));
       }
     };
-    AF ac[BOT_MT];
-    aload(entry(lr.sel), ac);
-    for (int j = 0; j < NGRP; ++j) {
-      const AF cb0 = b0, cb1 = b1;
-      b0 = n0;
-      b1 = n1;
-      if (j + 2 < NGRP) {
-        const int e2 = entry(OPM * (j + 2) + lr.sel);
-        n0 = bload(e2, 0);
-        n1 = bload(e2, 1);
-      }
-      AF an[BOT_MT];
-      if (j + 1 < NGRP) aload(entry(OPM * (j + 1) + lr.sel), an);
+    int es[3];
+    AF bs[3][2], as[3][BOT_MT];
+    es[0] = entry(lr.sel);
+    bs[0][0] = bload(es[0], 0);
+    bs[0][1] = bload(es[0], 1);
+    es[1] = entry(OPM + lr.sel);
+    bs[1][0] = bload(es[1], 0);
+    bs[1][1] = bload(es[1], 1);
+    aload(es[0], as[0]);
+    for (int j = 0; j < NGRP; j += 3) {
 #pragma unroll
-      for (int m = 0; m < BOT_MT; ++m) {
-        acc[m][0] = M::op(ac[m], cb0, acc[m][0]);
-        acc[m][1] = M::op(ac[m], cb1, acc[m][1]);
-      }
+      for (int u = 0; u < 3; ++u) {
+        const int jj = j + u, cur = u, nx = (u + 1) % 3, nn = (u + 2) % 3;
+        if (jj < NGRP) {
+          if (jj + 2 < NGRP) {
+            es[nn] = entry(OPM * (jj + 2) + lr.sel);
+            bs[nn][0] = bload(es[nn], 0);
+            bs[nn][1] = bload(es[nn], 1);
+          }
+          if (jj + 1 < NGRP) aload(es[nx], as[nx]);
 #pragma unroll
-      for (int m = 0; m < BOT_MT; ++m) ac[m] = an[m];
+          for (int m = 0; m < BOT_MT; ++m) {
+            acc[m][0] = M::op(as[cur][m], bs[cur][0], acc[m][0]);
+            acc[m][1] = M::op(as[cur][m], bs[cur][1], acc[m][1]);
+          }
+        }
+      }
     }
   }
 
@@ -436,7 +466,10 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   constexpr int NGRP = (NLIST + OPM - 1) / OPM;
   using S = BotShape<CZ>;
   constexpr int HZ = S::HZ, HZ2 = S::HZ2, BZ2 = S::BZ2, YPT = S::YPT, TPX = S::TPX;
-  __shared__ H halo[HX * HY * HZ * KC];
+  using HL = Halo<CT, CZ>;
+  __shared__ H halo[HL::SIZE];
+  __shared__ int slist[8 * NLIST_PAD];  // the interaction lists of the 8 parity classes
+  for (int t = threadIdx.x; t < 8 * NLIST_PAD; t += M2L_THREADS) slist[t] = dlists[t];
   const int grp = (int)blockIdx.x / T;
   const int T0 = grp * NT;
   const int lbk = (int)blockIdx.x - grp * T;
@@ -471,7 +504,7 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   for (int m = 0; m < CMT; ++m)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[m][t] = Acc{0, 0, 0, 0};
-  const int* dl = dlists + r * NLIST_PAD;
+  const int* dl = slist + r * NLIST_PAD;  // visible after the first chunk's barrier
   // the rotation of the offset order must be the same for every part of a
   // split tile (the parts take consecutive slices of one ordering)
   const int rot = (int)(((unsigned)(sg.first_block + tb * split) * 37u) % NLIST);
@@ -491,30 +524,22 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
       const int hz = h % HZ, hy = (h / HZ) % HY, hx = h / (HZ * HY);
       const int px = tx0 + hx, py = ty0 + hy, pz = tz0 + hz;
       const bool in = px < nsp && py < nsp && pz < nsp;
-      H* hd = halo + S::halo_index(hx, hy, hz) * KC;
+      H* hd = halo + HL::cell(hx, hy, hz);
+      const int sw = HL::swz(hy);
 #pragma unroll
       for (int s4 = 0; s4 < KC / 4; ++s4) {
         const int sc = c * (KC / 4) + s4;
         d4 v = d4{0, 0, 0, 0};
         if (in && sc < NC4) v = *reinterpret_cast<const d4*>(src + (sc * ncellp + ((long long)px * nsp + py) * nsp + pz) * 4);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) hd[4 * s4 + e] = static_cast<H>(v[e]);
+        for (int e = 0; e < 4; ++e) hd[(4 * s4 + e) ^ sw] = static_cast<H>(v[e]);
       }
     }
     __syncthreads();
-    AF b0[NT], b1[NT];
-    {
-      const int e0 = entry(OPM * j0 + lr.sel), e1 = entry(OPM * (j0 + 1) + lr.sel);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        if (c < vt[t]) {
-          b0[t] = bload(e0, t, c);
-          b1[t] = bload(e1, t, c);
-        }
-      }
-    }
-    // A fragments of offset group j (source halo cell 3 + 2 g + r - d); the
-    // next group's are read while the current group's products run
+    // A fragments of offset group j (source halo cell 3 + 2 g + r - d).
+    // Three register slots for the list entries, the B fragments and the A
+    // fragments of groups j, j + 1, j + 2 (the loop is unrolled by three, so
+    // no slot is copied): B is loaded two groups ahead, A one group ahead.
     auto aload = [&](int e, AF (&a)[CMT]) {
       const int d0 = dl_d0(e), d1 = dl_d1(e), d2 = dl_d2(e);
       const int zz = 3 + r2 - d2;
@@ -523,33 +548,40 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
       for (int m = 0; m < CMT; ++m) {
         const int hx = 3 + 2 * (m / TPX) + r0 - d0;
         const int hy = 3 + 2 * (YPT * (m % TPX) + gyo) + r1 - d1;
-        a[m] = *reinterpret_cast<const AF*>(halo + ((hx * HY + hy) * 2 * HZ2 + zoff) * KC + lr.tic);
+        a[m] = *reinterpret_cast<const AF*>(halo + hx * HL::XS + hy * HL::YS + zoff * KC + (lr.tic ^ HL::swz(hy)));
       }
     };
-    AF ac[CMT];
-    aload(entry(OPM * j0 + lr.sel), ac);
-    for (int j = j0; j < j1; ++j) {
-      AF cb[NT];
+    int es[3];
+    AF bs[3][NT], as[3][CMT];
+    es[0] = entry(OPM * j0 + lr.sel);
+    es[1] = entry(OPM * (j0 + 1) + lr.sel);
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        cb[t] = b0[t];
-        b0[t] = b1[t];
+    for (int t = 0; t < NT; ++t) {
+      if (c < vt[t]) {
+        bs[0][t] = bload(es[0], t, c);
+        bs[1][t] = bload(es[1], t, c);
       }
-      if (j + 2 < j1) {
-        const int en = entry(OPM * (j + 2) + lr.sel);
+    }
+    aload(es[0], as[0]);
+    for (int j = j0; j < j1; j += 3) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
-          if (c < vt[t]) b1[t] = bload(en, t, c);
+      for (int u = 0; u < 3; ++u) {
+        const int jj = j + u, cur = u, nx = (u + 1) % 3, nn = (u + 2) % 3;
+        if (jj < j1) {
+          if (jj + 2 < j1) {
+            es[nn] = entry(OPM * (jj + 2) + lr.sel);
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+              if (c < vt[t]) bs[nn][t] = bload(es[nn], t, c);
+          }
+          if (jj + 1 < j1) aload(es[nx], as[nx]);
+#pragma unroll
+          for (int m = 0; m < CMT; ++m)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+              if (c < vt[t]) acc[m][t] = M::op(as[cur][m], bs[cur][t], acc[m][t]);
+        }
       }
-      AF an[CMT];
-      if (j + 1 < j1) aload(entry(OPM * (j + 1) + lr.sel), an);
-#pragma unroll
-      for (int m = 0; m < CMT; ++m)
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-          if (c < vt[t]) acc[m][t] = M::op(ac[m], cb[t], acc[m][t]);
-#pragma unroll
-      for (int m = 0; m < CMT; ++m) ac[m] = an[m];
     }
   }
   // epilogue: element v of tile t is row M::row(v, kq), column 16 (T0 + t) + i
