@@ -109,6 +109,8 @@ void release(fmm_plan* pl) {
     for (auto& st : a) free_st(st);
   for (auto& st : pl->s_m2lt) free_st(st);
   for (auto& st : pl->s_red) free_st(st);
+  free_st(pl->s_m2lt_red);
+  if (pl->adj_part) (void)hipFree(pl->adj_part);
   if (pl->conv_part) (void)hipFree(pl->conv_part);
   for (auto& row : pl->tiletab)
     for (auto t : row)
@@ -360,6 +362,7 @@ int build_schedule(fmm_plan* pl) {
           Seg r{};
           r.n = c.n;
           r.split = c.split;
+          r.count = (long long)c.n * c.n * c.n * RS;
           r.field = c.field;
           r.a = pl->conv_part + at[x][i];
           r.b = c.b;
@@ -840,17 +843,41 @@ static int ensure_adjoint(fmm_plan* pl, hipStream_t s) {
   {
     // segment tables of the transposed convolutions: M2L^T rows are the
     // sources of every target level, M2P^T rows the level-F cells
+    // The transposed M2L's first column group needs every K chunk (the
+    // degree-0 multipole term couples to all local terms), so each tile's
+    // offset sum is split over kAdjSplit blocks; the partial adjoint
+    // multipoles are added afterwards in a fixed order.
     const int klow = fmm::m2l_low_from(pl);
-    SegList lt[2], pt;
+    constexpr int kAdjSplit = 4;
+    long long part_doubles = 0;
+    for (int k = 3; k <= pl->F; ++k) {
+      const long long np = (1LL << (k - 1)) + 6;
+      part_doubles += (long long)kAdjSplit * pl->NC * np * np * np * 4;
+    }
+    if (dev_alloc(pl, (void**)&pl->adj_part, (size_t)part_doubles * sizeof(double))) return FMM_ERR_OUT_OF_MEMORY;
+    // zero once: margins and unused chunk slots are never written, and the
+    // reduction stores the whole padded grid (which the forward solve reads)
+    if (hipMemset(pl->adj_part, 0, (size_t)part_doubles * sizeof(double)) != hipSuccess)
+      return fail(FMM_ERR_DEVICE, "hipMemset failed");
+    SegList lt[2], pt, ltr;
+    long long at = 0;
     for (int k = 3; k <= pl->F; ++k) {
       fmm::Seg c{};
       c.n = 1 << (k - 1);
       c.tpa = (int)cdiv(c.n, kConvTile);
       c.tz = (int)cdiv(c.n, kConvTileZ);
-      c.split = 1;
+      c.split = kAdjSplit;
       c.a = pl->abar[k];
-      c.b = (double*)pl->lev[k - 1].M;
-      lt[k >= klow ? 1 : 0].add(c, (long long)c.tpa * c.tpa * c.tz);
+      c.b = pl->adj_part + at;
+      lt[k >= klow ? 1 : 0].add(c, (long long)c.tpa * c.tpa * c.tz * kAdjSplit);
+      const long long cnt = (long long)pl->NC * (c.n + 6) * (c.n + 6) * (c.n + 6) * 4;
+      fmm::Seg r{};
+      r.split = kAdjSplit;
+      r.count = cnt;
+      r.a = pl->adj_part + at;
+      r.b = (double*)pl->lev[k - 1].M;
+      ltr.add(r, cdiv(cnt, 256));
+      at += kAdjSplit * cnt;
     }
     fmm::Seg c{};
     c.n = nF;
@@ -862,7 +889,7 @@ static int ensure_adjoint(fmm_plan* pl, hipStream_t s) {
     pt.add(c, (long long)c.tpa * c.tpa * c.tz);
     int rc;
     if ((rc = upload_segs(pl, pl->s_m2lt[0], lt[0])) || (rc = upload_segs(pl, pl->s_m2lt[1], lt[1])) ||
-        (rc = upload_segs(pl, pl->s_m2pt, pt)))
+        (rc = upload_segs(pl, pl->s_m2pt, pt)) || (rc = upload_segs(pl, pl->s_m2lt_red, ltr)))
       return rc;
   }
   if (dev_alloc(pl, (void**)&pl->adj_l2p, (size_t)pl->NL * 32 * sizeof(double))) return FMM_ERR_OUT_OF_MEMORY;

@@ -740,11 +740,11 @@ hipError_t tables_all(fmm_plan* pl, hipStream_t s) {
   return e;
 }
 
-// Sums the split partial M2L results of each segment into its locals.
-// Segments: n = source cells per axis, split, a = partials, b = locals.
-__global__ __launch_bounds__(256) void k_split_reduce(const Seg* __restrict__ segs, int nseg, int RS) {
+// Sums the split partial results of each segment of a convolution.
+// Segments: count = values per part, split, a = partials, b = result.
+__global__ __launch_bounds__(256) void k_split_reduce(const Seg* __restrict__ segs, int nseg) {
   const Seg& sg = find_seg(segs, nseg, blockIdx.x);
-  const long long cnt = (long long)sg.n * sg.n * sg.n * RS;
+  const long long cnt = sg.count;
   const long long x = (long long)(blockIdx.x - sg.first_block) * 256 + threadIdx.x;
   if (x >= cnt) return;
   double v = 0.0;
@@ -772,7 +772,7 @@ hipError_t launch_conv(fmm_plan* pl, const SegTable& st, const void* W, hipStrea
 
 hipError_t launch_split_reduce(fmm_plan* pl, const SegTable& st, hipStream_t s) {
   if (!st.nseg) return hipSuccess;
-  hipLaunchKernelGGL(k_split_reduce, dim3(st.blocks), dim3(256), 0, s, st.dev, st.nseg, loc_stride(pl->p));
+  hipLaunchKernelGGL(k_split_reduce, dim3(st.blocks), dim3(256), 0, s, st.dev, st.nseg);
   return hipGetLastError();
 }
 
@@ -898,6 +898,7 @@ hipError_t backward_ct(fmm_plan* pl, const TI* dphi, const TI* dg, TO* drho, hip
     if ((e = launch_conv<P, double, CV_M2LT>(pl, pl->s_m2lt[0], pl->wt_m2l[0], s)) != hipSuccess) return e;
     if constexpr (!std::is_same<CT, double>::value)
       if ((e = launch_conv<P, CT, CV_M2LT>(pl, pl->s_m2lt[1], pl->wt_m2l[Mf<CT>::IDX], s)) != hipSuccess) return e;
+    if ((e = launch_split_reduce(pl, pl->s_m2lt_red, s)) != hipSuccess) return e;
   }
   // transposed M2P at the finest level
   if (bottom_low(pl, F))

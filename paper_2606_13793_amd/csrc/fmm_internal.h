@@ -178,6 +178,7 @@ struct Seg {
   int field;  // index into the I/O table
   int tz;     // tiles along z
   int split;  // convolutions: blocks sharing one tile, each summing a slice of the offsets
+  long long count;  // reductions: values per part
   const double* a;
   double* b;
   const double* c;
@@ -250,7 +251,9 @@ struct fmm_plan {
   fmm::SegTable s_bot[2][2];        // bottom [FP64 | low][tile depth 16 | 8]
   fmm::SegTable s_red[2];           // reductions of split forward M2L partial sums
   fmm::SegTable s_m2lt[2], s_m2pt;  // adjoint convolutions (field 0)
+  fmm::SegTable s_m2lt_red;         // reductions of the split transposed M2L
   double* conv_part = nullptr;      // partial sums of split forward M2L segments
+  double* adj_part = nullptr;       // partial sums of the split transposed M2L
   // per convolution kind and compute type: (K chunks, first fragment) of
   // every column tile, zero-padded past the last tile
   int* tiletab[3][3] = {};

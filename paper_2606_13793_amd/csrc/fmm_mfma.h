@@ -609,6 +609,7 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
           if (T0 + t < NTILES) o[16 * t] = ldexp((double)acc[m][t][v], escale[t]);
       }
   } else {
+    if (split > 1) dst += (long long)part * ((NM + 3) / 4) * ncellp * 4;
 #pragma unroll
     for (int m = 0; m < CMT; ++m)
 #pragma unroll

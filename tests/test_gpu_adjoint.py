@@ -165,3 +165,19 @@ def test_fp32_adjoint_against_finite_differences(F):
     e = rel(gv, fd)
     _say(f"  rel L2 over 64 cells {e:.3e}")
     assert e < 1e-4, e
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+def test_forward_unchanged_after_backward(F, precision):
+    """The adjoint reuses the plan's multipole grids; a solve after a
+    backward call must equal the solve before it."""
+    import torch
+    _say(f"case forward after backward {precision} n=32 p=4")
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    plan = F.Plan(32, 4, precision, coarse_fp64_levels=0)
+    rho = torch.as_tensor(fi.plummer_density(32, fi.multi_plummer_params(8, 77))).to("cuda", dt)
+    phi1, g1 = plan.solve(rho)
+    plan.backward(torch.randn_like(rho), torch.randn((3, 32, 32, 32), dtype=dt, device="cuda"))
+    phi2, g2 = plan.solve(rho)
+    torch.cuda.synchronize()
+    assert torch.equal(phi1, phi2) and torch.equal(g1, g2)
