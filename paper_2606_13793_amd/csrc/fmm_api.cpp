@@ -136,6 +136,9 @@ void release(fmm_plan* pl) {
   if (pl->adj_l2p) (void)hipFree(pl->adj_l2p);
   if (pl->adj_l2p2) (void)hipFree(pl->adj_l2p2);
   if (pl->m2m_start) (void)hipFree(pl->m2m_start);
+  if (pl->m2mt_start) (void)hipFree(pl->m2mt_start);
+  if (pl->m2mt_a) (void)hipFree(pl->m2mt_a);
+  if (pl->m2mt_coef) (void)hipFree(pl->m2mt_coef);
   if (pl->m2m_off) (void)hipFree(pl->m2m_off);
   if (pl->m2m_coef) (void)hipFree(pl->m2m_coef);
   if (pl->l2l_start) (void)hipFree(pl->l2l_start);
@@ -529,6 +532,32 @@ fmm_plan* create_plan(const std::vector<int>& ns, int p, const fmm_options& o, i
             coef.push_back(std::ldexp(1.0 / (fact(gx) * fact(gy) * fact(gz)), -(x + y + z) - 2 * (gx + gy + gz)));
           }
       start.push_back((int)off.size());
+    }
+    // the same pairs grouped for the transposed M2M: for each b and parity
+    // pattern of g, the terms a = b + g
+    std::vector<int> tstart(1, 0), ta;
+    std::vector<double> tcoef;
+    for (int t = 0; t < pl->NM; ++t) {
+      const int bx = ex[3 * t], by = ex[3 * t + 1], bz = ex[3 * t + 2], bd = bx + by + bz;
+      for (int pat = 0; pat < 8; ++pat) {
+        for (int gx = 0; gx + bd <= P; ++gx)
+          for (int gy = 0; gx + gy + bd <= P; ++gy)
+            for (int gz = 0; gx + gy + gz + bd <= P; ++gz) {
+              if ((((gx & 1) << 2) | ((gy & 1) << 1) | (gz & 1)) != pat) continue;
+              ta.push_back(fmm::mi_index(bx + gx, by + gy, bz + gz));
+              tcoef.push_back(std::ldexp(1.0 / (fact(gx) * fact(gy) * fact(gz)), -bd - 2 * (gx + gy + gz)));
+            }
+        tstart.push_back((int)ta.size());
+      }
+    }
+    if (dev_alloc(pl, (void**)&pl->m2mt_start, tstart.size() * sizeof(int))) return bail();
+    if (dev_alloc(pl, (void**)&pl->m2mt_a, ta.size() * sizeof(int))) return bail();
+    if (dev_alloc(pl, (void**)&pl->m2mt_coef, tcoef.size() * sizeof(double))) return bail();
+    if (hipMemcpy(pl->m2mt_start, tstart.data(), tstart.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(pl->m2mt_a, ta.data(), ta.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(pl->m2mt_coef, tcoef.data(), tcoef.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+      fail(FMM_ERR_DEVICE, "upload failed");
+      return bail();
     }
     if (dev_alloc(pl, (void**)&pl->m2m_start, start.size() * sizeof(int))) return bail();
     if (dev_alloc(pl, (void**)&pl->m2m_off, off.size() * sizeof(int))) return bail();

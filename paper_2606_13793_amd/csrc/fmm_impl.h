@@ -451,65 +451,83 @@ __global__ void k_adj_coef(double* __restrict__ own, double* __restrict__ par, i
     par[((z - 1) * NL + b) * 32 + k] = l2p_parent_coef(b, z - 1, k >> 2, k & 3);
 }
 
-// L2P^T and (parent-level L2P)^T.  Block = 4 level-(F-1) cells P, whose 8
-// children's Ybar (4 x 256 values) are staged in LDS.  Outputs: the adjoint
-// local of every child T = 2P + rp in P's row (column (rp, b)) and, when the
-// parent level has locals, the adjoint full local of P in its parent's row
-// (column (qP, b)).
-__global__ __launch_bounds__(256) void k_adj_l2p(const double* __restrict__ Y, const double* __restrict__ cown,
-                                                 const double* __restrict__ cpar, double* __restrict__ Aown,
-                                                 double* __restrict__ Apar, int nF, int NL, int RS) {
-  __shared__ double y[4][256];
+// L2P^T and (parent-level L2P)^T.  Block = 32 level-(F-1) cells P (consecutive
+// in C order); the Ybar of their 8 children (256 values each) is staged in
+// LDS with an odd row stride.  Thread (parent, slice): the adjoint local of
+// every child T = 2P + rp is written in P's row in 4-column chunks (columns
+// (rp, b) in the M2L order), and, when the parent level has locals, the
+// adjoint full local of P in its parent's row (column (qP, b)).
+constexpr int ADJ_L2P_PAR = 32, ADJ_L2P_THREADS = 256, ADJ_L2P_YS = 257;
+__global__ __launch_bounds__(ADJ_L2P_THREADS) void k_adj_l2p(const double* __restrict__ Y,
+                                                             const double* __restrict__ cown,
+                                                             const double* __restrict__ cpar,
+                                                             double* __restrict__ Aown, double* __restrict__ Apar,
+                                                             int nF, int NL, int RS) {
+  __shared__ double y[ADJ_L2P_PAR * ADJ_L2P_YS];
   const int nP = nF >> 1, nFp = nF + 6, nPp = nP + 6, nPP = nP >> 1, nPPp = nPP + 6;
   const long long ncF = (long long)nFp * nFp * nFp, ncP = (long long)nPp * nPp * nPp,
                   ncPP = (long long)nPPp * nPPp * nPPp;
   const long long nPc = (long long)nP * nP * nP;
-  const long long P0 = (long long)blockIdx.x * 4;
-  for (int w = threadIdx.x; w < 4 * 256; w += 256) {
-    const int pl = w >> 8, k = w & 255, rp = k >> 5, qo = k & 31;
+  const long long P0 = (long long)blockIdx.x * ADJ_L2P_PAR;
+  // staging: load l = (q, parent, rp), children of consecutive parents are
+  // contiguous along z
+  for (int l = threadIdx.x; l < 8 * ADJ_L2P_PAR * 8; l += ADJ_L2P_THREADS) {
+    const int rp = l & 7, pl = (l >> 3) % ADJ_L2P_PAR, q = l / (8 * ADJ_L2P_PAR);
     const long long P = P0 + pl;
-    double v = 0.0;
+    d4 v = d4{0, 0, 0, 0};
     if (P < nPc) {
       const int p2 = (int)(P % nP), p1 = (int)((P / nP) % nP), p0 = (int)(P / ((long long)nP * nP));
       const long long cT = ((long long)(2 * p0 + ((rp >> 2) & 1) + 3) * nFp + (2 * p1 + ((rp >> 1) & 1) + 3)) * nFp +
                            (2 * p2 + (rp & 1) + 3);
-      v = Y[((qo >> 2) * ncF + cT) * 4 + (qo & 3)];
+      v = *reinterpret_cast<const d4*>(Y + (q * ncF + cT) * 4);
     }
-    y[pl][k] = v;
+    double* yy = y + pl * ADJ_L2P_YS + rp * 32 + q * 4;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) yy[e] = v[e];
   }
   __syncthreads();
-  const int per = 8 * NL + (Apar ? NL : 0);
-  for (int w = threadIdx.x; w < 4 * per; w += 256) {
-    const int pl = w / per, j = w % per;
-    const long long P = P0 + pl;
-    if (P >= nPc) continue;
-    const int p2 = (int)(P % nP), p1 = (int)((P / nP) % nP), p0 = (int)(P / ((long long)nP * nP));
-    if (j < 8 * NL) {
-      // own: column j = (rp, b) in the M2L order
-      const int md = m2l_col_degree(j);
-      const int cin = j - 8 * nterms(md - 1);
-      const int rp = cin / ndeg(md), bt = nterms(md - 1) + cin % ndeg(md);
-      const double* c = cown + bt * 32;
-      const double* yy = &y[pl][rp * 32];
+  const int pl = threadIdx.x % ADJ_L2P_PAR, sl = threadIdx.x / ADJ_L2P_PAR;
+  constexpr int NSL = ADJ_L2P_THREADS / ADJ_L2P_PAR;  // slices (8)
+  const long long P = P0 + pl;
+  if (P >= nPc) return;
+  const int p2 = (int)(P % nP), p1 = (int)((P / nP) % nP), p0 = (int)(P / ((long long)nP * nP));
+  const double* yp = y + pl * ADJ_L2P_YS;
+  // own: column chunks of P's row
+  const long long cp = ((long long)(p0 + 3) * nPp + (p1 + 3)) * nPp + (p2 + 3);
+  const int ncol = 8 * NL;
+  for (int cc = sl; cc < RS / 4; cc += NSL) {
+    d4 out;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int j = 4 * cc + e;
       double acc = 0.0;
-#pragma unroll 8
-      for (int k = 0; k < 32; ++k) acc += c[k] * yy[k];
-      const long long cp = ((long long)(p0 + 3) * nPp + (p1 + 3)) * nPp + (p2 + 3);
-      Aown[((j >> 2) * ncP + cp) * 4 + (j & 3)] = acc;
-    } else {
-      const int bt = j - 8 * NL;
-      double acc = 0.0;
-      for (int rp = 0; rp < 8; ++rp) {
-        const double* c = cpar + (rp * NL + bt) * 32;
-        const double* yy = &y[pl][rp * 32];
+      if (j < ncol) {
+        const int md = m2l_col_degree(j);
+        const int cin = j - 8 * nterms(md - 1);
+        const int rp = cin / ndeg(md), bt = nterms(md - 1) + cin % ndeg(md);
+        const double* c = cown + bt * 32;
+        const double* yy = yp + rp * 32;
 #pragma unroll 8
         for (int k = 0; k < 32; ++k) acc += c[k] * yy[k];
       }
-      const int ex = c_mi_exp[bt];
-      const int col = m2l_col(((p0 & 1) << 2) | ((p1 & 1) << 1) | (p2 & 1), bt, mi_a(ex) + mi_b(ex) + mi_c(ex));
-      const long long cpp = ((long long)((p0 >> 1) + 3) * nPPp + ((p1 >> 1) + 3)) * nPPp + ((p2 >> 1) + 3);
-      Apar[((col >> 2) * ncPP + cpp) * 4 + (col & 3)] = acc;
+      out[e] = acc;
     }
+    *reinterpret_cast<d4*>(Aown + (cc * ncP + cp) * 4) = out;
+  }
+  if (!Apar) return;
+  const int qP = ((p0 & 1) << 2) | ((p1 & 1) << 1) | (p2 & 1);
+  const long long cpp = ((long long)((p0 >> 1) + 3) * nPPp + ((p1 >> 1) + 3)) * nPPp + ((p2 >> 1) + 3);
+  for (int bt = sl; bt < NL; bt += NSL) {
+    double acc = 0.0;
+    for (int rp = 0; rp < 8; ++rp) {
+      const double* c = cpar + (rp * NL + bt) * 32;
+      const double* yy = yp + rp * 32;
+#pragma unroll 8
+      for (int k = 0; k < 32; ++k) acc += c[k] * yy[k];
+    }
+    const int ex = c_mi_exp[bt];
+    const int col = m2l_col(qP, bt, mi_a(ex) + mi_b(ex) + mi_c(ex));
+    Apar[((col >> 2) * ncPP + cpp) * 4 + (col & 3)] = acc;
   }
 }
 
@@ -554,51 +572,79 @@ __global__ __launch_bounds__(256) void k_adj_l2l(const double* __restrict__ Ak, 
 
 // M2M^T for one level k: Mbar_k[2P+q][b] += sum_{a >= b}
 //   2^-|b| 4^-|g| / g! (-1)^(q.g) Mbar_{k-1}[P][a],  g = a - b.
-// Thread = (cell P of level k-1, term b); the 8 sign patterns of g are summed
-// first and the children are formed by a Walsh transform.
-__global__ __launch_bounds__(256) void k_adj_m2m(const double* __restrict__ Mp, double* __restrict__ Mc, int np,
-                                                 int P, int NM) {
-  const long long nps = (long long)np * np * np;
-  const long long id = blockIdx.x * 256LL + threadIdx.x;
-  if (id >= nps * NM) return;
-  const long long Pc = id / NM;
-  const int bt = (int)(id % NM);
-  const int p2 = (int)(Pc % np), p1 = (int)((Pc / np) % np), p0 = (int)(Pc / ((long long)np * np));
+// Block = 16 cells P of level k - 1 (consecutive in C order), whose adjoint
+// multipoles are staged in LDS with the plan's coefficient lists (for each
+// (b, parity pattern of g): the entries a = b + g and their weights).  Thread
+// (parent, b) forms the 8 pattern sums, then the children by a Walsh
+// transform.  Segments are not used: one level per launch.
+constexpr int ADJ_M2M_PAR = 16, ADJ_M2M_THREADS = 256;
+template <int PO>
+__global__ __launch_bounds__(ADJ_M2M_THREADS) void k_adj_m2m(const double* __restrict__ Mp, double* __restrict__ Mc,
+                                                             int np, const int* __restrict__ lstart,
+                                                             const int* __restrict__ la,
+                                                             const double* __restrict__ lcoef) {
+  constexpr int NM = nterms(PO), NC = (NM + 3) / 4, MS = NM | 1;
+  constexpr int NE = (PO + 1) * (PO + 2) * (PO + 3) * (PO + 4) * (PO + 5) * (PO + 6) / 720;
+  __shared__ double mrow[ADJ_M2M_PAR * MS];
+  __shared__ int sstart[NM * 8 + 1];
+  __shared__ int sa[NE];
+  __shared__ double scoef[NE];
   const int npp = np + 6, nk = 2 * np, nkp = nk + 6;
   const long long ncp = (long long)npp * npp * npp, nck = (long long)nkp * nkp * nkp;
-  const long long cp = ((long long)(p0 + 3) * npp + (p1 + 3)) * npp + (p2 + 3);
-  const int ex = c_mi_exp[bt];
-  const int bx = mi_a(ex), by = mi_b(ex), bz = mi_c(ex), bd = bx + by + bz;
-  double S[8];
+  const long long nps = (long long)np * np * np;
+  const long long P0 = (long long)blockIdx.x * ADJ_M2M_PAR;
+  for (int t = threadIdx.x; t <= NM * 8; t += ADJ_M2M_THREADS) sstart[t] = lstart[t];
+  for (int t = threadIdx.x; t < NE; t += ADJ_M2M_THREADS) {
+    sa[t] = la[t];
+    scoef[t] = lcoef[t];
+  }
+  for (int l = threadIdx.x; l < NC * ADJ_M2M_PAR; l += ADJ_M2M_THREADS) {
+    const int pl = l % ADJ_M2M_PAR, c = l / ADJ_M2M_PAR;
+    const long long P = P0 + pl;
+    d4 v = d4{0, 0, 0, 0};
+    if (P < nps) {
+      const int p2 = (int)(P % np), p1 = (int)((P / np) % np), p0 = (int)(P / ((long long)np * np));
+      const long long cp = ((long long)(p0 + 3) * npp + (p1 + 3)) * npp + (p2 + 3);
+      v = *reinterpret_cast<const d4*>(Mp + (c * ncp + cp) * 4);
+    }
 #pragma unroll
-  for (int k = 0; k < 8; ++k) S[k] = 0.0;
-  for (int gx = 0; gx + bd <= P; ++gx)
-    for (int gy = 0; gx + gy + bd <= P; ++gy)
-      for (int gz = 0; gx + gy + gz + bd <= P; ++gz) {
-        const int a = mi_index(bx + gx, by + gy, bz + gz);
-        const double x = ldexp(c_mi_invfact[mi_index(gx, gy, gz)], -bd - 2 * (gx + gy + gz)) *
-                         Mp[((a >> 2) * ncp + cp) * 4 + (a & 3)];
-        const int pat = ((gx & 1) << 2) | ((gy & 1) << 1) | (gz & 1);
+    for (int e = 0; e < 4; ++e)
+      if (4 * c + e < NM) mrow[pl * MS + 4 * c + e] = v[e];
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < ADJ_M2M_PAR * NM; w += ADJ_M2M_THREADS) {
+    const int pl = w % ADJ_M2M_PAR, bt = w / ADJ_M2M_PAR;
+    const long long P = P0 + pl;
+    if (P >= nps) continue;
+    const double* mr = mrow + pl * MS;
+    double S[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
-          if (k == pat) S[k] += x;
-      }
+    for (int pat = 0; pat < 8; ++pat) {
+      double x = 0.0;
+      for (int j = sstart[bt * 8 + pat]; j < sstart[bt * 8 + pat + 1]; ++j) x += scoef[j] * mr[sa[j]];
+      S[pat] = x;
+    }
+    const int p2 = (int)(P % np), p1 = (int)((P / np) % np), p0 = (int)(P / ((long long)np * np));
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    double v = 0.0;
+    for (int q = 0; q < 8; ++q) {
+      double v = 0.0;
 #pragma unroll
-    for (int pat = 0; pat < 8; ++pat) v += (__popc(q & pat) & 1) ? -S[pat] : S[pat];
-    const long long cc = ((long long)(2 * p0 + ((q >> 2) & 1) + 3) * nkp + (2 * p1 + ((q >> 1) & 1) + 3)) * nkp +
-                         (2 * p2 + (q & 1) + 3);
-    Mc[((bt >> 2) * nck + cc) * 4 + (bt & 3)] += v;
+      for (int pat = 0; pat < 8; ++pat) v += (__popc(q & pat) & 1) ? -S[pat] : S[pat];
+      const long long cc = ((long long)(2 * p0 + ((q >> 2) & 1) + 3) * nkp + (2 * p1 + ((q >> 1) & 1) + 3)) * nkp +
+                           (2 * p2 + (q & 1) + 3);
+      Mc[((bt >> 2) * nck + cc) * 4 + (bt & 3)] += v;
+    }
   }
 }
 
-// P2M^T + near^T: rho_bar[w] = sum_a 4^-|a| / a! (-1)^(q_w.a) Mbar_F[T_w][a]
-//   + sum_{e in [-1,1]^3} sum_{(q,o)} p2p_coef(q_w - 2e, q, o) Ybar_{T_w+e}[(q,o)].
-// Block = 8^3 unigrid cells (4^3 level-F cells); the Ybar of the 6^3 cells
-// around them and the near-field stencil are staged in LDS.
-constexpr int ADJ_BOT_THREADS = 512;
+// P2M^T + near^T for the 8 unigrid children w = 2T + q_w of a level-F cell T:
+//   rho_bar[w] = sum_a 4^-|a| / a! (-1)^(q_w.a) Mbar_F[T][a]
+//     + sum_{e in [-1,1]^3} sum_{(q,o)} p2p_coef(q_w - 2e, q, o) Ybar_{T+e}[(q,o)].
+// Thread = cell T (block = 4^3 cells): each neighbour's 32 values are read
+// once from LDS and applied to all 8 children; the stencil weights depend
+// only on (e, q, q_w) and are read from LDS tables at uniform addresses.
+// The P2M^T part is a Walsh transform of 8 signed sums of the cell's terms.
+constexpr int ADJ_BOT_THREADS = 64;
 template <typename TO>
 __global__ __launch_bounds__(ADJ_BOT_THREADS) void k_adj_bottom(const double* __restrict__ Mb,
                                                                 const double* __restrict__ Y, TO* __restrict__ drho,
@@ -616,48 +662,63 @@ __global__ __launch_bounds__(ADJ_BOT_THREADS) void k_adj_bottom(const double* __
     ys[h] = *reinterpret_cast<const d4*>(Y + (q * ncellp + cp) * 4);
   }
   for (int t = threadIdx.x; t < 343; t += ADJ_BOT_THREADS) {
-    sp[t] = c_p2p_phi[t];
-    sg3[t] = c_p2p_g[t];
-    sg3[343 + t] = c_p2p_g[343 + t];
-    sg3[686 + t] = c_p2p_g[686 + t];
+    sp[t] = 2.0 * c_p2p_phi[t];
+    sg3[t] = -4.0 * c_p2p_g[t];
+    sg3[343 + t] = -4.0 * c_p2p_g[343 + t];
+    sg3[686 + t] = -4.0 * c_p2p_g[686 + t];
   }
   __syncthreads();
-  const int lz = threadIdx.x & 7, ly = (threadIdx.x >> 3) & 7, lx = threadIdx.x >> 6;
-  const int qw0 = lx & 1, qw1 = ly & 1, qw2 = lz & 1;
-  const int tl0 = lx >> 1, tl1 = ly >> 1, tl2 = lz >> 1;
-  double acc = 0.0;
-  for (int e0 = -1; e0 <= 1; ++e0)
-    for (int e1 = -1; e1 <= 1; ++e1)
-      for (int e2 = -1; e2 <= 1; ++e2) {
-        const d4* yc = ys + (((tl0 + e0 + 1) * 6 + (tl1 + e1 + 1)) * 6 + (tl2 + e2 + 1)) * 8;
+  const int tl2 = threadIdx.x & 3, tl1 = (threadIdx.x >> 2) & 3, tl0 = threadIdx.x >> 4;
+  double acc[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          // delta = u - w = 2e + q - q_w in [-3, 3]^3
-          const int t = (2 * e0 + ((q >> 2) & 1) - qw0 + 3) * 49 + (2 * e1 + ((q >> 1) & 1) - qw1 + 3) * 7 +
-                        (2 * e2 + (q & 1) - qw2 + 3);
-          const d4 v = yc[q];
-          acc += 2.0 * sp[t] * v[0] - 4.0 * (sg3[t] * v[1] + sg3[343 + t] * v[2] + sg3[686 + t] * v[3]);
-        }
+  for (int qw = 0; qw < 8; ++qw) acc[qw] = 0.0;
+  for (int e = 0; e < 27; ++e) {
+    const int e0 = e / 9 - 1, e1 = (e / 3) % 3 - 1, e2 = e % 3 - 1;
+    const d4* yc = ys + (((tl0 + e0 + 1) * 6 + (tl1 + e1 + 1)) * 6 + (tl2 + e2 + 1)) * 8;
+    // delta = u - w = 2e + q - q_w in [-3, 3]^3; index base of 2e
+    const int tb = (2 * e0 + 3) * 49 + (2 * e1 + 3) * 7 + (2 * e2 + 3);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const d4 v = yc[q];
+#pragma unroll
+      for (int qw = 0; qw < 8; ++qw) {
+        const int t = tb + ((((q >> 2) & 1) - ((qw >> 2) & 1)) * 49 + (((q >> 1) & 1) - ((qw >> 1) & 1)) * 7 +
+                            ((q & 1) - (qw & 1)));
+        acc[qw] += sp[t] * v[0] + sg3[t] * v[1] + sg3[343 + t] * v[2] + sg3[686 + t] * v[3];
       }
-  // P2M^T from the adjoint multipoles of the cell's own level-F cell
+    }
+  }
+  // P2M^T from the adjoint multipoles of the cell
   const int t0 = T0x + tl0, t1 = T0y + tl1, t2 = T0z + tl2;
   const long long cp = ((long long)(t0 + 3) * nFp + (t1 + 3)) * nFp + (t2 + 3);
-  const int qw = (qw0 << 2) | (qw1 << 1) | qw2;
+  double S[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) S[k] = 0.0;
   for (int c = 0; c < (NM + 3) / 4; ++c) {
     const d4 m = *reinterpret_cast<const d4*>(Mb + (c * ncellp + cp) * 4);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int a = 4 * c + e;
-      if (a >= NM) break;
-      const int ex = c_mi_exp[a];
-      const int ax = mi_a(ex), ay = mi_b(ex), az = mi_c(ex);
-      const int pat = ((ax & 1) << 2) | ((ay & 1) << 1) | (az & 1);
-      const double x = ldexp(c_mi_invfact[a], -2 * (ax + ay + az)) * m[e];
-      acc += (__popc(qw & pat) & 1) ? -x : x;
+      if (a < NM) {
+        const int ex = c_mi_exp[a];
+        const int ax = mi_a(ex), ay = mi_b(ex), az = mi_c(ex);
+        const int pat = ((ax & 1) << 2) | ((ay & 1) << 1) | (az & 1);
+        const double x = ldexp(c_mi_invfact[a], -2 * (ax + ay + az)) * m[e];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (k == pat) S[k] += x;
+      }
     }
   }
-  const long long w = ((long long)(2 * t0 + qw0) * n + (2 * t1 + qw1)) * n + (2 * t2 + qw2);
-  drho[w] = (TO)acc;
+#pragma unroll
+  for (int qw = 0; qw < 8; ++qw) {
+    double v = acc[qw];
+#pragma unroll
+    for (int pat = 0; pat < 8; ++pat) v += (__popc(qw & pat) & 1) ? -S[pat] : S[pat];
+    const long long w = ((long long)(2 * t0 + ((qw >> 2) & 1)) * n + (2 * t1 + ((qw >> 1) & 1))) * n +
+                        (2 * t2 + (qw & 1));
+    drho[w] = (TO)v;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -884,7 +945,8 @@ hipError_t backward_ct(fmm_plan* pl, const TI* dphi, const TI* dg, TO* drho, hip
   if (F >= 3) {
     // transposed L2P of the own local and of the parent level's local
     const long long nP = nT / 8;
-    hipLaunchKernelGGL(k_adj_l2p, dim3(blocks_for(nP, 4)), dim3(256), 0, s, pl->ybar, pl->adj_l2p, pl->adj_l2p2,
+    hipLaunchKernelGGL(k_adj_l2p, dim3(blocks_for(nP, ADJ_L2P_PAR)), dim3(ADJ_L2P_THREADS), 0, s, pl->ybar,
+                       pl->adj_l2p, pl->adj_l2p2,
                        pl->abar[F], F >= 4 ? pl->abar[F - 1] : nullptr, nF, NL, loc_stride(P));
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // transposed L2L chain, fine to coarse
@@ -909,8 +971,9 @@ hipError_t backward_ct(fmm_plan* pl, const TI* dphi, const TI* dg, TO* drho, hip
   // transposed M2M chain, coarse to fine
   for (int k = 3; k <= F; ++k) {
     const int np = 1 << (k - 1);
-    hipLaunchKernelGGL(k_adj_m2m, dim3(blocks_for((long long)np * np * np * NM, 256)), dim3(256), 0, s,
-                       (const double*)pl->lev[k - 1].M, (double*)pl->lev[k].M, np, P, NM);
+    hipLaunchKernelGGL((k_adj_m2m<P>), dim3(blocks_for((long long)np * np * np, ADJ_M2M_PAR)), dim3(ADJ_M2M_THREADS),
+                       0, s, (const double*)pl->lev[k - 1].M, (double*)pl->lev[k].M, np, pl->m2mt_start,
+                       pl->m2mt_a, pl->m2mt_coef);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   dim3 bgrid(nF / 4, nF / 4, nF / 4);

@@ -239,6 +239,9 @@ struct fmm_plan {
   int* m2m_start = nullptr;     // M2M coefficient lists (CSR over multipole terms)
   int* m2m_off = nullptr;       // 8 b + parity pattern of g, for b + g = a
   double* m2m_coef = nullptr;   // 2^-|b| 4^-|g| / g!
+  int* m2mt_start = nullptr;    // transposed M2M lists: CSR over (b, parity pattern of g)
+  int* m2mt_a = nullptr;        // a = b + g
+  double* m2mt_coef = nullptr;  // 2^-|b| 4^-|g| / g!
   int* l2l_start = nullptr;     // L2L coefficient lists (CSR over local terms)
   int* l2l_idx = nullptr;       // (index of b+g) << 3 | parity pattern of g
   double* l2l_coef = nullptr;
