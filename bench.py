@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed-precision, equal-accuracy, adjoint and batch sections")
-    ap.add_argument("--section", default=None, choices=["mixed", "adjoint", "batch"],
+    ap.add_argument("--section", default=None, choices=["mixed", "adjoint", "batch", "large"],
                     help="run only this extra section (for profiling) and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device-to-device copy of BYTES bytes (a known-size "
@@ -109,7 +109,37 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def run_extras(args, rho64, fi, fmm, costs, sections=("mixed", "adjoint", "batch")) -> dict:
+def run_large(fi, fmm, costs, n: int = 512, p: int = 6) -> dict:
+    """The same 256-sphere field at 512^3: solve time per policy and the
+    mixed policies' error against the FP64 solve at 4096 sampled cells."""
+    import numpy as np
+    import torch
+    rho64 = fi.plummer_density(n, fi.multi_plummer_params(256, 256), device="cuda")
+    N = n ** 3
+    idx = torch.as_tensor(np.sort(np.random.default_rng(11).choice(N, 4096, replace=False)), device="cuda")
+    out = {"n": n, "p": p}
+    ref = None
+    for prec in ("fp64", "fp32", "bf16"):
+        plan = fmm.Plan(n, p, prec)
+        rho = rho64 if prec == "fp64" else rho64.float()
+        phi = torch.empty((n, n, n), dtype=plan.io_dtype, device="cuda")
+        g = torch.empty((3, n, n, n), dtype=plan.io_dtype, device="cuda")
+        ms = _event_ms(lambda: plan.solve_into(rho, phi, g), 3, 1)
+        ps = phi.reshape(-1)[idx].double().cpu().numpy()
+        rec = {"ms_per_solve": ms, "cells_per_s": N / (ms * 1e-3),
+               "useful_tflops": costs.solve_flops(n, p)["total"] / (ms * 1e-3) / 1e12}
+        if prec == "fp64":
+            ref = ps
+        else:
+            rec["phi_rel_l2_vs_fp64"] = _rel(ps, ref)
+        out[prec] = rec
+        log(f"extras: {n}^3 {prec}: {ms:.1f} ms ({N / (ms * 1e-3):.3e} cells/s)")
+        del plan, phi, g
+        torch.cuda.empty_cache()
+    return out
+
+
+def run_extras(args, rho64, fi, fmm, costs, sections=("mixed", "adjoint", "batch", "large")) -> dict:
     """The other measured rows at the same workload: mixed precision (with
     the equal-accuracy comparison against FP64 at lower order), the adjoint,
     and the uneven 96-field batch against a loop of single solves."""
@@ -192,6 +222,8 @@ def run_extras(args, rho64, fi, fmm, costs, sections=("mixed", "adjoint", "batch
     if adj:
         out["adjoint"] = adj
     torch.cuda.empty_cache()
+    if "large" in sections:
+        out["large_512"] = run_large(fi, fmm, costs)
     if "batch" not in sections:
         return out
     # the uneven batch (96 fields: 55 x 32^3, 27 x 64^3, 14 x 128^3), FP32

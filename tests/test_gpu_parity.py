@@ -113,7 +113,7 @@ def _sample_cells(n, count, seed):
     return np.unique(np.concatenate([corners, rng.choice(n ** 3, count, replace=False)]))
 
 
-@pytest.mark.parametrize("n,p,k,seed", [(128, 6, 32, 128), (256, 6, 256, 256)])
+@pytest.mark.parametrize("n,p,k,seed", [(128, 6, 32, 128), (256, 6, 256, 256), (512, 6, 256, 256)])
 def test_fp64_full_size_sampled(F, orc, n, p, k, seed):
     """Full-size workloads (the benchmark's launch configuration), checked at
     sampled cells that the oracle evaluates one by one."""
