@@ -82,6 +82,14 @@ struct LaneRole {
   }
 };
 
+// The list entry a lane uses for one offset group.  With one offset per
+// MFMA the entry is wave-uniform and is read into a scalar register, so its
+// decode runs on the scalar unit; with two (BF16) each lane reads the entry
+// of its half of the K range.
+struct EntryGroup {
+  int e;
+};
+
 // ---------------------------------------------------------------------------
 // Bottom of the downward pass for the unigrid children of level-F cells:
 // columns (q, o), o in {phi, gx, gy, gz}; 32 columns = 2 tiles.  After the
@@ -106,11 +114,11 @@ struct BotShape {
 };
 
 // LDS halo layout: element (hx, hy, hz, k) at hx XS + hy YS + (hz & 1) HZ2 KC +
-// (hz >> 1) KC + (k ^ swz(hy)), z de-interleaved by parity.  The 16 rows of
-// an operand fragment are 8 z cells x 2 y cells two apart; they are spread
-// over the LDS banks by an odd y stride in doubles for FP64 (8-byte reads)
-// and, for BF16 (16-byte reads, which must stay 16-byte aligned), by swapping
-// the two 16-byte halves of a cell on every other pair of y rows.
+// (hz >> 1) KC + k, z de-interleaved by parity.  The 16 rows of an operand
+// fragment are 8 z cells x 2 y cells two apart; for FP64 (8-byte reads) an odd
+// y stride in doubles spreads them over the LDS banks.  An operand address is
+// a per-lane part (fixed for the kernel) + a per-offset part (uniform) + a
+// per-row-tile constant, so each offset costs one vector add.
 template <typename CT, int BZ>
 struct Halo {
   static constexpr int KC = Mf<CT>::KC, HZ2 = BotShape<BZ>::HZ2;
@@ -121,8 +129,18 @@ struct Halo {
   __device__ static int cell(int hx, int hy, int hz) {
     return hx * XS + hy * YS + ((hz & 1) * HZ2 + (hz >> 1)) * KC;
   }
-  __device__ static int swz(int hy) { return Mf<CT>::IDX == 2 ? ((hy >> 1) & 1) * 8 : 0; }
+  // per-offset part: halo cell 3 + r - d of row g = 0 (z by parity plane)
+  __device__ static int offset_part(int r0, int r1, int r2, int d0, int d1, int d2) {
+    const int zz = 3 + r2 - d2;
+    return (3 + r0 - d0) * XS + (3 + r1 - d1) * YS + ((zz & 1) * HZ2 + (zz >> 1)) * KC;
+  }
 };
+// per-row-tile constant of an operand address: lattice x = m / TPX and
+// y = YPT (m % TPX) of row tile m
+template <typename HL, int TPX, int YPT>
+__device__ constexpr int tile_part(int m) {
+  return 2 * (m / TPX) * HL::XS + 2 * YPT * (m % TPX) * HL::YS;
+}
 
 // Segments: n = nF (level-F cells per axis), tpa = tiles along x and y,
 // tz = tiles along z, field, a = Mhat_F, c = Lam_F (or null), d = the parent
@@ -172,6 +190,8 @@ __global__ __launch_bounds__(BOT_THREADS, bottom_min_waves<CT>()) void k_bottom(
   const long long ncellp = (long long)nFp * nFp * nFp;
   const int tx0 = (lb / (sg.tpa * sg.tz)) * BX, ty0 = ((lb / sg.tz) % sg.tpa) * BY, tz0 = (lb % sg.tz) * BZ;
   const int gz = i % BZ2, gyo = i / BZ2;
+  // per-lane part of the operand addresses: row (gyo, gz) and the lane's K slice
+  const H* hlane = halo + 2 * gyo * HL::YS + gz * KC + lr.tic;
 
   Acc acc[BOT_MT][2];
 #pragma unroll
@@ -192,43 +212,45 @@ __global__ __launch_bounds__(BOT_THREADS, bottom_min_waves<CT>()) void k_bottom(
       const int px = tx0 + hx, py = ty0 + hy, pz = tz0 + hz;  // padded coordinates
       const bool in = px < nFp && py < nFp && pz < nFp;
       H* dst = halo + HL::cell(hx, hy, hz);
-      const int sw = HL::swz(hy);
 #pragma unroll
       for (int s4 = 0; s4 < KC / 4; ++s4) {
         const int sc = c * (KC / 4) + s4;
         d4 v = d4{0, 0, 0, 0};
         if (in && sc < NC4) v = *reinterpret_cast<const d4*>(Mh + (sc * ncellp + ((long long)px * nFp + py) * nFp + pz) * 4);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) dst[(4 * s4 + e) ^ sw] = static_cast<H>(v[e]);
+        for (int e = 0; e < 4; ++e) dst[4 * s4 + e] = static_cast<H>(v[e]);
       }
     }
     __syncthreads();
     const H* wc = Wm2p + (size_t)c * NSLOT * 2 * EL * VPL + lr.tl * VPL;
-    auto bload = [&](int e, int t) {
-      return *reinterpret_cast<const AF*>(wc + ((size_t)dl_dd(e) * 2 + t) * EL * VPL);
+    auto bload = [&](EntryGroup g, int t) {
+      return *reinterpret_cast<const AF*>(wc + ((size_t)dl_dd(g.e) * 2 + t) * EL * VPL);
     };
     // A fragments of offset group j: source halo cell of row (gx, gy, gz) is
     // 3 + 2 g + r - d.  Three register slots for the list entries, the B
     // fragments and the A fragments of groups j, j + 1, j + 2 (the loop is
     // unrolled by three, so no slot is copied): B is loaded two groups
     // ahead, A one group ahead, while the current group's products run.
-    auto aload = [&](int e, AF (&a)[BOT_MT]) {
-      const int d0 = dl_d0(e), d1 = dl_d1(e), d2 = dl_d2(e);
-      const int zz = 3 + r2 - d2;  // in [1, 6]
-      const int zoff = (zz & 1) * HZ2 + gz + (zz >> 1);
+    auto aload = [&](EntryGroup g, AF (&a)[BOT_MT]) {
+      const H* base = hlane + HL::offset_part(r0, r1, r2, dl_d0(g.e), dl_d1(g.e), dl_d2(g.e));
 #pragma unroll
-      for (int m = 0; m < BOT_MT; ++m) {
-        const int hx = 3 + 2 * (m / TPX) + r0 - d0;
-        const int hy = 3 + 2 * (YPT * (m % TPX) + gyo) + r1 - d1;
-        a[m] = *reinterpret_cast<const AF*>(halo + hx * HL::XS + hy * HL::YS + zoff * KC + (lr.tic ^ HL::swz(hy)));
-      }
+      for (int m = 0; m < BOT_MT; ++m)
+        a[m] = *reinterpret_cast<const AF*>(base + tile_part<HL, TPX, YPT>(m));
     };
-    int es[3];
+    auto group = [&](int j) {
+      EntryGroup g;
+      if constexpr (OPM == 1)
+        g.e = __builtin_amdgcn_readfirstlane(entry(j));
+      else
+        g.e = entry(OPM * j + lr.sel);
+      return g;
+    };
+    EntryGroup es[3];
     AF bs[3][2], as[3][BOT_MT];
-    es[0] = entry(lr.sel);
+    es[0] = group(0);
     bs[0][0] = bload(es[0], 0);
     bs[0][1] = bload(es[0], 1);
-    es[1] = entry(OPM + lr.sel);
+    es[1] = group(1);
     bs[1][0] = bload(es[1], 0);
     bs[1][1] = bload(es[1], 1);
     aload(es[0], as[0]);
@@ -238,7 +260,7 @@ __global__ __launch_bounds__(BOT_THREADS, bottom_min_waves<CT>()) void k_bottom(
         const int jj = j + u, cur = u, nx = (u + 1) % 3, nn = (u + 2) % 3;
         if (jj < NGRP) {
           if (jj + 2 < NGRP) {
-            es[nn] = entry(OPM * (jj + 2) + lr.sel);
+            es[nn] = group(jj + 2);
             bs[nn][0] = bload(es[nn], 0);
             bs[nn][1] = bload(es[nn], 1);
           }
@@ -498,6 +520,8 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   const LaneRole<CT> lr(lane);
   const int r0 = (r >> 2) & 1, r1 = (r >> 1) & 1, r2 = r & 1;
   const int gz = i % BZ2, gyo = i / BZ2;  // row i of tile m: lattice (m / TPX, YPT (m % TPX) + gyo, gz)
+  // per-lane part of the operand addresses: row (gyo, gz) and the lane's K slice
+  const H* hlane = halo + 2 * gyo * HL::YS + gz * KC + lr.tic;
 
   Acc acc[CMT][NT];
 #pragma unroll
@@ -514,8 +538,16 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
     return dl[pos < NLIST ? pos : pos - NLIST];
   };
   const H* wl = Wt + lr.tl * VPL;
-  auto bload = [&](int e, int t, int c) {
-    return *reinterpret_cast<const AF*>(wl + ((size_t)(off[t] + c) * NSLOT + dl_dd(e)) * EL * VPL);
+  auto bload = [&](EntryGroup g, int t, int c) {
+    return *reinterpret_cast<const AF*>(wl + ((size_t)(off[t] + c) * NSLOT + dl_dd(g.e)) * EL * VPL);
+  };
+  auto group = [&](int j) {
+    EntryGroup g;
+    if constexpr (OPM == 1)
+      g.e = __builtin_amdgcn_readfirstlane(entry(j));
+    else
+      g.e = entry(OPM * j + lr.sel);
+    return g;
   };
 
   for (int c = 0; c < CM; ++c) {
@@ -525,14 +557,13 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
       const int px = tx0 + hx, py = ty0 + hy, pz = tz0 + hz;
       const bool in = px < nsp && py < nsp && pz < nsp;
       H* hd = halo + HL::cell(hx, hy, hz);
-      const int sw = HL::swz(hy);
 #pragma unroll
       for (int s4 = 0; s4 < KC / 4; ++s4) {
         const int sc = c * (KC / 4) + s4;
         d4 v = d4{0, 0, 0, 0};
         if (in && sc < NC4) v = *reinterpret_cast<const d4*>(src + (sc * ncellp + ((long long)px * nsp + py) * nsp + pz) * 4);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) hd[(4 * s4 + e) ^ sw] = static_cast<H>(v[e]);
+        for (int e = 0; e < 4; ++e) hd[4 * s4 + e] = static_cast<H>(v[e]);
       }
     }
     __syncthreads();
@@ -540,21 +571,16 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
     // Three register slots for the list entries, the B fragments and the A
     // fragments of groups j, j + 1, j + 2 (the loop is unrolled by three, so
     // no slot is copied): B is loaded two groups ahead, A one group ahead.
-    auto aload = [&](int e, AF (&a)[CMT]) {
-      const int d0 = dl_d0(e), d1 = dl_d1(e), d2 = dl_d2(e);
-      const int zz = 3 + r2 - d2;
-      const int zoff = (zz & 1) * HZ2 + gz + (zz >> 1);
+    auto aload = [&](EntryGroup g, AF (&a)[CMT]) {
+      const H* base = hlane + HL::offset_part(r0, r1, r2, dl_d0(g.e), dl_d1(g.e), dl_d2(g.e));
 #pragma unroll
-      for (int m = 0; m < CMT; ++m) {
-        const int hx = 3 + 2 * (m / TPX) + r0 - d0;
-        const int hy = 3 + 2 * (YPT * (m % TPX) + gyo) + r1 - d1;
-        a[m] = *reinterpret_cast<const AF*>(halo + hx * HL::XS + hy * HL::YS + zoff * KC + (lr.tic ^ HL::swz(hy)));
-      }
+      for (int m = 0; m < CMT; ++m)
+        a[m] = *reinterpret_cast<const AF*>(base + tile_part<HL, TPX, YPT>(m));
     };
-    int es[3];
+    EntryGroup es[3];
     AF bs[3][NT], as[3][CMT];
-    es[0] = entry(OPM * j0 + lr.sel);
-    es[1] = entry(OPM * (j0 + 1) + lr.sel);
+    es[0] = group(j0);
+    es[1] = group(j0 + 1);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       if (c < vt[t]) {
@@ -569,7 +595,7 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
         const int jj = j + u, cur = u, nx = (u + 1) % 3, nn = (u + 2) % 3;
         if (jj < j1) {
           if (jj + 2 < j1) {
-            es[nn] = entry(OPM * (jj + 2) + lr.sel);
+            es[nn] = group(jj + 2);
 #pragma unroll
             for (int t = 0; t < NT; ++t)
               if (c < vt[t]) bs[nn][t] = bload(es[nn], t, c);
