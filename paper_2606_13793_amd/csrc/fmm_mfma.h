@@ -135,6 +135,65 @@ struct Halo {
     return (3 + r0 - d0) * XS + (3 + r1 - d1) * YS + ((zz & 1) * HZ2 + (zz >> 1)) * KC;
   }
 };
+// A pointer known to address global memory: loads through it are global
+// (vector-memory) loads rather than flat loads, which also hold the LDS
+// counter that the matrix-core loops wait on.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
+// Copies chunk c (KC terms) of an FP64 operand grid, chunked [nc4][np^3][4],
+// into the LDS halo of the tile whose padded origin is (x0, y0, z0),
+// converting to the compute type; cells past the grid's end read as zero.
+// The loads of a batch of cells are all issued before any is stored, so a
+// thread waits for memory once per batch instead of once per cell.
+template <typename CT, int BZ, int NTHR>
+__device__ __forceinline__ void stage_halo(typename Mf<CT>::H* __restrict__ halo, const double* src, int nc4,
+                                           long long ncellp, int np, int x0, int y0, int z0, int c) {
+  using H = typename Mf<CT>::H;
+  using HL = Halo<CT, BZ>;
+  constexpr int S4 = Mf<CT>::KC / 4;
+  constexpr int HZ = BotShape<BZ>::HZ, NH = HX * HY * HZ, NIT = (NH + NTHR - 1) / NTHR;
+  // cells per batch, sized to the registers the kernels leave free: FP64
+  // 5 (40 registers in flight), FP32 2 (16), BF16 1 (the 4 loads of a cell)
+  constexpr int BATCH = Mf<CT>::IDX == 0 ? 5 : (Mf<CT>::IDX == 1 ? 2 : 1);
+  const __attribute__((address_space(1))) d4* g = gmem(reinterpret_cast<const d4*>(src));
+#pragma unroll 1
+  for (int b0 = 0; b0 < NIT; b0 += BATCH) {
+    d4 v[BATCH][S4];
+    int to[BATCH];
+#pragma unroll
+    for (int k = 0; k < BATCH; ++k) {
+      const int h = threadIdx.x + (b0 + k) * NTHR;
+      to[k] = -1;
+#pragma unroll
+      for (int s4 = 0; s4 < S4; ++s4) v[k][s4] = d4{0, 0, 0, 0};
+      if (b0 + k < NIT && h < NH) {
+        const int hz = h % HZ, hy = (h / HZ) % HY, hx = h / (HZ * HY);
+        to[k] = HL::cell(hx, hy, hz);
+        const int px = x0 + hx, py = y0 + hy, pz = z0 + hz;
+        if (px < np && py < np && pz < np) {
+          const long long cell = ((long long)px * np + py) * np + pz;
+#pragma unroll
+          for (int s4 = 0; s4 < S4; ++s4) {
+            const int sc = c * S4 + s4;
+            if (sc < nc4) v[k][s4] = g[sc * ncellp + cell];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < BATCH; ++k)
+      if (to[k] >= 0) {
+#pragma unroll
+        for (int s4 = 0; s4 < S4; ++s4)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) halo[to[k] + 4 * s4 + e] = static_cast<H>(v[k][s4][e]);
+      }
+  }
+}
+
 // per-row-tile constant of an operand address: lattice x = m / TPX and
 // y = YPT (m % TPX) of row tile m
 template <typename HL, int TPX, int YPT>
@@ -207,20 +266,7 @@ __global__ __launch_bounds__(BOT_THREADS, bottom_min_waves<CT>()) void k_bottom(
 
   for (int c = 0; c < NCK; ++c) {
     __syncthreads();  // previous chunk fully consumed
-    for (int h = threadIdx.x; h < HX * HY * HZ; h += BOT_THREADS) {
-      const int hz = h % HZ, hy = (h / HZ) % HY, hx = h / (HZ * HY);
-      const int px = tx0 + hx, py = ty0 + hy, pz = tz0 + hz;  // padded coordinates
-      const bool in = px < nFp && py < nFp && pz < nFp;
-      H* dst = halo + HL::cell(hx, hy, hz);
-#pragma unroll
-      for (int s4 = 0; s4 < KC / 4; ++s4) {
-        const int sc = c * (KC / 4) + s4;
-        d4 v = d4{0, 0, 0, 0};
-        if (in && sc < NC4) v = *reinterpret_cast<const d4*>(Mh + (sc * ncellp + ((long long)px * nFp + py) * nFp + pz) * 4);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) dst[4 * s4 + e] = static_cast<H>(v[e]);
-      }
-    }
+    stage_halo<CT, BZ, BOT_THREADS>(halo, Mh, NC4, ncellp, nFp, tx0, ty0, tz0, c);
     __syncthreads();
     const H* wc = Wm2p + (size_t)c * NSLOT * 2 * EL * VPL + lr.tl * VPL;
     auto bload = [&](EntryGroup g, int t) {
@@ -288,54 +334,81 @@ __global__ __launch_bounds__(BOT_THREADS, bottom_min_waves<CT>()) void k_bottom(
     c2 = c2 < nF ? c2 : 0;
   };
   // tail K blocks of row tile m: L2P of the M2L part of the own local (stored
-  // with the parent P'), L2P from the parent level's full local, near field
+  // with the parent P'), L2P from the parent level's full local, near field.
+  // U chunks at a time, their operand loads issued together.
+  constexpr int U = M::IDX == 0 ? 4 : (M::IDX == 1 ? 2 : 1);
   auto tail = [&](int m, Acc (&am)[2]) {
     int c0, c1, c2;
     cell_of(m, c0, c1, c2);
     if (Lf) {
       const int nP = nF >> 1, nPP = nP >> 1;
-      const double* own = Lf + (((long long)(c0 >> 1) * nP + (c1 >> 1)) * nP + (c2 >> 1)) * RS;
-      const double* par = Lpar ? Lpar + (((long long)(c0 >> 2) * nPP + (c1 >> 2)) * nPP + (c2 >> 2)) * RS : nullptr;
+      const auto own = gmem(Lf + (((long long)(c0 >> 1) * nP + (c1 >> 1)) * nP + (c2 >> 1)) * RS);
+      const auto par =
+          gmem(Lpar ? Lpar + (((long long)(c0 >> 2) * nPP + (c1 >> 2)) * nPP + (c2 >> 2)) * RS : Lf);
       const int qP = (((c0 >> 1) & 1) << 2) | (((c1 >> 1) & 1) << 1) | ((c2 >> 1) & 1);
       const H* w2 = Wl2p2 + (size_t)r * NLT * 2 * 64 * VPL + lane * VPL;
 #pragma unroll 1
-      for (int c = 0; c < NLT; ++c) {
-        double va[VPL], vp[VPL];
+      for (int cb = 0; cb < NLT; cb += U) {
+        double va[U][VPL], vp[U][VPL];
+        AF bo[U][2], bp[U][2];
 #pragma unroll
-        for (int v = 0; v < VPL; ++v) {
-          const int bt = KT * c + VPL * kq + v;
-          const int ex = c_mi_exp[bt < NL ? bt : 0];
-          const int deg = mi_a(ex) + mi_b(ex) + mi_c(ex);
-          va[v] = bt < NL ? own[m2l_col(r, bt, deg)] : 0.0;
-          vp[v] = (bt < NL && par) ? par[m2l_col(qP, bt, deg)] : 0.0;
+        for (int u = 0; u < U; ++u) {
+          const int c = cb + u < NLT ? cb + u : 0;
+#pragma unroll
+          for (int v = 0; v < VPL; ++v) {
+            const int bt = KT * c + VPL * kq + v;
+            const bool ok = cb + u < NLT && bt < NL;
+            const int ex = c_mi_exp[ok ? bt : 0];
+            const int deg = mi_a(ex) + mi_b(ex) + mi_c(ex);
+            va[u][v] = ok ? own[m2l_col(r, bt, deg)] : 0.0;
+            vp[u][v] = (ok && Lpar) ? par[m2l_col(qP, bt, deg)] : 0.0;
+          }
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            bo[u][t] = *reinterpret_cast<const AF*>(Wl2p + ((size_t)(c * 2 + t) * 64 + lane) * VPL);
+            bp[u][t] = Lpar ? *reinterpret_cast<const AF*>(w2 + (size_t)(c * 2 + t) * 64 * VPL) : bo[u][t];
+          }
         }
-        const AF bo0 = *reinterpret_cast<const AF*>(Wl2p + ((size_t)c * 2 * 64 + lane) * VPL);
-        const AF bo1 = *reinterpret_cast<const AF*>(Wl2p + ((size_t)(c * 2 + 1) * 64 + lane) * VPL);
-        am[0] = M::op(M::frag(va), bo0, am[0]);
-        am[1] = M::op(M::frag(va), bo1, am[1]);
-        if (par) {
-          const AF bp0 = *reinterpret_cast<const AF*>(w2 + (size_t)c * 2 * 64 * VPL);
-          const AF bp1 = *reinterpret_cast<const AF*>(w2 + (size_t)(c * 2 + 1) * 64 * VPL);
-          am[0] = M::op(M::frag(vp), bp0, am[0]);
-          am[1] = M::op(M::frag(vp), bp1, am[1]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (cb + u < NLT) {
+            am[0] = M::op(M::frag(va[u]), bo[u][0], am[0]);
+            am[1] = M::op(M::frag(va[u]), bo[u][1], am[1]);
+            if (Lpar) {
+              am[0] = M::op(M::frag(vp[u]), bp[u][0], am[0]);
+              am[1] = M::op(M::frag(vp[u]), bp[u][1], am[1]);
+            }
+          }
         }
       }
     }
+    const auto rg = gmem(rho);
 #pragma unroll 1
-    for (int c = 0; c < NPT; ++c) {
-      double va[VPL];
+    for (int cb = 0; cb < NPT; cb += U) {
+      double va[U][VPL];
+      AF bn[U][2];
 #pragma unroll
-      for (int v = 0; v < VPL; ++v) {
-        const int k = KT * c + VPL * kq + v;
-        const int w0 = 2 * c0 + k / 36 - 2, w1 = 2 * c1 + (k / 6) % 6 - 2, w2 = 2 * c2 + k % 6 - 2;
-        va[v] = (k < 216 && w0 >= 0 && w1 >= 0 && w2 >= 0 && w0 < n && w1 < n && w2 < n)
-                    ? (double)rho[((long long)w0 * n + w1) * n + w2]
-                    : 0.0;
+      for (int u = 0; u < U; ++u) {
+        const int c = cb + u < NPT ? cb + u : 0;
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) {
+          const int k = KT * c + VPL * kq + v;
+          const int w0 = 2 * c0 + k / 36 - 2, w1 = 2 * c1 + (k / 6) % 6 - 2, w2 = 2 * c2 + k % 6 - 2;
+          va[u][v] = (cb + u < NPT && k < 216 && w0 >= 0 && w1 >= 0 && w2 >= 0 && w0 < n && w1 < n && w2 < n)
+                         ? (double)rg[((long long)w0 * n + w1) * n + w2]
+                         : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+          bn[u][t] = *reinterpret_cast<const AF*>(Wp2p + ((size_t)(c * 2 + t) * 64 + lane) * VPL);
       }
-      const AF bn0 = *reinterpret_cast<const AF*>(Wp2p + ((size_t)c * 2 * 64 + lane) * VPL);
-      const AF bn1 = *reinterpret_cast<const AF*>(Wp2p + ((size_t)(c * 2 + 1) * 64 + lane) * VPL);
-      am[0] = M::op(M::frag(va), bn0, am[0]);
-      am[1] = M::op(M::frag(va), bn1, am[1]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (cb + u < NPT) {
+          am[0] = M::op(M::frag(va[u]), bn[u][0], am[0]);
+          am[1] = M::op(M::frag(va[u]), bn[u][1], am[1]);
+        }
+      }
     }
   };
 #pragma unroll
@@ -552,20 +625,7 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
 
   for (int c = 0; c < CM; ++c) {
     __syncthreads();
-    for (int h = threadIdx.x; h < HX * HY * HZ; h += M2L_THREADS) {
-      const int hz = h % HZ, hy = (h / HZ) % HY, hx = h / (HZ * HY);
-      const int px = tx0 + hx, py = ty0 + hy, pz = tz0 + hz;
-      const bool in = px < nsp && py < nsp && pz < nsp;
-      H* hd = halo + HL::cell(hx, hy, hz);
-#pragma unroll
-      for (int s4 = 0; s4 < KC / 4; ++s4) {
-        const int sc = c * (KC / 4) + s4;
-        d4 v = d4{0, 0, 0, 0};
-        if (in && sc < NC4) v = *reinterpret_cast<const d4*>(src + (sc * ncellp + ((long long)px * nsp + py) * nsp + pz) * 4);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) hd[4 * s4 + e] = static_cast<H>(v[e]);
-      }
-    }
+    stage_halo<CT, CZ, M2L_THREADS>(halo, src, NC4, ncellp, nsp, tx0, ty0, tz0, c);
     __syncthreads();
     // A fragments of offset group j (source halo cell 3 + 2 g + r - d).
     // Three register slots for the list entries, the B fragments and the A
