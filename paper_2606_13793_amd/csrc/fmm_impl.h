@@ -751,6 +751,8 @@ hipError_t build_tile_table(fmm_plan* pl, int op, hipStream_t s) {
   for (int t = 0; t < nt; ++t) {
     h[2 * t] = conv_tile_chunks(op, pl->p, t, KC);
     h[2 * t + 1] = conv_frag_offset(op, pl->p, t, KC);
+    // the kernel takes the tiles that have a chunk to be a prefix of the group
+    if (t > 0 && h[2 * t] > h[2 * t - 2]) return hipErrorInvalidValue;
   }
   hipError_t e = hipMalloc(&pl->tiletab[op][X], h.size() * sizeof(int));
   if (e != hipSuccess) return e;

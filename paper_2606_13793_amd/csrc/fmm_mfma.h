@@ -538,6 +538,13 @@ struct ConvGroup {
   static constexpr int NT = V == 0 ? WIDE : (WIDE + 1) / 2;
 };
 
+// Calls f(std::integral_constant<int, k>) for k = N, N - 1, ..., 1.
+template <int N, typename F>
+__device__ __forceinline__ void count_down(F&& f) {
+  f(std::integral_constant<int, N>{});
+  if constexpr (N > 1) count_down<N - 1>(f);
+}
+
 // Segments: n = row grid cells per axis, tpa = tiles along x and y, tz =
 // tiles along z, split = number of blocks sharing a tile (each sums a slice of the offsets), a = operand
 // grid (chunked [NK/4][(n+6)^3][4] with a zero margin), b = output (CV_M2L:
@@ -584,7 +591,6 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
     off[t] = e.y;
   }
   const int CM = vt[0];
-  const int j0 = part * NGRP / split, j1 = (part + 1) * NGRP / split;
   const int tx0 = (tb / (tpa * sg.tz)) * CX, ty0 = ((tb / sg.tz) % tpa) * CX, tz0 = (tb % sg.tz) * CZ;
   const long long ncellp = (long long)nsp * nsp * nsp;
   const int lane = threadIdx.x & 63;
@@ -610,65 +616,98 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
     pos += rot;
     return dl[pos < NLIST ? pos : pos - NLIST];
   };
-  const H* wl = Wt + lr.tl * VPL;
-  auto bload = [&](EntryGroup g, int t, int c) {
-    return *reinterpret_cast<const AF*>(wl + ((size_t)(off[t] + c) * NSLOT + dl_dd(g.e)) * EL * VPL);
-  };
-  auto group = [&](int j) {
-    EntryGroup g;
-    if constexpr (OPM == 1)
-      g.e = __builtin_amdgcn_readfirstlane(entry(j));
-    else
-      g.e = entry(OPM * j + lr.sel);
-    return g;
-  };
+  // Packed groups: M2L column tiles of degree p need the single multipole
+  // term a = 0, so one K chunk would carry one useful term in KC.  With one
+  // offset per MFMA (FP64, FP32) such a group instead packs four offsets into
+  // K: lane k-group kq takes offset 4 j + kq, term 0, and its B value from
+  // the k-group-0 lane of that offset's fragment.
+  constexpr bool CAN_PACK = OPM == 1 && OP == CV_M2L;
+  const bool packed = CAN_PACK && m2l_col_degree(16 * T0) == P;
 
-  for (int c = 0; c < CM; ++c) {
-    __syncthreads();
-    stage_halo<CT, CZ, M2L_THREADS>(halo, src, NC4, ncellp, nsp, tx0, ty0, tz0, c);
-    __syncthreads();
-    // A fragments of offset group j (source halo cell 3 + 2 g + r - d).
-    // Three register slots for the list entries, the B fragments and the A
-    // fragments of groups j, j + 1, j + 2 (the loop is unrolled by three, so
-    // no slot is copied): B is loaded two groups ahead, A one group ahead.
+  // One chunk's offset sum.  Three register slots for the list entries, the
+  // B fragments and the A fragments of groups j, j + 1, j + 2 (the loop is
+  // unrolled by three, so no slot is copied): B is loaded two groups ahead,
+  // A one group ahead.  A fragment m of offset d reads halo cell 3 + 2 g + r
+  // - d of its rows.
+  auto offsets = [&](auto pk, auto na, int c) {
+    constexpr bool PK = decltype(pk)::value;
+    constexpr int NA = decltype(na)::value;  // column tiles with chunk c (the first NA)
+    constexpr int NG = PK ? (NLIST + 3) / 4 : NGRP;
+    const int ja = part * NG / split, jb = (part + 1) * NG / split;
+    const H* wl = Wt + (PK ? i : lr.tl) * VPL;
+    const H* hl = PK ? hlane - lr.tic : hlane;
+    auto bload = [&](EntryGroup g, int t) {
+      return *reinterpret_cast<const AF*>(wl + ((size_t)(off[t] + c) * NSLOT + dl_dd(g.e)) * EL * VPL);
+    };
+    auto group = [&](int j) {
+      EntryGroup g;
+      if constexpr (PK)
+        g.e = entry(4 * j + kq);
+      else if constexpr (OPM == 1)
+        g.e = __builtin_amdgcn_readfirstlane(entry(j));
+      else
+        g.e = entry(OPM * j + lr.sel);
+      return g;
+    };
     auto aload = [&](EntryGroup g, AF (&a)[CMT]) {
-      const H* base = hlane + HL::offset_part(r0, r1, r2, dl_d0(g.e), dl_d1(g.e), dl_d2(g.e));
+      const H* base = hl + HL::offset_part(r0, r1, r2, dl_d0(g.e), dl_d1(g.e), dl_d2(g.e));
 #pragma unroll
       for (int m = 0; m < CMT; ++m)
         a[m] = *reinterpret_cast<const AF*>(base + tile_part<HL, TPX, YPT>(m));
     };
     EntryGroup es[3];
-    AF bs[3][NT], as[3][CMT];
-    es[0] = group(j0);
-    es[1] = group(j0 + 1);
+    AF bs[3][NA], as[3][CMT];
+    es[0] = group(ja);
+    es[1] = group(ja + 1);
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      if (c < vt[t]) {
-        bs[0][t] = bload(es[0], t, c);
-        bs[1][t] = bload(es[1], t, c);
-      }
+    for (int t = 0; t < NA; ++t) {
+      bs[0][t] = bload(es[0], t);
+      bs[1][t] = bload(es[1], t);
     }
     aload(es[0], as[0]);
-    for (int j = j0; j < j1; j += 3) {
+    for (int j = ja; j < jb; j += 3) {
 #pragma unroll
       for (int u = 0; u < 3; ++u) {
         const int jj = j + u, cur = u, nx = (u + 1) % 3, nn = (u + 2) % 3;
-        if (jj < j1) {
-          if (jj + 2 < j1) {
+        if (jj < jb) {
+          if (jj + 2 < jb) {
             es[nn] = group(jj + 2);
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
-              if (c < vt[t]) bs[nn][t] = bload(es[nn], t, c);
+            for (int t = 0; t < NA; ++t) bs[nn][t] = bload(es[nn], t);
           }
-          if (jj + 1 < j1) aload(es[nx], as[nx]);
+          if (jj + 1 < jb) aload(es[nx], as[nx]);
 #pragma unroll
           for (int m = 0; m < CMT; ++m)
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
-              if (c < vt[t]) acc[m][t] = M::op(as[cur][m], bs[cur][t], acc[m][t]);
+            for (int t = 0; t < NA; ++t) acc[m][t] = M::op(as[cur][m], bs[cur][t], acc[m][t]);
         }
       }
     }
+  };
+
+  // Tiles are sorted by degree, so the tiles that have chunk c are a prefix
+  // of the group, and its length NA falls as c rises: the chunks with NA
+  // tiles, [vt[NA], vt[NA - 1]), run as one loop with branch-free products.
+  auto chunks = [&](auto pk) {
+    count_down<NT>([&](auto nac) {
+      constexpr int NA = decltype(nac)::value;
+      int cb = 0;
+      if constexpr (NA < NT) cb = vt[NA];
+      for (int c = cb; c < vt[NA - 1]; ++c) {
+        __syncthreads();
+        stage_halo<CT, CZ, M2L_THREADS>(halo, src, NC4, ncellp, nsp, tx0, ty0, tz0, c);
+        __syncthreads();
+        offsets(pk, nac, c);
+      }
+    });
+  };
+  if constexpr (CAN_PACK) {
+    if (packed)
+      chunks(std::true_type{});
+    else
+      chunks(std::false_type{});
+  } else {
+    chunks(std::false_type{});
   }
   // epilogue: element v of tile t is row M::row(v, kq), column 16 (T0 + t) + i
   if constexpr (OP == CV_M2L) {
