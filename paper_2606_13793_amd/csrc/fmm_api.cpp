@@ -871,17 +871,24 @@ static int ensure_adjoint(fmm_plan* pl, hipStream_t s) {
   }
   {
     // segment tables of the transposed convolutions: M2L^T rows are the
-    // sources of every target level, M2P^T rows the level-F cells
+    // sources of every target level, M2P^T rows the level-F cells.
     // The transposed M2L's first column group needs every K chunk (the
-    // degree-0 multipole term couples to all local terms), so each tile's
-    // offset sum is split over kAdjSplit blocks; the partial adjoint
-    // multipoles are added afterwards in a fixed order.
+    // degree-0 multipole term couples to all local terms), and its blocks do
+    // the same work at every level.  A level with fewer tiles than about one
+    // per compute unit splits each tile's offset sum over several blocks;
+    // the partial adjoint multipoles are added afterwards in a fixed order
+    // (a level that is not split is copied).  The finest level comes first,
+    // so its long blocks start first.
     const int klow = fmm::m2l_low_from(pl);
-    constexpr int kAdjSplit = 4;
+    auto adj_split = [&](int k) {
+      const int n = 1 << (k - 1);
+      const long long T = cdiv(n, kConvTile) * cdiv(n, kConvTile) * cdiv(n, kConvTileZ);
+      return T >= 256 ? 1 : (int)std::min<long long>(16, std::max<long long>(2, 256 / T));
+    };
     long long part_doubles = 0;
     for (int k = 3; k <= pl->F; ++k) {
       const long long np = (1LL << (k - 1)) + 6;
-      part_doubles += (long long)kAdjSplit * pl->NC * np * np * np * 4;
+      part_doubles += (long long)adj_split(k) * pl->NC * np * np * np * 4;
     }
     if (dev_alloc(pl, (void**)&pl->adj_part, (size_t)part_doubles * sizeof(double))) return FMM_ERR_OUT_OF_MEMORY;
     // zero once: margins and unused chunk slots are never written, and the
@@ -890,23 +897,24 @@ static int ensure_adjoint(fmm_plan* pl, hipStream_t s) {
       return fail(FMM_ERR_DEVICE, "hipMemset failed");
     SegList lt[2], pt, ltr;
     long long at = 0;
-    for (int k = 3; k <= pl->F; ++k) {
+    for (int k = pl->F; k >= 3; --k) {
+      const int S = adj_split(k);
       fmm::Seg c{};
       c.n = 1 << (k - 1);
       c.tpa = (int)cdiv(c.n, kConvTile);
       c.tz = (int)cdiv(c.n, kConvTileZ);
-      c.split = kAdjSplit;
+      c.split = S;
       c.a = pl->abar[k];
       c.b = pl->adj_part + at;
-      lt[k >= klow ? 1 : 0].add(c, (long long)c.tpa * c.tpa * c.tz * kAdjSplit);
+      lt[k >= klow ? 1 : 0].add(c, (long long)c.tpa * c.tpa * c.tz * S);
       const long long cnt = (long long)pl->NC * (c.n + 6) * (c.n + 6) * (c.n + 6) * 4;
       fmm::Seg r{};
-      r.split = kAdjSplit;
+      r.split = S;
       r.count = cnt;
       r.a = pl->adj_part + at;
       r.b = (double*)pl->lev[k - 1].M;
       ltr.add(r, cdiv(cnt, 256));
-      at += kAdjSplit * cnt;
+      at += S * cnt;
     }
     fmm::Seg c{};
     c.n = nF;
