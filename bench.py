@@ -365,12 +365,21 @@ def main():
         rho_host = rho64.cpu().numpy() if prec == "fp64" else rho.double().cpu().numpy()
         phi_o, g_o, t_up, t_down, threads = oracle.solve_timed(rho_host, p, cells)
         t_full = t_up + t_down * (n ** 3 / len(cells))
+        cpu_model = "unknown CPU"
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        cpu_model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
         cpu = {
             "value": n ** 3 / t_full,
             "unit": "cells/s",
             "cores": threads,
             "kind": "oracle",
-            "sample": (f"FP64 oracle on this host, {threads} OpenMP threads: full upward pass ({t_up:.2f} s) + "
+            "sample": (f"FP64 oracle on this host ({cpu_model}), {threads} OpenMP threads: full upward pass ({t_up:.2f} s) + "
                        f"downward pass for {planes} central unigrid planes ({len(cells)} cells, {t_down:.2f} s); "
                        f"full solve = upward + downward x n^3/{len(cells)} = {t_full:.1f} s"),
         }
