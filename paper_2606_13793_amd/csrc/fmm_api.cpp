@@ -319,7 +319,7 @@ int build_schedule(fmm_plan* pl) {
       l.field = f;
       l.a = (const double*)fd.lev[k - 1].L;
       l.b = (double*)fd.lev[k].L;
-      l2l[k].add(l, cdiv((long long)l.n * l.n * l.n * RS, 256));
+      l2l[k].add(l, cdiv((long long)l.n * l.n * l.n, fmm::L2L_ROWS));
     }
     for (int z = 0; z < 2; ++z) {
       Seg b{};
@@ -495,6 +495,10 @@ fmm_plan* create_plan(const std::vector<int>& ns, int p, const fmm_options& o, i
             coef.push_back(std::ldexp(1.0 / (fact(gx) * fact(gy) * fact(gz)), -(m + 1) - 2 * ng));
           }
       start.push_back((int)idx.size());
+    }
+    if ((int)idx.size() != fmm::l2l_entries(p)) {  // k_l2l stages exactly this many entries
+      fail(FMM_ERR_DEVICE, "L2L coefficient list size");
+      return bail();
     }
     if (dev_alloc(pl, (void**)&pl->l2l_start, start.size() * sizeof(int))) return bail();
     if (dev_alloc(pl, (void**)&pl->l2l_idx, idx.size() * sizeof(int))) return bail();

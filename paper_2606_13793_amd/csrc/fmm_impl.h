@@ -360,44 +360,65 @@ __device__ __forceinline__ double l2p_parent_coef(int bt, int rp, int q, int o) 
 // ---------------------------------------------------------------------------
 // L2L, eq. (L2L), for one level k: Lhat_k[T] += shift of Lhat_{k-1}[parent(T)]
 //   Lhat_k[b] += sum_{|b|+|g|<=p} 2^-(|b|+1) 4^-|g| / g! (2q-1)^g Lhat_{k-1}[b+g]
-// in the per-parent column layout.  Thread = (cell P of level k-1, column
-// (q, b)); lanes run along columns, so loads and stores of the child locals
-// are contiguous and, inside a degree block, every lane walks a list of the
-// same length.  Lists (CSR over b): coefficient and, packed,
-// column base of b+g (column with q = 0) << 9 | ndeg(|b+g|) << 3 | parity of g.
+// in the per-parent column layout.  A block takes L2L_ROWS cells P of level
+// k - 1: it stages the coefficient lists (CSR over b: coefficient and,
+// packed, column base of b+g (column with q = 0) << 9 | ndeg(|b+g|) << 3 |
+// parity of g) and the level-(k-1) local of each P (its terms at their
+// child-0 columns) in LDS; a thread then forms columns (q, b) of P's child
+// locals, so the read-modify-writes of the child rows are contiguous.
 // ---------------------------------------------------------------------------
 // Segments: n = cells per axis of level k - 1, a = Lhat_{k-1}, b = Lhat_k.
+template <int P>
 __global__ __launch_bounds__(256) void k_l2l(const Seg* __restrict__ segs, int nseg, const int* __restrict__ cs,
-                                             const int* __restrict__ cidx, const double* __restrict__ ccoef, int NL,
-                                             int RS) {
+                                             const int* __restrict__ cidx, const double* __restrict__ ccoef) {
+  constexpr int NL = nterms(P), NCOL = 8 * NL, RS = loc_stride(P), E = l2l_entries(P);
+  __shared__ int s_cs[NL + 1];
+  __shared__ int s_idx[E];
+  __shared__ double s_coef[E];
+  __shared__ double s_src[L2L_ROWS][NCOL];
   const Seg& sg = find_seg(segs, nseg, blockIdx.x);
   const double* __restrict__ Lprev = sg.a;
   double* __restrict__ Lk = sg.b;
-  const int ns = sg.n;
+  const int ns = sg.n, nsp = ns >> 1;
   const long long nps = (long long)ns * ns * ns;
-  const long long id = (long long)(blockIdx.x - sg.first_block) * 256 + threadIdx.x;
-  if (id >= nps * RS) return;
-  const long long P = id / RS;
-  const int col = (int)(id % RS);
-  if (col >= 8 * NL) return;
-  const int md = m2l_col_degree(col);
-  const int cin = col - 8 * nterms(md - 1);
-  const int q = cin / ndeg(md);
-  const int bt = nterms(md - 1) + cin % ndeg(md);
-  const int p2 = (int)(P % ns), p1 = (int)((P / ns) % ns), p0 = (int)(P / ((long long)ns * ns));
-  const int nsp = ns >> 1;
-  const long long PP = ((long long)(p0 >> 1) * nsp + (p1 >> 1)) * nsp + (p2 >> 1);
-  const int qP = ((p0 & 1) << 2) | ((p1 & 1) << 1) | (p2 & 1);
-  const int nq = (~q) & 7;  // axes with q_i = 0
-  const double* src = Lprev + PP * RS;
-  double acc = 0.0;
-  for (int j = cs[bt]; j < cs[bt + 1]; ++j) {
-    const int id2 = cidx[j];
-    const int cb = id2 >> 9, nd = (id2 >> 3) & 63, pat = id2 & 7;
-    const double x = ccoef[j] * src[cb + qP * nd];
-    acc += (__popc(nq & pat) & 1) ? -x : x;
+  const long long P0 = (long long)(blockIdx.x - sg.first_block) * L2L_ROWS;
+  for (int t = threadIdx.x; t <= NL; t += 256) s_cs[t] = cs[t];
+  for (int t = threadIdx.x; t < E; t += 256) {
+    s_idx[t] = cidx[t];
+    s_coef[t] = ccoef[t];
   }
-  Lk[P * RS + col] += acc;
+  // P's level-(k-1) local sits in its parent's row, in the column block of
+  // P's position qP
+  for (int e = threadIdx.x; e < L2L_ROWS * NL; e += 256) {
+    const int g = e / NL, c = e - g * NL;
+    const long long Pc = P0 + g;
+    if (Pc >= nps) continue;
+    const int p2 = (int)(Pc % ns), p1 = (int)((Pc / ns) % ns), p0 = (int)(Pc / ((long long)ns * ns));
+    const long long PP = ((long long)(p0 >> 1) * nsp + (p1 >> 1)) * nsp + (p2 >> 1);
+    const int qP = ((p0 & 1) << 2) | ((p1 & 1) << 1) | (p2 & 1);
+    const int ex = c_mi_exp[c];
+    const int d = mi_a(ex) + mi_b(ex) + mi_c(ex);
+    const int cb = m2l_col(0, c, d);
+    s_src[g][cb] = Lprev[PP * RS + cb + qP * ndeg(d)];
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < L2L_ROWS * NCOL; o += 256) {
+    const int g = o / NCOL, col = o - g * NCOL;
+    const long long Pc = P0 + g;
+    if (Pc >= nps) continue;
+    const int md = m2l_col_degree(col);
+    const int cin = col - 8 * nterms(md - 1);
+    const int q = cin / ndeg(md);
+    const int bt = nterms(md - 1) + cin % ndeg(md);
+    const int nq = (~q) & 7;  // axes with q_i = 0
+    double acc = 0.0;
+    for (int j = s_cs[bt]; j < s_cs[bt + 1]; ++j) {
+      const int id2 = s_idx[j];
+      const double x = s_coef[j] * s_src[g][id2 >> 9];
+      acc += (__popc(nq & id2 & 7) & 1) ? -x : x;
+    }
+    Lk[Pc * RS + col] += acc;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -839,10 +860,11 @@ hipError_t launch_split_reduce(fmm_plan* pl, const SegTable& st, hipStream_t s) 
   return hipGetLastError();
 }
 
+template <int P>
 hipError_t launch_l2l_site(fmm_plan* pl, const SegTable& st, hipStream_t s) {
   if (!st.nseg) return hipSuccess;
-  hipLaunchKernelGGL(k_l2l, dim3(st.blocks), dim3(256), 0, s, st.dev, st.nseg, pl->l2l_start, pl->l2l_idx,
-                     pl->l2l_coef, pl->NL, loc_stride(pl->p));
+  hipLaunchKernelGGL(k_l2l<P>, dim3(st.blocks), dim3(256), 0, s, st.dev, st.nseg, pl->l2l_start, pl->l2l_idx,
+                     pl->l2l_coef);
   return hipGetLastError();
 }
 
@@ -894,7 +916,7 @@ hipError_t solve_ct(fmm_plan* pl, IoArg io, hipStream_t s) {
   // Lhat_{F-1} directly by the bottom kernel
   for (int k = 4; k <= pl->maxF - 1; ++k) {
     StageScope sc(pl, ST_L2L, pl->s_l2l[k].nseg ? 1 : 0, s);
-    if ((e = launch_l2l_site(pl, pl->s_l2l[k], s)) != hipSuccess) return e;
+    if ((e = launch_l2l_site<P>(pl, pl->s_l2l[k], s)) != hipSuccess) return e;
   }
   if ((e = launch_bottom<P, double, TI, TO>(pl, 0, io, s)) != hipSuccess) return e;
   if constexpr (!std::is_same<CT, double>::value)
@@ -1046,8 +1068,8 @@ hipError_t Impl<P>::finish_locals(fmm_plan* pl, int level, hipStream_t s) {
     SegTable st;
     st.dev = dev;
     st.nseg = 1;
-    st.blocks = (int)blocks_for((long long)sg.n * sg.n * sg.n * loc_stride(P), 256);
-    e = launch_l2l_site(pl, st, s);
+    st.blocks = (int)blocks_for((long long)sg.n * sg.n * sg.n, L2L_ROWS);
+    e = launch_l2l_site<P>(pl, st, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   }
   (void)hipFree(dev);

@@ -27,6 +27,14 @@ constexpr int NTMAX = (PDMAX + 1) * (PDMAX + 2) * (PDMAX + 3) / 6;  // 220
 
 constexpr __host__ __device__ int nterms(int P) { return P < 0 ? 0 : (P + 1) * (P + 2) * (P + 3) / 6; }
 constexpr __host__ __device__ int ndeg(int m) { return (m + 1) * (m + 2) / 2; }  // terms of degree m
+// entries of the L2L coefficient lists: pairs (b, g) with |b| + |g| <= P
+constexpr __host__ __device__ int l2l_entries(int P) {
+  int e = 0;
+  for (int m = 0; m <= P; ++m) e += ndeg(m) * nterms(P - m);
+  return e;
+}
+// level-(k-1) cells whose child locals one k_l2l block forms
+constexpr int L2L_ROWS = 4;
 
 // index of (a, b, c) in the graded order
 constexpr __host__ __device__ int mi_index(int a, int b, int c) {
