@@ -877,11 +877,11 @@ hipError_t launch_bottom(fmm_plan* pl, int x, IoArg io, hipStream_t s) {
   if (!st.nseg) return hipSuccess;
   StageScope sc(pl, ST_BOTTOM, 1, s);
   if (z == 0)
-    hipLaunchKernelGGL((k_bottom<P, CT, TI, TO, 16>), dim3(st.blocks), dim3(BOT_THREADS), 0, s, st.dev, st.nseg, io,
+    hipLaunchKernelGGL((k_bottom<P, CT, TI, TO, 16>), dim3(st.blocks), dim3(bottom_threads<CT>()), 0, s, st.dev, st.nseg, io,
                        (const H*)pl->wm2p[X], (const H*)pl->wl2p[X], (const H*)pl->wl2p2[X], (const H*)pl->wp2p[X],
                        pl->dlists);
   else
-    hipLaunchKernelGGL((k_bottom<P, CT, TI, TO, 8>), dim3(st.blocks), dim3(BOT_THREADS), 0, s, st.dev, st.nseg, io,
+    hipLaunchKernelGGL((k_bottom<P, CT, TI, TO, 8>), dim3(st.blocks), dim3(bottom_threads<CT>()), 0, s, st.dev, st.nseg, io,
                        (const H*)pl->wm2p[X], (const H*)pl->wl2p[X], (const H*)pl->wl2p2[X], (const H*)pl->wp2p[X],
                        pl->dlists);
   return hipGetLastError();

@@ -103,7 +103,13 @@ struct EntryGroup {
 // 16: tile m holds x = m / TPX, y = YPT (m % TPX) + i / BZ2, z = i % BZ2.
 constexpr int BX = 8, BY = 8;
 constexpr int HX = BX + 6, HY = BY + 6;
-constexpr int BOT_THREADS = 512;
+// Waves per parity class of a bottom block: with FP64 operands two waves
+// share a class's row tiles, so a CU holds 16 waves to keep the 64-cycle
+// MFMAs fed; the other types keep one (FP32 fits two blocks per CU instead).
+template <typename CT>
+constexpr int bottom_wpr() { return Mf<CT>::IDX == 0 ? 2 : 1; }
+template <typename CT>
+constexpr int bottom_threads() { return 512 * bottom_wpr<CT>(); }
 
 template <int BZ>
 struct BotShape {
@@ -157,7 +163,7 @@ __device__ __forceinline__ void stage_halo(typename Mf<CT>::H* __restrict__ halo
   constexpr int HZ = BotShape<BZ>::HZ, NH = HX * HY * HZ, NIT = (NH + NTHR - 1) / NTHR;
   // cells per batch, sized to the registers the kernels leave free: FP64
   // 5 (40 registers in flight), FP32 2 (16), BF16 1 (the 4 loads of a cell)
-  constexpr int BATCH = Mf<CT>::IDX == 0 ? 5 : (Mf<CT>::IDX == 1 ? 2 : 1);
+  constexpr int BATCH = Mf<CT>::IDX == 0 ? 3 : (Mf<CT>::IDX == 1 ? 2 : 1);
   const __attribute__((address_space(1))) d4* g = gmem(reinterpret_cast<const d4*>(src));
 #pragma unroll 1
   for (int b0 = 0; b0 < NIT; b0 += BATCH) {
@@ -204,13 +210,14 @@ __device__ constexpr int tile_part(int m) {
 // Segments: n = nF (level-F cells per axis), tpa = tiles along x and y,
 // tz = tiles along z, field, a = Mhat_F, c = Lam_F (or null), d = the parent
 // level's locals (or null).
-// minimum waves per SIMD (the second launch bound): FP32 operands leave room
-// for two 512-thread blocks per CU (4 waves per SIMD, <= 128 registers)
+// minimum waves per SIMD (the second launch bound): one 1024-thread FP64
+// block or two 512-thread FP32 blocks per CU (4 waves per SIMD, <= 128
+// registers); BF16 one 512-thread block
 template <typename CT>
-constexpr int bottom_min_waves() { return Mf<CT>::IDX == 1 ? 4 : 2; }
+constexpr int bottom_min_waves() { return Mf<CT>::IDX == 2 ? 2 : 4; }
 
 template <int P, typename CT, typename TI, typename TO, int BZ>
-__global__ __launch_bounds__(BOT_THREADS, bottom_min_waves<CT>()) void k_bottom(
+__global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void k_bottom(
     const Seg* __restrict__ segs, int nseg, IoArg io, const typename Mf<CT>::H* __restrict__ Wm2p,
     const typename Mf<CT>::H* __restrict__ Wl2p, const typename Mf<CT>::H* __restrict__ Wl2p2,
     const typename Mf<CT>::H* __restrict__ Wp2p, const int* __restrict__ dlists) {
@@ -225,10 +232,11 @@ __global__ __launch_bounds__(BOT_THREADS, bottom_min_waves<CT>()) void k_bottom(
   constexpr int NL = nterms(P);
   constexpr int KT = 4 * VPL, NLT = (NL + KT - 1) / KT, NPT = (216 + KT - 1) / KT;
   constexpr int NGRP = (NLIST + OPM - 1) / OPM;
+  constexpr int THREADS = bottom_threads<CT>(), MTW = BOT_MT / bottom_wpr<CT>();  // row tiles per wave
   using HL = Halo<CT, BZ>;
   __shared__ H halo[HL::SIZE];
   __shared__ int slist[8 * NLIST_PAD];  // the interaction lists of the 8 parity classes
-  for (int t = threadIdx.x; t < 8 * NLIST_PAD; t += BOT_THREADS) slist[t] = dlists[t];
+  for (int t = threadIdx.x; t < 8 * NLIST_PAD; t += THREADS) slist[t] = dlists[t];
   const Seg& sg = find_seg(segs, nseg, blockIdx.x);
   const int nF = sg.n;
   const double* __restrict__ Mh = sg.a;
@@ -241,7 +249,9 @@ __global__ __launch_bounds__(BOT_THREADS, bottom_min_waves<CT>()) void k_bottom(
   const double sphi = 0.5 * dxf * dxf, sgr = -0.25 * dxf;
   const int lb = blockIdx.x - sg.first_block;
   const int lane = threadIdx.x & 63;
-  const int r = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave = parity class (uniform)
+  // wave = parity class r and, of its BOT_MT row tiles, the MTW from m0 (uniform)
+  const int r = __builtin_amdgcn_readfirstlane((threadIdx.x >> 6) & 7);
+  const int m0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 9) * MTW;
   const int i = lane & 15, kq = lane >> 4;
   const LaneRole<CT> lr(lane);
   const int r0 = (r >> 2) & 1, r1 = (r >> 1) & 1, r2 = r & 1;
@@ -249,12 +259,14 @@ __global__ __launch_bounds__(BOT_THREADS, bottom_min_waves<CT>()) void k_bottom(
   const long long ncellp = (long long)nFp * nFp * nFp;
   const int tx0 = (lb / (sg.tpa * sg.tz)) * BX, ty0 = ((lb / sg.tz) % sg.tpa) * BY, tz0 = (lb % sg.tz) * BZ;
   const int gz = i % BZ2, gyo = i / BZ2;
-  // per-lane part of the operand addresses: row (gyo, gz) and the lane's K slice
-  const H* hlane = halo + 2 * gyo * HL::YS + gz * KC + lr.tic;
+  // per-lane part of the operand addresses: row (gyo, gz), the lane's K slice
+  // and the wave's first row tile (MTW is a multiple of TPX, so the tile
+  // offset splits into that of m0 and that of the tile within the wave)
+  const H* hlane = halo + 2 * gyo * HL::YS + gz * KC + lr.tic + tile_part<HL, TPX, YPT>(m0);
 
-  Acc acc[BOT_MT][2];
+  Acc acc[MTW][2];
 #pragma unroll
-  for (int m = 0; m < BOT_MT; ++m) acc[m][0] = acc[m][1] = Acc{0, 0, 0, 0};
+  for (int m = 0; m < MTW; ++m) acc[m][0] = acc[m][1] = Acc{0, 0, 0, 0};
   const int* dl = slist + r * NLIST_PAD;  // visible after the first chunk's barrier
   // blocks walk the (order-independent) offset sum from different starting points
   const int rot = (int)((blockIdx.x * 37u) % NLIST);
@@ -266,7 +278,7 @@ __global__ __launch_bounds__(BOT_THREADS, bottom_min_waves<CT>()) void k_bottom(
 
   for (int c = 0; c < NCK; ++c) {
     __syncthreads();  // previous chunk fully consumed
-    stage_halo<CT, BZ, BOT_THREADS>(halo, Mh, NC4, ncellp, nFp, tx0, ty0, tz0, c);
+    stage_halo<CT, BZ, THREADS>(halo, Mh, NC4, ncellp, nFp, tx0, ty0, tz0, c);
     __syncthreads();
     const H* wc = Wm2p + (size_t)c * NSLOT * 2 * EL * VPL + lr.tl * VPL;
     auto bload = [&](EntryGroup g, int t) {
@@ -277,10 +289,10 @@ __global__ __launch_bounds__(BOT_THREADS, bottom_min_waves<CT>()) void k_bottom(
     // fragments and the A fragments of groups j, j + 1, j + 2 (the loop is
     // unrolled by three, so no slot is copied): B is loaded two groups
     // ahead, A one group ahead, while the current group's products run.
-    auto aload = [&](EntryGroup g, AF (&a)[BOT_MT]) {
+    auto aload = [&](EntryGroup g, AF (&a)[MTW]) {
       const H* base = hlane + HL::offset_part(r0, r1, r2, dl_d0(g.e), dl_d1(g.e), dl_d2(g.e));
 #pragma unroll
-      for (int m = 0; m < BOT_MT; ++m)
+      for (int m = 0; m < MTW; ++m)
         a[m] = *reinterpret_cast<const AF*>(base + tile_part<HL, TPX, YPT>(m));
     };
     auto group = [&](int j) {
@@ -292,7 +304,7 @@ __global__ __launch_bounds__(BOT_THREADS, bottom_min_waves<CT>()) void k_bottom(
       return g;
     };
     EntryGroup es[3];
-    AF bs[3][2], as[3][BOT_MT];
+    AF bs[3][2], as[3][MTW];
     es[0] = group(0);
     bs[0][0] = bload(es[0], 0);
     bs[0][1] = bload(es[0], 1);
@@ -312,7 +324,7 @@ __global__ __launch_bounds__(BOT_THREADS, bottom_min_waves<CT>()) void k_bottom(
           }
           if (jj + 1 < NGRP) aload(es[nx], as[nx]);
 #pragma unroll
-          for (int m = 0; m < BOT_MT; ++m) {
+          for (int m = 0; m < MTW; ++m) {
             acc[m][0] = M::op(as[cur][m], bs[cur][0], acc[m][0]);
             acc[m][1] = M::op(as[cur][m], bs[cur][1], acc[m][1]);
           }
@@ -336,7 +348,7 @@ __global__ __launch_bounds__(BOT_THREADS, bottom_min_waves<CT>()) void k_bottom(
   // tail K blocks of row tile m: L2P of the M2L part of the own local (stored
   // with the parent P'), L2P from the parent level's full local, near field.
   // U chunks at a time, their operand loads issued together.
-  constexpr int U = M::IDX == 0 ? 4 : (M::IDX == 1 ? 2 : 1);
+  constexpr int U = M::IDX == 1 ? 2 : 1;
   auto tail = [&](int m, Acc (&am)[2]) {
     int c0, c1, c2;
     cell_of(m, c0, c1, c2);
@@ -412,10 +424,11 @@ __global__ __launch_bounds__(BOT_THREADS, bottom_min_waves<CT>()) void k_bottom(
     }
   };
 #pragma unroll
-  for (int m = 0; m < BOT_MT; ++m) tail(m, acc[m]);
+  for (int m = 0; m < MTW; ++m) tail(m0 + m, acc[m]);
   // epilogue: element v of tile t is row M::row(v, kq), column 16 t + i
 #pragma unroll
-  for (int m = 0; m < BOT_MT; ++m) {
+  for (int mw = 0; mw < MTW; ++mw) {
+    const int m = m0 + mw;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int row = M::row(v, kq);
@@ -428,7 +441,7 @@ __global__ __launch_bounds__(BOT_THREADS, bottom_min_waves<CT>()) void k_bottom(
         const int q = col >> 2, o = col & 3;
         const long long u = ((long long)(2 * o0 + ((q >> 2) & 1)) * n + (2 * o1 + ((q >> 1) & 1))) * n +
                             (2 * o2 + (q & 1));
-        const double val = (double)acc[m][t][v];
+        const double val = (double)acc[mw][t][v];
         if (o == 0)
           phi[u] = (TO)(sphi * val);
         else if (g)
