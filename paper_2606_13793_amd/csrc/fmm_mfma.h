@@ -103,11 +103,12 @@ struct EntryGroup {
 // 16: tile m holds x = m / TPX, y = YPT (m % TPX) + i / BZ2, z = i % BZ2.
 constexpr int BX = 8, BY = 8;
 constexpr int HX = BX + 6, HY = BY + 6;
-// Waves per parity class of a bottom block: with FP64 operands two waves
-// share a class's row tiles, so a CU holds 16 waves to keep the 64-cycle
-// MFMAs fed; the other types keep one (FP32 fits two blocks per CU instead).
+// Waves per parity class of a bottom block: with FP64 and BF16 operands two
+// waves share a class's row tiles (1024-thread blocks), so a CU holds 16
+// waves to hide the operand latencies; FP32 keeps one and fits two 512-thread
+// blocks per CU instead.
 template <typename CT>
-constexpr int bottom_wpr() { return Mf<CT>::IDX == 0 ? 2 : 1; }
+constexpr int bottom_wpr() { return Mf<CT>::IDX == 1 ? 1 : 2; }
 template <typename CT>
 constexpr int bottom_threads() { return 512 * bottom_wpr<CT>(); }
 
@@ -210,11 +211,10 @@ __device__ constexpr int tile_part(int m) {
 // Segments: n = nF (level-F cells per axis), tpa = tiles along x and y,
 // tz = tiles along z, field, a = Mhat_F, c = Lam_F (or null), d = the parent
 // level's locals (or null).
-// minimum waves per SIMD (the second launch bound): one 1024-thread FP64
-// block or two 512-thread FP32 blocks per CU (4 waves per SIMD, <= 128
-// registers); BF16 one 512-thread block
+// minimum waves per SIMD (the second launch bound): one 1024-thread block or
+// two 512-thread FP32 blocks per CU (4 waves per SIMD, <= 128 registers)
 template <typename CT>
-constexpr int bottom_min_waves() { return Mf<CT>::IDX == 2 ? 2 : 4; }
+constexpr int bottom_min_waves() { return 4; }
 
 template <int P, typename CT, typename TI, typename TO, int BZ>
 __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void k_bottom(
