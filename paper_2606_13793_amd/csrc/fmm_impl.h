@@ -661,50 +661,52 @@ __global__ __launch_bounds__(ADJ_M2M_THREADS) void k_adj_m2m(const double* __res
 // P2M^T + near^T for the 8 unigrid children w = 2T + q_w of a level-F cell T:
 //   rho_bar[w] = sum_a 4^-|a| / a! (-1)^(q_w.a) Mbar_F[T][a]
 //     + sum_{e in [-1,1]^3} sum_{(q,o)} p2p_coef(q_w - 2e, q, o) Ybar_{T+e}[(q,o)].
-// Thread = cell T (block = 4^3 cells): each neighbour's 32 values are read
-// once from LDS and applied to all 8 children; the stencil weights depend
-// only on (e, q, q_w) and are read from LDS tables at uniform addresses.
-// The P2M^T part is a Walsh transform of 8 signed sums of the cell's terms.
-constexpr int ADJ_BOT_THREADS = 64;
+// Thread = cell T, block = 4 x 4 x TZ cells (TZ = blockDim / 16).  The Ybar
+// chunks q (4 values each) of the block's cells and their one-cell halo are
+// staged in LDS one chunk at a time, so a block needs little LDS and a CU
+// holds many; each neighbour's chunk is read once and applied to all 8
+// children.  The stencil weights depend only on (e, q, q_w) and are read from
+// LDS tables at uniform addresses.  The P2M^T part is a Walsh transform of 8
+// signed sums of the cell's terms.
+constexpr int ADJ_BOT_TZ = 16;  // cells along z per block (fewer when the grid is smaller)
 template <typename TO>
-__global__ __launch_bounds__(ADJ_BOT_THREADS) void k_adj_bottom(const double* __restrict__ Mb,
+__global__ __launch_bounds__(16 * ADJ_BOT_TZ) void k_adj_bottom(const double* __restrict__ Mb,
                                                                 const double* __restrict__ Y, TO* __restrict__ drho,
                                                                 int n, int NM) {
-  __shared__ d4 ys[216 * 8];
+  __shared__ d4 ys[36 * (ADJ_BOT_TZ + 2)];
   __shared__ double sp[343], sg3[3 * 343];
+  const int TZ = blockDim.x >> 4, HZ = TZ + 2, nthr = blockDim.x;
   const int nF = n >> 1, nFp = nF + 6;
   const long long ncellp = (long long)nFp * nFp * nFp;
-  const int T0x = blockIdx.x * 4, T0y = blockIdx.y * 4, T0z = blockIdx.z * 4;
-  for (int h = threadIdx.x; h < 216 * 8; h += ADJ_BOT_THREADS) {
-    const int q = h & 7, c = h >> 3;
-    const int cz = c % 6, cy = (c / 6) % 6, cx = c / 36;
-    // padded coordinates of T = T0 + (cx, cy, cz) - 1, inside [2, nF + 4)
-    const long long cp = ((long long)(T0x + cx + 2) * nFp + (T0y + cy + 2)) * nFp + (T0z + cz + 2);
-    ys[h] = *reinterpret_cast<const d4*>(Y + (q * ncellp + cp) * 4);
-  }
-  for (int t = threadIdx.x; t < 343; t += ADJ_BOT_THREADS) {
+  const int T0x = blockIdx.x * 4, T0y = blockIdx.y * 4, T0z = blockIdx.z * TZ;
+  for (int t = threadIdx.x; t < 343; t += nthr) {
     sp[t] = 2.0 * c_p2p_phi[t];
     sg3[t] = -4.0 * c_p2p_g[t];
     sg3[343 + t] = -4.0 * c_p2p_g[343 + t];
     sg3[686 + t] = -4.0 * c_p2p_g[686 + t];
   }
-  __syncthreads();
-  const int tl2 = threadIdx.x & 3, tl1 = (threadIdx.x >> 2) & 3, tl0 = threadIdx.x >> 4;
+  const int tl2 = threadIdx.x % TZ, tl1 = (threadIdx.x / TZ) & 3, tl0 = threadIdx.x / (4 * TZ);
   double acc[8];
 #pragma unroll
   for (int qw = 0; qw < 8; ++qw) acc[qw] = 0.0;
-  for (int e = 0; e < 27; ++e) {
-    const int e0 = e / 9 - 1, e1 = (e / 3) % 3 - 1, e2 = e % 3 - 1;
-    const d4* yc = ys + (((tl0 + e0 + 1) * 6 + (tl1 + e1 + 1)) * 6 + (tl2 + e2 + 1)) * 8;
-    // delta = u - w = 2e + q - q_w in [-3, 3]^3; index base of 2e
-    const int tb = (2 * e0 + 3) * 49 + (2 * e1 + 3) * 7 + (2 * e2 + 3);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const d4 v = yc[q];
+  for (int q = 0; q < 8; ++q) {
+    __syncthreads();  // the previous chunk is consumed (and the tables are written)
+    for (int c = threadIdx.x; c < 36 * HZ; c += nthr) {
+      const int cz = c % HZ, cy = (c / HZ) % 6, cx = c / (6 * HZ);
+      // padded coordinates of T = T0 + (cx, cy, cz) - 1, inside [2, nF + 4)
+      const long long cp = ((long long)(T0x + cx + 2) * nFp + (T0y + cy + 2)) * nFp + (T0z + cz + 2);
+      ys[c] = *reinterpret_cast<const d4*>(Y + (q * ncellp + cp) * 4);
+    }
+    __syncthreads();
+    const int qd = (((q >> 2) & 1) * 49) + (((q >> 1) & 1) * 7) + (q & 1);
+    for (int e = 0; e < 27; ++e) {
+      const int e0 = e / 9 - 1, e1 = (e / 3) % 3 - 1, e2 = e % 3 - 1;
+      const d4 v = ys[((tl0 + e0 + 1) * 6 + (tl1 + e1 + 1)) * HZ + (tl2 + e2 + 1)];
+      // delta = u - w = 2e + q - q_w in [-3, 3]^3; index base of 2e + q
+      const int tb = (2 * e0 + 3) * 49 + (2 * e1 + 3) * 7 + (2 * e2 + 3) + qd;
 #pragma unroll
       for (int qw = 0; qw < 8; ++qw) {
-        const int t = tb + ((((q >> 2) & 1) - ((qw >> 2) & 1)) * 49 + (((q >> 1) & 1) - ((qw >> 1) & 1)) * 7 +
-                            ((q & 1) - (qw & 1)));
+        const int t = tb - (((qw >> 2) & 1) * 49 + ((qw >> 1) & 1) * 7 + (qw & 1));
         acc[qw] += sp[t] * v[0] + sg3[t] * v[1] + sg3[343 + t] * v[2] + sg3[686 + t] * v[3];
       }
     }
@@ -1000,9 +1002,11 @@ hipError_t backward_ct(fmm_plan* pl, const TI* dphi, const TI* dg, TO* drho, hip
                        pl->m2mt_a, pl->m2mt_coef);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  dim3 bgrid(nF / 4, nF / 4, nF / 4);
-  hipLaunchKernelGGL((k_adj_bottom<TO>), bgrid, dim3(ADJ_BOT_THREADS), 0, s, (const double*)pl->lev[F].M, pl->ybar,
-                     drho, n, NM);
+  // nF is a power of two >= 4: the block's z extent divides it
+  const int tz = nF < ADJ_BOT_TZ ? nF : ADJ_BOT_TZ;
+  dim3 bgrid(nF / 4, nF / 4, nF / tz);
+  hipLaunchKernelGGL((k_adj_bottom<TO>), bgrid, dim3(16 * tz), 0, s, (const double*)pl->lev[F].M, pl->ybar, drho, n,
+                     NM);
   return hipGetLastError();
 }
 
