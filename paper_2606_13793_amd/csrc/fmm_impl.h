@@ -472,19 +472,26 @@ __global__ void k_adj_coef(double* __restrict__ own, double* __restrict__ par, i
     par[((z - 1) * NL + b) * 32 + k] = l2p_parent_coef(b, z - 1, k >> 2, k & 3);
 }
 
-// L2P^T and (parent-level L2P)^T.  Block = 32 level-(F-1) cells P (consecutive
-// in C order); the Ybar of their 8 children (256 values each) is staged in
-// LDS with an odd row stride.  Thread (parent, slice): the adjoint local of
-// every child T = 2P + rp is written in P's row in 4-column chunks (columns
-// (rp, b) in the M2L order), and, when the parent level has locals, the
-// adjoint full local of P in its parent's row (column (qP, b)).
-constexpr int ADJ_L2P_PAR = 32, ADJ_L2P_THREADS = 256, ADJ_L2P_YS = 257;
+// L2P^T and (parent-level L2P)^T on the matrix cores (v_mfma_f64_16x16x4f64).
+// Block = 16 level-(F-1) cells P (consecutive in C order) = one row tile; the
+// Ybar of their 8 children (256 values each) is staged in LDS with an odd row
+// stride.  Wave rp (of 8) takes child rp of every P: for each 16-column tile
+// of local terms b,
+//   own[P][(rp, b)] = sum_k cown[b][k] Ybar[2P + rp][k]       (K = 32)
+//   par[P][b]      += sum_k cpar[rp][b][k] Ybar[2P + rp][k]   (K = 32 of 256)
+// own is written to P's row (columns (rp, b) in the M2L order); the 8 waves'
+// par partials are added in LDS in a fixed order and written, when the parent
+// level has locals, to the row of P's parent (column (qP, b)).
+constexpr int ADJ_L2P_PAR = 16, ADJ_L2P_THREADS = 512, ADJ_L2P_YS = 257;
+template <int P>
 __global__ __launch_bounds__(ADJ_L2P_THREADS) void k_adj_l2p(const double* __restrict__ Y,
                                                              const double* __restrict__ cown,
                                                              const double* __restrict__ cpar,
                                                              double* __restrict__ Aown, double* __restrict__ Apar,
-                                                             int nF, int NL, int RS) {
+                                                             int nF) {
+  constexpr int NL = nterms(P), RS = loc_stride(P), NBT = (NL + 15) / 16;
   __shared__ double y[ADJ_L2P_PAR * ADJ_L2P_YS];
+  __shared__ double red[8][16][17];
   const int nP = nF >> 1, nFp = nF + 6, nPp = nP + 6, nPP = nP >> 1, nPPp = nPP + 6;
   const long long ncF = (long long)nFp * nFp * nFp, ncP = (long long)nPp * nPp * nPp,
                   ncPP = (long long)nPPp * nPPp * nPPp;
@@ -494,10 +501,10 @@ __global__ __launch_bounds__(ADJ_L2P_THREADS) void k_adj_l2p(const double* __res
   // contiguous along z
   for (int l = threadIdx.x; l < 8 * ADJ_L2P_PAR * 8; l += ADJ_L2P_THREADS) {
     const int rp = l & 7, pl = (l >> 3) % ADJ_L2P_PAR, q = l / (8 * ADJ_L2P_PAR);
-    const long long P = P0 + pl;
+    const long long Pc = P0 + pl;
     d4 v = d4{0, 0, 0, 0};
-    if (P < nPc) {
-      const int p2 = (int)(P % nP), p1 = (int)((P / nP) % nP), p0 = (int)(P / ((long long)nP * nP));
+    if (Pc < nPc) {
+      const int p2 = (int)(Pc % nP), p1 = (int)((Pc / nP) % nP), p0 = (int)(Pc / ((long long)nP * nP));
       const long long cT = ((long long)(2 * p0 + ((rp >> 2) & 1) + 3) * nFp + (2 * p1 + ((rp >> 1) & 1) + 3)) * nFp +
                            (2 * p2 + (rp & 1) + 3);
       v = *reinterpret_cast<const d4*>(Y + (q * ncF + cT) * 4);
@@ -506,49 +513,73 @@ __global__ __launch_bounds__(ADJ_L2P_THREADS) void k_adj_l2p(const double* __res
 #pragma unroll
     for (int e = 0; e < 4; ++e) yy[e] = v[e];
   }
-  __syncthreads();
-  const int pl = threadIdx.x % ADJ_L2P_PAR, sl = threadIdx.x / ADJ_L2P_PAR;
-  constexpr int NSL = ADJ_L2P_THREADS / ADJ_L2P_PAR;  // slices (8)
-  const long long P = P0 + pl;
-  if (P >= nPc) return;
-  const int p2 = (int)(P % nP), p1 = (int)((P / nP) % nP), p0 = (int)(P / ((long long)nP * nP));
-  const double* yp = y + pl * ADJ_L2P_YS;
-  // own: column chunks of P's row
-  const long long cp = ((long long)(p0 + 3) * nPp + (p1 + 3)) * nPp + (p2 + 3);
-  const int ncol = 8 * NL;
-  for (int cc = sl; cc < RS / 4; cc += NSL) {
-    d4 out;
+  const int lane = threadIdx.x & 63;
+  const int rp = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int i = lane & 15, kq = lane >> 4;
+  // padded-grid cells of the lane's output rows 4 v + kq
+  long long cpo[4];
+  bool okr[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int j = 4 * cc + e;
-      double acc = 0.0;
-      if (j < ncol) {
-        const int md = m2l_col_degree(j);
-        const int cin = j - 8 * nterms(md - 1);
-        const int rp = cin / ndeg(md), bt = nterms(md - 1) + cin % ndeg(md);
-        const double* c = cown + bt * 32;
-        const double* yy = yp + rp * 32;
-#pragma unroll 8
-        for (int k = 0; k < 32; ++k) acc += c[k] * yy[k];
-      }
-      out[e] = acc;
-    }
-    *reinterpret_cast<d4*>(Aown + (cc * ncP + cp) * 4) = out;
+  for (int v = 0; v < 4; ++v) {
+    const long long Pc = P0 + 4 * v + kq;
+    okr[v] = Pc < nPc;
+    const long long Pq = okr[v] ? Pc : 0;
+    const int p2 = (int)(Pq % nP), p1 = (int)((Pq / nP) % nP), p0 = (int)(Pq / ((long long)nP * nP));
+    cpo[v] = ((long long)(p0 + 3) * nPp + (p1 + 3)) * nPp + (p2 + 3);
   }
-  if (!Apar) return;
-  const int qP = ((p0 & 1) << 2) | ((p1 & 1) << 1) | (p2 & 1);
-  const long long cpp = ((long long)((p0 >> 1) + 3) * nPPp + ((p1 >> 1) + 3)) * nPPp + ((p2 >> 1) + 3);
-  for (int bt = sl; bt < NL; bt += NSL) {
-    double acc = 0.0;
-    for (int rp = 0; rp < 8; ++rp) {
-      const double* c = cpar + (rp * NL + bt) * 32;
-      const double* yy = yp + rp * 32;
-#pragma unroll 8
-      for (int k = 0; k < 32; ++k) acc += c[k] * yy[k];
+  __syncthreads();
+  const double* ya = y + i * ADJ_L2P_YS + rp * 32 + kq;
+  for (int T = 0; T < NBT; ++T) {
+    const int bt = 16 * T + i;  // the lane's column (B operand and output)
+    const bool okc = bt < NL;
+    d4 ao = d4{0, 0, 0, 0}, ap = d4{0, 0, 0, 0};
+#pragma unroll
+    for (int kc = 0; kc < 8; ++kc) {
+      const double a = ya[4 * kc];
+      const double bo = okc ? cown[bt * 32 + 4 * kc + kq] : 0.0;
+      const double bp = okc ? cpar[((size_t)rp * NL + bt) * 32 + 4 * kc + kq] : 0.0;
+      ao = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bo, ao, 0, 0, 0);
+      ap = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bp, ap, 0, 0, 0);
     }
-    const int ex = c_mi_exp[bt];
-    const int col = m2l_col(qP, bt, mi_a(ex) + mi_b(ex) + mi_c(ex));
-    Apar[((col >> 2) * ncPP + cpp) * 4 + (col & 3)] = acc;
+    if (okc) {
+      const int ex = c_mi_exp[bt];
+      const int col = m2l_col(rp, bt, mi_a(ex) + mi_b(ex) + mi_c(ex));
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (okr[v]) Aown[((col >> 2) * ncP + cpo[v]) * 4 + (col & 3)] = ao[v];
+    }
+    if (Apar) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[rp][4 * v + kq][i] = ap[v];
+      __syncthreads();
+      if (threadIdx.x < 256) {
+        const int row = threadIdx.x >> 4, c = threadIdx.x & 15, b2 = 16 * T + c;
+        const long long Pc = P0 + row;
+        if (b2 < NL && Pc < nPc) {
+          double acc = 0.0;
+#pragma unroll
+          for (int w = 0; w < 8; ++w) acc += red[w][row][c];
+          const int p2 = (int)(Pc % nP), p1 = (int)((Pc / nP) % nP), p0 = (int)(Pc / ((long long)nP * nP));
+          const int qP = ((p0 & 1) << 2) | ((p1 & 1) << 1) | (p2 & 1);
+          const long long cpp = ((long long)((p0 >> 1) + 3) * nPPp + ((p1 >> 1) + 3)) * nPPp + ((p2 >> 1) + 3);
+          const int ex = c_mi_exp[b2];
+          const int col = m2l_col(qP, b2, mi_a(ex) + mi_b(ex) + mi_c(ex));
+          Apar[((col >> 2) * ncPP + cpp) * 4 + (col & 3)] = acc;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // the padding columns of P's row (past 8 NL) stay zero
+  if constexpr (RS > 8 * NL) {
+    for (int t = threadIdx.x; t < ADJ_L2P_PAR * (RS - 8 * NL) / 4; t += ADJ_L2P_THREADS) {
+      const int pl = t % ADJ_L2P_PAR, cc = 2 * NL + t / ADJ_L2P_PAR;
+      const long long Pc = P0 + pl;
+      if (Pc >= nPc) continue;
+      const int p2 = (int)(Pc % nP), p1 = (int)((Pc / nP) % nP), p0 = (int)(Pc / ((long long)nP * nP));
+      const long long cp = ((long long)(p0 + 3) * nPp + (p1 + 3)) * nPp + (p2 + 3);
+      *reinterpret_cast<d4*>(Aown + (cc * ncP + cp) * 4) = d4{0, 0, 0, 0};
+    }
   }
 }
 
@@ -971,9 +1002,8 @@ hipError_t backward_ct(fmm_plan* pl, const TI* dphi, const TI* dg, TO* drho, hip
   if (F >= 3) {
     // transposed L2P of the own local and of the parent level's local
     const long long nP = nT / 8;
-    hipLaunchKernelGGL(k_adj_l2p, dim3(blocks_for(nP, ADJ_L2P_PAR)), dim3(ADJ_L2P_THREADS), 0, s, pl->ybar,
-                       pl->adj_l2p, pl->adj_l2p2,
-                       pl->abar[F], F >= 4 ? pl->abar[F - 1] : nullptr, nF, NL, loc_stride(P));
+    hipLaunchKernelGGL(k_adj_l2p<P>, dim3(blocks_for(nP, ADJ_L2P_PAR)), dim3(ADJ_L2P_THREADS), 0, s, pl->ybar,
+                       pl->adj_l2p, pl->adj_l2p2, pl->abar[F], F >= 4 ? pl->abar[F - 1] : nullptr, nF);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // transposed L2L chain, fine to coarse
     for (int k = F - 1; k >= 4; --k) {
