@@ -333,6 +333,21 @@ int build_schedule(fmm_plan* pl) {
       bot[bottom_low(pl, F) ? 1 : 0][z].add(b, (long long)b.tpa * b.tpa * b.tz);
     }
   }
+  // A site whose row grids are all at most 8 cells deep (the coarse FP64
+  // levels of mixed-precision plans, small fields) uses 8-deep tiles.
+  int cz[2] = {16, 16};
+  for (int x = 0; x < 2; ++x) {
+    bool shallow = !conv[x].v.empty();
+    for (auto& c : conv[x].v) shallow = shallow && c.n <= 8;
+    if (!shallow) continue;
+    cz[x] = 8;
+    SegList sh;
+    for (auto c : conv[x].v) {
+      c.tz = (int)cdiv(c.n, 8);
+      sh.add(c, (long long)c.tpa * c.tpa * c.tz);
+    }
+    conv[x] = sh;
+  }
   // Launch sites with few tiles (the coarse levels of mixed-precision plans,
   // small grids) split each tile's offset sum over several blocks; the
   // partial sums are added in a fixed order afterwards.
@@ -382,6 +397,7 @@ int build_schedule(fmm_plan* pl) {
   }
   for (int x = 0; x < 2; ++x) {
     if ((rc = upload_segs(pl, pl->s_conv[x], conv[x]))) return rc;
+    pl->s_conv[x].cz = cz[x];
     if ((rc = upload_segs(pl, pl->s_red[x], red[x]))) return rc;
     for (int z = 0; z < 2; ++z)
       if ((rc = upload_segs(pl, pl->s_bot[x][z], bot[x][z]))) return rc;

@@ -873,8 +873,14 @@ template <int P, typename CT, int OP, int NT>
 hipError_t launch_conv_nt(fmm_plan* pl, const SegTable& st, const void* W, hipStream_t s) {
   constexpr int G = (conv_ntiles(OP, P) + NT - 1) / NT;
   StageScope sc(pl, ST_M2L, 1, s);
-  hipLaunchKernelGGL((k_conv<P, CT, OP, NT>), dim3((unsigned)G * st.blocks), dim3(M2L_THREADS), 0, s, st.dev, st.nseg,
-                     st.blocks, (const int2*)pl->tiletab[OP][Mf<CT>::IDX], (const typename Mf<CT>::H*)W, pl->dlists);
+  const int2* tiles = (const int2*)pl->tiletab[OP][Mf<CT>::IDX];
+  const auto* w = (const typename Mf<CT>::H*)W;
+  if (st.cz == 8)
+    hipLaunchKernelGGL((k_conv<P, CT, OP, NT, 8>), dim3((unsigned)G * st.blocks), dim3(M2L_THREADS), 0, s, st.dev,
+                       st.nseg, st.blocks, tiles, w, pl->dlists);
+  else
+    hipLaunchKernelGGL((k_conv<P, CT, OP, NT, 16>), dim3((unsigned)G * st.blocks), dim3(M2L_THREADS), 0, s, st.dev,
+                       st.nseg, st.blocks, tiles, w, pl->dlists);
   return hipGetLastError();
 }
 

@@ -197,6 +197,7 @@ struct SegTable {
   Seg* dev = nullptr;
   int nseg = 0;
   int blocks = 0;
+  int cz = 16;  // k_conv sites: tile depth along z (8 when every grid is at most 8 deep)
 };
 
 // launch-shape choices picked by the batch autotuner

@@ -537,13 +537,14 @@ __global__ void k_expand_bottom(const double* __restrict__ Dtab, typename Mf<CT>
 //          scaled adjoint outputs (q, o) of X, col = a,
 //          B_d[(q, o)][a] = D[a + e_o](Rhat_{-d,q}).
 // ---------------------------------------------------------------------------
-// Conv tile: CX x CX x CZ row-grid cells (the bottom kernel's shape), per
-// parity class 4 x 4 x 8 rows in CMT = 8 row tiles of 16 (BotShape<CZ>).
-constexpr int CX = 8, CZ = 16;
-constexpr int CMT = BotShape<CZ>::MT;
+// Conv tile: CX x CX x CZ row-grid cells (the bottom kernel's shapes), per
+// parity class 4 x 4 x CZ/2 rows in CMT = CZ/2 row tiles of 16
+// (BotShape<CZ>).  CZ = 16, or 8 for launches whose grids are all at most 8
+// cells deep (coarse levels), which would leave a 16-deep tile half empty.
+constexpr int CX = 8;
 constexpr int M2L_THREADS = 512;
 
-// column tiles per group by compute type (accumulator registers: CMT row
+// column tiles per group by compute type (accumulator registers: 8 row
 // tiles x NT); variant 1 halves them
 template <typename CT, int V = 0>
 struct ConvGroup {
@@ -566,7 +567,7 @@ __device__ __forceinline__ void count_down(F&& f) {
 // Grid: ngroups x T blocks, T = the tile blocks of all segments; block b works
 // on column group b / T (the heaviest groups first) of tile block b % T.
 // tiles[t] = (K chunks, first fragment) of column tile t, zero past the last.
-template <int P, typename CT, int OP, int NT>
+template <int P, typename CT, int OP, int NT, int CZ>
 __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__ segs, int nseg, int T,
                                                         const int2* __restrict__ tiles,
                                                         const typename Mf<CT>::H* __restrict__ Wt,
@@ -580,6 +581,7 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   constexpr int NM = nterms(P), NCOL = 8 * nterms(P), NTILES = conv_ntiles(OP, P);
   constexpr int NGRP = (NLIST + OPM - 1) / OPM;
   using S = BotShape<CZ>;
+  constexpr int CMT = S::MT;  // row tiles per wave
   constexpr int HZ = S::HZ, HZ2 = S::HZ2, BZ2 = S::BZ2, YPT = S::YPT, TPX = S::TPX;
   using HL = Halo<CT, CZ>;
   __shared__ H halo[HL::SIZE];
