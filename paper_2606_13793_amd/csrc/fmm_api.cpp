@@ -457,6 +457,11 @@ fmm_plan* create_plan(const std::vector<int>& ns, int p, const fmm_options& o, i
   pl->coarse_fp64_levels = o.coarse_fp64_levels;
   pl->check_finite = o.check_finite;
   pl->device = dev;
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) pl->cus = cus;
+    (void)hipGetLastError();
+  }
   pl->batch = batch;
   pl->NM = fmm::nterms(pl->nmax);
   pl->NC = (pl->NM + 3) / 4;

@@ -911,7 +911,11 @@ template <int P, typename CT, typename TI, typename TO>
 hipError_t launch_bottom(fmm_plan* pl, int x, IoArg io, hipStream_t s) {
   using H = typename Mf<CT>::H;
   constexpr int X = Mf<CT>::IDX;
-  const int z = pl->tune.bz == 8 ? 1 : 0;
+  // the tuned tile depth, or 8 when 16-deep tiles would leave compute units
+  // idle (few or small fields at this site, e.g. the FP64 bottoms of the
+  // coarse fields of a mixed-precision batch)
+  int z = pl->tune.bz == 8 ? 1 : 0;
+  if (z == 0 && pl->s_bot[x][0].blocks < pl->cus) z = 1;
   const SegTable& st = pl->s_bot[x][z];
   if (!st.nseg) return hipSuccess;
   StageScope sc(pl, ST_BOTTOM, 1, s);

@@ -223,6 +223,7 @@ struct fmm_plan {
   int coarse_fp64_levels = 4;
   int check_finite = 0;
   int device = 0;
+  int cus = 256;  // compute units of the device
   double dx = 0.0;
   int NM = 0, NC = 0, NL = 0, NCL = 0, ND = 0;
   std::vector<fmm::Field> fld;  // the fields; fld[0].lev are field 0's grids
