@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed-precision, equal-accuracy, adjoint and batch sections")
-    ap.add_argument("--section", default=None, choices=["mixed", "adjoint", "batch", "large"],
+    ap.add_argument("--section", default=None, choices=["mixed", "adjoint", "batch", "large", "huge"],
                     help="run only this extra section (for profiling) and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device-to-device copy of BYTES bytes (a known-size "
@@ -110,16 +110,22 @@ def _rel(a, b):
 
 
 def run_large(fi, fmm, costs, n: int = 512, p: int = 6) -> dict:
-    """The same 256-sphere field at 512^3: solve time per policy and the
-    mixed policies' error against the FP64 solve at 4096 sampled cells."""
+    """The same 256-sphere field at 512^3 (or 1024^3): solve time per policy
+    and the mixed policies' error against the FP64 solve at 4096 sampled
+    cells.  At 1024^3 a plan holds about 196 GiB and the FP64 input and
+    outputs 40 GiB, so the density's temporaries are released first."""
     import numpy as np
     import torch
+    log(f"extras: {n}^3 density")
     rho64 = fi.plummer_density(n, fi.multi_plummer_params(256, 256), device="cuda")
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     N = n ** 3
     idx = torch.as_tensor(np.sort(np.random.default_rng(11).choice(N, 4096, replace=False)), device="cuda")
     out = {"n": n, "p": p}
     ref = None
     for prec in ("fp64", "fp32", "bf16"):
+        log(f"extras: {n}^3 {prec} plan")
         plan = fmm.Plan(n, p, prec)
         rho = rho64 if prec == "fp64" else rho64.float()
         phi = torch.empty((n, n, n), dtype=plan.io_dtype, device="cuda")
@@ -224,6 +230,8 @@ def run_extras(args, rho64, fi, fmm, costs, sections=("mixed", "adjoint", "batch
     torch.cuda.empty_cache()
     if "large" in sections:
         out["large_512"] = run_large(fi, fmm, costs)
+    if "huge" in sections:
+        out["huge_1024"] = run_large(fi, fmm, costs, n=1024)
     if "batch" not in sections:
         return out
     # the uneven batch (96 fields: 55 x 32^3, 27 x 64^3, 14 x 128^3), FP32
