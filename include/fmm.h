@@ -66,7 +66,9 @@ typedef enum { FMM_FP64 = 0, FMM_FP32 = 1, FMM_BF16 = 2 } fmm_precision;
 typedef struct {
   int struct_size;          /* sizeof(fmm_options), for forward compatibility */
   int precision;            /* fmm_precision, default FMM_FP64 */
-  int nmax;                 /* multipole order, -1 = p (default); 0 <= nmax <= p */
+  int nmax;                 /* multipole order, -1 = p (default); 0 <= nmax <= p.  Multipoles
+                               are truncated at nmax (Sec. 2.1); the solve still runs at the
+                               cost of order p */
   int coarse_fp64_levels;   /* mixed plans: levels k <= this stay FP64; default 4 */
   int delta_l;              /* level offset unigrid -> finest FMM grid; only 1 */
   int check_finite;         /* nonzero: fmm_solve scans rho for NaN/Inf first (single-field plans) */
@@ -160,7 +162,7 @@ int fmm_last_status(void);
  * only its M2L part during a solve), so call it only between solves on the
  * null stream's device.  Copies to HOST
  * memory `out`, as double, the scaled expansions the kernels keep:
- *   which = 0: multipoles of level `level` (2 <= level <= F),
+ *   which = 0: multipoles of level `level` (2 <= level <= F), nterms(nmax) per cell,
  *              Mhat[a] = (-1)^|a| M[a] / (a! h^|a| dx^3), M[a] = sum m (x - c)^a
  *   which = 1: locals of level `level` (3 <= level <= F),
  *              Lhat[b] = h^(|b|+1) L[b] / dx^3, L[b] = d^b phi at the centre

@@ -59,7 +59,6 @@ int validate(int n, int p, int isolated, const fmm_options* o) {
       return fail(FMM_ERR_INVALID_ARG, "nmax must be -1 or in [0, p] (got %d)", o->nmax);
     if (o->delta_l != 1) return fail(FMM_ERR_UNSUPPORTED, "only delta_l = 1 is provided (got %d)", o->delta_l);
     if (o->coarse_fp64_levels < 0) return fail(FMM_ERR_INVALID_ARG, "coarse_fp64_levels must be >= 0");
-    if (o->nmax != -1 && o->nmax != p) return fail(FMM_ERR_UNSUPPORTED, "nmax != p is not built yet");
   }
   return FMM_OK;
 }
@@ -463,7 +462,11 @@ fmm_plan* create_plan(const std::vector<int>& ns, int p, const fmm_options& o, i
     (void)hipGetLastError();
   }
   pl->batch = batch;
-  pl->NM = fmm::nterms(pl->nmax);
+  // multipoles truncated at nmax < p are held in grids of order p whose
+  // terms above nmax are zero (P2M and M2M write them as zero), so every
+  // kernel runs at the size of order p
+  pl->NM = fmm::nterms(p);
+  pl->NMX = fmm::nterms(pl->nmax);
   pl->NC = (pl->NM + 3) / 4;
   pl->NL = fmm::nterms(p);
   pl->NCL = (pl->NL + 3) / 4;
@@ -538,7 +541,7 @@ fmm_plan* create_plan(const std::vector<int>& ns, int p, const fmm_options& o, i
     std::vector<int> start(1, 0), off;
     std::vector<double> coef;
     auto fact = [](int k) { double f = 1; for (int i = 2; i <= k; ++i) f *= i; return f; };
-    const int P = pl->nmax;
+    const int P = pl->p;
     std::vector<int> ex(pl->NM * 3);
     for (int a = 0; a <= P; ++a)
       for (int b = 0; a + b <= P; ++b)
@@ -1040,7 +1043,7 @@ int fmm_debug_expansions(fmm_plan* plan, int which, int level, double* out, size
   const int lo = which == 0 ? 2 : 3;
   if (level < lo || level > plan->F) return fail(FMM_ERR_INVALID_ARG, "level %d outside [%d, %d]", level, lo, plan->F);
   const fmm::Level& lv = plan->lev[level];
-  const int nt = which == 0 ? plan->NM : plan->NL;
+  const int nt = which == 0 ? plan->NMX : plan->NL;
   const int nch = (nt + 3) / 4;
   if (!out || count < (size_t)lv.ncell * nt) return fail(FMM_ERR_INVALID_ARG, "out must hold %lld doubles", lv.ncell * nt);
   const int nk = lv.nk;

@@ -226,7 +226,7 @@ template <int PO>
 __global__ __launch_bounds__(M2MShape<PO>::THREADS) void k_m2m(const Seg* __restrict__ segs, int nseg,
                                                               const int* __restrict__ cstart,
                                                               const int* __restrict__ coff,
-                                                              const double* __restrict__ ccoef) {
+                                                              const double* __restrict__ ccoef, int nmx) {
   constexpr int NM = M2MShape<PO>::NM, NC = M2MShape<PO>::NC, M2M_THREADS = M2MShape<PO>::THREADS;
   constexpr int NE = M2MShape<PO>::NE, M2M_PAR = M2MShape<PO>::PAR;
   constexpr int WS = NM * 8 + 2;  // per-parent stride, padded against bank conflicts
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(M2MShape<PO>::THREADS) void k_m2m(const Seg* __rest
     for (int j = sstart[al]; j < sstart[al + 1]; ++j) acc += scoef[j] * Wp[soff[j]];
     const int p2 = (int)(P % np), p1 = (int)((P / np) % np), p0 = (int)(P / ((long long)np * np));
     const long long cp = ((long long)(p0 + 3) * npp + (p1 + 3)) * npp + (p2 + 3);
-    Mp[((al >> 2) * ncp_p + cp) * 4 + (al & 3)] = acc;
+    Mp[((al >> 2) * ncp_p + cp) * 4 + (al & 3)] = al < nmx ? acc : 0.0;  // truncation at nmax
   }
 }
 
@@ -634,7 +634,7 @@ template <int PO>
 __global__ __launch_bounds__(ADJ_M2M_THREADS) void k_adj_m2m(const double* __restrict__ Mp, double* __restrict__ Mc,
                                                              int np, const int* __restrict__ lstart,
                                                              const int* __restrict__ la,
-                                                             const double* __restrict__ lcoef) {
+                                                             const double* __restrict__ lcoef, int nmx) {
   constexpr int NM = nterms(PO), NC = (NM + 3) / 4, MS = NM | 1;
   constexpr int NE = (PO + 1) * (PO + 2) * (PO + 3) * (PO + 4) * (PO + 5) * (PO + 6) / 720;
   __shared__ double mrow[ADJ_M2M_PAR * MS];
@@ -661,7 +661,7 @@ __global__ __launch_bounds__(ADJ_M2M_THREADS) void k_adj_m2m(const double* __res
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e)
-      if (4 * c + e < NM) mrow[pl * MS + 4 * c + e] = v[e];
+      if (4 * c + e < NM) mrow[pl * MS + 4 * c + e] = 4 * c + e < nmx ? v[e] : 0.0;  // transpose of the truncation
   }
   __syncthreads();
   for (int w = threadIdx.x; w < ADJ_M2M_PAR * NM; w += ADJ_M2M_THREADS) {
@@ -938,7 +938,9 @@ hipError_t solve_ct(fmm_plan* pl, IoArg io, hipStream_t s) {
   hipError_t e;
   {
     StageScope sc(pl, ST_P2M, 1, s);
-    hipLaunchKernelGGL((k_p2m<TI>), dim3(pl->s_p2m.blocks), dim3(256), 0, s, pl->s_p2m.dev, pl->s_p2m.nseg, io, NM, NC);
+    // terms past nmax are written as zero
+    hipLaunchKernelGGL((k_p2m<TI>), dim3(pl->s_p2m.blocks), dim3(256), 0, s, pl->s_p2m.dev, pl->s_p2m.nseg, io, pl->NMX,
+                       NC);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   for (int k = pl->maxF; k >= 3; --k) {
@@ -946,7 +948,7 @@ hipError_t solve_ct(fmm_plan* pl, IoArg io, hipStream_t s) {
     if (!st.nseg) continue;
     StageScope sc(pl, ST_M2M, 1, s);
     hipLaunchKernelGGL((k_m2m<P>), dim3(st.blocks), dim3(M2MShape<P>::THREADS), 0, s, st.dev, st.nseg, pl->m2m_start,
-                       pl->m2m_off, pl->m2m_coef);
+                       pl->m2m_off, pl->m2m_coef, pl->NMX);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if ((e = launch_conv<P, double, CV_M2L>(pl, pl->s_conv[0], pl->wm2l[0], s)) != hipSuccess) return e;
@@ -1001,7 +1003,7 @@ hipError_t adjoint_tables_all(fmm_plan* pl, hipStream_t s) {
 
 template <int P, typename CT, typename TI, typename TO>
 hipError_t backward_ct(fmm_plan* pl, const TI* dphi, const TI* dg, TO* drho, hipStream_t s) {
-  constexpr int NM = nterms(P), NL = nterms(P);
+  constexpr int NL = nterms(P);
   const int n = pl->n, F = pl->F, nF = n / 2;
   const double dx = pl->dx;
   hipError_t e;
@@ -1039,14 +1041,14 @@ hipError_t backward_ct(fmm_plan* pl, const TI* dphi, const TI* dg, TO* drho, hip
     const int np = 1 << (k - 1);
     hipLaunchKernelGGL((k_adj_m2m<P>), dim3(blocks_for((long long)np * np * np, ADJ_M2M_PAR)), dim3(ADJ_M2M_THREADS),
                        0, s, (const double*)pl->lev[k - 1].M, (double*)pl->lev[k].M, np, pl->m2mt_start,
-                       pl->m2mt_a, pl->m2mt_coef);
+                       pl->m2mt_a, pl->m2mt_coef, pl->NMX);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   // nF is a power of two >= 4: the block's z extent divides it
   const int tz = nF < ADJ_BOT_TZ ? nF : ADJ_BOT_TZ;
   dim3 bgrid(nF / 4, nF / 4, nF / tz);
   hipLaunchKernelGGL((k_adj_bottom<TO>), bgrid, dim3(16 * tz), 0, s, (const double*)pl->lev[F].M, pl->ybar, drho, n,
-                     NM);
+                     pl->NMX);
   return hipGetLastError();
 }
 

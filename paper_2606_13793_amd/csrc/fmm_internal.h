@@ -225,7 +225,9 @@ struct fmm_plan {
   int device = 0;
   int cus = 256;  // compute units of the device
   double dx = 0.0;
-  int NM = 0, NC = 0, NL = 0, NCL = 0, ND = 0;
+  // NM multipole terms of order p in the grids and kernels (NC chunks of 4);
+  // NMX = terms of order nmax, the ones kept (the others stay zero)
+  int NM = 0, NC = 0, NL = 0, NCL = 0, ND = 0, NMX = 0;
   std::vector<fmm::Field> fld;  // the fields; fld[0].lev are field 0's grids
   int maxF = 0;
   fmm::Level* lev = nullptr;    // fld[0].lev

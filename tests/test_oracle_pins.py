@@ -386,3 +386,37 @@ def test_adjoint_close_to_direct_sum_gradient(orc):
     phi_f = orc.solve(rho, p)[0]
     grad_fmm = orc.adjoint(2 * (phi_f - phi_t), None, p)
     assert rel(grad_fmm, grad_direct) < 1e-4
+
+
+# --------------------------------------------------------------------------
+# multipoles truncated at nmax < p (Sec. 2.1: separate multipole and local
+# orders; the paper's own pair is p = 3, nmax = 2)
+# --------------------------------------------------------------------------
+def test_truncated_multipoles_are_the_leading_terms(orc):
+    """M2M only maps child terms of degree <= |a| to parent term a, so the
+    multipoles kept at nmax are exactly the leading terms of the order-p
+    multipoles at every level; the truncation drops, never alters."""
+    n, p, nmax = 16, 5, 2
+    rho = fi.plummer_density(n, fi.multi_plummer_params(6, 41))
+    nt = (nmax + 1) * (nmax + 2) * (nmax + 3) // 6
+    for level in (2, 3):
+        full = orc.expansions(rho, p, "M", level)
+        cut = orc.expansions(rho, p, "M", level, nmax=nmax)
+        assert cut.shape[1] == nt
+        assert rel(cut, full[:, :nt]) < 1e-14
+
+
+def test_m2l_with_nmax_sums_only_the_kept_terms(orc):
+    """eq. (M2L) with nmax < p is the order-p M2L of a multipole whose terms
+    above nmax are zero."""
+    rng = np.random.default_rng(43)
+    p, nmax = 4, 2
+    nt_p = (p + 1) * (p + 2) * (p + 3) // 6
+    nt_m = (nmax + 1) * (nmax + 2) * (nmax + 3) // 6
+    M = rng.standard_normal(nt_p)
+    Mz = M.copy()
+    Mz[nt_m:] = 0.0
+    R = np.array([0.31, -0.27, 0.44])
+    assert rel(orc.op_m2l(p, nmax, R, M[:nt_m]), orc.op_m2l(p, p, R, Mz)) < 1e-14
+    # and dropping terms changes the result
+    assert rel(orc.op_m2l(p, nmax, R, M[:nt_m]), orc.op_m2l(p, p, R, M)) > 1e-6
