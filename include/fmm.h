@@ -67,8 +67,8 @@ typedef struct {
   int struct_size;          /* sizeof(fmm_options), for forward compatibility */
   int precision;            /* fmm_precision, default FMM_FP64 */
   int nmax;                 /* multipole order, -1 = p (default); 0 <= nmax <= p.  Multipoles
-                               are truncated at nmax (Sec. 2.1); the solve still runs at the
-                               cost of order p */
+                               are truncated at nmax (Sec. 2.1); M2L and M2P then sum only
+                               the kept terms */
   int coarse_fp64_levels;   /* mixed plans: levels k <= this stay FP64; default 4 */
   int delta_l;              /* level offset unigrid -> finest FMM grid; only 1 */
   int check_finite;         /* nonzero: fmm_solve scans rho for NaN/Inf first (single-field plans) */

@@ -805,6 +805,12 @@ hipError_t build_tile_table(fmm_plan* pl, int op, hipStream_t s) {
   for (int t = 0; t < nt; ++t) {
     h[2 * t] = conv_tile_chunks(op, pl->p, t, KC);
     h[2 * t + 1] = conv_frag_offset(op, pl->p, t, KC);
+    // multipoles truncated at nmax: M2L needs only the K chunks of the kept
+    // terms; the transposes skip column tiles whose terms are all dropped
+    if (op == CV_M2L)
+      h[2 * t] = std::min(h[2 * t], (pl->NMX + KC - 1) / KC);
+    else if (mi_degree(16 * t) > pl->nmax)
+      h[2 * t] = 0;
     // the kernel takes the tiles that have a chunk to be a prefix of the group
     if (t > 0 && h[2 * t] > h[2 * t - 2]) return hipErrorInvalidValue;
   }
@@ -918,15 +924,17 @@ hipError_t launch_bottom(fmm_plan* pl, int x, IoArg io, hipStream_t s) {
   if (z == 0 && pl->s_bot[x][0].blocks < pl->cus) z = 1;
   const SegTable& st = pl->s_bot[x][z];
   if (!st.nseg) return hipSuccess;
+  // M2P K chunks: those of the multipole terms kept (nmax)
+  const int nck = (pl->NMX + Mf<CT>::KC - 1) / Mf<CT>::KC;
   StageScope sc(pl, ST_BOTTOM, 1, s);
   if (z == 0)
     hipLaunchKernelGGL((k_bottom<P, CT, TI, TO, 16>), dim3(st.blocks), dim3(bottom_threads<CT>()), 0, s, st.dev, st.nseg, io,
                        (const H*)pl->wm2p[X], (const H*)pl->wl2p[X], (const H*)pl->wl2p2[X], (const H*)pl->wp2p[X],
-                       pl->dlists);
+                       pl->dlists, nck);
   else
     hipLaunchKernelGGL((k_bottom<P, CT, TI, TO, 8>), dim3(st.blocks), dim3(bottom_threads<CT>()), 0, s, st.dev, st.nseg, io,
                        (const H*)pl->wm2p[X], (const H*)pl->wl2p[X], (const H*)pl->wl2p2[X], (const H*)pl->wp2p[X],
-                       pl->dlists);
+                       pl->dlists, nck);
   return hipGetLastError();
 }
 

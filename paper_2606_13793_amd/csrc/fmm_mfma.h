@@ -220,7 +220,7 @@ template <int P, typename CT, typename TI, typename TO, int BZ>
 __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void k_bottom(
     const Seg* __restrict__ segs, int nseg, IoArg io, const typename Mf<CT>::H* __restrict__ Wm2p,
     const typename Mf<CT>::H* __restrict__ Wl2p, const typename Mf<CT>::H* __restrict__ Wl2p2,
-    const typename Mf<CT>::H* __restrict__ Wp2p, const int* __restrict__ dlists) {
+    const typename Mf<CT>::H* __restrict__ Wp2p, const int* __restrict__ dlists, int nck) {
   using M = Mf<CT>;
   using H = typename M::H;
   using AF = typename M::AF;
@@ -276,7 +276,9 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
     return dl[pos < NLIST ? pos : pos - NLIST];
   };
 
-  for (int c = 0; c < NCK; ++c) {
+  // the M2P K chunks: nck <= NCK, fewer when the multipoles are truncated at
+  // nmax < p (the chunks past it hold only zero terms)
+  for (int c = 0; c < nck; ++c) {
     __syncthreads();  // previous chunk fully consumed
     stage_halo<CT, BZ, THREADS>(halo, Mh, NC4, ncellp, nFp, tx0, ty0, tz0, c);
     __syncthreads();
