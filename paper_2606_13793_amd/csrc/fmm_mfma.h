@@ -33,7 +33,8 @@ struct Mf<double> {
   __device__ static Acc op(AF a, AF b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
   // accumulator element v of a lane with k-group kq holds row:
   __device__ static int row(int v, int kq) { return 4 * v + kq; }
-  __device__ __forceinline__ static AF frag(const double (&v)[1]) { return v[0]; }
+  template <typename E>
+  __device__ __forceinline__ static AF frag(const E (&v)[1]) { return (double)v[0]; }
 };
 template <>
 struct Mf<float> {
@@ -43,7 +44,8 @@ struct Mf<float> {
   static constexpr int KC = 4, OPM = 1, VPL = 1, IDX = 1;
   __device__ static Acc op(AF a, AF b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
   __device__ static int row(int v, int kq) { return 4 * kq + v; }
-  __device__ __forceinline__ static AF frag(const double (&v)[1]) { return (float)v[0]; }
+  template <typename E>
+  __device__ __forceinline__ static AF frag(const E (&v)[1]) { return (float)v[0]; }
 };
 template <>
 struct Mf<bf16_tag> {
@@ -53,7 +55,10 @@ struct Mf<bf16_tag> {
   static constexpr int KC = 16, OPM = 2, VPL = 8, IDX = 2;
   __device__ static Acc op(AF a, AF b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
   __device__ static int row(int v, int kq) { return 4 * kq + v; }
-  __device__ __forceinline__ static AF frag(const double (&v)[8]) {
+  // (round to nearest even; a float converts to the same bf16 directly or
+  // through double, which holds it exactly)
+  template <typename E>
+  __device__ __forceinline__ static AF frag(const E (&v)[8]) {
     AF f;
 #pragma unroll
     for (int e = 0; e < 8; ++e) f[e] = static_cast<__bf16>(v[e]);
@@ -236,7 +241,15 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
   using HL = Halo<CT, BZ>;
   __shared__ H halo[HL::SIZE];
   __shared__ int slist[8 * NLIST_PAD];  // the interaction lists of the 8 parity classes
+  // column of local term bt of child q in the locals' M2L layout, for the
+  // tail's L2P reads (-1 past the last term)
+  __shared__ int scol[8 * NLT * KT];
   for (int t = threadIdx.x; t < 8 * NLIST_PAD; t += THREADS) slist[t] = dlists[t];
+  for (int t = threadIdx.x; t < 8 * NLT * KT; t += THREADS) {
+    const int q = t / (NLT * KT), bt = t - q * (NLT * KT);
+    const int ex = c_mi_exp[bt < NL ? bt : 0];
+    scol[t] = bt < NL ? m2l_col(q, bt, mi_a(ex) + mi_b(ex) + mi_c(ex)) : -1;
+  }
   const Seg& sg = find_seg(segs, nseg, blockIdx.x);
   const int nF = sg.n;
   const double* __restrict__ Mh = sg.a;
@@ -349,8 +362,9 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
   };
   // tail K blocks of row tile m: L2P of the M2L part of the own local (stored
   // with the parent P'), L2P from the parent level's full local, near field.
-  // U chunks at a time, their operand loads issued together.
-  constexpr int U = M::IDX == 1 ? 2 : 1;
+  // UL (L2P) and UN (near field) chunks at a time, their operand loads issued
+  // together: the tail is bound by load latency, not by its few products.
+  constexpr int UL = M::IDX == 1 ? 2 : 1, UN = 4;
   auto tail = [&](int m, Acc (&am)[2]) {
     int c0, c1, c2;
     cell_of(m, c0, c1, c2);
@@ -360,22 +374,23 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
       const auto par =
           gmem(Lpar ? Lpar + (((long long)(c0 >> 2) * nPP + (c1 >> 2)) * nPP + (c2 >> 2)) * RS : Lf);
       const int qP = (((c0 >> 1) & 1) << 2) | (((c1 >> 1) & 1) << 1) | ((c2 >> 1) & 1);
+      const int* colr = scol + r * (NLT * KT);
+      const int* colq = scol + qP * (NLT * KT);
       const H* w2 = Wl2p2 + (size_t)r * NLT * 2 * 64 * VPL + lane * VPL;
 #pragma unroll 1
-      for (int cb = 0; cb < NLT; cb += U) {
-        double va[U][VPL], vp[U][VPL];
-        AF bo[U][2], bp[U][2];
+      for (int cb = 0; cb < NLT; cb += UL) {
+        double va[UL][VPL], vp[UL][VPL];
+        AF bo[UL][2], bp[UL][2];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int u = 0; u < UL; ++u) {
           const int c = cb + u < NLT ? cb + u : 0;
 #pragma unroll
           for (int v = 0; v < VPL; ++v) {
             const int bt = KT * c + VPL * kq + v;
-            const bool ok = cb + u < NLT && bt < NL;
-            const int ex = c_mi_exp[ok ? bt : 0];
-            const int deg = mi_a(ex) + mi_b(ex) + mi_c(ex);
-            va[u][v] = ok ? own[m2l_col(r, bt, deg)] : 0.0;
-            vp[u][v] = (ok && Lpar) ? par[m2l_col(qP, bt, deg)] : 0.0;
+            const int co = colr[bt], cq = colq[bt];
+            const bool ok = cb + u < NLT && co >= 0;
+            va[u][v] = ok ? own[co] : 0.0;
+            vp[u][v] = (ok && Lpar) ? par[cq] : 0.0;
           }
 #pragma unroll
           for (int t = 0; t < 2; ++t) {
@@ -384,7 +399,7 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
           }
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int u = 0; u < UL; ++u) {
           if (cb + u < NLT) {
             am[0] = M::op(M::frag(va[u]), bo[u][0], am[0]);
             am[1] = M::op(M::frag(va[u]), bo[u][1], am[1]);
@@ -398,26 +413,26 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
     }
     const auto rg = gmem(rho);
 #pragma unroll 1
-    for (int cb = 0; cb < NPT; cb += U) {
-      double va[U][VPL];
-      AF bn[U][2];
+    for (int cb = 0; cb < NPT; cb += UN) {
+      TI va[UN][VPL];  // densities in the input type until the conversion
+      AF bn[UN][2];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < UN; ++u) {
         const int c = cb + u < NPT ? cb + u : 0;
 #pragma unroll
         for (int v = 0; v < VPL; ++v) {
           const int k = KT * c + VPL * kq + v;
           const int w0 = 2 * c0 + k / 36 - 2, w1 = 2 * c1 + (k / 6) % 6 - 2, w2 = 2 * c2 + k % 6 - 2;
           va[u][v] = (cb + u < NPT && k < 216 && w0 >= 0 && w1 >= 0 && w2 >= 0 && w0 < n && w1 < n && w2 < n)
-                         ? (double)rg[((long long)w0 * n + w1) * n + w2]
-                         : 0.0;
+                         ? rg[((long long)w0 * n + w1) * n + w2]
+                         : TI(0);
         }
 #pragma unroll
         for (int t = 0; t < 2; ++t)
           bn[u][t] = *reinterpret_cast<const AF*>(Wp2p + ((size_t)(c * 2 + t) * 64 + lane) * VPL);
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
+      for (int u = 0; u < UN; ++u) {
         if (cb + u < NPT) {
           am[0] = M::op(M::frag(va[u]), bn[u][0], am[0]);
           am[1] = M::op(M::frag(va[u]), bn[u][1], am[1]);
