@@ -231,9 +231,9 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
   using AF = typename M::AF;
   using Acc = typename M::Acc;
   using S = BotShape<BZ>;
-  constexpr int HZ = S::HZ, HZ2 = S::HZ2, BZ2 = S::BZ2, BOT_MT = S::MT, YPT = S::YPT, TPX = S::TPX;
+  constexpr int BZ2 = S::BZ2, BOT_MT = S::MT, YPT = S::YPT, TPX = S::TPX;
   constexpr int KC = M::KC, OPM = M::OPM, VPL = M::VPL, EL = 64 / OPM;
-  constexpr int NM = nterms(P), NC4 = (NM + 3) / 4, NCK = (NM + KC - 1) / KC;
+  constexpr int NM = nterms(P), NC4 = (NM + 3) / 4;
   constexpr int NL = nterms(P);
   constexpr int KT = 4 * VPL, NLT = (NL + KT - 1) / KT, NPT = (216 + KT - 1) / KT;
   constexpr int NGRP = (NLIST + OPM - 1) / OPM;
@@ -289,8 +289,8 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
     return dl[pos < NLIST ? pos : pos - NLIST];
   };
 
-  // the M2P K chunks: nck <= NCK, fewer when the multipoles are truncated at
-  // nmax < p (the chunks past it hold only zero terms)
+  // the M2P K chunks: nck <= ceil(NM / KC), fewer when the multipoles are
+  // truncated at nmax < p (the chunks past it hold only zero terms)
   for (int c = 0; c < nck; ++c) {
     __syncthreads();  // previous chunk fully consumed
     stage_halo<CT, BZ, THREADS>(halo, Mh, NC4, ncellp, nFp, tx0, ty0, tz0, c);
@@ -599,7 +599,7 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   constexpr int NGRP = (NLIST + OPM - 1) / OPM;
   using S = BotShape<CZ>;
   constexpr int CMT = S::MT;  // row tiles per wave
-  constexpr int HZ = S::HZ, HZ2 = S::HZ2, BZ2 = S::BZ2, YPT = S::YPT, TPX = S::TPX;
+  constexpr int BZ2 = S::BZ2, YPT = S::YPT, TPX = S::TPX;
   using HL = Halo<CT, CZ>;
   __shared__ H halo[HL::SIZE];
   __shared__ int slist[8 * NLIST_PAD];  // the interaction lists of the 8 parity classes
@@ -622,7 +622,6 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
     vt[t] = e.x;
     off[t] = e.y;
   }
-  const int CM = vt[0];
   const int tx0 = (tb / (tpa * sg.tz)) * CX, ty0 = ((tb / sg.tz) % tpa) * CX, tz0 = (tb % sg.tz) * CZ;
   const long long ncellp = (long long)nsp * nsp * nsp;
   const int lane = threadIdx.x & 63;
