@@ -278,8 +278,8 @@ def run_extras(args, rho64, fi, fmm, costs, sections=("mixed", "adjoint", "batch
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(every box has one MI355X; see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the solver "
+              "runs on one GPU (its multi-GPU sharding is designed but not built)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -1,6 +1,6 @@
 """Parity of the HIP solver (through the C ABI) with the FP64 CPU oracle.
 
-Bar: relative L2 error <= 1e-12 for phi and g in FP64 (spec tolerance;
+Bar: relative L2 error <= 1e-12 for phi and g in FP64 (the stated FP64 tolerance;
 the two sides differ only in rounding order: scaled vs physical units,
 different derivative recurrences, matrix-core vs scalar summation).
 """
