@@ -335,6 +335,19 @@ def main():
     ms_per_step = 1e3 * elapsed / args.steps
     cells_per_s = n ** 3 * args.steps / elapsed
     log(f"timed {args.steps} solves: {ms_per_step:.3f} ms/solve, {cells_per_s:.4e} cells/s")
+    # spread of single solves (HIP events around each, after the timed
+    # region): median and mean +- 1 sigma, the paper's timing protocol
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a, b in evs:
+        a.record()
+        plan.solve_into(rho, phi, g)
+        b.record()
+    torch.cuda.synchronize()
+    per = np.array([a.elapsed_time(b) for a, b in evs])
+    spread = {"samples": len(per), "median_ms": float(np.median(per)), "mean_ms": float(per.mean()),
+              "std_ms": float(per.std(ddof=1)) if len(per) > 1 else 0.0, "min_ms": float(per.min()),
+              "max_ms": float(per.max())}
+    log(f"single solves: median {spread['median_ms']:.3f} ms, mean {spread['mean_ms']:.3f} +- {spread['std_ms']:.3f} ms")
 
     flops = costs.solve_flops(n, p)
     stage_flops = {"p2m": flops["p2m"], "m2m": flops["m2m"], "m2l": flops["m2l"], "bottom": flops["bottom"]}
@@ -441,6 +454,7 @@ def main():
         "stages": stages,
         "kernels": extra,
         "parity_vs_oracle": parity,
+        "solve_ms_spread": spread,
         **extras,
     }
     print(json.dumps(out), flush=True)
