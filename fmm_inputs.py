@@ -109,6 +109,16 @@ def uniform_sphere_density(n: int, centre, radius: float, value: float = 1.0) ->
     return np.where(r2 <= radius * radius, value, 0.0).astype(np.float64)
 
 
+def point_charge_cic(n: int, mass: float = 1.0) -> np.ndarray:
+    """Density of a point mass at the centre of the unit box deposited by
+    cloud-in-cell: the point sits on the common corner of the 8 central cells,
+    so each receives mass / 8 (density mass / 8 / dx^3)."""
+    rho = np.zeros((n, n, n))
+    h = n // 2
+    rho[h - 1:h + 1, h - 1:h + 1, h - 1:h + 1] = mass / 8.0 * n ** 3
+    return rho
+
+
 def batch_sizes(count: int = 96, seed: int = 4) -> list[int]:
     """Grid sizes of the uneven batch: 32^3, 64^3, 128^3 in ratio 4:2:1.
 

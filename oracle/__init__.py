@@ -52,6 +52,8 @@ def lib():
         L.or_op_m2p.argtypes = [ctypes.c_int, _dp, _dp, _dp]
         L.or_solve.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
                                ctypes.c_longlong, _lp, _dp, _dp]
+        L.or_solve_dl.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
+                                  ctypes.c_longlong, _lp, _dp, _dp]
         L.or_expansions.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
                                     ctypes.c_int, ctypes.c_int, _dp]
         L.or_direct.argtypes = [ctypes.c_int, _dp, ctypes.c_longlong, _lp, _dp, _dp]
@@ -62,6 +64,7 @@ def lib():
         L.or_pair_pass.argtypes = [ctypes.c_int, ctypes.c_longlong, ctypes.c_longlong]
         L.or_list_size.argtypes = [ctypes.c_int] * 4
         L.or_pair_pass_row.argtypes = [ctypes.c_int, ctypes.c_longlong, _ip]
+        L.or_pair_pass_row_dl.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_longlong, _ip]
         _lib = L
     return _lib
 
@@ -136,23 +139,25 @@ def op_m2p(nmax: int, R, M) -> np.ndarray:
     return out
 
 
-def solve(rho, p: int, nmax: int | None = None, targets=None):
+def solve(rho, p: int, nmax: int | None = None, targets=None, delta_l: int = 1):
     """FMM potential and acceleration.  Returns (phi, g): full grid shapes
-    (n,n,n) and (3,n,n,n), or (k,) and (3,k) for ``targets`` (flat indices)."""
+    (n,n,n) and (3,n,n,n), or (k,) and (3,k) for ``targets`` (flat indices).
+    ``delta_l`` = 1 (FMM-1) or 2 (FMM-2): the finest FMM level sits that many
+    levels above the unigrid (App. A)."""
     rho = _f64(rho)
     n = rho.shape[0]
     nmax = p if nmax is None else nmax
     if targets is None:
         phi = np.zeros((n, n, n))
         g = np.zeros((3, n, n, n))
-        rc = lib().or_solve(n, p, nmax, _d(rho), 0, None, _d(phi), _d(g))
+        rc = lib().or_solve_dl(n, p, nmax, delta_l, _d(rho), 0, None, _d(phi), _d(g))
     else:
         t = np.ascontiguousarray(targets, dtype=np.int64)
         phi = np.zeros(len(t))
         g = np.zeros((3, len(t)))
-        rc = lib().or_solve(n, p, nmax, _d(rho), len(t), t.ctypes.data_as(_lp), _d(phi), _d(g))
+        rc = lib().or_solve_dl(n, p, nmax, delta_l, _d(rho), len(t), t.ctypes.data_as(_lp), _d(phi), _d(g))
     if rc != 0:
-        raise ValueError(f"oracle solve rejected n={n} p={p} nmax={nmax}")
+        raise ValueError(f"oracle solve rejected n={n} p={p} nmax={nmax} delta_l={delta_l}")
     return phi, g
 
 
@@ -208,9 +213,12 @@ def list_size(level: int, i: int, j: int, l: int) -> int:
     return lib().or_list_size(level, i, j, l)
 
 
-def pair_pass_row(n: int, u: int) -> np.ndarray:
+def pair_pass_row(n: int, u: int, delta_l: int = 1) -> np.ndarray:
     out = np.zeros(n ** 3, dtype=np.int32)
-    lib().or_pair_pass_row(n, u, out.ctypes.data_as(_ip))
+    if delta_l == 1:
+        lib().or_pair_pass_row(n, u, out.ctypes.data_as(_ip))
+    else:
+        lib().or_pair_pass_row_dl(n, delta_l, u, out.ctypes.data_as(_ip))
     return out
 
 

@@ -53,8 +53,11 @@
  *  - The acceleration returned is -grad(phi) of the FMM potential: L2P
  *    differentiates the local polynomial, M2P uses D up to order nmax + 1,
  *    P2P is the exact pairwise force.
- *  - Level k has 2^k cells per axis; the finest FMM level is F = L - 1
- *    (delta_l = 1, App. A); locals exist from level 3, L2L from level 4.
+ *  - Level k has 2^k cells per axis; the finest FMM level is F = L - dl,
+ *    dl = 1 (FMM-1) or 2 (FMM-2), App. A: a finest FMM cell holds 8^dl
+ *    unigrid cells and the near field of a unigrid cell is the 27 x 8^dl
+ *    cells of the finest FMM cells adjacent to its own (Sec. 4); locals
+ *    exist from level 3, L2L from level 4.
  */
 #include <math.h>
 #include <stdint.h>
@@ -294,7 +297,7 @@ static double green_soft(const double r[3], double dx) {
 /* the solver state                                                     */
 /* ------------------------------------------------------------------ */
 typedef struct {
-  int n, L, F, p, nmax, ntM, ntL;
+  int n, L, F, dl, p, nmax, ntM, ntL;
   double dx;
   mindex mi;       /* orders up to p + 1 */
   double *mass;    /* n^3 */
@@ -308,11 +311,11 @@ static int ilog2(int n) {
   return (1 << L) == n ? L : -1;
 }
 
-static int st_init(ostate *s, int n, int p, int nmax) {
+static int st_init(ostate *s, int n, int p, int nmax, int dl) {
   memset(s, 0, sizeof(*s));
   int L = ilog2(n);
-  if (L < 3 || L > 10 || p < 1 || p > 8 || nmax < 0 || nmax > p) return -1;
-  s->n = n; s->L = L; s->F = L - 1; s->p = p; s->nmax = nmax;
+  if (dl < 1 || dl > 2 || L < 2 + dl || L > 10 || p < 1 || p > 8 || nmax < 0 || nmax > p) return -1;
+  s->n = n; s->L = L; s->F = L - dl; s->dl = dl; s->p = p; s->nmax = nmax;
   s->ntM = nterms(nmax); s->ntL = nterms(p);
   s->dx = 1.0 / n;
   mi_init(&s->mi, p + 1);
@@ -326,7 +329,7 @@ static void st_free(ostate *s) {
 
 /* upward pass: P2M on the finest FMM level, then M2M up to level 2 */
 static void upward(ostate *s, const double *rho) {
-  const int n = s->n, F = s->F, ntM = s->ntM;
+  const int n = s->n, F = s->F, dl = s->dl, ntM = s->ntM;
   const double vol = s->dx * s->dx * s->dx;
   s->mass = (double *)malloc(sizeof(double) * (size_t)n * n * n);
 #pragma omp parallel for schedule(static)
@@ -340,8 +343,10 @@ static void upward(ostate *s, const double *rho) {
   for (i64 T = 0; T < (i64)nF * nF * nF; ++T) {
     int t0 = (int)(T / ((i64)nF * nF)), t1 = (int)((T / nF) % nF), t2 = (int)(T % nF);
     double *M = s->M[F] + T * ntM;
-    for (int q = 0; q < 8; ++q) {
-      int i = 2 * t0 + ((q >> 2) & 1), j = 2 * t1 + ((q >> 1) & 1), l = 2 * t2 + (q & 1);
+    /* the 8^dl unigrid cells of T */
+    const int m = (1 << dl) - 1;
+    for (int q = 0; q < (1 << (3 * dl)); ++q) {
+      int i = (t0 << dl) + ((q >> (2 * dl)) & m), j = (t1 << dl) + ((q >> dl) & m), l = (t2 << dl) + (q & m);
       double v[3] = {centre(i, s->L) - centre(t0, F), centre(j, s->L) - centre(t1, F),
                      centre(l, s->L) - centre(t2, F)};
       op_p2m(&s->mi, ntM, s->mass[lin(i, j, l, n)], v, M);
@@ -364,19 +369,21 @@ static void upward(ostate *s, const double *rho) {
 }
 
 /* D tables for the fixed geometry (Sec. 2.2: displacements and Green's
-   function derivatives are precomputed).  For target level k (child q of P)
-   and source J = P - d at level k-1, R = c_k(2P+q) - c_{k-1}(P-d); with P = 0
-   this is centre(q, k) - centre(-d, k-1).  Layout [q][d+3 (343)][nterms(P)]. */
-static double *geometry_table(const ostate *s, int k, int P) {
-  const int nt = nterms(P);
-  double *tab = (double *)malloc(sizeof(double) * (size_t)8 * 343 * nt);
+   function derivatives are precomputed).  For a target at level k, descendant
+   q of a cell P of level ks = k - sh, and source J = P - d at level ks,
+   R = c_k(2^sh P + q) - c_ks(P - d); with P = 0 this is
+   centre(q, k) - centre(-d, ks).  Layout [q (8^sh)][d+3 (343)][nterms(P)]. */
+static double *geometry_table(const ostate *s, int k, int sh, int P) {
+  const int nt = nterms(P), nq = 1 << (3 * sh), m = (1 << sh) - 1;
+  (void)s;
+  double *tab = (double *)malloc(sizeof(double) * (size_t)nq * 343 * nt);
 #pragma omp parallel for schedule(static)
-  for (int qd = 0; qd < 8 * 343; ++qd) {
+  for (int qd = 0; qd < nq * 343; ++qd) {
     int q = qd / 343, dd = qd % 343;
     int d0 = dd / 49 - 3, d1 = (dd / 7) % 7 - 3, d2 = dd % 7 - 3;
-    int q0 = (q >> 2) & 1, q1 = (q >> 1) & 1, q2 = q & 1;
-    double R[3] = {centre(q0, k) - centre(-d0, k - 1), centre(q1, k) - centre(-d1, k - 1),
-                   centre(q2, k) - centre(-d2, k - 1)};
+    int q0 = (q >> (2 * sh)) & m, q1 = (q >> sh) & m, q2 = q & m;
+    double R[3] = {centre(q0, k) - centre(-d0, k - sh), centre(q1, k) - centre(-d1, k - sh),
+                   centre(q2, k) - centre(-d2, k - sh)};
     if (abs(d0) <= 1 && abs(d1) <= 1 && abs(d2) <= 1) {
       for (int i = 0; i < nt; ++i) tab[(size_t)qd * nt + i] = 0.0; /* never used */
     } else {
@@ -393,7 +400,7 @@ static void downward(ostate *s, unsigned char **need) {
     const int nk = 1 << k, ns = 1 << (k - 1);
     i64 nc = (i64)1 << (3 * k);
     s->Lc[k] = (double *)calloc((size_t)(nc * ntL), sizeof(double));
-    double *tab = geometry_table(s, k, p);
+    double *tab = geometry_table(s, k, 1, p);
 #pragma omp parallel for schedule(dynamic, 64)
     for (i64 T = 0; T < nc; ++T) {
       if (need && !need[k][T]) continue;
@@ -419,11 +426,12 @@ static void downward(ostate *s, unsigned char **need) {
   }
 }
 
-/* finest level: L2P + M2P + P2P at unigrid cell u */
+/* finest level: L2P + M2P + P2P at unigrid cell u; T = T_F(u) is the
+   finest FMM cell holding u and q the position of u inside it */
 static void bottom_cell(const ostate *s, const double *tab, int i, int j, int l, double *phi, double g[3]) {
-  const int n = s->n, F = s->F, nF = 1 << F;
-  const int t0 = i >> 1, t1 = j >> 1, t2 = l >> 1;
-  const int q = ((i & 1) << 2) | ((j & 1) << 1) | (l & 1);
+  const int n = s->n, F = s->F, nF = 1 << F, dl = s->dl, m = (1 << dl) - 1;
+  const int t0 = i >> dl, t1 = j >> dl, t2 = l >> dl;
+  const int q = ((i & m) << (2 * dl)) | ((j & m) << dl) | (l & m);
   *phi = 0.0; g[0] = g[1] = g[2] = 0.0;
   if (F >= 3) {
     double v[3] = {centre(i, s->L) - centre(t0, F), centre(j, s->L) - centre(t1, F),
@@ -438,11 +446,12 @@ static void bottom_cell(const ostate *s, const double *tab, int i, int j, int l,
         op_m2p(&s->mi, s->nmax, tab + ((size_t)q * 343 + dd) * nterms(s->nmax + 1),
                s->M[F] + lin(j0, j1, j2, nF) * s->ntM, phi, g);
       }
+  /* near field: every unigrid cell of the finest FMM cells adjacent to T */
   const double xu[3] = {centre(i, s->L), centre(j, s->L), centre(l, s->L)};
-  for (int w0 = i - 3; w0 <= i + 3; ++w0)
-    for (int w1 = j - 3; w1 <= j + 3; ++w1)
-      for (int w2 = l - 3; w2 <= l + 3; ++w2) {
-        if (!inside(w0, w1, w2, n) || !adjacent(t0, t1, t2, w0 >> 1, w1 >> 1, w2 >> 1)) continue;
+  for (int w0 = (t0 - 1) << dl; w0 < (t0 + 2) << dl; ++w0)
+    for (int w1 = (t1 - 1) << dl; w1 < (t1 + 2) << dl; ++w1)
+      for (int w2 = (t2 - 1) << dl; w2 < (t2 + 2) << dl; ++w2) {
+        if (!inside(w0, w1, w2, n) || !adjacent(t0, t1, t2, w0 >> dl, w1 >> dl, w2 >> dl)) continue;
         double m = s->mass[lin(w0, w1, w2, n)];
         double r[3] = {xu[0] - centre(w0, s->L), xu[1] - centre(w1, s->L), xu[2] - centre(w2, s->L)};
         *phi += m * green_soft(r, s->dx);
@@ -526,10 +535,10 @@ int or_op_m2p(int nmax, const double *R, const double *M, double *out4) {
  *                  only the ancestors of the targets get local expansions.
  * Returns 0, or -1 on invalid arguments.
  */
-static int solve_impl(int n, int p, int nmax, const double *rho, i64 ntarget, const i64 *targets,
+static int solve_impl(int n, int p, int nmax, int dl, const double *rho, i64 ntarget, const i64 *targets,
                       double *phi, double *g, double *times) {
   ostate s;
-  if (st_init(&s, n, p, nmax) != 0) return -1;
+  if (st_init(&s, n, p, nmax, dl) != 0) return -1;
   const double t0 = wall_seconds();
   upward(&s, rho);
   const double t1 = wall_seconds();
@@ -547,7 +556,7 @@ static int solve_impl(int n, int p, int nmax, const double *rho, i64 ntarget, co
     }
   }
   downward(&s, targets ? need : NULL);
-  double *tab = geometry_table(&s, F + 1, s.nmax + 1); /* targets at level L, sources at F */
+  double *tab = geometry_table(&s, s.L, dl, s.nmax + 1); /* targets at level L, sources at F */
   (void)nF;
   if (!targets) {
     const i64 N = (i64)n * n * n;
@@ -577,14 +586,21 @@ static int solve_impl(int n, int p, int nmax, const double *rho, i64 ntarget, co
 
 int or_solve(int n, int p, int nmax, const double *rho, i64 ntarget, const i64 *targets,
              double *phi, double *g) {
-  return solve_impl(n, p, nmax, rho, ntarget, targets, phi, g, NULL);
+  return solve_impl(n, p, nmax, 1, rho, ntarget, targets, phi, g, NULL);
+}
+
+/* or_solve with the finest FMM level dl levels above the unigrid (App. A):
+   dl = 1 is FMM-1 (or_solve), dl = 2 FMM-2 (n >= 16). */
+int or_solve_dl(int n, int p, int nmax, int dl, const double *rho, i64 ntarget, const i64 *targets,
+                double *phi, double *g) {
+  return solve_impl(n, p, nmax, dl, rho, ntarget, targets, phi, g, NULL);
 }
 
 /* or_solve that also reports wall seconds of the upward pass (times[0]) and
    of the downward pass for the requested targets (times[1]). */
 int or_solve_timed(int n, int p, int nmax, const double *rho, i64 ntarget, const i64 *targets,
                    double *phi, double *g, double *times) {
-  return solve_impl(n, p, nmax, rho, ntarget, targets, phi, g, times);
+  return solve_impl(n, p, nmax, 1, rho, ntarget, targets, phi, g, times);
 }
 
 /* OpenMP threads the oracle runs with. */
@@ -600,7 +616,7 @@ int or_threads(void) {
    physical units and the oracle's multi-index order: out[8^level][nterms]. */
 int or_expansions(int n, int p, int nmax, const double *rho, int which, int level, double *out) {
   ostate s;
-  if (st_init(&s, n, p, nmax) != 0) return -1;
+  if (st_init(&s, n, p, nmax, 1) != 0) return -1;
   if (which == 0 && (level < 2 || level > s.F)) return -1;
   if (which == 1 && (level < 3 || level > s.F)) return -1;
   upward(&s, rho);
@@ -652,7 +668,7 @@ int or_direct(int n, const double *rho, i64 ntarget, const i64 *targets, double 
  */
 int or_adjoint(int n, int p, int nmax, const double *dphi, const double *dg, double *drho) {
   ostate s;
-  if (st_init(&s, n, p, nmax) != 0) return -1;
+  if (st_init(&s, n, p, nmax, 1) != 0) return -1;
   const int F = s.F, Lv = s.L, ntM = s.ntM, ntL = s.ntL;
   const i64 N = (i64)n * n * n;
   const int nF = 1 << F;
@@ -708,7 +724,7 @@ int or_adjoint(int n, int p, int nmax, const double *dphi, const double *dg, dou
   }
   /* M2P^T (gather over targets T whose list holds J) */
   {
-    double *tab = geometry_table(&s, F + 1, nmax + 1);
+    double *tab = geometry_table(&s, F + 1, 1, nmax + 1);
     const int ntD = nterms(nmax + 1);
 #pragma omp parallel for schedule(dynamic, 64)
     for (i64 J = 0; J < (i64)nF * nF * nF; ++J) {
@@ -762,7 +778,7 @@ int or_adjoint(int n, int p, int nmax, const double *dphi, const double *dg, dou
         }
       }
     }
-    double *tab = geometry_table(&s, k, p);
+    double *tab = geometry_table(&s, k, 1, p);
     const int ntD = nterms(p);
 #pragma omp parallel for schedule(dynamic, 64)
     for (i64 J = 0; J < (i64)ns * ns * ns; ++J) {
@@ -843,21 +859,22 @@ int or_adjoint(int n, int p, int nmax, const double *dphi, const double *dg, dou
  * no pass counts the pair and -3 if several do.  Used to check that the
  * fields of Sec. 2.2 partition the domain.
  */
-int or_pair_pass(int n, i64 u, i64 w) {
+static int pair_pass(int n, int dl, i64 u, i64 w) {
   int L = ilog2(n);
-  if (L < 3) return -4;
-  const int F = L - 1;
+  if (L < 2 + dl || dl < 1 || dl > 2) return -4;
+  const int F = L - dl;
   int ui[3] = {(int)(u / ((i64)n * n)), (int)((u / n) % n), (int)(u % n)};
   int wi[3] = {(int)(w / ((i64)n * n)), (int)((w / n) % n), (int)(w % n)};
   int count = 0, res = -2;
-  if (adjacent(ui[0] >> 1, ui[1] >> 1, ui[2] >> 1, wi[0] >> 1, wi[1] >> 1, wi[2] >> 1)) { ++count; res = -1; }
-  if (in_list(ui[0] >> 1, ui[1] >> 1, ui[2] >> 1, wi[0] >> 1, wi[1] >> 1, wi[2] >> 1)) { ++count; res = F; }
+  if (adjacent(ui[0] >> dl, ui[1] >> dl, ui[2] >> dl, wi[0] >> dl, wi[1] >> dl, wi[2] >> dl)) { ++count; res = -1; }
+  if (in_list(ui[0] >> dl, ui[1] >> dl, ui[2] >> dl, wi[0] >> dl, wi[1] >> dl, wi[2] >> dl)) { ++count; res = F; }
   for (int k = 3; k <= F; ++k) {
     int sh = L - (k - 1);
     if (in_list(ui[0] >> sh, ui[1] >> sh, ui[2] >> sh, wi[0] >> sh, wi[1] >> sh, wi[2] >> sh)) { ++count; res = k - 1; }
   }
   return count > 1 ? -3 : res;
 }
+int or_pair_pass(int n, i64 u, i64 w) { return pair_pass(n, 1, u, w); }
 
 /* Size of the (clipped) interaction list of cell (i,j,l) at level k. */
 int or_list_size(int k, int i, int j, int l) {
@@ -874,6 +891,14 @@ int or_list_size(int k, int i, int j, int l) {
 int or_pair_pass_row(int n, i64 u, int *out) {
   const i64 N = (i64)n * n * n;
 #pragma omp parallel for schedule(static)
-  for (i64 w = 0; w < N; ++w) out[w] = or_pair_pass(n, u, w);
+  for (i64 w = 0; w < N; ++w) out[w] = pair_pass(n, 1, u, w);
+  return 0;
+}
+
+/* or_pair_pass_row with the finest FMM level dl levels above the unigrid. */
+int or_pair_pass_row_dl(int n, int dl, i64 u, int *out) {
+  const i64 N = (i64)n * n * n;
+#pragma omp parallel for schedule(static)
+  for (i64 w = 0; w < N; ++w) out[w] = pair_pass(n, dl, u, w);
   return 0;
 }
