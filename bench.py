@@ -194,6 +194,31 @@ def run_extras(args, rho64, fi, fmm, costs, sections=("mixed", "adjoint", "batch
         out["paper_orders"] = {"p": 3, "nmax": 2, "ms_per_solve": ms, "phi_err_vs_direct": _rel(ps, phi_d)}
         del plan, phi, g
         log(f"extras: fp64 p=3 nmax=2: {ms:.2f} ms, error vs direct {out['paper_orders']['phi_err_vs_direct']:.3e}")
+    # FMM-2 (finest FMM level two above the unigrid, App. A): time and error
+    # at order P and at the paper's orders, and the FMM-1 vs FMM-2 potential
+    # difference of a CIC point charge at the box centre on the midplane
+    if "mixed" in sections and P >= 3:
+        fmm2 = {}
+        for q, nm in ((P, None), (3, 2)):
+            plan = fmm.Plan(n, q, "fp64", nmax=nm, delta_l=2)
+            phi = torch.empty((n, n, n), dtype=torch.float64, device="cuda")
+            g = torch.empty((3, n, n, n), dtype=torch.float64, device="cuda")
+            ms = _event_ms(lambda: plan.solve_into(rho64, phi, g), 5, 2)
+            ps, _ = sampled(plan, rho64)
+            key = f"p{q}" + ("" if nm is None else f"_nmax{nm}")
+            fmm2[key] = {"ms_per_solve": ms, "cells_per_s": N / (ms * 1e-3), "phi_err_vs_direct": _rel(ps, phi_d)}
+            del plan, phi, g
+            log(f"extras: fmm-2 {key}: {ms:.2f} ms, error vs direct {fmm2[key]['phi_err_vs_direct']:.3e}")
+        pc = torch.as_tensor(fi.point_charge_cic(n)).cuda()
+        s1 = fmm.Plan(n, 3, "fp64", nmax=2).solve(pc, want_g=False)[0][:, :, n // 2].cpu().numpy()
+        s2 = fmm.Plan(n, 3, "fp64", nmax=2, delta_l=2).solve(pc, want_g=False)[0][:, :, n // 2].cpu().numpy()
+        d = np.abs(s2 - s1) / np.abs(s1)
+        fmm2["point_charge_fmm1_vs_fmm2"] = {"p": 3, "nmax": 2, "slice": "midplane through the charge",
+                                             "max": float(d.max()), "p99": float(np.percentile(d, 99)),
+                                             "p90": float(np.percentile(d, 90))}
+        del pc
+        log(f"extras: point charge FMM-1 vs FMM-2: max {d.max():.3e}, p99 {np.percentile(d, 99):.3e}")
+        out["fmm2"] = fmm2
     # mixed precision at order P
     mixed = {}
     if "mixed" in sections:

@@ -8,8 +8,11 @@
  * one downward pass (M2L over the fixed oct-shared interaction lists of
  * Sec. 2.2, eq. (M2L); L2L, eq. (L2L); and at the finest FMM level L2P, M2P
  * at the unigrid cell centres and the near-field direct sum, eq. (direct),
- * Sec. 2.3 and Sec. 4).  Cartesian expansions to order p; the FMM grids sit
- * delta_l = 1 level above the unigrid (App. A).
+ * Sec. 2.3 and Sec. 4).  Cartesian expansions to order p; the finest FMM
+ * grid sits delta_l levels above the unigrid (App. A): 1 (FMM-1, default) or
+ * 2 (FMM-2, whose finest FMM cells hold 4^3 unigrid cells and whose near
+ * field is the 27 x 64 cells of the adjacent ones; FP64 single-field plans,
+ * forward solve).
  *
  * Conventions shared by every entry point
  *  - Grid: unit box [0,1]^3, n cells per axis, cell (i,j,k) centred at
@@ -48,7 +51,8 @@ typedef struct fmm_plan fmm_plan;
 typedef enum {
   FMM_OK = 0,
   FMM_ERR_INVALID_ARG = -1,   /* bad size, order, pointer or option */
-  FMM_ERR_UNSUPPORTED = -2,   /* well-formed but not provided (periodic BC, delta_l != 1) */
+  FMM_ERR_UNSUPPORTED = -2,   /* well-formed but not provided (periodic BC, delta_l outside {1, 2},
+                                 delta_l = 2 with FP32/BF16, a batch or the backward pass) */
   FMM_ERR_OUT_OF_MEMORY = -3, /* device allocation failed */
   FMM_ERR_DEVICE = -4,        /* HIP runtime error (no device, launch failure) */
   FMM_ERR_NONFINITE = -5      /* rho holds NaN/Inf (only with check_finite) */
@@ -70,7 +74,9 @@ typedef struct {
                                are truncated at nmax (Sec. 2.1); M2L and M2P then sum only
                                the kept terms */
   int coarse_fp64_levels;   /* mixed plans: levels k <= this stay FP64; default 4 */
-  int delta_l;              /* level offset unigrid -> finest FMM grid; only 1 */
+  int delta_l;              /* level offset unigrid -> finest FMM grid: 1 (default) or 2
+                               (FP64 only, n >= 16; fmm_solve_backward and batch plans
+                               return FMM_ERR_UNSUPPORTED for 2) */
   int check_finite;         /* nonzero: fmm_solve scans rho for NaN/Inf first (single-field plans) */
   int autotune;             /* batch plans: time the launch-shape candidates at creation; default 1 */
 } fmm_options;
@@ -145,7 +151,7 @@ int fmm_batch_info(const fmm_plan* plan, int* count, int* bottom_tile, int* m2l_
 /* Device bytes owned by the plan (tables and pyramids); 0 for NULL. */
 size_t fmm_plan_workspace_bytes(const fmm_plan* plan);
 
-/* Plan accessors: n, p, nmax, precision, finest FMM level F = log2(n) - 1. */
+/* Plan accessors: n, p, nmax, precision, finest FMM level F = log2(n) - delta_l. */
 int fmm_plan_info(const fmm_plan* plan, int* n, int* p, int* nmax, int* precision, int* finest_level);
 
 /* Last error message of the calling thread ("" if none).  Never NULL. */

@@ -57,21 +57,29 @@ int validate(int n, int p, int isolated, const fmm_options* o) {
       return fail(FMM_ERR_INVALID_ARG, "unknown precision %d", o->precision);
     if (o->nmax != -1 && (o->nmax < 0 || o->nmax > p))
       return fail(FMM_ERR_INVALID_ARG, "nmax must be -1 or in [0, p] (got %d)", o->nmax);
-    if (o->delta_l != 1) return fail(FMM_ERR_UNSUPPORTED, "only delta_l = 1 is provided (got %d)", o->delta_l);
+    if (o->delta_l != 1 && o->delta_l != 2)
+      return fail(FMM_ERR_UNSUPPORTED, "delta_l must be 1 or 2 (got %d)", o->delta_l);
+    if (o->delta_l == 2 && o->precision != FMM_FP64)
+      return fail(FMM_ERR_UNSUPPORTED, "delta_l = 2 is provided for FP64 plans only");
+    if (o->delta_l == 2 && L < 4) return fail(FMM_ERR_INVALID_ARG, "delta_l = 2 needs n >= 16 (got %d)", n);
     if (o->coarse_fp64_levels < 0) return fail(FMM_ERR_INVALID_ARG, "coarse_fp64_levels must be >= 0");
   }
   return FMM_OK;
 }
 
 // device bytes a plan will allocate (tables once, grids per field)
-size_t plan_bytes(const std::vector<int>& ns, int p) {
+size_t plan_bytes(const std::vector<int>& ns, int p, int dl) {
   const int NM = fmm::nterms(p), NC = (NM + 3) / 4, NCL = NC, ND = fmm::nterms(p + 1);
   size_t b = (size_t)343 * 8 * ND * sizeof(double) + 8 * fmm::NLIST_PAD * sizeof(int) + 256;
   // FP64 matrix-core tables (the largest set a plan builds)
   b += ((size_t)21 * fmm::NSLOT * 128 + (size_t)NCL * 128 * 9 + 54 * 128) * sizeof(double);
+  // delta_l = 2: the 64-position M2P derivative table and 8 groups of bottom tables
+  if (dl == 2)
+    b += (size_t)343 * 64 * ND * sizeof(double) +
+         ((size_t)21 * fmm::NSLOT * 128 + (size_t)NCL * 128 * 9 + 432 * 128) * 8 * sizeof(double);
   b += (size_t)fmm::NSLOT * fmm::conv_nfrags(fmm::CV_M2L, p, 4) * 64 * sizeof(double);
   for (int n : ns) {
-    const int F = ilog2_exact(n) - 1;
+    const int F = ilog2_exact(n) - dl;
     for (int k = 2; k <= F; ++k) {
       const size_t nkp = (size_t)(1 << k) + 6;
       b += (size_t)NC * nkp * nkp * nkp * 4 * sizeof(double);
@@ -117,6 +125,7 @@ void release(fmm_plan* pl) {
   free_st(pl->s_m2pt);
   if (pl->io) (void)hipFree(pl->io);
   if (pl->dtab) (void)hipFree(pl->dtab);
+  if (pl->dtab2) (void)hipFree(pl->dtab2);
   if (pl->dlists) (void)hipFree(pl->dlists);
   for (int x = 0; x < 3; ++x) {
     if (pl->wm2p[x]) (void)hipFree(pl->wm2p[x]);
@@ -286,7 +295,7 @@ int build_schedule(fmm_plan* pl) {
   SegList p2m, m2m[16], conv[2], l2l[16], bot[2][2];
   for (int f = 0; f < (int)pl->fld.size(); ++f) {
     const Field& fd = pl->fld[f];
-    const int F = fd.F, nF = fd.n / 2;
+    const int F = fd.F, nF = fd.n >> pl->dl;
     Seg sg{};
     sg.n = fd.n;
     sg.field = f;
@@ -426,7 +435,7 @@ namespace {
 
 // Plan for one or several fields (a batch) of the same order and precision.
 fmm_plan* create_plan(const std::vector<int>& ns, int p, const fmm_options& o, int batch) {
-  const size_t need = plan_bytes(ns, p);
+  const size_t need = plan_bytes(ns, p, o.delta_l);
   if (const char* cap = std::getenv("FMM_TEST_MAX_WORKSPACE")) {
     const unsigned long long lim = std::strtoull(cap, nullptr, 10);
     if (need > lim) {
@@ -451,6 +460,7 @@ fmm_plan* create_plan(const std::vector<int>& ns, int p, const fmm_options& o, i
     return nullptr;
   }
   pl->p = p;
+  pl->dl = o.delta_l;
   pl->nmax = (o.nmax < 0) ? p : o.nmax;
   pl->precision = o.precision;
   pl->coarse_fp64_levels = o.coarse_fp64_levels;
@@ -476,7 +486,7 @@ fmm_plan* create_plan(const std::vector<int>& ns, int p, const fmm_options& o, i
     fmm::Field& fd = pl->fld[f];
     fd.n = ns[f];
     fd.L = ilog2_exact(ns[f]);
-    fd.F = fd.L - 1;
+    fd.F = fd.L - pl->dl;
     fd.dx = 1.0 / ns[f];
     if (fd.F > pl->maxF) pl->maxF = fd.F;
   }
@@ -491,6 +501,7 @@ fmm_plan* create_plan(const std::vector<int>& ns, int p, const fmm_options& o, i
     return nullptr;
   };
   if (dev_alloc(pl, (void**)&pl->dtab, (size_t)343 * 8 * pl->ND * sizeof(double))) return bail();
+  if (pl->dl == 2 && dev_alloc(pl, (void**)&pl->dtab2, (size_t)343 * 64 * pl->ND * sizeof(double))) return bail();
   if (dev_alloc(pl, (void**)&pl->dlists, 8 * fmm::NLIST_PAD * sizeof(int))) return bail();
   {
     // L2L coefficient lists: for each local term b, the terms b + g with
@@ -768,6 +779,10 @@ fmm_plan* fmm_batch_plan_create(int count, const int* n, int p, int isolated, co
     fail(FMM_ERR_UNSUPPORTED, "check_finite is provided for single-field plans only");
     return nullptr;
   }
+  if (o.delta_l != 1) {
+    fail(FMM_ERR_UNSUPPORTED, "batch plans are provided for delta_l = 1");
+    return nullptr;
+  }
   fmm_plan* pl = create_plan(std::vector<int>(n, n + count), p, o, 1);
   if (!pl) return nullptr;
   if (o.autotune && autotune(pl) != FMM_OK) {
@@ -973,6 +988,7 @@ static int ensure_adjoint(fmm_plan* pl, hipStream_t s) {
 int fmm_solve_backward(fmm_plan* plan, const void* dphi, const void* dg, void* drho, void* stream) {
   if (!plan) return fail(FMM_ERR_INVALID_ARG, "plan is NULL");
   if (plan->batch) return fail(FMM_ERR_UNSUPPORTED, "the backward pass is provided for single-field plans");
+  if (plan->dl != 1) return fail(FMM_ERR_UNSUPPORTED, "the backward pass is provided for delta_l = 1 plans");
   if (!dphi || !drho) return fail(FMM_ERR_INVALID_ARG, "dphi and drho must be device pointers (got NULL)");
   if (drho == dphi || (dg && (dg == drho || dg == dphi))) return fail(FMM_ERR_INVALID_ARG, "buffers must not alias");
   if (int rc = ensure_adjoint(plan, (hipStream_t)stream)) return rc;

@@ -118,13 +118,7 @@ hipError_t upload_constants_tu() {
 // (f is harmonic and homogeneous of degree -1); D = -d^g f is stored.
 // FP64, once per plan.
 // ---------------------------------------------------------------------------
-__global__ void k_dtab(double* __restrict__ out, int PD, int ND) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 343 * 8) return;
-  const int dd = t >> 3, q = t & 7;
-  const double R0 = double(dd / 49 - 3) + (((q >> 2) & 1) ? 0.25 : -0.25);
-  const double R1 = double((dd / 7) % 7 - 3) + (((q >> 1) & 1) ? 0.25 : -0.25);
-  const double R2 = double(dd % 7 - 3) + ((q & 1) ? 0.25 : -0.25);
+__device__ void green_derivs(double R0, double R1, double R2, int PD, int ND, double* __restrict__ out) {
   const double r2 = R0 * R0 + R1 * R1 + R2 * R2;
   double f[NTMAX];
   f[0] = 1.0 / sqrt(r2);
@@ -147,7 +141,28 @@ __global__ void k_dtab(double* __restrict__ out, int PD, int ND) {
         }
         f[mi_index(a, b, c)] = -((2 * n - 1) * s1 + (n - 1) * s2) / (n * r2);
       }
-  for (int i = 0; i < ND; ++i) out[(size_t)t * ND + i] = -f[i];
+  for (int i = 0; i < ND; ++i) out[i] = -f[i];
+}
+__global__ void k_dtab(double* __restrict__ out, int PD, int ND) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 343 * 8) return;
+  const int dd = t >> 3, q = t & 7;
+  const double R0 = double(dd / 49 - 3) + (((q >> 2) & 1) ? 0.25 : -0.25);
+  const double R1 = double((dd / 7) % 7 - 3) + (((q >> 1) & 1) ? 0.25 : -0.25);
+  const double R2 = double(dd % 7 - 3) + ((q & 1) ? 0.25 : -0.25);
+  green_derivs(R0, R1, R2, PD, ND, out + (size_t)t * ND);
+}
+// The M2P table of FMM-2: Rhat = d + (2 s - 3) / 8 for the unigrid cell at
+// s in {0..3}^3 inside its level-F cell (units of that cell's size).
+// Layout [343][64][ND].
+__global__ void k_dtab2(double* __restrict__ out, int PD, int ND) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 343 * 64) return;
+  const int dd = t >> 6, sb = t & 63;
+  const double R0 = double(dd / 49 - 3) + (2 * ((sb >> 4) & 3) - 3) / 8.0;
+  const double R1 = double((dd / 7) % 7 - 3) + (2 * ((sb >> 2) & 3) - 3) / 8.0;
+  const double R2 = double(dd % 7 - 3) + (2 * (sb & 3) - 3) / 8.0;
+  green_derivs(R0, R1, R2, PD, ND, out + (size_t)t * ND);
 }
 
 // ---------------------------------------------------------------------------
@@ -194,6 +209,66 @@ __global__ __launch_bounds__(256) void k_p2m(const Seg* __restrict__ segs, int n
         const int a = mi_a(ex), b = mi_b(ex), cc = mi_c(ex);
         const int pat = ((a & 1) << 2) | ((b & 1) << 1) | (cc & 1);
         val = ldexp(c_mi_invfact[al], -2 * (a + b + cc)) * S[pat];
+      }
+      o[e] = val;
+    }
+    *reinterpret_cast<d4*>(M + (c * ncellp + cp) * 4) = o;
+  }
+}
+
+// P2M of FMM-2: Mhat_F[a] = sum_s rho_{4T+s} w_s^a / a!, w_s,i = (3 - 2 s_i) / 8
+// over the 64 unigrid cells s of T, summed axis by axis.  Segments as k_p2m.
+template <typename TI>
+__global__ __launch_bounds__(256) void k_p2m2(const Seg* __restrict__ segs, int nseg, IoArg io, int NM, int NC) {
+  const Seg& sg = find_seg(segs, nseg, blockIdx.x);
+  const int n = sg.n;
+  const TI* __restrict__ rho = io_rho<TI>(io, sg.field);
+  double* __restrict__ M = sg.b;
+  const int nF = n >> 2, nFp = nF + 6;
+  const long long nT = (long long)nF * nF * nF;
+  const long long T = (long long)(blockIdx.x - sg.first_block) * 256 + threadIdx.x;
+  if (T >= nT) return;
+  const int t2 = (int)(T % nF), t1 = (int)((T / nF) % nF), t0 = (int)(T / ((long long)nF * nF));
+  double v[64];
+#pragma unroll
+  for (int sb = 0; sb < 64; ++sb)
+    v[sb] = (double)rho[((long long)(4 * t0 + (sb >> 4)) * n + (4 * t1 + ((sb >> 2) & 3))) * n + (4 * t2 + (sb & 3))];
+  const long long ncellp = (long long)nFp * nFp * nFp;
+  const long long cp = ((long long)(t0 + 3) * nFp + (t1 + 3)) * nFp + (t2 + 3);
+#pragma unroll 1
+  for (int c = 0; c < NC; ++c) {
+    d4 o;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int al = 4 * c + e;
+      double val = 0.0;
+      if (al < NM) {
+        const int ex = c_mi_exp[al];
+        const int be[3] = {mi_a(ex), mi_b(ex), mi_c(ex)};
+        double pw[3][4];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const double w = (3 - 2 * s) / 8.0;
+            double m = 1.0;
+            for (int z = 0; z < be[ax]; ++z) m *= w;
+            pw[ax][s] = m;
+          }
+        double sx = 0.0;
+#pragma unroll
+        for (int s0 = 0; s0 < 4; ++s0) {
+          double sy = 0.0;
+#pragma unroll
+          for (int s1 = 0; s1 < 4; ++s1) {
+            double sz = 0.0;
+#pragma unroll
+            for (int s2 = 0; s2 < 4; ++s2) sz += pw[2][s2] * v[16 * s0 + 4 * s1 + s2];
+            sy += pw[1][s1] * sz;
+          }
+          sx += pw[0][s0] * sy;
+        }
+        val = c_mi_invfact[al] * sx;
       }
       o[e] = val;
     }
@@ -353,6 +428,55 @@ __device__ __forceinline__ double l2p_parent_coef(int bt, int rp, int q, int o) 
   for (int ax = 0; ax < 3; ++ax)
     for (int z = 0; z < be[ax] - (ax == dax); ++z) mono *= w[ax];
   return base * be[dax] * mono;
+}
+
+// FMM-2 (the finest FMM level two above the unigrid, App. A).  A unigrid
+// cell sits at s in {0..3}^3 inside its level-F cell of size h = 4 dx; the
+// bottom accumulators are in units of dx^3 / h (phi) and -dx^3 / h^2 (g).
+// Position s of child q of the level-(F+1) child grp, along axis ax:
+__device__ __forceinline__ int sub_pos(int grp, int q, int ax) {
+  return 2 * ((grp >> (2 - ax)) & 1) + ((q >> (2 - ax)) & 1);
+}
+// Evaluation of a local about a centre at offset -w (units of that local's
+// cell size, times the factor f of its scale against level F): phi takes
+// f w^b / b!, g_d takes f_g b_d w^(b - e_d) / b!.
+__device__ __forceinline__ double l2p_w_coef(int bt, const double (&w)[3], double fphi, double fg, int o) {
+  const int ex = c_mi_exp[bt];
+  const int be[3] = {mi_a(ex), mi_b(ex), mi_c(ex)};
+  const int dax = o - 1;
+  if (o > 0 && be[dax] == 0) return 0.0;
+  double mono = c_mi_invfact[bt];
+  for (int ax = 0; ax < 3; ++ax)
+    for (int z = 0; z < be[ax] - (o > 0 && ax == dax); ++z) mono *= w[ax];
+  return o == 0 ? fphi * mono : fg * be[dax] * mono;
+}
+// L2P of the own local: w = (2 s - 3) / 8, the unigrid centre from the
+// level-F centre in units of h.
+__device__ __forceinline__ double l2p2_coef(int bt, int grp, int q, int o) {
+  const double w[3] = {(2 * sub_pos(grp, q, 0) - 3) / 8.0, (2 * sub_pos(grp, q, 1) - 3) / 8.0,
+                       (2 * sub_pos(grp, q, 2) - 3) / 8.0};
+  return l2p_w_coef(bt, w, 1.0, 1.0, o);
+}
+// L2P from the parent level's local (cell size 2 h, so phi / 2 and g / 4 in
+// the accumulator units): the row's cell is child rp of the parent, and
+// w = (s - 3/2 + 4 (rp - 1/2)) / 8 in units of 2 h.
+__device__ __forceinline__ double l2p2_parent_coef(int bt, int rp, int grp, int q, int o) {
+  double w[3];
+  for (int ax = 0; ax < 3; ++ax)
+    w[ax] = (sub_pos(grp, q, ax) - 1.5 + 4.0 * (((rp >> (2 - ax)) & 1) - 0.5)) / 8.0;
+  return l2p_w_coef(bt, w, 0.5, 0.25, o);
+}
+// Near field: source k of the 12^3 block (w = 4 T - 4 + k), target
+// u = 4 T + s, delta = u - w = s + 4 - k (units of dx); eq. (direct) in the
+// accumulator units: phi 4 (-1 / max(|delta|, 1)), g_d 16 delta_d / |delta|^3
+// (0 at delta = 0).
+__device__ __forceinline__ double p2p2_coef(int k, int grp, int q, int o) {
+  const int kk[3] = {k / 144, (k / 12) % 12, k % 12};
+  double d[3];
+  for (int ax = 0; ax < 3; ++ax) d[ax] = (double)(sub_pos(grp, q, ax) + 4 - kk[ax]);
+  const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  if (o == 0) return r2 == 0.0 ? -4.0 : -4.0 / sqrt(r2);
+  return r2 == 0.0 ? 0.0 : 16.0 * d[o - 1] / (r2 * sqrt(r2));
 }
 
 #include "fmm_mfma.h"
@@ -830,6 +954,21 @@ hipError_t build_tables_t(fmm_plan* pl, bool bottom, bool m2l, hipStream_t s) {
   const int NM = pl->NM, NL = pl->NL;
   const long long NCK = (NM + KC - 1) / KC, NLT = (NL + KT - 1) / KT, NPT = (216 + KT - 1) / KT;
   hipError_t e;
+  if (bottom && !pl->wm2p[X] && pl->dl == 2) {
+    // FMM-2: 8 groups of each table, near field over the 12^3 block
+    const long long NPT2 = (1728 + KT - 1) / KT;
+    const long long n_m2p = 8 * NCK * NSLOT * 2 * EL * VPL, n_l2p = 8 * NLT * 2 * 64 * VPL,
+                    n_p2p = 8 * NPT2 * 2 * 64 * VPL;
+    if ((e = hipMalloc(&pl->wm2p[X], n_m2p * sizeof(H))) != hipSuccess) return e;
+    if ((e = hipMalloc(&pl->wl2p[X], n_l2p * sizeof(H))) != hipSuccess) return e;
+    if ((e = hipMalloc(&pl->wl2p2[X], 8 * n_l2p * sizeof(H))) != hipSuccess) return e;
+    if ((e = hipMalloc(&pl->wp2p[X], n_p2p * sizeof(H))) != hipSuccess) return e;
+    pl->bytes += (n_m2p + 9 * n_l2p + n_p2p) * sizeof(H);
+    const long long cnt = n_m2p + 9 * n_l2p + n_p2p;
+    hipLaunchKernelGGL((k_expand_bottom2<CT>), dim3(blocks_for(cnt, 256)), dim3(256), 0, s, pl->dtab2,
+                       (H*)pl->wm2p[X], (H*)pl->wl2p[X], (H*)pl->wl2p2[X], (H*)pl->wp2p[X], NM, NL, pl->ND);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if (bottom && !pl->wm2p[X]) {
     const long long n_m2p = NCK * NSLOT * 2 * EL * VPL, n_l2p = NLT * 2 * 64 * VPL, n_p2p = NPT * 2 * 64 * VPL;
     if ((e = hipMalloc(&pl->wm2p[X], n_m2p * sizeof(H))) != hipSuccess) return e;
@@ -855,6 +994,10 @@ hipError_t tables_all(fmm_plan* pl, hipStream_t s) {
   hipLaunchKernelGGL(k_dtab, dim3(blocks_for(343 * 8, 64)), dim3(64), 0, s, pl->dtab, pl->p + 1, pl->ND);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (pl->dl == 2) {
+    hipLaunchKernelGGL(k_dtab2, dim3(blocks_for(343 * 64, 64)), dim3(64), 0, s, pl->dtab2, pl->p + 1, pl->ND);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   const bool m2l64 = pl->s_conv[0].nseg > 0, m2llow = pl->s_conv[1].nseg > 0;
   const bool bot64 = pl->s_bot[0][0].nseg > 0, botlow = pl->s_bot[1][0].nseg > 0;
   if ((e = build_tables_t<double>(pl, bot64, m2l64, s)) != hipSuccess) return e;
@@ -922,17 +1065,27 @@ hipError_t launch_bottom(fmm_plan* pl, int x, IoArg io, hipStream_t s) {
   // coarse fields of a mixed-precision batch)
   int z = pl->tune.bz == 8 ? 1 : 0;
   if (z == 0 && pl->s_bot[x][0].blocks < pl->cus) z = 1;
+  if (pl->dl == 2) z = 0;  // FMM-2 launches 8 blocks per tile
   const SegTable& st = pl->s_bot[x][z];
   if (!st.nseg) return hipSuccess;
   // M2P K chunks: those of the multipole terms kept (nmax)
   const int nck = (pl->NMX + Mf<CT>::KC - 1) / Mf<CT>::KC;
   StageScope sc(pl, ST_BOTTOM, 1, s);
-  if (z == 0)
-    hipLaunchKernelGGL((k_bottom<P, CT, TI, TO, 16>), dim3(st.blocks), dim3(bottom_threads<CT>()), 0, s, st.dev, st.nseg, io,
+  if (pl->dl == 2) {
+    // FMM-2 is built for FP64 plans only (the plan validation rejects others)
+    if constexpr (std::is_same<CT, double>::value && std::is_same<TI, double>::value &&
+                  std::is_same<TO, double>::value)
+      hipLaunchKernelGGL((k_bottom<P, CT, TI, TO, 16, 2>), dim3(st.blocks, 8), dim3(bottom_threads<CT>()), 0, s, st.dev,
+                         st.nseg, io, (const H*)pl->wm2p[X], (const H*)pl->wl2p[X], (const H*)pl->wl2p2[X],
+                         (const H*)pl->wp2p[X], pl->dlists, nck);
+    else
+      return hipErrorNotSupported;
+  } else if (z == 0)
+    hipLaunchKernelGGL((k_bottom<P, CT, TI, TO, 16, 1>), dim3(st.blocks), dim3(bottom_threads<CT>()), 0, s, st.dev, st.nseg, io,
                        (const H*)pl->wm2p[X], (const H*)pl->wl2p[X], (const H*)pl->wl2p2[X], (const H*)pl->wp2p[X],
                        pl->dlists, nck);
   else
-    hipLaunchKernelGGL((k_bottom<P, CT, TI, TO, 8>), dim3(st.blocks), dim3(bottom_threads<CT>()), 0, s, st.dev, st.nseg, io,
+    hipLaunchKernelGGL((k_bottom<P, CT, TI, TO, 8, 1>), dim3(st.blocks), dim3(bottom_threads<CT>()), 0, s, st.dev, st.nseg, io,
                        (const H*)pl->wm2p[X], (const H*)pl->wl2p[X], (const H*)pl->wl2p2[X], (const H*)pl->wp2p[X],
                        pl->dlists, nck);
   return hipGetLastError();
@@ -947,8 +1100,12 @@ hipError_t solve_ct(fmm_plan* pl, IoArg io, hipStream_t s) {
   {
     StageScope sc(pl, ST_P2M, 1, s);
     // terms past nmax are written as zero
-    hipLaunchKernelGGL((k_p2m<TI>), dim3(pl->s_p2m.blocks), dim3(256), 0, s, pl->s_p2m.dev, pl->s_p2m.nseg, io, pl->NMX,
-                       NC);
+    if (pl->dl == 2)
+      hipLaunchKernelGGL((k_p2m2<TI>), dim3(pl->s_p2m.blocks), dim3(256), 0, s, pl->s_p2m.dev, pl->s_p2m.nseg, io,
+                         pl->NMX, NC);
+    else
+      hipLaunchKernelGGL((k_p2m<TI>), dim3(pl->s_p2m.blocks), dim3(256), 0, s, pl->s_p2m.dev, pl->s_p2m.nseg, io,
+                         pl->NMX, NC);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   for (int k = pl->maxF; k >= 3; --k) {

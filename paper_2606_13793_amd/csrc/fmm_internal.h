@@ -219,6 +219,7 @@ struct StageRec {
 
 struct fmm_plan {
   int n = 0, p = 0, nmax = 0, L = 0, F = 0;  // of field 0 (the only field of a single plan)
+  int dl = 1;  // levels between the finest FMM level and the unigrid (F = L - dl)
   int precision = 0;
   int coarse_fp64_levels = 4;
   int check_finite = 0;
@@ -232,6 +233,7 @@ struct fmm_plan {
   int maxF = 0;
   fmm::Level* lev = nullptr;    // fld[0].lev
   double* dtab = nullptr;   // [343][8][ND] D[g](Rhat) in FP64
+  double* dtab2 = nullptr;  // dl = 2: [343][64][ND] the M2P's D[g](Rhat)
   int* dlists = nullptr;    // [8][NLIST_PAD] packed interaction offsets per parity
   // matrix-core B operands in fragment order, per compute type (index
   // 0 = FP64, 1 = FP32, 2 = BF16); only the types a plan uses are built

@@ -216,12 +216,18 @@ __device__ constexpr int tile_part(int m) {
 // Segments: n = nF (level-F cells per axis), tpa = tiles along x and y,
 // tz = tiles along z, field, a = Mhat_F, c = Lam_F (or null), d = the parent
 // level's locals (or null).
+// DL = levels between the finest FMM level and the unigrid (App. A).  DL = 1:
+// a level-F cell holds 8 unigrid cells, the 32 columns (q, o).  DL = 2
+// (FMM-2): it holds 64; blockIdx.y = g picks the level-(F+1) child of the
+// row's cell and the columns are the 8 unigrid children q of that child.
+// The B tables then hold 8 groups, and the near field is the 12^3 block of
+// unigrid cells of the 27 level-F cells around the row's cell.
 // minimum waves per SIMD (the second launch bound): one 1024-thread block or
 // two 512-thread FP32 blocks per CU (4 waves per SIMD, <= 128 registers)
 template <typename CT>
 constexpr int bottom_min_waves() { return 4; }
 
-template <int P, typename CT, typename TI, typename TO, int BZ>
+template <int P, typename CT, typename TI, typename TO, int BZ, int DL>
 __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void k_bottom(
     const Seg* __restrict__ segs, int nseg, IoArg io, const typename Mf<CT>::H* __restrict__ Wm2p,
     const typename Mf<CT>::H* __restrict__ Wl2p, const typename Mf<CT>::H* __restrict__ Wl2p2,
@@ -235,7 +241,9 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
   constexpr int KC = M::KC, OPM = M::OPM, VPL = M::VPL, EL = 64 / OPM;
   constexpr int NM = nterms(P), NC4 = (NM + 3) / 4;
   constexpr int NL = nterms(P);
-  constexpr int KT = 4 * VPL, NLT = (NL + KT - 1) / KT, NPT = (216 + KT - 1) / KT;
+  constexpr int NB = 3 << DL, NNEAR = NB * NB * NB;  // near-field block: 6^3 or 12^3 unigrid cells
+  constexpr int KT = 4 * VPL, NLT = (NL + KT - 1) / KT, NPT = (NNEAR + KT - 1) / KT;
+  constexpr int NCK = (NM + KC - 1) / KC;
   constexpr int NGRP = (NLIST + OPM - 1) / OPM;
   constexpr int THREADS = bottom_threads<CT>(), MTW = BOT_MT / bottom_wpr<CT>();  // row tiles per wave
   using HL = Halo<CT, BZ>;
@@ -252,14 +260,24 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
   }
   const Seg& sg = find_seg(segs, nseg, blockIdx.x);
   const int nF = sg.n;
+  // DL = 2: this block's group of unigrid cells, and its part of each B table
+  const int grp = DL == 2 ? (int)blockIdx.y : 0;
+  if constexpr (DL == 2) {
+    Wm2p += (size_t)grp * NCK * NSLOT * 2 * EL * VPL;
+    Wl2p += (size_t)grp * NLT * 2 * 64 * VPL;
+    Wl2p2 += (size_t)grp * 8 * NLT * 2 * 64 * VPL;
+    Wp2p += (size_t)grp * NPT * 2 * 64 * VPL;
+  }
   const double* __restrict__ Mh = sg.a;
   const double* __restrict__ Lf = sg.c;
   const double* __restrict__ Lpar = sg.d;
   const TI* __restrict__ rho = io_rho<TI>(io, sg.field);
   TO* __restrict__ phi = io_phi<TO>(io, sg.field);
   TO* __restrict__ g = io_g<TO>(io, sg.field);
-  const double dxf = 0.5 / nF;  // unigrid cell size
-  const double sphi = 0.5 * dxf * dxf, sgr = -0.25 * dxf;
+  // unigrid cell size; the accumulators are in units of dx^3 / h and
+  // -dx^3 / h^2, h = 2^DL dx the level-F cell size
+  const double dxf = DL == 1 ? 0.5 / nF : 0.25 / nF;
+  const double sphi = (DL == 1 ? 0.5 : 0.25) * dxf * dxf, sgr = (DL == 1 ? -0.25 : -0.0625) * dxf;
   const int lb = blockIdx.x - sg.first_block;
   const int lane = threadIdx.x & 63;
   // wave = parity class r and, of its BOT_MT row tiles, the MTW from m0 (uniform)
@@ -348,7 +366,7 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
     }
   }
 
-  const int n = 2 * nF;
+  const int n = nF << DL;
   const long long N = (long long)n * n * n;
   constexpr int RS = loc_stride(P);
   // the lane's own row (A operand) of tile m and its level-F cell, clamped into the grid
@@ -422,8 +440,9 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
 #pragma unroll
         for (int v = 0; v < VPL; ++v) {
           const int k = KT * c + VPL * kq + v;
-          const int w0 = 2 * c0 + k / 36 - 2, w1 = 2 * c1 + (k / 6) % 6 - 2, w2 = 2 * c2 + k % 6 - 2;
-          va[u][v] = (cb + u < NPT && k < 216 && w0 >= 0 && w1 >= 0 && w2 >= 0 && w0 < n && w1 < n && w2 < n)
+          const int w0 = (c0 << DL) + k / (NB * NB) - (1 << DL), w1 = (c1 << DL) + (k / NB) % NB - (1 << DL),
+                    w2 = (c2 << DL) + k % NB - (1 << DL);
+          va[u][v] = (cb + u < NPT && k < NNEAR && w0 >= 0 && w1 >= 0 && w2 >= 0 && w0 < n && w1 < n && w2 < n)
                          ? rg[((long long)w0 * n + w1) * n + w2]
                          : TI(0);
         }
@@ -456,8 +475,11 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
       for (int t = 0; t < 2; ++t) {
         const int col = 16 * t + i;
         const int q = col >> 2, o = col & 3;
-        const long long u = ((long long)(2 * o0 + ((q >> 2) & 1)) * n + (2 * o1 + ((q >> 1) & 1))) * n +
-                            (2 * o2 + (q & 1));
+        // unigrid cell: child q of the row's cell (DL = 1), or of its child grp (DL = 2)
+        const int u0 = DL == 1 ? 2 * o0 : 4 * o0 + 2 * ((grp >> 2) & 1);
+        const int u1 = DL == 1 ? 2 * o1 : 4 * o1 + 2 * ((grp >> 1) & 1);
+        const int u2 = DL == 1 ? 2 * o2 : 4 * o2 + 2 * (grp & 1);
+        const long long u = ((long long)(u0 + ((q >> 2) & 1)) * n + (u1 + ((q >> 1) & 1))) * n + (u2 + (q & 1));
         const double val = (double)acc[mw][t][v];
         if (o == 0)
           phi[u] = (TO)(sphi * val);
@@ -531,6 +553,82 @@ __global__ void k_expand_bottom(const double* __restrict__ Dtab, typename Mf<CT>
     if (k < NL) val = l2p_parent_coef(k, rp, q, o);
   } else {
     if (k < 216) val = p2p_coef(k / 36 - 2, (k / 6) % 6 - 2, k % 6 - 2, q, o);
+  }
+  out[e] = static_cast<H>(val);
+}
+
+// The same tables for FMM-2, one set per group g of 8 unigrid cells (the
+// children of level-(F+1) child g of a level-F cell):
+//   M2P:   [8][NCK][NSLOT][2][EL][VPL]  from Dtab2 [343][64][ND] (Rhat_{d,s})
+//   L2P:   [8][NLT][2][64][VPL]         l2p2_coef
+//   L2P2:  [8][8][NLT][2][64][VPL]      l2p2_parent_coef
+//   near:  [8][NPT2][2][64][VPL]        p2p2_coef over the 12^3 block
+template <typename CT>
+__global__ void k_expand_bottom2(const double* __restrict__ Dtab2, typename Mf<CT>::H* __restrict__ Wm2p,
+                                 typename Mf<CT>::H* __restrict__ Wl2p, typename Mf<CT>::H* __restrict__ Wl2p2,
+                                 typename Mf<CT>::H* __restrict__ Wp2p, int NM, int NL, int ND) {
+  using M = Mf<CT>;
+  using H = typename M::H;
+  constexpr int KC = M::KC, OPM = M::OPM, VPL = M::VPL, EL = 64 / OPM, KT = 4 * VPL;
+  const int NCK = (NM + KC - 1) / KC, NLT = (NL + KT - 1) / KT, NPT = (1728 + KT - 1) / KT;
+  const long long n_m2p = (long long)NCK * NSLOT * 2 * EL * VPL;
+  const long long n_l2p = (long long)NLT * 2 * 64 * VPL, n_l2p2 = 8 * n_l2p, n_p2p = (long long)NPT * 2 * 64 * VPL;
+  const long long per = n_m2p + n_l2p + n_l2p2 + n_p2p;
+  long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= 8 * per) return;
+  // region by region, each [8 groups][...]
+  if (e < 8 * n_m2p) {
+    const int grp = (int)(e / n_m2p);
+    const long long x = e % n_m2p;
+    const int v = (int)(x % VPL), el = (int)((x / VPL) % EL), t = (int)((x / ((long long)VPL * EL)) % 2);
+    const int slot = (int)((x / ((long long)VPL * EL * 2)) % NSLOT), c = (int)(x / ((long long)VPL * EL * 2 * NSLOT));
+    const int j = el & 15, col = 16 * t + j, q = col >> 2, o = col & 3;
+    const int tic = OPM == 2 ? 8 * (el >> 4) : (el >> 4);
+    const int al = c * KC + tic + v;
+    double val = 0.0;
+    if (al < NM && slot < 343) {
+      const int ex = c_mi_exp[al];
+      const int sub = (sub_pos(grp, q, 0) << 4) | (sub_pos(grp, q, 1) << 2) | sub_pos(grp, q, 2);
+      val = Dtab2[((size_t)slot * 64 + sub) * ND +
+                  mi_index(mi_a(ex) + (o == 1), mi_b(ex) + (o == 2), mi_c(ex) + (o == 3))];
+    }
+    Wm2p[e] = static_cast<H>(val);
+    return;
+  }
+  e -= 8 * n_m2p;
+  H* out;
+  long long cnt;
+  int kind;
+  if (e < 8 * n_l2p) {
+    out = Wl2p;
+    cnt = n_l2p;
+    kind = 0;
+  } else if (e < 8 * (n_l2p + n_l2p2)) {
+    e -= 8 * n_l2p;
+    out = Wl2p2;
+    cnt = n_l2p2;
+    kind = 1;
+  } else {
+    e -= 8 * (n_l2p + n_l2p2);
+    out = Wp2p;
+    cnt = n_p2p;
+    kind = 2;
+  }
+  const int grp = (int)(e / cnt);
+  const long long x = e % cnt;
+  const int rp = kind == 1 ? (int)(x / n_l2p) : 0;
+  const long long el = kind == 1 ? x % n_l2p : x;
+  const int v = (int)(el % VPL), lane = (int)((el / VPL) % 64), t = (int)((el / (VPL * 64)) % 2);
+  const int c = (int)(el / (VPL * 64 * 2));
+  const int j = lane & 15, kq = lane >> 4, col = 16 * t + j, q = col >> 2, o = col & 3;
+  const int k = KT * c + VPL * kq + v;
+  double val = 0.0;
+  if (kind == 0) {
+    if (k < NL) val = l2p2_coef(k, grp, q, o);
+  } else if (kind == 1) {
+    if (k < NL) val = l2p2_parent_coef(k, rp, grp, q, o);
+  } else {
+    if (k < 1728) val = p2p2_coef(k, grp, q, o);
   }
   out[e] = static_cast<H>(val);
 }

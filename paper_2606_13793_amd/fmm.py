@@ -142,7 +142,8 @@ class Plan:
         self._ptr = ptr
         self.n, self.p, self.precision = int(n), int(p), precision
         self.nmax = self.p if nmax is None else int(nmax)
-        self.finest_level = int(np.log2(n)) - 1
+        self.delta_l = int(delta_l)
+        self.finest_level = int(np.log2(n)) - self.delta_l
 
     @property
     def ptr(self) -> int:

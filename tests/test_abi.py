@@ -78,7 +78,10 @@ def test_invalid_sizes_rejected_without_device(F, n, p, iso, code, text):
 
 
 @pytest.mark.parametrize("opt,code", [
-    ({"delta_l": 2}, -2),
+    ({"delta_l": 3}, -2),
+    ({"delta_l": 0}, -2),
+    ({"delta_l": 2, "precision": 1}, -2),
+    ({"delta_l": 2, "precision": 2}, -2),
     ({"nmax": 7}, -1),
     ({"nmax": -3}, -1),
     ({"precision": 5}, -1),
@@ -88,6 +91,11 @@ def test_invalid_sizes_rejected_without_device(F, n, p, iso, code, text):
 def test_invalid_options_rejected(F, opt, code):
     ptr, status, msg = _create(F, 16, 4, **opt)
     assert not ptr and status == code and msg
+
+
+def test_delta_l_2_needs_n_16(F):
+    ptr, status, msg = _create(F, 8, 4, delta_l=2)
+    assert not ptr and status == -1 and "n >= 16" in msg
 
 
 def test_workspace_cap_reports_out_of_memory():

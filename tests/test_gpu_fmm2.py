@@ -1,0 +1,126 @@
+"""FMM-2 (delta_l = 2, App. A) on the GPU against the FP64 oracle's FMM-2.
+
+Same bar as FMM-1: relative L2 error <= 1e-12 for phi and g (the two sides
+differ only in rounding order).  Covers several tiles and ragged tails
+(n = 16 .. 64 full grids), the paper's orders (p = 3, nmax = 2), the
+benchmark size (256^3, sampled cells evaluated by the oracle one by one),
+the FMM-1 vs FMM-2 point-charge difference of App. A at the paper's 256^3,
+and the combinations the plan rejects.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import fmm_inputs as fi
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    from paper_2606_13793_amd import fmm
+    assert os.path.exists(fmm.LIB_PATH), "libfmm.so must be built before the GPU tests"
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return fmm
+
+
+def rel(a, b):
+    a, b = np.ravel(a), np.ravel(b)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def solve2(F, rho, p, nmax=None):
+    import torch
+    n = rho.shape[0]
+    plan = F.Plan(n, p, "fp64", nmax=nmax, delta_l=2)
+    r = torch.as_tensor(rho).to(device="cuda", dtype=torch.float64).contiguous()
+    phi, g = plan.solve(r)
+    torch.cuda.synchronize()
+    return phi.cpu().numpy(), g.cpu().numpy(), plan
+
+
+@pytest.mark.parametrize("n,p,nmax", [(16, 4, None), (16, 1, None), (32, 6, None), (32, 3, 2),
+                                      (64, 6, None), (64, 8, None)])
+def test_fmm2_full_grid_matches_oracle(F, orc, n, p, nmax):
+    _say(f"case fmm2 full n={n} p={p} nmax={nmax}")
+    rho = fi.plummer_density(n, fi.multi_plummer_params(32, 300 + n))
+    phi, g, plan = solve2(F, rho, p, nmax)
+    assert plan.finest_level == int(np.log2(n)) - 2
+    phi_o, g_o = orc.solve(rho, p, nmax=nmax, delta_l=2)
+    assert rel(phi, phi_o) < TOL64, rel(phi, phi_o)
+    assert rel(g, g_o) < TOL64, rel(g, g_o)
+
+
+def test_fmm2_random_density_every_cell(F, orc):
+    """A density with no structure, so every table entry and every near-field
+    offset carries weight; checked cell by cell."""
+    _say("case fmm2 random n=32 p=5")
+    rho = np.random.default_rng(21).uniform(-1.0, 1.0, (32, 32, 32))
+    phi, g, _ = solve2(F, rho, 5)
+    phi_o, g_o = orc.solve(rho, 5, delta_l=2)
+    assert np.abs(phi - phi_o).max() <= 1e-12 * np.abs(phi_o).max()
+    assert np.abs(g - g_o).max() <= 1e-12 * np.abs(g_o).max()
+
+
+def test_fmm2_full_size_sampled(F, orc):
+    """256^3, p = 6: the benchmark's FMM-2 launch, at sampled cells."""
+    import torch
+    n, p = 256, 6
+    _say(f"case fmm2 sampled n={n} p={p}")
+    rho_t = fi.plummer_density(n, fi.multi_plummer_params(256, 256), device="cuda")
+    plan = F.Plan(n, p, "fp64", delta_l=2)
+    phi, g = plan.solve(rho_t)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(2)
+    corners = [0, n - 1, (n - 1) * n * n, n ** 3 - 1, ((n // 2) * n + n // 2) * n + n // 2, n * n - 1]
+    cells = np.unique(np.concatenate([corners, rng.choice(n ** 3, 40, replace=False)]))
+    idx = torch.as_tensor(cells, device="cuda")
+    phi_s = phi.reshape(-1)[idx].cpu().numpy()
+    g_s = g.reshape(3, -1)[:, idx].cpu().numpy()
+    rho = rho_t.cpu().numpy()
+    del phi, g
+    phi_o, g_o = orc.solve(rho, p, targets=cells, delta_l=2)
+    assert rel(phi_s, phi_o) < TOL64, rel(phi_s, phi_o)
+    assert rel(g_s, g_o) < TOL64, rel(g_s, g_o)
+    assert np.max(np.abs(phi_s - phi_o) / np.abs(phi_o)) < 1e-11
+
+
+def test_fmm1_fmm2_point_charge_256(F):
+    """App. A at the paper's 256^3 with its orders (p = 3, nmax = 2): the
+    midplane potentials of FMM-1 and FMM-2 differ by about 0.3 % at most
+    (99 % of the slice below 0.3 %, the largest 0.31 %, as in the oracle)."""
+    import torch
+    n = 256
+    _say("case fmm1 vs fmm2 point charge n=256 p=3 nmax=2")
+    rho = torch.as_tensor(fi.point_charge_cic(n)).cuda()
+    p1, _ = F.Plan(n, 3, "fp64", nmax=2).solve(rho, want_g=False)
+    p2, _ = F.Plan(n, 3, "fp64", nmax=2, delta_l=2).solve(rho, want_g=False)
+    s1, s2 = p1[:, :, n // 2].cpu().numpy(), p2[:, :, n // 2].cpu().numpy()
+    d = np.abs(s2 - s1) / np.abs(s1)
+    assert np.percentile(d, 99) < 3e-3, np.percentile(d, 99)
+    assert 1e-3 < d.max() < 4e-3, d.max()
+
+
+def test_fmm2_rejections(F):
+    import torch
+    _say("case fmm2 rejections")
+    with pytest.raises(F.FmmError):
+        F.Plan(8, 4, "fp64", delta_l=2)          # needs n >= 16
+    with pytest.raises(F.FmmError):
+        F.Plan(32, 4, "fp32", delta_l=2)         # FP64 only
+    with pytest.raises(F.FmmError):
+        F.Plan(32, 4, "fp64", delta_l=3)
+    plan = F.Plan(16, 4, "fp64", delta_l=2)
+    x = torch.zeros(16, 16, 16, dtype=torch.float64, device="cuda")
+    with pytest.raises(F.FmmError):
+        plan.backward(x, None)
