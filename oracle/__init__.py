@@ -65,6 +65,7 @@ def lib():
         L.or_list_size.argtypes = [ctypes.c_int] * 4
         L.or_pair_pass_row.argtypes = [ctypes.c_int, ctypes.c_longlong, _ip]
         L.or_pair_pass_row_dl.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_longlong, _ip]
+        L.or_deposit_cic.argtypes = [ctypes.c_int, ctypes.c_longlong, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -235,3 +236,16 @@ def solve_timed(rho, p: int, targets, nmax: int | None = None):
     if rc != 0:
         raise ValueError("bad arguments")
     return phi, g, float(times[0]), float(times[1]), int(lib().or_threads())
+
+
+def deposit_cic(n: int, pos, mass) -> np.ndarray:
+    """Cloud-in-cell density (n, n, n) of particles pos (k, 3) in the unit box
+    with masses mass (k,); shares outside the box are dropped."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+    mass = np.ascontiguousarray(mass, dtype=np.float64).reshape(-1)
+    if len(mass) != len(pos):
+        raise ValueError("pos and mass differ in length")
+    rho = np.zeros((n, n, n))
+    if lib().or_deposit_cic(n, len(mass), _d(pos), _d(mass), _d(rho)) != 0:
+        raise ValueError(f"oracle CIC rejected n={n}")
+    return rho

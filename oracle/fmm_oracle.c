@@ -628,6 +628,37 @@ int or_expansions(int n, int p, int nmax, const double *rho, int which, int leve
   return 0;
 }
 
+/*
+ * Cloud-in-cell deposition (Sec. 3: the test particles are put on the grid
+ * with CIC).  A particle of mass m at x spreads over the cells c whose centre
+ * lies within one cell of it along every axis, with the tent weights
+ *   W_c = prod_d max(0, 1 - |x_d - x_c,d| / dx),
+ * and rho_c += m W_c / dx^3.  Cells outside the box do not exist (isolated
+ * box): their share is dropped.  pos: [count][3] in the unit box.
+ */
+int or_deposit_cic(int n, i64 count, const double *pos, const double *mass, double *rho) {
+  if (ilog2(n) < 0 || count < 0) return -1;
+  const double dx = 1.0 / n, inv_vol = (double)n * n * n;
+  for (i64 t = 0; t < count; ++t) {
+    const double *x = pos + 3 * t;
+    int lo[3];
+    for (int d = 0; d < 3; ++d) lo[d] = (int)floor(x[d] / dx - 0.5);
+    for (int a = lo[0]; a <= lo[0] + 1; ++a)
+      for (int b = lo[1]; b <= lo[1] + 1; ++b)
+        for (int c = lo[2]; c <= lo[2] + 1; ++c) {
+          if (!inside(a, b, c, n)) continue;
+          const int cell[3] = {a, b, c};
+          double w = 1.0;
+          for (int d = 0; d < 3; ++d) {
+            const double u = 1.0 - fabs(x[d] - ((double)cell[d] + 0.5) * dx) / dx;
+            w *= u > 0.0 ? u : 0.0;
+          }
+          rho[lin(a, b, c, n)] += mass[t] * w * inv_vol;
+        }
+  }
+  return 0;
+}
+
 /* O(N^2) direct sum with the same softened Green's function (eq. direct):
    phi_u = sum_w m_w g(x_u - x_w), g_u = -sum_{w != u} m_w (x_u-x_w)/|x_u-x_w|^3.
    targets as in or_solve. */
