@@ -179,6 +179,27 @@ int fmm_last_status(void);
 int fmm_debug_expansions(fmm_plan* plan, int which, int level, double* out, size_t count);
 
 /*
+ * Cloud-in-cell deposition, the step before a solve (Sec. 3: the paper's test
+ * particles reach the grid this way).  A particle of mass m at x adds
+ * m W_c / dx^3 to the density of each cell c whose centre lies within one
+ * cell of x along every axis, W_c = prod_d (1 - |x_d - x_c,d| / dx).
+ *  n      cells per axis, a power of two in [8, 1024] (dx = 1/n)
+ *  count  particles, >= 0
+ *  pos    DEVICE, count x 3 doubles, (x, y, z) per particle in the unit box;
+ *         x runs along the grid's first index
+ *  mass   DEVICE, count doubles (G = 1)
+ *  rho    DEVICE, n^3 doubles, C order; the densities are ADDED to it (zero
+ *         it first for a fresh grid)
+ * Shares of cells outside the box are dropped (isolated boundaries); a
+ * particle with a coordinate that is not finite deposits nothing.  The
+ * shares are added with FP64 atomics, so the last bits of a cell that several
+ * particles reach can differ between runs.  Enqueued on `stream`.  Returns
+ * FMM_OK, FMM_ERR_INVALID_ARG (n, count or a NULL pointer with count > 0) or
+ * FMM_ERR_DEVICE (launch failure).
+ */
+int fmm_deposit_cic(int n, long long count, const double* pos, const double* mass, double* rho, void* stream);
+
+/*
  * Per-stage device timing with HIP events recorded on the solve's stream.
  * fmm_profile_enable(plan, 1) makes every following fmm_solve /
  * fmm_solve_backward record an event pair around each stage; 0 stops it.

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -1051,6 +1052,20 @@ int fmm_multi_index(int P, int* out, size_t count) {
       }
   ok();
   return nt;
+}
+
+int fmm_deposit_cic(int n, long long count, const double* pos, const double* mass, double* rho, void* stream) {
+  const int L = ilog2_exact(n);
+  if (L < 3 || L > 10) return fail(FMM_ERR_INVALID_ARG, "n must be a power of two in [8, 1024] (got %d)", n);
+  if (count < 0) return fail(FMM_ERR_INVALID_ARG, "count must be >= 0 (got %lld)", count);
+  if (count > 0 && (!pos || !mass || !rho)) return fail(FMM_ERR_INVALID_ARG, "pos, mass and rho must be device pointers");
+  if (count > (long long)UINT32_MAX * 256) return fail(FMM_ERR_INVALID_ARG, "count %lld is too large", count);
+  hipError_t e = fmm::launch_cic(n, count, pos, mass, rho, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FMM_ERR_DEVICE, "CIC launch failed: %s", hipGetErrorString(e));
+  }
+  return ok();
 }
 
 int fmm_debug_expansions(fmm_plan* plan, int which, int level, double* out, size_t count) {

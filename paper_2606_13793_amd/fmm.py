@@ -30,7 +30,7 @@ EXPORTS = (
     "fmm_solve", "fmm_solve_backward", "fmm_plan_workspace_bytes", "fmm_plan_info",
     "fmm_last_error", "fmm_last_status", "fmm_debug_expansions", "fmm_multi_index",
     "fmm_profile_enable", "fmm_profile_read", "fmm_profile_stage_name",
-    "fmm_batch_plan_create", "fmm_batch_solve", "fmm_batch_info",
+    "fmm_batch_plan_create", "fmm_batch_solve", "fmm_batch_info", "fmm_deposit_cic",
 )
 
 
@@ -90,6 +90,7 @@ def lib():
         L.fmm_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
         L.fmm_batch_info.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
                                      ctypes.POINTER(ctypes.c_double), i]
+        L.fmm_deposit_cic.argtypes = [i, ctypes.c_longlong, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -364,3 +365,23 @@ def solve(plan: Plan, rho):
     if _FN is None:
         _FN = _autograd_fn()
     return _FN.apply(rho, plan)
+
+
+def deposit_cic(n: int, pos, mass, rho=None, stream=None):
+    """Cloud-in-cell density of particles (``fmm_deposit_cic``): pos (k, 3)
+    and mass (k,) float64 CUDA tensors in the unit box; returns rho (n, n, n)
+    float64, or adds into the given ``rho``."""
+    import torch
+    if pos.dtype != torch.float64 or mass.dtype != torch.float64 or not pos.is_cuda or not mass.is_cuda:
+        raise TypeError("pos and mass must be float64 CUDA tensors")
+    pos = pos.contiguous()
+    mass = mass.contiguous()
+    if pos.dim() != 2 or pos.shape[1] != 3 or mass.shape != (pos.shape[0],):
+        raise ValueError("pos must be (k, 3) and mass (k,)")
+    if rho is None:
+        rho = torch.zeros((n, n, n), dtype=torch.float64, device=pos.device)
+    elif rho.dtype != torch.float64 or tuple(rho.shape) != (n, n, n) or not rho.is_contiguous():
+        raise ValueError("rho must be a contiguous float64 (n, n, n) tensor")
+    _check(lib().fmm_deposit_cic(int(n), int(pos.shape[0]), pos.data_ptr(), mass.data_ptr(), rho.data_ptr(),
+                                 _stream_ptr(stream)))
+    return rho

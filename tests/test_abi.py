@@ -181,3 +181,13 @@ def test_batch_arguments_rejected_before_the_device(F):
     assert L.fmm_last_status() == -1
     assert L.fmm_batch_solve(None, None, None, None, None) == -1
     assert L.fmm_batch_info(None, None, None, None, None, 0) == -1
+
+
+def test_deposit_arguments_rejected_before_the_device(F):
+    L = F.lib()
+    assert L.fmm_deposit_cic(12, 1, 8, 8, 8, None) == -1            # n not a power of two
+    assert L.fmm_deposit_cic(2048, 1, 8, 8, 8, None) == -1          # n too large
+    assert L.fmm_deposit_cic(16, -1, 8, 8, 8, None) == -1           # negative count
+    assert L.fmm_deposit_cic(16, 4, None, 8, 8, None) == -1         # NULL with particles
+    assert "pos" in F.last_error()
+    assert L.fmm_deposit_cic(16, 0, None, None, None, None) == 0    # nothing to do
