@@ -216,9 +216,39 @@ def run_extras(args, rho64, fi, fmm, costs, sections=("mixed", "adjoint", "batch
         fmm2["point_charge_fmm1_vs_fmm2"] = {"p": 3, "nmax": 2, "slice": "midplane through the charge",
                                              "max": float(d.max()), "p99": float(np.percentile(d, 99)),
                                              "p90": float(np.percentile(d, 90))}
+        # against the exact potential -1/r of the point, over the whole slice
+        # (the charge's own cells included)
+        c = fi.cell_centres(n)
+        r = np.sqrt((c[:, None] - 0.5) ** 2 + (c[None, :] - 0.5) ** 2 + (c[n // 2] - 0.5) ** 2)
+        for key, sl in (("fmm1", s1), ("fmm2", s2)):
+            e = np.abs(sl + 1.0 / r) * r
+            fmm2["point_charge_fmm1_vs_fmm2"][f"{key}_vs_exact_p90"] = float(np.percentile(e, 90))
+            fmm2["point_charge_fmm1_vs_fmm2"][f"{key}_vs_exact_p99"] = float(np.percentile(e, 99))
         del pc
         log(f"extras: point charge FMM-1 vs FMM-2: max {d.max():.3e}, p99 {np.percentile(d, 99):.3e}")
         out["fmm2"] = fmm2
+        # the paper's two uniform spheres (Sec. 3), scaled to the unit box:
+        # 4M particles, CIC deposit on the GPU, FMM-1 and FMM-2 at the paper's
+        # orders, errors against the exact potential on the midplane
+        pos, m = fi.two_spheres_particles(1 << 22)
+        pos_t = torch.as_tensor(pos).cuda()
+        m_t = torch.as_tensor(m).cuda()
+        rho_s = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+        dep_ms = _event_ms(lambda: (rho_s.zero_(), fmm.deposit_cic(n, pos_t, m_t, rho=rho_s)), 5, 2)
+        pts = np.stack(np.meshgrid(c, c, [c[n // 2]], indexing="ij"), -1).reshape(-1, 3)
+        exact = fi.two_spheres_potential(pts).reshape(n, n)
+        spheres = {"particles": int(len(m)), "zero_and_deposit_ms": dep_ms, "p": 3, "nmax": 2,
+                   "slice": "midplane through both centres"}
+        for dl in (1, 2):
+            ph = fmm.Plan(n, 3, "fp64", nmax=2, delta_l=dl).solve(rho_s, want_g=False)[0]
+            e = np.abs(ph[:, :, n // 2].cpu().numpy() - exact) / np.abs(exact)
+            spheres[f"fmm{dl}_p90"] = float(np.percentile(e, 90))
+            spheres[f"fmm{dl}_p99"] = float(np.percentile(e, 99))
+            del ph
+        del pos_t, m_t, rho_s
+        out["two_spheres"] = spheres
+        log(f"extras: two spheres: deposit {dep_ms:.2f} ms; P90/P99 FMM-1 {spheres['fmm1_p90']:.2e}/"
+            f"{spheres['fmm1_p99']:.2e}, FMM-2 {spheres['fmm2_p90']:.2e}/{spheres['fmm2_p99']:.2e}")
     # mixed precision at order P
     mixed = {}
     if "mixed" in sections:

@@ -119,6 +119,41 @@ def point_charge_cic(n: int, mass: float = 1.0) -> np.ndarray:
     return rho
 
 
+# The paper's two uniform-density spheres (Sec. 3: radii 0.1 and 0.2 at
+# x = 0.7 and 1.2 on the axis y = z = 1 of a box of size 2), scaled to the
+# unit box: radii 0.05 and 0.1, density 1.
+TWO_SPHERES = (((0.35, 0.5, 0.5), 0.05), ((0.6, 0.5, 0.5), 0.1))
+
+
+def two_spheres_particles(count: int, seed: int = 11):
+    """Particles spread uniformly through the two spheres, count in
+    proportion to their volumes, each sphere's particles sharing its mass
+    4/3 pi R^3.  Returns pos (k, 3), mass (k,) as float64 arrays."""
+    rng = np.random.default_rng(seed)
+    vols = [r ** 3 for _, r in TWO_SPHERES]
+    pos, mass = [], []
+    for (c, r), v in zip(TWO_SPHERES, vols):
+        k = int(round(count * v / sum(vols)))
+        d = rng.standard_normal((k, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        d *= r * rng.uniform(0, 1, (k, 1)) ** (1.0 / 3.0)
+        pos.append(np.asarray(c) + d)
+        mass.append(np.full(k, 4.0 / 3.0 * math.pi * r ** 3 / k))
+    return np.concatenate(pos), np.concatenate(mass)
+
+
+def two_spheres_potential(points) -> np.ndarray:
+    """Exact potential (G = 1) of the two uniform spheres at points (k, 3):
+    -M/r outside a sphere, -M (3 R^2 - r^2) / (2 R^3) inside."""
+    points = np.asarray(points, dtype=np.float64)
+    phi = np.zeros(len(points))
+    for c, r in TWO_SPHERES:
+        m = 4.0 / 3.0 * math.pi * r ** 3
+        d = np.linalg.norm(points - np.asarray(c), axis=1)
+        phi += np.where(d >= r, -m / np.maximum(d, 1e-300), -m * (3 * r * r - d * d) / (2 * r ** 3))
+    return phi
+
+
 def batch_sizes(count: int = 96, seed: int = 4) -> list[int]:
     """Grid sizes of the uneven batch: 32^3, 64^3, 128^3 in ratio 4:2:1.
 
