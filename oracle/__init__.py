@@ -66,6 +66,7 @@ def lib():
         L.or_pair_pass_row.argtypes = [ctypes.c_int, ctypes.c_longlong, _ip]
         L.or_pair_pass_row_dl.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_longlong, _ip]
         L.or_deposit_cic.argtypes = [ctypes.c_int, ctypes.c_longlong, _dp, _dp, _dp]
+        L.or_fd_force.argtypes = [ctypes.c_int, _dp, _dp]
         _lib = L
     return _lib
 
@@ -249,3 +250,14 @@ def deposit_cic(n: int, pos, mass) -> np.ndarray:
     if lib().or_deposit_cic(n, len(mass), _d(pos), _d(mass), _d(rho)) != 0:
         raise ValueError(f"oracle CIC rejected n={n}")
     return rho
+
+
+def fd_force(phi) -> np.ndarray:
+    """Force -grad(phi) by the 5-cell fourth-order differences (App. C),
+    one-sided in the two layers next to each wall: (3, n, n, n)."""
+    phi = _f64(phi)
+    n = phi.shape[0]
+    f = np.zeros((3, n, n, n))
+    if lib().or_fd_force(n, _d(phi), _d(f)) != 0:
+        raise ValueError(f"oracle FD force rejected n={n}")
+    return f

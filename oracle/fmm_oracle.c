@@ -659,6 +659,47 @@ int or_deposit_cic(int n, i64 count, const double *pos, const double *mass, doub
   return 0;
 }
 
+/*
+ * Force from the potential by finite differences, as the host code does
+ * after the solve (App. C: a 5-point stencil).  Along each axis, at cell i of
+ * n, f = -dphi/dx with the fourth-order differences over 5 cells:
+ *   central  (i = 2 .. n-3):  (phi[i-2] - 8 phi[i-1] + 8 phi[i+1] - phi[i+2]) / (12 dx)
+ *   i = 1:                    (-3 phi[0] - 10 phi[1] + 18 phi[2] - 6 phi[3] + phi[4]) / (12 dx)
+ *   i = 0:                    (-25 phi[0] + 48 phi[1] - 36 phi[2] + 16 phi[3] - 3 phi[4]) / (12 dx)
+ * and the mirror images at i = n-2, n-1 (the box has no cells beyond its
+ * walls, so the last two layers take one-sided stencils of the same order).
+ * Each is exact for polynomials of degree <= 4.  f: [3][n^3].
+ */
+static double fd_deriv(const double *v, int i, int n, double dx) {
+  /* v(k) = phi at position k along the axis */
+  if (i >= 2 && i <= n - 3) return (v[i - 2] - 8.0 * v[i - 1] + 8.0 * v[i + 1] - v[i + 2]) / (12.0 * dx);
+  if (i == 1) return (-3.0 * v[0] - 10.0 * v[1] + 18.0 * v[2] - 6.0 * v[3] + v[4]) / (12.0 * dx);
+  if (i == 0) return (-25.0 * v[0] + 48.0 * v[1] - 36.0 * v[2] + 16.0 * v[3] - 3.0 * v[4]) / (12.0 * dx);
+  if (i == n - 2)
+    return -(-3.0 * v[n - 1] - 10.0 * v[n - 2] + 18.0 * v[n - 3] - 6.0 * v[n - 4] + v[n - 5]) / (12.0 * dx);
+  return -(-25.0 * v[n - 1] + 48.0 * v[n - 2] - 36.0 * v[n - 3] + 16.0 * v[n - 4] - 3.0 * v[n - 5]) / (12.0 * dx);
+}
+
+int or_fd_force(int n, const double *phi, double *f) {
+  if (ilog2(n) < 0 || n < 8) return -1;
+  const double dx = 1.0 / n;
+  const i64 N = (i64)n * n * n;
+#pragma omp parallel for schedule(static)
+  for (i64 u = 0; u < N; ++u) {
+    int c[3] = {(int)(u / ((i64)n * n)), (int)((u / n) % n), (int)(u % n)};
+    double line[1024];
+    for (int d = 0; d < 3; ++d) {
+      for (int k = 0; k < n; ++k) {
+        int w[3] = {c[0], c[1], c[2]};
+        w[d] = k;
+        line[k] = phi[lin(w[0], w[1], w[2], n)];
+      }
+      f[(i64)d * N + u] = -fd_deriv(line, c[d], n, dx);
+    }
+  }
+  return 0;
+}
+
 /* O(N^2) direct sum with the same softened Green's function (eq. direct):
    phi_u = sum_w m_w g(x_u - x_w), g_u = -sum_{w != u} m_w (x_u-x_w)/|x_u-x_w|^3.
    targets as in or_solve. */
