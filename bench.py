@@ -228,9 +228,9 @@ def run_extras(args, rho64, fi, fmm, costs, sections=("mixed", "adjoint", "batch
         log(f"extras: point charge FMM-1 vs FMM-2: max {d.max():.3e}, p99 {np.percentile(d, 99):.3e}")
         out["fmm2"] = fmm2
         # the paper's two uniform spheres (Sec. 3), scaled to the unit box:
-        # 4M particles, CIC deposit on the GPU, FMM-1 and FMM-2 at the paper's
+        # 16M particles, CIC deposit on the GPU, FMM-1 and FMM-2 at the paper's
         # orders, errors against the exact potential on the midplane
-        pos, m = fi.two_spheres_particles(1 << 22)
+        pos, m = fi.two_spheres_particles(1 << 24)
         pos_t = torch.as_tensor(pos).cuda()
         m_t = torch.as_tensor(m).cuda()
         rho_s = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
@@ -245,8 +245,31 @@ def run_extras(args, rho64, fi, fmm, costs, sections=("mixed", "adjoint", "batch
             spheres[f"fmm{dl}_p90"] = float(np.percentile(e, 90))
             spheres[f"fmm{dl}_p99"] = float(np.percentile(e, 99))
             del ph
+        # App. C: force magnitudes inside the spheres (cells whose centres lie
+        # inside), the finite-difference force from phi and the solve's g
+        X, Y, Z = np.meshgrid(c, c, c, indexing="ij")
+        pts3 = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+        inside = np.zeros(len(pts3), bool)
+        for cc, rr in fi.TWO_SPHERES:
+            inside |= np.linalg.norm(pts3 - np.asarray(cc), axis=1) < rr
+        sel = np.nonzero(inside)[0]
+        sel_t = torch.as_tensor(sel).cuda()
+        fexact = np.linalg.norm(fi.two_spheres_force(pts3[sel]), axis=0)
+        del X, Y, Z, pts3, inside
+        ph, gg = fmm.Plan(n, 3, "fp64", nmax=2).solve(rho_s)
+        fd_ms = _event_ms(lambda: fmm.fd_force(ph), 10, 2)
+        for name, force in (("fd", fmm.fd_force(ph)), ("g", gg)):
+            mag = torch.linalg.vector_norm(force.reshape(3, -1)[:, sel_t], dim=0).cpu().numpy()
+            e = np.abs(mag - fexact) / fexact
+            spheres[f"force_{name}_inside_p90"] = float(np.percentile(e, 90))
+            spheres[f"force_{name}_inside_p99"] = float(np.percentile(e, 99))
+        spheres["fd_force_ms"] = fd_ms
+        spheres["fd_force_GBps_at_32B_per_cell"] = 32 * N / (fd_ms * 1e-3) / 1e9
+        del ph, gg, sel_t
         del pos_t, m_t, rho_s
         out["two_spheres"] = spheres
+        log(f"extras: two spheres force inside, P90: FD {spheres['force_fd_inside_p90']:.2e}, "
+            f"g {spheres['force_g_inside_p90']:.2e}; FD force {fd_ms:.3f} ms")
         log(f"extras: two spheres: deposit {dep_ms:.2f} ms; P90/P99 FMM-1 {spheres['fmm1_p90']:.2e}/"
             f"{spheres['fmm1_p99']:.2e}, FMM-2 {spheres['fmm2_p90']:.2e}/{spheres['fmm2_p99']:.2e}")
     # mixed precision at order P

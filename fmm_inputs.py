@@ -154,6 +154,20 @@ def two_spheres_potential(points) -> np.ndarray:
     return phi
 
 
+def two_spheres_force(points) -> np.ndarray:
+    """Exact acceleration (G = 1) of the two uniform spheres at points (k, 3):
+    -M d / r^3 outside a sphere, -M d / R^3 inside (d = x - centre); (3, k)."""
+    points = np.asarray(points, dtype=np.float64)
+    g = np.zeros((3, len(points)))
+    for c, r in TWO_SPHERES:
+        m = 4.0 / 3.0 * math.pi * r ** 3
+        d = points - np.asarray(c)
+        dist = np.linalg.norm(d, axis=1)
+        scale = np.where(dist >= r, m / np.maximum(dist, 1e-300) ** 3, m / r ** 3)
+        g -= (d * scale[:, None]).T
+    return g
+
+
 def batch_sizes(count: int = 96, seed: int = 4) -> list[int]:
     """Grid sizes of the uneven batch: 32^3, 64^3, 128^3 in ratio 4:2:1.
 

@@ -200,6 +200,21 @@ int fmm_debug_expansions(fmm_plan* plan, int which, int level, double* out, size
 int fmm_deposit_cic(int n, long long count, const double* pos, const double* mass, double* rho, void* stream);
 
 /*
+ * Force from a potential by finite differences, the step after a solve
+ * (App. C: the host code differentiates phi with a 5-point stencil).  Along
+ * each axis f = -dphi/dx by fourth-order differences over 5 cells, central
+ * away from the walls and one-sided of the same order in the two layers
+ * next to each wall (the box has no cells beyond them).  This is the host
+ * code's force; fmm_solve's g is the exact gradient of the FMM potential.
+ *  n    cells per axis, a power of two in [8, 1024]
+ *  phi  DEVICE, n^3 doubles, C order (e.g. fmm_solve's phi)
+ *  f    DEVICE, 3 x n^3 doubles, component-major like g; must not alias phi
+ * Enqueued on `stream`.  Returns FMM_OK, FMM_ERR_INVALID_ARG (n, NULL or
+ * aliasing pointers) or FMM_ERR_DEVICE (launch failure).
+ */
+int fmm_fd_force(int n, const double* phi, double* f, void* stream);
+
+/*
  * Per-stage device timing with HIP events recorded on the solve's stream.
  * fmm_profile_enable(plan, 1) makes every following fmm_solve /
  * fmm_solve_backward record an event pair around each stage; 0 stops it.

@@ -1068,6 +1068,22 @@ int fmm_deposit_cic(int n, long long count, const double* pos, const double* mas
   return ok();
 }
 
+int fmm_fd_force(int n, const double* phi, double* f, void* stream) {
+  const int L = ilog2_exact(n);
+  if (L < 3 || L > 10) return fail(FMM_ERR_INVALID_ARG, "n must be a power of two in [8, 1024] (got %d)", n);
+  if (!phi || !f) return fail(FMM_ERR_INVALID_ARG, "phi and f must be device pointers");
+  const size_t N = (size_t)n * n * n;
+  const char *pb = (const char*)phi, *fb = (const char*)f;
+  if (pb < fb + 3 * N * sizeof(double) && fb < pb + N * sizeof(double))
+    return fail(FMM_ERR_INVALID_ARG, "phi and f must not overlap");
+  hipError_t e = fmm::launch_fd_force(n, phi, f, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FMM_ERR_DEVICE, "force launch failed: %s", hipGetErrorString(e));
+  }
+  return ok();
+}
+
 int fmm_debug_expansions(fmm_plan* plan, int which, int level, double* out, size_t count) {
   if (!plan) return fail(FMM_ERR_INVALID_ARG, "plan is NULL");
   if (which != 0 && which != 1) return fail(FMM_ERR_INVALID_ARG, "which must be 0 or 1");

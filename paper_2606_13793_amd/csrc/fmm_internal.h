@@ -318,6 +318,8 @@ hipError_t launch_tables(fmm_plan* pl, hipStream_t s);
 // cloud-in-cell deposition (fmm_deposit.hip): rho[n^3] += the CIC densities
 // of `count` particles
 hipError_t launch_cic(int n, long long count, const double* pos, const double* mass, double* rho, hipStream_t s);
+// finite-difference force (fmm_force.hip): f[3][n^3] = -grad(phi) by 5-cell differences
+hipError_t launch_fd_force(int n, const double* phi, double* f, hipStream_t s);
 hipError_t launch_solve(fmm_plan* pl, IoArg io, hipStream_t s);
 hipError_t launch_backward(fmm_plan* pl, const void* dphi, const void* dg, void* drho, hipStream_t s);
 hipError_t launch_adjoint_tables(fmm_plan* pl, hipStream_t s);

@@ -31,6 +31,7 @@ EXPORTS = (
     "fmm_last_error", "fmm_last_status", "fmm_debug_expansions", "fmm_multi_index",
     "fmm_profile_enable", "fmm_profile_read", "fmm_profile_stage_name",
     "fmm_batch_plan_create", "fmm_batch_solve", "fmm_batch_info", "fmm_deposit_cic",
+    "fmm_fd_force",
 )
 
 
@@ -91,6 +92,7 @@ def lib():
         L.fmm_batch_info.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
                                      ctypes.POINTER(ctypes.c_double), i]
         L.fmm_deposit_cic.argtypes = [i, ctypes.c_longlong, vp, vp, vp, vp]
+        L.fmm_fd_force.argtypes = [i, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -385,3 +387,17 @@ def deposit_cic(n: int, pos, mass, rho=None, stream=None):
     _check(lib().fmm_deposit_cic(int(n), int(pos.shape[0]), pos.data_ptr(), mass.data_ptr(), rho.data_ptr(),
                                  _stream_ptr(stream)))
     return rho
+
+
+def fd_force(phi, stream=None):
+    """Force -grad(phi) by 5-cell fourth-order differences (``fmm_fd_force``),
+    the host code's force of App. C: (3, n, n, n) float64 from a float64
+    (n, n, n) CUDA tensor."""
+    import torch
+    if phi.dtype != torch.float64 or not phi.is_cuda or phi.dim() != 3 or len(set(phi.shape)) != 1:
+        raise TypeError("phi must be a float64 (n, n, n) CUDA tensor")
+    phi = phi.contiguous()
+    n = phi.shape[0]
+    f = torch.empty((3, n, n, n), dtype=torch.float64, device=phi.device)
+    _check(lib().fmm_fd_force(int(n), phi.data_ptr(), f.data_ptr(), _stream_ptr(stream)))
+    return f

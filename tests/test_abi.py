@@ -191,3 +191,11 @@ def test_deposit_arguments_rejected_before_the_device(F):
     assert L.fmm_deposit_cic(16, 4, None, 8, 8, None) == -1         # NULL with particles
     assert "pos" in F.last_error()
     assert L.fmm_deposit_cic(16, 0, None, None, None, None) == 0    # nothing to do
+
+
+def test_fd_force_arguments_rejected_before_the_device(F):
+    L = F.lib()
+    assert L.fmm_fd_force(12, 8, 4096, None) == -1           # n not a power of two
+    assert L.fmm_fd_force(16, None, 8, None) == -1           # NULL phi
+    assert L.fmm_fd_force(16, 8, 8 + 8 * 100, None) == -1    # f overlaps phi
+    assert "overlap" in F.last_error()
