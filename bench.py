@@ -79,7 +79,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed-precision, equal-accuracy, adjoint and batch sections")
-    ap.add_argument("--section", default=None, choices=["mixed", "adjoint", "batch", "large", "huge"],
+    ap.add_argument("--section", default=None,
+                    choices=["mixed", "fmm2", "particles", "adjoint", "batch", "large", "huge"],
                     help="run only this extra section (for profiling) and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device-to-device copy of BYTES bytes (a known-size "
@@ -145,7 +146,8 @@ def run_large(fi, fmm, costs, n: int = 512, p: int = 6) -> dict:
     return out
 
 
-def run_extras(args, rho64, fi, fmm, costs, sections=("mixed", "adjoint", "batch", "large")) -> dict:
+def run_extras(args, rho64, fi, fmm, costs,
+               sections=("mixed", "fmm2", "particles", "adjoint", "batch", "large")) -> dict:
     """The other measured rows at the same workload: mixed precision (with
     the equal-accuracy comparison against FP64 at lower order), the adjoint,
     and the uneven 96-field batch against a loop of single solves."""
@@ -160,7 +162,7 @@ def run_extras(args, rho64, fi, fmm, costs, sections=("mixed", "adjoint", "batch
     idx = torch.as_tensor(cells, device="cuda")
     rho_host = rho64.cpu().numpy()
     phi_d = None
-    if "mixed" in sections:
+    if "mixed" in sections or "fmm2" in sections:
         log("extras: direct sum at 64 sampled cells")
         phi_d, _ = oracle.direct(rho_host, targets=cells)
 
@@ -197,7 +199,8 @@ def run_extras(args, rho64, fi, fmm, costs, sections=("mixed", "adjoint", "batch
     # FMM-2 (finest FMM level two above the unigrid, App. A): time and error
     # at order P and at the paper's orders, and the FMM-1 vs FMM-2 potential
     # difference of a CIC point charge at the box centre on the midplane
-    if "mixed" in sections and P >= 3:
+    c = fi.cell_centres(n)
+    if "fmm2" in sections and P >= 3:
         fmm2 = {}
         for q, nm in ((P, None), (3, 2)):
             plan = fmm.Plan(n, q, "fp64", nmax=nm, delta_l=2)
@@ -218,7 +221,6 @@ def run_extras(args, rho64, fi, fmm, costs, sections=("mixed", "adjoint", "batch
                                              "p90": float(np.percentile(d, 90))}
         # against the exact potential -1/r of the point, over the whole slice
         # (the charge's own cells included)
-        c = fi.cell_centres(n)
         r = np.sqrt((c[:, None] - 0.5) ** 2 + (c[None, :] - 0.5) ** 2 + (c[n // 2] - 0.5) ** 2)
         for key, sl in (("fmm1", s1), ("fmm2", s2)):
             e = np.abs(sl + 1.0 / r) * r
@@ -227,6 +229,7 @@ def run_extras(args, rho64, fi, fmm, costs, sections=("mixed", "adjoint", "batch
         del pc
         log(f"extras: point charge FMM-1 vs FMM-2: max {d.max():.3e}, p99 {np.percentile(d, 99):.3e}")
         out["fmm2"] = fmm2
+    if "particles" in sections:
         # the paper's two uniform spheres (Sec. 3), scaled to the unit box:
         # 16M particles, CIC deposit on the GPU, FMM-1 and FMM-2 at the paper's
         # orders, errors against the exact potential on the midplane
