@@ -429,6 +429,7 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
         }
       }
     }
+    if constexpr (DL == 2) return;  // FMM-2 runs its near field for all row tiles below
     const auto rg = gmem(rho);
 #pragma unroll 1
     for (int cb = 0; cb < NPT; cb += UN) {
@@ -461,6 +462,56 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
   };
 #pragma unroll
   for (int m = 0; m < MTW; ++m) tail(m0 + m, acc[m]);
+  if constexpr (DL == 2) {
+    // FMM-2's near field, 12^3 sources per row: the B fragments of a K step
+    // serve every row tile of the wave, so they are loaded once per step
+    // instead of once per row tile.  Row cells packed as c0 << 16 | c1 << 8 | c2.
+    constexpr int UN2 = 3;
+    int cpk[MTW];
+#pragma unroll
+    for (int mw = 0; mw < MTW; ++mw) {
+      int c0, c1, c2;
+      cell_of(m0 + mw, c0, c1, c2);
+      cpk[mw] = (c0 << 16) | (c1 << 8) | c2;
+    }
+    const auto rg = gmem(rho);
+#pragma unroll 1
+    for (int cb = 0; cb < NPT; cb += UN2) {
+      TI va[UN2][MTW][VPL];
+      AF bn[UN2][2];
+#pragma unroll
+      for (int u = 0; u < UN2; ++u) {
+        const int c = cb + u < NPT ? cb + u : 0;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+          bn[u][t] = *reinterpret_cast<const AF*>(Wp2p + ((size_t)(c * 2 + t) * 64 + lane) * VPL);
+#pragma unroll
+        for (int v = 0; v < VPL; ++v) {
+          const int k = KT * c + VPL * kq + v;
+          const int k0 = k / (NB * NB) - 4, k1 = (k / NB) % NB - 4, k2 = k % NB - 4;
+          const bool kok = cb + u < NPT && k < NNEAR;
+#pragma unroll
+          for (int mw = 0; mw < MTW; ++mw) {
+            const int w0 = ((cpk[mw] >> 16) << 2) + k0, w1 = (((cpk[mw] >> 8) & 255) << 2) + k1,
+                      w2 = ((cpk[mw] & 255) << 2) + k2;
+            va[u][mw][v] = (kok && w0 >= 0 && w1 >= 0 && w2 >= 0 && w0 < n && w1 < n && w2 < n)
+                               ? rg[((long long)w0 * n + w1) * n + w2]
+                               : TI(0);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UN2; ++u) {
+        if (cb + u < NPT) {
+#pragma unroll
+          for (int mw = 0; mw < MTW; ++mw) {
+            acc[mw][0] = M::op(M::frag(va[u][mw]), bn[u][0], acc[mw][0]);
+            acc[mw][1] = M::op(M::frag(va[u][mw]), bn[u][1], acc[mw][1]);
+          }
+        }
+      }
+    }
+  }
   // epilogue: element v of tile t is row M::row(v, kq), column 16 t + i
 #pragma unroll
   for (int mw = 0; mw < MTW; ++mw) {
