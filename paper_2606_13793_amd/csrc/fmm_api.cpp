@@ -60,8 +60,6 @@ int validate(int n, int p, int isolated, const fmm_options* o) {
       return fail(FMM_ERR_INVALID_ARG, "nmax must be -1 or in [0, p] (got %d)", o->nmax);
     if (o->delta_l != 1 && o->delta_l != 2)
       return fail(FMM_ERR_UNSUPPORTED, "delta_l must be 1 or 2 (got %d)", o->delta_l);
-    if (o->delta_l == 2 && o->precision != FMM_FP64)
-      return fail(FMM_ERR_UNSUPPORTED, "delta_l = 2 is provided for FP64 plans only");
     if (o->delta_l == 2 && L < 4) return fail(FMM_ERR_INVALID_ARG, "delta_l = 2 needs n >= 16 (got %d)", n);
     if (o->coarse_fp64_levels < 0) return fail(FMM_ERR_INVALID_ARG, "coarse_fp64_levels must be >= 0");
   }

@@ -1072,14 +1072,9 @@ hipError_t launch_bottom(fmm_plan* pl, int x, IoArg io, hipStream_t s) {
   const int nck = (pl->NMX + Mf<CT>::KC - 1) / Mf<CT>::KC;
   StageScope sc(pl, ST_BOTTOM, 1, s);
   if (pl->dl == 2) {
-    // FMM-2 is built for FP64 plans only (the plan validation rejects others)
-    if constexpr (std::is_same<CT, double>::value && std::is_same<TI, double>::value &&
-                  std::is_same<TO, double>::value)
-      hipLaunchKernelGGL((k_bottom<P, CT, TI, TO, 16, 2>), dim3(st.blocks, 8), dim3(bottom_threads<CT>()), 0, s, st.dev,
-                         st.nseg, io, (const H*)pl->wm2p[X], (const H*)pl->wl2p[X], (const H*)pl->wl2p2[X],
-                         (const H*)pl->wp2p[X], pl->dlists, nck);
-    else
-      return hipErrorNotSupported;
+    hipLaunchKernelGGL((k_bottom<P, CT, TI, TO, 16, 2>), dim3(st.blocks, 8), dim3(bottom_threads<CT>()), 0, s, st.dev,
+                       st.nseg, io, (const H*)pl->wm2p[X], (const H*)pl->wl2p[X], (const H*)pl->wl2p2[X],
+                       (const H*)pl->wp2p[X], pl->dlists, nck);
   } else if (z == 0)
     hipLaunchKernelGGL((k_bottom<P, CT, TI, TO, 16, 1>), dim3(st.blocks), dim3(bottom_threads<CT>()), 0, s, st.dev, st.nseg, io,
                        (const H*)pl->wm2p[X], (const H*)pl->wl2p[X], (const H*)pl->wl2p2[X], (const H*)pl->wp2p[X],

@@ -466,7 +466,9 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
     // FMM-2's near field, 12^3 sources per row: the B fragments of a K step
     // serve every row tile of the wave, so they are loaded once per step
     // instead of once per row tile.  Row cells packed as c0 << 16 | c1 << 8 | c2.
-    constexpr int UN2 = 3;
+    // K steps in flight, sized to the registers left: FP64 3; FP32 (8 row
+    // tiles per wave) and BF16 (8 densities per lane and tile) 1
+    constexpr int UN2 = M::IDX == 0 ? 3 : 1;
     int cpk[MTW];
 #pragma unroll
     for (int mw = 0; mw < MTW; ++mw) {

@@ -80,8 +80,6 @@ def test_invalid_sizes_rejected_without_device(F, n, p, iso, code, text):
 @pytest.mark.parametrize("opt,code", [
     ({"delta_l": 3}, -2),
     ({"delta_l": 0}, -2),
-    ({"delta_l": 2, "precision": 1}, -2),
-    ({"delta_l": 2, "precision": 2}, -2),
     ({"nmax": 7}, -1),
     ({"nmax": -3}, -1),
     ({"precision": 5}, -1),

@@ -111,13 +111,30 @@ def test_fmm1_fmm2_point_charge_256(F):
     assert 1e-3 < d.max() < 4e-3, d.max()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("n,p,coarse", [(32, 6, 0), (64, 6, 0), (64, 4, 2)])
+def test_fmm2_mixed_precision_matches_oracle(F, orc, precision, n, p, coarse):
+    """FMM-2 with FP32 / BF16 operands against the FP64 oracle's FMM-2 of the
+    same float-rounded density, at the mixed-precision bars of FMM-1."""
+    import torch
+    _say(f"case fmm2 {precision} n={n} p={p} coarse_fp64_levels={coarse}")
+    bars = {"fp32": (1e-5, 1e-4), "bf16": (5e-3, 5e-2)}
+    rho32 = fi.plummer_density(n, fi.multi_plummer_params(32, 900 + n + p)).astype(np.float32)
+    plan = F.Plan(n, p, precision, coarse_fp64_levels=coarse, delta_l=2)
+    phi, g = plan.solve(torch.as_tensor(rho32).cuda())
+    torch.cuda.synchronize()
+    assert phi.dtype == torch.float32
+    phi_o, g_o = orc.solve(rho32.astype(np.float64), p, delta_l=2)
+    ep, eg = rel(phi.double().cpu().numpy(), phi_o), rel(g.double().cpu().numpy(), g_o)
+    bp, bg = bars[precision]
+    assert ep <= bp and eg <= bg, (ep, eg)
+
+
 def test_fmm2_rejections(F):
     import torch
     _say("case fmm2 rejections")
     with pytest.raises(F.FmmError):
         F.Plan(8, 4, "fp64", delta_l=2)          # needs n >= 16
-    with pytest.raises(F.FmmError):
-        F.Plan(32, 4, "fp32", delta_l=2)         # FP64 only
     with pytest.raises(F.FmmError):
         F.Plan(32, 4, "fp64", delta_l=3)
     plan = F.Plan(16, 4, "fp64", delta_l=2)
