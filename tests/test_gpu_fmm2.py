@@ -72,10 +72,12 @@ def test_fmm2_random_density_every_cell(F, orc):
     assert np.abs(g - g_o).max() <= 1e-12 * np.abs(g_o).max()
 
 
-def test_fmm2_full_size_sampled(F, orc):
-    """256^3, p = 6: the benchmark's FMM-2 launch, at sampled cells."""
+@pytest.mark.parametrize("n", [256, 512])
+def test_fmm2_full_size_sampled(F, orc, n):
+    """256^3 and 512^3, p = 6: the benchmark's FMM-2 launch and a larger
+    one, at sampled cells."""
     import torch
-    n, p = 256, 6
+    p = 6
     _say(f"case fmm2 sampled n={n} p={p}")
     rho_t = fi.plummer_density(n, fi.multi_plummer_params(256, 256), device="cuda")
     plan = F.Plan(n, p, "fp64", delta_l=2)
