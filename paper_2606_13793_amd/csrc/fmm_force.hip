@@ -5,9 +5,13 @@
 // order (the box has no cells beyond its walls).  Each is exact for
 // polynomials of degree <= 4.
 //
-// Bandwidth-bound: one thread per cell, 256 consecutive cells of a z line
-// per block, so every stencil read of a wave is a contiguous run; the 13
-// values a cell reads come mostly from the caches.
+// Bandwidth-bound, so each phi value should leave HBM once.  A block owns a
+// tile of FD_TJ x FD_TK cells of the (y, z) plane and walks FD_CI planes
+// along x.  Per plane it stages the tile with a 2-cell margin in LDS, where
+// the y and z stencils read it; the x stencil of a cell comes from a
+// register window of its own column, phi at x - 2 .. x + 2, which slides by
+// one load per plane (the layers next to the x walls read their one-sided
+// stencils from memory).  Writes are whole z runs.
 #include <hip/hip_runtime.h>
 
 #include "fmm_internal.h"
@@ -15,36 +19,73 @@
 namespace fmm {
 namespace {
 
-constexpr int FD_THREADS = 256;
+constexpr int FD_TK = 64, FD_TJ = 4, FD_CI = 16, FD_THREADS = FD_TK * FD_TJ;
+constexpr int FD_HK = FD_TK + 4, FD_HJ = FD_TJ + 4;  // staged plane with its margin
 
-// 12 dx dphi/dx at position x of a line of n values v(0..n-1) spaced by s
-__device__ __forceinline__ double fd12(const double* __restrict__ v, long long s, int x, int n) {
-  if (x >= 2 && x <= n - 3) return (v[(x - 2) * s] - v[(x + 2) * s]) + 8.0 * (v[(x + 1) * s] - v[(x - 1) * s]);
-  if (x == 1) return -3.0 * v[0] - 10.0 * v[s] + 18.0 * v[2 * s] - 6.0 * v[3 * s] + v[4 * s];
-  if (x == 0) return -25.0 * v[0] + 48.0 * v[s] - 36.0 * v[2 * s] + 16.0 * v[3 * s] - 3.0 * v[4 * s];
-  const double* w = v + (long long)(n - 1) * s;  // mirrored: the line read backwards from the far wall
-  if (x == n - 2) return 3.0 * w[0] + 10.0 * w[-s] - 18.0 * w[-2 * s] + 6.0 * w[-3 * s] - w[-4 * s];
-  return 25.0 * w[0] - 48.0 * w[-s] + 36.0 * w[-2 * s] - 16.0 * w[-3 * s] + 3.0 * w[-4 * s];
+// 12 dx dphi/dx at position x of a line of n values, at(a) = phi at a
+template <typename V>
+__device__ __forceinline__ double fd12(V at, int x, int n) {
+  if (x >= 2 && x <= n - 3) return (at(x - 2) - at(x + 2)) + 8.0 * (at(x + 1) - at(x - 1));
+  if (x == 1) return -3.0 * at(0) - 10.0 * at(1) + 18.0 * at(2) - 6.0 * at(3) + at(4);
+  if (x == 0) return -25.0 * at(0) + 48.0 * at(1) - 36.0 * at(2) + 16.0 * at(3) - 3.0 * at(4);
+  if (x == n - 2) return 3.0 * at(n - 1) + 10.0 * at(n - 2) - 18.0 * at(n - 3) + 6.0 * at(n - 4) - at(n - 5);
+  return 25.0 * at(n - 1) - 48.0 * at(n - 2) + 36.0 * at(n - 3) - 16.0 * at(n - 4) + 3.0 * at(n - 5);
 }
 
+// Grid: (tiles along z, tiles along y, chunks of FD_CI planes along x).
 __global__ __launch_bounds__(FD_THREADS) void k_fd_force(int n, const double* __restrict__ phi, double* __restrict__ f) {
-  const long long N = (long long)n * n * n;
-  const long long u = (long long)blockIdx.x * FD_THREADS + threadIdx.x;
-  if (u >= N) return;
-  const int k = (int)(u % n), j = (int)((u / n) % n), i = (int)(u / ((long long)n * n));
+  __shared__ double plane[FD_HJ * FD_HK];
+  const long long nn = (long long)n * n, N = nn * n;
+  const int tk = threadIdx.x % FD_TK, tj = threadIdx.x / FD_TK;
+  const int k0 = blockIdx.x * FD_TK, j0 = blockIdx.y * FD_TJ, i0 = blockIdx.z * FD_CI;
+  const int k = k0 + tk, j = j0 + tj;
+  const bool mine = k < n && j < n;
+  const int i1 = i0 + FD_CI < n ? i0 + FD_CI : n;
   const double s = (double)n / 12.0;  // 1 / (12 dx)
-  const long long nn = (long long)n * n;
-  f[u] = -s * fd12(phi + (u - i * nn), nn, i, n);
-  f[N + u] = -s * fd12(phi + (u - (long long)j * n), n, j, n);
-  f[2 * N + u] = -s * fd12(phi + (u - k), 1, k, n);
+  const long long col = (long long)(mine ? j : 0) * n + (mine ? k : 0);
+  // x window: q[d] = phi at x = i - 2 + d of this column (interior planes)
+  double q[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) {
+    const int x = i0 - 2 + d;
+    q[d] = (x >= 0 && x < n) ? phi[x * nn + col] : 0.0;
+  }
+#pragma unroll 1
+  for (int i = i0; i < i1; ++i) {
+    // stage plane i, rows j0 - 2 .. j0 + FD_TJ + 1, columns k0 - 2 .. k0 + FD_TK + 1
+    __syncthreads();  // the previous plane is consumed
+    for (int e = threadIdx.x; e < FD_HJ * FD_HK; e += FD_THREADS) {
+      const int hj = e / FD_HK, hk = e - hj * FD_HK;
+      const int jj = j0 - 2 + hj, kk = k0 - 2 + hk;
+      plane[e] = (jj >= 0 && jj < n && kk >= 0 && kk < n) ? phi[i * nn + (long long)jj * n + kk] : 0.0;
+    }
+    __syncthreads();
+    if (mine) {
+      const long long u = i * nn + col;
+      // the x walls read their one-sided stencils from memory
+      const double fx = (i >= 2 && i <= n - 3) ? (q[0] - q[4]) + 8.0 * (q[3] - q[1])
+                                               : fd12([&](int a) { return phi[a * nn + col]; }, i, n);
+      // staged cell (jj, kk) sits at row jj - j0 + 2, column kk - k0 + 2
+      const double fy = fd12([&](int a) { return plane[(a - j0 + 2) * FD_HK + tk + 2]; }, j, n);
+      const double fz = fd12([&](int a) { return plane[(tj + 2) * FD_HK + a - k0 + 2]; }, k, n);
+      f[u] = -s * fx;
+      f[N + u] = -s * fy;
+      f[2 * N + u] = -s * fz;
+    }
+    // slide the x window by one plane
+#pragma unroll
+    for (int d = 0; d < 4; ++d) q[d] = q[d + 1];
+    const int x = i + 3;
+    q[4] = (mine && x < n) ? phi[x * nn + col] : 0.0;
+  }
 }
 
 }  // namespace
 
 hipError_t launch_fd_force(int n, const double* phi, double* f, hipStream_t s) {
-  const long long N = (long long)n * n * n;
-  hipLaunchKernelGGL(k_fd_force, dim3((unsigned)((N + FD_THREADS - 1) / FD_THREADS)), dim3(FD_THREADS), 0, s, n, phi,
-                     f);
+  const dim3 grid((unsigned)((n + FD_TK - 1) / FD_TK), (unsigned)((n + FD_TJ - 1) / FD_TJ),
+                  (unsigned)((n + FD_CI - 1) / FD_CI));
+  hipLaunchKernelGGL(k_fd_force, grid, dim3(FD_THREADS), 0, s, n, phi, f);
   return hipGetLastError();
 }
 
