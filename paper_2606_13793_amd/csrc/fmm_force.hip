@@ -19,7 +19,7 @@
 namespace fmm {
 namespace {
 
-constexpr int FD_TK = 64, FD_TJ = 4, FD_CI = 16, FD_THREADS = FD_TK * FD_TJ;
+constexpr int FD_TK = 64, FD_TJ = 8, FD_CI = 4, FD_THREADS = FD_TK * FD_TJ;
 constexpr int FD_HK = FD_TK + 4, FD_HJ = FD_TJ + 4;  // staged plane with its margin
 
 // 12 dx dphi/dx at position x of a line of n values, at(a) = phi at a
