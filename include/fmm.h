@@ -11,8 +11,8 @@
  * Sec. 2.3 and Sec. 4).  Cartesian expansions to order p; the finest FMM
  * grid sits delta_l levels above the unigrid (App. A): 1 (FMM-1, default) or
  * 2 (FMM-2, whose finest FMM cells hold 4^3 unigrid cells and whose near
- * field is the 27 x 64 cells of the adjacent ones; single-field plans,
- * forward solve).
+ * field is the 27 x 64 cells of the adjacent ones; forward solves, single
+ * fields and batches).
  *
  * Conventions shared by every entry point
  *  - Grid: unit box [0,1]^3, n cells per axis, cell (i,j,k) centred at
@@ -52,7 +52,7 @@ typedef enum {
   FMM_OK = 0,
   FMM_ERR_INVALID_ARG = -1,   /* bad size, order, pointer or option */
   FMM_ERR_UNSUPPORTED = -2,   /* well-formed but not provided (periodic BC, delta_l outside {1, 2},
-                                 delta_l = 2 in a batch or for the backward pass) */
+                                 the backward pass of a delta_l = 2 plan) */
   FMM_ERR_OUT_OF_MEMORY = -3, /* device allocation failed */
   FMM_ERR_DEVICE = -4,        /* HIP runtime error (no device, launch failure) */
   FMM_ERR_NONFINITE = -5      /* rho holds NaN/Inf (only with check_finite) */
@@ -75,8 +75,8 @@ typedef struct {
                                the kept terms */
   int coarse_fp64_levels;   /* mixed plans: levels k <= this stay FP64; default 4 */
   int delta_l;              /* level offset unigrid -> finest FMM grid: 1 (default) or 2
-                               (n >= 16; fmm_solve_backward and batch plans return
-                               FMM_ERR_UNSUPPORTED for 2) */
+                               (n >= 16; fmm_solve_backward returns FMM_ERR_UNSUPPORTED
+                               for 2) */
   int check_finite;         /* nonzero: fmm_solve scans rho for NaN/Inf first (single-field plans) */
   int autotune;             /* batch plans: time the launch-shape candidates at creation; default 1 */
 } fmm_options;

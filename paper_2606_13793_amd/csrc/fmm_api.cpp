@@ -778,10 +778,6 @@ fmm_plan* fmm_batch_plan_create(int count, const int* n, int p, int isolated, co
     fail(FMM_ERR_UNSUPPORTED, "check_finite is provided for single-field plans only");
     return nullptr;
   }
-  if (o.delta_l != 1) {
-    fail(FMM_ERR_UNSUPPORTED, "batch plans are provided for delta_l = 1");
-    return nullptr;
-  }
   fmm_plan* pl = create_plan(std::vector<int>(n, n + count), p, o, 1);
   if (!pl) return nullptr;
   if (o.autotune && autotune(pl) != FMM_OK) {

@@ -249,13 +249,14 @@ class Batch:
     replay a captured HIP graph."""
 
     def __init__(self, sizes, p: int, precision: str = "fp32", coarse_fp64_levels: int = 4,
-                 autotune: bool = True, isolated: int = 1):
+                 autotune: bool = True, isolated: int = 1, delta_l: int = 1):
         L = lib()
         opt = FmmOptions()
         L.fmm_options_default(ctypes.byref(opt))
         opt.precision = PRECISIONS[precision]
         opt.coarse_fp64_levels = int(coarse_fp64_levels)
         opt.autotune = int(bool(autotune))
+        opt.delta_l = int(delta_l)
         self.sizes = [int(n) for n in sizes]
         arr = (ctypes.c_int * len(self.sizes))(*self.sizes)
         ptr = L.fmm_batch_plan_create(len(self.sizes), arr, int(p), int(isolated), ctypes.byref(opt))

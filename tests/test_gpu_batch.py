@@ -66,6 +66,29 @@ def test_fp64_batch_matches_oracle_and_single_plans(F, orc, p):
         assert rel(gs[f].cpu().numpy(), g1.cpu().numpy()) < 1e-14
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fmm2_batch_matches_single_plans(F, orc, precision):
+    """FMM-2 (delta_l = 2) fields in one batch: each equals its single-field
+    FMM-2 plan, and the FP64 ones the oracle's FMM-2."""
+    import torch
+    sizes = [32, 16, 64, 16, 32]
+    _say(f"case batch fmm2 {precision} sizes={sizes}")
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    B = F.Batch(sizes, 4, precision, delta_l=2)
+    rhos = _fields(sizes, dt)
+    phis, gs = B.solve(rhos)
+    torch.cuda.synchronize()
+    for f, n in enumerate(sizes):
+        ps, g1 = F.Plan(n, 4, precision, delta_l=2).solve(rhos[f])
+        torch.cuda.synchronize()
+        assert rel(phis[f].double().cpu().numpy(), ps.double().cpu().numpy()) < 1e-6
+        assert rel(gs[f].double().cpu().numpy(), g1.double().cpu().numpy()) < 1e-6
+        if precision == "fp64":
+            assert rel(phis[f].cpu().numpy(), ps.cpu().numpy()) < 1e-14
+            phi_o, g_o = orc.solve(rhos[f].cpu().numpy(), 4, delta_l=2)
+            assert rel(phis[f].cpu().numpy(), phi_o) < TOL64 and rel(gs[f].cpu().numpy(), g_o) < TOL64
+
+
 def test_graph_replays_and_buffer_changes(F):
     """Replays of the captured graph, with eager work between them and new
     buffers on the third call, give the eager (profiled, directly launched)
