@@ -237,10 +237,16 @@ def run_extras(args, rho64, fi, fmm, costs,
         pos_t = torch.as_tensor(pos).cuda()
         m_t = torch.as_tensor(m).cuda()
         rho_s = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+        dep_random_ms = _event_ms(lambda: (rho_s.zero_(), fmm.deposit_cic(n, pos_t, m_t, rho=rho_s)), 5, 2)
+        # the same particles in cell order, as AMR codes keep them
+        order = torch.as_tensor(fi.cell_order(pos, n)).cuda()
+        pos_t, m_t = pos_t[order].contiguous(), m_t[order].contiguous()
+        del order
         dep_ms = _event_ms(lambda: (rho_s.zero_(), fmm.deposit_cic(n, pos_t, m_t, rho=rho_s)), 5, 2)
         pts = np.stack(np.meshgrid(c, c, [c[n // 2]], indexing="ij"), -1).reshape(-1, 3)
         exact = fi.two_spheres_potential(pts).reshape(n, n)
-        spheres = {"particles": int(len(m)), "zero_and_deposit_ms": dep_ms, "p": 3, "nmax": 2,
+        spheres = {"particles": int(len(m)), "zero_and_deposit_ms_cell_order": dep_ms,
+                   "zero_and_deposit_ms_random_order": dep_random_ms, "p": 3, "nmax": 2,
                    "slice": "midplane through both centres"}
         for dl in (1, 2):
             ph = fmm.Plan(n, 3, "fp64", nmax=2, delta_l=dl).solve(rho_s, want_g=False)[0]
@@ -273,7 +279,8 @@ def run_extras(args, rho64, fi, fmm, costs,
         out["two_spheres"] = spheres
         log(f"extras: two spheres force inside, P90: FD {spheres['force_fd_inside_p90']:.2e}, "
             f"g {spheres['force_g_inside_p90']:.2e}; FD force {fd_ms:.3f} ms")
-        log(f"extras: two spheres: deposit {dep_ms:.2f} ms; P90/P99 FMM-1 {spheres['fmm1_p90']:.2e}/"
+        log(f"extras: two spheres: deposit {dep_ms:.2f} ms in cell order, {dep_random_ms:.2f} ms in random order; "
+            f"P90/P99 FMM-1 {spheres['fmm1_p90']:.2e}/"
             f"{spheres['fmm1_p99']:.2e}, FMM-2 {spheres['fmm2_p90']:.2e}/{spheres['fmm2_p99']:.2e}")
     # mixed precision at order P
     mixed = {}

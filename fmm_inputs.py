@@ -154,6 +154,14 @@ def two_spheres_potential(points) -> np.ndarray:
     return phi
 
 
+def cell_order(pos, n: int) -> np.ndarray:
+    """Permutation that puts particles in cell order on an n^3 grid (by the
+    cell below-left of each, C order), the order AMR codes keep them in."""
+    lo = np.floor(np.asarray(pos) * n - 0.5).astype(np.int64) + 1
+    key = (lo[:, 0] * (n + 2) + lo[:, 1]) * (n + 2) + lo[:, 2]
+    return np.argsort(key, kind="stable")
+
+
 def two_spheres_force(points) -> np.ndarray:
     """Exact acceleration (G = 1) of the two uniform spheres at points (k, 3):
     -M d / r^3 outside a sphere, -M d / R^3 inside (d = x - centre); (3, k)."""

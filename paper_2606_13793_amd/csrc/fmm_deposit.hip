@@ -7,7 +7,12 @@
 //
 // One thread per particle; the 8 shares are added with FP64 atomics, so the
 // order of the additions into a cell, and with it the last bits of a cell
-// that several particles reach, varies from run to run.
+// that several particles reach, varies from run to run.  Particles are
+// usually kept in cell order (as AMR codes keep them), and then the lanes of
+// a wave mostly share their 8 target cells: a wave first sums the shares of
+// each run of consecutive lanes with the same cells (a segmented scan over
+// the lanes), and only the last lane of a run adds them to memory.  In random
+// order the runs are single lanes and the scan costs a few shuffles.
 #include <hip/hip_runtime.h>
 
 #include "fmm_internal.h"
@@ -20,37 +25,59 @@ constexpr int CIC_THREADS = 256;
 __global__ __launch_bounds__(CIC_THREADS) void k_cic(int n, long long count, const double* __restrict__ pos,
                                                      const double* __restrict__ mass, double* __restrict__ rho) {
   const long long t = (long long)blockIdx.x * CIC_THREADS + threadIdx.x;
-  if (t >= count) return;
-  int lo[3];
-  double up[3];  // weight of the upper cell along each axis
+  const int lane = threadIdx.x & 63;
+  // every lane of a wave takes part in the shuffles; lanes past the end or
+  // whose particle reaches no cell carry a key of their own and zero shares
+  bool ok = t < count;
+  int lo[3] = {0, 0, 0};
+  double up[3] = {0.0, 0.0, 0.0};  // weight of the upper cell along each axis
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     // s = x / dx - 1/2: the cell centres below and above x are floor(s), floor(s) + 1
-    const double s = pos[3 * t + d] * n - 0.5;
-    if (!(s >= -1.0 && s < (double)n)) return;  // reaches no cell (or not a number)
-    const double f = floor(s);
+    const double s = ok ? pos[3 * t + d] * n - 0.5 : 0.0;
+    if (!(s >= -1.0 && s < (double)n)) ok = false;  // reaches no cell (or not a number)
+    const double f = ok ? floor(s) : 0.0;
     lo[d] = (int)f;
     up[d] = s - f;
   }
-  const double m = mass[t] * ((double)n * n * n);
+  const double m = ok ? mass[t] * ((double)n * n * n) : 0.0;
+  double v[8];
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    const int i = lo[0] + a;
-    if (i < 0 || i >= n) continue;
-    const double wa = a ? up[0] : 1.0 - up[0];
+  for (int c = 0; c < 8; ++c) {
+    const double wa = (c & 4) ? up[0] : 1.0 - up[0];
+    const double wb = (c & 2) ? up[1] : 1.0 - up[1];
+    const double wc = (c & 1) ? up[2] : 1.0 - up[2];
+    v[c] = ok ? m * (wa * wb * wc) : 0.0;
+  }
+  // lower corner cell, offset by one so that it is >= 0; lanes without a
+  // deposit get distinct negative keys
+  const int np = n + 2;
+  const int key = ok ? ((lo[0] + 1) * np + (lo[1] + 1)) * np + (lo[2] + 1) : -1 - lane;
+  // runs of equal keys: the lane where this lane's run starts
+  const int prev = __shfl_up(key, 1);
+  int start = (lane == 0 || prev != key) ? lane : 0;
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int j = lo[1] + b;
-      if (j < 0 || j >= n) continue;
-      const double wb = b ? up[1] : 1.0 - up[1];
+  for (int d = 1; d < 64; d <<= 1) {
+    const int o = __shfl_up(start, d);
+    if (lane >= d && o > start) start = o;
+  }
+  // inclusive sums of the shares within each run
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const int k = lo[2] + c;
-        if (k < 0 || k >= n) continue;
-        const double wc = c ? up[2] : 1.0 - up[2];
-        atomicAdd(rho + ((long long)i * n + j) * n + k, m * (wa * wb * wc));
-      }
+  for (int d = 1; d < 64; d <<= 1) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const double o = __shfl_up(v[c], d);
+      if (lane - d >= start) v[c] += o;
     }
+  }
+  const int next = __shfl_down(key, 1);
+  const bool last = lane == 63 || next != key;
+  if (!ok || !last) return;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int i = lo[0] + ((c >> 2) & 1), j = lo[1] + ((c >> 1) & 1), k = lo[2] + (c & 1);
+    if (i < 0 || i >= n || j < 0 || j >= n || k < 0 || k >= n) continue;
+    atomicAdd(rho + ((long long)i * n + j) * n + k, v[c]);
   }
 }
 

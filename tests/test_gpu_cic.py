@@ -69,6 +69,23 @@ def test_cic_many_particles_per_cell(F, orc):
     assert abs(rho.sum() / n ** 3 - want.sum() / n ** 3) <= 1e-12 * m.sum()
 
 
+def test_cic_particles_in_cell_order(F, orc):
+    """Particles sorted by cell, so the lanes of a wave share their target
+    cells and merge their shares before the atomics; with some particles
+    outside the box and repeated runs of one cell."""
+    n = 32
+    _say("case cic cell order n=32")
+    rng = np.random.default_rng(14)
+    pos = np.concatenate([rng.uniform(0.3, 0.4, (50000, 3)), rng.uniform(-0.05, 1.05, (3000, 3)),
+                          np.full((200, 3), 0.5)])
+    pos = pos[fi.cell_order(pos, n)]
+    pos = np.concatenate([pos, pos[:100], np.full((77, 3), 0.5)])  # runs that recur later
+    m = rng.uniform(0.1, 2.0, len(pos))
+    rho = F.deposit_cic(n, _dev(pos), _dev(m)).cpu().numpy()
+    want = orc.deposit_cic(n, pos, m)
+    assert np.abs(rho - want).max() <= 1e-13 * np.abs(want).max()
+
+
 def test_cic_adds_into_rho_and_skips_non_finite(F):
     import torch
     n = 16
