@@ -207,11 +207,22 @@ def run_extras(args, rho64, fi, fmm, costs,
             phi = torch.empty((n, n, n), dtype=torch.float64, device="cuda")
             g = torch.empty((3, n, n, n), dtype=torch.float64, device="cuda")
             ms = _event_ms(lambda: plan.solve_into(rho64, phi, g), 5, 2)
+            # the bottom kernel's own time (HIP events per stage) against its useful flops
+            plan.profile(True)
+            plan.profile_read()
+            for _ in range(5):
+                plan.solve_into(rho64, phi, g)
+            torch.cuda.synchronize()
+            bot_ms = plan.profile_read()["bottom"][0] / 5
+            plan.profile(False)
+            bot_tf = costs.solve_flops(n, q, nm, delta_l=2)["bottom"] / (bot_ms * 1e-3) / 1e12
             ps, _ = sampled(plan, rho64)
             key = f"p{q}" + ("" if nm is None else f"_nmax{nm}")
-            fmm2[key] = {"ms_per_solve": ms, "cells_per_s": N / (ms * 1e-3), "phi_err_vs_direct": _rel(ps, phi_d)}
+            fmm2[key] = {"ms_per_solve": ms, "cells_per_s": N / (ms * 1e-3), "phi_err_vs_direct": _rel(ps, phi_d),
+                         "bottom_ms": bot_ms, "bottom_tflops": bot_tf, "bottom_frac_of_fp64_peak": bot_tf / 78.6}
             del plan, phi, g
-            log(f"extras: fmm-2 {key}: {ms:.2f} ms, error vs direct {fmm2[key]['phi_err_vs_direct']:.3e}")
+            log(f"extras: fmm-2 {key}: {ms:.2f} ms (bottom {bot_ms:.2f} ms, {bot_tf:.1f} TF/s), "
+                f"error vs direct {fmm2[key]['phi_err_vs_direct']:.3e}")
         pc = torch.as_tensor(fi.point_charge_cic(n)).cuda()
         s1 = fmm.Plan(n, 3, "fp64", nmax=2).solve(pc, want_g=False)[0][:, :, n // 2].cpu().numpy()
         s2 = fmm.Plan(n, 3, "fp64", nmax=2, delta_l=2).solve(pc, want_g=False)[0][:, :, n // 2].cpu().numpy()

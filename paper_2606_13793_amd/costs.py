@@ -37,11 +37,13 @@ def list_pairs(m: int) -> int:
     return sa ** 3 - sb ** 3
 
 
-def near_pairs(n: int) -> int:
-    """Sum over unigrid cells of their near-field source count (incl. self)."""
-    m = n // 2
+def near_pairs(n: int, delta_l: int = 1) -> int:
+    """Sum over unigrid cells of their near-field source count (incl. self):
+    every unigrid cell of the finest FMM cells adjacent to the target's own,
+    8^delta_l of them per FMM cell."""
+    m = n >> delta_l
     sb = sum(_b(t, m) for t in range(m))
-    return 64 * sb ** 3
+    return 8 ** (2 * delta_l) * sb ** 3
 
 
 def pair_count_m2l(p: int, nmax: int | None = None) -> int:
@@ -50,11 +52,11 @@ def pair_count_m2l(p: int, nmax: int | None = None) -> int:
     return sum(comb(mb + 2, 2) * nterms(min(nmax, p - mb)) for mb in range(p + 1))
 
 
-def solve_flops(n: int, p: int, nmax: int | None = None) -> dict:
+def solve_flops(n: int, p: int, nmax: int | None = None, delta_l: int = 1) -> dict:
     """Useful flops of each stage of one solve (phi and g)."""
     nmax = p if nmax is None else nmax
     L = n.bit_length() - 1
-    F = L - 1
+    F = L - delta_l
     NM, NL = nterms(nmax), nterms(p)
     out = {}
     out["p2m"] = 2 * NM * n ** 3
@@ -64,8 +66,8 @@ def solve_flops(n: int, p: int, nmax: int | None = None) -> dict:
     out["m2m"] = sum(2 * m2m_terms * 8 ** k for k in range(3, F + 1))
     out["m2l"] = sum(2 * pair_count_m2l(p, nmax) * 8 * list_pairs(2 ** (k - 1)) for k in range(3, F + 1))
     out["l2l"] = sum(2 * pair_count_m2l(p, p) * 8 ** k for k in range(4, F + 1))
-    out["near_l2p"] = 8 * near_pairs(n) + (8 * NL * n ** 3 if F >= 3 else 0)
-    out["m2p"] = 2 * 4 * NM * 8 * list_pairs(2 ** F)
+    out["near_l2p"] = 8 * near_pairs(n, delta_l) + (8 * NL * n ** 3 if F >= 3 else 0)
+    out["m2p"] = 2 * 4 * NM * 8 ** delta_l * list_pairs(2 ** F)
     out["total"] = sum(out.values())
     # per fused kernel stage of the HIP solve
     out["m2l_l2l"] = out["m2l"] + out["l2l"]
@@ -73,6 +75,6 @@ def solve_flops(n: int, p: int, nmax: int | None = None) -> dict:
     return out
 
 
-def m2p_pairs(n: int) -> int:
+def m2p_pairs(n: int, delta_l: int = 1) -> int:
     """(unigrid target, list source) pairs of the M2P stage."""
-    return 8 * list_pairs(n // 2)
+    return 8 ** delta_l * list_pairs(n >> delta_l)

@@ -50,3 +50,19 @@ def test_near_pairs_brute_force():
                     cnt += 8
         brute += 8 * cnt
     assert costs.near_pairs(n) == brute
+
+
+@pytest.mark.parametrize("n,dl", [(16, 1), (16, 2), (32, 2)])
+def test_near_and_m2p_pairs_equal_the_oracle_partition(orc, n, dl):
+    """Summed over every target, the oracle's near-field and M2P sources
+    (FMM-1 and FMM-2) are the pair counts the model gives."""
+    import numpy as np
+    F = int(np.log2(n)) - dl
+    near = m2p = 0
+    for u in range(n ** 3):
+        row = orc.pair_pass_row(n, u, delta_l=dl)
+        near += int((row == -1).sum())
+        m2p += int((row == F).sum())
+    assert costs.near_pairs(n, dl) == near
+    # the oracle reports unigrid sources; an M2P source is a finest FMM cell of 8^dl of them
+    assert costs.m2p_pairs(n, dl) * 8 ** dl == m2p
