@@ -156,7 +156,8 @@ def two_spheres_potential(points) -> np.ndarray:
 
 def cell_order(pos, n: int) -> np.ndarray:
     """Permutation that puts particles in cell order on an n^3 grid (by the
-    cell below-left of each, C order), the order AMR codes keep them in."""
+    cell below-left of each, C order, for particles inside the box), the
+    order AMR codes keep them in."""
     lo = np.floor(np.asarray(pos) * n - 0.5).astype(np.int64) + 1
     key = (lo[:, 0] * (n + 2) + lo[:, 1]) * (n + 2) + lo[:, 2]
     return np.argsort(key, kind="stable")
