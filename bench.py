@@ -35,12 +35,12 @@ PROFILE = os.path.join(ROOT, "profiles", "k_bottom_256cubed_p6_fp64.md")
 KERNEL_SOURCES = ["fmm_impl.h", "fmm_mfma.h", "fmm_internal.h"]
 
 
-def profiled_traffic(n: int, p: int, prec: str):
+def profiled_traffic(n: int, p: int, prec: str, delta_l: int = 1):
     """HBM bytes per launch of the bottom kernel from the committed rocprofv3
     byte-counter summary, or None when it does not describe the current
     kernel sources or this workload."""
     import hashlib
-    if (n, p, prec) != (256, 6, "fp64") or not os.path.exists(PROFILE):
+    if (n, p, prec, delta_l) != (256, 6, "fp64", 1) or not os.path.exists(PROFILE):
         return None
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--p", type=int, default=6)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--delta-l", type=int, default=1, choices=[1, 2],
+                    help="levels between the finest FMM level and the unigrid (2 = FMM-2)")
     ap.add_argument("--spheres", type=int, default=256)
     ap.add_argument("--seed", type=int, default=256)
     ap.add_argument("--cpu-planes", type=int, default=16,
@@ -393,9 +395,9 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a HIP device")
 
-    n, p, prec = args.n, args.p, args.precision
+    n, p, prec, dl = args.n, args.p, args.precision, args.delta_l
     dev = "cuda"
-    log(f"workload n={n} p={p} precision={prec} spheres={args.spheres} seed={args.seed}")
+    log(f"workload n={n} p={p} precision={prec} delta_l={dl} spheres={args.spheres} seed={args.seed}")
     params = fi.multi_plummer_params(args.spheres, args.seed)
     rho64 = fi.plummer_density(n, params, device=dev)
     torch.cuda.synchronize()
@@ -403,7 +405,7 @@ def main():
         res = run_extras(args, rho64, fi, fmm, costs, sections=(args.section,))
         print(json.dumps({"section": args.section, "config": {"n": n, "p": p}, **res}), flush=True)
         return
-    plan = fmm.Plan(n, p, prec)
+    plan = fmm.Plan(n, p, prec, delta_l=dl)
     rho = rho64 if prec == "fp64" else rho64.float()
     phi = torch.empty((n, n, n), dtype=plan.io_dtype, device=dev)
     g = torch.empty((3, n, n, n), dtype=plan.io_dtype, device=dev)
@@ -448,7 +450,7 @@ def main():
               "max_ms": float(per.max())}
     log(f"single solves: median {spread['median_ms']:.3f} ms, mean {spread['mean_ms']:.3f} +- {spread['std_ms']:.3f} ms")
 
-    flops = costs.solve_flops(n, p)
+    flops = costs.solve_flops(n, p, delta_l=dl)
     stage_flops = {"p2m": flops["p2m"], "m2m": flops["m2m"], "m2l": flops["m2l"], "bottom": flops["bottom"]}
     stages = {}
     for name, (ms, launches) in prof.items():
@@ -467,11 +469,11 @@ def main():
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": round(bot_tflops / peak, 4),
-        "traffic": profiled_traffic(n, p, prec),
+        "traffic": profiled_traffic(n, p, prec, dl),
         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "avg_launch_ms": round(bot_avg_s * 1e3, 4),
         "flops_per_launch": stage_flops["bottom"],
-        "m2p_pairs_per_launch": costs.m2p_pairs(n),
+        "m2p_pairs_per_launch": costs.m2p_pairs(n, dl),
     }
     m2l_ms, m2l_launches = prof["m2l"]
     solve_tflops = flops["total"] / (elapsed / args.steps) / 1e12
@@ -493,7 +495,7 @@ def main():
         cells = np.arange(i0 * n * n, (i0 + planes) * n * n, dtype=np.int64)
         log(f"cpu baseline: oracle upward pass + downward on {planes} planes ({len(cells)} cells)")
         rho_host = rho64.cpu().numpy() if prec == "fp64" else rho.double().cpu().numpy()
-        phi_o, g_o, t_up, t_down, threads = oracle.solve_timed(rho_host, p, cells)
+        phi_o, g_o, t_up, t_down, threads = oracle.solve_timed(rho_host, p, cells, delta_l=dl)
         t_full = t_up + t_down * (n ** 3 / len(cells))
         cpu_model = "unknown CPU"
         try:
@@ -525,7 +527,7 @@ def main():
         log(f"parity on the slab: {parity}")
 
     extras = {}
-    if not args.no_extras and prec == "fp64":
+    if not args.no_extras and prec == "fp64" and dl == 1:
         del plan, phi, g
         torch.cuda.empty_cache()
         extras = run_extras(args, rho64, fi, fmm, costs)
@@ -544,9 +546,10 @@ def main():
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[prec],
         "data": "synthetic",
         "config": {
-            "workload": f"{n}^3 unigrid FMM solve, isolated BC, p={p}, {prec}, phi+g, "
-                        f"{args.spheres}-sphere multi-Plummer density (seed {args.seed})",
-            "n": n, "p": p, "precision": prec, "spheres": args.spheres, "seed": args.seed,
+            "workload": (f"{n}^3 unigrid FMM solve, isolated BC, p={p}, {prec}, phi+g, "
+                         + ("" if dl == 1 else "FMM-2 (finest FMM level two above the unigrid), ")
+                         + f"{args.spheres}-sphere multi-Plummer density (seed {args.seed})"),
+            "n": n, "p": p, "precision": prec, "delta_l": dl, "spheres": args.spheres, "seed": args.seed,
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

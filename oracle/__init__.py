@@ -60,6 +60,8 @@ def lib():
         L.or_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
         L.or_solve_timed.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
                                      ctypes.c_longlong, _lp, _dp, _dp, _dp]
+        L.or_solve_timed_dl.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
+                                        ctypes.c_longlong, _lp, _dp, _dp, _dp]
         L.or_threads.argtypes = []
         L.or_pair_pass.argtypes = [ctypes.c_int, ctypes.c_longlong, ctypes.c_longlong]
         L.or_list_size.argtypes = [ctypes.c_int] * 4
@@ -224,7 +226,7 @@ def pair_pass_row(n: int, u: int, delta_l: int = 1) -> np.ndarray:
     return out
 
 
-def solve_timed(rho, p: int, targets, nmax: int | None = None):
+def solve_timed(rho, p: int, targets, nmax: int | None = None, delta_l: int = 1):
     """solve() at the listed targets, plus (upward s, downward s, threads)."""
     rho = _f64(rho)
     n = rho.shape[0]
@@ -233,7 +235,8 @@ def solve_timed(rho, p: int, targets, nmax: int | None = None):
     phi = np.zeros(len(t))
     g = np.zeros((3, len(t)))
     times = np.zeros(2)
-    rc = lib().or_solve_timed(n, p, nmax, _d(rho), len(t), t.ctypes.data_as(_lp), _d(phi), _d(g), _d(times))
+    rc = lib().or_solve_timed_dl(n, p, nmax, delta_l, _d(rho), len(t), t.ctypes.data_as(_lp), _d(phi), _d(g),
+                                 _d(times))
     if rc != 0:
         raise ValueError("bad arguments")
     return phi, g, float(times[0]), float(times[1]), int(lib().or_threads())

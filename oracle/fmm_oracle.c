@@ -603,6 +603,12 @@ int or_solve_timed(int n, int p, int nmax, const double *rho, i64 ntarget, const
   return solve_impl(n, p, nmax, 1, rho, ntarget, targets, phi, g, times);
 }
 
+/* or_solve_timed with the finest FMM level dl levels above the unigrid. */
+int or_solve_timed_dl(int n, int p, int nmax, int dl, const double *rho, i64 ntarget, const i64 *targets,
+                      double *phi, double *g, double *times) {
+  return solve_impl(n, p, nmax, dl, rho, ntarget, targets, phi, g, times);
+}
+
 /* OpenMP threads the oracle runs with. */
 int or_threads(void) {
 #ifdef _OPENMP
