@@ -79,6 +79,18 @@ typedef struct {
                                for 2) */
   int check_finite;         /* nonzero: fmm_solve scans rho for NaN/Inf first (single-field plans) */
   int autotune;             /* batch plans: time the launch-shape candidates at creation; default 1 */
+  int bottom_tile;          /* depth (level-F cells along z) of the bottom kernel's tiles: 0 = chosen
+                               by the plan (default: 16, or 8 where 16-deep tiles would leave
+                               compute units idle, or the autotuner's choice), 8 or 16 to force one
+                               (delta_l = 2 plans take 16 only).  Results do not depend on it
+                               beyond rounding order. */
+  const char* autotune_cache; /* batch plans with autotune: path of a text file that remembers the
+                               autotuner's choice per (GPU architecture, compute units, field sizes,
+                               p, nmax, precision, delta_l, coarse_fp64_levels).  A plan whose key is
+                               in the file takes that choice without timing; otherwise it times the
+                               candidates and appends a line.  NULL (default) = always time.  A file
+                               that cannot be read is treated as empty; one that cannot be written
+                               is left alone (the plan is still created). */
 } fmm_options;
 
 /* Fill *opt with the defaults above.  Returns FMM_OK or FMM_ERR_INVALID_ARG. */
@@ -140,8 +152,10 @@ int fmm_solve_backward(fmm_plan* plan, const void* dphi, const void* dg, void* d
  * fmm_batch_info: field count, the chosen bottom tile depth and M2L grouping
  *   (0 wide, 1 narrow), and the autotuner's mean milliseconds per candidate
  *   in the order (16, wide), (16, narrow), (8, wide), (8, narrow) for the
- *   first ncand entries of tune_ms (zeros without autotuning).  Any pointer
- *   may be NULL.
+ *   first ncand entries of tune_ms (zeros without autotuning, and for the
+ *   candidates a delta_l = 2 plan or a forced bottom_tile rules out; the
+ *   cached figures when the choice came from opt->autotune_cache).  Any
+ *   pointer may be NULL.
  */
 fmm_plan* fmm_batch_plan_create(int count, const int* n, int p, int isolated, const fmm_options* opt);
 int fmm_batch_solve(fmm_plan* plan, const void* const* rho, void* const* phi, void* const* g, void* stream);

@@ -62,6 +62,10 @@ int validate(int n, int p, int isolated, const fmm_options* o) {
       return fail(FMM_ERR_UNSUPPORTED, "delta_l must be 1 or 2 (got %d)", o->delta_l);
     if (o->delta_l == 2 && L < 4) return fail(FMM_ERR_INVALID_ARG, "delta_l = 2 needs n >= 16 (got %d)", n);
     if (o->coarse_fp64_levels < 0) return fail(FMM_ERR_INVALID_ARG, "coarse_fp64_levels must be >= 0");
+    if (o->bottom_tile != 0 && o->bottom_tile != 8 && o->bottom_tile != 16)
+      return fail(FMM_ERR_INVALID_ARG, "bottom_tile must be 0, 8 or 16 (got %d)", o->bottom_tile);
+    if (o->delta_l == 2 && o->bottom_tile == 8)
+      return fail(FMM_ERR_INVALID_ARG, "delta_l = 2 plans run 16-deep bottom tiles (bottom_tile = 8 given)");
   }
   return FMM_OK;
 }
@@ -86,6 +90,17 @@ size_t plan_bytes(const std::vector<int>& ns, int p, int dl) {
     }
   }
   return b;
+}
+
+// Frees a plan-owned backward workspace (NULL-safe per buffer) and resets it.
+void release_adj(fmm::AdjWs& w) {
+  if (w.ybar) (void)hipFree(w.ybar);
+  for (auto a : w.abar)
+    if (a) (void)hipFree(a);
+  if (w.part) (void)hipFree(w.part);
+  for (fmm::SegTable* st : {&w.m2lt[0], &w.m2lt[1], &w.m2pt, &w.m2lt_red})
+    if (st->dev) (void)hipFree(st->dev);
+  w = fmm::AdjWs{};
 }
 
 void release(fmm_plan* pl) {
@@ -113,15 +128,12 @@ void release(fmm_plan* pl) {
   for (auto& st : pl->s_l2l) free_st(st);
   for (auto& a : pl->s_bot)
     for (auto& st : a) free_st(st);
-  for (auto& st : pl->s_m2lt) free_st(st);
   for (auto& st : pl->s_red) free_st(st);
-  free_st(pl->s_m2lt_red);
-  if (pl->adj_part) (void)hipFree(pl->adj_part);
+  release_adj(pl->adj);
   if (pl->conv_part) (void)hipFree(pl->conv_part);
   for (auto& row : pl->tiletab)
     for (auto t : row)
       if (t) (void)hipFree(t);
-  free_st(pl->s_m2pt);
   if (pl->io) (void)hipFree(pl->io);
   if (pl->dtab) (void)hipFree(pl->dtab);
   if (pl->dtab2) (void)hipFree(pl->dtab2);
@@ -137,9 +149,6 @@ void release(fmm_plan* pl) {
     if (pl->wt_m2l[x]) (void)hipFree(pl->wt_m2l[x]);
     if (pl->wt_m2p[x]) (void)hipFree(pl->wt_m2p[x]);
   }
-  if (pl->ybar) (void)hipFree(pl->ybar);
-  for (auto a : pl->abar)
-    if (a) (void)hipFree(a);
   if (pl->adj_l2p) (void)hipFree(pl->adj_l2p);
   if (pl->adj_l2p2) (void)hipFree(pl->adj_l2p2);
   if (pl->m2m_start) (void)hipFree(pl->m2m_start);
@@ -242,8 +251,9 @@ StageScope::~StageScope() {
 hipError_t upload_constants(int p) { FMM_BY_ORDER(p, upload_constants()) }
 hipError_t launch_tables(fmm_plan* pl, hipStream_t s) { FMM_BY_ORDER(pl->p, tables(pl, s)) }
 hipError_t launch_solve(fmm_plan* pl, IoArg io, hipStream_t s) { FMM_BY_ORDER(pl->p, solve(pl, io, s)) }
-hipError_t launch_backward(fmm_plan* pl, const void* dphi, const void* dg, void* drho, hipStream_t s) {
-  FMM_BY_ORDER(pl->p, backward(pl, dphi, dg, drho, s))
+hipError_t launch_backward(fmm_plan* pl, const AdjWs& w, const void* dphi, const void* dg, void* drho,
+                           hipStream_t s) {
+  FMM_BY_ORDER(pl->p, backward(pl, w, dphi, dg, drho, s))
 }
 hipError_t launch_adjoint_tables(fmm_plan* pl, hipStream_t s) { FMM_BY_ORDER(pl->p, adjoint_tables(pl, s)) }
 hipError_t launch_check_finite(fmm_plan* pl, const void* rho, int* host_flag, hipStream_t s) {
@@ -413,6 +423,120 @@ int build_schedule(fmm_plan* pl) {
 }
 }  // namespace fmm
 
+namespace {
+
+// Splits of the transposed M2L's offset sums at target level k: a level
+// with fewer tiles than about one per compute unit shares each tile among
+// several blocks, so its heavy first column group does not leave units idle.
+int adj_split(int k) {
+  const int n = 1 << (k - 1);
+  const long long T = cdiv(n, kConvTile) * cdiv(n, kConvTile) * cdiv(n, kConvTileZ);
+  return T >= 256 ? 1 : (int)std::min<long long>(16, std::max<long long>(2, 256 / T));
+}
+
+// Bytes of each backward-workspace buffer of a plan.
+struct AdjLayout {
+  size_t ybar = 0;
+  size_t abar[16] = {};
+};
+AdjLayout adj_layout(const fmm_plan* pl) {
+  AdjLayout l;
+  const size_t nFp = (size_t)(pl->n >> pl->dl) + 6;
+  l.ybar = ((size_t)8 << (3 * (pl->dl - 1))) * nFp * nFp * nFp * 4 * sizeof(double);
+  for (int k = 3; k <= pl->F; ++k) {
+    const size_t np = ((size_t)1 << (k - 1)) + 6;
+    l.abar[k] = (size_t)fmm::loc_stride(pl->p) * np * np * np * sizeof(double);
+  }
+  return l;
+}
+
+// Doubles of the split transposed M2L's partial sums (every level passes
+// through them and is then summed, or copied when not split).
+long long adj_part_doubles(const fmm_plan* pl) {
+  long long d = 0;
+  for (int k = 3; k <= pl->F; ++k) {
+    const long long np = (1LL << (k - 1)) + 6;
+    d += (long long)adj_split(k) * pl->NC * np * np * np * 4;
+  }
+  return d;
+}
+
+// A segment list of fixed capacity (built without allocating).
+struct SegArr {
+  fmm::Seg v[fmm::kMaxAdjSegs];
+  int n = 0;
+  long long blocks = 0;
+  void add(fmm::Seg sg, long long nb) {
+    sg.first_block = (int)blocks;
+    blocks += nb;
+    v[n++] = sg;
+  }
+};
+struct AdjSegs {
+  SegArr lt[2], pt, ltr;
+};
+
+// Segments of the transposed convolutions over workspace w: M2L^T rows are
+// the sources of every target level (the finest first, so its long blocks
+// start first; FP64 levels and low-precision levels in separate launches),
+// M2P^T rows the level-F cells.  With w.part every level writes partial sums
+// there and the reductions add them into the multipole grids in a fixed
+// order; without it every level writes its adjoint multipoles in place.
+AdjSegs adj_segments(const fmm_plan* pl, const fmm::AdjWs& w) {
+  AdjSegs a;
+  const int klow = fmm::m2l_low_from(pl), nF = pl->n >> pl->dl;
+  long long at = 0;
+  for (int k = pl->F; k >= 3; --k) {
+    const int S = w.part ? adj_split(k) : 1;
+    fmm::Seg c{};
+    c.n = 1 << (k - 1);
+    c.tpa = (int)cdiv(c.n, kConvTile);
+    c.tz = (int)cdiv(c.n, kConvTileZ);
+    c.split = S;
+    c.a = w.abar[k];
+    if (w.part) {
+      const long long cnt = (long long)pl->NC * (c.n + 6) * (c.n + 6) * (c.n + 6) * 4;
+      c.b = w.part + at;
+      fmm::Seg r{};
+      r.split = S;
+      r.count = cnt;
+      r.a = w.part + at;
+      r.b = (double*)pl->lev[k - 1].M;
+      a.ltr.add(r, cdiv(cnt, 256));
+      at += S * cnt;
+    } else {
+      c.b = (double*)pl->lev[k - 1].M;
+    }
+    a.lt[k >= klow ? 1 : 0].add(c, (long long)c.tpa * c.tpa * c.tz * S);
+  }
+  fmm::Seg c{};
+  c.n = nF;
+  c.tpa = (int)cdiv(nF, kConvTile);
+  c.tz = (int)cdiv(nF, kConvTileZ);
+  c.split = 1;
+  c.a = w.ybar;
+  c.b = (double*)pl->lev[pl->F].M;
+  a.pt.add(c, (long long)c.tpa * c.tpa * c.tz);
+  return a;
+}
+
+int upload_arr(fmm_plan* pl, fmm::SegTable& st, const SegArr& l) {
+  st = fmm::SegTable{};
+  if (!l.n) return FMM_OK;
+  if (dev_alloc(pl, (void**)&st.dev, l.n * sizeof(fmm::Seg))) return FMM_ERR_OUT_OF_MEMORY;
+  if (hipMemcpy(st.dev, l.v, l.n * sizeof(fmm::Seg), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FMM_ERR_DEVICE, "segment upload failed");
+  }
+  st.nseg = l.n;
+  st.blocks = (int)l.blocks;
+  return FMM_OK;
+}
+
+static_assert(fmm::kMaxAdjSegs * 4 * sizeof(fmm::Seg) <= fmm::kNoallocSegBytes, "segment area too small");
+
+}  // namespace
+
 extern "C" {
 
 int fmm_options_default(fmm_options* opt) {
@@ -425,6 +549,8 @@ int fmm_options_default(fmm_options* opt) {
   opt->delta_l = 1;
   opt->check_finite = 0;
   opt->autotune = 1;
+  opt->bottom_tile = 0;
+  opt->autotune_cache = nullptr;
   return ok();
 }
 
@@ -464,6 +590,7 @@ fmm_plan* create_plan(const std::vector<int>& ns, int p, const fmm_options& o, i
   pl->precision = o.precision;
   pl->coarse_fp64_levels = o.coarse_fp64_levels;
   pl->check_finite = o.check_finite;
+  pl->force_bz = o.bottom_tile;
   pl->device = dev;
   {
     int cus = 0;
@@ -648,6 +775,20 @@ fmm_plan* create_plan(const std::vector<int>& ns, int p, const fmm_options& o, i
          hipGetErrorString(e));
     return bail();
   }
+  if (!batch && pl->dl == 1) {
+    // the backward pass's tables: coefficients of the transposed L2P steps
+    // and the transposed convolutions' B fragments
+    if (dev_alloc(pl, (void**)&pl->adj_l2p, (size_t)pl->NL * 32 * sizeof(double)) ||
+        dev_alloc(pl, (void**)&pl->adj_l2p2, (size_t)8 * pl->NL * 32 * sizeof(double)))
+      return bail();
+    if ((e = fmm::launch_adjoint_tables(pl, nullptr)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
+      (void)hipGetLastError();
+      fail(e == hipErrorOutOfMemory ? FMM_ERR_OUT_OF_MEMORY : FMM_ERR_DEVICE, "adjoint tables: %s",
+           hipGetErrorString(e));
+      return bail();
+    }
+    pl->adj_tables = 1;
+  }
   if (batch) {
     if (dev_alloc(pl, (void**)&pl->io, ns.size() * sizeof(fmm::Io))) return bail();
     if ((e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
@@ -676,9 +817,67 @@ int set_io(fmm_plan* pl, const std::vector<fmm::Io>& io) {
   return FMM_OK;
 }
 
+// Key of a batch plan in the autotune cache: everything the launch shapes'
+// speed depends on (device, field sizes in order, order, truncation,
+// precision policy, level offset).  No whitespace inside.
+std::string tune_key(const fmm_plan* pl) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, pl->device) == hipSuccess) arch = prop.gcnArchName;
+  (void)hipGetLastError();
+  for (char& c : arch)
+    if (c == ' ' || c == '\t') c = '_';
+  std::string k = arch + "/cu" + std::to_string(pl->cus) + "/p" + std::to_string(pl->p) + "/nmax" +
+                  std::to_string(pl->nmax) + "/prec" + std::to_string(pl->precision) + "/dl" + std::to_string(pl->dl) +
+                  "/kc" + std::to_string(pl->coarse_fp64_levels) + "/n";
+  for (size_t f = 0; f < pl->fld.size(); ++f) k += (f ? "," : "") + std::to_string(pl->fld[f].n);
+  return k;
+}
+
+// Cache lines are "<key> <bottom tile> <grouping> <ms> <ms> <ms> <ms>"; the
+// last line with the key wins.  Returns true and fills the choice if found.
+bool tune_cache_lookup(const char* path, const std::string& key, fmm::Tuning* t, std::vector<double>* ms) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+  std::fclose(f);
+  bool found = false;
+  size_t pos = 0;
+  while (pos < text.size()) {
+    size_t end = text.find('\n', pos);
+    if (end == std::string::npos) end = text.size();
+    const std::string line = text.substr(pos, end - pos);
+    pos = end + 1;
+    const size_t sp = line.find(' ');
+    if (sp != key.size() || line.compare(0, sp, key) != 0) continue;
+    int bz = 0, grp = -1;
+    double m[4] = {0, 0, 0, 0};
+    if (std::sscanf(line.c_str() + sp, "%d %d %lf %lf %lf %lf", &bz, &grp, &m[0], &m[1], &m[2], &m[3]) == 6 &&
+        (bz == 8 || bz == 16) && (grp == 0 || grp == 1)) {
+      t->bz = bz;
+      t->grp = grp;
+      ms->assign(m, m + 4);
+      found = true;
+    }
+  }
+  return found;
+}
+
+void tune_cache_store(const char* path, const std::string& key, const fmm::Tuning& t, const std::vector<double>& ms) {
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d %.6f %.6f %.6f %.6f\n", key.c_str(), t.bz, t.grp, ms[0], ms[1], ms[2], ms[3]);
+  std::fclose(f);
+}
+
 // Launch-shape autotuner of batch plans: every candidate (bottom tile depth,
 // M2L column grouping) solves the batch on zero densities, the fastest mean
-// of three timed solves wins.
+// of three timed solves wins.  Candidates that cannot differ are skipped
+// (FMM-2 and a forced tile depth fix the bottom tile); their slots in
+// tune_ms stay 0.
 int autotune(fmm_plan* pl) {
   const size_t esz = pl->precision == 0 ? sizeof(double) : sizeof(float);
   std::vector<void*> bufs;
@@ -709,6 +908,7 @@ int autotune(fmm_plan* pl) {
     return rc;
   }
   const fmm::Tuning cand[4] = {{16, 0}, {16, 1}, {8, 0}, {8, 1}};
+  const int fixed_bz = pl->dl == 2 ? 16 : pl->force_bz;
   hipEvent_t a = nullptr, b = nullptr;
   (void)hipEventCreate(&a);
   (void)hipEventCreate(&b);
@@ -717,9 +917,10 @@ int autotune(fmm_plan* pl) {
   pl->profiling = 0;
   pl->tune_ms.assign(4, 0.0);
   double best = 1e300;
-  fmm::Tuning pick = cand[0];
+  fmm::Tuning pick = cand[fixed_bz == 8 ? 2 : 0];
   hipError_t e = hipSuccess;
   for (int c = 0; c < 4 && e == hipSuccess; ++c) {
+    if (fixed_bz && cand[c].bz != fixed_bz) continue;
     pl->tune = cand[c];
     e = fmm::launch_solve(pl, arg, pl->cap_stream);
     if (e == hipSuccess) e = hipEventRecord(a, pl->cap_stream);
@@ -780,12 +981,22 @@ fmm_plan* fmm_batch_plan_create(int count, const int* n, int p, int isolated, co
   }
   fmm_plan* pl = create_plan(std::vector<int>(n, n + count), p, o, 1);
   if (!pl) return nullptr;
-  if (o.autotune && autotune(pl) != FMM_OK) {
-    const std::string msg = g_err;
-    const int code = g_status;
-    release(pl);
-    fail(code, "%s", msg.c_str());
-    return nullptr;
+  if (pl->dl == 2 || pl->force_bz) pl->tune.bz = pl->dl == 2 ? 16 : pl->force_bz;
+  if (o.autotune) {
+    const std::string key = o.autotune_cache ? tune_key(pl) : std::string();
+    if (o.autotune_cache && tune_cache_lookup(o.autotune_cache, key, &pl->tune, &pl->tune_ms)) {
+      pl->tune_cached = 1;
+      if (pl->dl == 2 || pl->force_bz) pl->tune.bz = pl->dl == 2 ? 16 : pl->force_bz;
+    } else {
+      if (autotune(pl) != FMM_OK) {
+        const std::string msg = g_err;
+        const int code = g_status;
+        release(pl);
+        fail(code, "%s", msg.c_str());
+        return nullptr;
+      }
+      if (o.autotune_cache) tune_cache_store(o.autotune_cache, key, pl->tune, pl->tune_ms);
+    }
   }
   ok();
   return pl;
@@ -891,105 +1102,60 @@ int fmm_solve(fmm_plan* plan, const void* rho, void* phi, void* g, void* stream)
   return ok();
 }
 
-// Adjoint workspace: the scaled adjoint outputs of the level-F cells and one
-// adjoint-local grid per level 3..F (zeroed once: their margins and padding
-// columns are never written).  The adjoint multipoles reuse the plan's
-// multipole grids.  Allocated by the first backward call of a plan.
-static int ensure_adjoint(fmm_plan* pl, hipStream_t s) {
+// Workspace of a plan's backward pass: the scaled adjoint outputs of the
+// level-F cells, one adjoint-local grid per level 3..F and the split
+// transposed M2L's partial sums, all zeroed once (their margins and padding
+// columns are never written); the adjoint multipoles reuse the plan's
+// multipole grids.  Allocated by the first fmm_solve_backward call; on
+// failure nothing stays allocated.
+static int ensure_adjoint(fmm_plan* pl) {
   if (pl->adj_ready) return FMM_OK;
-  const int nF = pl->n / 2, RS = fmm::loc_stride(pl->p);
-  const size_t yb = (size_t)8 * (nF + 6) * (nF + 6) * (nF + 6) * 4 * sizeof(double);
-  if (dev_alloc(pl, (void**)&pl->ybar, yb)) return FMM_ERR_OUT_OF_MEMORY;
-  if (hipMemset(pl->ybar, 0, yb) != hipSuccess) return fail(FMM_ERR_DEVICE, "hipMemset failed");
-  for (int k = 3; k <= pl->F; ++k) {
-    const size_t np = ((size_t)1 << (k - 1)) + 6;
-    const size_t ab = (size_t)RS * np * np * np * sizeof(double);
-    if (dev_alloc(pl, (void**)&pl->abar[k], ab)) return FMM_ERR_OUT_OF_MEMORY;
-    if (hipMemset(pl->abar[k], 0, ab) != hipSuccess) return fail(FMM_ERR_DEVICE, "hipMemset failed");
-  }
-  {
-    // segment tables of the transposed convolutions: M2L^T rows are the
-    // sources of every target level, M2P^T rows the level-F cells.
-    // The transposed M2L's first column group needs every K chunk (the
-    // degree-0 multipole term couples to all local terms), and its blocks do
-    // the same work at every level.  A level with fewer tiles than about one
-    // per compute unit splits each tile's offset sum over several blocks;
-    // the partial adjoint multipoles are added afterwards in a fixed order
-    // (a level that is not split is copied).  The finest level comes first,
-    // so its long blocks start first.
-    const int klow = fmm::m2l_low_from(pl);
-    auto adj_split = [&](int k) {
-      const int n = 1 << (k - 1);
-      const long long T = cdiv(n, kConvTile) * cdiv(n, kConvTile) * cdiv(n, kConvTileZ);
-      return T >= 256 ? 1 : (int)std::min<long long>(16, std::max<long long>(2, 256 / T));
-    };
-    long long part_doubles = 0;
-    for (int k = 3; k <= pl->F; ++k) {
-      const long long np = (1LL << (k - 1)) + 6;
-      part_doubles += (long long)adj_split(k) * pl->NC * np * np * np * 4;
-    }
-    if (dev_alloc(pl, (void**)&pl->adj_part, (size_t)part_doubles * sizeof(double))) return FMM_ERR_OUT_OF_MEMORY;
-    // zero once: margins and unused chunk slots are never written, and the
-    // reduction stores the whole padded grid (which the forward solve reads)
-    if (hipMemset(pl->adj_part, 0, (size_t)part_doubles * sizeof(double)) != hipSuccess)
+  fmm::AdjWs w;
+  const size_t bytes0 = pl->bytes;
+  auto bail = [&](int rc) {
+    release_adj(w);
+    pl->bytes = bytes0;
+    return rc;
+  };
+  auto zalloc = [&](double** ptr, size_t bytes) -> int {
+    if (dev_alloc(pl, (void**)ptr, bytes)) return FMM_ERR_OUT_OF_MEMORY;
+    if (hipMemset(*ptr, 0, bytes) != hipSuccess) {
+      (void)hipGetLastError();
       return fail(FMM_ERR_DEVICE, "hipMemset failed");
-    SegList lt[2], pt, ltr;
-    long long at = 0;
-    for (int k = pl->F; k >= 3; --k) {
-      const int S = adj_split(k);
-      fmm::Seg c{};
-      c.n = 1 << (k - 1);
-      c.tpa = (int)cdiv(c.n, kConvTile);
-      c.tz = (int)cdiv(c.n, kConvTileZ);
-      c.split = S;
-      c.a = pl->abar[k];
-      c.b = pl->adj_part + at;
-      lt[k >= klow ? 1 : 0].add(c, (long long)c.tpa * c.tpa * c.tz * S);
-      const long long cnt = (long long)pl->NC * (c.n + 6) * (c.n + 6) * (c.n + 6) * 4;
-      fmm::Seg r{};
-      r.split = S;
-      r.count = cnt;
-      r.a = pl->adj_part + at;
-      r.b = (double*)pl->lev[k - 1].M;
-      ltr.add(r, cdiv(cnt, 256));
-      at += S * cnt;
     }
-    fmm::Seg c{};
-    c.n = nF;
-    c.tpa = (int)cdiv(nF, kConvTile);
-    c.tz = (int)cdiv(nF, kConvTileZ);
-    c.split = 1;
-    c.a = pl->ybar;
-    c.b = (double*)pl->lev[pl->F].M;
-    pt.add(c, (long long)c.tpa * c.tpa * c.tz);
-    int rc;
-    if ((rc = upload_segs(pl, pl->s_m2lt[0], lt[0])) || (rc = upload_segs(pl, pl->s_m2lt[1], lt[1])) ||
-        (rc = upload_segs(pl, pl->s_m2pt, pt)) || (rc = upload_segs(pl, pl->s_m2lt_red, ltr)))
-      return rc;
-  }
-  if (dev_alloc(pl, (void**)&pl->adj_l2p, (size_t)pl->NL * 32 * sizeof(double))) return FMM_ERR_OUT_OF_MEMORY;
-  if (dev_alloc(pl, (void**)&pl->adj_l2p2, (size_t)8 * pl->NL * 32 * sizeof(double))) return FMM_ERR_OUT_OF_MEMORY;
-  hipError_t e = fmm::launch_adjoint_tables(pl, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(e == hipErrorOutOfMemory ? FMM_ERR_OUT_OF_MEMORY : FMM_ERR_DEVICE, "adjoint tables: %s",
-                hipGetErrorString(e));
-  }
+    return FMM_OK;
+  };
+  const AdjLayout lay = adj_layout(pl);
+  int rc;
+  if ((rc = zalloc(&w.ybar, lay.ybar))) return bail(rc);
+  for (int k = 3; k <= pl->F; ++k)
+    if ((rc = zalloc(&w.abar[k], lay.abar[k]))) return bail(rc);
+  if ((rc = zalloc(&w.part, (size_t)adj_part_doubles(pl) * sizeof(double)))) return bail(rc);
+  const AdjSegs sg = adj_segments(pl, w);
+  if ((rc = upload_arr(pl, w.m2lt[0], sg.lt[0])) || (rc = upload_arr(pl, w.m2lt[1], sg.lt[1])) ||
+      (rc = upload_arr(pl, w.m2pt, sg.pt)) || (rc = upload_arr(pl, w.m2lt_red, sg.ltr)))
+    return bail(rc);
+  pl->adj = w;
   pl->adj_ready = 1;
   return FMM_OK;
 }
 
-int fmm_solve_backward(fmm_plan* plan, const void* dphi, const void* dg, void* drho, void* stream) {
+// Argument checks shared by both backward entry points.
+static int check_backward_args(fmm_plan* plan, const void* dphi, const void* dg, void* drho) {
   if (!plan) return fail(FMM_ERR_INVALID_ARG, "plan is NULL");
   if (plan->batch) return fail(FMM_ERR_UNSUPPORTED, "the backward pass is provided for single-field plans");
   if (plan->dl != 1) return fail(FMM_ERR_UNSUPPORTED, "the backward pass is provided for delta_l = 1 plans");
   if (!dphi || !drho) return fail(FMM_ERR_INVALID_ARG, "dphi and drho must be device pointers (got NULL)");
   if (drho == dphi || (dg && (dg == drho || dg == dphi))) return fail(FMM_ERR_INVALID_ARG, "buffers must not alias");
-  if (int rc = ensure_adjoint(plan, (hipStream_t)stream)) return rc;
+  if (!plan->adj_tables) return fail(FMM_ERR_DEVICE, "the plan's backward tables were not built");
+  return FMM_OK;
+}
+
+int fmm_solve_backward(fmm_plan* plan, const void* dphi, const void* dg, void* drho, void* stream) {
+  if (int rc = check_backward_args(plan, dphi, dg, drho)) return rc;
+  if (int rc = ensure_adjoint(plan)) return rc;
   fmm::StageScope whole(plan, fmm::ST_BACKWARD, 0, (hipStream_t)stream);
-  hipError_t e = fmm::launch_backward(plan, dphi, dg, drho, (hipStream_t)stream);
-  if (e == hipErrorNotSupported) return fail(FMM_ERR_UNSUPPORTED, "backward pass is not built for this plan");
+  hipError_t e = fmm::launch_backward(plan, plan->adj, dphi, dg, drho, (hipStream_t)stream);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(FMM_ERR_DEVICE, "backward launch failed: %s", hipGetErrorString(e));

@@ -1065,6 +1065,7 @@ hipError_t launch_bottom(fmm_plan* pl, int x, IoArg io, hipStream_t s) {
   // coarse fields of a mixed-precision batch)
   int z = pl->tune.bz == 8 ? 1 : 0;
   if (z == 0 && pl->s_bot[x][0].blocks < pl->cus) z = 1;
+  if (pl->force_bz) z = pl->force_bz == 8 ? 1 : 0;  // the caller's choice
   if (pl->dl == 2) z = 0;  // FMM-2 launches 8 blocks per tile
   const SegTable& st = pl->s_bot[x][z];
   if (!st.nseg) return hipSuccess;
@@ -1137,11 +1138,15 @@ hipError_t adjoint_tables_all(fmm_plan* pl, hipStream_t s) {
   const int NL = pl->NL;
   hipLaunchKernelGGL(k_adj_coef, dim3(blocks_for(9LL * NL * 32, 256)), dim3(256), 0, s, pl->adj_l2p, pl->adj_l2p2, NL);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (pl->s_m2lt[0].nseg) {
+  // the transposed M2L of target levels k < klow runs in FP64, the others in
+  // the plan's compute type
+  const int klow = m2l_low_from(pl);
+  const bool lt64 = pl->F >= 3 && klow > 3, ltlow = pl->F >= klow;
+  if (lt64) {
     if ((e = build_conv_table<double>(pl, CV_M2LT, &pl->wt_m2l[0], s)) != hipSuccess) return e;
     if ((e = build_tile_table<double>(pl, CV_M2LT, s)) != hipSuccess) return e;
   }
-  if (pl->s_m2lt[1].nseg) {
+  if (ltlow) {
     if (pl->precision == 1 && ((e = build_conv_table<float>(pl, CV_M2LT, &pl->wt_m2l[1], s)) != hipSuccess ||
                                (e = build_tile_table<float>(pl, CV_M2LT, s)) != hipSuccess))
       return e;
@@ -1162,39 +1167,39 @@ hipError_t adjoint_tables_all(fmm_plan* pl, hipStream_t s) {
 }
 
 template <int P, typename CT, typename TI, typename TO>
-hipError_t backward_ct(fmm_plan* pl, const TI* dphi, const TI* dg, TO* drho, hipStream_t s) {
+hipError_t backward_ct(fmm_plan* pl, const AdjWs& w, const TI* dphi, const TI* dg, TO* drho, hipStream_t s) {
   constexpr int NL = nterms(P);
   const int n = pl->n, F = pl->F, nF = n / 2;
   const double dx = pl->dx;
   hipError_t e;
   const long long nT = (long long)nF * nF * nF;
-  hipLaunchKernelGGL((k_adj_seed<TI>), dim3(blocks_for(nT, 256)), dim3(256), 0, s, dphi, dg, pl->ybar, n,
+  hipLaunchKernelGGL((k_adj_seed<TI>), dim3(blocks_for(nT, 256)), dim3(256), 0, s, dphi, dg, w.ybar, n,
                      0.5 * dx * dx, -0.25 * dx);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (F >= 3) {
     // transposed L2P of the own local and of the parent level's local
     const long long nP = nT / 8;
-    hipLaunchKernelGGL(k_adj_l2p<P>, dim3(blocks_for(nP, ADJ_L2P_PAR)), dim3(ADJ_L2P_THREADS), 0, s, pl->ybar,
-                       pl->adj_l2p, pl->adj_l2p2, pl->abar[F], F >= 4 ? pl->abar[F - 1] : nullptr, nF);
+    hipLaunchKernelGGL(k_adj_l2p<P>, dim3(blocks_for(nP, ADJ_L2P_PAR)), dim3(ADJ_L2P_THREADS), 0, s, w.ybar,
+                       pl->adj_l2p, pl->adj_l2p2, w.abar[F], F >= 4 ? w.abar[F - 1] : nullptr, nF);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // transposed L2L chain, fine to coarse
     for (int k = F - 1; k >= 4; --k) {
       const int ns = 1 << (k - 1);
       hipLaunchKernelGGL(k_adj_l2l, dim3(blocks_for((long long)ns * ns * ns * NL, 256)), dim3(256), 0, s,
-                         pl->abar[k], pl->abar[k - 1], ns, NL);
+                         w.abar[k], w.abar[k - 1], ns, NL);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     // transposed M2L of every target level (sources k - 1 receive)
-    if ((e = launch_conv<P, double, CV_M2LT>(pl, pl->s_m2lt[0], pl->wt_m2l[0], s)) != hipSuccess) return e;
+    if ((e = launch_conv<P, double, CV_M2LT>(pl, w.m2lt[0], pl->wt_m2l[0], s)) != hipSuccess) return e;
     if constexpr (!std::is_same<CT, double>::value)
-      if ((e = launch_conv<P, CT, CV_M2LT>(pl, pl->s_m2lt[1], pl->wt_m2l[Mf<CT>::IDX], s)) != hipSuccess) return e;
-    if ((e = launch_split_reduce(pl, pl->s_m2lt_red, s)) != hipSuccess) return e;
+      if ((e = launch_conv<P, CT, CV_M2LT>(pl, w.m2lt[1], pl->wt_m2l[Mf<CT>::IDX], s)) != hipSuccess) return e;
+    if ((e = launch_split_reduce(pl, w.m2lt_red, s)) != hipSuccess) return e;
   }
   // transposed M2P at the finest level
   if (bottom_low(pl, F))
-    e = launch_conv<P, CT, CV_M2PT>(pl, pl->s_m2pt, pl->wt_m2p[Mf<CT>::IDX], s);
+    e = launch_conv<P, CT, CV_M2PT>(pl, w.m2pt, pl->wt_m2p[Mf<CT>::IDX], s);
   else
-    e = launch_conv<P, double, CV_M2PT>(pl, pl->s_m2pt, pl->wt_m2p[0], s);
+    e = launch_conv<P, double, CV_M2PT>(pl, w.m2pt, pl->wt_m2p[0], s);
   if (e != hipSuccess) return e;
   // transposed M2M chain, coarse to fine
   for (int k = 3; k <= F; ++k) {
@@ -1207,7 +1212,7 @@ hipError_t backward_ct(fmm_plan* pl, const TI* dphi, const TI* dg, TO* drho, hip
   // nF is a power of two >= 4: the block's z extent divides it
   const int tz = nF < ADJ_BOT_TZ ? nF : ADJ_BOT_TZ;
   dim3 bgrid(nF / 4, nF / 4, nF / tz);
-  hipLaunchKernelGGL((k_adj_bottom<TO>), bgrid, dim3(16 * tz), 0, s, (const double*)pl->lev[F].M, pl->ybar, drho, n,
+  hipLaunchKernelGGL((k_adj_bottom<TO>), bgrid, dim3(16 * tz), 0, s, (const double*)pl->lev[F].M, w.ybar, drho, n,
                      pl->NMX);
   return hipGetLastError();
 }
@@ -1244,11 +1249,12 @@ hipError_t Impl<P>::solve(fmm_plan* pl, IoArg io, hipStream_t s) {
 }
 
 template <int P>
-hipError_t Impl<P>::backward(fmm_plan* pl, const void* dphi, const void* dg, void* drho, hipStream_t s) {
+hipError_t Impl<P>::backward(fmm_plan* pl, const AdjWs& w, const void* dphi, const void* dg, void* drho,
+                             hipStream_t s) {
   switch (pl->precision) {
-    case 0: return backward_ct<P, double>(pl, (const double*)dphi, (const double*)dg, (double*)drho, s);
-    case 1: return backward_ct<P, float>(pl, (const float*)dphi, (const float*)dg, (float*)drho, s);
-    case 2: return backward_ct<P, bf16_tag>(pl, (const float*)dphi, (const float*)dg, (float*)drho, s);
+    case 0: return backward_ct<P, double>(pl, w, (const double*)dphi, (const double*)dg, (double*)drho, s);
+    case 1: return backward_ct<P, float>(pl, w, (const float*)dphi, (const float*)dg, (float*)drho, s);
+    case 2: return backward_ct<P, bf16_tag>(pl, w, (const float*)dphi, (const float*)dg, (float*)drho, s);
   }
   return hipErrorInvalidValue;
 }

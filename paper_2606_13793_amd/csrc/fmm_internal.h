@@ -16,6 +16,7 @@
 
 #include <hip/hip_runtime.h>
 #include <cstddef>
+#include <algorithm>
 #include <cstdint>
 #include <vector>
 
@@ -200,6 +201,24 @@ struct SegTable {
   int cz = 16;  // k_conv sites: tile depth along z (8 when every grid is at most 8 deep)
 };
 
+// Workspace of one backward pass: the scaled adjoint outputs of the level-F
+// cells, the adjoint locals of levels 3..F and, when the transposed M2L
+// splits its offset sums over blocks, their partial sums; plus the segment
+// tables of the transposed convolutions, which point into it.  A plan owns
+// one (fmm_solve_backward); fmm_solve_backward_noalloc lays one out in the
+// library's static workspace for each call.
+struct AdjWs {
+  double* ybar = nullptr;    // [YC][(nF+6)^3][4], YC = 8^dl chunks of (phi, gx, gy, gz)
+  double* abar[16] = {};     // level k: [loc_stride/4][(2^(k-1)+6)^3][4]
+  double* part = nullptr;    // split partial sums of the transposed M2L (null: unsplit)
+  SegTable m2lt[2], m2pt, m2lt_red;
+};
+// Static workspace of fmm_solve_backward_noalloc (bytes per device) and the
+// most segments its tables hold.
+constexpr size_t kNoallocBytes = (size_t)96 << 20;
+constexpr size_t kNoallocSegBytes = 4096;
+constexpr int kMaxAdjSegs = 16;
+
 // launch-shape choices picked by the batch autotuner
 struct Tuning {
   int bz = 16;   // bottom tile depth (8 or 16 level-F cells)
@@ -223,6 +242,7 @@ struct fmm_plan {
   int precision = 0;
   int coarse_fp64_levels = 4;
   int check_finite = 0;
+  int force_bz = 0;  // bottom tile depth forced by the caller (0 = the plan's choice)
   int device = 0;
   int cus = 256;  // compute units of the device
   double dx = 0.0;
@@ -242,10 +262,11 @@ struct fmm_plan {
   void* wl2p2[3] = {nullptr, nullptr, nullptr};  // L2P from the parent level
   void* wp2p[3] = {nullptr, nullptr, nullptr};   // near field
   void* wm2l[3] = {nullptr, nullptr, nullptr};   // M2L
-  // adjoint workspace and tables, built by the first backward call
-  int adj_ready = 0;
-  double* ybar = nullptr;       // [8][(nF+6)^3][4] scaled adjoint outputs per level-F cell
-  double* abar[16] = {};        // adjoint locals of level k: [loc_stride/4][(2^(k-1)+6)^3][4]
+  // adjoint tables (built with every single-field plan) and workspace
+  // (allocated by the first fmm_solve_backward call)
+  int adj_tables = 0;           // the tables below are built
+  int adj_ready = 0;            // `adj` is allocated
+  fmm::AdjWs adj;
   double* adj_l2p = nullptr;    // [NL][32]     L2P coefficients
   double* adj_l2p2 = nullptr;   // [8][NL][32]  parent-level L2P coefficients
   void* wt_m2l[3] = {nullptr, nullptr, nullptr};  // transposed M2L B fragments
@@ -267,10 +288,7 @@ struct fmm_plan {
   fmm::SegTable s_l2l[16];          // L2L into level k (index k)
   fmm::SegTable s_bot[2][2];        // bottom [FP64 | low][tile depth 16 | 8]
   fmm::SegTable s_red[2];           // reductions of split forward M2L partial sums
-  fmm::SegTable s_m2lt[2], s_m2pt;  // adjoint convolutions (field 0)
-  fmm::SegTable s_m2lt_red;         // reductions of the split transposed M2L
   double* conv_part = nullptr;      // partial sums of split forward M2L segments
-  double* adj_part = nullptr;       // partial sums of the split transposed M2L
   // per convolution kind and compute type: (K chunks, first fragment) of
   // every column tile, zero-padded past the last tile
   int* tiletab[3][3] = {};
@@ -280,6 +298,7 @@ struct fmm_plan {
   std::vector<fmm::Io> io_last;     // what the table holds
   fmm::Tuning tune;
   std::vector<double> tune_ms;      // autotuner timings (ms) of each candidate
+  int tune_cached = 0;              // the choice came from the autotune cache file
   hipStream_t cap_stream = nullptr; // stream the batch graph is captured on
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -298,7 +317,8 @@ struct Impl {
   static hipError_t upload_constants();
   static hipError_t tables(fmm_plan* pl, hipStream_t s);           // derivative and B tables
   static hipError_t solve(fmm_plan* pl, IoArg io, hipStream_t s);  // every field of the plan
-  static hipError_t backward(fmm_plan* pl, const void* dphi, const void* dg, void* drho, hipStream_t s);
+  static hipError_t backward(fmm_plan* pl, const AdjWs& w, const void* dphi, const void* dg, void* drho,
+                             hipStream_t s);
   static hipError_t adjoint_tables(fmm_plan* pl, hipStream_t s);
   static hipError_t finish_locals(fmm_plan* pl, int level, hipStream_t s);
   static hipError_t check_finite(fmm_plan* pl, const void* rho, int* host_flag, hipStream_t s);
@@ -321,7 +341,14 @@ hipError_t launch_cic(int n, long long count, const double* pos, const double* m
 // finite-difference force (fmm_force.hip): f[3][n^3] = -grad(phi) by 5-cell differences
 hipError_t launch_fd_force(int n, const double* phi, double* f, hipStream_t s);
 hipError_t launch_solve(fmm_plan* pl, IoArg io, hipStream_t s);
-hipError_t launch_backward(fmm_plan* pl, const void* dphi, const void* dg, void* drho, hipStream_t s);
+hipError_t launch_backward(fmm_plan* pl, const AdjWs& w, const void* dphi, const void* dg, void* drho,
+                           hipStream_t s);
+// the static workspace of fmm_solve_backward_noalloc on the current device
+// (fmm_noalloc.hip): its device address, a zero fill and a segment upload
+// that record only kernels on the stream
+hipError_t noalloc_base(int device, void** base);
+hipError_t noalloc_zero(double* p, long long count, hipStream_t s);
+hipError_t noalloc_put_segs(const Seg* segs, int count, Seg* dst, hipStream_t s);
 hipError_t launch_adjoint_tables(fmm_plan* pl, hipStream_t s);
 hipError_t launch_check_finite(fmm_plan* pl, const void* rho, int* host_flag, hipStream_t s);
 // completes the stored locals of `level` of field 0 (the finest level keeps

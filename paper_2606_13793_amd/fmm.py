@@ -44,6 +44,8 @@ class FmmOptions(ctypes.Structure):
         ("delta_l", ctypes.c_int),
         ("check_finite", ctypes.c_int),
         ("autotune", ctypes.c_int),
+        ("bottom_tile", ctypes.c_int),
+        ("autotune_cache", ctypes.c_char_p),
     ]
 
 
@@ -130,7 +132,7 @@ class Plan:
 
     def __init__(self, n: int, p: int, precision: str = "fp64", nmax: int | None = None,
                  isolated: int = 1, check_finite: bool = False, coarse_fp64_levels: int = 4,
-                 delta_l: int = 1):
+                 delta_l: int = 1, bottom_tile: int = 0):
         L = lib()
         opt = FmmOptions()
         L.fmm_options_default(ctypes.byref(opt))
@@ -139,6 +141,7 @@ class Plan:
         opt.check_finite = int(bool(check_finite))
         opt.coarse_fp64_levels = int(coarse_fp64_levels)
         opt.delta_l = int(delta_l)
+        opt.bottom_tile = int(bottom_tile)
         ptr = L.fmm_plan_create_ex(int(n), int(p), int(isolated), ctypes.byref(opt))
         if not ptr:
             raise FmmError(L.fmm_last_status(), last_error())
@@ -249,7 +252,8 @@ class Batch:
     replay a captured HIP graph."""
 
     def __init__(self, sizes, p: int, precision: str = "fp32", coarse_fp64_levels: int = 4,
-                 autotune: bool = True, isolated: int = 1, delta_l: int = 1):
+                 autotune: bool = True, isolated: int = 1, delta_l: int = 1, bottom_tile: int = 0,
+                 autotune_cache: str | None = None):
         L = lib()
         opt = FmmOptions()
         L.fmm_options_default(ctypes.byref(opt))
@@ -257,6 +261,9 @@ class Batch:
         opt.coarse_fp64_levels = int(coarse_fp64_levels)
         opt.autotune = int(bool(autotune))
         opt.delta_l = int(delta_l)
+        opt.bottom_tile = int(bottom_tile)
+        cache = None if autotune_cache is None else os.fsencode(autotune_cache)
+        opt.autotune_cache = cache  # `cache` keeps the bytes alive through the call
         self.sizes = [int(n) for n in sizes]
         arr = (ctypes.c_int * len(self.sizes))(*self.sizes)
         ptr = L.fmm_batch_plan_create(len(self.sizes), arr, int(p), int(isolated), ctypes.byref(opt))

@@ -85,6 +85,9 @@ def test_invalid_sizes_rejected_without_device(F, n, p, iso, code, text):
     ({"precision": 5}, -1),
     ({"struct_size": 4}, -1),
     ({"coarse_fp64_levels": -1}, -1),
+    ({"bottom_tile": 4}, -1),
+    ({"bottom_tile": 32}, -1),
+    ({"bottom_tile": 8, "delta_l": 2}, -1),
 ])
 def test_invalid_options_rejected(F, opt, code):
     ptr, status, msg = _create(F, 16, 4, **opt)
@@ -127,6 +130,7 @@ def test_options_default(F):
     assert F.lib().fmm_options_default(ctypes.byref(o)) == 0
     assert o.struct_size == ctypes.sizeof(F.FmmOptions)
     assert (o.precision, o.nmax, o.coarse_fp64_levels, o.delta_l, o.check_finite) == (0, -1, 4, 1, 0)
+    assert (o.autotune, o.bottom_tile, o.autotune_cache) == (1, 0, None)
 
 
 def test_multi_index_order(F):

@@ -160,8 +160,11 @@ def test_fp32_batch(F, orc):
             phi_s = phis[f].reshape(-1)[idx].double().cpu().numpy()
             g_s = gs[f].reshape(3, -1)[:, idx].double().cpu().numpy()
         e1, e2 = rel(phi_s, phi_o), rel(g_s, g_o)
-        _say(f"  field {f} n={n}: phi {e1:.2e} g {e2:.2e}")
+        c1 = float(np.abs(phi_s - phi_o).max() / np.abs(phi_o).max())
+        c2 = float(np.abs(g_s - g_o).max() / np.abs(g_o).max())
+        _say(f"  field {f} n={n}: phi {e1:.2e} g {e2:.2e}; per cell {c1:.2e} {c2:.2e}")
         assert e1 < 1e-5 and e2 < 1e-4, (f, n, e1, e2)
+        assert c1 < 1e-5 and c2 < 1e-4, (f, n, c1, c2)
 
 
 def test_single_and_batch_entry_points_are_distinct(F):
@@ -173,3 +176,52 @@ def test_single_and_batch_entry_points_are_distinct(F):
     assert rc == F.FMM_ERR_INVALID_ARG
     with pytest.raises(F.FmmError):
         B.solve_into([x], [x])  # rho and phi alias
+
+
+def test_autotune_cache_round_trip(F, tmp_path):
+    """opt.autotune_cache: the first plan times the candidates and appends
+    its choice; a second plan with the same key reads it back without
+    timing (same figures, no new line); a hand-written entry is obeyed; a
+    different batch adds its own line."""
+    import torch
+    path = str(tmp_path / "tune.txt")
+    sizes = [32, 64, 16]
+    _say("case batch autotune cache")
+    B1 = F.Batch(sizes, 4, "fp32", autotune_cache=path)
+    i1 = B1.info()
+    lines = open(path).read().splitlines()
+    assert len(lines) == 1, lines
+    key, rest = lines[0].split(" ", 1)
+    assert "/p4/" in key and key.endswith("/n32,64,16")
+    bz, grp = (int(x) for x in rest.split()[:2])
+    assert (bz, grp) == (i1["bottom_tile"], i1["m2l_grouping"])
+    B2 = F.Batch(sizes, 4, "fp32", autotune_cache=path)
+    i2 = B2.info()
+    assert len(open(path).read().splitlines()) == 1
+    assert (i2["bottom_tile"], i2["m2l_grouping"]) == (bz, grp)
+    assert np.allclose(i2["tune_ms"], i1["tune_ms"], rtol=0, atol=1e-6)
+    # a hand-written choice for the key wins (the last line with the key)
+    with open(path, "a") as fh:
+        fh.write(f"{key} 8 1 9.5 9.5 9.5 9.5\n")
+    B3 = F.Batch(sizes, 4, "fp32", autotune_cache=path)
+    i3 = B3.info()
+    assert (i3["bottom_tile"], i3["m2l_grouping"], i3["tune_ms"]) == (8, 1, [9.5] * 4)
+    rhos = _fields(sizes, torch.float32)
+    p1, g1 = B1.solve(rhos)
+    p3, g3 = B3.solve(rhos)
+    torch.cuda.synchronize()
+    for f in range(len(sizes)):
+        assert rel(p3[f].double().cpu().numpy(), p1[f].double().cpu().numpy()) < 1e-6
+        assert rel(g3[f].double().cpu().numpy(), g1[f].double().cpu().numpy()) < 1e-6
+    F.Batch([32, 32], 4, "fp32", autotune_cache=path)
+    assert len(open(path).read().splitlines()) == 3
+
+
+def test_fmm2_batch_times_only_its_tile_depth(F):
+    """FMM-2 fields always run 16-deep bottom tiles: the autotuner times
+    only those candidates and reports 16."""
+    B = F.Batch([32, 16], 3, "fp64", delta_l=2)
+    info = B.info()
+    assert info["bottom_tile"] == 16
+    assert info["tune_ms"][0] > 0 and info["tune_ms"][1] > 0
+    assert info["tune_ms"][2] == 0 and info["tune_ms"][3] == 0

@@ -127,9 +127,16 @@ def test_fmm2_mixed_precision_matches_oracle(F, orc, precision, n, p, coarse):
     torch.cuda.synchronize()
     assert phi.dtype == torch.float32
     phi_o, g_o = orc.solve(rho32.astype(np.float64), p, delta_l=2)
-    ep, eg = rel(phi.double().cpu().numpy(), phi_o), rel(g.double().cpu().numpy(), g_o)
+    phi, g = phi.double().cpu().numpy(), g.double().cpu().numpy()
+    ep, eg = rel(phi, phi_o), rel(g, g_o)
+    # per cell as well: max |err| / max |ref| (operand rounding bounds each
+    # cell's error by about 2u times the sum of its term magnitudes)
+    cp = float(np.abs(phi - phi_o).max() / np.abs(phi_o).max())
+    cg = float(np.abs(g - g_o).max() / np.abs(g_o).max())
+    _say(f"  rel L2 phi {ep:.2e} g {eg:.2e}; per cell phi {cp:.2e} g {cg:.2e}")
     bp, bg = bars[precision]
     assert ep <= bp and eg <= bg, (ep, eg)
+    assert cp <= bp and cg <= bg, (cp, cg)
 
 
 def test_fmm2_rejections(F):
