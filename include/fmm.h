@@ -129,6 +129,29 @@ int fmm_solve(fmm_plan* plan, const void* rho, void* phi, void* g, void* stream)
 int fmm_solve_backward(fmm_plan* plan, const void* dphi, const void* dg, void* drho, void* stream);
 
 /*
+ * fmm_solve_backward for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, result and error codes as fmm_solve_backward
+ * (up to the rounding order of the transposed M2L's sums), but the call
+ * allocates nothing: the backward workspace (the scaled adjoint outputs of
+ * the finest FMM cells and the adjoint locals of every level) is laid out in
+ * one static device array of the library, 96 MiB (100663296 bytes) per
+ * device, which each GPU that loads the library holds until the process
+ * ends.  The call enqueues only kernels on `stream`: it clears the part of
+ * the array it uses, writes its launch tables there and runs the backward
+ * pass.  Plans whose workspace does not fit are rejected with
+ * FMM_ERR_INVALID_ARG before anything is enqueued: it needs
+ *   4096 + ceil256(8 (n/2+6)^3 32) + sum_{k=3..F} ceil256(S (2^(k-1)+6)^3 8)
+ * bytes, S = 16 ceil(8 nterms(p) / 16), which fits n <= 32 at every p and
+ * n = 64 up to p = 6.  The array keeps the last call's contents; every call
+ * on a device shares it, so calls that overlap in time on one device (two
+ * streams, two threads, two plans) race, and only one may be in flight per
+ * device.  The current device must be the plan's.  Stage profiling is not
+ * recorded for this call.  Single-field delta_l = 1 plans.
+ */
+int fmm_solve_backward_noalloc(fmm_plan* plan, const void* dphi, const void* dg, void* drho, void* stream);
+
+/*
  * Batches: several density fields of (possibly different) sizes solved by
  * one plan, each stage of the solve being a single launch over the tiles of
  * every field (the unigrid solve of Sec. 2 applied per field; fields do not

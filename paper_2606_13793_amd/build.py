@@ -16,7 +16,7 @@ LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libfmm.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["fmm_api.cpp", "fmm_deposit.hip", "fmm_force.hip"] + [f"fmm_p{p}.hip" for p in range(1, 9)]
+SOURCES = ["fmm_api.cpp", "fmm_deposit.hip", "fmm_force.hip", "fmm_noalloc.hip"] + [f"fmm_p{p}.hip" for p in range(1, 9)]
 
 # Packed FP32 instructions are disabled for all device code.
 HIPFLAGS = [

@@ -1163,6 +1163,72 @@ int fmm_solve_backward(fmm_plan* plan, const void* dphi, const void* dg, void* d
   return ok();
 }
 
+// The backward pass with its workspace laid out in the library's static
+// device array instead of plan memory: [segment tables | Ybar | adjoint
+// locals of levels F..3], each part 256-byte aligned, zeroed by a kernel on
+// `stream` at every call; the transposed M2L writes its adjoint multipoles
+// in place (no split partial sums).  Only kernels are enqueued.
+int fmm_solve_backward_noalloc(fmm_plan* plan, const void* dphi, const void* dg, void* drho, void* stream) {
+  if (int rc = check_backward_args(plan, dphi, dg, drho)) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const AdjLayout lay = adj_layout(plan);
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  size_t at = fmm::kNoallocSegBytes;
+  const size_t y_off = at;
+  at += al(lay.ybar);
+  size_t a_off[16] = {};
+  for (int k = plan->F; k >= 3; --k) {
+    a_off[k] = at;
+    at += al(lay.abar[k]);
+  }
+  if (at > fmm::kNoallocBytes)
+    return fail(FMM_ERR_INVALID_ARG,
+                "fmm_solve_backward_noalloc: this plan's backward workspace needs %zu bytes, more than the "
+                "%zu-byte static workspace (use fmm_solve_backward)",
+                at, fmm::kNoallocBytes);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != plan->device) {
+    (void)hipGetLastError();
+    return fail(FMM_ERR_INVALID_ARG, "the current HIP device (%d) is not the plan's (%d)", dev, plan->device);
+  }
+  void* base = nullptr;
+  hipError_t e = fmm::noalloc_base(dev, &base);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FMM_ERR_DEVICE, "static workspace address: %s", hipGetErrorString(e));
+  }
+  char* b = (char*)base;
+  fmm::AdjWs w;
+  w.ybar = (double*)(b + y_off);
+  for (int k = 3; k <= plan->F; ++k) w.abar[k] = (double*)(b + a_off[k]);
+  const AdjSegs sg = adj_segments(plan, w);
+  fmm::Seg* sd = (fmm::Seg*)b;
+  int used = 0;
+  e = hipSuccess;
+  for (auto pr : {std::make_pair(&w.m2lt[0], &sg.lt[0]), std::make_pair(&w.m2lt[1], &sg.lt[1]),
+                  std::make_pair(&w.m2pt, &sg.pt)}) {
+    fmm::SegTable& st = *pr.first;
+    const SegArr& l = *pr.second;
+    if (!l.n || e != hipSuccess) continue;
+    st.dev = sd + used;
+    st.nseg = l.n;
+    st.blocks = (int)l.blocks;
+    e = fmm::noalloc_put_segs(l.v, l.n, sd + used, s);
+    used += l.n;
+  }
+  if (e == hipSuccess) e = fmm::noalloc_zero(w.ybar, (long long)((at - y_off) / sizeof(double)), s);
+  // stage timing would create events: it is off for this call
+  const int prof = plan->profiling;
+  plan->profiling = 0;
+  if (e == hipSuccess) e = fmm::launch_backward(plan, w, dphi, dg, drho, s);
+  plan->profiling = prof;
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FMM_ERR_DEVICE, "backward launch failed: %s", hipGetErrorString(e));
+  }
+  return ok();
+}
+
 int fmm_profile_enable(fmm_plan* plan, int enable) {
   if (!plan) return fail(FMM_ERR_INVALID_ARG, "plan is NULL");
   plan->profiling = enable ? 1 : 0;

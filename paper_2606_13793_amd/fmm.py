@@ -31,7 +31,7 @@ EXPORTS = (
     "fmm_last_error", "fmm_last_status", "fmm_debug_expansions", "fmm_multi_index",
     "fmm_profile_enable", "fmm_profile_read", "fmm_profile_stage_name",
     "fmm_batch_plan_create", "fmm_batch_solve", "fmm_batch_info", "fmm_deposit_cic",
-    "fmm_fd_force",
+    "fmm_fd_force", "fmm_solve_backward_noalloc",
 )
 
 
@@ -75,6 +75,7 @@ def lib():
         L.fmm_plan_destroy.restype = None
         L.fmm_solve.argtypes = [vp, vp, vp, vp, vp]
         L.fmm_solve_backward.argtypes = [vp, vp, vp, vp, vp]
+        L.fmm_solve_backward_noalloc.argtypes = [vp, vp, vp, vp, vp]
         L.fmm_plan_workspace_bytes.argtypes = [vp]
         L.fmm_plan_workspace_bytes.restype = sz
         L.fmm_plan_info.argtypes = [vp] + [ctypes.POINTER(i)] * 5
