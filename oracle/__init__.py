@@ -58,6 +58,7 @@ def lib():
                                     ctypes.c_int, ctypes.c_int, _dp]
         L.or_direct.argtypes = [ctypes.c_int, _dp, ctypes.c_longlong, _lp, _dp, _dp]
         L.or_adjoint.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
+        L.or_adjoint_dl.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp]
         L.or_solve_timed.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
                                      ctypes.c_longlong, _lp, _dp, _dp, _dp]
         L.or_solve_timed_dl.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
@@ -195,14 +196,16 @@ def direct(rho, targets=None):
     return phi, g
 
 
-def adjoint(dphi, dg, p: int, nmax: int | None = None) -> np.ndarray:
-    """d(<phi,dphi> + <g,dg>)/drho of the FMM solve (dg may be None)."""
+def adjoint(dphi, dg, p: int, nmax: int | None = None, delta_l: int = 1) -> np.ndarray:
+    """d(<phi,dphi> + <g,dg>)/drho of the FMM solve (dg may be None), for the
+    finest FMM level ``delta_l`` levels above the unigrid."""
     dphi = _f64(dphi)
     n = dphi.shape[0]
     nmax = p if nmax is None else nmax
     drho = np.zeros((n, n, n))
-    dgp = None if dg is None else _d(_f64(dg))
-    rc = lib().or_adjoint(n, p, nmax, _d(dphi), dgp, _d(drho))
+    dgv = None if dg is None else _f64(dg)
+    dgp = None if dgv is None else _d(dgv)
+    rc = lib().or_adjoint_dl(n, p, nmax, delta_l, _d(dphi), dgp, _d(drho))
     if rc != 0:
         raise ValueError("bad arguments")
     return drho

@@ -737,17 +737,21 @@ int or_direct(int n, const double *rho, i64 ntarget, const i64 *targets, double 
 }
 
 /*
- * Adjoint (vector-Jacobian product) of or_solve over the full grid:
- * drho = d(<phi, dphi> + <g, dg>)/drho.  The solve is linear in the cell
- * masses m = rho dx^3; each forward operator is transposed and the passes run
- * in reverse: P2P^T, L2P^T and M2P^T at the finest level, then for
- * k = F..3 L2L^T and M2L^T, then M2M^T for k = 3..F, then P2M^T.
- * dg may be NULL (treated as zero).
+ * Adjoint (vector-Jacobian product) of or_solve_dl over the full grid:
+ * drho = d(<phi, dphi> + <g, dg>)/drho, with the finest FMM level dl levels
+ * above the unigrid (dl = 1 FMM-1, dl = 2 FMM-2 of App. A).  The solve is
+ * linear in the cell masses m = rho dx^3; each forward operator is transposed
+ * and the passes run in reverse: P2P^T, L2P^T and M2P^T at the finest level
+ * (each finest FMM cell holds 8^dl unigrid cells, the near field of a
+ * unigrid cell is every unigrid cell of the finest FMM cells adjacent to its
+ * own), then for k = F..3 L2L^T and M2L^T, then M2M^T for k = 3..F, then
+ * P2M^T.  dg may be NULL (treated as zero).
  */
-int or_adjoint(int n, int p, int nmax, const double *dphi, const double *dg, double *drho) {
+int or_adjoint_dl(int n, int p, int nmax, int dl, const double *dphi, const double *dg, double *drho) {
   ostate s;
-  if (st_init(&s, n, p, nmax, 1) != 0) return -1;
+  if (st_init(&s, n, p, nmax, dl) != 0) return -1;
   const int F = s.F, Lv = s.L, ntM = s.ntM, ntL = s.ntL;
+  const int msk = (1 << dl) - 1, nq = 1 << (3 * dl), reach = (2 << dl) - 1;
   const i64 N = (i64)n * n * n;
   const int nF = 1 << F;
   const double dx = s.dx;
@@ -763,10 +767,10 @@ int or_adjoint(int n, int p, int nmax, const double *dphi, const double *dg, dou
   for (i64 w = 0; w < N; ++w) {
     int a = (int)(w / ((i64)n * n)), b = (int)((w / n) % n), c = (int)(w % n);
     double acc = 0.0;
-    for (int i = a - 3; i <= a + 3; ++i)
-      for (int j = b - 3; j <= b + 3; ++j)
-        for (int l = c - 3; l <= c + 3; ++l) {
-          if (!inside(i, j, l, n) || !adjacent(i >> 1, j >> 1, l >> 1, a >> 1, b >> 1, c >> 1)) continue;
+    for (int i = a - reach; i <= a + reach; ++i)
+      for (int j = b - reach; j <= b + reach; ++j)
+        for (int l = c - reach; l <= c + reach; ++l) {
+          if (!inside(i, j, l, n) || !adjacent(i >> dl, j >> dl, l >> dl, a >> dl, b >> dl, c >> dl)) continue;
           i64 u = lin(i, j, l, n);
           double r[3] = {centre(i, Lv) - centre(a, Lv), centre(j, Lv) - centre(b, Lv), centre(l, Lv) - centre(c, Lv)};
           acc += dphi[u] * green_soft(r, dx);
@@ -782,8 +786,8 @@ int or_adjoint(int n, int p, int nmax, const double *dphi, const double *dg, dou
 #pragma omp parallel for schedule(static)
     for (i64 T = 0; T < (i64)nF * nF * nF; ++T) {
       int t0 = (int)(T / ((i64)nF * nF)), t1 = (int)((T / nF) % nF), t2 = (int)(T % nF);
-      for (int q = 0; q < 8; ++q) {
-        int i = 2 * t0 + ((q >> 2) & 1), j = 2 * t1 + ((q >> 1) & 1), l = 2 * t2 + (q & 1);
+      for (int q = 0; q < nq; ++q) {
+        int i = (t0 << dl) + ((q >> (2 * dl)) & msk), j = (t1 << dl) + ((q >> dl) & msk), l = (t2 << dl) + (q & msk);
         i64 u = lin(i, j, l, n);
         double v[3] = {centre(i, Lv) - centre(t0, F), centre(j, Lv) - centre(t1, F), centre(l, Lv) - centre(t2, F)};
         for (int bb = 0; bb < ntL; ++bb) {
@@ -802,7 +806,7 @@ int or_adjoint(int n, int p, int nmax, const double *dphi, const double *dg, dou
   }
   /* M2P^T (gather over targets T whose list holds J) */
   {
-    double *tab = geometry_table(&s, F + 1, 1, nmax + 1);
+    double *tab = geometry_table(&s, F + dl, dl, nmax + 1);
     const int ntD = nterms(nmax + 1);
 #pragma omp parallel for schedule(dynamic, 64)
     for (i64 J = 0; J < (i64)nF * nF * nF; ++J) {
@@ -813,8 +817,9 @@ int or_adjoint(int n, int p, int nmax, const double *dphi, const double *dg, dou
           for (int t2 = j2 - 3; t2 <= j2 + 3; ++t2) {
             if (!inside(t0, t1, t2, nF) || !in_list(t0, t1, t2, j0, j1, j2)) continue;
             int dd = (t0 - j0 + 3) * 49 + (t1 - j1 + 3) * 7 + (t2 - j2 + 3);
-            for (int q = 0; q < 8; ++q) {
-              int i = 2 * t0 + ((q >> 2) & 1), j = 2 * t1 + ((q >> 1) & 1), l = 2 * t2 + (q & 1);
+            for (int q = 0; q < nq; ++q) {
+              int i = (t0 << dl) + ((q >> (2 * dl)) & msk), j = (t1 << dl) + ((q >> dl) & msk),
+                  l = (t2 << dl) + (q & msk);
               i64 u = lin(i, j, l, n);
               const double *D = tab + ((size_t)q * 343 + dd) * ntD;
               for (int a = 0; a < ntM; ++a) {
@@ -916,7 +921,7 @@ int or_adjoint(int n, int p, int nmax, const double *dphi, const double *dg, dou
 #pragma omp parallel for schedule(static)
   for (i64 u = 0; u < N; ++u) {
     int i = (int)(u / ((i64)n * n)), j = (int)((u / n) % n), l = (int)(u % n);
-    int t0 = i >> 1, t1 = j >> 1, t2 = l >> 1;
+    int t0 = i >> dl, t1 = j >> dl, t2 = l >> dl;
     const double *M = Mb[F] + lin(t0, t1, t2, nF) * ntM;
     double v[3] = {centre(i, Lv) - centre(t0, F), centre(j, Lv) - centre(t1, F), centre(l, Lv) - centre(t2, F)};
     double acc = mb[u];
@@ -928,6 +933,11 @@ int or_adjoint(int n, int p, int nmax, const double *dphi, const double *dg, dou
   for (int k = 0; k < 32; ++k) { free(Mb[k]); free(Lb[k]); }
   st_free(&s);
   return 0;
+}
+
+/* or_adjoint_dl for FMM-1 (dl = 1). */
+int or_adjoint(int n, int p, int nmax, const double *dphi, const double *dg, double *drho) {
+  return or_adjoint_dl(n, p, nmax, 1, dphi, dg, drho);
 }
 
 /*

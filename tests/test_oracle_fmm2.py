@@ -147,3 +147,73 @@ def test_fmm1_fmm2_point_charge_differ_below_0p3_percent(orc):
     d = np.abs(p2 - p1) / np.abs(p1)
     assert np.percentile(d, 99) < 3e-3, np.percentile(d, 99)
     assert 1e-3 < d.max() < 4e-3, d.max()
+
+
+# --------------------------------------------------------------------------
+# adjoint of FMM-2: the explicit transposes against the oracle's own FMM-2
+# forward solve (dot-product identity, central differences of a quadratic
+# loss, both exact up to rounding for a linear solve) and against the exact
+# Green's matrix (agreement to the truncation error)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,p,nmax", [(16, 4, None), (32, 4, None), (32, 3, 2), (64, 2, None)])
+def test_fmm2_adjoint_dot_product(orc, n, p, nmax):
+    """<A rho, (psi, chi)> = <rho, A^T (psi, chi)> for random vectors; at
+    64^3 (F = 4) every pass of the transpose carries weight, the parent-level
+    L2P and the L2L chain included."""
+    rng = np.random.default_rng(300 + n + p)
+    rho = rng.standard_normal((n, n, n))
+    wphi = rng.standard_normal((n, n, n))
+    wg = rng.standard_normal((3, n, n, n))
+    phi, g = orc.solve(rho, p, nmax=nmax, delta_l=2)
+    lhs = (phi * wphi).sum() + (g * wg).sum()
+    rhs = (rho * orc.adjoint(wphi, wg, p, nmax=nmax, delta_l=2)).sum()
+    assert abs(lhs - rhs) <= 1e-13 * (np.abs(phi * wphi).sum() + np.abs(g * wg).sum())
+    # the potential part and the acceleration part separately
+    rhs_phi = (rho * orc.adjoint(wphi, None, p, nmax=nmax, delta_l=2)).sum()
+    assert abs((phi * wphi).sum() - rhs_phi) <= 1e-13 * np.abs(phi * wphi).sum()
+
+
+def test_fmm2_adjoint_finite_differences(orc):
+    """Central differences of L = sum (phi - phi_t)^2 through the FMM-2
+    forward solve are exact up to rounding."""
+    n, p = 32, 4
+    rho = fi.plummer_density(n, fi.multi_plummer_params(6, 5001))
+    phi_t, _ = orc.solve(fi.plummer_density(n, fi.multi_plummer_params(6, 5002)), p, delta_l=2)
+    phi, _ = orc.solve(rho, p, delta_l=2)
+    grad = orc.adjoint(2 * (phi - phi_t), None, p, delta_l=2)
+    eps = 1e-3 * rho.max()
+    for c in fi.fd_cells(n, 6):
+        idx = np.unravel_index(c, rho.shape)
+        rp, rm = rho.copy(), rho.copy()
+        rp[idx] += eps
+        rm[idx] -= eps
+        fp = orc.solve(rp, p, delta_l=2)[0]
+        fm = orc.solve(rm, p, delta_l=2)[0]
+        fd = float(((fp - fm) * (fp + fm - 2 * phi_t)).sum()) / (2 * eps)
+        assert fd == pytest.approx(grad[idx], rel=1e-6, abs=1e-9 * abs(grad).max())
+
+
+def test_fmm2_adjoint_differs_from_fmm1(orc):
+    """The FMM-2 adjoint is not the FMM-1 one: their difference is of the
+    truncation level (App. A's comparison, transposed), while each is the
+    exact transpose of its own forward solve."""
+    n, p = 32, 3
+    rng = np.random.default_rng(77)
+    w = rng.standard_normal((n, n, n))
+    a1 = orc.adjoint(w, None, p, delta_l=1)
+    a2 = orc.adjoint(w, None, p, delta_l=2)
+    d = rel(a2, a1)
+    assert 1e-9 < d < 1e-2, d
+
+
+def test_fmm2_adjoint_close_to_direct_sum_gradient(orc):
+    """The gradient of sum (phi - phi_t)^2 with the exact Green's matrix is
+    2 dx^3 G (phi - phi_t); the FMM-2 adjoint agrees to its truncation
+    error."""
+    n, p = 16, 6
+    rho = fi.plummer_density(n, fi.multi_plummer_params(6, 5001))
+    phi_t = orc.direct(fi.plummer_density(n, fi.multi_plummer_params(6, 5002)))[0]
+    grad_direct = 2 * orc.direct(orc.direct(rho)[0] - phi_t)[0]
+    phi_f = orc.solve(rho, p, delta_l=2)[0]
+    grad_fmm = orc.adjoint(2 * (phi_f - phi_t), None, p, delta_l=2)
+    assert rel(grad_fmm, grad_direct) < 1e-4
