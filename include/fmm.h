@@ -11,8 +11,7 @@
  * Sec. 2.3 and Sec. 4).  Cartesian expansions to order p; the finest FMM
  * grid sits delta_l levels above the unigrid (App. A): 1 (FMM-1, default) or
  * 2 (FMM-2, whose finest FMM cells hold 4^3 unigrid cells and whose near
- * field is the 27 x 64 cells of the adjacent ones; forward solves, single
- * fields and batches).
+ * field is the 27 x 64 cells of the adjacent ones).
  *
  * Conventions shared by every entry point
  *  - Grid: unit box [0,1]^3, n cells per axis, cell (i,j,k) centred at
@@ -52,7 +51,7 @@ typedef enum {
   FMM_OK = 0,
   FMM_ERR_INVALID_ARG = -1,   /* bad size, order, pointer or option */
   FMM_ERR_UNSUPPORTED = -2,   /* well-formed but not provided (periodic BC, delta_l outside {1, 2},
-                                 the backward pass of a delta_l = 2 plan) */
+                                 the backward pass of a batch plan) */
   FMM_ERR_OUT_OF_MEMORY = -3, /* device allocation failed */
   FMM_ERR_DEVICE = -4,        /* HIP runtime error (no device, launch failure) */
   FMM_ERR_NONFINITE = -5      /* rho holds NaN/Inf (only with check_finite) */
@@ -75,8 +74,7 @@ typedef struct {
                                the kept terms */
   int coarse_fp64_levels;   /* mixed plans: levels k <= this stay FP64; default 4 */
   int delta_l;              /* level offset unigrid -> finest FMM grid: 1 (default) or 2
-                               (n >= 16; fmm_solve_backward returns FMM_ERR_UNSUPPORTED
-                               for 2) */
+                               (FMM-2, App. A; n >= 16) */
   int check_finite;         /* nonzero: fmm_solve scans rho for NaN/Inf first (single-field plans) */
   int autotune;             /* batch plans: time the launch-shape candidates at creation; default 1 */
   int bottom_tile;          /* depth (level-F cells along z) of the bottom kernel's tiles: 0 = chosen
@@ -140,14 +138,16 @@ int fmm_solve_backward(fmm_plan* plan, const void* dphi, const void* dg, void* d
  * ends.  The call enqueues only kernels on `stream`: it clears the part of
  * the array it uses, writes its launch tables there and runs the backward
  * pass.  Plans whose workspace does not fit are rejected with
- * FMM_ERR_INVALID_ARG before anything is enqueued: it needs
- *   4096 + ceil256(8 (n/2+6)^3 32) + sum_{k=3..F} ceil256(S (2^(k-1)+6)^3 8)
+ * FMM_ERR_INVALID_ARG before anything is enqueued: with m = n / 2^delta_l
+ * it needs
+ *   4096 + ceil256(8^delta_l (m+6)^3 32) + sum_{k=3..F} ceil256(S (2^(k-1)+6)^3 8)
+ *   (+ ceil256(16 (m+6)^3 32) for delta_l = 2)
  * bytes, S = 16 ceil(8 nterms(p) / 16), which fits n <= 32 at every p and
- * n = 64 up to p = 6.  The array keeps the last call's contents; every call
- * on a device shares it, so calls that overlap in time on one device (two
- * streams, two threads, two plans) race, and only one may be in flight per
- * device.  The current device must be the plan's.  Stage profiling is not
- * recorded for this call.  Single-field delta_l = 1 plans.
+ * n = 64 up to p = 6 (FMM-2: n <= 64 at every p).  The array keeps the last
+ * call's contents; every call on a device shares it, so calls that overlap in
+ * time on one device (two streams, two threads, two plans) race, and only one
+ * may be in flight per device.  The current device must be the plan's.
+ * Stage profiling is not recorded for this call.  Single-field plans.
  */
 int fmm_solve_backward_noalloc(fmm_plan* plan, const void* dphi, const void* dg, void* drho, void* stream);
 

@@ -98,7 +98,8 @@ void release_adj(fmm::AdjWs& w) {
   for (auto a : w.abar)
     if (a) (void)hipFree(a);
   if (w.part) (void)hipFree(w.part);
-  for (fmm::SegTable* st : {&w.m2lt[0], &w.m2lt[1], &w.m2pt, &w.m2lt_red})
+  if (w.near) (void)hipFree(w.near);
+  for (fmm::SegTable* st : {&w.m2lt[0], &w.m2lt[1], &w.m2pt, &w.m2lt_red, &w.p2pt})
     if (st->dev) (void)hipFree(st->dev);
   w = fmm::AdjWs{};
 }
@@ -148,7 +149,9 @@ void release(fmm_plan* pl) {
   for (int x = 0; x < 3; ++x) {
     if (pl->wt_m2l[x]) (void)hipFree(pl->wt_m2l[x]);
     if (pl->wt_m2p[x]) (void)hipFree(pl->wt_m2p[x]);
+    if (pl->wt_p2p[x]) (void)hipFree(pl->wt_p2p[x]);
   }
+  if (pl->dlists_p2p) (void)hipFree(pl->dlists_p2p);
   if (pl->adj_l2p) (void)hipFree(pl->adj_l2p);
   if (pl->adj_l2p2) (void)hipFree(pl->adj_l2p2);
   if (pl->m2m_start) (void)hipFree(pl->m2m_start);
@@ -200,6 +203,20 @@ std::vector<int> build_dlists() {
     }
     if (count != fmm::NLIST) return {};
     for (int pad = fmm::NLIST; pad < fmm::NLIST_PAD; ++pad) out.push_back(pack(343, rr[0], rr[1], rr[2]));
+  }
+  return out;
+}
+
+// FMM-2's near-field transpose: per parity class the 27 offsets d in
+// [-1, 1]^3 of the adjacent finest cells, packed like the interaction lists
+// with the compact slot (d0 + 1) 9 + (d1 + 1) 3 + (d2 + 1); the null entry
+// (slot 27, zero weights, d = 0) pads each class to NLIST_PAD.
+std::vector<int> build_dlists_p2p() {
+  std::vector<int> out;
+  auto pack = [](int dd, int d0, int d1, int d2) { return dd | ((d0 + 3) << 9) | ((d1 + 3) << 12) | ((d2 + 3) << 15); };
+  for (int r = 0; r < 8; ++r) {
+    for (int e = 0; e < fmm::NP2P; ++e) out.push_back(pack(e, e / 9 - 1, (e / 3) % 3 - 1, e % 3 - 1));
+    for (int pad = fmm::NP2P; pad < fmm::NLIST_PAD; ++pad) out.push_back(pack(fmm::NP2P, 0, 0, 0));
   }
   return out;
 }
@@ -438,11 +455,13 @@ int adj_split(int k) {
 struct AdjLayout {
   size_t ybar = 0;
   size_t abar[16] = {};
+  size_t near = 0;  // FMM-2 only
 };
 AdjLayout adj_layout(const fmm_plan* pl) {
   AdjLayout l;
   const size_t nFp = (size_t)(pl->n >> pl->dl) + 6;
   l.ybar = ((size_t)8 << (3 * (pl->dl - 1))) * nFp * nFp * nFp * 4 * sizeof(double);
+  if (pl->dl == 2) l.near = (size_t)16 * nFp * nFp * nFp * 4 * sizeof(double);
   for (int k = 3; k <= pl->F; ++k) {
     const size_t np = ((size_t)1 << (k - 1)) + 6;
     l.abar[k] = (size_t)fmm::loc_stride(pl->p) * np * np * np * sizeof(double);
@@ -473,7 +492,7 @@ struct SegArr {
   }
 };
 struct AdjSegs {
-  SegArr lt[2], pt, ltr;
+  SegArr lt[2], pt, ltr, p2pt;
 };
 
 // Segments of the transposed convolutions over workspace w: M2L^T rows are
@@ -517,6 +536,10 @@ AdjSegs adj_segments(const fmm_plan* pl, const fmm::AdjWs& w) {
   c.a = w.ybar;
   c.b = (double*)pl->lev[pl->F].M;
   a.pt.add(c, (long long)c.tpa * c.tpa * c.tz);
+  if (pl->dl == 2) {  // the near-field transpose: the same rows, into w.near
+    c.b = w.near;
+    a.p2pt.add(c, (long long)c.tpa * c.tpa * c.tz);
+  }
   return a;
 }
 
@@ -775,12 +798,22 @@ fmm_plan* create_plan(const std::vector<int>& ns, int p, const fmm_options& o, i
          hipGetErrorString(e));
     return bail();
   }
-  if (!batch && pl->dl == 1) {
+  if (!batch) {
     // the backward pass's tables: coefficients of the transposed L2P steps
-    // and the transposed convolutions' B fragments
-    if (dev_alloc(pl, (void**)&pl->adj_l2p, (size_t)pl->NL * 32 * sizeof(double)) ||
-        dev_alloc(pl, (void**)&pl->adj_l2p2, (size_t)8 * pl->NL * 32 * sizeof(double)))
+    // (one set per group of 8 unigrid cells), the transposed convolutions'
+    // B fragments and, for FMM-2, the near-field transpose's offset lists
+    const size_t ng = pl->dl == 2 ? 8 : 1;
+    if (dev_alloc(pl, (void**)&pl->adj_l2p, ng * pl->NL * 32 * sizeof(double)) ||
+        dev_alloc(pl, (void**)&pl->adj_l2p2, ng * 8 * pl->NL * 32 * sizeof(double)))
       return bail();
+    if (pl->dl == 2) {
+      const std::vector<int> lp = build_dlists_p2p();
+      if (dev_alloc(pl, (void**)&pl->dlists_p2p, lp.size() * sizeof(int))) return bail();
+      if ((e = hipMemcpy(pl->dlists_p2p, lp.data(), lp.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) {
+        fail(FMM_ERR_DEVICE, "upload failed: %s", hipGetErrorString(e));
+        return bail();
+      }
+    }
     if ((e = fmm::launch_adjoint_tables(pl, nullptr)) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
       (void)hipGetLastError();
       fail(e == hipErrorOutOfMemory ? FMM_ERR_OUT_OF_MEMORY : FMM_ERR_DEVICE, "adjoint tables: %s",
@@ -1131,9 +1164,11 @@ static int ensure_adjoint(fmm_plan* pl) {
   for (int k = 3; k <= pl->F; ++k)
     if ((rc = zalloc(&w.abar[k], lay.abar[k]))) return bail(rc);
   if ((rc = zalloc(&w.part, (size_t)adj_part_doubles(pl) * sizeof(double)))) return bail(rc);
+  if (lay.near && (rc = zalloc(&w.near, lay.near))) return bail(rc);
   const AdjSegs sg = adj_segments(pl, w);
   if ((rc = upload_arr(pl, w.m2lt[0], sg.lt[0])) || (rc = upload_arr(pl, w.m2lt[1], sg.lt[1])) ||
-      (rc = upload_arr(pl, w.m2pt, sg.pt)) || (rc = upload_arr(pl, w.m2lt_red, sg.ltr)))
+      (rc = upload_arr(pl, w.m2pt, sg.pt)) || (rc = upload_arr(pl, w.m2lt_red, sg.ltr)) ||
+      (rc = upload_arr(pl, w.p2pt, sg.p2pt)))
     return bail(rc);
   pl->adj = w;
   pl->adj_ready = 1;
@@ -1144,7 +1179,6 @@ static int ensure_adjoint(fmm_plan* pl) {
 static int check_backward_args(fmm_plan* plan, const void* dphi, const void* dg, void* drho) {
   if (!plan) return fail(FMM_ERR_INVALID_ARG, "plan is NULL");
   if (plan->batch) return fail(FMM_ERR_UNSUPPORTED, "the backward pass is provided for single-field plans");
-  if (plan->dl != 1) return fail(FMM_ERR_UNSUPPORTED, "the backward pass is provided for delta_l = 1 plans");
   if (!dphi || !drho) return fail(FMM_ERR_INVALID_ARG, "dphi and drho must be device pointers (got NULL)");
   if (drho == dphi || (dg && (dg == drho || dg == dphi))) return fail(FMM_ERR_INVALID_ARG, "buffers must not alias");
   if (!plan->adj_tables) return fail(FMM_ERR_DEVICE, "the plan's backward tables were not built");
@@ -1181,6 +1215,8 @@ int fmm_solve_backward_noalloc(fmm_plan* plan, const void* dphi, const void* dg,
     a_off[k] = at;
     at += al(lay.abar[k]);
   }
+  const size_t n_off = at;
+  at += al(lay.near);
   if (at > fmm::kNoallocBytes)
     return fail(FMM_ERR_INVALID_ARG,
                 "fmm_solve_backward_noalloc: this plan's backward workspace needs %zu bytes, more than the "
@@ -1201,12 +1237,13 @@ int fmm_solve_backward_noalloc(fmm_plan* plan, const void* dphi, const void* dg,
   fmm::AdjWs w;
   w.ybar = (double*)(b + y_off);
   for (int k = 3; k <= plan->F; ++k) w.abar[k] = (double*)(b + a_off[k]);
+  if (lay.near) w.near = (double*)(b + n_off);
   const AdjSegs sg = adj_segments(plan, w);
   fmm::Seg* sd = (fmm::Seg*)b;
   int used = 0;
   e = hipSuccess;
   for (auto pr : {std::make_pair(&w.m2lt[0], &sg.lt[0]), std::make_pair(&w.m2lt[1], &sg.lt[1]),
-                  std::make_pair(&w.m2pt, &sg.pt)}) {
+                  std::make_pair(&w.m2pt, &sg.pt), std::make_pair(&w.p2pt, &sg.p2pt)}) {
     fmm::SegTable& st = *pr.first;
     const SegArr& l = *pr.second;
     if (!l.n || e != hipSuccess) continue;

@@ -466,17 +466,21 @@ __device__ __forceinline__ double l2p2_parent_coef(int bt, int rp, int grp, int 
     w[ax] = (sub_pos(grp, q, ax) - 1.5 + 4.0 * (((rp >> (2 - ax)) & 1) - 0.5)) / 8.0;
   return l2p_w_coef(bt, w, 0.5, 0.25, o);
 }
-// Near field: source k of the 12^3 block (w = 4 T - 4 + k), target
-// u = 4 T + s, delta = u - w = s + 4 - k (units of dx); eq. (direct) in the
-// accumulator units: phi 4 (-1 / max(|delta|, 1)), g_d 16 delta_d / |delta|^3
-// (0 at delta = 0).
-__device__ __forceinline__ double p2p2_coef(int k, int grp, int q, int o) {
-  const int kk[3] = {k / 144, (k / 12) % 12, k % 12};
-  double d[3];
-  for (int ax = 0; ax < 3; ++ax) d[ax] = (double)(sub_pos(grp, q, ax) + 4 - kk[ax]);
+// Near-field coefficient of FMM-2 for output o of a target u and a source w,
+// delta = u - w (units of dx): eq. (direct) in the accumulator units, phi
+// 4 (-1 / max(|delta|, 1)), g_d 16 delta_d / |delta|^3 (0 at delta = 0).
+__device__ __forceinline__ double p2p2_delta_coef(int d0, int d1, int d2, int o) {
+  const double d[3] = {(double)d0, (double)d1, (double)d2};
   const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
   if (o == 0) return r2 == 0.0 ? -4.0 : -4.0 / sqrt(r2);
   return r2 == 0.0 ? 0.0 : 16.0 * d[o - 1] / (r2 * sqrt(r2));
+}
+// Near field: source k of the 12^3 block (w = 4 T - 4 + k), target
+// u = 4 T + s, delta = u - w = s + 4 - k.
+__device__ __forceinline__ double p2p2_coef(int k, int grp, int q, int o) {
+  const int kk[3] = {k / 144, (k / 12) % 12, k % 12};
+  return p2p2_delta_coef(sub_pos(grp, q, 0) + 4 - kk[0], sub_pos(grp, q, 1) + 4 - kk[1],
+                         sub_pos(grp, q, 2) + 4 - kk[2], o);
 }
 
 #include "fmm_mfma.h"
@@ -560,20 +564,25 @@ __global__ __launch_bounds__(256) void k_l2l(const Seg* __restrict__ segs, int n
 // transposed M2L stages them like multipoles.
 // ---------------------------------------------------------------------------
 
-// Ybar: [8 children][(nF+6)^3][4]: (sphi phi_bar, sg g_bar_x, sg g_bar_y, sg g_bar_z)
-template <typename TI>
+// Ybar: [8^DL chunks][(nF+6)^3][4]: (sphi phi_bar, sg g_bar_x, sg g_bar_y,
+// sg g_bar_z) of each unigrid cell of a level-F cell; chunk q (DL = 1) is
+// child q, chunk 8 g + q (DL = 2) is child q of the level-(F+1) child g.
+template <typename TI, int DL>
 __global__ void k_adj_seed(const TI* __restrict__ dphi, const TI* __restrict__ dg, double* __restrict__ Y, int n,
                            double sphi, double sg) {
-  const int nF = n >> 1, nFp = nF + 6;
+  const int nF = n >> DL, nFp = nF + 6;
   const long long nT = (long long)nF * nF * nF, N = (long long)n * n * n;
   const long long T = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (T >= nT) return;
   const int t2 = (int)(T % nF), t1 = (int)((T / nF) % nF), t0 = (int)(T / ((long long)nF * nF));
   const long long ncellp = (long long)nFp * nFp * nFp;
   const long long cp = ((long long)(t0 + 3) * nFp + (t1 + 3)) * nFp + (t2 + 3);
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const long long u = ((long long)(2 * t0 + ((q >> 2) & 1)) * n + (2 * t1 + ((q >> 1) & 1))) * n + (2 * t2 + (q & 1));
+#pragma unroll 8
+  for (int q = 0; q < (8 << (3 * (DL - 1))); ++q) {
+    const int s0 = DL == 1 ? (q >> 2) & 1 : sub_pos(q >> 3, q & 7, 0);
+    const int s1 = DL == 1 ? (q >> 1) & 1 : sub_pos(q >> 3, q & 7, 1);
+    const int s2 = DL == 1 ? q & 1 : sub_pos(q >> 3, q & 7, 2);
+    const long long u = ((long long)((t0 << DL) + s0) * n + ((t1 << DL) + s1)) * n + ((t2 << DL) + s2);
     d4 v;
     v[0] = sphi * (double)dphi[u];
     v[1] = dg ? sg * (double)dg[u] : 0.0;
@@ -596,24 +605,40 @@ __global__ void k_adj_coef(double* __restrict__ own, double* __restrict__ par, i
     par[((z - 1) * NL + b) * 32 + k] = l2p_parent_coef(b, z - 1, k >> 2, k & 3);
 }
 
+// The same for FMM-2, per group g of 8 unigrid cells:
+//   own [8][NL][32]:     l2p2_coef(b, g, q, o)
+//   par [8][8][NL][32]:  l2p2_parent_coef(b, rp, g, q, o)   ([g][rp])
+__global__ void k_adj_coef2(double* __restrict__ own, double* __restrict__ par, int NL) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= 72 * NL * 32) return;
+  const int k = id % 32, b = (id / 32) % NL, z = id / (32 * NL);
+  if (z < 8)
+    own[(z * NL + b) * 32 + k] = l2p2_coef(b, z, k >> 2, k & 3);
+  else
+    par[((size_t)(z - 8) * NL + b) * 32 + k] = l2p2_parent_coef(b, (z - 8) & 7, (z - 8) >> 3, k >> 2, k & 3);
+}
+
 // L2P^T and (parent-level L2P)^T on the matrix cores (v_mfma_f64_16x16x4f64).
-// Block = 16 level-(F-1) cells P (consecutive in C order) = one row tile; the
-// Ybar of their 8 children (256 values each) is staged in LDS with an odd row
-// stride.  Wave rp (of 8) takes child rp of every P: for each 16-column tile
-// of local terms b,
-//   own[P][(rp, b)] = sum_k cown[b][k] Ybar[2P + rp][k]       (K = 32)
-//   par[P][b]      += sum_k cpar[rp][b][k] Ybar[2P + rp][k]   (K = 32 of 256)
-// own is written to P's row (columns (rp, b) in the M2L order); the 8 waves'
-// par partials are added in LDS in a fixed order and written, when the parent
-// level has locals, to the row of P's parent (column (qP, b)).
+// Block = 16 level-(F-1) cells P (consecutive in C order) = one row tile.
+// Wave rp (of 8) takes child T = 2P + rp of every P.  The K range of a level-F
+// cell is its 8^DL unigrid cells times (phi, g): one group of 32 for DL = 1,
+// eight for DL = 2 (group g = the level-(F+1) child).  Group by group, the
+// Ybar of the 8 children of the 16 P (256 values each) is staged in LDS with
+// an odd row stride and, for each 16-column tile of local terms b,
+//   own[P][(rp, b)] += sum_k cown[g][b][k] Ybar_g[2P + rp][k]      (K = 32)
+//   par[P][b]      += sum_k cpar[g][rp][b][k] Ybar_g[2P + rp][k]
+// accumulate in registers.  own is then written to P's row (columns (rp, b)
+// in the M2L order); the 8 waves' par partials are added in LDS in a fixed
+// order and written, when the parent level has locals, to the row of P's
+// parent (column (qP, b)).
 constexpr int ADJ_L2P_PAR = 16, ADJ_L2P_THREADS = 512, ADJ_L2P_YS = 257;
-template <int P>
+template <int P, int DL>
 __global__ __launch_bounds__(ADJ_L2P_THREADS) void k_adj_l2p(const double* __restrict__ Y,
                                                              const double* __restrict__ cown,
                                                              const double* __restrict__ cpar,
                                                              double* __restrict__ Aown, double* __restrict__ Apar,
                                                              int nF) {
-  constexpr int NL = nterms(P), RS = loc_stride(P), NBT = (NL + 15) / 16;
+  constexpr int NL = nterms(P), RS = loc_stride(P), NBT = (NL + 15) / 16, NG = DL == 1 ? 1 : 8;
   __shared__ double y[ADJ_L2P_PAR * ADJ_L2P_YS];
   __shared__ double red[8][16][17];
   const int nP = nF >> 1, nFp = nF + 6, nPp = nP + 6, nPP = nP >> 1, nPPp = nPP + 6;
@@ -621,22 +646,6 @@ __global__ __launch_bounds__(ADJ_L2P_THREADS) void k_adj_l2p(const double* __res
                   ncPP = (long long)nPPp * nPPp * nPPp;
   const long long nPc = (long long)nP * nP * nP;
   const long long P0 = (long long)blockIdx.x * ADJ_L2P_PAR;
-  // staging: load l = (q, parent, rp), children of consecutive parents are
-  // contiguous along z
-  for (int l = threadIdx.x; l < 8 * ADJ_L2P_PAR * 8; l += ADJ_L2P_THREADS) {
-    const int rp = l & 7, pl = (l >> 3) % ADJ_L2P_PAR, q = l / (8 * ADJ_L2P_PAR);
-    const long long Pc = P0 + pl;
-    d4 v = d4{0, 0, 0, 0};
-    if (Pc < nPc) {
-      const int p2 = (int)(Pc % nP), p1 = (int)((Pc / nP) % nP), p0 = (int)(Pc / ((long long)nP * nP));
-      const long long cT = ((long long)(2 * p0 + ((rp >> 2) & 1) + 3) * nFp + (2 * p1 + ((rp >> 1) & 1) + 3)) * nFp +
-                           (2 * p2 + (rp & 1) + 3);
-      v = *reinterpret_cast<const d4*>(Y + (q * ncF + cT) * 4);
-    }
-    double* yy = y + pl * ADJ_L2P_YS + rp * 32 + q * 4;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) yy[e] = v[e];
-  }
   const int lane = threadIdx.x & 63;
   const int rp = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int i = lane & 15, kq = lane >> 4;
@@ -651,30 +660,59 @@ __global__ __launch_bounds__(ADJ_L2P_THREADS) void k_adj_l2p(const double* __res
     const int p2 = (int)(Pq % nP), p1 = (int)((Pq / nP) % nP), p0 = (int)(Pq / ((long long)nP * nP));
     cpo[v] = ((long long)(p0 + 3) * nPp + (p1 + 3)) * nPp + (p2 + 3);
   }
-  __syncthreads();
-  const double* ya = y + i * ADJ_L2P_YS + rp * 32 + kq;
-  for (int T = 0; T < NBT; ++T) {
-    const int bt = 16 * T + i;  // the lane's column (B operand and output)
-    const bool okc = bt < NL;
-    d4 ao = d4{0, 0, 0, 0}, ap = d4{0, 0, 0, 0};
+  d4 ao[NBT], ap[NBT];
 #pragma unroll
-    for (int kc = 0; kc < 8; ++kc) {
-      const double a = ya[4 * kc];
-      const double bo = okc ? cown[bt * 32 + 4 * kc + kq] : 0.0;
-      const double bp = okc ? cpar[((size_t)rp * NL + bt) * 32 + 4 * kc + kq] : 0.0;
-      ao = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bo, ao, 0, 0, 0);
-      ap = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bp, ap, 0, 0, 0);
+  for (int T = 0; T < NBT; ++T) ao[T] = ap[T] = d4{0, 0, 0, 0};
+  const double* ya = y + i * ADJ_L2P_YS + rp * 32 + kq;
+  for (int g = 0; g < NG; ++g) {
+    if (g) __syncthreads();  // the previous group is consumed
+    // staging: load l = (q, parent, rp), children of consecutive parents are
+    // contiguous along z
+    for (int l = threadIdx.x; l < 8 * ADJ_L2P_PAR * 8; l += ADJ_L2P_THREADS) {
+      const int lr = l & 7, pl = (l >> 3) % ADJ_L2P_PAR, q = l / (8 * ADJ_L2P_PAR);
+      const long long Pc = P0 + pl;
+      d4 v = d4{0, 0, 0, 0};
+      if (Pc < nPc) {
+        const int p2 = (int)(Pc % nP), p1 = (int)((Pc / nP) % nP), p0 = (int)(Pc / ((long long)nP * nP));
+        const long long cT = ((long long)(2 * p0 + ((lr >> 2) & 1) + 3) * nFp + (2 * p1 + ((lr >> 1) & 1) + 3)) * nFp +
+                             (2 * p2 + (lr & 1) + 3);
+        v = *reinterpret_cast<const d4*>(Y + ((8 * g + q) * ncF + cT) * 4);
+      }
+      double* yy = y + pl * ADJ_L2P_YS + lr * 32 + q * 4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) yy[e] = v[e];
     }
-    if (okc) {
+    __syncthreads();
+    const double* co = cown + (size_t)g * NL * 32;
+    const double* cp = cpar + ((size_t)g * 8 + rp) * NL * 32;
+#pragma unroll
+    for (int T = 0; T < NBT; ++T) {
+      const int bt = 16 * T + i;  // the lane's column (B operand)
+      const bool okc = bt < NL;
+#pragma unroll
+      for (int kc = 0; kc < 8; ++kc) {
+        const double a = ya[4 * kc];
+        const double bo = okc ? co[bt * 32 + 4 * kc + kq] : 0.0;
+        const double bp = okc ? cp[bt * 32 + 4 * kc + kq] : 0.0;
+        ao[T] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bo, ao[T], 0, 0, 0);
+        ap[T] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bp, ap[T], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int T = 0; T < NBT; ++T) {
+    const int bt = 16 * T + i;
+    if (bt < NL) {
       const int ex = c_mi_exp[bt];
       const int col = m2l_col(rp, bt, mi_a(ex) + mi_b(ex) + mi_c(ex));
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        if (okr[v]) Aown[((col >> 2) * ncP + cpo[v]) * 4 + (col & 3)] = ao[v];
+        if (okr[v]) Aown[((col >> 2) * ncP + cpo[v]) * 4 + (col & 3)] = ao[T][v];
     }
     if (Apar) {
+      __syncthreads();  // the staging buffer / previous reduction is consumed
 #pragma unroll
-      for (int v = 0; v < 4; ++v) red[rp][4 * v + kq][i] = ap[v];
+      for (int v = 0; v < 4; ++v) red[rp][4 * v + kq][i] = ap[T][v];
       __syncthreads();
       if (threadIdx.x < 256) {
         const int row = threadIdx.x >> 4, c = threadIdx.x & 15, b2 = 16 * T + c;
@@ -691,7 +729,6 @@ __global__ __launch_bounds__(ADJ_L2P_THREADS) void k_adj_l2p(const double* __res
           Apar[((col >> 2) * ncPP + cpp) * 4 + (col & 3)] = acc;
         }
       }
-      __syncthreads();
     }
   }
   // the padding columns of P's row (past 8 NL) stay zero
@@ -899,6 +936,50 @@ __global__ __launch_bounds__(16 * ADJ_BOT_TZ) void k_adj_bottom(const double* __
   }
 }
 
+// P2M^T of FMM-2 plus the near-field transpose (computed by k_conv as
+// CV_P2PT2 into Near, [16][(nF+6)^3][4], column s = 16 s0 + 4 s1 + s2):
+//   rho_bar[4T + s] = Near[T][s] + sum_{|a| <= nmax} w_s^a / a! Mbar_F[T][a],
+//   w_s,i = (3 - 2 s_i) / 8,
+// the transpose of k_p2m2.  A wave takes one level-F cell T (its Mbar row is
+// staged in LDS and read by all lanes at once), lane s one unigrid cell; the
+// powers of w are formed as the multi-index loops advance.
+template <typename TO>
+__global__ __launch_bounds__(256) void k_adj_p2mt2(const double* __restrict__ Mb, const double* __restrict__ Near,
+                                                   TO* __restrict__ drho, int n, int NM, int nmx) {
+  __shared__ double mrow[4][NTMAX];
+  const int nF = n >> 2, nFp = nF + 6;
+  const long long ncellp = (long long)nFp * nFp * nFp, nT = (long long)nF * nF * nF;
+  const int wv = threadIdx.x >> 6, sl = threadIdx.x & 63;
+  const long long T = blockIdx.x * 4LL + wv;
+  const bool okT = T < nT;
+  const long long Tq = okT ? T : 0;
+  const int t2 = (int)(Tq % nF), t1 = (int)((Tq / nF) % nF), t0 = (int)(Tq / ((long long)nF * nF));
+  const long long cp = ((long long)(t0 + 3) * nFp + (t1 + 3)) * nFp + (t2 + 3);
+  for (int a = sl; a < NM; a += 64) mrow[wv][a] = a < nmx ? Mb[((a >> 2) * ncellp + cp) * 4 + (a & 3)] : 0.0;
+  __syncthreads();
+  if (!okT) return;
+  const int s0 = sl >> 4, s1 = (sl >> 2) & 3, s2 = sl & 3;
+  const double w0 = (3 - 2 * s0) / 8.0, w1 = (3 - 2 * s1) / 8.0, w2 = (3 - 2 * s2) / 8.0;
+  const int P = mi_degree(nmx - 1);  // nmax (nmx = nterms(nmax) >= 1)
+  double acc = Near[((sl >> 2) * ncellp + cp) * 4 + (sl & 3)];
+  double px = 1.0;
+  for (int ax = 0; ax <= P; ++ax) {
+    double py = px;
+    for (int ay = 0; ax + ay <= P; ++ay) {
+      double pz = py;
+      for (int az = 0; ax + ay + az <= P; ++az) {
+        const int a = mi_index(ax, ay, az);
+        acc += c_mi_invfact[a] * pz * mrow[wv][a];
+        pz *= w2;
+      }
+      py *= w1;
+    }
+    px *= w0;
+  }
+  const long long u = ((long long)(4 * t0 + s0) * n + (4 * t1 + s1)) * n + (4 * t2 + s2);
+  drho[u] = (TO)acc;
+}
+
 // ---------------------------------------------------------------------------
 // launch helpers
 // ---------------------------------------------------------------------------
@@ -909,11 +990,11 @@ template <typename CT>
 hipError_t build_conv_table(fmm_plan* pl, int op, void** out, hipStream_t s) {
   using M = Mf<CT>;
   constexpr int EL = 64 / M::OPM;
-  const long long cnt = (long long)conv_nfrags(op, pl->p, M::KC) * NSLOT * EL * M::VPL;
+  const long long cnt = (long long)conv_nfrags(op, pl->p, M::KC) * conv_nslot(op) * EL * M::VPL;
   hipError_t e = hipMalloc(out, cnt * sizeof(typename M::H));
   if (e != hipSuccess) return e;
   pl->bytes += cnt * sizeof(typename M::H);
-  hipLaunchKernelGGL((k_expand_conv<CT>), dim3(blocks_for(cnt, 256)), dim3(256), 0, s, pl->dtab,
+  hipLaunchKernelGGL((k_expand_conv<CT>), dim3(blocks_for(cnt, 256)), dim3(256), 0, s, pl->dtab, pl->dtab2,
                      (typename M::H*)*out, op, pl->p, pl->ND);
   return hipGetLastError();
 }
@@ -933,7 +1014,7 @@ hipError_t build_tile_table(fmm_plan* pl, int op, hipStream_t s) {
     // terms; the transposes skip column tiles whose terms are all dropped
     if (op == CV_M2L)
       h[2 * t] = std::min(h[2 * t], (pl->NMX + KC - 1) / KC);
-    else if (mi_degree(16 * t) > pl->nmax)
+    else if (op != CV_P2PT2 && mi_degree(16 * t) > pl->nmax)
       h[2 * t] = 0;
     // the kernel takes the tiles that have a chunk to be a prefix of the group
     if (t > 0 && h[2 * t] > h[2 * t - 2]) return hipErrorInvalidValue;
@@ -1024,12 +1105,13 @@ hipError_t launch_conv_nt(fmm_plan* pl, const SegTable& st, const void* W, hipSt
   StageScope sc(pl, ST_M2L, 1, s);
   const int2* tiles = (const int2*)pl->tiletab[OP][Mf<CT>::IDX];
   const auto* w = (const typename Mf<CT>::H*)W;
+  const int* lists = OP == CV_P2PT2 ? pl->dlists_p2p : pl->dlists;
   if (st.cz == 8)
     hipLaunchKernelGGL((k_conv<P, CT, OP, NT, 8>), dim3((unsigned)G * st.blocks), dim3(M2L_THREADS), 0, s, st.dev,
-                       st.nseg, st.blocks, tiles, w, pl->dlists);
+                       st.nseg, st.blocks, tiles, w, lists);
   else
     hipLaunchKernelGGL((k_conv<P, CT, OP, NT, 16>), dim3((unsigned)G * st.blocks), dim3(M2L_THREADS), 0, s, st.dev,
-                       st.nseg, st.blocks, tiles, w, pl->dlists);
+                       st.nseg, st.blocks, tiles, w, lists);
   return hipGetLastError();
 }
 
@@ -1133,10 +1215,31 @@ hipError_t solve_ct(fmm_plan* pl, IoArg io, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // adjoint solve (field 0)
 // ---------------------------------------------------------------------------
+// The transposed M2P, and for FMM-2 the transposed near field, in one
+// compute type.
+template <typename CT>
+hipError_t adjoint_bottom_tables(fmm_plan* pl, hipStream_t s) {
+  constexpr int X = Mf<CT>::IDX;
+  const int op = pl->dl == 2 ? CV_M2PT2 : CV_M2PT;
+  hipError_t e;
+  if ((e = build_tile_table<CT>(pl, op, s)) != hipSuccess) return e;
+  if ((e = build_conv_table<CT>(pl, op, &pl->wt_m2p[X], s)) != hipSuccess) return e;
+  if (pl->dl == 2) {
+    if ((e = build_tile_table<CT>(pl, CV_P2PT2, s)) != hipSuccess) return e;
+    if ((e = build_conv_table<CT>(pl, CV_P2PT2, &pl->wt_p2p[X], s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t adjoint_tables_all(fmm_plan* pl, hipStream_t s) {
   hipError_t e;
   const int NL = pl->NL;
-  hipLaunchKernelGGL(k_adj_coef, dim3(blocks_for(9LL * NL * 32, 256)), dim3(256), 0, s, pl->adj_l2p, pl->adj_l2p2, NL);
+  if (pl->dl == 2)
+    hipLaunchKernelGGL(k_adj_coef2, dim3(blocks_for(72LL * NL * 32, 256)), dim3(256), 0, s, pl->adj_l2p,
+                       pl->adj_l2p2, NL);
+  else
+    hipLaunchKernelGGL(k_adj_coef, dim3(blocks_for(9LL * NL * 32, 256)), dim3(256), 0, s, pl->adj_l2p,
+                       pl->adj_l2p2, NL);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // the transposed M2L of target levels k < klow runs in FP64, the others in
   // the plan's compute type
@@ -1154,33 +1257,35 @@ hipError_t adjoint_tables_all(fmm_plan* pl, hipStream_t s) {
                                (e = build_tile_table<bf16_tag>(pl, CV_M2LT, s)) != hipSuccess))
       return e;
   }
-  if (!bottom_low(pl, pl->F)) {
-    if ((e = build_tile_table<double>(pl, CV_M2PT, s)) != hipSuccess) return e;
-    return build_conv_table<double>(pl, CV_M2PT, &pl->wt_m2p[0], s);
-  }
-  if (pl->precision == 1) {
-    if ((e = build_tile_table<float>(pl, CV_M2PT, s)) != hipSuccess) return e;
-    return build_conv_table<float>(pl, CV_M2PT, &pl->wt_m2p[1], s);
-  }
-  if ((e = build_tile_table<bf16_tag>(pl, CV_M2PT, s)) != hipSuccess) return e;
-  return build_conv_table<bf16_tag>(pl, CV_M2PT, &pl->wt_m2p[2], s);
+  if (!bottom_low(pl, pl->F)) return adjoint_bottom_tables<double>(pl, s);
+  if (pl->precision == 1) return adjoint_bottom_tables<float>(pl, s);
+  return adjoint_bottom_tables<bf16_tag>(pl, s);
 }
 
 template <int P, typename CT, typename TI, typename TO>
 hipError_t backward_ct(fmm_plan* pl, const AdjWs& w, const TI* dphi, const TI* dg, TO* drho, hipStream_t s) {
   constexpr int NL = nterms(P);
-  const int n = pl->n, F = pl->F, nF = n / 2;
+  const int n = pl->n, F = pl->F, dl = pl->dl, nF = n >> dl;
   const double dx = pl->dx;
   hipError_t e;
   const long long nT = (long long)nF * nF * nF;
-  hipLaunchKernelGGL((k_adj_seed<TI>), dim3(blocks_for(nT, 256)), dim3(256), 0, s, dphi, dg, w.ybar, n,
-                     0.5 * dx * dx, -0.25 * dx);
+  // the scale of the bottom accumulators (k_bottom): phi = sphi acc, g = sg acc
+  if (dl == 2)
+    hipLaunchKernelGGL((k_adj_seed<TI, 2>), dim3(blocks_for(nT, 256)), dim3(256), 0, s, dphi, dg, w.ybar, n,
+                       0.25 * dx * dx, -0.0625 * dx);
+  else
+    hipLaunchKernelGGL((k_adj_seed<TI, 1>), dim3(blocks_for(nT, 256)), dim3(256), 0, s, dphi, dg, w.ybar, n,
+                       0.5 * dx * dx, -0.25 * dx);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (F >= 3) {
     // transposed L2P of the own local and of the parent level's local
     const long long nP = nT / 8;
-    hipLaunchKernelGGL(k_adj_l2p<P>, dim3(blocks_for(nP, ADJ_L2P_PAR)), dim3(ADJ_L2P_THREADS), 0, s, w.ybar,
-                       pl->adj_l2p, pl->adj_l2p2, w.abar[F], F >= 4 ? w.abar[F - 1] : nullptr, nF);
+    if (dl == 2)
+      hipLaunchKernelGGL((k_adj_l2p<P, 2>), dim3(blocks_for(nP, ADJ_L2P_PAR)), dim3(ADJ_L2P_THREADS), 0, s, w.ybar,
+                         pl->adj_l2p, pl->adj_l2p2, w.abar[F], F >= 4 ? w.abar[F - 1] : nullptr, nF);
+    else
+      hipLaunchKernelGGL((k_adj_l2p<P, 1>), dim3(blocks_for(nP, ADJ_L2P_PAR)), dim3(ADJ_L2P_THREADS), 0, s, w.ybar,
+                         pl->adj_l2p, pl->adj_l2p2, w.abar[F], F >= 4 ? w.abar[F - 1] : nullptr, nF);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // transposed L2L chain, fine to coarse
     for (int k = F - 1; k >= 4; --k) {
@@ -1195,11 +1300,19 @@ hipError_t backward_ct(fmm_plan* pl, const AdjWs& w, const TI* dphi, const TI* d
       if ((e = launch_conv<P, CT, CV_M2LT>(pl, w.m2lt[1], pl->wt_m2l[Mf<CT>::IDX], s)) != hipSuccess) return e;
     if ((e = launch_split_reduce(pl, w.m2lt_red, s)) != hipSuccess) return e;
   }
-  // transposed M2P at the finest level
-  if (bottom_low(pl, F))
-    e = launch_conv<P, CT, CV_M2PT>(pl, w.m2pt, pl->wt_m2p[Mf<CT>::IDX], s);
-  else
-    e = launch_conv<P, double, CV_M2PT>(pl, w.m2pt, pl->wt_m2p[0], s);
+  // transposed M2P at the finest level (and for FMM-2 the transposed near
+  // field, on the same pattern over the 27 adjacent cells)
+  const bool low = bottom_low(pl, F);
+  if (dl == 2) {
+    e = low ? launch_conv<P, CT, CV_M2PT2>(pl, w.m2pt, pl->wt_m2p[Mf<CT>::IDX], s)
+            : launch_conv<P, double, CV_M2PT2>(pl, w.m2pt, pl->wt_m2p[0], s);
+    if (e == hipSuccess)
+      e = low ? launch_conv<P, CT, CV_P2PT2>(pl, w.p2pt, pl->wt_p2p[Mf<CT>::IDX], s)
+              : launch_conv<P, double, CV_P2PT2>(pl, w.p2pt, pl->wt_p2p[0], s);
+  } else {
+    e = low ? launch_conv<P, CT, CV_M2PT>(pl, w.m2pt, pl->wt_m2p[Mf<CT>::IDX], s)
+            : launch_conv<P, double, CV_M2PT>(pl, w.m2pt, pl->wt_m2p[0], s);
+  }
   if (e != hipSuccess) return e;
   // transposed M2M chain, coarse to fine
   for (int k = 3; k <= F; ++k) {
@@ -1208,6 +1321,11 @@ hipError_t backward_ct(fmm_plan* pl, const AdjWs& w, const TI* dphi, const TI* d
                        0, s, (const double*)pl->lev[k - 1].M, (double*)pl->lev[k].M, np, pl->m2mt_start,
                        pl->m2mt_a, pl->m2mt_coef, pl->NMX);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (dl == 2) {
+    hipLaunchKernelGGL((k_adj_p2mt2<TO>), dim3(blocks_for(nT, 4)), dim3(256), 0, s, (const double*)pl->lev[F].M,
+                       w.near, drho, n, pl->NM, pl->NMX);
+    return hipGetLastError();
   }
   // nF is a power of two >= 4: the block's z extent divides it
   const int tz = nF < ADJ_BOT_TZ ? nF : ADJ_BOT_TZ;

@@ -74,10 +74,25 @@ constexpr __host__ __device__ int m2l_tile_chunks(int P, int t, int KC = 4) {
 //            (q, b) of the targets' parents, N = multipole terms a
 //   CV_M2PT  transposed M2P: rows = level-F cells J, K = the 32 adjoint
 //            outputs (q, o) of a target cell, N = multipole terms a
+//   CV_M2PT2 the same for FMM-2 (App. A): K = the 256 adjoint outputs
+//            (g, q, o) of the 64 unigrid cells of a target cell
+//   CV_P2PT2 transposed near field of FMM-2: rows = level-F cells W, the 27
+//            offsets of the adjacent cells, K = the 256 adjoint outputs of
+//            an adjacent cell, N = the 64 unigrid (source) cells of W
 // The interaction relation is symmetric (J is in the list of P iff P is in
-// the list of J), so all three walk the same per-parity offset lists.
+// the list of J), so the first four walk the same per-parity offset lists;
+// CV_P2PT2 walks the 27 neighbour offsets.
 // ---------------------------------------------------------------------------
-enum ConvOp { CV_M2L = 0, CV_M2LT = 1, CV_M2PT = 2 };
+enum ConvOp { CV_M2L = 0, CV_M2LT = 1, CV_M2PT = 2, CV_M2PT2 = 3, CV_P2PT2 = 4, CV_NOPS = 5 };
+constexpr int NP2P = 27;       // near-field offsets of a finest FMM cell
+constexpr int NSLOT_P2P = 28;  // their B-table slots: 27 offsets + the null one
+// offsets in a convolution's list, and the B-table slots they index
+constexpr __host__ __device__ int conv_noff(int op) { return op == CV_P2PT2 ? NP2P : 189; }
+constexpr __host__ __device__ int conv_nslot(int op) { return op == CV_P2PT2 ? NSLOT_P2P : 344; }
+// output columns: local columns (M2L), multipole terms, or 64 unigrid cells
+constexpr __host__ __device__ int conv_ncols(int op, int P) {
+  return op == CV_M2L ? 8 * nterms(P) : (op == CV_P2PT2 ? 64 : nterms(P));
+}
 // degree of multipole term index a
 constexpr __host__ __device__ int mi_degree(int a) {
   int m = 0;
@@ -85,14 +100,15 @@ constexpr __host__ __device__ int mi_degree(int a) {
   return m;
 }
 constexpr __host__ __device__ int conv_nk(int op, int P) {
-  return op == CV_M2L ? nterms(P) : (op == CV_M2LT ? loc_stride(P) : 32);
+  return op == CV_M2L ? nterms(P) : (op == CV_M2LT ? loc_stride(P) : (op == CV_M2PT ? 32 : 256));
 }
 constexpr __host__ __device__ int conv_ntiles(int op, int P) {
-  return op == CV_M2L ? m2l_ntiles(P) : (nterms(P) + 15) / 16;
+  return op == CV_M2L ? m2l_ntiles(P) : (conv_ncols(op, P) + 15) / 16;
 }
 constexpr __host__ __device__ int conv_tile_chunks(int op, int P, int t, int KC) {
   return op == CV_M2L ? m2l_tile_chunks(P, t, KC)
-                      : (op == CV_M2LT ? (8 * nterms(P - mi_degree(16 * t)) + KC - 1) / KC : (32 + KC - 1) / KC);
+                      : (op == CV_M2LT ? (8 * nterms(P - mi_degree(16 * t)) + KC - 1) / KC
+                                       : (conv_nk(op, P) + KC - 1) / KC);
 }
 constexpr __host__ __device__ int conv_frag_offset(int op, int P, int t, int KC) {
   int f = 0;
@@ -211,7 +227,8 @@ struct AdjWs {
   double* ybar = nullptr;    // [YC][(nF+6)^3][4], YC = 8^dl chunks of (phi, gx, gy, gz)
   double* abar[16] = {};     // level k: [loc_stride/4][(2^(k-1)+6)^3][4]
   double* part = nullptr;    // split partial sums of the transposed M2L (null: unsplit)
-  SegTable m2lt[2], m2pt, m2lt_red;
+  double* near = nullptr;    // FMM-2: the near-field transpose per finest cell, [16][(nF+6)^3][4]
+  SegTable m2lt[2], m2pt, m2lt_red, p2pt;
 };
 // Static workspace of fmm_solve_backward_noalloc (bytes per device) and the
 // most segments its tables hold.
@@ -267,10 +284,12 @@ struct fmm_plan {
   int adj_tables = 0;           // the tables below are built
   int adj_ready = 0;            // `adj` is allocated
   fmm::AdjWs adj;
-  double* adj_l2p = nullptr;    // [NL][32]     L2P coefficients
-  double* adj_l2p2 = nullptr;   // [8][NL][32]  parent-level L2P coefficients
+  double* adj_l2p = nullptr;    // [G][NL][32]     L2P coefficients (G = 8^(dl-1) groups of 8 unigrid cells)
+  double* adj_l2p2 = nullptr;   // [G][8][NL][32]  parent-level L2P coefficients
   void* wt_m2l[3] = {nullptr, nullptr, nullptr};  // transposed M2L B fragments
-  void* wt_m2p[3] = {nullptr, nullptr, nullptr};  // transposed M2P B fragments
+  void* wt_m2p[3] = {nullptr, nullptr, nullptr};  // transposed M2P B fragments (CV_M2PT2 for dl = 2)
+  void* wt_p2p[3] = {nullptr, nullptr, nullptr};  // dl = 2: transposed near field B fragments
+  int* dlists_p2p = nullptr;    // dl = 2: [8][NLIST_PAD] the 27 neighbour offsets (+ null) per parity
   int* m2m_start = nullptr;     // M2M coefficient lists (CSR over multipole terms)
   int* m2m_off = nullptr;       // 8 b + parity pattern of g, for b + g = a
   double* m2m_coef = nullptr;   // 2^-|b| 4^-|g| / g!
@@ -291,7 +310,7 @@ struct fmm_plan {
   double* conv_part = nullptr;      // partial sums of split forward M2L segments
   // per convolution kind and compute type: (K chunks, first fragment) of
   // every column tile, zero-padded past the last tile
-  int* tiletab[3][3] = {};
+  int* tiletab[fmm::CV_NOPS][3] = {};
   // batches
   int batch = 0;                    // nonzero for fmm_batch_plan_create plans
   fmm::Io* io = nullptr;            // device I/O table, one entry per field

@@ -746,8 +746,10 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   using Acc = typename M::Acc;
   constexpr int KC = M::KC, OPM = M::OPM, VPL = M::VPL, EL = 64 / OPM;
   constexpr int NC4 = (conv_nk(OP, P) + 3) / 4;  // 4-term chunks of the operand grid
-  constexpr int NM = nterms(P), NCOL = 8 * nterms(P), NTILES = conv_ntiles(OP, P);
-  constexpr int NGRP = (NLIST + OPM - 1) / OPM;
+  constexpr int NCOL = 8 * nterms(P), NTILES = conv_ntiles(OP, P);
+  constexpr int NCO = conv_ncols(OP, P);  // output columns (transposes: the chunked output grid's terms)
+  constexpr int NOFF = conv_noff(OP), NS = conv_nslot(OP);  // list offsets, B-table slots
+  constexpr int NGRP = (NOFF + OPM - 1) / OPM;
   using S = BotShape<CZ>;
   constexpr int CMT = S::MT;  // row tiles per wave
   constexpr int BZ2 = S::BZ2, YPT = S::YPT, TPX = S::TPX;
@@ -792,11 +794,11 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   const int* dl = slist + r * NLIST_PAD;  // visible after the first chunk's barrier
   // the rotation of the offset order must be the same for every part of a
   // split tile (the parts take consecutive slices of one ordering)
-  const int rot = (int)(((unsigned)(sg.first_block + tb * split) * 37u) % NLIST);
+  const int rot = (int)(((unsigned)(sg.first_block + tb * split) * 37u) % NOFF);
   auto entry = [&](int pos) {
-    if (pos >= NLIST) return dl[NLIST];
+    if (pos >= NOFF) return dl[NOFF];
     pos += rot;
-    return dl[pos < NLIST ? pos : pos - NLIST];
+    return dl[pos < NOFF ? pos : pos - NOFF];
   };
   // Packed groups: M2L column tiles of degree p need the single multipole
   // term a = 0, so one K chunk would carry one useful term in KC.  With one
@@ -814,12 +816,12 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   auto offsets = [&](auto pk, auto na, int c) {
     constexpr bool PK = decltype(pk)::value;
     constexpr int NA = decltype(na)::value;  // column tiles with chunk c (the first NA)
-    constexpr int NG = PK ? (NLIST + 3) / 4 : NGRP;
+    constexpr int NG = PK ? (NOFF + 3) / 4 : NGRP;
     const int ja = part * NG / split, jb = (part + 1) * NG / split;
     const H* wl = Wt + (PK ? i : lr.tl) * VPL;
     const H* hl = PK ? hlane - lr.tic : hlane;
     auto bload = [&](EntryGroup g, int t) {
-      return *reinterpret_cast<const AF*>(wl + ((size_t)(off[t] + c) * NSLOT + dl_dd(g.e)) * EL * VPL);
+      return *reinterpret_cast<const AF*>(wl + ((size_t)(off[t] + c) * NS + dl_dd(g.e)) * EL * VPL);
     };
     auto group = [&](int j) {
       EntryGroup g;
@@ -916,7 +918,7 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
           if (T0 + t < NTILES) o[16 * t] = ldexp((double)acc[m][t][v], escale[t]);
       }
   } else {
-    if (split > 1) dst += (long long)part * ((NM + 3) / 4) * ncellp * 4;
+    if (split > 1) dst += (long long)part * ((NCO + 3) / 4) * ncellp * 4;
 #pragma unroll
     for (int m = 0; m < CMT; ++m)
 #pragma unroll
@@ -929,7 +931,7 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
           const int a = 16 * (T0 + t) + i;
-          if (a < NM) dst[((a >> 2) * ncellp + cp) * 4 + (a & 3)] = (double)acc[m][t][v];
+          if (a < NCO) dst[((a >> 2) * ncellp + cp) * 4 + (a & 3)] = (double)acc[m][t][v];
         }
       }
   }
@@ -941,15 +943,15 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
 // (0 where the truncation |a| + |b| <= p drops the pair, past the ends, and in
 // the null slot).
 template <typename CT>
-__global__ void k_expand_conv(const double* __restrict__ Dtab, typename Mf<CT>::H* __restrict__ W, int op, int P,
-                              int ND) {
+__global__ void k_expand_conv(const double* __restrict__ Dtab, const double* __restrict__ Dtab2,
+                              typename Mf<CT>::H* __restrict__ W, int op, int P, int ND) {
   using M = Mf<CT>;
   constexpr int KC = M::KC, OPM = M::OPM, VPL = M::VPL, EL = 64 / OPM;
-  const int NF = conv_nfrags(op, P, KC);
+  const int NF = conv_nfrags(op, P, KC), NS = conv_nslot(op);
   const long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (id >= (long long)NF * NSLOT * EL * VPL) return;
+  if (id >= (long long)NF * NS * EL * VPL) return;
   const int v = (int)(id % VPL), el = (int)((id / VPL) % EL);
-  const int slot = (int)((id / ((long long)VPL * EL)) % NSLOT), f = (int)(id / ((long long)VPL * EL * NSLOT));
+  const int slot = (int)((id / ((long long)VPL * EL)) % NS), f = (int)(id / ((long long)VPL * EL * NS));
   int t = 0;
   while (conv_frag_offset(op, P, t + 1, KC) <= f) ++t;
   const int c = f - conv_frag_offset(op, P, t, KC);
@@ -958,7 +960,28 @@ __global__ void k_expand_conv(const double* __restrict__ Dtab, typename Mf<CT>::
   const int col = 16 * t + j, kk = KC * c + tic + v;
   const int NM = nterms(P);
   double val = 0.0;
-  if (slot < 343) {
+  if (op == CV_P2PT2) {
+    // K = (g, q, o) of a unigrid target u of the adjacent cell W - d, column
+    // = unigrid source s of W: the near-field coefficient at delta = u - w
+    if (slot < NP2P && kk < 256) {
+      const int d[3] = {slot / 9 - 1, (slot / 3) % 3 - 1, slot % 3 - 1};
+      const int cq = kk >> 2, o = kk & 3, g = cq >> 3, q = cq & 7;
+      const int sw[3] = {(col >> 4) & 3, (col >> 2) & 3, col & 3};
+      int dl3[3];
+      for (int ax = 0; ax < 3; ++ax) dl3[ax] = -4 * d[ax] + sub_pos(g, q, ax) - sw[ax];
+      val = p2p2_delta_coef(dl3[0], dl3[1], dl3[2], o);
+    }
+  } else if (op == CV_M2PT2) {
+    // K = (g, q, o), column = multipole term a, the derivative at the
+    // negated offset and the unigrid position of (g, q)
+    const int ns = 342 - slot;
+    if (slot < 343 && col < NM && kk < 256) {
+      const int aex = c_mi_exp[col];
+      const int cq = kk >> 2, o = kk & 3, g = cq >> 3, q = cq & 7;
+      const int sub = (sub_pos(g, q, 0) << 4) | (sub_pos(g, q, 1) << 2) | sub_pos(g, q, 2);
+      val = Dtab2[((size_t)ns * 64 + sub) * ND + mi_index(mi_a(aex) + (o == 1), mi_b(aex) + (o == 2), mi_c(aex) + (o == 3))];
+    }
+  } else if (slot < 343) {
     if (op == CV_M2L) {
       // K = multipole term a, column (q, b)
       if (col < 8 * NM && kk < NM) {

@@ -140,13 +140,95 @@ def test_fmm2_mixed_precision_matches_oracle(F, orc, precision, n, p, coarse):
 
 
 def test_fmm2_rejections(F):
-    import torch
     _say("case fmm2 rejections")
     with pytest.raises(F.FmmError):
         F.Plan(8, 4, "fp64", delta_l=2)          # needs n >= 16
     with pytest.raises(F.FmmError):
         F.Plan(32, 4, "fp64", delta_l=3)
-    plan = F.Plan(16, 4, "fp64", delta_l=2)
-    x = torch.zeros(16, 16, 16, dtype=torch.float64, device="cuda")
     with pytest.raises(F.FmmError):
-        plan.backward(x, None)
+        F.Plan(32, 4, "fp64", delta_l=2, bottom_tile=8)
+
+
+# --------------------------------------------------------------------------
+# the backward pass of FMM-2 plans
+# --------------------------------------------------------------------------
+def _cot(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n, n, n)), rng.standard_normal((3, n, n, n))
+
+
+def _gpu_bwd(F, n, p, dphi, dg, precision="fp64", nmax=None, coarse=4):
+    import torch
+    plan = F.Plan(n, p, precision, nmax=nmax, coarse_fp64_levels=coarse, delta_l=2)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    a = torch.as_tensor(dphi).to("cuda", dt).contiguous()
+    b = None if dg is None else torch.as_tensor(dg).to("cuda", dt).contiguous()
+    out = plan.backward(a, b)
+    torch.cuda.synchronize()
+    return out.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("n,p,nmax", [(16, 4, None), (32, 6, None), (32, 3, 2), (64, 6, None), (64, 2, None),
+                                      (32, 8, None)])
+def test_fmm2_adjoint_matches_oracle(F, orc, n, p, nmax):
+    """Every cell against the oracle's explicit transposes of FMM-2: 16^3
+    (no locals), 32^3 (locals at one level) and 64^3 (parent-level L2P and
+    the L2L chain)."""
+    _say(f"case fmm2 adjoint fp64 n={n} p={p} nmax={nmax}")
+    dphi, dg = _cot(n, 500 + n + p)
+    got = _gpu_bwd(F, n, p, dphi, dg, nmax=nmax)
+    ref = orc.adjoint(dphi, dg, p, nmax=nmax, delta_l=2)
+    e, c = rel(got, ref), float(np.abs(got - ref).max() / np.abs(ref).max())
+    _say(f"  rel L2 {e:.2e}, per cell {c:.2e}")
+    assert e <= TOL64 and c <= TOL64, (e, c)
+    got = _gpu_bwd(F, n, p, dphi, None, nmax=nmax)
+    assert rel(got, orc.adjoint(dphi, None, p, nmax=nmax, delta_l=2)) <= TOL64
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_fmm2_adjoint_dot_product(F, n):
+    """<A rho, (psi, chi)> = <rho, A^T (psi, chi)> with the GPU's own FMM-2
+    forward solve, at the sizes the benchmark runs (exact up to rounding)."""
+    import torch
+    _say(f"case fmm2 dot product fp64 n={n} p=6")
+    plan = F.Plan(n, 6, "fp64", delta_l=2)
+    rho = fi.plummer_density(n, fi.multi_plummer_params(16, 9 + n), device="cuda")
+    gen = torch.Generator(device="cuda").manual_seed(n)
+    psi = torch.randn((n, n, n), dtype=torch.float64, device="cuda", generator=gen)
+    chi = torch.randn((3, n, n, n), dtype=torch.float64, device="cuda", generator=gen)
+    phi, g = plan.solve(rho)
+    lhs = float((phi * psi).sum() + (g * chi).sum())
+    rhs = float((rho * plan.backward(psi, chi)).sum())
+    scale = float(phi.norm() * psi.norm() + g.norm() * chi.norm())
+    _say(f"  |lhs - rhs| / scale = {abs(lhs - rhs) / scale:.2e}")
+    assert abs(lhs - rhs) <= 1e-13 * scale, (lhs, rhs, scale)
+
+
+@pytest.mark.parametrize("precision,bar", [("fp32", 1e-4), ("bf16", 5e-2)])
+def test_fmm2_adjoint_mixed(F, orc, precision, bar):
+    """Low-precision FMM-2 adjoint on every level (threshold 0) against the
+    oracle, relative L2 and per cell."""
+    _say(f"case fmm2 adjoint {precision} n=64 p=6")
+    dphi, dg = _cot(64, 41)
+    d32, g32 = dphi.astype(np.float32), dg.astype(np.float32)
+    got = _gpu_bwd(F, 64, 6, d32, g32, precision, coarse=0)
+    ref = orc.adjoint(d32.astype(np.float64), g32.astype(np.float64), 6, delta_l=2)
+    e, c = rel(got, ref), float(np.abs(got - ref).max() / np.abs(ref).max())
+    _say(f"  rel L2 {e:.2e}, per cell {c:.2e}")
+    assert e < bar and c < bar, (e, c)
+
+
+def test_fmm2_autograd(F, orc):
+    """torch.autograd through an FMM-2 plan: the gradient of sum (phi - phi_t)^2
+    is the oracle's FMM-2 adjoint of 2 (phi - phi_t)."""
+    import torch
+    n, p = 32, 4
+    _say("case fmm2 autograd n=32 p=4")
+    rho = fi.plummer_density(n, fi.multi_plummer_params(16, 5001))
+    phi_t, _ = orc.solve(fi.plummer_density(n, fi.multi_plummer_params(16, 5002)), p, delta_l=2)
+    plan = F.Plan(n, p, delta_l=2)
+    x = torch.as_tensor(rho, device="cuda").requires_grad_(True)
+    phi, g = F.solve(plan, x)
+    ((phi - torch.as_tensor(phi_t, device="cuda")) ** 2).sum().backward()
+    r = phi.detach().cpu().numpy() - phi_t
+    assert rel(x.grad.cpu().numpy(), orc.adjoint(2 * r, None, p, delta_l=2)) < TOL64

@@ -5,8 +5,8 @@ Two calls in a row, the second on a smaller plan (so it finds the first
 call's contents in the static array), in FP64 (bar: relative L2 and per-cell
 max|err|/max|ref| <= 1e-12, the FP64 tolerance; the two entry points differ
 only in the rounding order of the transposed M2L's sums), one FP32 plan (the
-FP32 adjoint bar, 1e-4), and a plan too large for the array, which must be
-rejected before anything is enqueued.
+FP32 adjoint bar, 1e-4), an FMM-2 plan, and a plan too large for the array,
+which must be rejected before anything is enqueued.
 """
 import ctypes
 import sys
@@ -36,11 +36,11 @@ def _cmp(got, ref):
             float(np.abs(got - ref).max() / np.abs(ref).max()))
 
 
-def _both(F, n, p, precision, seed, coarse=4):
+def _both(F, n, p, precision, seed, coarse=4, delta_l=1):
     """(noalloc result, regular result) for one plan and seeded cotangents."""
     import torch
     dt = torch.float64 if precision == "fp64" else torch.float32
-    plan = F.Plan(n, p, precision, coarse_fp64_levels=coarse)
+    plan = F.Plan(n, p, precision, coarse_fp64_levels=coarse, delta_l=delta_l)
     gen = torch.Generator(device="cuda").manual_seed(seed)
     dphi = torch.randn((n, n, n), dtype=dt, device="cuda", generator=gen)
     dg = torch.randn((3, n, n, n), dtype=dt, device="cuda", generator=gen)
@@ -73,6 +73,14 @@ def test_noalloc_fp32(F):
     e = _cmp(out, ref)
     _say(f"  rel L2 {e[0]:.2e}, per cell {e[1]:.2e}")
     assert e[0] <= 1e-4 and e[1] <= 1e-4, e
+
+
+def test_noalloc_fmm2(F):
+    _say("case noalloc fp64 FMM-2 n=64 p=6")
+    out, ref, _ = _both(F, 64, 6, "fp64", 4, delta_l=2)
+    e = _cmp(out, ref)
+    _say(f"  rel L2 {e[0]:.2e}, per cell {e[1]:.2e}")
+    assert e[0] <= 1e-12 and e[1] <= 1e-12, e
 
 
 def test_noalloc_rejects_plans_too_large(F):
