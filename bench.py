@@ -82,7 +82,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed-precision, equal-accuracy, adjoint and batch sections")
     ap.add_argument("--section", default=None,
-                    choices=["mixed", "fmm2", "particles", "adjoint", "batch", "large", "huge"],
+                    choices=["mixed", "fmm2", "particles", "adjoint", "batch", "large", "huge", "cpu"],
                     help="run only this extra section (for profiling) and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one plain device-to-device copy of BYTES bytes (a known-size "
@@ -148,8 +148,91 @@ def run_large(fi, fmm, costs, n: int = 512, p: int = 6) -> dict:
     return out
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
+def run_cpu_oracle(fi, fmm, n: int = 128, p: int = 6) -> dict:
+    """The CPU baseline workload (128^3, p = 6, FP64, 32 spheres, seed 128):
+    the oracle's full solve on all host threads (measured, not
+    extrapolated), a bounded sample on one thread (the full upward pass and
+    the downward pass for 2 central planes), and the GPU solve of the same
+    input beside them, compared with the oracle on every cell."""
+    import numpy as np
+    import torch
+    import oracle
+    rho = fi.plummer_density(n, fi.multi_plummer_params(32, 128))
+    nthr = oracle.threads()
+    log(f"cpu oracle: full {n}^3 p={p} solve on {nthr} threads")
+    t0 = time.perf_counter()
+    phi_o, g_o = oracle.solve(rho, p)
+    t_all = time.perf_counter() - t0
+    planes = 2
+    i0 = n // 2 - planes // 2
+    cells = np.arange(i0 * n * n, (i0 + planes) * n * n, dtype=np.int64)
+    oracle.set_threads(1)
+    try:
+        log(f"cpu oracle: one thread, upward pass + {planes} planes")
+        _, _, t_up1, t_down1, _ = oracle.solve_timed(rho, p, cells)
+    finally:
+        oracle.set_threads(nthr)
+    t_one = t_up1 + t_down1 * n ** 3 / len(cells)
+    plan = fmm.Plan(n, p, "fp64")
+    r = torch.as_tensor(rho, device="cuda")
+    phi = torch.empty((n, n, n), dtype=torch.float64, device="cuda")
+    g = torch.empty((3, n, n, n), dtype=torch.float64, device="cuda")
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+    for _ in range(3):
+        plan.solve_into(r, phi, g)
+    for a, b in evs:
+        a.record()
+        plan.solve_into(r, phi, g)
+        b.record()
+    torch.cuda.synchronize()
+    gpu_ms = float(np.median([a.elapsed_time(b) for a, b in evs]))
+    ph, gg = phi.cpu().numpy(), g.cpu().numpy()
+    out = {
+        "workload": f"{n}^3 unigrid, p={p}, FP64, phi+g, 32 Plummer spheres (seed 128)",
+        "cpu_model": cpu_model(),
+        "all_threads": {"threads": nthr, "seconds": t_all, "cells_per_s": n ** 3 / t_all,
+                        "sample": "the full solve, measured"},
+        "one_thread": {"threads": 1, "seconds_estimated": t_one, "cells_per_s": n ** 3 / t_one,
+                       "sample": f"full upward pass ({t_up1:.2f} s) + downward pass for {planes} central planes "
+                                 f"({len(cells)} cells, {t_down1:.2f} s), scaled to the full grid"},
+        "thread_speedup": t_one / t_all,
+        "gpu_fp64_ms_median": gpu_ms,
+        "gpu_cells_per_s": n ** 3 / (gpu_ms * 1e-3),
+        "gpu_vs_cpu_all_threads": t_all / (gpu_ms * 1e-3),
+        "dense_parity": {"phi_rel_l2": _rel(ph, phi_o), "g_rel_l2": _rel(gg, g_o),
+                         "phi_max_over_max": float(np.abs(ph - phi_o).max() / np.abs(phi_o).max()),
+                         "g_max_over_max": float(np.abs(gg - g_o).max() / np.abs(g_o).max())},
+    }
+    log(f"cpu oracle: {t_all:.1f} s on {nthr} threads, ~{t_one:.0f} s on one; GPU {gpu_ms:.2f} ms; "
+        f"dense parity phi {out['dense_parity']['phi_rel_l2']:.2e}")
+    return out
+
+
+def paper_flop_table(costs) -> dict:
+    """The paper's per-operator counts (Sec. 4, p = 3, nmax = 2) beside this
+    library's counting of the same operators."""
+    ours = costs.operator_counts(3, 2)
+    tab = {}
+    for op, paper in costs.PAPER_SEC4.items():
+        v = ours[op]
+        tab[op] = {"paper": paper, "ours_phi_only": v[0] if isinstance(v, tuple) else v,
+                   "ours_phi_and_g": v[1] if isinstance(v, tuple) else v}
+    return tab
+
+
 def run_extras(args, rho64, fi, fmm, costs,
-               sections=("mixed", "fmm2", "particles", "adjoint", "batch", "large")) -> dict:
+               sections=("mixed", "fmm2", "particles", "adjoint", "batch", "large", "cpu")) -> dict:
     """The other measured rows at the same workload: mixed precision (with
     the equal-accuracy comparison against FP64 at lower order), the adjoint,
     and the uneven 96-field batch against a loop of single solves."""
@@ -339,6 +422,9 @@ def run_extras(args, rho64, fi, fmm, costs,
     if adj:
         out["adjoint"] = adj
     torch.cuda.empty_cache()
+    if "cpu" in sections:
+        out["cpu_oracle"] = run_cpu_oracle(fi, fmm)
+        torch.cuda.empty_cache()
     if "large" in sections:
         out["large_512"] = run_large(fi, fmm, costs)
     if "huge" in sections:
@@ -356,6 +442,18 @@ def run_extras(args, rho64, fi, fmm, costs,
         gs = [torch.empty((3, m, m, m), dtype=torch.float32, device="cuda") for m in sizes]
         ms_b = _event_ms(lambda: B.solve_into(rhos, phis, gs), 5, 2)
         info = B.info()
+        # per-field latency: device wall-clock time from the start of a
+        # graph-replayed batch solve to the end of each field's last block
+        B.timestamps(True)
+        for _ in range(3):
+            B.solve_into(rhos, phis, gs)
+        fms = np.array(B.field_ms())
+        B.timestamps(False)
+        lat = {"all": {"min_ms": float(fms.min()), "median_ms": float(np.median(fms)), "max_ms": float(fms.max())}}
+        for m in sorted(set(sizes)):
+            sel = fms[[i for i, x in enumerate(sizes) if x == m]]
+            lat[f"{m}^3"] = {"fields": int(len(sel)), "min_ms": float(sel.min()), "median_ms": float(np.median(sel)),
+                             "max_ms": float(sel.max())}
         del B
         singles = [fmm.Plan(m, q, "fp32") for m in sizes]
         ms_l = _event_ms(lambda: [pl.solve_into(r, ph, gg) for pl, r, ph, gg in zip(singles, rhos, phis, gs)], 3, 1)
@@ -369,6 +467,7 @@ def run_extras(args, rho64, fi, fmm, costs,
             "speedup_vs_loop": ms_l / ms_b,
             "autotuned": {"bottom_tile": info["bottom_tile"], "m2l_grouping": info["m2l_grouping"],
                           "candidate_ms": info["tune_ms"]},
+            "field_latency": lat,
         }
         log(f"extras: batch p={q}: {ms_b:.2f} ms ({cells_b / (ms_b * 1e-3):.3e} cells/s), loop {ms_l:.2f} ms")
         torch.cuda.empty_cache()
@@ -497,21 +596,13 @@ def main():
         rho_host = rho64.cpu().numpy() if prec == "fp64" else rho.double().cpu().numpy()
         phi_o, g_o, t_up, t_down, threads = oracle.solve_timed(rho_host, p, cells, delta_l=dl)
         t_full = t_up + t_down * (n ** 3 / len(cells))
-        cpu_model = "unknown CPU"
-        try:
-            with open("/proc/cpuinfo") as f:
-                for line in f:
-                    if line.startswith("model name"):
-                        cpu_model = line.split(":", 1)[1].strip()
-                        break
-        except OSError:
-            pass
+        cpu_model_name = cpu_model()
         cpu = {
             "value": n ** 3 / t_full,
             "unit": "cells/s",
             "cores": threads,
             "kind": "oracle",
-            "sample": (f"FP64 oracle on this host ({cpu_model}), {threads} OpenMP threads: full upward pass ({t_up:.2f} s) + "
+            "sample": (f"FP64 oracle on this host ({cpu_model_name}), {threads} OpenMP threads: full upward pass ({t_up:.2f} s) + "
                        f"downward pass for {planes} central unigrid planes ({len(cells)} cells, {t_down:.2f} s); "
                        f"full solve = upward + downward x n^3/{len(cells)} = {t_full:.1f} s"),
         }
@@ -557,6 +648,7 @@ def main():
         "kernels": extra,
         "parity_vs_oracle": parity,
         "solve_ms_spread": spread,
+        "paper_flop_table": paper_flop_table(costs),
         **extras,
     }
     print(json.dumps(out), flush=True)

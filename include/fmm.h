@@ -181,6 +181,21 @@ int fmm_solve_backward_noalloc(fmm_plan* plan, const void* dphi, const void* dg,
  *   pointer may be NULL.
  */
 fmm_plan* fmm_batch_plan_create(int count, const int* n, int p, int isolated, const fmm_options* opt);
+
+/*
+ * Per-field latency of batch solves.  fmm_batch_timestamps(plan, 1) makes
+ * every following fmm_batch_solve record, on the device wall clock, its start
+ * and the moment each field's last bottom-kernel block has written its
+ * phi and g (the field's results are then complete); 0 stops it.  Switching
+ * synchronises the device and drops the captured graph (the next solve
+ * captures it again); the first enable allocates 12 bytes per field.
+ * fmm_batch_field_ms(plan, ms, count) waits for the device and writes, for
+ * each of the plan's fields, the milliseconds from the start of the last
+ * timed solve to that field's completion (count must be at least the field
+ * count).  Both return FMM_ERR_INVALID_ARG for a single-field plan.
+ */
+int fmm_batch_timestamps(fmm_plan* plan, int enable);
+int fmm_batch_field_ms(fmm_plan* plan, double* ms, int count);
 int fmm_batch_solve(fmm_plan* plan, const void* const* rho, void* const* phi, void* const* g, void* stream);
 int fmm_batch_info(const fmm_plan* plan, int* count, int* bottom_tile, int* m2l_grouping, double* tune_ms,
                    int ncand);

@@ -64,6 +64,7 @@ def lib():
         L.or_solve_timed_dl.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp,
                                         ctypes.c_longlong, _lp, _dp, _dp, _dp]
         L.or_threads.argtypes = []
+        L.or_set_threads.argtypes = [ctypes.c_int]
         L.or_pair_pass.argtypes = [ctypes.c_int, ctypes.c_longlong, ctypes.c_longlong]
         L.or_list_size.argtypes = [ctypes.c_int] * 4
         L.or_pair_pass_row.argtypes = [ctypes.c_int, ctypes.c_longlong, _ip]
@@ -243,6 +244,16 @@ def solve_timed(rho, p: int, targets, nmax: int | None = None, delta_l: int = 1)
     if rc != 0:
         raise ValueError("bad arguments")
     return phi, g, float(times[0]), float(times[1]), int(lib().or_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the following oracle calls."""
+    if lib().or_set_threads(int(n)) != 0:
+        raise ValueError("threads must be >= 1")
+
+
+def threads() -> int:
+    return int(lib().or_threads())
 
 
 def deposit_cic(n: int, pos, mass) -> np.ndarray:

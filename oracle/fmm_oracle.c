@@ -448,9 +448,10 @@ static void bottom_cell(const ostate *s, const double *tab, int i, int j, int l,
       }
   /* near field: every unigrid cell of the finest FMM cells adjacent to T */
   const double xu[3] = {centre(i, s->L), centre(j, s->L), centre(l, s->L)};
-  for (int w0 = (t0 - 1) << dl; w0 < (t0 + 2) << dl; ++w0)
-    for (int w1 = (t1 - 1) << dl; w1 < (t1 + 2) << dl; ++w1)
-      for (int w2 = (t2 - 1) << dl; w2 < (t2 + 2) << dl; ++w2) {
+  const int side = 1 << dl; /* unigrid cells per finest cell along an axis */
+  for (int w0 = (t0 - 1) * side; w0 < (t0 + 2) * side; ++w0)
+    for (int w1 = (t1 - 1) * side; w1 < (t1 + 2) * side; ++w1)
+      for (int w2 = (t2 - 1) * side; w2 < (t2 + 2) * side; ++w2) {
         if (!inside(w0, w1, w2, n) || !adjacent(t0, t1, t2, w0 >> dl, w1 >> dl, w2 >> dl)) continue;
         double m = s->mass[lin(w0, w1, w2, n)];
         double r[3] = {xu[0] - centre(w0, s->L), xu[1] - centre(w1, s->L), xu[2] - centre(w2, s->L)};
@@ -616,6 +617,15 @@ int or_threads(void) {
 #else
   return 1;
 #endif
+}
+
+/* Sets the number of OpenMP threads of the following calls (n >= 1). */
+int or_set_threads(int n) {
+  if (n < 1) return -1;
+#ifdef _OPENMP
+  omp_set_num_threads(n);
+#endif
+  return 0;
 }
 
 /* Multipoles (level 2..F) or locals (level 3..F) of the full solve, in

@@ -78,3 +78,39 @@ def solve_flops(n: int, p: int, nmax: int | None = None, delta_l: int = 1) -> di
 def m2p_pairs(n: int, delta_l: int = 1) -> int:
     """(unigrid target, list source) pairs of the M2P stage."""
     return 8 ** delta_l * list_pairs(n >> delta_l)
+
+
+# The paper's per-operator counts at its own orders (Sec. 4: locals p = 3,
+# multipoles nmax = 2, only the potential at the finest level), per cell and
+# interaction, as printed there.
+PAPER_SEC4 = {"m2m": 10, "l2l": 357, "l2p": 74, "m2l": 228, "m2p": 36, "p2p": 2}
+
+
+def operator_counts(p: int = 3, nmax: int | None = None) -> dict:
+    """Flops of one application of each operator in this library's counting
+    (one multiply-add of a coefficient and an expansion term = 2; the
+    coefficients are precomputed tables, so nothing else is counted):
+      m2m  one child's multipoles shifted into the parent: every b <= a
+      l2l  one parent local shifted to a child: every (b, g), |b| + |g| <= p
+      m2l  one (target, source) pair: every (a, b), |b| <= p, |a| <= min(nmax, p - |b|)
+      l2p  one unigrid target from its local: each term for phi, the terms
+           with b_d >= 1 for g_d
+      m2p  one (unigrid target, source cell) pair: every a <= nmax for phi,
+           and once more per component of g
+      p2p  one (target, source) cell pair: phi, and phi and g
+    Returned per operator as (phi only, phi and g) where the distinction
+    exists (the finest level), else the single count."""
+    nmax = p if nmax is None else nmax
+    NM, NL = nterms(nmax), nterms(p)
+    m2m = 2 * sum((a + 1) * (b + 1) * (c + 1)
+                  for a in range(nmax + 1) for b in range(nmax + 1 - a) for c in range(nmax + 1 - a - b))
+    l2p_g = sum(1 for a in range(p + 1) for b in range(p + 1 - a) for c in range(p + 1 - a - b)
+                for d in (a, b, c) if d >= 1)
+    return {
+        "m2m": m2m,
+        "l2l": 2 * pair_count_m2l(p, p),
+        "m2l": 2 * pair_count_m2l(p, nmax),
+        "l2p": (2 * NL, 2 * (NL + l2p_g)),
+        "m2p": (2 * NM, 2 * 4 * NM),
+        "p2p": (2, 8),
+    }

@@ -117,6 +117,7 @@ void release(fmm_plan* pl) {
   for (auto& f : pl->fld)
     for (auto& lv : f.lev) {
       if (lv.M) (void)hipFree(lv.M);
+      if (lv.Mt) (void)hipFree(lv.Mt);
       if (lv.L) (void)hipFree(lv.L);
     }
   auto free_st = [](fmm::SegTable& st) {
@@ -136,6 +137,8 @@ void release(fmm_plan* pl) {
     for (auto t : row)
       if (t) (void)hipFree(t);
   if (pl->io) (void)hipFree(pl->io);
+  if (pl->stamp_time) (void)hipFree(pl->stamp_time);
+  if (pl->stamp_cnt) (void)hipFree(pl->stamp_cnt);
   if (pl->dtab) (void)hipFree(pl->dtab);
   if (pl->dtab2) (void)hipFree(pl->dtab2);
   if (pl->dlists) (void)hipFree(pl->dlists);
@@ -326,6 +329,7 @@ int build_schedule(fmm_plan* pl) {
     sg.n = fd.n;
     sg.field = f;
     sg.b = (double*)fd.lev[F].M;
+    sg.t = fd.lev[F].Mt;
     p2m.add(sg, cdiv((long long)nF * nF * nF, 256));
     for (int k = F; k >= 3; --k) {
       Seg m{};
@@ -333,6 +337,7 @@ int build_schedule(fmm_plan* pl) {
       m.field = f;
       m.a = (const double*)fd.lev[k].M;
       m.b = (double*)fd.lev[k - 1].M;
+      m.t = fd.lev[k - 1].Mt;
       // parents per block of k_m2m: 16 up to 56 terms, else 8
       m2m[k].add(m, cdiv(1LL << (3 * (k - 1)), pl->NM <= 56 ? 16 : 8));
     }
@@ -345,6 +350,7 @@ int build_schedule(fmm_plan* pl) {
       c.split = 1;
       c.a = (const double*)fd.lev[k - 1].M;
       c.b = (double*)fd.lev[k].L;
+      c.t = k >= klow ? fd.lev[k - 1].Mt : nullptr;
       conv[k >= klow ? 1 : 0].add(c, (long long)c.tpa * c.tpa * c.tz);
     }
     for (int k = 4; k <= F - 1; ++k) {
@@ -364,6 +370,7 @@ int build_schedule(fmm_plan* pl) {
       b.a = (const double*)fd.lev[F].M;
       b.c = F >= 3 ? (const double*)fd.lev[F].L : nullptr;
       b.d = F >= 4 ? (const double*)fd.lev[F - 1].L : nullptr;
+      b.t = fd.lev[F].Mt;
       bot[bottom_low(pl, F) ? 1 : 0][z].add(b, (long long)b.tpa * b.tpa * b.tz);
     }
   }
@@ -772,6 +779,16 @@ fmm_plan* create_plan(const std::vector<int>& ns, int p, const fmm_options& o, i
         fail(FMM_ERR_DEVICE, "hipMemset failed");
         return bail();
       }
+      if (fmm::typed_level(pl, fd.F, k)) {
+        // the copy in the compute type: BF16 chunks of 16 terms, FP32 of 4
+        const int kc = pl->precision == 2 ? 16 : 4;
+        const size_t tb = (size_t)((pl->NM + kc - 1) / kc) * kc * lv.ncellp * (pl->precision == 2 ? 2 : 4);
+        if (dev_alloc(pl, &lv.Mt, tb)) return bail();
+        if (hipMemset(lv.Mt, 0, tb) != hipSuccess) {
+          fail(FMM_ERR_DEVICE, "hipMemset failed");
+          return bail();
+        }
+      }
       if (k >= 3) {
         const size_t lb = (size_t)(lv.ncell / 8) * fmm::loc_stride(p) * sizeof(double);
         if (dev_alloc(pl, &lv.L, lb)) return bail();
@@ -1079,6 +1096,53 @@ int fmm_batch_solve(fmm_plan* plan, const void* const* rho, void* const* phi, vo
     (void)hipGetLastError();
     return fail(FMM_ERR_DEVICE, "batch launch failed: %s", hipGetErrorString(e));
   }
+  return ok();
+}
+
+int fmm_batch_timestamps(fmm_plan* plan, int enable) {
+  if (!plan) return fail(FMM_ERR_INVALID_ARG, "plan is NULL");
+  if (!plan->batch) return fail(FMM_ERR_INVALID_ARG, "not a batch plan");
+  const int on = enable ? 1 : 0;
+  if (on == plan->stamps) return ok();
+  if (on && !plan->stamp_time) {
+    const size_t nf = plan->fld.size();
+    if (dev_alloc(plan, (void**)&plan->stamp_time, (nf + 1) * sizeof(unsigned long long)) ||
+        dev_alloc(plan, (void**)&plan->stamp_cnt, nf * sizeof(unsigned int)))
+      return FMM_ERR_OUT_OF_MEMORY;
+    if (hipMemset(plan->stamp_time, 0, (nf + 1) * sizeof(unsigned long long)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(FMM_ERR_DEVICE, "hipMemset failed");
+    }
+  }
+  // the captured graph holds the bottom kernel's arguments: capture again
+  if (hipDeviceSynchronize() != hipSuccess) (void)hipGetLastError();
+  if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  plan->gexec = nullptr;
+  plan->graph = nullptr;
+  plan->stamps = on;
+  return ok();
+}
+
+int fmm_batch_field_ms(fmm_plan* plan, double* ms, int count) {
+  if (!plan) return fail(FMM_ERR_INVALID_ARG, "plan is NULL");
+  if (!plan->batch || !plan->stamps) return fail(FMM_ERR_INVALID_ARG, "timestamps are not enabled on this plan");
+  const int nf = (int)plan->fld.size();
+  if (!ms || count < nf) return fail(FMM_ERR_INVALID_ARG, "ms must hold %d doubles", nf);
+  int rate_khz = 0;
+  hipError_t e = hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, plan->device);
+  if (e != hipSuccess || rate_khz <= 0) {
+    (void)hipGetLastError();
+    return fail(FMM_ERR_DEVICE, "device wall-clock rate unavailable");
+  }
+  std::vector<unsigned long long> t(nf + 1);
+  if ((e = hipDeviceSynchronize()) != hipSuccess ||
+      (e = hipMemcpy(t.data(), plan->stamp_time, t.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost)) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FMM_ERR_DEVICE, "reading timestamps failed: %s", hipGetErrorString(e));
+  }
+  for (int f = 0; f < nf; ++f) ms[f] = t[1 + f] >= t[0] ? (double)(t[1 + f] - t[0]) / rate_khz : -1.0;
   return ok();
 }
 

@@ -32,6 +32,7 @@ namespace fmm {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+#include "fmm_types.h"
 
 // multi-index table for orders <= PDMAX: packed exponents a | b<<8 | c<<16,
 // and 1/a!
@@ -170,8 +171,10 @@ __global__ void k_dtab2(double* __restrict__ out, int PD, int ND) {
 // (-1)^(q.a) depends on a only through a mod 2, so the 8 signed sums of the
 // children are formed once (a Walsh transform) and each term is one product.
 // ---------------------------------------------------------------------------
-// Segments: n = unigrid cells per axis, field, b = Mhat_F.  256 cells T per block.
-template <typename TI>
+// Segments: n = unigrid cells per axis, field, b = Mhat_F, t = its copy in
+// the compute type CT (mixed precision; null or CT = double: none).  256
+// cells T per block.
+template <typename TI, typename CT>
 __global__ __launch_bounds__(256) void k_p2m(const Seg* __restrict__ segs, int nseg, IoArg io, int NM, int NC) {
   const Seg& sg = find_seg(segs, nseg, blockIdx.x);
   const int n = sg.n;
@@ -213,12 +216,17 @@ __global__ __launch_bounds__(256) void k_p2m(const Seg* __restrict__ segs, int n
       o[e] = val;
     }
     *reinterpret_cast<d4*>(M + (c * ncellp + cp) * 4) = o;
+    if constexpr (Mf<CT>::IDX != 0) {
+      constexpr int KC = Mf<CT>::KC;
+      if (sg.t)
+        store4((typename Mf<CT>::H*)sg.t + ((4 * c / KC) * ncellp + cp) * KC + (4 * c) % KC, o[0], o[1], o[2], o[3]);
+    }
   }
 }
 
 // P2M of FMM-2: Mhat_F[a] = sum_s rho_{4T+s} w_s^a / a!, w_s,i = (3 - 2 s_i) / 8
 // over the 64 unigrid cells s of T, summed axis by axis.  Segments as k_p2m.
-template <typename TI>
+template <typename TI, typename CT>
 __global__ __launch_bounds__(256) void k_p2m2(const Seg* __restrict__ segs, int nseg, IoArg io, int NM, int NC) {
   const Seg& sg = find_seg(segs, nseg, blockIdx.x);
   const int n = sg.n;
@@ -273,6 +281,11 @@ __global__ __launch_bounds__(256) void k_p2m2(const Seg* __restrict__ segs, int 
       o[e] = val;
     }
     *reinterpret_cast<d4*>(M + (c * ncellp + cp) * 4) = o;
+    if constexpr (Mf<CT>::IDX != 0) {
+      constexpr int KC = Mf<CT>::KC;
+      if (sg.t)
+        store4((typename Mf<CT>::H*)sg.t + ((4 * c / KC) * ncellp + cp) * KC + (4 * c) % KC, o[0], o[1], o[2], o[3]);
+    }
   }
 }
 
@@ -283,7 +296,8 @@ __global__ __launch_bounds__(256) void k_p2m2(const Seg* __restrict__ segs, int 
 // chunk c of the parent's 8 children and forms, in registers, the signed sums
 // W[pat][b] = sum_q (-1)^popc(q & pat) Mhat[2P+q][b] (a Walsh transform over
 // q), staged in LDS.  Phase 2: each output term sums its b <= a.
-// Segments: n = child grid cells per axis, a = Mhat_k, b = Mhat_{k-1}.
+// Segments: n = child grid cells per axis, a = Mhat_k, b = Mhat_{k-1}, t =
+// the copy of Mhat_{k-1} in the compute type CT (or null).
 // ---------------------------------------------------------------------------
 template <int PO>
 struct M2MShape {
@@ -297,7 +311,7 @@ struct M2MShape {
 // output term a, entries cstart[a] .. cstart[a+1]-1 hold the LDS offset
 // 8 b + pat(g) and the coefficient 2^-|b| 4^-|g| / g! for every b <= a,
 // g = a - b.
-template <int PO>
+template <int PO, typename CT>
 __global__ __launch_bounds__(M2MShape<PO>::THREADS) void k_m2m(const Seg* __restrict__ segs, int nseg,
                                                               const int* __restrict__ cstart,
                                                               const int* __restrict__ coff,
@@ -364,7 +378,12 @@ __global__ __launch_bounds__(M2MShape<PO>::THREADS) void k_m2m(const Seg* __rest
     for (int j = sstart[al]; j < sstart[al + 1]; ++j) acc += scoef[j] * Wp[soff[j]];
     const int p2 = (int)(P % np), p1 = (int)((P / np) % np), p0 = (int)(P / ((long long)np * np));
     const long long cp = ((long long)(p0 + 3) * npp + (p1 + 3)) * npp + (p2 + 3);
-    Mp[((al >> 2) * ncp_p + cp) * 4 + (al & 3)] = al < nmx ? acc : 0.0;  // truncation at nmax
+    const double v = al < nmx ? acc : 0.0;  // truncation at nmax
+    Mp[((al >> 2) * ncp_p + cp) * 4 + (al & 3)] = v;
+    if constexpr (Mf<CT>::IDX != 0) {
+      constexpr int KC = Mf<CT>::KC;
+      if (sg.t) ((typename Mf<CT>::H*)sg.t)[((al / KC) * ncp_p + cp) * KC + al % KC] = static_cast<typename Mf<CT>::H>(v);
+    }
   }
 }
 
@@ -1153,19 +1172,21 @@ hipError_t launch_bottom(fmm_plan* pl, int x, IoArg io, hipStream_t s) {
   if (!st.nseg) return hipSuccess;
   // M2P K chunks: those of the multipole terms kept (nmax)
   const int nck = (pl->NMX + Mf<CT>::KC - 1) / Mf<CT>::KC;
+  unsigned int* cnt = pl->stamps ? pl->stamp_cnt : nullptr;
+  unsigned long long* done = pl->stamps ? pl->stamp_time + 1 : nullptr;
   StageScope sc(pl, ST_BOTTOM, 1, s);
   if (pl->dl == 2) {
     hipLaunchKernelGGL((k_bottom<P, CT, TI, TO, 16, 2>), dim3(st.blocks, 8), dim3(bottom_threads<CT>()), 0, s, st.dev,
                        st.nseg, io, (const H*)pl->wm2p[X], (const H*)pl->wl2p[X], (const H*)pl->wl2p2[X],
-                       (const H*)pl->wp2p[X], pl->dlists, nck);
+                       (const H*)pl->wp2p[X], pl->dlists, nck, cnt, done);
   } else if (z == 0)
     hipLaunchKernelGGL((k_bottom<P, CT, TI, TO, 16, 1>), dim3(st.blocks), dim3(bottom_threads<CT>()), 0, s, st.dev, st.nseg, io,
                        (const H*)pl->wm2p[X], (const H*)pl->wl2p[X], (const H*)pl->wl2p2[X], (const H*)pl->wp2p[X],
-                       pl->dlists, nck);
+                       pl->dlists, nck, cnt, done);
   else
     hipLaunchKernelGGL((k_bottom<P, CT, TI, TO, 8, 1>), dim3(st.blocks), dim3(bottom_threads<CT>()), 0, s, st.dev, st.nseg, io,
                        (const H*)pl->wm2p[X], (const H*)pl->wl2p[X], (const H*)pl->wl2p2[X], (const H*)pl->wp2p[X],
-                       pl->dlists, nck);
+                       pl->dlists, nck, cnt, done);
   return hipGetLastError();
 }
 
@@ -1175,14 +1196,19 @@ template <int P, typename CT, typename TI, typename TO>
 hipError_t solve_ct(fmm_plan* pl, IoArg io, hipStream_t s) {
   constexpr int NM = nterms(P), NC = (NM + 3) / 4;
   hipError_t e;
+  if (pl->stamps) {
+    const int nf = (int)pl->fld.size();
+    hipLaunchKernelGGL(k_stamp_start, dim3(blocks_for(nf, 256)), dim3(256), 0, s, pl->stamp_time, pl->stamp_cnt, nf);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   {
     StageScope sc(pl, ST_P2M, 1, s);
     // terms past nmax are written as zero
     if (pl->dl == 2)
-      hipLaunchKernelGGL((k_p2m2<TI>), dim3(pl->s_p2m.blocks), dim3(256), 0, s, pl->s_p2m.dev, pl->s_p2m.nseg, io,
+      hipLaunchKernelGGL((k_p2m2<TI, CT>), dim3(pl->s_p2m.blocks), dim3(256), 0, s, pl->s_p2m.dev, pl->s_p2m.nseg, io,
                          pl->NMX, NC);
     else
-      hipLaunchKernelGGL((k_p2m<TI>), dim3(pl->s_p2m.blocks), dim3(256), 0, s, pl->s_p2m.dev, pl->s_p2m.nseg, io,
+      hipLaunchKernelGGL((k_p2m<TI, CT>), dim3(pl->s_p2m.blocks), dim3(256), 0, s, pl->s_p2m.dev, pl->s_p2m.nseg, io,
                          pl->NMX, NC);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
@@ -1190,8 +1216,8 @@ hipError_t solve_ct(fmm_plan* pl, IoArg io, hipStream_t s) {
     const SegTable& st = pl->s_m2m[k];
     if (!st.nseg) continue;
     StageScope sc(pl, ST_M2M, 1, s);
-    hipLaunchKernelGGL((k_m2m<P>), dim3(st.blocks), dim3(M2MShape<P>::THREADS), 0, s, st.dev, st.nseg, pl->m2m_start,
-                       pl->m2m_off, pl->m2m_coef, pl->NMX);
+    hipLaunchKernelGGL((k_m2m<P, CT>), dim3(st.blocks), dim3(M2MShape<P>::THREADS), 0, s, st.dev, st.nseg,
+                       pl->m2m_start, pl->m2m_off, pl->m2m_coef, pl->NMX);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if ((e = launch_conv<P, double, CV_M2L>(pl, pl->s_conv[0], pl->wm2l[0], s)) != hipSuccess) return e;

@@ -165,6 +165,11 @@ struct Level {
   long long ncell = 0;   // nk^3
   long long ncellp = 0;  // nkp^3
   void* M = nullptr;  // multipoles, chunked [NC][ncellp][4], zero halo of 3 cells
+  // mixed-precision plans: the same multipoles rounded to the compute type of
+  // the kernels that read this level, chunked [ceil(NM/KC)][ncellp][KC] with
+  // KC the type's K chunk (16 BF16 / 4 FP32 terms), zero halo; null where no
+  // low-precision kernel reads the level
+  void* Mt = nullptr;
   // locals of level k >= 3, stored per parent cell P (level k-1) in M2L
   // column order: L[P][m2l_col(q, b)] = Lhat of child 2P + q, term b;
   // row stride loc_stride(p)
@@ -208,6 +213,7 @@ struct Seg {
   double* b;
   const double* c;
   const double* d;
+  void* t;  // mixed precision: the typed copy of a (convolutions, bottom) or of b (P2M, M2M), or null
 };
 // a segment table in device memory, plus its launch size
 struct SegTable {
@@ -234,7 +240,7 @@ struct AdjWs {
 // most segments its tables hold.
 constexpr size_t kNoallocBytes = (size_t)96 << 20;
 constexpr size_t kNoallocSegBytes = 4096;
-constexpr int kMaxAdjSegs = 16;
+constexpr int kMaxAdjSegs = 12;
 
 // launch-shape choices picked by the batch autotuner
 struct Tuning {
@@ -318,6 +324,12 @@ struct fmm_plan {
   fmm::Tuning tune;
   std::vector<double> tune_ms;      // autotuner timings (ms) of each candidate
   int tune_cached = 0;              // the choice came from the autotune cache file
+  // per-field completion times (fmm_batch_timestamps): stamp_time[0] the
+  // solve's start, stamp_time[1 + f] the end of field f's last bottom block
+  // (device wall clock), stamp_cnt[f] the field's finished bottom blocks
+  int stamps = 0;
+  unsigned long long* stamp_time = nullptr;
+  unsigned int* stamp_cnt = nullptr;
   hipStream_t cap_stream = nullptr; // stream the batch graph is captured on
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -380,6 +392,13 @@ int build_schedule(fmm_plan* pl);
 inline bool bottom_low(const fmm_plan* pl, int F) { return pl->precision != 0 && F > pl->coarse_fp64_levels; }
 inline int m2l_low_from(const fmm_plan* pl) {
   return pl->precision == 0 ? 64 : (pl->coarse_fp64_levels + 1 > 3 ? pl->coarse_fp64_levels + 1 : 3);
+}
+// whether the multipoles of level k (of a field with finest level F) get a
+// copy in the compute type: the low-precision bottom reads level F, the
+// low-precision M2L into level k + 1 reads level k
+inline bool typed_level(const fmm_plan* pl, int F, int k) {
+  if (pl->precision == 0) return false;
+  return (k == F && bottom_low(pl, F)) || (k < F && k + 1 >= m2l_low_from(pl));
 }
 
 // Records an event pair around a stage when the plan is profiling.

@@ -1,9 +1,6 @@
-// Matrix-core kernels of the downward pass, generic over the compute type:
-//   double     v_mfma_f64_16x16x4f64   K = 4 per op, FP64 accumulation
-//   float      v_mfma_f32_16x16x4f32   K = 4 per op, FP32 accumulation
-//   bf16_tag   v_mfma_f32_16x16x32_bf16 K = 32 per op (two interaction
-//              offsets x 16 multipole terms), FP32 accumulation
-// Included by fmm_kernels.hip (needs its constant tables and helpers).
+// Matrix-core kernels of the downward pass, generic over the compute type
+// (fmm_types.h).  Included by fmm_impl.h (needs its constant tables and
+// helpers).
 //
 // Both kernels are sums over the 189 offsets d of a parity class (Sec. 2.2):
 // with the source grid s, a "row" is a cell P of grid s of parity r and
@@ -16,55 +13,6 @@
 // staging; one wave per parity class.  B fragments come from plan-time
 // tables in fragment order, two offset groups in flight.
 #pragma once
-
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-
-struct bf16_tag {};
-
-template <typename CT>
-struct Mf;
-template <>
-struct Mf<double> {
-  using H = double;  // staged / tabulated element
-  using AF = double;  // operand fragment of one lane
-  using Acc = d4;
-  static constexpr int KC = 4, OPM = 1, VPL = 1, IDX = 0;
-  __device__ static Acc op(AF a, AF b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-  // accumulator element v of a lane with k-group kq holds row:
-  __device__ static int row(int v, int kq) { return 4 * v + kq; }
-  template <typename E>
-  __device__ __forceinline__ static AF frag(const E (&v)[1]) { return (double)v[0]; }
-};
-template <>
-struct Mf<float> {
-  using H = float;
-  using AF = float;
-  using Acc = f4;
-  static constexpr int KC = 4, OPM = 1, VPL = 1, IDX = 1;
-  __device__ static Acc op(AF a, AF b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-  __device__ static int row(int v, int kq) { return 4 * kq + v; }
-  template <typename E>
-  __device__ __forceinline__ static AF frag(const E (&v)[1]) { return (float)v[0]; }
-};
-template <>
-struct Mf<bf16_tag> {
-  using H = __bf16;
-  using AF = bf8;
-  using Acc = f4;
-  static constexpr int KC = 16, OPM = 2, VPL = 8, IDX = 2;
-  __device__ static Acc op(AF a, AF b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
-  __device__ static int row(int v, int kq) { return 4 * kq + v; }
-  // (round to nearest even; a float converts to the same bf16 directly or
-  // through double, which holds it exactly)
-  template <typename E>
-  __device__ __forceinline__ static AF frag(const E (&v)[8]) {
-    AF f;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) f[e] = static_cast<__bf16>(v[e]);
-    return f;
-  }
-};
 
 // Lane roles.  kq = lane / 16.  For OPM = 2 the lanes with kq < 2 take the
 // first offset of a pair and kq >= 2 the second; each lane holds VPL terms
@@ -92,7 +40,8 @@ struct LaneRole {
 // decode runs on the scalar unit; with two (BF16) each lane reads the entry
 // of its half of the K range.
 struct EntryGroup {
-  int e;
+  int e;           // the packed list entry (one offset per MFMA)
+  int aoff, boff;  // two offsets per MFMA: the lane's halo and B-table offsets
 };
 
 // ---------------------------------------------------------------------------
@@ -131,6 +80,12 @@ struct BotShape {
 // y stride in doubles spreads them over the LDS banks.  An operand address is
 // a per-lane part (fixed for the kernel) + a per-offset part (uniform) + a
 // per-row-tile constant, so each offset costs one vector add.
+// BF16 (two 16-byte halves of K per cell chunk): the natural y stride is a
+// multiple of 128 bytes, so the rows of the two y values of an operand
+// fragment would read the same banks.  The halves of a cell's chunk are
+// therefore swapped when bit 1 of its halo y index is set (SWZ): a lane
+// whose K half is kh reads position kh ^ swz(hy), and the two y rows of a
+// fragment (halo y two apart) always take opposite halves.
 template <typename CT, int BZ>
 struct Halo {
   static constexpr int KC = Mf<CT>::KC, HZ2 = BotShape<BZ>::HZ2;
@@ -138,9 +93,12 @@ struct Halo {
   static constexpr int YS = Mf<CT>::IDX == 0 ? (NAT | 1) : NAT;
   static constexpr int XS = HY * YS;
   static constexpr int SIZE = HX * XS;
+  static constexpr bool SWZ = Mf<CT>::IDX == 2;
   __device__ static int cell(int hx, int hy, int hz) {
     return hx * XS + hy * YS + ((hz & 1) * HZ2 + (hz >> 1)) * KC;
   }
+  // element offset, within its cell's chunk, at which K index k is stored
+  __device__ static int kpos(int hy, int k) { return SWZ ? k ^ (((hy >> 1) & 1) << 3) : k; }
   // per-offset part: halo cell 3 + r - d of row g = 0 (z by parity plane)
   __device__ static int offset_part(int r0, int r1, int r2, int d0, int d1, int d2) {
     const int zz = 3 + r2 - d2;
@@ -174,16 +132,18 @@ __device__ __forceinline__ void stage_halo(typename Mf<CT>::H* __restrict__ halo
 #pragma unroll 1
   for (int b0 = 0; b0 < NIT; b0 += BATCH) {
     d4 v[BATCH][S4];
-    int to[BATCH];
+    int to[BATCH], ty[BATCH];
 #pragma unroll
     for (int k = 0; k < BATCH; ++k) {
       const int h = threadIdx.x + (b0 + k) * NTHR;
       to[k] = -1;
+      ty[k] = 0;
 #pragma unroll
       for (int s4 = 0; s4 < S4; ++s4) v[k][s4] = d4{0, 0, 0, 0};
       if (b0 + k < NIT && h < NH) {
         const int hz = h % HZ, hy = (h / HZ) % HY, hx = h / (HZ * HY);
         to[k] = HL::cell(hx, hy, hz);
+        ty[k] = hy;
         const int px = x0 + hx, py = y0 + hy, pz = z0 + hz;
         if (px < np && py < np && pz < np) {
           const long long cell = ((long long)px * np + py) * np + pz;
@@ -201,8 +161,85 @@ __device__ __forceinline__ void stage_halo(typename Mf<CT>::H* __restrict__ halo
 #pragma unroll
         for (int s4 = 0; s4 < S4; ++s4)
 #pragma unroll
-          for (int e = 0; e < 4; ++e) halo[to[k] + 4 * s4 + e] = static_cast<H>(v[k][s4][e]);
+          for (int e = 0; e < 4; ++e) halo[to[k] + HL::kpos(ty[k], 4 * s4 + e)] = static_cast<H>(v[k][s4][e]);
       }
+  }
+}
+
+// Staging from a grid already held in the compute type (the typed copies of
+// mixed-precision plans, chunked [ceil(NM / KC)][np^3][KC]): a cell's chunk is
+// KC contiguous elements, copied with 16-byte loads and 16-byte LDS stores and
+// no conversion.  The LDS destination and the grid cell of each cell a thread
+// copies are the same for every chunk, so they are computed once per block
+// (plan) and each chunk only streams (run).  Cells past the grid's end are
+// staged as zeros.
+template <typename CT, int BZ, int NTHR>
+struct TypedStage {
+  using H = typename Mf<CT>::H;
+  using HL = Halo<CT, BZ>;
+  static constexpr int KC = Mf<CT>::KC, NV = KC * (int)sizeof(H) / 16;  // 16-byte pieces per cell chunk
+  static constexpr int HZ = BotShape<BZ>::HZ, NH = HX * HY * HZ, NIT = (NH + NTHR - 1) / NTHR;
+  // cells loaded before any is stored (registers in flight: 4 NV per cell)
+  static constexpr int BATCH = NV == 2 ? 2 : 4;
+  int np_, x0_, y0_, z0_;
+  __device__ __forceinline__ void plan(int np, int x0, int y0, int z0) {
+    np_ = np;
+    x0_ = x0;
+    y0_ = y0;
+    z0_ = z0;
+  }
+  __device__ __forceinline__ void run(H* __restrict__ halo, const H* src, long long ncellp, int c) const {
+    const __attribute__((address_space(1))) u32x4* g = gmem(reinterpret_cast<const u32x4*>(src)) + c * ncellp * NV;
+#pragma unroll 1
+    for (int b0 = 0; b0 < NIT; b0 += BATCH) {
+      u32x4 v[BATCH][NV];
+      int to[BATCH], ty[BATCH];
+#pragma unroll
+      for (int k = 0; k < BATCH; ++k) {
+        const int h = threadIdx.x + (b0 + k) * NTHR;
+        to[k] = -1;
+        ty[k] = 0;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[k][q] = u32x4{0, 0, 0, 0};
+        if (b0 + k < NIT && h < NH) {
+          const int hz = h % HZ, hy = (h / HZ) % HY, hx = h / (HZ * HY);
+          to[k] = HL::cell(hx, hy, hz);
+          ty[k] = hy;
+          const int px = x0_ + hx, py = y0_ + hy, pz = z0_ + hz;
+          if (px < np_ && py < np_ && pz < np_) {
+            const long long from = ((long long)px * np_ + py) * np_ + pz;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) v[k][q] = g[from * NV + q];
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < BATCH; ++k)
+        if (to[k] >= 0) {
+#pragma unroll
+          for (int q = 0; q < NV; ++q)
+            *reinterpret_cast<u32x4*>(halo + to[k] + HL::kpos(ty[k], q * (16 / (int)sizeof(H)))) = v[k][q];
+        }
+    }
+  }
+};
+
+// Operand addresses of two interaction offsets per MFMA (BF16): for parity
+// class r and offset pair j (list entries 2 j and 2 j + 1), entry sel of the
+// table holds the halo element offset of the offset's operand cells
+// (relative to a lane's base address) and the element offset of its B-table
+// slot.  Built once per block; a lane then reads its half with one LDS load.
+template <typename HL>
+__device__ __forceinline__ void build_pair_table(int2* __restrict__ tab, const int* __restrict__ dlists, int npair,
+                                                 int slot_elems, int nthr) {
+  for (int t = threadIdx.x; t < 8 * npair * 2; t += nthr) {
+    const int r = t / (2 * npair), j = (t >> 1) % npair, sel = t & 1;
+    const int e = dlists[r * NLIST_PAD + 2 * j + sel];
+    // with swizzled K halves, bit 0 (free: offsets are multiples of KC)
+    // holds bit 1 of the halo y index 3 + r1 - d1 of the fragment's first row
+    const int swz = HL::SWZ ? ((3 + ((r >> 1) & 1) - dl_d1(e)) >> 1) & 1 : 0;
+    tab[t] = int2{HL::offset_part((r >> 2) & 1, (r >> 1) & 1, r & 1, dl_d0(e), dl_d1(e), dl_d2(e)) | swz,
+                  dl_dd(e) * slot_elems};
   }
 }
 
@@ -227,11 +264,14 @@ __device__ constexpr int tile_part(int m) {
 template <typename CT>
 constexpr int bottom_min_waves() { return 4; }
 
+// stamp_cnt / stamp_done (or null): per field, the finished blocks and the
+// device wall-clock time at which its last block finished.
 template <int P, typename CT, typename TI, typename TO, int BZ, int DL>
 __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void k_bottom(
     const Seg* __restrict__ segs, int nseg, IoArg io, const typename Mf<CT>::H* __restrict__ Wm2p,
     const typename Mf<CT>::H* __restrict__ Wl2p, const typename Mf<CT>::H* __restrict__ Wl2p2,
-    const typename Mf<CT>::H* __restrict__ Wp2p, const int* __restrict__ dlists, int nck) {
+    const typename Mf<CT>::H* __restrict__ Wp2p, const int* __restrict__ dlists, int nck,
+    unsigned int* __restrict__ stamp_cnt, unsigned long long* __restrict__ stamp_done) {
   using M = Mf<CT>;
   using H = typename M::H;
   using AF = typename M::AF;
@@ -246,13 +286,21 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
   constexpr int NCK = (NM + KC - 1) / KC;
   constexpr int NGRP = (NLIST + OPM - 1) / OPM;
   constexpr int THREADS = bottom_threads<CT>(), MTW = BOT_MT / bottom_wpr<CT>();  // row tiles per wave
+  // mixed precision: the level-F multipoles are staged from their typed copy
+  constexpr bool TYPED = M::IDX != 0;
   using HL = Halo<CT, BZ>;
-  __shared__ H halo[HL::SIZE];
-  __shared__ int slist[8 * NLIST_PAD];  // the interaction lists of the 8 parity classes
+  __shared__ __attribute__((aligned(16))) H halo[HL::SIZE];
+  // the interaction lists of the 8 parity classes (one offset per MFMA), or
+  // the lanes' operand offsets of each offset pair (two per MFMA)
+  __shared__ int slist[OPM == 1 ? 8 * NLIST_PAD : 1];
+  __shared__ int2 spair[OPM == 2 ? 8 * NGRP * 2 : 1];
   // column of local term bt of child q in the locals' M2L layout, for the
   // tail's L2P reads (-1 past the last term)
   __shared__ int scol[8 * NLT * KT];
-  for (int t = threadIdx.x; t < 8 * NLIST_PAD; t += THREADS) slist[t] = dlists[t];
+  if constexpr (OPM == 1)
+    for (int t = threadIdx.x; t < 8 * NLIST_PAD; t += THREADS) slist[t] = dlists[t];
+  else
+    build_pair_table<HL>(spair, dlists, NGRP, 2 * EL * VPL, THREADS);
   for (int t = threadIdx.x; t < 8 * NLT * KT; t += THREADS) {
     const int q = t / (NLT * KT), bt = t - q * (NLT * KT);
     const int ex = c_mi_exp[bt < NL ? bt : 0];
@@ -294,28 +342,43 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
   // and the wave's first row tile (MTW is a multiple of TPX, so the tile
   // offset splits into that of m0 and that of the tile within the wave)
   const H* hlane = halo + 2 * gyo * HL::YS + gz * KC + lr.tic + tile_part<HL, TPX, YPT>(m0);
+  // swizzled K halves (BF16): the lane's base for swizzle bit 0 and bit 1 of
+  // the fragment's first row (its own row is gyo rows of two further on)
+  const int kh = lr.tic >> 3;
+  const H* hsw0 = halo + 2 * gyo * HL::YS + gz * KC + 8 * (kh ^ (gyo & 1)) + tile_part<HL, TPX, YPT>(m0);
+  const H* hsw1 = halo + 2 * gyo * HL::YS + gz * KC + 8 * (kh ^ (gyo & 1) ^ 1) + tile_part<HL, TPX, YPT>(m0);
 
   Acc acc[MTW][2];
 #pragma unroll
   for (int m = 0; m < MTW; ++m) acc[m][0] = acc[m][1] = Acc{0, 0, 0, 0};
   const int* dl = slist + r * NLIST_PAD;  // visible after the first chunk's barrier
-  // blocks walk the (order-independent) offset sum from different starting points
-  const int rot = (int)((blockIdx.x * 37u) % NLIST);
+  const int2* dp = spair + r * NGRP * 2 + lr.sel;
+  // blocks walk the (order-independent) offset sum from different starting
+  // points: rotated entries (one offset per MFMA) or rotated pairs (two)
+  const int rot = (int)((blockIdx.x * 37u) % (OPM == 1 ? NLIST : NGRP));
   auto entry = [&](int pos) {
     if (pos >= NLIST) return dl[NLIST];
     pos += rot;
     return dl[pos < NLIST ? pos : pos - NLIST];
   };
+  TypedStage<CT, BZ, THREADS> ts;
+  if constexpr (TYPED) ts.plan(nFp, tx0, ty0, tz0);
 
   // the M2P K chunks: nck <= ceil(NM / KC), fewer when the multipoles are
   // truncated at nmax < p (the chunks past it hold only zero terms)
   for (int c = 0; c < nck; ++c) {
     __syncthreads();  // previous chunk fully consumed
-    stage_halo<CT, BZ, THREADS>(halo, Mh, NC4, ncellp, nFp, tx0, ty0, tz0, c);
+    if constexpr (TYPED)
+      ts.run(halo, (const H*)sg.t, ncellp, c);
+    else
+      stage_halo<CT, BZ, THREADS>(halo, Mh, NC4, ncellp, nFp, tx0, ty0, tz0, c);
     __syncthreads();
     const H* wc = Wm2p + (size_t)c * NSLOT * 2 * EL * VPL + lr.tl * VPL;
     auto bload = [&](EntryGroup g, int t) {
-      return *reinterpret_cast<const AF*>(wc + ((size_t)dl_dd(g.e) * 2 + t) * EL * VPL);
+      if constexpr (OPM == 1)
+        return *reinterpret_cast<const AF*>(wc + ((size_t)dl_dd(g.e) * 2 + t) * EL * VPL);
+      else
+        return *reinterpret_cast<const AF*>(wc + g.boff + t * EL * VPL);
     };
     // A fragments of offset group j: source halo cell of row (gx, gy, gz) is
     // 3 + 2 g + r - d.  Three register slots for the list entries, the B
@@ -323,17 +386,28 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
     // unrolled by three, so no slot is copied): B is loaded two groups
     // ahead, A one group ahead, while the current group's products run.
     auto aload = [&](EntryGroup g, AF (&a)[MTW]) {
-      const H* base = hlane + HL::offset_part(r0, r1, r2, dl_d0(g.e), dl_d1(g.e), dl_d2(g.e));
+      const H* base;
+      if constexpr (OPM == 1)
+        base = hlane + HL::offset_part(r0, r1, r2, dl_d0(g.e), dl_d1(g.e), dl_d2(g.e));
+      else if constexpr (HL::SWZ)
+        base = ((g.aoff & 1) ? hsw1 : hsw0) + (g.aoff & ~1);
+      else
+        base = hlane + g.aoff;
 #pragma unroll
       for (int m = 0; m < MTW; ++m)
         a[m] = *reinterpret_cast<const AF*>(base + tile_part<HL, TPX, YPT>(m));
     };
     auto group = [&](int j) {
       EntryGroup g;
-      if constexpr (OPM == 1)
+      if constexpr (OPM == 1) {
         g.e = __builtin_amdgcn_readfirstlane(entry(j));
-      else
-        g.e = entry(OPM * j + lr.sel);
+      } else {
+        int jr = j + rot;  // wave-uniform
+        jr = jr < NGRP ? jr : jr - NGRP;
+        const int2 v = dp[2 * jr];
+        g.aoff = v.x;
+        g.boff = v.y;
+      }
       return g;
     };
     EntryGroup es[3];
@@ -345,6 +419,9 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
     bs[1][0] = bload(es[1], 0);
     bs[1][1] = bload(es[1], 1);
     aload(es[0], as[0]);
+    // (the body is unrolled by three by hand; unrolling the loop itself would
+    // hoist every group's table address out of the chunk loop)
+#pragma unroll 1
     for (int j = 0; j < NGRP; j += 3) {
 #pragma unroll
       for (int u = 0; u < 3; ++u) {
@@ -541,6 +618,24 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
       }
     }
   }
+  if (stamp_cnt) {
+    // the field's last block records when the field is complete: its stores
+    // are made visible, then one lane counts the block with a global atomic
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      const unsigned int blocks = (unsigned int)(sg.tpa * sg.tpa * sg.tz) * gridDim.y;
+      if (atomicAdd(stamp_cnt + sg.field, 1u) == blocks - 1) stamp_done[sg.field] = wall_clock64();
+    }
+  }
+}
+
+// Start of a timed solve: the device wall-clock time, and the per-field
+// block counters cleared (a kernel, so the solve can be captured in a graph).
+__global__ void k_stamp_start(unsigned long long* __restrict__ time, unsigned int* __restrict__ cnt, int nf) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) time[0] = wall_clock64();
+  if (t < nf) cnt[t] = 0;
 }
 
 // Plan-time expansion of the bottom kernel's B operands into fragment order,
@@ -754,9 +849,17 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   constexpr int CMT = S::MT;  // row tiles per wave
   constexpr int BZ2 = S::BZ2, YPT = S::YPT, TPX = S::TPX;
   using HL = Halo<CT, CZ>;
-  __shared__ H halo[HL::SIZE];
-  __shared__ int slist[8 * NLIST_PAD];  // the interaction lists of the 8 parity classes
-  for (int t = threadIdx.x; t < 8 * NLIST_PAD; t += M2L_THREADS) slist[t] = dlists[t];
+  // the forward M2L of mixed-precision plans stages the typed multipole copy
+  constexpr bool TYPED = OP == CV_M2L && M::IDX != 0;
+  __shared__ __attribute__((aligned(16))) H halo[HL::SIZE];
+  // the offset lists of the 8 parity classes (one offset per MFMA), or the
+  // lanes' operand offsets of each offset pair (two per MFMA)
+  __shared__ int slist[OPM == 1 ? 8 * NLIST_PAD : 1];
+  __shared__ int2 spair[OPM == 2 ? 8 * NGRP * 2 : 1];
+  if constexpr (OPM == 1)
+    for (int t = threadIdx.x; t < 8 * NLIST_PAD; t += M2L_THREADS) slist[t] = dlists[t];
+  else
+    build_pair_table<HL>(spair, dlists, NGRP, EL * VPL, M2L_THREADS);
   const int grp = (int)blockIdx.x / T;
   const int T0 = grp * NT;
   const int lbk = (int)blockIdx.x - grp * T;
@@ -785,6 +888,11 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   const int gz = i % BZ2, gyo = i / BZ2;  // row i of tile m: lattice (m / TPX, YPT (m % TPX) + gyo, gz)
   // per-lane part of the operand addresses: row (gyo, gz) and the lane's K slice
   const H* hlane = halo + 2 * gyo * HL::YS + gz * KC + lr.tic;
+  // swizzled K halves (BF16): the lane's base for swizzle bit 0 and bit 1 of
+  // the fragment's first row
+  const int kh = lr.tic >> 3;
+  const H* hsw0 = halo + 2 * gyo * HL::YS + gz * KC + 8 * (kh ^ (gyo & 1));
+  const H* hsw1 = halo + 2 * gyo * HL::YS + gz * KC + 8 * (kh ^ (gyo & 1) ^ 1);
 
   Acc acc[CMT][NT];
 #pragma unroll
@@ -792,9 +900,11 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[m][t] = Acc{0, 0, 0, 0};
   const int* dl = slist + r * NLIST_PAD;  // visible after the first chunk's barrier
-  // the rotation of the offset order must be the same for every part of a
-  // split tile (the parts take consecutive slices of one ordering)
-  const int rot = (int)(((unsigned)(sg.first_block + tb * split) * 37u) % NOFF);
+  const int2* dp = spair + r * NGRP * 2 + lr.sel;
+  // the rotation of the offset order (of entries, or of pairs) must be the
+  // same for every part of a split tile (the parts take consecutive slices of
+  // one ordering)
+  const int rot = (int)(((unsigned)(sg.first_block + tb * split) * 37u) % (OPM == 1 ? NOFF : NGRP));
   auto entry = [&](int pos) {
     if (pos >= NOFF) return dl[NOFF];
     pos += rot;
@@ -821,20 +931,34 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
     const H* wl = Wt + (PK ? i : lr.tl) * VPL;
     const H* hl = PK ? hlane - lr.tic : hlane;
     auto bload = [&](EntryGroup g, int t) {
-      return *reinterpret_cast<const AF*>(wl + ((size_t)(off[t] + c) * NS + dl_dd(g.e)) * EL * VPL);
+      if constexpr (OPM == 1)
+        return *reinterpret_cast<const AF*>(wl + ((size_t)(off[t] + c) * NS + dl_dd(g.e)) * EL * VPL);
+      else
+        return *reinterpret_cast<const AF*>(wl + (size_t)(off[t] + c) * NS * EL * VPL + g.boff);
     };
     auto group = [&](int j) {
       EntryGroup g;
-      if constexpr (PK)
+      if constexpr (PK) {
         g.e = entry(4 * j + kq);
-      else if constexpr (OPM == 1)
+      } else if constexpr (OPM == 1) {
         g.e = __builtin_amdgcn_readfirstlane(entry(j));
-      else
-        g.e = entry(OPM * j + lr.sel);
+      } else {
+        int jr = j + rot;  // wave-uniform
+        jr = jr < NGRP ? jr : jr - NGRP;
+        const int2 v = dp[2 * jr];
+        g.aoff = v.x;
+        g.boff = v.y;
+      }
       return g;
     };
     auto aload = [&](EntryGroup g, AF (&a)[CMT]) {
-      const H* base = hl + HL::offset_part(r0, r1, r2, dl_d0(g.e), dl_d1(g.e), dl_d2(g.e));
+      const H* base;
+      if constexpr (OPM == 1)
+        base = hl + HL::offset_part(r0, r1, r2, dl_d0(g.e), dl_d1(g.e), dl_d2(g.e));
+      else if constexpr (HL::SWZ)
+        base = ((g.aoff & 1) ? hsw1 : hsw0) + (g.aoff & ~1);
+      else
+        base = hl + g.aoff;
 #pragma unroll
       for (int m = 0; m < CMT; ++m)
         a[m] = *reinterpret_cast<const AF*>(base + tile_part<HL, TPX, YPT>(m));
@@ -849,6 +973,7 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
       bs[1][t] = bload(es[1], t);
     }
     aload(es[0], as[0]);
+#pragma unroll 1
     for (int j = ja; j < jb; j += 3) {
 #pragma unroll
       for (int u = 0; u < 3; ++u) {
@@ -872,6 +997,8 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   // Tiles are sorted by degree, so the tiles that have chunk c are a prefix
   // of the group, and its length NA falls as c rises: the chunks with NA
   // tiles, [vt[NA], vt[NA - 1]), run as one loop with branch-free products.
+  TypedStage<CT, CZ, M2L_THREADS> ts;
+  if constexpr (TYPED) ts.plan(nsp, tx0, ty0, tz0);
   auto chunks = [&](auto pk) {
     count_down<NT>([&](auto nac) {
       constexpr int NA = decltype(nac)::value;
@@ -879,7 +1006,10 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
       if constexpr (NA < NT) cb = vt[NA];
       for (int c = cb; c < vt[NA - 1]; ++c) {
         __syncthreads();
-        stage_halo<CT, CZ, M2L_THREADS>(halo, src, NC4, ncellp, nsp, tx0, ty0, tz0, c);
+        if constexpr (TYPED)
+          ts.run(halo, (const H*)sg.t, ncellp, c);
+        else
+          stage_halo<CT, CZ, M2L_THREADS>(halo, src, NC4, ncellp, nsp, tx0, ty0, tz0, c);
         __syncthreads();
         offsets(pk, nac, c);
       }

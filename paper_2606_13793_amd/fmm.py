@@ -31,7 +31,7 @@ EXPORTS = (
     "fmm_last_error", "fmm_last_status", "fmm_debug_expansions", "fmm_multi_index",
     "fmm_profile_enable", "fmm_profile_read", "fmm_profile_stage_name",
     "fmm_batch_plan_create", "fmm_batch_solve", "fmm_batch_info", "fmm_deposit_cic",
-    "fmm_fd_force", "fmm_solve_backward_noalloc",
+    "fmm_fd_force", "fmm_solve_backward_noalloc", "fmm_batch_timestamps", "fmm_batch_field_ms",
 )
 
 
@@ -94,6 +94,8 @@ def lib():
         L.fmm_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
         L.fmm_batch_info.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
                                      ctypes.POINTER(ctypes.c_double), i]
+        L.fmm_batch_timestamps.argtypes = [vp, i]
+        L.fmm_batch_field_ms.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i]
         L.fmm_deposit_cic.argtypes = [i, ctypes.c_longlong, vp, vp, vp, vp]
         L.fmm_fd_force.argtypes = [i, vp, vp, vp]
         _lib = L
@@ -293,6 +295,17 @@ class Batch:
 
     def workspace_bytes(self) -> int:
         return int(lib().fmm_plan_workspace_bytes(self.ptr))
+
+    def timestamps(self, enable: bool = True):
+        """Record per-field completion times of the following solves."""
+        _check(lib().fmm_batch_timestamps(self.ptr, int(bool(enable))))
+
+    def field_ms(self) -> list:
+        """Milliseconds from the start of the last timed solve to each field's completion."""
+        k = len(self.sizes)
+        ms = (ctypes.c_double * k)()
+        _check(lib().fmm_batch_field_ms(self.ptr, ms, k))
+        return [ms[i] for i in range(k)]
 
     def profile(self, enable: bool = True):
         _check(lib().fmm_profile_enable(self.ptr, int(bool(enable))))

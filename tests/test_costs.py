@@ -66,3 +66,22 @@ def test_near_and_m2p_pairs_equal_the_oracle_partition(orc, n, dl):
     assert costs.near_pairs(n, dl) == near
     # the oracle reports unigrid sources; an M2P source is a finest FMM cell of 8^dl of them
     assert costs.m2p_pairs(n, dl) * 8 ** dl == m2p
+
+
+def test_operator_counts_at_the_papers_orders():
+    """Per-operator counts at p = 3, nmax = 2 (the paper's Sec. 4 setting),
+    each re-derived by enumerating the terms the operator sums."""
+    c = costs.operator_counts(3, 2)
+    deg = lambda t: sum(t)
+    terms = lambda P: [(a, b, k) for a in range(P + 1) for b in range(P + 1 - a) for k in range(P + 1 - a - b)]
+    # M2M: pairs b <= a (componentwise), |a| <= 2
+    assert c["m2m"] == 2 * sum(1 for a in terms(2) for b in terms(2) if all(x <= y for x, y in zip(b, a)))
+    # L2L: pairs (b, g) with |b| + |g| <= 3
+    assert c["l2l"] == 2 * sum(1 for b in terms(3) for g in terms(3) if deg(b) + deg(g) <= 3)
+    # M2L: pairs (a, b) with |b| <= 3, |a| <= min(2, 3 - |b|)
+    assert c["m2l"] == 2 * sum(1 for b in terms(3) for a in terms(2) if deg(a) <= 3 - deg(b))
+    assert c["l2p"] == (2 * 20, 2 * (20 + 3 * 10))
+    assert c["m2p"] == (2 * 10, 8 * 10)
+    assert c["p2p"] == (2, 8)
+    # the paper's direct-sum count is this counting's potential-only one
+    assert costs.PAPER_SEC4["p2p"] == c["p2p"][0]

@@ -225,3 +225,33 @@ def test_fmm2_batch_times_only_its_tile_depth(F):
     assert info["bottom_tile"] == 16
     assert info["tune_ms"][0] > 0 and info["tune_ms"][1] > 0
     assert info["tune_ms"][2] == 0 and info["tune_ms"][3] == 0
+
+
+def test_per_field_completion_times(F):
+    """fmm_batch_timestamps: each field's completion time lies inside the
+    batch solve's own span, fields are reported in both graph replays and
+    direct launches, and recording does not change the results."""
+    import torch
+    sizes = [32, 64, 16, 128, 32]
+    _say("case batch per-field timestamps")
+    B = F.Batch(sizes, 4, "fp32")
+    rhos = _fields(sizes, torch.float32)
+    ref, ref_g = B.solve(rhos)
+    B.timestamps(True)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for rep in range(3):  # the first captures a new graph
+        a.record()
+        phis, gs = B.solve(rhos)
+        b.record()
+    torch.cuda.synchronize()
+    span = a.elapsed_time(b)
+    ms = B.field_ms()
+    _say(f"  batch {span:.3f} ms; fields {['%.3f' % x for x in ms]}")
+    assert len(ms) == len(sizes) and all(0.0 < x <= span * 1.05 + 0.05 for x in ms), (ms, span)
+    for f in range(len(sizes)):
+        assert torch.equal(phis[f], ref[f]) and torch.equal(gs[f], ref_g[f])
+    B.timestamps(False)
+    with pytest.raises(F.FmmError):
+        B.field_ms()
+    single = F.Plan(16, 4)
+    assert F.lib().fmm_batch_timestamps(single.ptr, 1) == F.FMM_ERR_INVALID_ARG
