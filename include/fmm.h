@@ -227,6 +227,10 @@ int fmm_last_status(void);
  * with h = 2^-level the cell size and dx = 1/n.  Layout out[cell][term] with
  * cells of the level in C order and terms in the order of
  * fmm_multi_index().  `count` is the number of doubles `out` holds.
+ * A plan whose finest level runs M2P in FP32 or BF16 (delta_l = 1) keeps
+ * that level's multipoles in the compute type only (the level below is
+ * formed from the density directly): which = 0 at level F returns
+ * FMM_ERR_UNSUPPORTED there.
  */
 int fmm_debug_expansions(fmm_plan* plan, int which, int level, double* out, size_t count);
 

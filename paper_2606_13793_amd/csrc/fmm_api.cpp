@@ -125,6 +125,7 @@ void release(fmm_plan* pl) {
     st = fmm::SegTable{};
   };
   free_st(pl->s_p2m);
+  free_st(pl->s_p2m2);
   for (auto& st : pl->s_m2m) free_st(st);
   for (auto& st : pl->s_conv) free_st(st);
   for (auto& st : pl->s_l2l) free_st(st);
@@ -321,17 +322,34 @@ namespace fmm {
 // per level for the M2M and L2L chains) covers every field of the plan.
 int build_schedule(fmm_plan* pl) {
   const int RS = loc_stride(pl->p), klow = m2l_low_from(pl);
-  SegList p2m, m2m[16], conv[2], l2l[16], bot[2][2];
+  SegList p2m, p2m2, m2m[16], conv[2], l2l[16], bot[2][2];
   for (int f = 0; f < (int)pl->fld.size(); ++f) {
     const Field& fd = pl->fld[f];
     const int F = fd.F, nF = fd.n >> pl->dl;
     Seg sg{};
     sg.n = fd.n;
     sg.field = f;
-    sg.b = (double*)fd.lev[F].M;
+    // the FP64 level-F multipoles are read only by an FP64 bottom kernel (the
+    // level below is formed from the unigrid), so a low-precision bottom
+    // gets its typed copy alone
+    sg.b = pl->dl == 1 && bottom_low(pl, F) ? nullptr : (double*)fd.lev[F].M;
     sg.t = fd.lev[F].Mt;
     p2m.add(sg, cdiv((long long)nF * nF * nF, 256));
-    for (int k = F; k >= 3; --k) {
+    // FMM-1: the multipoles of level F - 1 straight from the 4^3 unigrid
+    // cells of each cell (as FMM-2's P2M), which reads the density instead
+    // of the 8x larger level-F grid; M2M then starts at level F - 1
+    int top = F;
+    if (pl->dl == 1 && F >= 3) {
+      Seg s2{};
+      s2.n = fd.n;
+      s2.field = f;
+      s2.b = (double*)fd.lev[F - 1].M;
+      s2.t = fd.lev[F - 1].Mt;
+      const long long nc = 1LL << (3 * (F - 1));
+      p2m2.add(s2, cdiv(nc, 256));
+      top = F - 1;
+    }
+    for (int k = top; k >= 3; --k) {
       Seg m{};
       m.n = 1 << k;
       m.field = f;
@@ -432,6 +450,7 @@ int build_schedule(fmm_plan* pl) {
   }
   int rc;
   if ((rc = upload_segs(pl, pl->s_p2m, p2m))) return rc;
+  if ((rc = upload_segs(pl, pl->s_p2m2, p2m2))) return rc;
   for (int k = 0; k < 16; ++k) {
     if ((rc = upload_segs(pl, pl->s_m2m[k], m2m[k]))) return rc;
     if ((rc = upload_segs(pl, pl->s_l2l[k], l2l[k]))) return rc;
@@ -1416,6 +1435,8 @@ int fmm_debug_expansions(fmm_plan* plan, int which, int level, double* out, size
   if (which != 0 && which != 1) return fail(FMM_ERR_INVALID_ARG, "which must be 0 or 1");
   const int lo = which == 0 ? 2 : 3;
   if (level < lo || level > plan->F) return fail(FMM_ERR_INVALID_ARG, "level %d outside [%d, %d]", level, lo, plan->F);
+  if (which == 0 && level == plan->F && plan->dl == 1 && fmm::bottom_low(plan, plan->F))
+    return fail(FMM_ERR_UNSUPPORTED, "a low-precision bottom keeps the level-%d multipoles in its compute type only", level);
   const fmm::Level& lv = plan->lev[level];
   const int nt = which == 0 ? plan->NMX : plan->NL;
   const int nch = (nt + 3) / 4;

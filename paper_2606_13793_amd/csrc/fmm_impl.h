@@ -171,9 +171,9 @@ __global__ void k_dtab2(double* __restrict__ out, int PD, int ND) {
 // (-1)^(q.a) depends on a only through a mod 2, so the 8 signed sums of the
 // children are formed once (a Walsh transform) and each term is one product.
 // ---------------------------------------------------------------------------
-// Segments: n = unigrid cells per axis, field, b = Mhat_F, t = its copy in
-// the compute type CT (mixed precision; null or CT = double: none).  256
-// cells T per block.
+// Segments: n = unigrid cells per axis, field, b = Mhat_F (or null: not
+// written), t = its copy in the compute type CT (mixed precision; null or
+// CT = double: none).  256 cells T per block.
 template <typename TI, typename CT>
 __global__ __launch_bounds__(256) void k_p2m(const Seg* __restrict__ segs, int nseg, IoArg io, int NM, int NC) {
   const Seg& sg = find_seg(segs, nseg, blockIdx.x);
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(256) void k_p2m(const Seg* __restrict__ segs, int n
       }
       o[e] = val;
     }
-    *reinterpret_cast<d4*>(M + (c * ncellp + cp) * 4) = o;
+    if (M) *reinterpret_cast<d4*>(M + (c * ncellp + cp) * 4) = o;
     if constexpr (Mf<CT>::IDX != 0) {
       constexpr int KC = Mf<CT>::KC;
       if (sg.t)
@@ -226,6 +226,9 @@ __global__ __launch_bounds__(256) void k_p2m(const Seg* __restrict__ segs, int n
 
 // P2M of FMM-2: Mhat_F[a] = sum_s rho_{4T+s} w_s^a / a!, w_s,i = (3 - 2 s_i) / 8
 // over the 64 unigrid cells s of T, summed axis by axis.  Segments as k_p2m.
+// FMM-1 plans use it for level F - 1, whose cells also hold 4^3 unigrid
+// cells: the same multipoles as M2M of the level-F P2M (M2M re-centres
+// exactly), without reading the level-F grid.
 template <typename TI, typename CT>
 __global__ __launch_bounds__(256) void k_p2m2(const Seg* __restrict__ segs, int nseg, IoArg io, int NM, int NC) {
   const Seg& sg = find_seg(segs, nseg, blockIdx.x);
@@ -1052,7 +1055,7 @@ hipError_t build_tables_t(fmm_plan* pl, bool bottom, bool m2l, hipStream_t s) {
   using H = typename M::H;
   constexpr int KC = M::KC, OPM = M::OPM, VPL = M::VPL, EL = 64 / OPM, KT = 4 * VPL, X = M::IDX;
   const int NM = pl->NM, NL = pl->NL;
-  const long long NCK = (NM + KC - 1) / KC, NLT = (NL + KT - 1) / KT, NPT = (216 + KT - 1) / KT;
+  const long long NCK = (NM + KC - 1) / KC, NLT = (NL + KT - 1) / KT, NPT = kNearK1 / KT;
   hipError_t e;
   if (bottom && !pl->wm2p[X] && pl->dl == 2) {
     // FMM-2: 8 groups of each table, near field over the 12^3 block
@@ -1211,6 +1214,11 @@ hipError_t solve_ct(fmm_plan* pl, IoArg io, hipStream_t s) {
       hipLaunchKernelGGL((k_p2m<TI, CT>), dim3(pl->s_p2m.blocks), dim3(256), 0, s, pl->s_p2m.dev, pl->s_p2m.nseg, io,
                          pl->NMX, NC);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (pl->s_p2m2.nseg) {
+      hipLaunchKernelGGL((k_p2m2<TI, CT>), dim3(pl->s_p2m2.blocks), dim3(256), 0, s, pl->s_p2m2.dev,
+                         pl->s_p2m2.nseg, io, pl->NMX, NC);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
   }
   for (int k = pl->maxF; k >= 3; --k) {
     const SegTable& st = pl->s_m2m[k];

@@ -308,6 +308,7 @@ struct fmm_plan {
   int* flag = nullptr;      // device scratch flag (finite check)
   // launch schedule: segment tables of every launch site, built with the plan
   fmm::SegTable s_p2m;
+  fmm::SegTable s_p2m2;             // FMM-1: level F - 1 formed from the unigrid (64 cells each)
   fmm::SegTable s_m2m[16];          // M2M into level k - 1 (index k)
   fmm::SegTable s_conv[2];          // forward M2L: [0] FP64 levels, [1] low-precision levels
   fmm::SegTable s_l2l[16];          // L2L into level k (index k)

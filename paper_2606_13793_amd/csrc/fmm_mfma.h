@@ -66,6 +66,12 @@ constexpr int bottom_wpr() { return Mf<CT>::IDX == 1 ? 1 : 2; }
 template <typename CT>
 constexpr int bottom_threads() { return 512 * bottom_wpr<CT>(); }
 
+// K extent of the near-field block of FMM-1: the 6^3 unigrid cells around a
+// row's level-F cell, z padded to 8 (K step k: z run (w0, w1) = k / 8 of the
+// block, z offset k % 8; offsets 6 and 7 have zero B rows), so that a lane's
+// 8 BF16 operands are one z run of the densities staged in LDS.
+constexpr int kNearK1 = 6 * 6 * 8;
+
 template <int BZ>
 struct BotShape {
   static constexpr int HZ = BZ + 6, HZ2 = HZ / 2, BZ2 = BZ / 2;
@@ -259,6 +265,15 @@ __device__ constexpr int tile_part(int m) {
 // row's cell and the columns are the 8 unigrid children q of that child.
 // The B tables then hold 8 groups, and the near field is the 12^3 block of
 // unigrid cells of the 27 level-F cells around the row's cell.
+// Calls f(std::integral_constant<int, k>) for k = I, I + 1, ..., N - 1.
+template <int N, int I = 0, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<N, I + 1>(f);
+  }
+}
+
 // minimum waves per SIMD (the second launch bound): one 1024-thread block or
 // two 512-thread FP32 blocks per CU (4 waves per SIMD, <= 128 registers)
 template <typename CT>
@@ -282,7 +297,8 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
   constexpr int NM = nterms(P), NC4 = (NM + 3) / 4;
   constexpr int NL = nterms(P);
   constexpr int NB = 3 << DL, NNEAR = NB * NB * NB;  // near-field block: 6^3 or 12^3 unigrid cells
-  constexpr int KT = 4 * VPL, NLT = (NL + KT - 1) / KT, NPT = (NNEAR + KT - 1) / KT;
+  constexpr int KT = 4 * VPL, NLT = (NL + KT - 1) / KT;
+  constexpr int NPT = DL == 1 ? kNearK1 / KT : (NNEAR + KT - 1) / KT;
   constexpr int NCK = (NM + KC - 1) / KC;
   constexpr int NGRP = (NLIST + OPM - 1) / OPM;
   constexpr int THREADS = bottom_threads<CT>(), MTW = BOT_MT / bottom_wpr<CT>();  // row tiles per wave
@@ -446,100 +462,188 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
   const int n = nF << DL;
   const long long N = (long long)n * n * n;
   constexpr int RS = loc_stride(P);
-  // the lane's own row (A operand) of tile m and its level-F cell, clamped into the grid
-  auto cell_of = [&](int m, int& c0, int& c1, int& c2) {
-    c0 = tx0 + 2 * (m / TPX) + r0;
-    c1 = ty0 + 2 * (YPT * (m % TPX) + gyo) + r1;
-    c2 = tz0 + 2 * gz + r2;
-    c0 = c0 < nF ? c0 : 0;
-    c1 = c1 < nF ? c1 : 0;
-    c2 = c2 < nF ? c2 : 0;
-  };
-  // tail K blocks of row tile m: L2P of the M2L part of the own local (stored
-  // with the parent P'), L2P from the parent level's full local, near field.
-  // UL (L2P) and UN (near field) chunks at a time, their operand loads issued
-  // together: the tail is bound by load latency, not by its few products.
-  constexpr int UL = M::IDX == 1 ? 2 : 1, UN = 4;
-  auto tail = [&](int m, Acc (&am)[2]) {
-    int c0, c1, c2;
-    cell_of(m, c0, c1, c2);
-    if (Lf) {
-      const int nP = nF >> 1, nPP = nP >> 1;
-      const auto own = gmem(Lf + (((long long)(c0 >> 1) * nP + (c1 >> 1)) * nP + (c2 >> 1)) * RS);
-      const auto par =
-          gmem(Lpar ? Lpar + (((long long)(c0 >> 2) * nPP + (c1 >> 2)) * nPP + (c2 >> 2)) * RS : Lf);
-      const int qP = (((c0 >> 1) & 1) << 2) | (((c1 >> 1) & 1) << 1) | ((c2 >> 1) & 1);
-      const int* colr = scol + r * (NLT * KT);
-      const int* colq = scol + qP * (NLT * KT);
-      const H* w2 = Wl2p2 + (size_t)r * NLT * 2 * 64 * VPL + lane * VPL;
+  // ---- Tail K blocks, after the M2P sum: L2P of the M2L part of each row's
+  // own local (stored with its parent), L2P from the parent level's full
+  // local, and (FMM-1) the near field.  Their operands are gathered per row
+  // and term, which as per-lane loads would issue one address per element;
+  // instead the block stages them in the (now free) halo LDS with loads in
+  // which consecutive lanes read consecutive elements, and the products run
+  // K step by K step over all of the wave's row tiles, so each B fragment is
+  // loaded once per step.
+  constexpr int TC = BX * BY * BZ, TP = TC / 8;  // the tile's level-F cells, and their parents
+  // tile-local index of the level-F cell of the lane's row in tile m, and of its parent
+  auto lcell = [&](int m) { return ((2 * (m / TPX) + r0) * BY + 2 * (YPT * (m % TPX) + gyo) + r1) * BZ + 2 * gz + r2; };
+  auto lpar = [&](int m) { return ((m / TPX) * (BY / 2) + YPT * (m % TPX) + gyo) * (BZ / 2) + gz; };
+  if constexpr (DL == 1) {
+  if (Lf) {
+    // terms per pass (chunks of KT): the own and parent operands of TC + TP
+    // cells fit the halo area; row stride KPS keeps BF16 rows 16-byte aligned
+    // and spreads the rows of a fragment over the LDS banks
+    constexpr int CPP = M::IDX == 2 ? 1 : 3, KP = CPP * KT, KPS = M::IDX == 2 ? 40 : 13;
+    static_assert((TC + TP) * KPS <= HL::SIZE, "tail operands exceed the halo area");
+    H* const own = halo;
+    H* const par = halo + TC * KPS;
+    const int nP = nF >> 1, nPP = nP >> 1;
+    const H* const w2 = Wl2p2 + (size_t)r * NLT * 2 * 64 * VPL + lane * VPL;
 #pragma unroll 1
-      for (int cb = 0; cb < NLT; cb += UL) {
-        double va[UL][VPL], vp[UL][VPL];
-        AF bo[UL][2], bp[UL][2];
-#pragma unroll
-        for (int u = 0; u < UL; ++u) {
-          const int c = cb + u < NLT ? cb + u : 0;
-#pragma unroll
-          for (int v = 0; v < VPL; ++v) {
-            const int bt = KT * c + VPL * kq + v;
-            const int co = colr[bt], cq = colq[bt];
-            const bool ok = cb + u < NLT && co >= 0;
-            va[u][v] = ok ? own[co] : 0.0;
-            vp[u][v] = (ok && Lpar) ? par[cq] : 0.0;
-          }
-#pragma unroll
-          for (int t = 0; t < 2; ++t) {
-            bo[u][t] = *reinterpret_cast<const AF*>(Wl2p + ((size_t)(c * 2 + t) * 64 + lane) * VPL);
-            bp[u][t] = Lpar ? *reinterpret_cast<const AF*>(w2 + (size_t)(c * 2 + t) * 64 * VPL) : bo[u][t];
-          }
+    for (int c0 = 0; c0 < NLT; c0 += CPP) {
+      __syncthreads();  // the area's previous contents fully consumed
+      const int k0 = c0 * KT;
+      for (int e = threadIdx.x; e < TC * KP; e += THREADS) {
+        const int cell = e / KP, kk = e - cell * KP, bt = k0 + kk;
+        const int g0 = tx0 + cell / (BY * BZ), g1 = ty0 + (cell / BZ) % BY, g2 = tz0 + cell % BZ;
+        double v = 0.0;
+        if (bt < NL && g0 < nF && g1 < nF && g2 < nF) {
+          const int q = ((g0 & 1) << 2) | ((g1 & 1) << 1) | (g2 & 1);
+          v = Lf[(((long long)(g0 >> 1) * nP + (g1 >> 1)) * nP + (g2 >> 1)) * RS + scol[q * (NLT * KT) + bt]];
         }
+        own[cell * KPS + kk] = static_cast<H>(v);
+      }
+      // (no parent level above F = 3: zero operands, so the products need no branch)
+      for (int e = threadIdx.x; e < TP * KP; e += THREADS) {
+        const int pc = e / KP, kk = e - pc * KP, bt = k0 + kk;
+        const int g0 = (tx0 >> 1) + pc / ((BY / 2) * (BZ / 2)), g1 = (ty0 >> 1) + (pc / (BZ / 2)) % (BY / 2),
+                  g2 = (tz0 >> 1) + pc % (BZ / 2);
+        double v = 0.0;
+        if (Lpar && bt < NL && g0 < nP && g1 < nP && g2 < nP) {
+          const int q = ((g0 & 1) << 2) | ((g1 & 1) << 1) | (g2 & 1);
+          v = Lpar[(((long long)(g0 >> 1) * nPP + (g1 >> 1)) * nPP + (g2 >> 1)) * RS + scol[q * (NLT * KT) + bt]];
+        }
+        par[pc * KPS + kk] = static_cast<H>(v);
+      }
+      __syncthreads();
+#pragma unroll 1
+      for (int cl = 0; cl < CPP; ++cl) {
+        const int c = c0 + cl;
+        if (c >= NLT) break;
+        AF bo[2], bp[2];
 #pragma unroll
-        for (int u = 0; u < UL; ++u) {
-          if (cb + u < NLT) {
-            am[0] = M::op(M::frag(va[u]), bo[u][0], am[0]);
-            am[1] = M::op(M::frag(va[u]), bo[u][1], am[1]);
-            if (Lpar) {
-              am[0] = M::op(M::frag(vp[u]), bp[u][0], am[0]);
-              am[1] = M::op(M::frag(vp[u]), bp[u][1], am[1]);
+        for (int t = 0; t < 2; ++t) {
+          bo[t] = *reinterpret_cast<const AF*>(Wl2p + ((size_t)(c * 2 + t) * 64 + lane) * VPL);
+          bp[t] = *reinterpret_cast<const AF*>(w2 + (size_t)(c * 2 + t) * 64 * VPL);
+        }
+        static_for<MTW>([&](auto mi) {
+          constexpr int mw = decltype(mi)::value;
+          const AF ao = *reinterpret_cast<const AF*>(own + lcell(m0 + mw) * KPS + KT * cl + VPL * kq);
+          const AF ap = *reinterpret_cast<const AF*>(par + lpar(m0 + mw) * KPS + KT * cl + VPL * kq);
+          acc[mw][0] = M::op(ao, bo[0], acc[mw][0]);
+          acc[mw][1] = M::op(ao, bo[1], acc[mw][1]);
+          acc[mw][0] = M::op(ap, bp[0], acc[mw][0]);
+          acc[mw][1] = M::op(ap, bp[1], acc[mw][1]);
+        });
+      }
+    }
+  }
+  {
+    // Near field: the densities of the tile's unigrid cells and a 2-cell
+    // margin, [UX][UY][UZ] from unigrid (2 tx0 - 2, 2 ty0 - 2, 2 tz0 - 2), in
+    // the compute type, zero outside the grid and in the two z positions past
+    // the margin.  K step k: z run k / 8 = (w0, w1) over the 6 x 6 block, z
+    // offset k % 8 (offsets 6 and 7 have zero B rows).
+    constexpr int UX = 2 * BX + 4, UY = 2 * BY + 4, UZ = 2 * BZ + 6;
+    static_assert(UX * UY * UZ <= HL::SIZE, "near-field block exceeds the halo area");
+    H* const ub = halo;
+    __syncthreads();
+    const int x0 = 2 * tx0 - 2, y0 = 2 * ty0 - 2, z0 = 2 * tz0 - 2;
+    for (int e = threadIdx.x; e < UX * UY * UZ; e += THREADS) {
+      const int uz = e % UZ, uy = (e / UZ) % UY, ux = e / (UZ * UY);
+      const int w0 = x0 + ux, w1 = y0 + uy, w2 = z0 + uz;
+      const bool in = uz < UZ - 2 && w0 >= 0 && w1 >= 0 && w2 >= 0 && w0 < n && w1 < n && w2 < n;
+      ub[e] = in ? static_cast<H>(rho[((long long)w0 * n + w1) * n + w2]) : H(0);
+    }
+    __syncthreads();
+    // the lane's row: ub offset of its 6^3 block's corner, per row tile
+    auto ubase = [&](int m) {
+      return (2 * (2 * (m / TPX) + r0) * UY + 2 * (2 * (YPT * (m % TPX) + gyo) + r1)) * UZ + 2 * (2 * gz + r2);
+    };
+#pragma unroll 1
+    for (int c = 0; c < NPT; ++c) {
+      AF bn[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) bn[t] = *reinterpret_cast<const AF*>(Wp2p + ((size_t)(c * 2 + t) * 64 + lane) * VPL);
+      const int k = KT * c + VPL * kq, run = k >> 3;
+      const int koff = (run / 6) * (UY * UZ) + (run % 6) * UZ + (k & 7);
+      static_for<MTW>([&](auto mi) {
+        constexpr int mw = decltype(mi)::value;
+        const H* src = ub + ubase(m0 + mw) + koff;
+        AF a;
+        if constexpr (VPL == 8) {
+          // 8 consecutive BF16 from an even element offset: four 4-byte reads
+          const unsigned int* s32 = reinterpret_cast<const unsigned int*>(src);
+          const u32x4 w = {s32[0], s32[1], s32[2], s32[3]};
+          a = __builtin_bit_cast(AF, w);
+        } else {
+          a = *src;
+        }
+        acc[mw][0] = M::op(a, bn[0], acc[mw][0]);
+        acc[mw][1] = M::op(a, bn[1], acc[mw][1]);
+      });
+    }
+  }
+  } else {
+    // FMM-2: per-row loads of the L2P operands (its tail is dominated by the
+    // 12^3 near field, whose B fragments serve all row tiles of the wave)
+    // the lane's own row (A operand) of tile m and its level-F cell, clamped into the grid
+    auto cell_of = [&](int m, int& c0, int& c1, int& c2) {
+      c0 = tx0 + 2 * (m / TPX) + r0;
+      c1 = ty0 + 2 * (YPT * (m % TPX) + gyo) + r1;
+      c2 = tz0 + 2 * gz + r2;
+      c0 = c0 < nF ? c0 : 0;
+      c1 = c1 < nF ? c1 : 0;
+      c2 = c2 < nF ? c2 : 0;
+    };
+    // L2P K blocks of row tile m: the M2L part of the own local (stored with
+    // the parent P'), then the parent level's full local; UL chunks at a time,
+    // their operand loads issued together
+    constexpr int UL = M::IDX == 1 ? 2 : 1;
+    auto tail = [&](int m, Acc (&am)[2]) __attribute__((always_inline)) {
+      int c0, c1, c2;
+      cell_of(m, c0, c1, c2);
+      if (Lf) {
+        const int nP = nF >> 1, nPP = nP >> 1;
+        const auto own = gmem(Lf + (((long long)(c0 >> 1) * nP + (c1 >> 1)) * nP + (c2 >> 1)) * RS);
+        const auto par =
+            gmem(Lpar ? Lpar + (((long long)(c0 >> 2) * nPP + (c1 >> 2)) * nPP + (c2 >> 2)) * RS : Lf);
+        const int qP = (((c0 >> 1) & 1) << 2) | (((c1 >> 1) & 1) << 1) | ((c2 >> 1) & 1);
+        const int* colr = scol + r * (NLT * KT);
+        const int* colq = scol + qP * (NLT * KT);
+        const H* w2 = Wl2p2 + (size_t)r * NLT * 2 * 64 * VPL + lane * VPL;
+#pragma unroll 1
+        for (int cb = 0; cb < NLT; cb += UL) {
+          double va[UL][VPL], vp[UL][VPL];
+          AF bo[UL][2], bp[UL][2];
+#pragma unroll
+          for (int u = 0; u < UL; ++u) {
+            const int c = cb + u < NLT ? cb + u : 0;
+#pragma unroll
+            for (int v = 0; v < VPL; ++v) {
+              const int bt = KT * c + VPL * kq + v;
+              const int co = colr[bt], cq = colq[bt];
+              const bool ok = cb + u < NLT && co >= 0;
+              va[u][v] = ok ? own[co] : 0.0;
+              vp[u][v] = (ok && Lpar) ? par[cq] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+              bo[u][t] = *reinterpret_cast<const AF*>(Wl2p + ((size_t)(c * 2 + t) * 64 + lane) * VPL);
+              bp[u][t] = Lpar ? *reinterpret_cast<const AF*>(w2 + (size_t)(c * 2 + t) * 64 * VPL) : bo[u][t];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < UL; ++u) {
+            if (cb + u < NLT) {
+              am[0] = M::op(M::frag(va[u]), bo[u][0], am[0]);
+              am[1] = M::op(M::frag(va[u]), bo[u][1], am[1]);
+              if (Lpar) {
+                am[0] = M::op(M::frag(vp[u]), bp[u][0], am[0]);
+                am[1] = M::op(M::frag(vp[u]), bp[u][1], am[1]);
+              }
             }
           }
         }
       }
-    }
-    if constexpr (DL == 2) return;  // FMM-2 runs its near field for all row tiles below
-    const auto rg = gmem(rho);
-#pragma unroll 1
-    for (int cb = 0; cb < NPT; cb += UN) {
-      TI va[UN][VPL];  // densities in the input type until the conversion
-      AF bn[UN][2];
-#pragma unroll
-      for (int u = 0; u < UN; ++u) {
-        const int c = cb + u < NPT ? cb + u : 0;
-#pragma unroll
-        for (int v = 0; v < VPL; ++v) {
-          const int k = KT * c + VPL * kq + v;
-          const int w0 = (c0 << DL) + k / (NB * NB) - (1 << DL), w1 = (c1 << DL) + (k / NB) % NB - (1 << DL),
-                    w2 = (c2 << DL) + k % NB - (1 << DL);
-          va[u][v] = (cb + u < NPT && k < NNEAR && w0 >= 0 && w1 >= 0 && w2 >= 0 && w0 < n && w1 < n && w2 < n)
-                         ? rg[((long long)w0 * n + w1) * n + w2]
-                         : TI(0);
-        }
-#pragma unroll
-        for (int t = 0; t < 2; ++t)
-          bn[u][t] = *reinterpret_cast<const AF*>(Wp2p + ((size_t)(c * 2 + t) * 64 + lane) * VPL);
-      }
-#pragma unroll
-      for (int u = 0; u < UN; ++u) {
-        if (cb + u < NPT) {
-          am[0] = M::op(M::frag(va[u]), bn[u][0], am[0]);
-          am[1] = M::op(M::frag(va[u]), bn[u][1], am[1]);
-        }
-      }
-    }
-  };
-#pragma unroll
-  for (int m = 0; m < MTW; ++m) tail(m0 + m, acc[m]);
-  if constexpr (DL == 2) {
+    };
+    static_for<MTW>([&](auto mi) { tail(m0 + decltype(mi)::value, acc[decltype(mi)::value]); });
     // FMM-2's near field, 12^3 sources per row: the B fragments of a K step
     // serve every row tile of the wave, so they are loaded once per step
     // instead of once per row tile.  Row cells packed as c0 << 16 | c1 << 8 | c2.
@@ -653,7 +757,7 @@ __global__ void k_expand_bottom(const double* __restrict__ Dtab, typename Mf<CT>
   using M = Mf<CT>;
   using H = typename M::H;
   constexpr int KC = M::KC, OPM = M::OPM, VPL = M::VPL, EL = 64 / OPM, KT = 4 * VPL;
-  const int NCK = (NM + KC - 1) / KC, NLT = (NL + KT - 1) / KT, NPT = (216 + KT - 1) / KT;
+  const int NCK = (NM + KC - 1) / KC, NLT = (NL + KT - 1) / KT, NPT = kNearK1 / KT;
   const long long n_m2p = (long long)NCK * NSLOT * 2 * EL * VPL;
   const long long n_l2p = (long long)NLT * 2 * 64 * VPL, n_l2p2 = 8 * n_l2p, n_p2p = (long long)NPT * 2 * 64 * VPL;
   long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -700,7 +804,8 @@ __global__ void k_expand_bottom(const double* __restrict__ Dtab, typename Mf<CT>
   } else if (kind == 1) {
     if (k < NL) val = l2p_parent_coef(k, rp, q, o);
   } else {
-    if (k < 216) val = p2p_coef(k / 36 - 2, (k / 6) % 6 - 2, k % 6 - 2, q, o);
+    const int run = k >> 3, w2 = k & 7;  // the padded near-field order (kNearK1)
+    if (k < kNearK1 && w2 < 6) val = p2p_coef(run / 6 - 2, run % 6 - 2, w2 - 2, q, o);
   }
   out[e] = static_cast<H>(val);
 }
