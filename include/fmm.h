@@ -51,7 +51,8 @@ typedef enum {
   FMM_OK = 0,
   FMM_ERR_INVALID_ARG = -1,   /* bad size, order, pointer or option */
   FMM_ERR_UNSUPPORTED = -2,   /* well-formed but not provided (periodic BC, delta_l outside {1, 2},
-                                 the backward pass of a batch plan) */
+                                 the backward pass of a batch plan, the FP64 export of a grid a
+                                 plan keeps in a low compute type only) */
   FMM_ERR_OUT_OF_MEMORY = -3, /* device allocation failed */
   FMM_ERR_DEVICE = -4,        /* HIP runtime error (no device, launch failure) */
   FMM_ERR_NONFINITE = -5      /* rho holds NaN/Inf (only with check_finite) */
@@ -228,9 +229,10 @@ int fmm_last_status(void);
  * cells of the level in C order and terms in the order of
  * fmm_multi_index().  `count` is the number of doubles `out` holds.
  * A plan whose finest level runs M2P in FP32 or BF16 (delta_l = 1) keeps
- * that level's multipoles in the compute type only (the level below is
- * formed from the density directly): which = 0 at level F returns
- * FMM_ERR_UNSUPPORTED there.
+ * that level's multipoles and the M2L part of its locals in the compute type
+ * only (the level below is formed from the density directly): level F
+ * returns FMM_ERR_UNSUPPORTED there, for which = 0 and, unless the M2L of
+ * that level splits its offset sums (small grids), for which = 1.
  */
 int fmm_debug_expansions(fmm_plan* plan, int which, int level, double* out, size_t count);
 

@@ -119,6 +119,7 @@ void release(fmm_plan* pl) {
       if (lv.M) (void)hipFree(lv.M);
       if (lv.Mt) (void)hipFree(lv.Mt);
       if (lv.L) (void)hipFree(lv.L);
+      if (lv.Lt) (void)hipFree(lv.Lt);
     }
   auto free_st = [](fmm::SegTable& st) {
     if (st.dev) (void)hipFree(st.dev);
@@ -369,6 +370,7 @@ int build_schedule(fmm_plan* pl) {
       c.a = (const double*)fd.lev[k - 1].M;
       c.b = (double*)fd.lev[k].L;
       c.t = k >= klow ? fd.lev[k - 1].Mt : nullptr;
+      c.u = k == F ? fd.lev[F].Lt : nullptr;
       conv[k >= klow ? 1 : 0].add(c, (long long)c.tpa * c.tpa * c.tz);
     }
     for (int k = 4; k <= F - 1; ++k) {
@@ -423,10 +425,12 @@ int build_schedule(fmm_plan* pl) {
         at[x].push_back(part_doubles);
         part_doubles += (long long)S * c.n * c.n * c.n * RS;
       }
-      // rebuild the site with the split
+      // rebuild the site with the split; split partial sums are FP64, so
+      // the finest level keeps its FP64 locals and the bottom reads those
       SegList sp;
       for (auto c : conv[x].v) {
         c.split = S;
+        c.u = nullptr;
         sp.add(c, (long long)c.tpa * c.tpa * c.tz * S);
       }
       conv[x] = sp;
@@ -447,6 +451,21 @@ int build_schedule(fmm_plan* pl) {
           red[x].add(r, cdiv((long long)c.n * c.n * c.n * RS, 256));
         }
     }
+  }
+  // a bottom reads its finest locals in the compute type exactly when the
+  // M2L into that level kept them so (an unsplit launch)
+  {
+    std::vector<void*> lt(pl->fld.size(), nullptr);
+    for (auto& cl : conv)
+      for (auto& c : cl.v)
+        if (c.u) lt[c.field] = c.u;
+    pl->lt_live = false;
+    for (auto& bs : bot)
+      for (auto& bl : bs)
+        for (auto& b : bl.v) {
+          b.u = lt[b.field];
+          pl->lt_live = pl->lt_live || b.u;
+        }
   }
   int rc;
   if ((rc = upload_segs(pl, pl->s_p2m, p2m))) return rc;
@@ -814,6 +833,14 @@ fmm_plan* create_plan(const std::vector<int>& ns, int p, const fmm_options& o, i
         if (hipMemset(lv.L, 0, lb) != hipSuccess) {
           fail(FMM_ERR_DEVICE, "hipMemset failed");
           return bail();
+        }
+        if (k == fd.F && pl->dl == 1 && fmm::bottom_low(pl, k)) {
+          const size_t tb = (size_t)(lv.ncell / 8) * fmm::loc_stride(p) * (pl->precision == 2 ? 2 : 4);
+          if (dev_alloc(pl, &lv.Lt, tb)) return bail();
+          if (hipMemset(lv.Lt, 0, tb) != hipSuccess) {
+            fail(FMM_ERR_DEVICE, "hipMemset failed");
+            return bail();
+          }
         }
       }
     }
@@ -1453,6 +1480,8 @@ int fmm_debug_expansions(fmm_plan* plan, int which, int level, double* out, size
     }
     return ok();
   }
+  if (level == plan->F && plan->lt_live)
+    return fail(FMM_ERR_UNSUPPORTED, "a low-precision bottom keeps the level-%d locals in its compute type only", level);
   hipError_t fe = fmm::finish_locals(plan, level, nullptr);
   if (fe == hipSuccess) fe = hipDeviceSynchronize();
   if (fe != hipSuccess) return fail(FMM_ERR_DEVICE, "completing locals failed: %s", hipGetErrorString(fe));

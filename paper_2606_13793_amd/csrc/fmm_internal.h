@@ -174,6 +174,10 @@ struct Level {
   // column order: L[P][m2l_col(q, b)] = Lhat of child 2P + q, term b;
   // row stride loc_stride(p)
   void* L = nullptr;
+  // the finest level's M2L part in the compute type of a low-precision
+  // bottom kernel (FMM-1), in the layout of L; null elsewhere.  Only the
+  // bottom kernel reads it, and it rounds its operands to that type anyway.
+  void* Lt = nullptr;
 };
 
 // one density field of a plan (a single-field plan has one)
@@ -214,6 +218,10 @@ struct Seg {
   const double* c;
   const double* d;
   void* t;  // mixed precision: the typed copy of a (convolutions, bottom) or of b (P2M, M2M), or null
+  // M2L into, and the bottom kernel reading, the finest level of a
+  // low-precision bottom (FMM-1): those locals in the compute type, which
+  // then replace b (M2L) and c (bottom); null otherwise
+  void* u;
 };
 // a segment table in device memory, plus its launch size
 struct SegTable {
@@ -309,6 +317,7 @@ struct fmm_plan {
   // launch schedule: segment tables of every launch site, built with the plan
   fmm::SegTable s_p2m;
   fmm::SegTable s_p2m2;             // FMM-1: level F - 1 formed from the unigrid (64 cells each)
+  bool lt_live = false;             // the M2L writes the finest locals in the compute type (Level::Lt)
   fmm::SegTable s_m2m[16];          // M2M into level k - 1 (index k)
   fmm::SegTable s_conv[2];          // forward M2L: [0] FP64 levels, [1] low-precision levels
   fmm::SegTable s_l2l[16];          // L2L into level k (index k)

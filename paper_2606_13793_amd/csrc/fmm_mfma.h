@@ -483,6 +483,8 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
     static_assert((TC + TP) * KPS <= HL::SIZE, "tail operands exceed the halo area");
     H* const own = halo;
     H* const par = halo + TC * KPS;
+    // the own locals in the compute type, written so by the M2L (or null: FP64)
+    const H* const Lt = static_cast<const H*>(sg.u);
     const int nP = nF >> 1, nPP = nP >> 1;
     const H* const w2 = Wl2p2 + (size_t)r * NLT * 2 * 64 * VPL + lane * VPL;
 #pragma unroll 1
@@ -492,12 +494,13 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
       for (int e = threadIdx.x; e < TC * KP; e += THREADS) {
         const int cell = e / KP, kk = e - cell * KP, bt = k0 + kk;
         const int g0 = tx0 + cell / (BY * BZ), g1 = ty0 + (cell / BZ) % BY, g2 = tz0 + cell % BZ;
-        double v = 0.0;
+        H v = H(0);
         if (bt < NL && g0 < nF && g1 < nF && g2 < nF) {
           const int q = ((g0 & 1) << 2) | ((g1 & 1) << 1) | (g2 & 1);
-          v = Lf[(((long long)(g0 >> 1) * nP + (g1 >> 1)) * nP + (g2 >> 1)) * RS + scol[q * (NLT * KT) + bt]];
+          const long long x = (((long long)(g0 >> 1) * nP + (g1 >> 1)) * nP + (g2 >> 1)) * RS + scol[q * (NLT * KT) + bt];
+          v = Lt ? Lt[x] : static_cast<H>(Lf[x]);
         }
-        own[cell * KPS + kk] = static_cast<H>(v);
+        own[cell * KPS + kk] = v;
       }
       // (no parent level above F = 3: zero operands, so the products need no branch)
       for (int e = threadIdx.x; e < TP * KP; e += THREADS) {
@@ -1133,6 +1136,8 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
     // the 16 lanes of a row write 128 contiguous bytes
     constexpr int RS = loc_stride(P);
     if (split > 1) dst += (long long)part * ns * ns * ns * RS;
+    // the finest level of a low-precision bottom: locals in the compute type
+    H* const ut = static_cast<H*>(sg.u);
     int escale[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -1147,10 +1152,16 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
         const int p0 = tx0 + 2 * (m / TPX) + r0, p1 = ty0 + 2 * (YPT * (m % TPX) + row / BZ2) + r1,
                   p2 = tz0 + 2 * (row % BZ2) + r2;
         if (p0 >= ns || p1 >= ns || p2 >= ns) continue;
-        double* o = dst + (((long long)p0 * ns + p1) * ns + p2) * RS + 16 * T0 + i;
+        const long long x = (((long long)p0 * ns + p1) * ns + p2) * RS + 16 * T0 + i;
+        if (ut) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
-          if (T0 + t < NTILES) o[16 * t] = ldexp((double)acc[m][t][v], escale[t]);
+          for (int t = 0; t < NT; ++t)
+            if (T0 + t < NTILES) ut[x + 16 * t] = static_cast<H>(ldexp((double)acc[m][t][v], escale[t]));
+        } else {
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            if (T0 + t < NTILES) dst[x + 16 * t] = ldexp((double)acc[m][t][v], escale[t]);
+        }
       }
   } else {
     if (split > 1) dst += (long long)part * ((NCO + 3) / 4) * ncellp * 4;

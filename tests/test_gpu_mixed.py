@@ -13,6 +13,7 @@ Levels at or below ``coarse_fp64_levels`` (default 4) keep FP64; small grids
 are run with that threshold lowered so the low-precision kernels carry every
 level.
 """
+import math
 import sys
 
 import numpy as np
@@ -101,10 +102,12 @@ def test_error_ordering(F, orc):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
-def test_mixed_full_size_sampled(F, orc, precision):
-    """128^3 p = 6 with the default policy (levels <= 4 in FP64), sampled cells."""
+@pytest.mark.parametrize("n", [128, 256])
+def test_mixed_full_size_sampled(F, orc, precision, n):
+    """128^3 and 256^3 (where the finest level's locals stay in the compute
+    type), p = 6, default policy (levels <= 4 in FP64), sampled cells."""
     import torch
-    n, p = 128, 6
+    p = 6
     _say(f"case {precision} sampled n={n} p={p}")
     rho_t = fi.plummer_density(n, fi.multi_plummer_params(32, 128), device="cuda").float()
     plan = F.Plan(n, p, precision)
@@ -122,3 +125,37 @@ def test_mixed_full_size_sampled(F, orc, precision):
     bp, bg = BARS[precision]
     assert ep <= bp and eg <= bg, (ep, eg)
     assert cp <= bp and cg <= bg, (cp, cg)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_finest_level_kept_in_compute_type(F, orc, precision):
+    """A low-precision bottom keeps the finest level's multipoles and M2L
+    locals in its compute type only, so their FP64 export is refused; the
+    level below, formed from the density in FP64, matches the oracle's
+    multipoles to 1e-12."""
+    import torch
+    # (below 256^3 the finest M2L launch is small enough to split its offset
+    # sums, whose FP64 partial sums keep the locals in FP64)
+    n, p = 256, 6
+    _say(f"case {precision} finest-level storage n={n} p={p}")
+    rho32 = fi.plummer_density(n, fi.multi_plummer_params(8, 47)).astype(np.float32)
+    plan = F.Plan(n, p, precision)
+    plan.solve(torch.as_tensor(rho32).cuda())
+    torch.cuda.synchronize()
+    lev = plan.finest_level
+    for which in ("M", "L"):
+        with pytest.raises(F.FmmError) as ei:
+            plan.expansions(which, lev)
+        assert ei.value.code == F.FMM_ERR_UNSUPPORTED
+    # the oracle's physical multipoles in the kernels' scaled form and order:
+    # Mhat[a] = (-1)^|a| M[a] / (a! h^|a| dx^3)
+    level = lev - 1
+    mi_o = [tuple(e) for e in orc.multi_index(p)]
+    mi_g = [tuple(e) for e in F.multi_index(p)]
+    col = [mi_o.index(e) for e in mi_g]
+    deg = np.array([sum(e) for e in mi_g])
+    fact = np.array([math.factorial(e[0]) * math.factorial(e[1]) * math.factorial(e[2]) for e in mi_g], float)
+    dx, h = 1.0 / n, 2.0 ** -level
+    want = orc.expansions(rho32.astype(np.float64), p, "M", level)[:, col] * ((-1.0) ** deg) / (fact * h ** deg * dx ** 3)
+    got = plan.expansions("M", level)
+    assert rel(got, want) < 1e-12, rel(got, want)
