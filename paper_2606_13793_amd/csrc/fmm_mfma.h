@@ -265,6 +265,27 @@ __device__ constexpr int tile_part(int m) {
 // row's cell and the columns are the 8 unigrid children q of that child.
 // The B tables then hold 8 groups, and the near field is the 12^3 block of
 // unigrid cells of the 27 level-F cells around the row's cell.
+// put(e, val(e)) for e in [0, count) over the block's threads, FB values
+// loaded per thread before any is put, so each thread waits for memory once
+// per FB elements instead of once per element.
+template <typename H, int THREADS, int FB, typename Val, typename Put>
+__device__ __forceinline__ void block_fill(int count, Val&& val, Put&& put) {
+#pragma unroll 1
+  for (int j0 = threadIdx.x; j0 < count; j0 += FB * THREADS) {
+    H v[FB];
+#pragma unroll
+    for (int u = 0; u < FB; ++u) {
+      const int e = j0 + u * THREADS;
+      v[u] = e < count ? val(e) : H(0);
+    }
+#pragma unroll
+    for (int u = 0; u < FB; ++u) {
+      const int e = j0 + u * THREADS;
+      if (e < count) put(e, v[u]);
+    }
+  }
+}
+
 // Calls f(std::integral_constant<int, k>) for k = I, I + 1, ..., N - 1.
 template <int N, int I = 0, typename F>
 __device__ __forceinline__ void static_for(F&& f) {
@@ -471,6 +492,8 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
   // K step by K step over all of the wave's row tiles, so each B fragment is
   // loaded once per step.
   constexpr int TC = BX * BY * BZ, TP = TC / 8;  // the tile's level-F cells, and their parents
+  // loads in flight per thread while filling LDS (as the registers allow)
+  constexpr int FILLB = M::IDX == 0 ? 2 : (M::IDX == 1 ? 8 : 4);
   // tile-local index of the level-F cell of the lane's row in tile m, and of its parent
   auto lcell = [&](int m) { return ((2 * (m / TPX) + r0) * BY + 2 * (YPT * (m % TPX) + gyo) + r1) * BZ + 2 * gz + r2; };
   auto lpar = [&](int m) { return ((m / TPX) * (BY / 2) + YPT * (m % TPX) + gyo) * (BZ / 2) + gz; };
@@ -480,6 +503,7 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
     // cells fit the halo area; row stride KPS keeps BF16 rows 16-byte aligned
     // and spreads the rows of a fragment over the LDS banks
     constexpr int CPP = M::IDX == 2 ? 1 : 3, KP = CPP * KT, KPS = M::IDX == 2 ? 40 : 13;
+
     static_assert((TC + TP) * KPS <= HL::SIZE, "tail operands exceed the halo area");
     H* const own = halo;
     H* const par = halo + TC * KPS;
@@ -491,28 +515,90 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
     for (int c0 = 0; c0 < NLT; c0 += CPP) {
       __syncthreads();  // the area's previous contents fully consumed
       const int k0 = c0 * KT;
-      for (int e = threadIdx.x; e < TC * KP; e += THREADS) {
-        const int cell = e / KP, kk = e - cell * KP, bt = k0 + kk;
-        const int g0 = tx0 + cell / (BY * BZ), g1 = ty0 + (cell / BZ) % BY, g2 = tz0 + cell % BZ;
-        H v = H(0);
-        if (bt < NL && g0 < nF && g1 < nF && g2 < nF) {
-          const int q = ((g0 & 1) << 2) | ((g1 & 1) << 1) | (g2 & 1);
-          const long long x = (((long long)(g0 >> 1) * nP + (g1 >> 1)) * nP + (g2 >> 1)) * RS + scol[q * (NLT * KT) + bt];
-          v = Lt ? Lt[x] : static_cast<H>(Lf[x]);
+      // BF16: thread t fills term k0 + t % KP of every CPR-th cell from t / KP
+      // (the lanes of a wave read consecutive columns of a row; the term's
+      // column in the M2L layout is cb + q nd for a cell that is child q of
+      // its parent), FILLB loads in flight.  FP64 and FP32, whose accumulators
+      // leave fewer registers, fill one element per thread and step.
+      if constexpr (M::IDX == 2) {
+        constexpr int CPR = THREADS / KP;
+        const int kk = threadIdx.x % KP, cf = threadIdx.x / KP, bt = k0 + kk;
+        const bool tok = cf < CPR && bt < NL;
+        const int cb = tok ? scol[bt] : 0, nd = tok ? scol[NLT * KT + bt] - cb : 0;
+        const auto gLf = gmem(Lf);
+        const auto gLt = gmem(Lt);
+        const auto gLp = gmem(Lpar);
+#pragma unroll 1
+        for (int j = 0; j < (TC + CPR - 1) / CPR; j += FILLB) {
+          H v[FILLB];
+#pragma unroll
+          for (int u = 0; u < FILLB; ++u) {
+            const int cell = cf + (j + u) * CPR;
+            const int g0 = tx0 + cell / (BY * BZ), g1 = ty0 + (cell / BZ) % BY, g2 = tz0 + cell % BZ;
+            v[u] = H(0);
+            if (tok && cell < TC && g0 < nF && g1 < nF && g2 < nF) {
+              const int q = ((g0 & 1) << 2) | ((g1 & 1) << 1) | (g2 & 1);
+              const long long x = (((long long)(g0 >> 1) * nP + (g1 >> 1)) * nP + (g2 >> 1)) * RS + cb + q * nd;
+              v[u] = Lt ? gLt[x] : static_cast<H>(gLf[x]);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < FILLB; ++u) {
+            const int cell = cf + (j + u) * CPR;
+            if (cf < CPR && cell < TC) own[cell * KPS + kk] = v[u];
+          }
         }
-        own[cell * KPS + kk] = v;
-      }
-      // (no parent level above F = 3: zero operands, so the products need no branch)
-      for (int e = threadIdx.x; e < TP * KP; e += THREADS) {
-        const int pc = e / KP, kk = e - pc * KP, bt = k0 + kk;
-        const int g0 = (tx0 >> 1) + pc / ((BY / 2) * (BZ / 2)), g1 = (ty0 >> 1) + (pc / (BZ / 2)) % (BY / 2),
-                  g2 = (tz0 >> 1) + pc % (BZ / 2);
-        double v = 0.0;
-        if (Lpar && bt < NL && g0 < nP && g1 < nP && g2 < nP) {
-          const int q = ((g0 & 1) << 2) | ((g1 & 1) << 1) | (g2 & 1);
-          v = Lpar[(((long long)(g0 >> 1) * nPP + (g1 >> 1)) * nPP + (g2 >> 1)) * RS + scol[q * (NLT * KT) + bt]];
+        // (no parent level above F = 3: zero operands, so the products need no branch)
+#pragma unroll 1
+        for (int j = 0; j < (TP + CPR - 1) / CPR; j += FILLB) {
+          H v[FILLB];
+#pragma unroll
+          for (int u = 0; u < FILLB; ++u) {
+            const int pc = cf + (j + u) * CPR;
+            const int g0 = (tx0 >> 1) + pc / ((BY / 2) * (BZ / 2)), g1 = (ty0 >> 1) + (pc / (BZ / 2)) % (BY / 2),
+                      g2 = (tz0 >> 1) + pc % (BZ / 2);
+            v[u] = H(0);
+            if (Lpar && tok && pc < TP && g0 < nP && g1 < nP && g2 < nP) {
+              const int q = ((g0 & 1) << 2) | ((g1 & 1) << 1) | (g2 & 1);
+              v[u] = static_cast<H>(gLp[(((long long)(g0 >> 1) * nPP + (g1 >> 1)) * nPP + (g2 >> 1)) * RS + cb + q * nd]);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < FILLB; ++u) {
+            const int pc = cf + (j + u) * CPR;
+            if (cf < CPR && pc < TP) par[pc * KPS + kk] = v[u];
+          }
         }
-        par[pc * KPS + kk] = static_cast<H>(v);
+      } else {
+        const auto gLf = gmem(Lf);
+        const auto gLt = gmem(Lt);
+        const auto gLp = gmem(Lpar);
+        for (int e = threadIdx.x; e < TC * KP; e += THREADS) {
+          const int cell = e / KP, kk = e - cell * KP, bt = k0 + kk;
+          const int g0 = tx0 + cell / (BY * BZ), g1 = ty0 + (cell / BZ) % BY, g2 = tz0 + cell % BZ;
+          H v = H(0);
+          if (bt < NL && g0 < nF && g1 < nF && g2 < nF) {
+            const int q = ((g0 & 1) << 2) | ((g1 & 1) << 1) | (g2 & 1);
+            const long long x = (((long long)(g0 >> 1) * nP + (g1 >> 1)) * nP + (g2 >> 1)) * RS + scol[q * (NLT * KT) + bt];
+            if constexpr (M::IDX == 0)
+              v = gLf[x];
+            else
+              v = Lt ? gLt[x] : static_cast<H>(gLf[x]);
+          }
+          own[cell * KPS + kk] = v;
+        }
+        // (no parent level above F = 3: zero operands, so the products need no branch)
+        for (int e = threadIdx.x; e < TP * KP; e += THREADS) {
+          const int pc = e / KP, kk = e - pc * KP, bt = k0 + kk;
+          const int g0 = (tx0 >> 1) + pc / ((BY / 2) * (BZ / 2)), g1 = (ty0 >> 1) + (pc / (BZ / 2)) % (BY / 2),
+                    g2 = (tz0 >> 1) + pc % (BZ / 2);
+          double v = 0.0;
+          if (Lpar && bt < NL && g0 < nP && g1 < nP && g2 < nP) {
+            const int q = ((g0 & 1) << 2) | ((g1 & 1) << 1) | (g2 & 1);
+            v = gLp[(((long long)(g0 >> 1) * nPP + (g1 >> 1)) * nPP + (g2 >> 1)) * RS + scol[q * (NLT * KT) + bt]];
+          }
+          par[pc * KPS + kk] = static_cast<H>(v);
+        }
       }
       __syncthreads();
 #pragma unroll 1
@@ -548,12 +634,16 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
     H* const ub = halo;
     __syncthreads();
     const int x0 = 2 * tx0 - 2, y0 = 2 * ty0 - 2, z0 = 2 * tz0 - 2;
-    for (int e = threadIdx.x; e < UX * UY * UZ; e += THREADS) {
-      const int uz = e % UZ, uy = (e / UZ) % UY, ux = e / (UZ * UY);
-      const int w0 = x0 + ux, w1 = y0 + uy, w2 = z0 + uz;
-      const bool in = uz < UZ - 2 && w0 >= 0 && w1 >= 0 && w2 >= 0 && w0 < n && w1 < n && w2 < n;
-      ub[e] = in ? static_cast<H>(rho[((long long)w0 * n + w1) * n + w2]) : H(0);
-    }
+    const auto grho = gmem(rho);
+    block_fill<H, THREADS, FILLB>(
+        UX * UY * UZ,
+        [&](int e) {
+          const int uz = e % UZ, uy = (e / UZ) % UY, ux = e / (UZ * UY);
+          const int w0 = x0 + ux, w1 = y0 + uy, w2 = z0 + uz;
+          const bool in = uz < UZ - 2 && w0 >= 0 && w1 >= 0 && w2 >= 0 && w0 < n && w1 < n && w2 < n;
+          return in ? static_cast<H>(grho[((long long)w0 * n + w1) * n + w2]) : H(0);
+        },
+        [&](int e, H v) { ub[e] = v; });
     __syncthreads();
     // the lane's row: ub offset of its 6^3 block's corner, per row tile
     auto ubase = [&](int m) {
