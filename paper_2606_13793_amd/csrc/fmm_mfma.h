@@ -334,8 +334,15 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
   // column of local term bt of child q in the locals' M2L layout, for the
   // tail's L2P reads (-1 past the last term)
   __shared__ int scol[8 * NLT * KT];
+  // blocks walk the (order-independent) offset sum from different starting
+  // points: the lists are stored rotated (one offset per MFMA; the null entry
+  // past the end), or the pairs are taken from a rotated index (two)
+  const int rot = (int)((blockIdx.x * 37u) % (OPM == 1 ? NLIST : NGRP));
   if constexpr (OPM == 1)
-    for (int t = threadIdx.x; t < 8 * NLIST_PAD; t += THREADS) slist[t] = dlists[t];
+    for (int t = threadIdx.x; t < 8 * NLIST_PAD; t += THREADS) {
+      const int cls = t / NLIST_PAD, j = t - cls * NLIST_PAD, jr = j + rot;
+      slist[t] = dlists[cls * NLIST_PAD + (j < NLIST ? (jr < NLIST ? jr : jr - NLIST) : NLIST)];
+    }
   else
     build_pair_table<HL>(spair, dlists, NGRP, 2 * EL * VPL, THREADS);
   for (int t = threadIdx.x; t < 8 * NLT * KT; t += THREADS) {
@@ -390,14 +397,7 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
   for (int m = 0; m < MTW; ++m) acc[m][0] = acc[m][1] = Acc{0, 0, 0, 0};
   const int* dl = slist + r * NLIST_PAD;  // visible after the first chunk's barrier
   const int2* dp = spair + r * NGRP * 2 + lr.sel;
-  // blocks walk the (order-independent) offset sum from different starting
-  // points: rotated entries (one offset per MFMA) or rotated pairs (two)
-  const int rot = (int)((blockIdx.x * 37u) % (OPM == 1 ? NLIST : NGRP));
-  auto entry = [&](int pos) {
-    if (pos >= NLIST) return dl[NLIST];
-    pos += rot;
-    return dl[pos < NLIST ? pos : pos - NLIST];
-  };
+  auto entry = [&](int pos) { return dl[pos]; };  // pos < NLIST_PAD
   TypedStage<CT, BZ, THREADS> ts;
   if constexpr (TYPED) ts.plan(nFp, tx0, ty0, tz0);
 
@@ -464,12 +464,14 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
       for (int u = 0; u < 3; ++u) {
         const int jj = j + u, cur = u, nx = (u + 1) % 3, nn = (u + 2) % 3;
         if (jj < NGRP) {
-          if (jj + 2 < NGRP) {
-            es[nn] = group(jj + 2);
-            bs[nn][0] = bload(es[nn], 0);
-            bs[nn][1] = bload(es[nn], 1);
-          }
-          if (jj + 1 < NGRP) aload(es[nx], as[nx]);
+          // the next groups' loads are issued unconditionally (past the end
+          // they repeat the last group, unused): with a branch around them
+          // the waits for this group's operands would depend on the path, and
+          // the compiler would then wait for every load in flight
+          es[nn] = group(jj + 2 < NGRP ? jj + 2 : NGRP - 1);
+          bs[nn][0] = bload(es[nn], 0);
+          bs[nn][1] = bload(es[nn], 1);
+          aload(es[nx], as[nx]);
 #pragma unroll
           for (int m = 0; m < MTW; ++m) {
             acc[m][0] = M::op(as[cur][m], bs[cur][0], acc[m][0]);
@@ -1054,10 +1056,6 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   // lanes' operand offsets of each offset pair (two per MFMA)
   __shared__ int slist[OPM == 1 ? 8 * NLIST_PAD : 1];
   __shared__ int2 spair[OPM == 2 ? 8 * NGRP * 2 : 1];
-  if constexpr (OPM == 1)
-    for (int t = threadIdx.x; t < 8 * NLIST_PAD; t += M2L_THREADS) slist[t] = dlists[t];
-  else
-    build_pair_table<HL>(spair, dlists, NGRP, EL * VPL, M2L_THREADS);
   const int grp = (int)blockIdx.x / T;
   const int T0 = grp * NT;
   const int lbk = (int)blockIdx.x - grp * T;
@@ -1065,6 +1063,18 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   const int split = sg.split;
   const int tbs = lbk - sg.first_block;
   const int tb = tbs / split, part = tbs - tb * split;
+  // the rotation of the offset order (of entries, or of pairs) must be the
+  // same for every part of a split tile (the parts take consecutive slices of
+  // one ordering); the entry lists are stored rotated, the null entry past
+  // the end
+  const int rot = (int)(((unsigned)(sg.first_block + tb * split) * 37u) % (OPM == 1 ? NOFF : NGRP));
+  if constexpr (OPM == 1)
+    for (int t = threadIdx.x; t < 8 * NLIST_PAD; t += M2L_THREADS) {
+      const int cls = t / NLIST_PAD, j = t - cls * NLIST_PAD, jr = j + rot;
+      slist[t] = dlists[cls * NLIST_PAD + (j < NOFF ? (jr < NOFF ? jr : jr - NOFF) : NOFF)];
+    }
+  else
+    build_pair_table<HL>(spair, dlists, NGRP, EL * VPL, M2L_THREADS);
   const int tpa = sg.tpa;
   const int ns = sg.n, nsp = ns + 6;
   const double* __restrict__ src = sg.a;
@@ -1099,15 +1109,7 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
     for (int t = 0; t < NT; ++t) acc[m][t] = Acc{0, 0, 0, 0};
   const int* dl = slist + r * NLIST_PAD;  // visible after the first chunk's barrier
   const int2* dp = spair + r * NGRP * 2 + lr.sel;
-  // the rotation of the offset order (of entries, or of pairs) must be the
-  // same for every part of a split tile (the parts take consecutive slices of
-  // one ordering)
-  const int rot = (int)(((unsigned)(sg.first_block + tb * split) * 37u) % (OPM == 1 ? NOFF : NGRP));
-  auto entry = [&](int pos) {
-    if (pos >= NOFF) return dl[NOFF];
-    pos += rot;
-    return dl[pos < NOFF ? pos : pos - NOFF];
-  };
+  auto entry = [&](int pos) { return dl[pos]; };  // pos < NLIST_PAD
   // Packed groups: M2L column tiles of degree p need the single multipole
   // term a = 0, so one K chunk would carry one useful term in KC.  With one
   // offset per MFMA (FP64, FP32) such a group instead packs four offsets into
@@ -1177,12 +1179,13 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
       for (int u = 0; u < 3; ++u) {
         const int jj = j + u, cur = u, nx = (u + 1) % 3, nn = (u + 2) % 3;
         if (jj < jb) {
-          if (jj + 2 < jb) {
-            es[nn] = group(jj + 2);
+          // unconditional loads of the next groups (past the end they repeat
+          // the last one, unused), so the waits below count a fixed number of
+          // loads in flight instead of draining them all
+          es[nn] = group(jj + 2 < jb ? jj + 2 : jb - 1);
 #pragma unroll
-            for (int t = 0; t < NA; ++t) bs[nn][t] = bload(es[nn], t);
-          }
-          if (jj + 1 < jb) aload(es[nx], as[nx]);
+          for (int t = 0; t < NA; ++t) bs[nn][t] = bload(es[nn], t);
+          aload(es[nx], as[nx]);
 #pragma unroll
           for (int m = 0; m < CMT; ++m)
 #pragma unroll
