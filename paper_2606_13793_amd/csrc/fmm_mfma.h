@@ -235,6 +235,8 @@ struct TypedStage {
 // table holds the halo element offset of the offset's operand cells
 // (relative to a lane's base address) and the element offset of its B-table
 // slot.  Built once per block; a lane then reads its half with one LDS load.
+// Built with one pair more than the list holds: the last is the null pair
+// (both entries the null offset, zero B rows).
 template <typename HL>
 __device__ __forceinline__ void build_pair_table(int2* __restrict__ tab, const int* __restrict__ dlists, int npair,
                                                  int slot_elems, int nthr) {
@@ -330,7 +332,7 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
   // the interaction lists of the 8 parity classes (one offset per MFMA), or
   // the lanes' operand offsets of each offset pair (two per MFMA)
   __shared__ int slist[OPM == 1 ? 8 * NLIST_PAD : 1];
-  __shared__ int2 spair[OPM == 2 ? 8 * NGRP * 2 : 1];
+  __shared__ int2 spair[OPM == 2 ? 8 * (NGRP + 1) * 2 : 1];
   // column of local term bt of child q in the locals' M2L layout, for the
   // tail's L2P reads (-1 past the last term)
   __shared__ int scol[8 * NLT * KT];
@@ -344,7 +346,7 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
       slist[t] = dlists[cls * NLIST_PAD + (j < NLIST ? (jr < NLIST ? jr : jr - NLIST) : NLIST)];
     }
   else
-    build_pair_table<HL>(spair, dlists, NGRP, 2 * EL * VPL, THREADS);
+    build_pair_table<HL>(spair, dlists, NGRP + 1, 2 * EL * VPL, THREADS);
   for (int t = threadIdx.x; t < 8 * NLT * KT; t += THREADS) {
     const int q = t / (NLT * KT), bt = t - q * (NLT * KT);
     const int ex = c_mi_exp[bt < NL ? bt : 0];
@@ -396,8 +398,16 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
 #pragma unroll
   for (int m = 0; m < MTW; ++m) acc[m][0] = acc[m][1] = Acc{0, 0, 0, 0};
   const int* dl = slist + r * NLIST_PAD;  // visible after the first chunk's barrier
-  const int2* dp = spair + r * NGRP * 2 + lr.sel;
+  const int2* dp = spair + r * (NGRP + 1) * 2 + lr.sel;
   auto entry = [&](int pos) { return dl[pos]; };  // pos < NLIST_PAD
+  // the same entry as a scalar load from the unrotated global list (pos
+  // wave-uniform): its value lands in a scalar register, so it ties up no
+  // vector register that a pending operand load could also write
+  const int* __restrict__ dg = dlists + r * NLIST_PAD;
+  auto entry_s = [&](int pos) {
+    const int jr = pos + rot;
+    return dg[pos < NLIST ? (jr < NLIST ? jr : jr - NLIST) : NLIST];
+  };
   TypedStage<CT, BZ, THREADS> ts;
   if constexpr (TYPED) ts.plan(nFp, tx0, ty0, tz0);
 
@@ -437,10 +447,12 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
     auto group = [&](int j) {
       EntryGroup g;
       if constexpr (OPM == 1) {
-        g.e = __builtin_amdgcn_readfirstlane(entry(j));
+        // FP32 keeps the entry in LDS (measured: its loop runs faster so,
+        // and without the scheduling fences below)
+        g.e = __builtin_amdgcn_readfirstlane(M::IDX == 1 ? entry(j) : entry_s(j));
       } else {
-        int jr = j + rot;  // wave-uniform
-        jr = jr < NGRP ? jr : jr - NGRP;
+        const int j0 = j + rot;  // wave-uniform; past the groups, the null pair
+        const int jr = j < NGRP ? (j0 < NGRP ? j0 : j0 - NGRP) : NGRP;
         const int2 v = dp[2 * jr];
         g.aoff = v.x;
         g.boff = v.y;
@@ -458,25 +470,33 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
     aload(es[0], as[0]);
     // (the body is unrolled by three by hand; unrolling the loop itself would
     // hoist every group's table address out of the chunk loop)
+    // whole unrolled iterations, the last padded with null groups (zero B
+    // rows), so there is no exit inside an iteration and every load is
+    // unconditional: each group's products then wait for a fixed number of
+    // loads in flight instead of draining them all
 #pragma unroll 1
     for (int j = 0; j < NGRP; j += 3) {
 #pragma unroll
       for (int u = 0; u < 3; ++u) {
         const int jj = j + u, cur = u, nx = (u + 1) % 3, nn = (u + 2) % 3;
-        if (jj < NGRP) {
-          // the next groups' loads are issued unconditionally (past the end
-          // they repeat the last group, unused): with a branch around them
-          // the waits for this group's operands would depend on the path, and
-          // the compiler would then wait for every load in flight
-          es[nn] = group(jj + 2 < NGRP ? jj + 2 : NGRP - 1);
+        // (FP32, measured faster so, keeps a bounds test and the last real
+        // group as the prefetch past the end; for the others both are
+        // compile-time true)
+        constexpr bool F32 = M::IDX == 1;
+        if (!F32 || jj < NGRP) {
+          es[nn] = group(!F32 || jj + 2 < NGRP ? jj + 2 : NGRP - 1);
           bs[nn][0] = bload(es[nn], 0);
           bs[nn][1] = bload(es[nn], 1);
           aload(es[nx], as[nx]);
+          // (keep the loads ahead of the products: the scheduler would move
+          // them next to their uses and expose their latency)
+          if constexpr (!F32) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int m = 0; m < MTW; ++m) {
             acc[m][0] = M::op(as[cur][m], bs[cur][0], acc[m][0]);
             acc[m][1] = M::op(as[cur][m], bs[cur][1], acc[m][1]);
           }
+          if constexpr (!F32) __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
@@ -1055,7 +1075,7 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   // the offset lists of the 8 parity classes (one offset per MFMA), or the
   // lanes' operand offsets of each offset pair (two per MFMA)
   __shared__ int slist[OPM == 1 ? 8 * NLIST_PAD : 1];
-  __shared__ int2 spair[OPM == 2 ? 8 * NGRP * 2 : 1];
+  __shared__ int2 spair[OPM == 2 ? 8 * (NGRP + 1) * 2 : 1];
   const int grp = (int)blockIdx.x / T;
   const int T0 = grp * NT;
   const int lbk = (int)blockIdx.x - grp * T;
@@ -1074,7 +1094,7 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
       slist[t] = dlists[cls * NLIST_PAD + (j < NOFF ? (jr < NOFF ? jr : jr - NOFF) : NOFF)];
     }
   else
-    build_pair_table<HL>(spair, dlists, NGRP, EL * VPL, M2L_THREADS);
+    build_pair_table<HL>(spair, dlists, NGRP + 1, EL * VPL, M2L_THREADS);
   const int tpa = sg.tpa;
   const int ns = sg.n, nsp = ns + 6;
   const double* __restrict__ src = sg.a;
@@ -1108,8 +1128,16 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[m][t] = Acc{0, 0, 0, 0};
   const int* dl = slist + r * NLIST_PAD;  // visible after the first chunk's barrier
-  const int2* dp = spair + r * NGRP * 2 + lr.sel;
+  const int2* dp = spair + r * (NGRP + 1) * 2 + lr.sel;
   auto entry = [&](int pos) { return dl[pos]; };  // pos < NLIST_PAD
+  // the same entry as a scalar load from the unrotated global list (pos
+  // wave-uniform): its value lands in a scalar register, so it ties up no
+  // vector register that a pending operand load could also write
+  const int* __restrict__ dg = dlists + r * NLIST_PAD;
+  auto entry_s = [&](int pos) {
+    const int jr = pos + rot;
+    return dg[pos < NOFF ? (jr < NOFF ? jr : jr - NOFF) : NOFF];
+  };
   // Packed groups: M2L column tiles of degree p need the single multipole
   // term a = 0, so one K chunk would carry one useful term in KC.  With one
   // offset per MFMA (FP64, FP32) such a group instead packs four offsets into
@@ -1139,12 +1167,12 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
     auto group = [&](int j) {
       EntryGroup g;
       if constexpr (PK) {
-        g.e = entry(4 * j + kq);
+        g.e = entry(j < jb ? 4 * j + kq : NLIST_PAD - 1);
       } else if constexpr (OPM == 1) {
-        g.e = __builtin_amdgcn_readfirstlane(entry(j));
+        g.e = __builtin_amdgcn_readfirstlane(entry_s(j < jb ? j : NOFF));
       } else {
-        int jr = j + rot;  // wave-uniform
-        jr = jr < NGRP ? jr : jr - NGRP;
+        const int j0 = j + rot;  // wave-uniform; past the part's groups, the null pair
+        const int jr = j < jb ? (j0 < NGRP ? j0 : j0 - NGRP) : NGRP;
         const int2 v = dp[2 * jr];
         g.aoff = v.x;
         g.boff = v.y;
@@ -1173,24 +1201,28 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
       bs[1][t] = bload(es[1], t);
     }
     aload(es[0], as[0]);
+    // The groups run in whole unrolled iterations, the last padded with null
+    // groups (zero B rows): with no exit inside an iteration and every load
+    // unconditional, each group's products wait for a fixed number of loads
+    // in flight instead of draining them all.
+    const int jp = ja + (jb - ja + 2) / 3 * 3;
 #pragma unroll 1
-    for (int j = ja; j < jb; j += 3) {
+    for (int j = ja; j < jp; j += 3) {
 #pragma unroll
       for (int u = 0; u < 3; ++u) {
         const int jj = j + u, cur = u, nx = (u + 1) % 3, nn = (u + 2) % 3;
-        if (jj < jb) {
-          // unconditional loads of the next groups (past the end they repeat
-          // the last one, unused), so the waits below count a fixed number of
-          // loads in flight instead of draining them all
-          es[nn] = group(jj + 2 < jb ? jj + 2 : jb - 1);
+        es[nn] = group(jj + 2);
 #pragma unroll
-          for (int t = 0; t < NA; ++t) bs[nn][t] = bload(es[nn], t);
-          aload(es[nx], as[nx]);
+        for (int t = 0; t < NA; ++t) bs[nn][t] = bload(es[nn], t);
+        aload(es[nx], as[nx]);
+        // (keep the loads ahead of the products: the scheduler would move
+        // them next to their uses and expose their latency)
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int m = 0; m < CMT; ++m)
+        for (int m = 0; m < CMT; ++m)
 #pragma unroll
-            for (int t = 0; t < NA; ++t) acc[m][t] = M::op(as[cur][m], bs[cur][t], acc[m][t]);
-        }
+          for (int t = 0; t < NA; ++t) acc[m][t] = M::op(as[cur][m], bs[cur][t], acc[m][t]);
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
   };
