@@ -515,7 +515,7 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
   // loaded once per step.
   constexpr int TC = BX * BY * BZ, TP = TC / 8;  // the tile's level-F cells, and their parents
   // loads in flight per thread while filling LDS (as the registers allow)
-  constexpr int FILLB = M::IDX == 0 ? 2 : (M::IDX == 1 ? 8 : 4);
+  constexpr int FILLB = M::IDX == 0 ? 2 : 4;
   // tile-local index of the level-F cell of the lane's row in tile m, and of its parent
   auto lcell = [&](int m) { return ((2 * (m / TPX) + r0) * BY + 2 * (YPT * (m % TPX) + gyo) + r1) * BZ + 2 * gz + r2; };
   auto lpar = [&](int m) { return ((m / TPX) * (BY / 2) + YPT * (m % TPX) + gyo) * (BZ / 2) + gz; };
@@ -537,12 +537,12 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
     for (int c0 = 0; c0 < NLT; c0 += CPP) {
       __syncthreads();  // the area's previous contents fully consumed
       const int k0 = c0 * KT;
-      // BF16: thread t fills term k0 + t % KP of every CPR-th cell from t / KP
-      // (the lanes of a wave read consecutive columns of a row; the term's
-      // column in the M2L layout is cb + q nd for a cell that is child q of
-      // its parent), FILLB loads in flight.  FP64 and FP32, whose accumulators
-      // leave fewer registers, fill one element per thread and step.
-      if constexpr (M::IDX == 2) {
+      // BF16, FP32: thread t fills term k0 + t % KP of every CPR-th cell from
+      // t / KP (the lanes of a wave read consecutive columns of a row; the
+      // term's column in the M2L layout is cb + q nd for a cell that is child
+      // q of its parent), FILLB loads in flight.  FP64, whose accumulators
+      // leave fewer registers, fills one element per thread and step.
+      if constexpr (M::IDX != 0) {
         constexpr int CPR = THREADS / KP;
         const int kk = threadIdx.x % KP, cf = threadIdx.x / KP, bt = k0 + kk;
         const bool tok = cf < CPR && bt < NL;
@@ -671,11 +671,23 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
     auto ubase = [&](int m) {
       return (2 * (2 * (m / TPX) + r0) * UY + 2 * (2 * (YPT * (m % TPX) + gyo) + r1)) * UZ + 2 * (2 * gz + r2);
     };
+    AF bn[2], bx[2];
+    if constexpr (M::IDX != 0) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t) bn[t] = *reinterpret_cast<const AF*>(Wp2p + ((size_t)t * 64 + lane) * VPL);
+    }
 #pragma unroll 1
     for (int c = 0; c < NPT; ++c) {
-      AF bn[2];
+      // B of step c; FP32 and BF16 also load step c + 1's ahead (FP64 has no
+      // registers for it)
+      if constexpr (M::IDX == 0) {
 #pragma unroll
-      for (int t = 0; t < 2; ++t) bn[t] = *reinterpret_cast<const AF*>(Wp2p + ((size_t)(c * 2 + t) * 64 + lane) * VPL);
+        for (int t = 0; t < 2; ++t) bn[t] = *reinterpret_cast<const AF*>(Wp2p + ((size_t)(c * 2 + t) * 64 + lane) * VPL);
+      } else {
+        const int cn = c + 1 < NPT ? c + 1 : c;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) bx[t] = *reinterpret_cast<const AF*>(Wp2p + ((size_t)(cn * 2 + t) * 64 + lane) * VPL);
+      }
       const int k = KT * c + VPL * kq, run = k >> 3;
       const int koff = (run / 6) * (UY * UZ) + (run % 6) * UZ + (k & 7);
       static_for<MTW>([&](auto mi) {
@@ -693,6 +705,10 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
         acc[mw][0] = M::op(a, bn[0], acc[mw][0]);
         acc[mw][1] = M::op(a, bn[1], acc[mw][1]);
       });
+      if constexpr (M::IDX != 0) {
+        bn[0] = bx[0];
+        bn[1] = bx[1];
+      }
     }
   }
   } else {
