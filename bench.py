@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 
 
 PROFILE = os.path.join(ROOT, "profiles", "k_bottom_256cubed_p6_fp64.md")
-KERNEL_SOURCES = ["fmm_impl.h", "fmm_mfma.h", "fmm_internal.h"]
+KERNEL_SOURCES = ["fmm_impl.h", "fmm_mfma.h", "fmm_internal.h", "fmm_types.h"]
 
 
 def profiled_traffic(n: int, p: int, prec: str, delta_l: int = 1):
@@ -551,6 +551,9 @@ def main():
 
     flops = costs.solve_flops(n, p, delta_l=dl)
     stage_flops = {"p2m": flops["p2m"], "m2m": flops["m2m"], "m2l": flops["m2l"], "bottom": flops["bottom"]}
+    if dl == 1:  # level F - 1 is formed by the P2M stage, from the density
+        stage_flops["p2m"] += flops["m2m_top"]
+        stage_flops["m2m"] -= flops["m2m_top"]
     stages = {}
     for name, (ms, launches) in prof.items():
         if launches or ms:

@@ -72,6 +72,9 @@ def solve_flops(n: int, p: int, nmax: int | None = None, delta_l: int = 1) -> di
     # per fused kernel stage of the HIP solve
     out["m2l_l2l"] = out["m2l"] + out["l2l"]
     out["bottom"] = out["m2p"] + out["near_l2p"]
+    # the M2M into level F - 1, which FMM-1 solves form in the P2M stage
+    # straight from the density (the same multipoles)
+    out["m2m_top"] = 2 * m2m_terms * 8 ** F if F >= 3 else 0
     return out
 
 

@@ -316,7 +316,40 @@ int upload_segs(fmm_plan* pl, fmm::SegTable& st, const SegList& l) {
 
 long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
 
+// Tiles of M2L launch site x (0: FP64 target levels, 1: low-precision ones)
+// over every field, 8-deep when all its row grids are at most 8 cells deep,
+// as build_schedule lays them out; a site under 128 tiles splits each tile's
+// offset sum over several blocks.
+long long conv_site_tiles(const fmm_plan* pl, int x) {
+  const int klow = fmm::m2l_low_from(pl);
+  bool any = false, shallow = true;
+  for (const auto& fd : pl->fld)
+    for (int k = 3; k <= fd.F; ++k)
+      if ((k >= klow ? 1 : 0) == x) {
+        any = true;
+        shallow = shallow && (1 << (k - 1)) <= 8;
+      }
+  long long T = 0;
+  for (const auto& fd : pl->fld)
+    for (int k = 3; k <= fd.F; ++k)
+      if ((k >= klow ? 1 : 0) == x) {
+        const long long n = 1LL << (k - 1);
+        T += cdiv(n, kConvTile) * cdiv(n, kConvTile) * cdiv(n, shallow ? 8 : kConvTileZ);
+      }
+  return any ? T : 0;
+}
+
 }  // namespace
+
+namespace fmm {
+// Whether the finest locals of field fd live only in the compute type
+// (Level::Lt): an FMM-1 field whose bottom kernel runs in FP32/BF16, when the
+// low-precision M2L launch does not split its offset sums (split partial sums
+// are FP64).  Then no FP64 locals are allocated for that level.
+bool finest_locals_typed(const fmm_plan* pl, const Field& fd) {
+  return pl->dl == 1 && fd.F >= 3 && bottom_low(pl, fd.F) && conv_site_tiles(pl, 1) >= 128;
+}
+}  // namespace fmm
 
 namespace fmm {
 // Segment tables of every launch site of a solve: one launch per stage (and
@@ -425,12 +458,12 @@ int build_schedule(fmm_plan* pl) {
         at[x].push_back(part_doubles);
         part_doubles += (long long)S * c.n * c.n * c.n * RS;
       }
-      // rebuild the site with the split; split partial sums are FP64, so
-      // the finest level keeps its FP64 locals and the bottom reads those
+      // rebuild the site with the split (split partial sums are FP64: a
+      // site that splits never holds a level with typed locals)
       SegList sp;
       for (auto c : conv[x].v) {
+        if (c.u) return fail(FMM_ERR_DEVICE, "internal: a split M2L launch with typed finest locals");
         c.split = S;
-        c.u = nullptr;
         sp.add(c, (long long)c.tpa * c.tpa * c.tz * S);
       }
       conv[x] = sp;
@@ -828,19 +861,16 @@ fmm_plan* create_plan(const std::vector<int>& ns, int p, const fmm_options& o, i
         }
       }
       if (k >= 3) {
-        const size_t lb = (size_t)(lv.ncell / 8) * fmm::loc_stride(p) * sizeof(double);
-        if (dev_alloc(pl, &lv.L, lb)) return bail();
-        if (hipMemset(lv.L, 0, lb) != hipSuccess) {
+        // the finest level of a low-precision bottom keeps its locals in the
+        // compute type only (Level::Lt)
+        const bool typed = k == fd.F && fmm::finest_locals_typed(pl, fd);
+        const size_t lb = (size_t)(lv.ncell / 8) * fmm::loc_stride(p) *
+                          (!typed ? sizeof(double) : pl->precision == 2 ? 2 : 4);
+        void*& dst = typed ? lv.Lt : lv.L;
+        if (dev_alloc(pl, &dst, lb)) return bail();
+        if (hipMemset(dst, 0, lb) != hipSuccess) {
           fail(FMM_ERR_DEVICE, "hipMemset failed");
           return bail();
-        }
-        if (k == fd.F && pl->dl == 1 && fmm::bottom_low(pl, k)) {
-          const size_t tb = (size_t)(lv.ncell / 8) * fmm::loc_stride(p) * (pl->precision == 2 ? 2 : 4);
-          if (dev_alloc(pl, &lv.Lt, tb)) return bail();
-          if (hipMemset(lv.Lt, 0, tb) != hipSuccess) {
-            fail(FMM_ERR_DEVICE, "hipMemset failed");
-            return bail();
-          }
         }
       }
     }

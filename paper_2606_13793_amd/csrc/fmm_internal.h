@@ -175,8 +175,9 @@ struct Level {
   // row stride loc_stride(p)
   void* L = nullptr;
   // the finest level's M2L part in the compute type of a low-precision
-  // bottom kernel (FMM-1), in the layout of L; null elsewhere.  Only the
-  // bottom kernel reads it, and it rounds its operands to that type anyway.
+  // bottom kernel (FMM-1), in the layout of L, in place of L (null then);
+  // null elsewhere.  Only the bottom kernel reads it, and it rounds its
+  // operands to that type anyway.
   void* Lt = nullptr;
 };
 
@@ -400,6 +401,7 @@ hipError_t finish_locals(fmm_plan* pl, int level, hipStream_t s);
 int build_schedule(fmm_plan* pl);
 // which levels run in which compute type (same rule for every field)
 inline bool bottom_low(const fmm_plan* pl, int F) { return pl->precision != 0 && F > pl->coarse_fp64_levels; }
+bool finest_locals_typed(const fmm_plan* pl, const Field& fd);
 inline int m2l_low_from(const fmm_plan* pl) {
   return pl->precision == 0 ? 64 : (pl->coarse_fp64_levels + 1 > 3 ? pl->coarse_fp64_levels + 1 : 3);
 }

@@ -520,7 +520,7 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
   auto lcell = [&](int m) { return ((2 * (m / TPX) + r0) * BY + 2 * (YPT * (m % TPX) + gyo) + r1) * BZ + 2 * gz + r2; };
   auto lpar = [&](int m) { return ((m / TPX) * (BY / 2) + YPT * (m % TPX) + gyo) * (BZ / 2) + gz; };
   if constexpr (DL == 1) {
-  if (Lf) {
+  if (Lf || sg.u) {
     // terms per pass (chunks of KT): the own and parent operands of TC + TP
     // cells fit the halo area; row stride KPS keeps BF16 rows 16-byte aligned
     // and spreads the rows of a fragment over the LDS banks
