@@ -1027,8 +1027,11 @@ template <typename CT>
 hipError_t build_tile_table(fmm_plan* pl, int op, hipStream_t s) {
   constexpr int X = Mf<CT>::IDX, KC = Mf<CT>::KC;
   if (pl->tiletab[op][X]) return hipSuccess;
-  const int nt = conv_ntiles(op, pl->p);
-  std::vector<int> h(2 * (nt + 16), 0);
+  const int nt = conv_ntiles(op, pl->p), nb = 2 * (nt + 16);
+  // [nt + 16] (K chunks, first fragment) per column tile, then [nt + 16] the
+  // first K chunk from which the FP64 transposed M2L's tile has non-zero B
+  // entries only in its first 4 columns (none: its chunk count)
+  std::vector<int> h(nb + nt + 16, 0);
   for (int t = 0; t < nt; ++t) {
     h[2 * t] = conv_tile_chunks(op, pl->p, t, KC);
     h[2 * t + 1] = conv_frag_offset(op, pl->p, t, KC);
@@ -1040,6 +1043,19 @@ hipError_t build_tile_table(fmm_plan* pl, int op, hipStream_t s) {
       h[2 * t] = 0;
     // the kernel takes the tiles that have a chunk to be a prefix of the group
     if (t > 0 && h[2 * t] > h[2 * t - 2]) return hipErrorInvalidValue;
+    h[nb + t] = h[2 * t];
+    if (X == 0 && op == CV_M2LT)
+      for (int c = 0; c < h[2 * t]; ++c) {
+        // K chunk c holds local columns of degree >= d; term a of the tile
+        // has non-zero entries there only if |a| + d <= p (a sorted by degree)
+        const int d = m2l_col_degree(KC * c);
+        int ncol = 0;
+        for (int a = 16 * t; a < 16 * t + 16 && a < nterms(pl->p); ++a) ncol += mi_degree(a) + d <= pl->p;
+        if (ncol <= 4) {
+          h[nb + t] = c;
+          break;
+        }
+      }
   }
   hipError_t e = hipMalloc(&pl->tiletab[op][X], h.size() * sizeof(int));
   if (e != hipSuccess) return e;
@@ -1143,7 +1159,12 @@ hipError_t launch_conv(fmm_plan* pl, const SegTable& st, const void* W, hipStrea
   if (!st.nseg) return hipSuccess;
   if constexpr (OP == CV_M2L)
     if (pl->tune.grp == 1) return launch_conv_nt<P, CT, OP, ConvGroup<CT, 1>::NT>(pl, st, W, s);
-  return launch_conv_nt<P, CT, OP, ConvGroup<CT, 0>::NT>(pl, st, W, s);
+  // the FP64 transposed M2L takes one column tile per block, so every tile's
+  // narrow K chunks (4-column products) run as such
+  if constexpr (OP == CV_M2LT && Mf<CT>::IDX == 0)
+    return launch_conv_nt<P, CT, OP, 1>(pl, st, W, s);
+  else
+    return launch_conv_nt<P, CT, OP, ConvGroup<CT, 0>::NT>(pl, st, W, s);
 }
 
 hipError_t launch_split_reduce(fmm_plan* pl, const SegTable& st, hipStream_t s) {
