@@ -1029,8 +1029,8 @@ hipError_t build_tile_table(fmm_plan* pl, int op, hipStream_t s) {
   if (pl->tiletab[op][X]) return hipSuccess;
   const int nt = conv_ntiles(op, pl->p), nb = 2 * (nt + 16);
   // [nt + 16] (K chunks, first fragment) per column tile, then [nt + 16] the
-  // first K chunk from which the FP64 transposed M2L's tile has non-zero B
-  // entries only in its first 4 columns (none: its chunk count)
+  // first K chunk from which an FP64 transpose's tile has non-zero B entries
+  // only in its first 4 columns (none: its chunk count)
   std::vector<int> h(nb + nt + 16, 0);
   for (int t = 0; t < nt; ++t) {
     h[2 * t] = conv_tile_chunks(op, pl->p, t, KC);
@@ -1044,11 +1044,13 @@ hipError_t build_tile_table(fmm_plan* pl, int op, hipStream_t s) {
     // the kernel takes the tiles that have a chunk to be a prefix of the group
     if (t > 0 && h[2 * t] > h[2 * t - 2]) return hipErrorInvalidValue;
     h[nb + t] = h[2 * t];
-    if (X == 0 && op == CV_M2LT)
+    if (X == 0 && (op == CV_M2LT || op == CV_M2PT || op == CV_M2PT2))
       for (int c = 0; c < h[2 * t]; ++c) {
-        // K chunk c holds local columns of degree >= d; term a of the tile
-        // has non-zero entries there only if |a| + d <= p (a sorted by degree)
-        const int d = m2l_col_degree(KC * c);
+        // the tile's columns are multipole terms a, sorted by degree; in the
+        // transposed M2L, K chunk c holds local columns of degree >= d, where
+        // term a has non-zero entries only if |a| + d <= p; the transposed
+        // M2Ps use every term (columns past the last term are padding)
+        const int d = op == CV_M2LT ? m2l_col_degree(KC * c) : 0;
         int ncol = 0;
         for (int a = 16 * t; a < 16 * t + 16 && a < nterms(pl->p); ++a) ncol += mi_degree(a) + d <= pl->p;
         if (ncol <= 4) {

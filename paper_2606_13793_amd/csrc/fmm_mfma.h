@@ -1143,16 +1143,24 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   for (int m = 0; m < CMT; ++m)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[m][t] = Acc{0, 0, 0, 0};
-  // FP64 transposed M2L (launched with one column tile per block): from K
-  // chunk nar on, the tile's B entries are zero outside its first 4 columns
-  // (|a| + |b| <= p with |b| large), so those chunks run as 4-column products
-  // (v_mfma_f64_4x4x4f64, four 4 x 4 blocks over the 16 rows, a quarter of
-  // the 16-column product's work) into acc4, added to the tile at the end
-  constexpr bool NARROW = OP == CV_M2LT && M::IDX == 0 && NT == 1;
-  const int nar = NARROW ? reinterpret_cast<const int*>(tiles)[2 * (NTILES + 16) + T0] : 1 << 30;
-  double acc4[NARROW ? CMT : 1];
+  // FP64 transposes: from K chunk nar(t) on, column tile t's B entries are
+  // zero outside its first 4 columns, so those chunks run the tile as
+  // 4-column products (v_mfma_f64_4x4x4f64, four 4 x 4 blocks over the 16
+  // rows, a quarter of the 16-column product's work) into acc4, added to the
+  // tile at the end.
+  //  - transposed M2L (one tile per block): |a| + |b| <= p with |b| large;
+  //    the narrow chunks are a suffix of the tile's chunks (NARROW_C);
+  //  - transposed M2Ps: the last tile, past the last multipole term, is
+  //    narrow in every chunk; its group runs the narrow form throughout
+  //    (NARROW_G, when the group's tiles have equal chunk counts).
+  constexpr bool NARROW_C = M::IDX == 0 && OP == CV_M2LT && NT == 1;
+  constexpr bool NARROW_G = M::IDX == 0 && (OP == CV_M2PT || OP == CV_M2PT2);
+  const int* ntab = reinterpret_cast<const int*>(tiles) + 2 * (NTILES + 16);
+  const int nar = NARROW_C ? ntab[T0] : 1 << 30;
+  const bool gnar = NARROW_G && T0 + NT - 1 < NTILES && vt[0] > 0 && vt[NT - 1] == vt[0] && ntab[T0 + NT - 1] == 0;
+  double acc4[NARROW_C || NARROW_G ? CMT : 1];
 #pragma unroll
-  for (int m = 0; m < (NARROW ? CMT : 1); ++m) acc4[m] = 0.0;
+  for (int m = 0; m < (NARROW_C || NARROW_G ? CMT : 1); ++m) acc4[m] = 0.0;
 
   const int* dl = slist + r * NLIST_PAD;  // visible after the first chunk's barrier
   const int2* dp = spair + r * (NGRP + 1) * 2 + lr.sel;
@@ -1181,16 +1189,18 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   auto offsets = [&](auto pk, auto na, int c, auto nr) {
     constexpr bool PK = decltype(pk)::value;
     constexpr int NA = decltype(na)::value;  // column tiles with chunk c (the first NA)
-    constexpr bool NR = decltype(nr)::value;  // narrow: the last tile's first 4 columns only
+    constexpr bool NR = decltype(nr)::value;  // narrow: tile NA - 1's first 4 columns only
     constexpr int NG = PK ? (NOFF + 3) / 4 : NGRP;
     const int ja = part * NG / split, jb = (part + 1) * NG / split;
+    const H* wl = Wt + (PK ? i : lr.tl) * VPL;
     // (narrow products: the lane holds the B value of column lane % 4 of its
     // K row, which the 16-column fragment keeps in lane (lane & 48) | (lane & 3))
-    const H* wl = Wt + (PK ? i : NR ? ((lane & 48) | (lane & 3)) : lr.tl) * VPL;
+    const H* wn = Wt + ((lane & 48) | (lane & 3)) * VPL;
     const H* hl = PK ? hlane - lr.tic : hlane;
     auto bload = [&](EntryGroup g, int t) {
       if constexpr (OPM == 1)
-        return *reinterpret_cast<const AF*>(wl + ((size_t)(off[t] + c) * NS + dl_dd(g.e)) * EL * VPL);
+        return *reinterpret_cast<const AF*>((NR && t == NA - 1 ? wn : wl) +
+                                            ((size_t)(off[t] + c) * NS + dl_dd(g.e)) * EL * VPL);
       else
         return *reinterpret_cast<const AF*>(wl + (size_t)(off[t] + c) * NS * EL * VPL + g.boff);
     };
@@ -1249,13 +1259,16 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
         // them next to their uses and expose their latency)
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int m = 0; m < CMT; ++m) {
-          if constexpr (NR)
-            acc4[m] = __builtin_amdgcn_mfma_f64_4x4x4f64(as[cur][m], bs[cur][0], acc4[m], 0, 0, 0);
-          else
+        for (int m = 0; m < CMT; ++m)
 #pragma unroll
-            for (int t = 0; t < NA; ++t) acc[m][t] = M::op(as[cur][m], bs[cur][t], acc[m][t]);
-        }
+          for (int t = 0; t < NA; ++t) {
+            if constexpr (NR)
+              if (t == NA - 1) {
+                acc4[m] = __builtin_amdgcn_mfma_f64_4x4x4f64(as[cur][m], bs[cur][t], acc4[m], 0, 0, 0);
+                continue;
+              }
+            acc[m][t] = M::op(as[cur][m], bs[cur][t], acc[m][t]);
+          }
         __builtin_amdgcn_sched_barrier(0);
       }
     }
@@ -1266,7 +1279,7 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
   // tiles, [vt[NA], vt[NA - 1]), run as one loop with branch-free products.
   TypedStage<CT, CZ, M2L_THREADS> ts;
   if constexpr (TYPED) ts.plan(nsp, tx0, ty0, tz0);
-  auto chunks = [&](auto pk) {
+  auto chunks = [&](auto pk, auto gn) {
     count_down<NT>([&](auto nac) {
       constexpr int NA = decltype(nac)::value;
       int cb = 0;
@@ -1278,35 +1291,44 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
         else
           stage_halo<CT, CZ, M2L_THREADS>(halo, src, NC4, ncellp, nsp, tx0, ty0, tz0, c);
         __syncthreads();
-        if constexpr (NARROW) {
+        if constexpr (NARROW_C) {
           if (c >= nar)
             offsets(pk, nac, c, std::true_type{});
           else
             offsets(pk, nac, c, std::false_type{});
         } else {
-          offsets(pk, nac, c, std::false_type{});
+          offsets(pk, nac, c, gn);
         }
       }
     });
   };
   if constexpr (CAN_PACK) {
     if (packed)
-      chunks(std::true_type{});
+      chunks(std::true_type{}, std::false_type{});
     else
-      chunks(std::false_type{});
+      chunks(std::false_type{}, std::false_type{});
+  } else if constexpr (NARROW_G) {
+    if (gnar)
+      chunks(std::false_type{}, std::true_type{});
+    else
+      chunks(std::false_type{}, std::false_type{});
   } else {
-    chunks(std::false_type{});
+    chunks(std::false_type{}, std::false_type{});
   }
-  if constexpr (NARROW) {
+  if constexpr (NARROW_C || NARROW_G) {
+    const int tn = NARROW_C ? (nar < vt[0] ? 0 : -1) : (gnar ? NT - 1 : -1);
     // narrow output C_b[i][j] (row 4 b + i, column j) sits in lane 16 i + 4 b + j;
     // the 16-column tile keeps row 4 v + kq, column i in element v of lane 16 kq + i
 #pragma unroll
-    for (int m = 0; m < CMT; ++m)
+    for (int t = 0; t < NT; ++t)
+      if (t == tn)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const double v = __shfl(acc4[m], (lane & 48) | (b << 2) | (lane & 3));
-        if ((lane & 12) == 0) acc[m][0][b] += v;  // the tile's columns 0..3
-      }
+        for (int m = 0; m < CMT; ++m)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const double v = __shfl(acc4[m], (lane & 48) | (b << 2) | (lane & 3));
+            if ((lane & 12) == 0) acc[m][t][b] += v;  // the tile's columns 0..3
+          }
   }
   // epilogue: element v of tile t is row M::row(v, kq), column 16 (T0 + t) + i
   if constexpr (OP == CV_M2L) {
