@@ -42,6 +42,9 @@ __constant__ double c_mi_invfact[NTMAX];
 //   c_p2p_phi = -1/max(|delta|, 1),  c_p2p_g = -delta/|delta|^3 (0 at delta = 0)
 __constant__ double c_p2p_phi[343];
 __constant__ double c_p2p_g[3 * 343];
+// the near-field weights of the transposed solve per offset delta:
+// (2 c_p2p_phi, -4 c_p2p_g) at [4 delta], read at wave-uniform addresses
+__constant__ double c_p2p_adj[4 * 343];
 
 __device__ __forceinline__ int mi_a(int e) { return e & 255; }
 __device__ __forceinline__ int mi_b(int e) { return (e >> 8) & 255; }
@@ -85,7 +88,7 @@ hipError_t upload_constants_tu() {
         for (int i = 2; i <= c; ++i) f *= i;
         inv[t] = 1.0 / f;
       }
-  double pp[343], pg[3 * 343];
+  double pp[343], pg[3 * 343], pa[4 * 343];
   for (int t = 0; t < 343; ++t) {
     const int d0 = t / 49 - 3, d1 = (t / 7) % 7 - 3, d2 = t % 7 - 3;
     const double r2 = double(d0 * d0 + d1 * d1 + d2 * d2);
@@ -100,12 +103,15 @@ hipError_t upload_constants_tu() {
       pg[343 + t] = -d1 * i3;
       pg[686 + t] = -d2 * i3;
     }
+    pa[4 * t] = 2.0 * pp[t];
+    for (int o = 0; o < 3; ++o) pa[4 * t + 1 + o] = -4.0 * pg[343 * o + t];
   }
   hipError_t e;
   if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_mi_exp), ex, sizeof(ex))) != hipSuccess) return e;
   if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_mi_invfact), inv, sizeof(inv))) != hipSuccess) return e;
   if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_p2p_phi), pp, sizeof(pp))) != hipSuccess) return e;
   if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_p2p_g), pg, sizeof(pg))) != hipSuccess) return e;
+  if ((e = hipMemcpyToSymbol(HIP_SYMBOL(c_p2p_adj), pa, sizeof(pa))) != hipSuccess) return e;
   done = true;
   return hipSuccess;
 }
@@ -649,10 +655,10 @@ __global__ void k_adj_coef2(double* __restrict__ own, double* __restrict__ par, 
 // an odd row stride and, for each 16-column tile of local terms b,
 //   own[P][(rp, b)] += sum_k cown[g][b][k] Ybar_g[2P + rp][k]      (K = 32)
 //   par[P][b]      += sum_k cpar[g][rp][b][k] Ybar_g[2P + rp][k]
-// accumulate in registers.  own is then written to P's row (columns (rp, b)
-// in the M2L order); the 8 waves' par partials are added in LDS in a fixed
-// order and written, when the parent level has locals, to the row of P's
-// parent (column (qP, b)).
+// accumulate in registers (with one group, tile by tile).  own is then
+// written to P's row (columns (rp, b) in the M2L order); the 8 waves' par
+// partials are added in LDS in a fixed order and written, when the parent
+// level has locals, to the row of P's parent (column (qP, b)).
 constexpr int ADJ_L2P_PAR = 16, ADJ_L2P_THREADS = 512, ADJ_L2P_YS = 257;
 template <int P, int DL>
 __global__ __launch_bounds__(ADJ_L2P_THREADS) void k_adj_l2p(const double* __restrict__ Y,
@@ -682,14 +688,10 @@ __global__ __launch_bounds__(ADJ_L2P_THREADS) void k_adj_l2p(const double* __res
     const int p2 = (int)(Pq % nP), p1 = (int)((Pq / nP) % nP), p0 = (int)(Pq / ((long long)nP * nP));
     cpo[v] = ((long long)(p0 + 3) * nPp + (p1 + 3)) * nPp + (p2 + 3);
   }
-  d4 ao[NBT], ap[NBT];
-#pragma unroll
-  for (int T = 0; T < NBT; ++T) ao[T] = ap[T] = d4{0, 0, 0, 0};
   const double* ya = y + i * ADJ_L2P_YS + rp * 32 + kq;
-  for (int g = 0; g < NG; ++g) {
-    if (g) __syncthreads();  // the previous group is consumed
-    // staging: load l = (q, parent, rp), children of consecutive parents are
-    // contiguous along z
+  // staging of group g: load l = (q, parent, rp), children of consecutive
+  // parents are contiguous along z
+  auto stage = [&](int g) {
     for (int l = threadIdx.x; l < 8 * ADJ_L2P_PAR * 8; l += ADJ_L2P_THREADS) {
       const int lr = l & 7, pl = (l >> 3) % ADJ_L2P_PAR, q = l / (8 * ADJ_L2P_PAR);
       const long long Pc = P0 + pl;
@@ -704,37 +706,22 @@ __global__ __launch_bounds__(ADJ_L2P_THREADS) void k_adj_l2p(const double* __res
 #pragma unroll
       for (int e = 0; e < 4; ++e) yy[e] = v[e];
     }
-    __syncthreads();
-    const double* co = cown + (size_t)g * NL * 32;
-    const double* cp = cpar + ((size_t)g * 8 + rp) * NL * 32;
-#pragma unroll
-    for (int T = 0; T < NBT; ++T) {
-      const int bt = 16 * T + i;  // the lane's column (B operand)
-      const bool okc = bt < NL;
-#pragma unroll
-      for (int kc = 0; kc < 8; ++kc) {
-        const double a = ya[4 * kc];
-        const double bo = okc ? co[bt * 32 + 4 * kc + kq] : 0.0;
-        const double bp = okc ? cp[bt * 32 + 4 * kc + kq] : 0.0;
-        ao[T] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bo, ao[T], 0, 0, 0);
-        ap[T] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bp, ap[T], 0, 0, 0);
-      }
-    }
-  }
-#pragma unroll
-  for (int T = 0; T < NBT; ++T) {
+  };
+  // tile T's own columns to P's row; the 8 waves' parent partials added in
+  // LDS in a fixed order, to the row of P's parent
+  auto store = [&](int T, const d4& ao, const d4& ap) {
     const int bt = 16 * T + i;
     if (bt < NL) {
       const int ex = c_mi_exp[bt];
       const int col = m2l_col(rp, bt, mi_a(ex) + mi_b(ex) + mi_c(ex));
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        if (okr[v]) Aown[((col >> 2) * ncP + cpo[v]) * 4 + (col & 3)] = ao[T][v];
+        if (okr[v]) Aown[((col >> 2) * ncP + cpo[v]) * 4 + (col & 3)] = ao[v];
     }
     if (Apar) {
       __syncthreads();  // the staging buffer / previous reduction is consumed
 #pragma unroll
-      for (int v = 0; v < 4; ++v) red[rp][4 * v + kq][i] = ap[T][v];
+      for (int v = 0; v < 4; ++v) red[rp][4 * v + kq][i] = ap[v];
       __syncthreads();
       if (threadIdx.x < 256) {
         const int row = threadIdx.x >> 4, c = threadIdx.x & 15, b2 = 16 * T + c;
@@ -752,6 +739,57 @@ __global__ __launch_bounds__(ADJ_L2P_THREADS) void k_adj_l2p(const double* __res
         }
       }
     }
+  };
+  if constexpr (NG == 1) {
+    // one group: tile by tile, so the accumulators of one tile are live
+    // (several blocks per CU overlap one block's staging with another's
+    // products)
+    stage(0);
+    __syncthreads();
+    double a[8];
+#pragma unroll
+    for (int kc = 0; kc < 8; ++kc) a[kc] = ya[4 * kc];
+    const double* cp = cpar + (size_t)rp * NL * 32;
+#pragma unroll 1
+    for (int T = 0; T < NBT; ++T) {
+      const int bt = 16 * T + i;  // the lane's column (B operand)
+      const bool okc = bt < NL;
+      d4 ao = d4{0, 0, 0, 0}, ap = d4{0, 0, 0, 0};
+#pragma unroll
+      for (int kc = 0; kc < 8; ++kc) {
+        const double bo = okc ? cown[bt * 32 + 4 * kc + kq] : 0.0;
+        const double bp = okc ? cp[bt * 32 + 4 * kc + kq] : 0.0;
+        ao = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kc], bo, ao, 0, 0, 0);
+        ap = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kc], bp, ap, 0, 0, 0);
+      }
+      store(T, ao, ap);
+    }
+  } else {
+    d4 ao[NBT], ap[NBT];
+#pragma unroll
+    for (int T = 0; T < NBT; ++T) ao[T] = ap[T] = d4{0, 0, 0, 0};
+    for (int g = 0; g < NG; ++g) {
+      if (g) __syncthreads();  // the previous group is consumed
+      stage(g);
+      __syncthreads();
+      const double* co = cown + (size_t)g * NL * 32;
+      const double* cp = cpar + ((size_t)g * 8 + rp) * NL * 32;
+#pragma unroll
+      for (int T = 0; T < NBT; ++T) {
+        const int bt = 16 * T + i;  // the lane's column (B operand)
+        const bool okc = bt < NL;
+#pragma unroll
+        for (int kc = 0; kc < 8; ++kc) {
+          const double a = ya[4 * kc];
+          const double bo = okc ? co[bt * 32 + 4 * kc + kq] : 0.0;
+          const double bp = okc ? cp[bt * 32 + 4 * kc + kq] : 0.0;
+          ao[T] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bo, ao[T], 0, 0, 0);
+          ap[T] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bp, ap[T], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int T = 0; T < NBT; ++T) store(T, ao[T], ap[T]);
   }
   // the padding columns of P's row (past 8 NL) stay zero
   if constexpr (RS > 8 * NL) {
@@ -879,32 +917,26 @@ __global__ __launch_bounds__(ADJ_M2M_THREADS) void k_adj_m2m(const double* __res
 // chunks q (4 values each) of the block's cells and their one-cell halo are
 // staged in LDS one chunk at a time, so a block needs little LDS and a CU
 // holds many; each neighbour's chunk is read once and applied to all 8
-// children.  The stencil weights depend only on (e, q, q_w) and are read from
-// LDS tables at uniform addresses.  The P2M^T part is a Walsh transform of 8
-// signed sums of the cell's terms.
+// children.  The stencil weights depend only on (e, q, q_w): constant-memory
+// reads at wave-uniform addresses (scalar loads, four weights per offset
+// contiguous), so the LDS serves only the staged chunks.  The P2M^T part is
+// a Walsh transform of 8 signed sums of the cell's terms.
 constexpr int ADJ_BOT_TZ = 16;  // cells along z per block (fewer when the grid is smaller)
 template <typename TO>
 __global__ __launch_bounds__(16 * ADJ_BOT_TZ) void k_adj_bottom(const double* __restrict__ Mb,
                                                                 const double* __restrict__ Y, TO* __restrict__ drho,
                                                                 int n, int NM) {
   __shared__ d4 ys[36 * (ADJ_BOT_TZ + 2)];
-  __shared__ double sp[343], sg3[3 * 343];
   const int TZ = blockDim.x >> 4, HZ = TZ + 2, nthr = blockDim.x;
   const int nF = n >> 1, nFp = nF + 6;
   const long long ncellp = (long long)nFp * nFp * nFp;
   const int T0x = blockIdx.x * 4, T0y = blockIdx.y * 4, T0z = blockIdx.z * TZ;
-  for (int t = threadIdx.x; t < 343; t += nthr) {
-    sp[t] = 2.0 * c_p2p_phi[t];
-    sg3[t] = -4.0 * c_p2p_g[t];
-    sg3[343 + t] = -4.0 * c_p2p_g[343 + t];
-    sg3[686 + t] = -4.0 * c_p2p_g[686 + t];
-  }
   const int tl2 = threadIdx.x % TZ, tl1 = (threadIdx.x / TZ) & 3, tl0 = threadIdx.x / (4 * TZ);
   double acc[8];
 #pragma unroll
   for (int qw = 0; qw < 8; ++qw) acc[qw] = 0.0;
   for (int q = 0; q < 8; ++q) {
-    __syncthreads();  // the previous chunk is consumed (and the tables are written)
+    __syncthreads();  // the previous chunk is consumed
     for (int c = threadIdx.x; c < 36 * HZ; c += nthr) {
       const int cz = c % HZ, cy = (c / HZ) % 6, cx = c / (6 * HZ);
       // padded coordinates of T = T0 + (cx, cy, cz) - 1, inside [2, nF + 4)
@@ -921,7 +953,9 @@ __global__ __launch_bounds__(16 * ADJ_BOT_TZ) void k_adj_bottom(const double* __
 #pragma unroll
       for (int qw = 0; qw < 8; ++qw) {
         const int t = tb - (((qw >> 2) & 1) * 49 + ((qw >> 1) & 1) * 7 + (qw & 1));
-        acc[qw] += sp[t] * v[0] + sg3[t] * v[1] + sg3[343 + t] * v[2] + sg3[686 + t] * v[3];
+        const double* cw = c_p2p_adj + 4 * t;
+#pragma unroll
+        for (int o = 0; o < 4; ++o) acc[qw] = fma(cw[o], v[o], acc[qw]);
       }
     }
   }
