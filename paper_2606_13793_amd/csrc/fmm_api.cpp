@@ -731,10 +731,10 @@ fmm_plan* create_plan(const std::vector<int>& ns, int p, const fmm_options& o, i
   if (pl->dl == 2 && dev_alloc(pl, (void**)&pl->dtab2, (size_t)343 * 64 * pl->ND * sizeof(double))) return bail();
   if (dev_alloc(pl, (void**)&pl->dlists, 8 * fmm::NLIST_PAD * sizeof(int))) return bail();
   {
-    // L2L coefficient lists: for each local term b, the terms b + g with
-    // |b + g| <= p, coefficient 2^-(|b|+1) 4^-|g| / g!, the column of b + g
-    // (child 0) and its degree block size, and the parity pattern of g (the
-    // sign for child q is (-1)^((1-q).g))
+    // L2L coefficient lists: for each local term b and parity pattern of g
+    // (start index 8 b + pattern), the terms b + g with |b + g| <= p and
+    // coefficient 2^-(|b|+1) 4^-|g| / g! (the sign for child q is
+    // (-1)^((1-q).g), applied per pattern by the kernel)
     std::vector<int> start(1, 0), idx;
     std::vector<double> coef;
     auto fact = [](int k) { double f = 1; for (int i = 2; i <= k; ++i) f *= i; return f; };
@@ -747,16 +747,16 @@ fmm_plan* create_plan(const std::vector<int>& ns, int p, const fmm_options& o, i
         }
     for (int t = 0; t < pl->NL; ++t) {
       const int bx = ex[3 * t], by = ex[3 * t + 1], bz = ex[3 * t + 2], m = bx + by + bz;
-      for (int gx = 0; gx <= p - m; ++gx)
-        for (int gy = 0; gx + gy <= p - m; ++gy)
-          for (int gz = 0; gx + gy + gz <= p - m; ++gz) {
-            const int ng = gx + gy + gz;
-            const int pat = ((gx & 1) << 2) | ((gy & 1) << 1) | (gz & 1);
-            const int bg = fmm::mi_index(bx + gx, by + gy, bz + gz), mg = m + ng;
-            idx.push_back((fmm::m2l_col(0, bg, mg) << 9) | (fmm::ndeg(mg) << 3) | pat);
-            coef.push_back(std::ldexp(1.0 / (fact(gx) * fact(gy) * fact(gz)), -(m + 1) - 2 * ng));
-          }
-      start.push_back((int)idx.size());
+      for (int pat = 0; pat < 8; ++pat) {
+        for (int gx = (pat >> 2) & 1; gx <= p - m; gx += 2)
+          for (int gy = (pat >> 1) & 1; gx + gy <= p - m; gy += 2)
+            for (int gz = pat & 1; gx + gy + gz <= p - m; gz += 2) {
+              const int ng = gx + gy + gz;
+              idx.push_back(fmm::mi_index(bx + gx, by + gy, bz + gz));
+              coef.push_back(std::ldexp(1.0 / (fact(gx) * fact(gy) * fact(gz)), -(m + 1) - 2 * ng));
+            }
+        start.push_back((int)idx.size());
+      }
     }
     if ((int)idx.size() != fmm::l2l_entries(p)) {  // k_l2l stages exactly this many entries
       fail(FMM_ERR_DEVICE, "L2L coefficient list size");

@@ -32,6 +32,16 @@ namespace fmm {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Calls f(std::integral_constant<int, k>) for k = I, I + 1, ..., N - 1.
+template <int N, int I = 0, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<N, I + 1>(f);
+  }
+}
+
 #include "fmm_types.h"
 
 // multi-index table for orders <= PDMAX: packed exponents a | b<<8 | c<<16,
@@ -231,12 +241,41 @@ __global__ __launch_bounds__(256) void k_p2m(const Seg* __restrict__ segs, int n
 }
 
 // P2M of FMM-2: Mhat_F[a] = sum_s rho_{4T+s} w_s^a / a!, w_s,i = (3 - 2 s_i) / 8
-// over the 64 unigrid cells s of T, summed axis by axis.  Segments as k_p2m.
-// FMM-1 plans use it for level F - 1, whose cells also hold 4^3 unigrid
-// cells: the same multipoles as M2M of the level-F P2M (M2M re-centres
-// exactly), without reading the level-F grid.
-template <typename TI, typename CT>
-__global__ __launch_bounds__(256) void k_p2m2(const Seg* __restrict__ segs, int nseg, IoArg io, int NM, int NC) {
+// over the 64 unigrid cells s of T.  Segments as k_p2m.  FMM-1 plans use it
+// for level F - 1, whose cells also hold 4^3 unigrid cells: the same
+// multipoles as M2M of the level-F P2M (M2M re-centres exactly), without
+// reading the level-F grid.
+// Along one axis w takes the values 3/8, 1/8, -1/8, -3/8, so
+//   sum_s w_s^k rho_s = (3/8)^k (rho_0 +- rho_3) + (1/8)^k (rho_1 +- rho_2)
+// with + for even k and - for odd k: one butterfly per axis turns the 4
+// values of each line into these 4 combinations (slot 2 (k odd) + (|w| =
+// 1/8)), and each term is then 8 products with the integer weights 3^k of
+// its slots, scaled by 8^-|a| / a!.  The term loop is unrolled (P fixed), so
+// the slots are register indices known at compile time.
+constexpr __host__ __device__ int mi_exp_of(int t) {
+  int n = 0;
+  while (nterms(n) <= t) ++n;
+  int r = t - nterms(n - 1), a = 0;
+  while (r >= n - a + 1) {
+    r -= n - a + 1;
+    ++a;
+  }
+  return a | r << 8 | (n - a - r) << 16;
+}
+constexpr bool mi_exp_inverts_index() {
+  for (int t = 0; t < NTMAX; ++t) {
+    const int e = mi_exp_of(t);
+    if (mi_index(e & 255, (e >> 8) & 255, e >> 16) != t) return false;
+  }
+  return true;
+}
+static_assert(mi_exp_inverts_index(), "mi_exp_of inverts mi_index");
+constexpr __host__ __device__ double pow3(int k) { return k == 0 ? 1.0 : 3.0 * pow3(k - 1); }
+constexpr __host__ __device__ double fact_d(int k) { return k <= 1 ? 1.0 : k * fact_d(k - 1); }
+
+template <int P, typename TI, typename CT>
+__global__ __launch_bounds__(256) void k_p2m2(const Seg* __restrict__ segs, int nseg, IoArg io, int NM) {
+  constexpr int NT = nterms(P), NC = (NT + 3) / 4;
   const Seg& sg = find_seg(segs, nseg, blockIdx.x);
   const int n = sg.n;
   const TI* __restrict__ rho = io_rho<TI>(io, sg.field);
@@ -250,52 +289,52 @@ __global__ __launch_bounds__(256) void k_p2m2(const Seg* __restrict__ segs, int 
 #pragma unroll
   for (int sb = 0; sb < 64; ++sb)
     v[sb] = (double)rho[((long long)(4 * t0 + (sb >> 4)) * n + (4 * t1 + ((sb >> 2) & 3))) * n + (4 * t2 + (sb & 3))];
+  // butterflies along z (stride 1), y (4), x (16)
+#pragma unroll
+  for (int st = 1; st <= 16; st *= 4) {
+#pragma unroll
+    for (int l = 0; l < 64; ++l)
+      if (((l / st) & 3) == 0) {
+        const double r0 = v[l], r1 = v[l + st], r2 = v[l + 2 * st], r3 = v[l + 3 * st];
+        v[l] = r0 + r3;
+        v[l + st] = r1 + r2;
+        v[l + 2 * st] = r0 - r3;
+        v[l + 3 * st] = r1 - r2;
+      }
+  }
   const long long ncellp = (long long)nFp * nFp * nFp;
   const long long cp = ((long long)(t0 + 3) * nFp + (t1 + 3)) * nFp + (t2 + 3);
-#pragma unroll 1
-  for (int c = 0; c < NC; ++c) {
+  static_for<NC>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
     d4 o;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int al = 4 * c + e;
+    static_for<4>([&](auto ec) {
+      constexpr int al = 4 * c + decltype(ec)::value;
       double val = 0.0;
-      if (al < NM) {
-        const int ex = c_mi_exp[al];
-        const int be[3] = {mi_a(ex), mi_b(ex), mi_c(ex)};
-        double pw[3][4];
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax)
-#pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            const double w = (3 - 2 * s) / 8.0;
-            double m = 1.0;
-            for (int z = 0; z < be[ax]; ++z) m *= w;
-            pw[ax][s] = m;
-          }
-        double sx = 0.0;
-#pragma unroll
-        for (int s0 = 0; s0 < 4; ++s0) {
-          double sy = 0.0;
-#pragma unroll
-          for (int s1 = 0; s1 < 4; ++s1) {
-            double sz = 0.0;
-#pragma unroll
-            for (int s2 = 0; s2 < 4; ++s2) sz += pw[2][s2] * v[16 * s0 + 4 * s1 + s2];
-            sy += pw[1][s1] * sz;
-          }
-          sx += pw[0][s0] * sy;
-        }
-        val = c_mi_invfact[al] * sx;
+      if constexpr (al < NT) {
+        constexpr int ex = mi_exp_of(al);
+        constexpr int ax = ex & 255, ay = (ex >> 8) & 255, az = ex >> 16;
+        constexpr int base = 16 * 2 * (ax & 1) + 4 * 2 * (ay & 1) + 2 * (az & 1);
+        double x = 0.0;
+        static_for<8>([&](auto mc) {
+          constexpr int m = decltype(mc)::value, mx = m >> 2, my = (m >> 1) & 1, mz = m & 1;
+          constexpr double wt = pow3(mx ? 0 : ax) * pow3(my ? 0 : ay) * pow3(mz ? 0 : az);
+          x = fma(wt, v[base + 16 * mx + 4 * my + mz], x);
+        });
+        constexpr double sc = 1.0 / (fact_d(ax) * fact_d(ay) * fact_d(az) * (double)(1LL << (3 * (ax + ay + az))));
+        if (al < NM) val = sc * x;
       }
-      o[e] = val;
-    }
+      o[decltype(ec)::value] = val;
+    });
     *reinterpret_cast<d4*>(M + (c * ncellp + cp) * 4) = o;
     if constexpr (Mf<CT>::IDX != 0) {
       constexpr int KC = Mf<CT>::KC;
       if (sg.t)
         store4((typename Mf<CT>::H*)sg.t + ((4 * c / KC) * ncellp + cp) * KC + (4 * c) % KC, o[0], o[1], o[2], o[3]);
     }
-  }
+    // (one chunk at a time: the scheduler would otherwise form every term
+    // before the first store and hold them all in registers)
+    __builtin_amdgcn_sched_barrier(0);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -516,29 +555,33 @@ __device__ __forceinline__ double p2p2_coef(int k, int grp, int q, int o) {
 // ---------------------------------------------------------------------------
 // L2L, eq. (L2L), for one level k: Lhat_k[T] += shift of Lhat_{k-1}[parent(T)]
 //   Lhat_k[b] += sum_{|b|+|g|<=p} 2^-(|b|+1) 4^-|g| / g! (2q-1)^g Lhat_{k-1}[b+g]
-// in the per-parent column layout.  A block takes L2L_ROWS cells P of level
-// k - 1: it stages the coefficient lists (CSR over b: coefficient and,
-// packed, column base of b+g (column with q = 0) << 9 | ndeg(|b+g|) << 3 |
-// parity of g) and the level-(k-1) local of each P (its terms at their
-// child-0 columns) in LDS; a thread then forms columns (q, b) of P's child
-// locals, so the read-modify-writes of the child rows are contiguous.
+// in the per-parent column layout.  The child q enters only through the sign
+// (2q-1)^g = (-1)^((1-q).g), which depends on the parity pattern of g: with
+//   S[b][pat] = sum_{g of pattern pat} 2^-(|b|+1) 4^-|g| / g! Lhat_{k-1}[b+g]
+// the 8 children's terms b are a sign transform of S[b][.] (one butterfly
+// stage per axis), so each coefficient is applied once instead of 8 times.
+// A block takes L2L_ROWS cells P of level k - 1 and stages the coefficient
+// lists (CSR over (b, pattern)) and the level-(k-1) local of each P in LDS;
+// thread (row r, slot s) forms terms b = s, s + 16, ... of P_r's 8 children
+// (the slots of a wave run the lists of 4 neighbouring terms at once).
 // ---------------------------------------------------------------------------
 // Segments: n = cells per axis of level k - 1, a = Lhat_{k-1}, b = Lhat_k.
 template <int P>
 __global__ __launch_bounds__(256) void k_l2l(const Seg* __restrict__ segs, int nseg, const int* __restrict__ cs,
                                              const int* __restrict__ cidx, const double* __restrict__ ccoef) {
-  constexpr int NL = nterms(P), NCOL = 8 * NL, RS = loc_stride(P), E = l2l_entries(P);
-  __shared__ int s_cs[NL + 1];
+  constexpr int NL = nterms(P), RS = loc_stride(P), E = l2l_entries(P), SS = NL + 1;
+  static_assert(L2L_ROWS == 16, "thread = (row, slot) over 16 rows and 16 slots");
+  __shared__ int s_cs[8 * NL + 1];
   __shared__ int s_idx[E];
   __shared__ double s_coef[E];
-  __shared__ double s_src[L2L_ROWS][NCOL];
+  __shared__ double s_src[L2L_ROWS * SS];  // odd row stride: the 16 rows of a slot hit distinct banks
   const Seg& sg = find_seg(segs, nseg, blockIdx.x);
   const double* __restrict__ Lprev = sg.a;
   double* __restrict__ Lk = sg.b;
   const int ns = sg.n, nsp = ns >> 1;
   const long long nps = (long long)ns * ns * ns;
   const long long P0 = (long long)(blockIdx.x - sg.first_block) * L2L_ROWS;
-  for (int t = threadIdx.x; t <= NL; t += 256) s_cs[t] = cs[t];
+  for (int t = threadIdx.x; t <= 8 * NL; t += 256) s_cs[t] = cs[t];
   for (int t = threadIdx.x; t < E; t += 256) {
     s_idx[t] = cidx[t];
     s_coef[t] = ccoef[t];
@@ -548,32 +591,49 @@ __global__ __launch_bounds__(256) void k_l2l(const Seg* __restrict__ segs, int n
   for (int e = threadIdx.x; e < L2L_ROWS * NL; e += 256) {
     const int g = e / NL, c = e - g * NL;
     const long long Pc = P0 + g;
-    if (Pc >= nps) continue;
-    const int p2 = (int)(Pc % ns), p1 = (int)((Pc / ns) % ns), p0 = (int)(Pc / ((long long)ns * ns));
-    const long long PP = ((long long)(p0 >> 1) * nsp + (p1 >> 1)) * nsp + (p2 >> 1);
-    const int qP = ((p0 & 1) << 2) | ((p1 & 1) << 1) | (p2 & 1);
-    const int ex = c_mi_exp[c];
-    const int d = mi_a(ex) + mi_b(ex) + mi_c(ex);
-    const int cb = m2l_col(0, c, d);
-    s_src[g][cb] = Lprev[PP * RS + cb + qP * ndeg(d)];
+    double v = 0.0;
+    if (Pc < nps) {
+      const int p2 = (int)(Pc % ns), p1 = (int)((Pc / ns) % ns), p0 = (int)(Pc / ((long long)ns * ns));
+      const long long PP = ((long long)(p0 >> 1) * nsp + (p1 >> 1)) * nsp + (p2 >> 1);
+      const int qP = ((p0 & 1) << 2) | ((p1 & 1) << 1) | (p2 & 1);
+      const int ex = c_mi_exp[c];
+      v = Lprev[PP * RS + m2l_col(qP, c, mi_a(ex) + mi_b(ex) + mi_c(ex))];
+    }
+    s_src[g * SS + c] = v;
   }
   __syncthreads();
-  for (int o = threadIdx.x; o < L2L_ROWS * NCOL; o += 256) {
-    const int g = o / NCOL, col = o - g * NCOL;
-    const long long Pc = P0 + g;
-    if (Pc >= nps) continue;
-    const int md = m2l_col_degree(col);
-    const int cin = col - 8 * nterms(md - 1);
-    const int q = cin / ndeg(md);
-    const int bt = nterms(md - 1) + cin % ndeg(md);
-    const int nq = (~q) & 7;  // axes with q_i = 0
-    double acc = 0.0;
-    for (int j = s_cs[bt]; j < s_cs[bt + 1]; ++j) {
-      const int id2 = s_idx[j];
-      const double x = s_coef[j] * s_src[g][id2 >> 9];
-      acc += (__popc(nq & id2 & 7) & 1) ? -x : x;
+  const int r = threadIdx.x & 15, slot = threadIdx.x >> 4;
+  const long long Pc = P0 + r;
+  if (Pc >= nps) return;
+  double* __restrict__ row = Lk + Pc * RS;
+  const double* src = s_src + r * SS;
+  for (int b = slot; b < NL; b += 16) {
+    const int ex = c_mi_exp[b];
+    const int m = mi_a(ex) + mi_b(ex) + mi_c(ex);
+    // the 8 child columns, read before the sums so their loads are in flight
+    double out[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) out[q] = row[m2l_col(q, b, m)];
+    double S[8];
+#pragma unroll
+    for (int pat = 0; pat < 8; ++pat) {
+      double x = 0.0;
+#pragma unroll 2
+      for (int j = s_cs[8 * b + pat]; j < s_cs[8 * b + pat + 1]; ++j) x = fma(s_coef[j], src[s_idx[j]], x);
+      S[pat] = x;
     }
-    Lk[Pc * RS + col] += acc;
+    // axis bit a: child q with q_a = 0 takes (-1)^g_a, with q_a = 1 takes +1
+#pragma unroll
+    for (int a = 4; a >= 1; a >>= 1)
+#pragma unroll
+      for (int x = 0; x < 8; ++x)
+        if (!(x & a)) {
+          const double u = S[x], w = S[x | a];
+          S[x] = u - w;
+          S[x | a] = u + w;
+        }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) row[m2l_col(q, b, m)] = out[q] + S[q];
   }
 }
 
@@ -1265,15 +1325,15 @@ hipError_t solve_ct(fmm_plan* pl, IoArg io, hipStream_t s) {
     StageScope sc(pl, ST_P2M, 1, s);
     // terms past nmax are written as zero
     if (pl->dl == 2)
-      hipLaunchKernelGGL((k_p2m2<TI, CT>), dim3(pl->s_p2m.blocks), dim3(256), 0, s, pl->s_p2m.dev, pl->s_p2m.nseg, io,
-                         pl->NMX, NC);
+      hipLaunchKernelGGL((k_p2m2<P, TI, CT>), dim3(pl->s_p2m.blocks), dim3(256), 0, s, pl->s_p2m.dev, pl->s_p2m.nseg,
+                         io, pl->NMX);
     else
       hipLaunchKernelGGL((k_p2m<TI, CT>), dim3(pl->s_p2m.blocks), dim3(256), 0, s, pl->s_p2m.dev, pl->s_p2m.nseg, io,
                          pl->NMX, NC);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (pl->s_p2m2.nseg) {
-      hipLaunchKernelGGL((k_p2m2<TI, CT>), dim3(pl->s_p2m2.blocks), dim3(256), 0, s, pl->s_p2m2.dev,
-                         pl->s_p2m2.nseg, io, pl->NMX, NC);
+      hipLaunchKernelGGL((k_p2m2<P, TI, CT>), dim3(pl->s_p2m2.blocks), dim3(256), 0, s, pl->s_p2m2.dev,
+                         pl->s_p2m2.nseg, io, pl->NMX);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }

@@ -35,7 +35,7 @@ constexpr __host__ __device__ int l2l_entries(int P) {
   return e;
 }
 // level-(k-1) cells whose child locals one k_l2l block forms
-constexpr int L2L_ROWS = 4;
+constexpr int L2L_ROWS = 16;
 
 // index of (a, b, c) in the graded order
 constexpr __host__ __device__ int mi_index(int a, int b, int c) {
@@ -311,8 +311,8 @@ struct fmm_plan {
   int* m2mt_start = nullptr;    // transposed M2M lists: CSR over (b, parity pattern of g)
   int* m2mt_a = nullptr;        // a = b + g
   double* m2mt_coef = nullptr;  // 2^-|b| 4^-|g| / g!
-  int* l2l_start = nullptr;     // L2L coefficient lists (CSR over local terms)
-  int* l2l_idx = nullptr;       // (index of b+g) << 3 | parity pattern of g
+  int* l2l_start = nullptr;     // L2L coefficient lists (CSR over (local term, parity of g))
+  int* l2l_idx = nullptr;       // index of the term b+g
   double* l2l_coef = nullptr;
   int* flag = nullptr;      // device scratch flag (finite check)
   // launch schedule: segment tables of every launch site, built with the plan

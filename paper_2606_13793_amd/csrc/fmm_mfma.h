@@ -288,15 +288,6 @@ __device__ __forceinline__ void block_fill(int count, Val&& val, Put&& put) {
   }
 }
 
-// Calls f(std::integral_constant<int, k>) for k = I, I + 1, ..., N - 1.
-template <int N, int I = 0, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (I < N) {
-    f(std::integral_constant<int, I>{});
-    static_for<N, I + 1>(f);
-  }
-}
-
 // minimum waves per SIMD (the second launch bound): one 1024-thread block or
 // two 512-thread FP32 blocks per CU (4 waves per SIMD, <= 128 registers)
 template <typename CT>
