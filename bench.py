@@ -112,11 +112,21 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def _cell_max(a, b):
+    """Largest per-cell error relative to the largest reference value."""
+    import numpy as np
+    a, b = np.ravel(a), np.ravel(b)
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
 def run_large(fi, fmm, costs, n: int = 512, p: int = 6) -> dict:
     """The same 256-sphere field at 512^3 (or 1024^3): solve time per policy
-    and the mixed policies' error against the FP64 solve at 4096 sampled
-    cells.  At 1024^3 a plan holds about 196 GiB and the FP64 input and
-    outputs 40 GiB, so the density's temporaries are released first."""
+    and, at 4096 sampled cells, phi and g of the mixed policies against the
+    FP64 solve and (up to 512^3, where the oracle's upward pass takes about
+    15 s and 13 GB of host memory) every policy against the FP64 oracle, as
+    relative L2 norms and as per-cell bounds max|err| / max|ref|.  At 1024^3
+    a plan holds about 196 GiB and the FP64 input and outputs 40 GiB, so the
+    density's temporaries are released first."""
     import numpy as np
     import torch
     log(f"extras: {n}^3 density")
@@ -124,8 +134,14 @@ def run_large(fi, fmm, costs, n: int = 512, p: int = 6) -> dict:
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     N = n ** 3
-    idx = torch.as_tensor(np.sort(np.random.default_rng(11).choice(N, 4096, replace=False)), device="cuda")
-    out = {"n": n, "p": p}
+    cells = np.sort(np.random.default_rng(11).choice(N, 4096, replace=False))
+    idx = torch.as_tensor(cells, device="cuda")
+    out = {"n": n, "p": p, "sampled_cells": len(cells)}
+    phi_o = g_o = None
+    if n <= 512:
+        import oracle
+        log(f"extras: {n}^3 oracle at {len(cells)} sampled cells")
+        phi_o, g_o = oracle.solve(rho64.cpu().numpy(), p, targets=cells)
     ref = None
     for prec in ("fp64", "fp32", "bf16"):
         log(f"extras: {n}^3 {prec} plan")
@@ -135,14 +151,25 @@ def run_large(fi, fmm, costs, n: int = 512, p: int = 6) -> dict:
         g = torch.empty((3, n, n, n), dtype=plan.io_dtype, device="cuda")
         ms = _event_ms(lambda: plan.solve_into(rho, phi, g), 3, 1)
         ps = phi.reshape(-1)[idx].double().cpu().numpy()
+        gs = g.reshape(3, -1)[:, idx].double().cpu().numpy()
         rec = {"ms_per_solve": ms, "cells_per_s": N / (ms * 1e-3),
                "useful_tflops": costs.solve_flops(n, p)["total"] / (ms * 1e-3) / 1e12}
         if prec == "fp64":
-            ref = ps
+            ref = (ps, gs)
         else:
-            rec["phi_rel_l2_vs_fp64"] = _rel(ps, ref)
+            rec["phi_rel_l2_vs_fp64"] = _rel(ps, ref[0])
+            rec["g_rel_l2_vs_fp64"] = _rel(gs, ref[1])
+            rec["phi_cell_max_vs_fp64"] = _cell_max(ps, ref[0])
+            rec["g_cell_max_vs_fp64"] = _cell_max(gs, ref[1])
+        if phi_o is not None:
+            rec["phi_rel_l2_vs_oracle"] = _rel(ps, phi_o)
+            rec["g_rel_l2_vs_oracle"] = _rel(gs, g_o)
+            rec["phi_cell_max_vs_oracle"] = _cell_max(ps, phi_o)
+            rec["g_cell_max_vs_oracle"] = _cell_max(gs, g_o)
         out[prec] = rec
-        log(f"extras: {n}^3 {prec}: {ms:.1f} ms ({N / (ms * 1e-3):.3e} cells/s)")
+        log(f"extras: {n}^3 {prec}: {ms:.1f} ms ({N / (ms * 1e-3):.3e} cells/s)"
+            + (f", vs oracle phi {rec['phi_rel_l2_vs_oracle']:.2e} g {rec['g_rel_l2_vs_oracle']:.2e}"
+               if phi_o is not None else ""))
         del plan, phi, g
         torch.cuda.empty_cache()
     return out
