@@ -866,41 +866,87 @@ __global__ __launch_bounds__(ADJ_L2P_THREADS) void k_adj_l2p(const double* __res
 
 // L2L^T for one level k: Lbar_{k-1}[P][b'] = sum_q sum_{b + g = b'}
 //   2^-(|b|+1) 4^-|g| / g! (2q-1)^g Lbar_k[2P+q][b].
-// Thread = (cell P of level k-1, term b'); P's row of Abar_k holds its 8
-// children, the result goes to P's parent's row of Abar_{k-1}.
+// P's row of Abar_k holds its 8 children; the result goes to P's parent's
+// row of Abar_{k-1}.  The child enters only through the sign
+// (2q-1)^g = (-1)^(popc(~q & pat(g))), so with the Walsh sums
+//   W[b][pat] = sum_q (-1)^(popc(~q & pat)) Lbar_k[2P+q][b]
+// (children taken in reverse order, q' = 7 - q, turn ~q into q') each output
+// is sum_{b + g = b'} coef W[b][pat(g)]: the M2M's coefficient lists (over
+// b <= b', offset 8 b + pat(g), weight 2^-|b| 4^-|g| / g!) at half weight.
+// Block = ADJ_L2L_PAR cells P: their rows are staged in LDS with the lists,
+// Walsh-transformed in place (thread (P, b)), then thread (P, b') sums.
+constexpr int ADJ_L2L_PAR = 8;
+template <int PO>
 __global__ __launch_bounds__(256) void k_adj_l2l(const double* __restrict__ Ak, double* __restrict__ Akm1, int ns,
-                                                 int NL) {
+                                                 const int* __restrict__ cstart, const int* __restrict__ coff,
+                                                 const double* __restrict__ ccoef) {
+  constexpr int NL = nterms(PO), NCH = 2 * NL, WS = 8 * NL + 1;  // NCH: 4-column chunks of a row
+  constexpr int NE = (PO + 1) * (PO + 2) * (PO + 3) * (PO + 4) * (PO + 5) * (PO + 6) / 720;
+  __shared__ double W[ADJ_L2L_PAR * WS];
+  __shared__ int sstart[NL + 1];
+  __shared__ int soff[NE];
+  __shared__ double scoef[NE];
   const long long nps = (long long)ns * ns * ns;
-  const long long id = blockIdx.x * 256LL + threadIdx.x;
-  if (id >= nps * NL) return;
-  const long long P = id / NL;
-  const int bt2 = (int)(id % NL);
-  const int p2 = (int)(P % ns), p1 = (int)((P / ns) % ns), p0 = (int)(P / ((long long)ns * ns));
   const int nsp = ns + 6, nh = ns >> 1, nhp = nh + 6;
   const long long nck = (long long)nsp * nsp * nsp, nckm = (long long)nhp * nhp * nhp;
-  const long long cp = ((long long)(p0 + 3) * nsp + (p1 + 3)) * nsp + (p2 + 3);
-  const int ex2 = c_mi_exp[bt2];
-  const int bx = mi_a(ex2), by = mi_b(ex2), bz = mi_c(ex2);
-  double acc = 0.0;
-  for (int gx = 0; gx <= bx; ++gx)
-    for (int gy = 0; gy <= by; ++gy)
-      for (int gz = 0; gz <= bz; ++gz) {
-        const int ax = bx - gx, ay = by - gy, az = bz - gz, md = ax + ay + az, gd = gx + gy + gz;
-        const int bt = mi_index(ax, ay, az);
-        const int pat = ((gx & 1) << 2) | ((gy & 1) << 1) | (gz & 1);
-        double sum = 0.0;
+  const long long P0 = (long long)blockIdx.x * ADJ_L2L_PAR;
+  for (int t = threadIdx.x; t <= NL; t += 256) sstart[t] = cstart[t];
+  for (int t = threadIdx.x; t < NE; t += 256) {
+    soff[t] = coff[t];
+    scoef[t] = ccoef[t];
+  }
+  // the rows: thread (P, column chunk), parents fastest (consecutive cells)
+#pragma unroll 2
+  for (int l = threadIdx.x; l < ADJ_L2L_PAR * NCH; l += 256) {
+    const int pl = l % ADJ_L2L_PAR, cc = l / ADJ_L2L_PAR;
+    const long long P = P0 + pl;
+    d4 v = d4{0, 0, 0, 0};
+    if (P < nps) {
+      const int p2 = (int)(P % ns), p1 = (int)((P / ns) % ns), p0 = (int)(P / ((long long)ns * ns));
+      const long long cp = ((long long)(p0 + 3) * nsp + (p1 + 3)) * nsp + (p2 + 3);
+      v = *reinterpret_cast<const d4*>(Ak + (cc * nck + cp) * 4);
+    }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int col = m2l_col(q, bt, md);
-          const double x = Ak[((col >> 2) * nck + cp) * 4 + (col & 3)];
-          sum += (__popc((~q) & pat) & 1) ? -x : x;
+    for (int e = 0; e < 4; ++e) {
+      const int col = 4 * cc + e, m = m2l_col_degree(col);
+      const int cin = col - 8 * nterms(m - 1), q = cin / ndeg(m), b = nterms(m - 1) + cin % ndeg(m);
+      W[pl * WS + 8 * b + (7 - q)] = v[e];
+    }
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int w = threadIdx.x; w < ADJ_L2L_PAR * NL; w += 256) {
+    double* x = W + (w % ADJ_L2L_PAR) * WS + 8 * (w / ADJ_L2L_PAR);
+    double y[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) y[q] = x[q];
+#pragma unroll
+    for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (!(q & bit)) {
+          const double u = y[q], v = y[q | bit];
+          y[q] = u + v;
+          y[q | bit] = u - v;
         }
-        acc += ldexp(c_mi_invfact[mi_index(gx, gy, gz)], -(md + 1) - 2 * gd) * sum;
-      }
-  const int qP = ((p0 & 1) << 2) | ((p1 & 1) << 1) | (p2 & 1);
-  const int col = m2l_col(qP, bt2, bx + by + bz);
-  const long long cpp = ((long long)((p0 >> 1) + 3) * nhp + ((p1 >> 1) + 3)) * nhp + ((p2 >> 1) + 3);
-  Akm1[((col >> 2) * nckm + cpp) * 4 + (col & 3)] = acc;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) x[q] = y[q];
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < ADJ_L2L_PAR * NL; w += 256) {
+    const int pl = w % ADJ_L2L_PAR, bt2 = w / ADJ_L2L_PAR;
+    const long long P = P0 + pl;
+    if (P >= nps) continue;
+    const double* Wp = W + pl * WS;
+    double acc = 0.0;
+    for (int j = sstart[bt2]; j < sstart[bt2 + 1]; ++j) acc += scoef[j] * Wp[soff[j]];
+    const int p2 = (int)(P % ns), p1 = (int)((P / ns) % ns), p0 = (int)(P / ((long long)ns * ns));
+    const int qP = ((p0 & 1) << 2) | ((p1 & 1) << 1) | (p2 & 1);
+    const int ex2 = c_mi_exp[bt2];
+    const int col = m2l_col(qP, bt2, mi_a(ex2) + mi_b(ex2) + mi_c(ex2));
+    const long long cpp = ((long long)((p0 >> 1) + 3) * nhp + ((p1 >> 1) + 3)) * nhp + ((p2 >> 1) + 3);
+    Akm1[((col >> 2) * nckm + cpp) * 4 + (col & 3)] = 0.5 * acc;
+  }
 }
 
 // M2M^T for one level k: Mbar_k[2P+q][b] += sum_{a >= b}
@@ -1441,8 +1487,8 @@ hipError_t backward_ct(fmm_plan* pl, const AdjWs& w, const TI* dphi, const TI* d
     // transposed L2L chain, fine to coarse
     for (int k = F - 1; k >= 4; --k) {
       const int ns = 1 << (k - 1);
-      hipLaunchKernelGGL(k_adj_l2l, dim3(blocks_for((long long)ns * ns * ns * NL, 256)), dim3(256), 0, s,
-                         w.abar[k], w.abar[k - 1], ns, NL);
+      hipLaunchKernelGGL(k_adj_l2l<P>, dim3(blocks_for((long long)ns * ns * ns, ADJ_L2L_PAR)), dim3(256), 0, s,
+                         w.abar[k], w.abar[k - 1], ns, pl->m2m_start, pl->m2m_off, pl->m2m_coef);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     // transposed M2L of every target level (sources k - 1 receive)
