@@ -1050,16 +1050,19 @@ __global__ __launch_bounds__(16 * ADJ_BOT_TZ) void k_adj_bottom(const double* __
       ys[c] = *reinterpret_cast<const d4*>(Y + (q * ncellp + cp) * 4);
     }
     __syncthreads();
-    const int qd = (((q >> 2) & 1) * 49) + (((q >> 1) & 1) * 7) + (q & 1);
+    // delta = u - w = 2e + q - q_w in [-3, 3]^3: the weights of chunk q start
+    // at offset qd, and (unrolled) those of (e, q_w) sit at a constant,
+    // non-negative distance from there
+    const double* cq = c_p2p_adj + 4 * ((((q >> 2) & 1) * 49) + (((q >> 1) & 1) * 7) + (q & 1));
+#pragma unroll
     for (int e = 0; e < 27; ++e) {
       const int e0 = e / 9 - 1, e1 = (e / 3) % 3 - 1, e2 = e % 3 - 1;
       const d4 v = ys[((tl0 + e0 + 1) * 6 + (tl1 + e1 + 1)) * HZ + (tl2 + e2 + 1)];
-      // delta = u - w = 2e + q - q_w in [-3, 3]^3; index base of 2e + q
-      const int tb = (2 * e0 + 3) * 49 + (2 * e1 + 3) * 7 + (2 * e2 + 3) + qd;
+      const int tb = (2 * e0 + 3) * 49 + (2 * e1 + 3) * 7 + (2 * e2 + 3);
 #pragma unroll
       for (int qw = 0; qw < 8; ++qw) {
         const int t = tb - (((qw >> 2) & 1) * 49 + ((qw >> 1) & 1) * 7 + (qw & 1));
-        const double* cw = c_p2p_adj + 4 * t;
+        const double* cw = cq + 4 * t;
 #pragma unroll
         for (int o = 0; o < 4; ++o) acc[qw] = fma(cw[o], v[o], acc[qw]);
       }
