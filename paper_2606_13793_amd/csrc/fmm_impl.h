@@ -708,25 +708,133 @@ __global__ void k_adj_coef2(double* __restrict__ own, double* __restrict__ par, 
 
 // L2P^T and (parent-level L2P)^T on the matrix cores (v_mfma_f64_16x16x4f64).
 // Block = 16 level-(F-1) cells P (consecutive in C order) = one row tile.
-// Wave rp (of 8) takes child T = 2P + rp of every P.  The K range of a level-F
-// cell is its 8^DL unigrid cells times (phi, g): one group of 32 for DL = 1,
-// eight for DL = 2 (group g = the level-(F+1) child).  Group by group, the
-// Ybar of the 8 children of the 16 P (256 values each) is staged in LDS with
-// an odd row stride and, for each 16-column tile of local terms b,
+// The K range of a level-F cell is its 8^DL unigrid cells times (phi, g): one
+// group of 32 for DL = 1, eight for DL = 2 (group g = the level-(F+1) child).
+// The Ybar of the 8 children of the 16 P (256 values each per group) is staged
+// in LDS with an odd row stride, and for each 16-column tile of local terms b
 //   own[P][(rp, b)] += sum_k cown[g][b][k] Ybar_g[2P + rp][k]      (K = 32)
-//   par[P][b]      += sum_k cpar[g][rp][b][k] Ybar_g[2P + rp][k]
-// accumulate in registers (with one group, tile by tile).  own is then
-// written to P's row (columns (rp, b) in the M2L order); the 8 waves' par
-// partials are added in LDS in a fixed order and written, when the parent
-// level has locals, to the row of P's parent (column (qP, b)).
+//   par[P][b]      += sum_{rp, k} cpar[g][rp][b][k] Ybar_g[2P + rp][k]
+// own goes to P's row (columns (rp, b) in the M2L order), par, when the
+// parent level has locals, to the row of P's parent (column (qP, b)).
+//  - FMM-1 (k_adj_l2p1): wave T takes column tile T and runs the 8 children
+//    one after the other, so par accumulates in the wave's own registers in a
+//    fixed order and a block needs one barrier (after the staging).
+//  - FMM-2 (k_adj_l2p<P, 2>): wave rp (of 8) takes child 2P + rp of every P
+//    for all tiles, group by group; the 8 waves' par partials are added in
+//    LDS in a fixed order.
 constexpr int ADJ_L2P_PAR = 16, ADJ_L2P_THREADS = 512, ADJ_L2P_YS = 257;
+template <int P>
+__global__ __launch_bounds__(64 * ((nterms(P) + 15) / 16)) void k_adj_l2p1(const double* __restrict__ Y,
+                                                                           const double* __restrict__ cown,
+                                                                           const double* __restrict__ cpar,
+                                                                           double* __restrict__ Aown,
+                                                                           double* __restrict__ Apar, int nF) {
+  constexpr int NL = nterms(P), RS = loc_stride(P), NBT = (NL + 15) / 16, THREADS = 64 * NBT;
+  __shared__ double y[ADJ_L2P_PAR * ADJ_L2P_YS];
+  const int nP = nF >> 1, nFp = nF + 6, nPp = nP + 6, nPP = nP >> 1, nPPp = nPP + 6;
+  const long long ncF = (long long)nFp * nFp * nFp, ncP = (long long)nPp * nPp * nPp,
+                  ncPP = (long long)nPPp * nPPp * nPPp;
+  const long long nPc = (long long)nP * nP * nP;
+  const long long P0 = (long long)blockIdx.x * ADJ_L2P_PAR;
+  const int lane = threadIdx.x & 63;
+  const int T = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // the wave's column tile
+  const int i = lane & 15, kq = lane >> 4;
+  // staging: load l = (q, parent, child), children of consecutive parents are
+  // contiguous along z
+  for (int l = threadIdx.x; l < 8 * ADJ_L2P_PAR * 8; l += THREADS) {
+    const int lr = l & 7, pl = (l >> 3) % ADJ_L2P_PAR, q = l / (8 * ADJ_L2P_PAR);
+    const long long Pc = P0 + pl;
+    d4 v = d4{0, 0, 0, 0};
+    if (Pc < nPc) {
+      const int p2 = (int)(Pc % nP), p1 = (int)((Pc / nP) % nP), p0 = (int)(Pc / ((long long)nP * nP));
+      const long long cT = ((long long)(2 * p0 + ((lr >> 2) & 1) + 3) * nFp + (2 * p1 + ((lr >> 1) & 1) + 3)) * nFp +
+                           (2 * p2 + (lr & 1) + 3);
+      v = *reinterpret_cast<const d4*>(Y + (q * ncF + cT) * 4);
+    }
+    double* yy = y + pl * ADJ_L2P_YS + lr * 32 + q * 4;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) yy[e] = v[e];
+  }
+  // the lane's output rows 4 v + kq: padded-grid cells of P and of its parent,
+  // and P's position in the parent
+  long long cpo[4], cpp[4];
+  int qP[4];
+  bool okr[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const long long Pc = P0 + 4 * v + kq;
+    okr[v] = Pc < nPc;
+    const long long Pq = okr[v] ? Pc : 0;
+    const int p2 = (int)(Pq % nP), p1 = (int)((Pq / nP) % nP), p0 = (int)(Pq / ((long long)nP * nP));
+    cpo[v] = ((long long)(p0 + 3) * nPp + (p1 + 3)) * nPp + (p2 + 3);
+    cpp[v] = ((long long)((p0 >> 1) + 3) * nPPp + ((p1 >> 1) + 3)) * nPPp + ((p2 >> 1) + 3);
+    qP[v] = ((p0 & 1) << 2) | ((p1 & 1) << 1) | (p2 & 1);
+  }
+  // the lane's column (B operand); past the last term the loads read the last
+  // column (no branch, so they issue together) and the values become zero
+  const int bt = 16 * T + i;
+  const bool okc = bt < NL;
+  const int btc = okc ? bt : NL - 1;
+  const int ex = c_mi_exp[btc];
+  const int deg = mi_a(ex) + mi_b(ex) + mi_c(ex);
+  double bo[8];
+#pragma unroll
+  for (int kc = 0; kc < 8; ++kc) {
+    const double x = cown[btc * 32 + 4 * kc + kq];
+    bo[kc] = okc ? x : 0.0;
+  }
+  __syncthreads();
+  const double* ya = y + i * ADJ_L2P_YS + kq;
+  d4 ap = d4{0, 0, 0, 0};
+#pragma unroll 1
+  for (int rp = 0; rp < 8; ++rp) {
+    double bp[8];
+#pragma unroll
+    for (int kc = 0; kc < 8; ++kc) {
+      const double x = cpar[((size_t)rp * NL + btc) * 32 + 4 * kc + kq];
+      bp[kc] = okc ? x : 0.0;
+    }
+    d4 ao = d4{0, 0, 0, 0};
+#pragma unroll
+    for (int kc = 0; kc < 8; ++kc) {
+      const double a = ya[rp * 32 + 4 * kc];
+      ao = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bo[kc], ao, 0, 0, 0);
+      ap = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bp[kc], ap, 0, 0, 0);
+    }
+    if (okc) {
+      const int col = m2l_col(rp, bt, deg);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (okr[v]) Aown[((col >> 2) * ncP + cpo[v]) * 4 + (col & 3)] = ao[v];
+    }
+  }
+  if (Apar && okc)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (okr[v]) {
+        const int col = m2l_col(qP[v], bt, deg);
+        Apar[((col >> 2) * ncPP + cpp[v]) * 4 + (col & 3)] = ap[v];
+      }
+  // the padding columns of P's row (past 8 NL) stay zero
+  if constexpr (RS > 8 * NL) {
+    for (int t = threadIdx.x; t < ADJ_L2P_PAR * (RS - 8 * NL) / 4; t += THREADS) {
+      const int pl = t % ADJ_L2P_PAR, cc = 2 * NL + t / ADJ_L2P_PAR;
+      const long long Pc = P0 + pl;
+      if (Pc >= nPc) continue;
+      const int p2 = (int)(Pc % nP), p1 = (int)((Pc / nP) % nP), p0 = (int)(Pc / ((long long)nP * nP));
+      const long long cp = ((long long)(p0 + 3) * nPp + (p1 + 3)) * nPp + (p2 + 3);
+      *reinterpret_cast<d4*>(Aown + (cc * ncP + cp) * 4) = d4{0, 0, 0, 0};
+    }
+  }
+}
 template <int P, int DL>
 __global__ __launch_bounds__(ADJ_L2P_THREADS) void k_adj_l2p(const double* __restrict__ Y,
                                                              const double* __restrict__ cown,
                                                              const double* __restrict__ cpar,
                                                              double* __restrict__ Aown, double* __restrict__ Apar,
                                                              int nF) {
-  constexpr int NL = nterms(P), RS = loc_stride(P), NBT = (NL + 15) / 16, NG = DL == 1 ? 1 : 8;
+  static_assert(DL == 2, "FMM-1 runs k_adj_l2p1");
+  constexpr int NL = nterms(P), RS = loc_stride(P), NBT = (NL + 15) / 16, NG = 8;
   __shared__ double y[ADJ_L2P_PAR * ADJ_L2P_YS];
   __shared__ double red[8][16][17];
   const int nP = nF >> 1, nFp = nF + 6, nPp = nP + 6, nPP = nP >> 1, nPPp = nPP + 6;
@@ -800,57 +908,31 @@ __global__ __launch_bounds__(ADJ_L2P_THREADS) void k_adj_l2p(const double* __res
       }
     }
   };
-  if constexpr (NG == 1) {
-    // one group: tile by tile, so the accumulators of one tile are live
-    // (several blocks per CU overlap one block's staging with another's
-    // products)
-    stage(0);
-    __syncthreads();
-    double a[8];
+  d4 ao[NBT], ap[NBT];
 #pragma unroll
-    for (int kc = 0; kc < 8; ++kc) a[kc] = ya[4 * kc];
-    const double* cp = cpar + (size_t)rp * NL * 32;
-#pragma unroll 1
+  for (int T = 0; T < NBT; ++T) ao[T] = ap[T] = d4{0, 0, 0, 0};
+  for (int g = 0; g < NG; ++g) {
+    if (g) __syncthreads();  // the previous group is consumed
+    stage(g);
+    __syncthreads();
+    const double* co = cown + (size_t)g * NL * 32;
+    const double* cp = cpar + ((size_t)g * 8 + rp) * NL * 32;
+#pragma unroll
     for (int T = 0; T < NBT; ++T) {
       const int bt = 16 * T + i;  // the lane's column (B operand)
       const bool okc = bt < NL;
-      d4 ao = d4{0, 0, 0, 0}, ap = d4{0, 0, 0, 0};
 #pragma unroll
       for (int kc = 0; kc < 8; ++kc) {
-        const double bo = okc ? cown[bt * 32 + 4 * kc + kq] : 0.0;
+        const double a = ya[4 * kc];
+        const double bo = okc ? co[bt * 32 + 4 * kc + kq] : 0.0;
         const double bp = okc ? cp[bt * 32 + 4 * kc + kq] : 0.0;
-        ao = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kc], bo, ao, 0, 0, 0);
-        ap = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kc], bp, ap, 0, 0, 0);
-      }
-      store(T, ao, ap);
-    }
-  } else {
-    d4 ao[NBT], ap[NBT];
-#pragma unroll
-    for (int T = 0; T < NBT; ++T) ao[T] = ap[T] = d4{0, 0, 0, 0};
-    for (int g = 0; g < NG; ++g) {
-      if (g) __syncthreads();  // the previous group is consumed
-      stage(g);
-      __syncthreads();
-      const double* co = cown + (size_t)g * NL * 32;
-      const double* cp = cpar + ((size_t)g * 8 + rp) * NL * 32;
-#pragma unroll
-      for (int T = 0; T < NBT; ++T) {
-        const int bt = 16 * T + i;  // the lane's column (B operand)
-        const bool okc = bt < NL;
-#pragma unroll
-        for (int kc = 0; kc < 8; ++kc) {
-          const double a = ya[4 * kc];
-          const double bo = okc ? co[bt * 32 + 4 * kc + kq] : 0.0;
-          const double bp = okc ? cp[bt * 32 + 4 * kc + kq] : 0.0;
-          ao[T] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bo, ao[T], 0, 0, 0);
-          ap[T] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bp, ap[T], 0, 0, 0);
-        }
+        ao[T] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bo, ao[T], 0, 0, 0);
+        ap[T] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bp, ap[T], 0, 0, 0);
       }
     }
-#pragma unroll
-    for (int T = 0; T < NBT; ++T) store(T, ao[T], ap[T]);
   }
+#pragma unroll
+  for (int T = 0; T < NBT; ++T) store(T, ao[T], ap[T]);
   // the padding columns of P's row (past 8 NL) stay zero
   if constexpr (RS > 8 * NL) {
     for (int t = threadIdx.x; t < ADJ_L2P_PAR * (RS - 8 * NL) / 4; t += ADJ_L2P_THREADS) {
@@ -1484,8 +1566,8 @@ hipError_t backward_ct(fmm_plan* pl, const AdjWs& w, const TI* dphi, const TI* d
       hipLaunchKernelGGL((k_adj_l2p<P, 2>), dim3(blocks_for(nP, ADJ_L2P_PAR)), dim3(ADJ_L2P_THREADS), 0, s, w.ybar,
                          pl->adj_l2p, pl->adj_l2p2, w.abar[F], F >= 4 ? w.abar[F - 1] : nullptr, nF);
     else
-      hipLaunchKernelGGL((k_adj_l2p<P, 1>), dim3(blocks_for(nP, ADJ_L2P_PAR)), dim3(ADJ_L2P_THREADS), 0, s, w.ybar,
-                         pl->adj_l2p, pl->adj_l2p2, w.abar[F], F >= 4 ? w.abar[F - 1] : nullptr, nF);
+      hipLaunchKernelGGL((k_adj_l2p1<P>), dim3(blocks_for(nP, ADJ_L2P_PAR)), dim3(64 * ((NL + 15) / 16)), 0, s,
+                         w.ybar, pl->adj_l2p, pl->adj_l2p2, w.abar[F], F >= 4 ? w.abar[F - 1] : nullptr, nF);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // transposed L2L chain, fine to coarse
     for (int k = F - 1; k >= 4; --k) {
