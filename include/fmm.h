@@ -113,13 +113,17 @@ fmm_plan* fmm_plan_create_ex(int n, int p, int isolated, const fmm_options* opt)
 void fmm_plan_destroy(fmm_plan* plan);
 
 /*
- * phi (and g, if not NULL) of the density rho.  Enqueued on `stream`.
+ * phi (and g, if not NULL) of the density rho: the solve of Sec. 2 (upward
+ * pass P2M, M2M; M2L over the oct-shared lists of Sec. 2.2; downward pass
+ * L2L; at the unigrid cells L2P, M2P and the direct near field, Sec. 4;
+ * FMM-2 with delta_l = 2, App. A).  Enqueued on `stream`.
  * rho: n^3 values; phi: n^3; g: 3 n^3 or NULL.
  */
 int fmm_solve(fmm_plan* plan, const void* rho, void* phi, void* g, void* stream);
 
 /*
- * Vector-Jacobian product of fmm_solve: drho = d(<phi, dphi> + <g, dg>)/drho.
+ * Vector-Jacobian product of fmm_solve (the transpose of the Sec. 2 solve,
+ * FMM-1 and FMM-2): drho = d(<phi, dphi> + <g, dg>)/drho.
  * The solve is linear in rho, so no forward state is needed; the kernels run
  * the transposes of the forward passes in reverse order (P2P^T, L2P^T and
  * M2P^T, then L2L^T and M2L^T from the finest level up, M2M^T down, P2M^T).

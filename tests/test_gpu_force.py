@@ -70,8 +70,9 @@ def test_two_spheres_force_inside_within_one_percent_256(F, source):
     the finite-difference force and for the solve's own g, with FMM-1 and
     FMM-2.  "cells": the spheres sampled at the cell centres (density 1
     inside).  "particles": 16M particles deposited by CIC, over the cells
-    whose centres lie inside (the CIC halo just outside the surfaces, also
-    of non-zero density, lifts the percentile to about 1.5 %)."""
+    whose centres lie inside; over every cell the deposit reaches (the CIC
+    halo just outside the surfaces included) the percentile is about 1.5 %,
+    held here below 2 %."""
     import torch
     n = 256
     _say(f"case two spheres force n=256 from {source}")
@@ -82,11 +83,17 @@ def test_two_spheres_force_inside_within_one_percent_256(F, source):
         rho = F.deposit_cic(n, torch.as_tensor(pos).cuda(), torch.as_tensor(m).cuda())
         del pos, m
     idx, pts = _inside_cells(n)
-    cells = torch.as_tensor(idx).cuda()
-    exact = np.linalg.norm(fi.two_spheres_force(pts), axis=0)
+    sets = [(torch.as_tensor(idx).cuda(), np.linalg.norm(fi.two_spheres_force(pts), axis=0), 1e-2)]
+    if source == "particles":
+        flat = torch.nonzero(rho.reshape(-1) > 0).flatten()
+        f = flat.cpu().numpy()
+        c = fi.cell_centres(n)
+        pts_nz = np.stack([c[f // (n * n)], c[(f // n) % n], c[f % n]], 1)
+        sets.append((flat, np.linalg.norm(fi.two_spheres_force(pts_nz), axis=0), 2e-2))
     for dl in (1, 2):
         phi, g = F.Plan(n, 3, "fp64", nmax=2, delta_l=dl).solve(rho)
         for name, force in (("fd", F.fd_force(phi)), ("g", g)):
-            mag = torch.linalg.vector_norm(force.reshape(3, -1)[:, cells], dim=0).cpu().numpy()
-            err = np.abs(mag - exact) / exact
-            assert np.percentile(err, 90) < 1e-2, (dl, name, np.percentile(err, 90))
+            for cells, exact, bar in sets:
+                mag = torch.linalg.vector_norm(force.reshape(3, -1)[:, cells], dim=0).cpu().numpy()
+                err = np.abs(mag - exact) / exact
+                assert np.percentile(err, 90) < bar, (dl, name, len(exact), np.percentile(err, 90))
