@@ -182,16 +182,42 @@ __global__ void k_dtab2(double* __restrict__ out, int PD, int ND) {
   green_derivs(R0, R1, R2, PD, ND, out + (size_t)t * ND);
 }
 
+// term index -> packed exponents a | b << 8 | c << 16 (the inverse of
+// mi_index), and small constant helpers, usable in constant expressions
+constexpr __host__ __device__ int mi_exp_of(int t) {
+  int n = 0;
+  while (nterms(n) <= t) ++n;
+  int r = t - nterms(n - 1), a = 0;
+  while (r >= n - a + 1) {
+    r -= n - a + 1;
+    ++a;
+  }
+  return a | r << 8 | (n - a - r) << 16;
+}
+constexpr bool mi_exp_inverts_index() {
+  for (int t = 0; t < NTMAX; ++t) {
+    const int e = mi_exp_of(t);
+    if (mi_index(e & 255, (e >> 8) & 255, e >> 16) != t) return false;
+  }
+  return true;
+}
+static_assert(mi_exp_inverts_index(), "mi_exp_of inverts mi_index");
+constexpr __host__ __device__ double pow3(int k) { return k == 0 ? 1.0 : 3.0 * pow3(k - 1); }
+constexpr __host__ __device__ double fact_d(int k) { return k <= 1 ? 1.0 : k * fact_d(k - 1); }
+
 // ---------------------------------------------------------------------------
 // P2M: Mhat_F[a] = sum_q rho_{2T+q} (s_q/4)^a / a!,  s_q,i = 1 - 2 q_i.
 // (-1)^(q.a) depends on a only through a mod 2, so the 8 signed sums of the
 // children are formed once (a Walsh transform) and each term is one product.
+// The term loop is unrolled (P fixed): each term's sign pattern and scale are
+// compile-time constants.  Terms past nmax are written as zero.
 // ---------------------------------------------------------------------------
 // Segments: n = unigrid cells per axis, field, b = Mhat_F (or null: not
 // written), t = its copy in the compute type CT (mixed precision; null or
 // CT = double: none).  256 cells T per block.
-template <typename TI, typename CT>
-__global__ __launch_bounds__(256) void k_p2m(const Seg* __restrict__ segs, int nseg, IoArg io, int NM, int NC) {
+template <int P, typename TI, typename CT>
+__global__ __launch_bounds__(256) void k_p2m(const Seg* __restrict__ segs, int nseg, IoArg io, int NM) {
+  constexpr int NT = nterms(P), NC = (NT + 3) / 4;
   const Seg& sg = find_seg(segs, nseg, blockIdx.x);
   const int n = sg.n;
   const TI* __restrict__ rho = io_rho<TI>(io, sg.field);
@@ -217,27 +243,28 @@ __global__ __launch_bounds__(256) void k_p2m(const Seg* __restrict__ segs, int n
   }
   const long long ncellp = (long long)nFp * nFp * nFp;
   const long long cp = ((long long)(t0 + 3) * nFp + (t1 + 3)) * nFp + (t2 + 3);
-  for (int c = 0; c < NC; ++c) {
+  static_for<NC>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
     d4 o;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int al = 4 * c + e;
+    static_for<4>([&](auto ec) {
+      constexpr int al = 4 * c + decltype(ec)::value;
       double val = 0.0;
-      if (al < NM) {
-        const int ex = c_mi_exp[al];
-        const int a = mi_a(ex), b = mi_b(ex), cc = mi_c(ex);
-        const int pat = ((a & 1) << 2) | ((b & 1) << 1) | (cc & 1);
-        val = ldexp(c_mi_invfact[al], -2 * (a + b + cc)) * S[pat];
+      if constexpr (al < NT) {
+        constexpr int ex = mi_exp_of(al);
+        constexpr int a = ex & 255, b = (ex >> 8) & 255, z = ex >> 16;
+        constexpr int pat = ((a & 1) << 2) | ((b & 1) << 1) | (z & 1);
+        constexpr double sc = 1.0 / (fact_d(a) * fact_d(b) * fact_d(z) * (double)(1LL << (2 * (a + b + z))));
+        if (al < NM) val = sc * S[pat];
       }
-      o[e] = val;
-    }
+      o[decltype(ec)::value] = val;
+    });
     if (M) *reinterpret_cast<d4*>(M + (c * ncellp + cp) * 4) = o;
     if constexpr (Mf<CT>::IDX != 0) {
       constexpr int KC = Mf<CT>::KC;
       if (sg.t)
         store4((typename Mf<CT>::H*)sg.t + ((4 * c / KC) * ncellp + cp) * KC + (4 * c) % KC, o[0], o[1], o[2], o[3]);
     }
-  }
+  });
 }
 
 // P2M of FMM-2: Mhat_F[a] = sum_s rho_{4T+s} w_s^a / a!, w_s,i = (3 - 2 s_i) / 8
@@ -252,27 +279,6 @@ __global__ __launch_bounds__(256) void k_p2m(const Seg* __restrict__ segs, int n
 // 1/8)), and each term is then 8 products with the integer weights 3^k of
 // its slots, scaled by 8^-|a| / a!.  The term loop is unrolled (P fixed), so
 // the slots are register indices known at compile time.
-constexpr __host__ __device__ int mi_exp_of(int t) {
-  int n = 0;
-  while (nterms(n) <= t) ++n;
-  int r = t - nterms(n - 1), a = 0;
-  while (r >= n - a + 1) {
-    r -= n - a + 1;
-    ++a;
-  }
-  return a | r << 8 | (n - a - r) << 16;
-}
-constexpr bool mi_exp_inverts_index() {
-  for (int t = 0; t < NTMAX; ++t) {
-    const int e = mi_exp_of(t);
-    if (mi_index(e & 255, (e >> 8) & 255, e >> 16) != t) return false;
-  }
-  return true;
-}
-static_assert(mi_exp_inverts_index(), "mi_exp_of inverts mi_index");
-constexpr __host__ __device__ double pow3(int k) { return k == 0 ? 1.0 : 3.0 * pow3(k - 1); }
-constexpr __host__ __device__ double fact_d(int k) { return k <= 1 ? 1.0 : k * fact_d(k - 1); }
-
 template <int P, typename TI, typename CT>
 __global__ __launch_bounds__(256) void k_p2m2(const Seg* __restrict__ segs, int nseg, IoArg io, int NM) {
   constexpr int NT = nterms(P), NC = (NT + 3) / 4;
@@ -1445,7 +1451,6 @@ hipError_t launch_bottom(fmm_plan* pl, int x, IoArg io, hipStream_t s) {
 // levels (double for FP64 plans).
 template <int P, typename CT, typename TI, typename TO>
 hipError_t solve_ct(fmm_plan* pl, IoArg io, hipStream_t s) {
-  constexpr int NM = nterms(P), NC = (NM + 3) / 4;
   hipError_t e;
   if (pl->stamps) {
     const int nf = (int)pl->fld.size();
@@ -1459,8 +1464,8 @@ hipError_t solve_ct(fmm_plan* pl, IoArg io, hipStream_t s) {
       hipLaunchKernelGGL((k_p2m2<P, TI, CT>), dim3(pl->s_p2m.blocks), dim3(256), 0, s, pl->s_p2m.dev, pl->s_p2m.nseg,
                          io, pl->NMX);
     else
-      hipLaunchKernelGGL((k_p2m<TI, CT>), dim3(pl->s_p2m.blocks), dim3(256), 0, s, pl->s_p2m.dev, pl->s_p2m.nseg, io,
-                         pl->NMX, NC);
+      hipLaunchKernelGGL((k_p2m<P, TI, CT>), dim3(pl->s_p2m.blocks), dim3(256), 0, s, pl->s_p2m.dev, pl->s_p2m.nseg,
+                         io, pl->NMX);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (pl->s_p2m2.nseg) {
       hipLaunchKernelGGL((k_p2m2<P, TI, CT>), dim3(pl->s_p2m2.blocks), dim3(256), 0, s, pl->s_p2m2.dev,
