@@ -459,6 +459,11 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
     bs[1][0] = bload(es[1], 0);
     bs[1][1] = bload(es[1], 1);
     aload(es[0], as[0]);
+    // (FP64, BF16: the list entry of a group is read three groups ahead and
+    // used one group later, so the wait for it, which also covers the LDS
+    // reads in flight, finds only reads at least one group old)
+    constexpr bool F32 = M::IDX == 1;
+    EntryGroup ahead = group(F32 ? 1 : 2);
     // (the body is unrolled by three by hand; unrolling the loop itself would
     // hoist every group's table address out of the chunk loop)
     // whole unrolled iterations, the last padded with null groups (zero B
@@ -473,11 +478,14 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
         // (FP32, measured faster so, keeps a bounds test and the last real
         // group as the prefetch past the end; for the others both are
         // compile-time true)
-        constexpr bool F32 = M::IDX == 1;
         if (!F32 || jj < NGRP) {
-          es[nn] = group(!F32 || jj + 2 < NGRP ? jj + 2 : NGRP - 1);
+          if constexpr (F32)
+            es[nn] = group(jj + 2 < NGRP ? jj + 2 : NGRP - 1);
+          else
+            es[nn] = ahead;
           bs[nn][0] = bload(es[nn], 0);
           bs[nn][1] = bload(es[nn], 1);
+          if constexpr (!F32) ahead = group(jj + 3);
           aload(es[nx], as[nx]);
           // (keep the loads ahead of the products: the scheduler would move
           // them next to their uses and expose their latency)
@@ -1232,6 +1240,11 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
       bs[1][t] = bload(es[1], t);
     }
     aload(es[0], as[0]);
+    // The list entry of a group is read three groups ahead and used one group
+    // later: a scalar load may return out of order, so the wait before the
+    // first use of its value covers every scalar and LDS read in flight, and
+    // this way those are all at least one group old.
+    EntryGroup ahead = group(ja + 2);
     // The groups run in whole unrolled iterations, the last padded with null
     // groups (zero B rows): with no exit inside an iteration and every load
     // unconditional, each group's products wait for a fixed number of loads
@@ -1242,9 +1255,10 @@ __global__ __launch_bounds__(M2L_THREADS, 1) void k_conv(const Seg* __restrict__
 #pragma unroll
       for (int u = 0; u < 3; ++u) {
         const int jj = j + u, cur = u, nx = (u + 1) % 3, nn = (u + 2) % 3;
-        es[nn] = group(jj + 2);
+        es[nn] = ahead;
 #pragma unroll
         for (int t = 0; t < NA; ++t) bs[nn][t] = bload(es[nn], t);
+        ahead = group(jj + 3);
         aload(es[nx], as[nx]);
         // (keep the loads ahead of the products: the scheduler would move
         // them next to their uses and expose their latency)
