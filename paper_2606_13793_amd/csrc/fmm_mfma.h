@@ -459,11 +459,17 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
     bs[1][0] = bload(es[1], 0);
     bs[1][1] = bload(es[1], 1);
     aload(es[0], as[0]);
-    // (FP64, BF16: the list entry of a group is read three groups ahead and
-    // used one group later, so the wait for it, which also covers the LDS
-    // reads in flight, finds only reads at least one group old)
+    // (the list entry of a group is read three groups ahead and used one
+    // group later, so the wait for it, which also covers the LDS reads in
+    // flight, finds only reads at least one group old.  FP64, BF16: a scalar
+    // load; FP32: an LDS read kept in a vector register until its use)
     constexpr bool F32 = M::IDX == 1;
-    EntryGroup ahead = group(F32 ? 1 : 2);
+    EntryGroup ahead{};
+    int raw = 0;
+    if constexpr (F32)
+      raw = entry(2 < NGRP ? 2 : NGRP - 1);
+    else
+      ahead = group(2);
     // (the body is unrolled by three by hand; unrolling the loop itself would
     // hoist every group's table address out of the chunk loop)
     // whole unrolled iterations, the last padded with null groups (zero B
@@ -480,12 +486,15 @@ __global__ __launch_bounds__(bottom_threads<CT>(), bottom_min_waves<CT>()) void 
         // compile-time true)
         if (!F32 || jj < NGRP) {
           if constexpr (F32)
-            es[nn] = group(jj + 2 < NGRP ? jj + 2 : NGRP - 1);
+            es[nn].e = __builtin_amdgcn_readfirstlane(raw);
           else
             es[nn] = ahead;
           bs[nn][0] = bload(es[nn], 0);
           bs[nn][1] = bload(es[nn], 1);
-          if constexpr (!F32) ahead = group(jj + 3);
+          if constexpr (F32)
+            raw = entry(jj + 3 < NGRP ? jj + 3 : NGRP - 1);
+          else
+            ahead = group(jj + 3);
           aload(es[nx], as[nx]);
           // (keep the loads ahead of the products: the scheduler would move
           // them next to their uses and expose their latency)
