@@ -568,33 +568,36 @@ __device__ __forceinline__ double p2p2_coef(int k, int grp, int q, int o) {
 // stage per axis), so each coefficient is applied once instead of 8 times.
 // A block takes L2L_ROWS cells P of level k - 1 and stages the coefficient
 // lists (CSR over (b, pattern)) and the level-(k-1) local of each P in LDS;
-// thread (row r, slot s) forms terms b = s, s + 16, ... of P_r's 8 children
-// (the slots of a wave run the lists of 4 neighbouring terms at once).
+// thread (row r, slot s) forms terms b = s, s + 32, ... of P_r's 8 children.
+// A wave holds two rows and 32 consecutive terms of each, so every child
+// column it reads or writes is a run of up to 32 consecutive doubles (inside
+// a degree block the terms of one child are contiguous).
 // ---------------------------------------------------------------------------
 // Segments: n = cells per axis of level k - 1, a = Lhat_{k-1}, b = Lhat_k.
+constexpr int L2L_THREADS = 512, L2L_SLOTS = L2L_THREADS / L2L_ROWS;
 template <int P>
-__global__ __launch_bounds__(256) void k_l2l(const Seg* __restrict__ segs, int nseg, const int* __restrict__ cs,
+__global__ __launch_bounds__(L2L_THREADS) void k_l2l(const Seg* __restrict__ segs, int nseg, const int* __restrict__ cs,
                                              const int* __restrict__ cidx, const double* __restrict__ ccoef) {
   constexpr int NL = nterms(P), RS = loc_stride(P), E = l2l_entries(P), SS = NL + 1;
-  static_assert(L2L_ROWS == 16, "thread = (row, slot) over 16 rows and 16 slots");
+  static_assert(L2L_SLOTS == 32, "thread = (row, slot) over 16 rows and 32 slots");
   __shared__ int s_cs[8 * NL + 1];
   __shared__ int s_idx[E];
   __shared__ double s_coef[E];
-  __shared__ double s_src[L2L_ROWS * SS];  // odd row stride: the 16 rows of a slot hit distinct banks
+  __shared__ double s_src[L2L_ROWS * SS];  // odd row stride: the rows start in distinct banks
   const Seg& sg = find_seg(segs, nseg, blockIdx.x);
   const double* __restrict__ Lprev = sg.a;
   double* __restrict__ Lk = sg.b;
   const int ns = sg.n, nsp = ns >> 1;
   const long long nps = (long long)ns * ns * ns;
   const long long P0 = (long long)(blockIdx.x - sg.first_block) * L2L_ROWS;
-  for (int t = threadIdx.x; t <= 8 * NL; t += 256) s_cs[t] = cs[t];
-  for (int t = threadIdx.x; t < E; t += 256) {
+  for (int t = threadIdx.x; t <= 8 * NL; t += L2L_THREADS) s_cs[t] = cs[t];
+  for (int t = threadIdx.x; t < E; t += L2L_THREADS) {
     s_idx[t] = cidx[t];
     s_coef[t] = ccoef[t];
   }
   // P's level-(k-1) local sits in its parent's row, in the column block of
   // P's position qP
-  for (int e = threadIdx.x; e < L2L_ROWS * NL; e += 256) {
+  for (int e = threadIdx.x; e < L2L_ROWS * NL; e += L2L_THREADS) {
     const int g = e / NL, c = e - g * NL;
     const long long Pc = P0 + g;
     double v = 0.0;
@@ -608,12 +611,12 @@ __global__ __launch_bounds__(256) void k_l2l(const Seg* __restrict__ segs, int n
     s_src[g * SS + c] = v;
   }
   __syncthreads();
-  const int r = threadIdx.x & 15, slot = threadIdx.x >> 4;
+  const int slot = threadIdx.x % L2L_SLOTS, r = threadIdx.x / L2L_SLOTS;
   const long long Pc = P0 + r;
   if (Pc >= nps) return;
   double* __restrict__ row = Lk + Pc * RS;
   const double* src = s_src + r * SS;
-  for (int b = slot; b < NL; b += 16) {
+  for (int b = slot; b < NL; b += L2L_SLOTS) {
     const int ex = c_mi_exp[b];
     const int m = mi_a(ex) + mi_b(ex) + mi_c(ex);
     // the 8 child columns, read before the sums so their loads are in flight
@@ -1409,7 +1412,7 @@ hipError_t launch_split_reduce(fmm_plan* pl, const SegTable& st, hipStream_t s) 
 template <int P>
 hipError_t launch_l2l_site(fmm_plan* pl, const SegTable& st, hipStream_t s) {
   if (!st.nseg) return hipSuccess;
-  hipLaunchKernelGGL(k_l2l<P>, dim3(st.blocks), dim3(256), 0, s, st.dev, st.nseg, pl->l2l_start, pl->l2l_idx,
+  hipLaunchKernelGGL(k_l2l<P>, dim3(st.blocks), dim3(L2L_THREADS), 0, s, st.dev, st.nseg, pl->l2l_start, pl->l2l_idx,
                      pl->l2l_coef);
   return hipGetLastError();
 }
