@@ -215,6 +215,29 @@ constexpr __host__ __device__ double fact_d(int k) { return k <= 1 ? 1.0 : k * f
 // Segments: n = unigrid cells per axis, field, b = Mhat_F (or null: not
 // written), t = its copy in the compute type CT (mixed precision; null or
 // CT = double: none).  256 cells T per block.
+// The typed copy of a multipole grid (mixed plans): term chunks of KC, so a
+// cell's chunk is KC/4 of the 4-term groups the P2M kernels form.  put<c, NC>
+// adds group c to the chunk being filled and stores the chunk in one vector
+// store when it is full or c is the last group (zero terms past the last).
+template <typename CT>
+struct TypedChunk {
+  static constexpr int KC = Mf<CT>::IDX != 0 ? Mf<CT>::KC : 1;
+  template <int c, int NC>
+  __device__ __forceinline__ static void put(double (&tv)[KC], const d4& o, const void* t, long long ncellp,
+                                             long long cp) {
+    if constexpr (Mf<CT>::IDX != 0) {
+      constexpr int j = (4 * c) % KC;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) tv[j + e] = o[e];
+      if constexpr (j + 4 == KC || c == NC - 1) {
+#pragma unroll
+        for (int e = j + 4; e < KC; ++e) tv[e] = 0.0;
+        if (t) store_chunk((typename Mf<CT>::H*)t + ((4 * c / KC) * ncellp + cp) * KC, tv);
+      }
+    }
+  }
+};
+
 template <int P, typename TI, typename CT>
 __global__ __launch_bounds__(256) void k_p2m(const Seg* __restrict__ segs, int nseg, IoArg io, int NM) {
   constexpr int NT = nterms(P), NC = (NT + 3) / 4;
@@ -243,6 +266,7 @@ __global__ __launch_bounds__(256) void k_p2m(const Seg* __restrict__ segs, int n
   }
   const long long ncellp = (long long)nFp * nFp * nFp;
   const long long cp = ((long long)(t0 + 3) * nFp + (t1 + 3)) * nFp + (t2 + 3);
+  double tv[TypedChunk<CT>::KC];  // the typed chunk being filled
   static_for<NC>([&](auto cc) {
     constexpr int c = decltype(cc)::value;
     d4 o;
@@ -259,11 +283,7 @@ __global__ __launch_bounds__(256) void k_p2m(const Seg* __restrict__ segs, int n
       o[decltype(ec)::value] = val;
     });
     if (M) *reinterpret_cast<d4*>(M + (c * ncellp + cp) * 4) = o;
-    if constexpr (Mf<CT>::IDX != 0) {
-      constexpr int KC = Mf<CT>::KC;
-      if (sg.t)
-        store4((typename Mf<CT>::H*)sg.t + ((4 * c / KC) * ncellp + cp) * KC + (4 * c) % KC, o[0], o[1], o[2], o[3]);
-    }
+    TypedChunk<CT>::template put<c, NC>(tv, o, sg.t, ncellp, cp);
   });
 }
 
@@ -310,6 +330,7 @@ __global__ __launch_bounds__(256) void k_p2m2(const Seg* __restrict__ segs, int 
   }
   const long long ncellp = (long long)nFp * nFp * nFp;
   const long long cp = ((long long)(t0 + 3) * nFp + (t1 + 3)) * nFp + (t2 + 3);
+  double tv[TypedChunk<CT>::KC];  // the typed chunk being filled
   static_for<NC>([&](auto cc) {
     constexpr int c = decltype(cc)::value;
     d4 o;
@@ -332,11 +353,7 @@ __global__ __launch_bounds__(256) void k_p2m2(const Seg* __restrict__ segs, int 
       o[decltype(ec)::value] = val;
     });
     *reinterpret_cast<d4*>(M + (c * ncellp + cp) * 4) = o;
-    if constexpr (Mf<CT>::IDX != 0) {
-      constexpr int KC = Mf<CT>::KC;
-      if (sg.t)
-        store4((typename Mf<CT>::H*)sg.t + ((4 * c / KC) * ncellp + cp) * KC + (4 * c) % KC, o[0], o[1], o[2], o[3]);
-    }
+    TypedChunk<CT>::template put<c, NC>(tv, o, sg.t, ncellp, cp);
     // (one chunk at a time: the scheduler would otherwise form every term
     // before the first store and hold them all in registers)
     __builtin_amdgcn_sched_barrier(0);

@@ -57,15 +57,14 @@ struct Mf<bf16_tag> {
   }
 };
 
-// Stores four consecutive terms, converted to H with round to nearest even,
-// at p (aligned to 4 elements): the typed multipole copies of mixed plans.
-template <typename H>
-__device__ __forceinline__ void store4(H* p, double a, double b, double c, double d) {
-  typedef H v4 __attribute__((ext_vector_type(4)));
-  v4 v;
-  v[0] = static_cast<H>(a);
-  v[1] = static_cast<H>(b);
-  v[2] = static_cast<H>(c);
-  v[3] = static_cast<H>(d);
-  *reinterpret_cast<v4*>(p) = v;
+// Stores one chunk of N consecutive terms, converted to H with round to
+// nearest even, at p (aligned to N elements) in one vector store: the typed
+// multipole copies of mixed plans.
+template <typename H, int N>
+__device__ __forceinline__ void store_chunk(H* p, const double (&v)[N]) {
+  typedef H vN __attribute__((ext_vector_type(N)));
+  vN x;
+#pragma unroll
+  for (int e = 0; e < N; ++e) x[e] = static_cast<H>(v[e]);
+  *reinterpret_cast<vN*>(p) = x;
 }
