@@ -446,6 +446,9 @@ __global__ __launch_bounds__(M2MShape<PO>::THREADS) void k_m2m(const Seg* __rest
     if (P >= nP) continue;
     const double* Wp = W + pl * WS;
     double acc = 0.0;
+    // (unrolled so several list entries' LDS reads are in flight; the sum
+    // keeps its order)
+#pragma unroll 4
     for (int j = sstart[al]; j < sstart[al + 1]; ++j) acc += scoef[j] * Wp[soff[j]];
     const int p2 = (int)(P % np), p1 = (int)((P / np) % np), p0 = (int)(P / ((long long)np * np));
     const long long cp = ((long long)(p0 + 3) * npp + (p1 + 3)) * npp + (p2 + 3);
